@@ -1,0 +1,22 @@
+"""Compile the C oracle into oracle/liboracle.so with gcc (FP64, no contraction)."""
+import os
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "tlmpm_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+
+def build(force=True):
+    """Build liboracle.so; with force=False only when missing or stale."""
+    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
+        return LIB
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
+           "-Wall", "-Wno-unused-function", "-o", LIB + ".tmp", SRC, "-lm"]
+    subprocess.check_call(cmd)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build())

@@ -1,0 +1,253 @@
+"""Seeded synthetic scenes and tool schedules.
+
+Input generation only: particle sampling, material parameters and blade/tool
+poses per step.  Nothing here evaluates the method; the same scenes feed the GPU
+library, the CPU oracle and the benchmark.
+
+A scene is a dict:
+  name, params (dict of scalars), X [n,3] float32, v0 [n,3] float32 or None,
+  vol0, mass, E: float32 arrays [n], steps (int), tools_at(j) -> list of tool dicts.
+
+A tool dict: {"blade": blade dict, "x_B", "v_B", "omega_B": 3-vectors, "w_B": float,
+"labels": bool (assign side digits from its band), "contact": bool, "cutting": bool}.
+A blade dict: cut_index, new_cut, x_e, n, e, d, v_e (float64 3-vectors), half_len,
+half_width, b_back, b_lead.  Blade poses are computed in float64 so every consumer
+sees bit-identical values.
+
+Particle sampling (jittered lattice): every reference cell is split into 2x2x2
+sub-cells; a sub-cell centre that lies inside the body yields one particle, moved by
+an independent uniform jitter in [-0.125, 0.125] dx per axis.  V0 = dx^3/8 and
+m = rho V0.  Particles are returned in a seeded random order.
+"""
+import math
+
+import numpy as np
+
+# Default contact and cutting constants (the paper names them without values,
+# except G_c, zeta and mu, which are taken from its banana experiment).
+CONTACT_DEFAULTS = dict(s_R=1.0, s_n=0.5, gamma_k=0.25, gamma_c=0.5, mu_s=0.2, mu_d=0.2,
+                        G_c=700.0, zeta=0.9, u_min=1e-3)
+
+
+def jittered_lattice(lo, hi, dx, origin, inside, rng, jitter=0.25):
+    """Sample the body {inside(P) == True} inside the box [lo, hi] (world units)."""
+    origin = np.asarray(origin, np.float64)
+    c0 = np.floor((np.asarray(lo) - origin) / dx).astype(np.int64)
+    c1 = np.ceil((np.asarray(hi) - origin) / dx).astype(np.int64)
+    ii = [np.arange(c0[a], c1[a]) for a in range(3)]
+    sub = np.array([[a, b, c] for c in (0, 1) for b in (0, 1) for a in (0, 1)], np.float64)
+    out = []
+    # iterate over z slabs to bound memory
+    for kz in ii[2]:
+        gx, gy = np.meshgrid(ii[0], ii[1], indexing="ij")
+        cells = np.stack([gx.ravel(), gy.ravel(), np.full(gx.size, kz)], axis=1).astype(np.float64)
+        centres = (cells[:, None, :] + (sub[None, :, :] + 0.5) * 0.5) * dx + origin
+        centres = centres.reshape(-1, 3)
+        keep = inside(centres)
+        if np.any(keep):
+            out.append(centres[keep])
+    if not out:
+        return np.zeros((0, 3), np.float32)
+    P = np.concatenate(out, axis=0)
+    P += rng.uniform(-jitter, jitter, size=P.shape) * (0.5 * dx)
+    return P.astype(np.float32)
+
+
+def _finish(name, params, X, rho, E, rng, steps, tools_at, v0=None):
+    n = X.shape[0]
+    perm = rng.permutation(n)
+    X = np.ascontiguousarray(X[perm])
+    dx = params["dx"]
+    V0 = np.float32(dx ** 3 / 8.0)
+    vol0 = np.full(n, V0, np.float32)
+    mass = (np.float32(rho) * vol0).astype(np.float32)
+    if np.isscalar(E):
+        Ea = np.full(n, E, np.float32)
+    else:
+        Ea = np.ascontiguousarray(np.asarray(E, np.float32)[perm])
+    if v0 is not None:
+        v0 = np.ascontiguousarray(np.asarray(v0, np.float32)[perm])
+    return dict(name=name, params=params, X=X, v0=v0, vol0=vol0, mass=mass, E=Ea, steps=steps,
+                tools_at=tools_at, rho=rho)
+
+
+def _grid(lo, hi, dx, pad=1):
+    """Reference grid covering [lo, hi] with `pad` empty cells on every side."""
+    lo = np.asarray(lo, np.float64)
+    hi = np.asarray(hi, np.float64)
+    origin = lo - pad * dx
+    cells = [int(math.ceil((hi[a] - lo[a]) / dx - 1e-9)) + 2 * pad for a in range(3)]
+    return origin.tolist(), cells
+
+
+def base_params(dx, origin, cells, dt, nu, **kw):
+    """Scene parameters.  A body "on the floor" has its lowest sub-cell centres at
+    z = dx/4; with the jitter of +-dx/8 and contact radius dx/4 its lowest spheres
+    just touch a floor at z = -dx/8, so the scene starts without penetration."""
+    p = dict(dx=float(dx), origin=[float(o) for o in origin], cells=[int(c) for c in cells],
+             dt=float(dt), nu=float(nu), gravity=[0.0, 0.0, -9.81], flip_beta=0.95,
+             max_cuts=4, material_contact=0, floor_on=1, floor_z=-float(dx) / 8.0, single_field=0)
+    p.update(CONTACT_DEFAULTS)
+    p.update(kw)
+    return p
+
+
+def blade(cut_index, x_e, n, d, v_e, half_len, half_width, b_back, b_lead, new_cut=False):
+    n = np.asarray(n, np.float64)
+    d = np.asarray(d, np.float64)
+    e = np.cross(n, d)  # (n, e, d) right-handed with e = n x d
+    return dict(cut_index=int(cut_index), new_cut=int(bool(new_cut)),
+                x_e=np.asarray(x_e, np.float64), n=n, e=e, d=d,
+                v_e=np.asarray(v_e, np.float64), half_len=float(half_len),
+                half_width=float(half_width), b_back=float(b_back), b_lead=float(b_lead))
+
+
+def tool(bl, labels=True, contact=True, cutting=True, x_B=None, v_B=None):
+    return dict(blade=bl, x_B=np.asarray(bl["x_e"] if x_B is None else x_B, np.float64),
+                v_B=np.asarray(bl["v_e"] if v_B is None else v_B, np.float64),
+                omega_B=np.zeros(3), w_B=0.0, labels=bool(labels), contact=bool(contact),
+                cutting=bool(cutting))
+
+
+# --------------------------------------------------------------------------- small
+def small(seed=1, deep=False, steps=100):
+    """Neo-Hookean cube [0, 0.1]^3 on a floor, dx = 5 mm, 8 ppc (64,000 particles),
+    E = 1e5, nu = 0.3, rho = 1000, dt = 1e-4.  A planar blade (0.15 x 0.05 m, plane
+    x = 0.05) descends at 0.2 m/s; it assigns side labels only (no tool contact).
+    deep=True starts the edge at z = 0.06 so the first label pass already cuts."""
+    dx = 0.005
+    origin, cells = _grid((0, 0, 0), (0.1, 0.1, 0.1), dx, pad=1)
+    rng = np.random.default_rng(seed)
+
+    def inside(P):
+        return np.all((P >= 0.0) & (P <= 0.1), axis=1)
+
+    X = jittered_lattice((0, 0, 0), (0.1, 0.1, 0.1), dx, origin, inside, rng)
+    params = base_params(dx, origin, cells, 1e-4, 0.3, material_contact=0, floor_on=1)
+    z0 = 0.06 if deep else 0.10
+    dt = params["dt"]
+
+    def tools_at(j):
+        z = z0 - 0.2 * (j * dt)
+        bl = blade(0, (0.05, 0.05, z), (1, 0, 0), (0, 0, -1), (0, 0, -0.2), 0.075, 6 * dx, 0.05, dx,
+                   new_cut=(j == 0))
+        return [tool(bl, labels=True, contact=False, cutting=False)]
+
+    return _finish("small-deep" if deep else "small", params, X, 1000.0, 1e5, rng, steps, tools_at)
+
+
+# -------------------------------------------------------------------------- medium
+def medium(seed=2, steps=8000, dx=0.002):
+    """Curved cylinder: radius 0.018 m around a horizontal centreline arc of radius
+    0.3 m and length 0.18 m (0.6 rad), resting on the floor; dx = 2 mm, 8 ppc,
+    E = 5e4, nu = 0.3, rho = 1000, dt = 1e-4, material contact on.  Two vertical cuts
+    normal to the centreline at +-3 cm of arc from the middle descend at 0.1 m/s from
+    z = 0.038 to 0; after each cut the blade pushes along its normal (+n, then -n) at
+    0.1 m/s for 0.3 s and is removed."""
+    Rc, rt, half_ang = 0.3, 0.018, 0.3
+    cy = -Rc  # centre of curvature at (0, cy); the arc passes through (0, 0)
+    rng = np.random.default_rng(seed)
+    lo = np.array([-Rc * math.sin(half_ang) - rt, -Rc * (1 - math.cos(half_ang)) - rt, 0.0])
+    hi = np.array([Rc * math.sin(half_ang) + rt, rt, 2 * rt])
+    origin, cells = _grid(lo, hi, dx, pad=1)
+
+    def inside(P):
+        qx, qy = P[:, 0], P[:, 1] - cy
+        ang = np.arctan2(qx, qy)
+        rho = np.hypot(qx, qy)
+        return (np.abs(ang) <= half_ang) & ((rho - Rc) ** 2 + (P[:, 2] - rt) ** 2 <= rt * rt)
+
+    X = jittered_lattice(lo, hi, dx, origin, inside, rng)
+    params = base_params(dx, origin, cells, 1e-4, 0.3, material_contact=1, floor_on=1)
+    dt = params["dt"]
+    t_cut = int(round(0.038 / 0.1 / dt))   # 3800 steps
+    t_push = int(round(0.3 / dt))          # 3000 steps
+    thetas = (-0.1, 0.1)
+    pushes = (1.0, -1.0)
+
+    def frame(th):
+        cpt = np.array([Rc * math.sin(th), cy + Rc * math.cos(th), 0.0])
+        tang = np.array([math.cos(th), -math.sin(th), 0.0])
+        return cpt, tang
+
+    def tools_at(j):
+        k, r = divmod(j, t_cut + t_push)
+        if k >= 2:
+            return []
+        cpt, nrm = frame(thetas[k])
+        if r < t_cut:
+            z = 0.038 - 0.1 * (r * dt)
+            bl = blade(k, (cpt[0], cpt[1], z), nrm, (0, 0, -1), (0, 0, -0.1), 0.075, 6 * dx, 0.05, dx,
+                       new_cut=(r == 0))
+            return [tool(bl, labels=True, contact=True, cutting=True)]
+        s = pushes[k] * 0.1 * ((r - t_cut) * dt)
+        ve = pushes[k] * 0.1 * nrm
+        pos = np.array([cpt[0], cpt[1], 0.0]) + s * nrm
+        bl = blade(k, pos, nrm, (0, 0, -1), ve, 0.075, 6 * dx, 0.05, dx)
+        return [tool(bl, labels=False, contact=True, cutting=False)]
+
+    return _finish("medium", params, X, 1000.0, 5e4, rng, steps, tools_at)
+
+
+# --------------------------------------------------------------------------- large
+def large(seed=3, steps=2000, dx=0.0015, box=(0.3, 0.2, 0.1)):
+    """Box 0.3 x 0.2 x 0.1 m on the floor, 8 ppc, per-particle E log-uniform in
+    [2e4, 2e5], nu = 0.3, rho = 1000, dt = 3e-5, contact on.  Blades at 0.2 m/s, edges
+    pre-inserted at z = 0.06: k0 plane x = 0.10, k1 plane x = 0.20, k2 vertical and
+    rotated 60 degrees from k0, crossing it at (0.10, 0.10); they descend for steps
+    0-999 and are withdrawn; k3 (plane y = 0.10, crossing k0 and k2) descends for
+    steps 1000-1999.  dx = 1.5 mm gives 14.2M particles; dx and box scale it."""
+    bx, by, bz = box
+    rng = np.random.default_rng(seed)
+    origin, cells = _grid((0, 0, 0), box, dx, pad=1)
+
+    def inside(P):
+        return (P[:, 0] >= 0) & (P[:, 0] <= bx) & (P[:, 1] >= 0) & (P[:, 1] <= by) & (P[:, 2] >= 0) & (P[:, 2] <= bz)
+
+    X = jittered_lattice((0, 0, 0), box, dx, origin, inside, rng)
+    E = np.exp(rng.uniform(math.log(2e4), math.log(2e5), size=X.shape[0])).astype(np.float32)
+    params = base_params(dx, origin, cells, 3e-5, 0.3, material_contact=1, floor_on=1)
+    dt = params["dt"]
+    s = bx / 0.3  # keep the blade layout proportional when the box is scaled
+    c60 = (math.cos(math.radians(60)), math.sin(math.radians(60)), 0.0)
+    specs = [  # cut index, edge centre (x, y), normal, half length, active steps
+        (0, (0.10 * s, by / 2), (1, 0, 0), 0.6 * by, (0, 1000)),
+        (1, (0.20 * s, by / 2), (1, 0, 0), 0.6 * by, (0, 1000)),
+        (2, (0.10 * s, 0.10 * by / 0.2), c60, 0.6 * by, (0, 1000)),
+        (3, (bx / 2, 0.10 * by / 0.2), (0, 1, 0), 0.55 * bx, (1000, 2000)),
+    ]
+
+    def tools_at(j):
+        out = []
+        for k, (cx, cy_), nrm, L, (a, b) in specs:
+            if not (a <= j < b):
+                continue
+            z = 0.06 * bz / 0.1 - 0.2 * ((j - a) * dt)
+            bl = blade(k, (cx, cy_, z), nrm, (0, 0, -1), (0, 0, -0.2), L, 6 * dx, 0.05, dx, new_cut=(j == a))
+            out.append(tool(bl, labels=True, contact=True, cutting=True))
+        return out
+
+    return _finish("large", params, X, 1000.0, E, rng, steps, tools_at)
+
+
+# ------------------------------------------------------------------- generic pieces
+def box_scene(n_cells=(6, 5, 4), dx=0.01, seed=0, E=1e4, nu=0.3, rho=1000.0, dt=1e-4, v0=None,
+              jitter=0.25, **kw):
+    """A small box of n_cells reference cells starting at the origin, for unit tests."""
+    rng = np.random.default_rng(seed)
+    hi = np.array(n_cells, np.float64) * dx
+    origin, cells = _grid((0, 0, 0), hi, dx, pad=1)
+
+    def inside(P):
+        return np.all((P >= 0) & (P <= hi), axis=1)
+
+    X = jittered_lattice((0, 0, 0), hi, dx, origin, inside, rng, jitter=jitter)
+    params = base_params(dx, origin, cells, dt, nu, **kw)
+    v = None
+    if v0 is not None:
+        v = np.broadcast_to(np.asarray(v0, np.float32), X.shape).copy()
+    return _finish("box", params, X, rho, E, rng, 1, lambda j: [], v0=v)
+
+
+CONFIGS = {"small": small, "small-deep": lambda **k: small(deep=True, **k), "medium": medium,
+           "large": large}
