@@ -1,0 +1,136 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the TLMPM cutting hot path on one MI355X.
+
+A step is one substep of the whole path: side-label pass of the active blades,
+slot-table maintenance, tool/floor/material contact, label-masked P2G, coupling
+and grid update, G2P, MUSL re-scatter and the deformation-gradient update.  The
+workload is a seeded synthetic scene (paper_2609_27342_amd.workloads) resident in
+HBM before timing; tool schedules run as constant-velocity segments.
+
+Prints ONE JSON line (rank 0) with particle-steps/s, the roofline of the dominant
+kernel (algorithmic bytes over its event-timed duration) and the FP64 CPU oracle
+timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per particle and launch (FP32 state; see the design notes):
+#   P2G kernel: read X 12, code 4, v 12, F 36; write F 36            -> 100 B
+#   G2P kernel: read X 12, code 4, u 12, v 12; write u 12, v 12       ->  64 B
+#   whole substep (each persistent field read/written once)           -> 136 B
+ALG_BYTES = {"p2g": 100, "g2p": 64}
+ALG_STEP_BYTES = 136
+DEFAULTS = {"small": (100, 10), "small-deep": (100, 10), "medium": (2000, 100), "large": (200, 10)}
+
+
+def run_steps(g, scene, j0, j1):
+    from paper_2609_27342_amd import workloads as W
+    for j, cnt, tools in W.segments(scene, j0, j1):
+        g.step([dict(t, advance=True) for t in tools], n_substeps=cnt)
+
+
+def cpu_baseline(scene, budget_s=12.0, max_steps=400):
+    """The FP64 oracle as it stands, single-threaded, on the first substeps of the
+    same workload until about budget_s seconds of CPU time have been spent."""
+    import oracle
+    o = oracle.OracleScene(scene)
+    t0 = time.perf_counter()
+    steps = 0
+    while steps < max_steps and time.perf_counter() - t0 < budget_s:
+        tools = scene["tools_at"](steps)
+        blades = [t["blade"] for t in tools if t["labels"]]
+        if blades:
+            o.assign_labels(blades)
+        o.step([dict(t, contact=int(t["contact"]), cutting=int(t["cutting"])) for t in tools])
+        steps += 1
+    dt = time.perf_counter() - t0
+    n = scene["X"].shape[0]
+    return {"value": n * steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {steps} substeps of {scene['name']} ({n} particles), FP64 C oracle, 1 thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
+    ap.add_argument("--workload", default=os.environ.get("TLMPM_BENCH_WORKLOAD", "medium"))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-steps", type=int, default=200)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
+                                   "described in the design notes, not built)"}))
+        sys.exit(2)
+
+    import torch
+    from paper_2609_27342_amd import tlmpm, workloads as W
+
+    steps_d, warm_d = DEFAULTS.get(args.workload, (200, 10))
+    K = args.steps if args.steps is not None else steps_d
+    Wm = args.warmup if args.warmup is not None else warm_d
+    scene = W.CONFIGS[args.workload]()
+    n = scene["X"].shape[0]
+    torch.cuda.set_device(0)
+    g = tlmpm.Scene(scene)
+    print(f"[bench] workload={args.workload} n={n} warmup={Wm} steps={K}", file=sys.stderr, flush=True)
+    run_steps(g, scene, 0, Wm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run_steps(g, scene, Wm, Wm + K)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / K
+    value = n * K / (t1 - t0)
+    status = g.status()
+    print(f"[bench] timed {K} steps: {ms_per_step:.4f} ms/step, status={status}", file=sys.stderr, flush=True)
+
+    # per-kernel durations from HIP events on the scene's stream, over a following
+    # stretch of the same schedule
+    P = min(args.profile_steps, K)
+    g.profile(True)
+    run_steps(g, scene, Wm + K, Wm + K + P)
+    prof = g.profile_read()
+    g.profile(False)
+    kern = {k: {"ms_avg": (v[0] / v[1]) if v[1] else None, "launches": v[1]} for k, v in prof.items()}
+    dom = max(("p2g", "g2p"), key=lambda k: prof[k][0])
+    avg_s = prof[dom][0] / prof[dom][1] * 1e-3
+    per_particle = ALG_BYTES[dom] + (4 if (dom == "p2g" and scene["E"].min() != scene["E"].max()) else 0)
+    achieved = per_particle * n / avg_s / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "step_alg_frac": value * ALG_STEP_BYTES / (HBM_PEAK_GBS * 1e9), "kernels": kern}
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(scene)
+    out = {
+        "metric": "particle-steps/s per GPU",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": Wm,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "particles": n, "dt": scene["params"]["dt"],
+                   "material_contact": bool(scene["params"]["material_contact"]), "path": "plain"},
+        "status": status,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

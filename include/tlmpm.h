@@ -1,0 +1,174 @@
+/*
+ * tlmpm.h -- C ABI of the MI355X (gfx950) TLMPM cutting library.
+ *
+ * One substep of total-Lagrangian MPM with persistent ternary side labels, as in
+ * BladeMaster (arXiv 2609.27342):
+ *   - online side-label assignment from the swept blade (Sec. III-C, Eqs. 3, 4, 6, 7);
+ *   - tool-material contact with directional contact work (Sec. III-E, Eqs. 5, 14-16)
+ *     and material-material contact (Eqs. 10-13);
+ *   - label-masked P2G of mass, momentum and internal force on the fixed reference
+ *     grid (Sec. III-B, Eqs. 1, 2);
+ *   - compatibility coupling and the grid update (Sec. III-D, Eqs. 8, 9);
+ *   - PIC/FLIP G2P of v and x, MUSL re-scatter with the same coupling and the
+ *     deformation-gradient update (Sec. III-B, App. Eq. 17).
+ *
+ * Conventions
+ *   - Every call returns a tlmpm_status; nothing throws across the ABI.  The text of
+ *     the last error of the calling thread is returned by tlmpm_last_error().
+ *   - Host arrays are owned by the caller and only read during the call.
+ *   - Device memory: the caller provides ONE device workspace of at least
+ *     tlmpm_scene_footprint() bytes (for instance a torch uint8 tensor) and keeps it
+ *     alive until tlmpm_destroy_scene().  The library never allocates device memory.
+ *   - Streams: the caller's HIP stream (hipStream_t passed as void*; NULL = default).
+ *     Calls are asynchronous on that stream except tlmpm_read_state, tlmpm_write_state,
+ *     tlmpm_get_status and a tlmpm_step given a non-NULL wrench pointer, which
+ *     synchronise it.
+ *   - Device-side failures (non-finite state, det F <= 0, too many logical grids at a
+ *     node) are sticky per scene and reported by the next synchronising call.
+ *   - A scene is used by one host thread at a time.
+ */
+#ifndef TLMPM_H
+#define TLMPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TLMPM_OK = 0,
+    TLMPM_E_INVALID = 1,       /* bad argument, particle outside the grid, bad blade frame */
+    TLMPM_E_NOMEM = 2,         /* workspace smaller than tlmpm_scene_footprint() */
+    TLMPM_E_DEVICE = 3,        /* a HIP runtime call failed */
+    TLMPM_E_SLOT_OVERFLOW = 4, /* more logical grids at a node than slot_capacity */
+    TLMPM_E_NONFINITE = 5      /* non-finite state or det F <= 0 */
+} tlmpm_status;
+
+typedef struct tlmpm_scene tlmpm_scene; /* opaque */
+
+/* Scene description (SI units).  Host arrays are array-of-structs as given. */
+typedef struct {
+    int64_t n;              /* number of particles (material points) */
+    const float* X;         /* [n][3] reference positions X_p (Sec. III-A) */
+    const float* v0;        /* [n][3] initial velocities, or NULL for zero; F0 = I */
+    const float* vol0;      /* [n] reference volumes V_p^0, or NULL => vol0_uniform */
+    const float* mass;      /* [n] masses m_p, or NULL => mass_uniform */
+    const float* E;         /* [n] Young's moduli, or NULL => E_uniform */
+    float vol0_uniform, mass_uniform, E_uniform;
+    float nu;               /* Poisson ratio */
+    double dx;              /* reference grid spacing */
+    double origin[3];       /* position of reference node (0,0,0) */
+    int32_t cells[3];       /* reference cells per axis; every X must lie inside */
+    double dt;              /* substep size */
+    float gravity[3];
+    float flip_beta;        /* PIC/FLIP blend of Eq. 17 */
+    /* contact (Sec. III-E): radius scale, normal scale, tangential stiffness and
+     * damping scales, static and dynamic friction */
+    float s_R, s_n, gamma_k, gamma_c, mu_s, mu_d;
+    int32_t material_contact;  /* material-material contact on */
+    int32_t floor_on;          /* rigid half-space z >= floor_z, outward normal +z */
+    float floor_z;
+    float G_c, zeta, u_min;    /* cutting-work threshold parameters (Eq. 5) */
+    int32_t max_cuts;          /* K, number of ternary digits (1..15) */
+    int32_t single_field;      /* 1: ignore codes (one logical grid), a negative control */
+} tlmpm_scene_desc;
+
+/* A blade record: the cut frame of Eq. 3 and the band of Eq. 4.  (n, e, d) must be
+ * orthonormal with d pointing toward the cutting front.  Doubles: the side
+ * predicates are evaluated in FP64. */
+typedef struct {
+    int32_t cut_index;       /* k: the ternary digit this blade assigns, 0..max_cuts-1 */
+    int32_t new_cut;         /* nonzero: start of cut k, reset D_p := 0 (Sec. III-A) */
+    double x_e[3];           /* point at the middle of the blade edge */
+    double n[3], e[3], d[3]; /* plane normal, edge axis, front direction */
+    double v_e[3];           /* velocity of x_e */
+    double half_len;         /* L_k: half length of the edge */
+    double half_width;       /* h_k: band half width (the paper uses 6 dx) */
+    double b_back;           /* band rear extent; also the blade height behind the edge */
+    double b_lead;           /* band lead extent */
+} tlmpm_blade;
+
+#define TLMPM_TOOL_LABELS 1u   /* assign side digits from the blade band each substep */
+#define TLMPM_TOOL_CONTACT 2u  /* tool-material contact (Eqs. 14-16) */
+#define TLMPM_TOOL_CUTTING 4u  /* directional contact work and release (Eq. 5) */
+#define TLMPM_TOOL_ADVANCE 8u  /* translate the pose by dt * velocity after each substep */
+
+/* A kinematic rigid tool: the zero-thickness rectangle of its blade record,
+ * |l| <= half_len along e and -b_back <= f <= 0 along d, in the plane s = 0. */
+typedef struct {
+    tlmpm_blade blade;
+    double x_B[3];     /* torque reference point of the tool (Eq. 16) */
+    double v_B[3];     /* linear velocity */
+    double omega_B[3]; /* angular velocity */
+    double w_B;        /* inverse effective mass along the normal; 0 = prescribed */
+    uint32_t flags;    /* TLMPM_TOOL_* */
+    int32_t reserved;
+} tlmpm_tool;
+
+/* Device bytes a scene of this description needs (depends on n, cells and the
+ * contact switches only). */
+tlmpm_status tlmpm_scene_footprint(const tlmpm_scene_desc* desc, size_t* device_bytes);
+
+/* Build a scene: validates the description, sorts particles by reference cell,
+ * carves the caller's workspace and uploads the state on `hip_stream`. */
+tlmpm_status tlmpm_create_scene(const tlmpm_scene_desc* desc, void* dev_workspace, size_t bytes,
+                                void* hip_stream, tlmpm_scene** out);
+
+tlmpm_status tlmpm_destroy_scene(tlmpm_scene* scene);
+
+/* Side-label pass (Eqs. 3, 4, 6) on the stored x^n, v^n for each blade in turn.
+ * Digits only go 0 -> 1 or 2.  A blade with new_cut first resets D to zero for
+ * every particle.  Labels govern the next substep's contact and P2G. */
+tlmpm_status tlmpm_assign_labels(tlmpm_scene* scene, const tlmpm_blade* blades, int32_t n_blades);
+
+/* n_substeps TLMPM substeps.  Each substep: label pass for tools with
+ * TLMPM_TOOL_LABELS, contact, P2G, coupling, grid update, G2P, re-scatter; the
+ * deformation-gradient update of a substep is completed lazily by the next one
+ * (or by tlmpm_read_state).  The tool pose is held fixed over the substeps unless
+ * TLMPM_TOOL_ADVANCE is set.  wrench: NULL, or [n_tools][6] (force, torque on each
+ * tool) averaged over the substeps so that it carries the same impulse (Sec.
+ * III-G); a non-NULL pointer synchronises. */
+tlmpm_status tlmpm_step(tlmpm_scene* scene, const tlmpm_tool* tools, int32_t n_tools, int32_t n_substeps,
+                        double* wrench);
+
+#define TLMPM_FIELD_X 1u      /* float [n][3] reference positions */
+#define TLMPM_FIELD_U 2u      /* float [n][3] displacement x - X */
+#define TLMPM_FIELD_V 4u      /* float [n][3] velocity */
+#define TLMPM_FIELD_F 8u      /* float [n][9] deformation gradient, row major */
+#define TLMPM_FIELD_CODE 16u  /* uint64 [n] ternary code sum_k d_k 3^k (Eq. 7) */
+#define TLMPM_FIELD_D 32u     /* float [n] cutting progress */
+#define TLMPM_FIELD_DIGITS 64u /* uint8 [n][max_cuts] ternary digits */
+
+/* Copy fields to host buffers in the caller's original particle order.  host_out
+ * has one pointer per bit of field_mask, in increasing bit order.  Synchronises. */
+tlmpm_status tlmpm_read_state(tlmpm_scene* scene, uint32_t field_mask, void* const* host_out);
+
+/* Overwrite fields from host buffers (original order; same layout as read_state;
+ * TLMPM_FIELD_X and TLMPM_FIELD_CODE are not writable).  For restarts and
+ * shared-input comparisons.  Synchronises. */
+tlmpm_status tlmpm_write_state(tlmpm_scene* scene, uint32_t field_mask, const void* const* host_in);
+
+/* Sticky device status of the scene (a tlmpm_status value, 0 = OK).  Synchronises. */
+tlmpm_status tlmpm_get_status(tlmpm_scene* scene, int32_t* status);
+
+/* Diagnostics: number of occupied logical-grid slots over all nodes and the
+ * largest count at one node (Sec. III-G, compact slots).  Synchronises. */
+tlmpm_status tlmpm_slot_stats(tlmpm_scene* scene, int64_t* total_slots, int32_t* max_per_node);
+
+/* Kernel timing (diagnostics).  While enabled, every kernel the scene launches is
+ * bracketed by HIP events on the scene's stream.  tlmpm_profile_read synchronises
+ * and returns, per kernel class (0 P2G, 1 grid update + G2P, 2 labels, 3 slot
+ * tables, 4 material contact, 5 other), the summed duration in ms and the launch
+ * count, then clears the record.  n_classes: length of both output arrays (<= 6). */
+tlmpm_status tlmpm_profile_enable(tlmpm_scene* scene, int32_t enable);
+tlmpm_status tlmpm_profile_read(tlmpm_scene* scene, int32_t n_classes, double* ms, int64_t* launches);
+
+/* Text of the last error on the calling thread ("" if none). */
+const char* tlmpm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TLMPM_H */

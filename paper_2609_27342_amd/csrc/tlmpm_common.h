@@ -1,0 +1,122 @@
+// tlmpm_common.h -- structures shared by the host runtime and the gfx950 kernels.
+//
+// Layout in HBM (one scene, all carved from the caller's workspace):
+//   particles, sorted by (brick, cell parity class, cell, input order), SoA float:
+//     X[3][N] reference positions, u[3][N] = x - X, v[3][N], H[9][N] = F - I
+//   code[N]      u32: side mask s1 (bits 0-14: digit == 1), s2 (bits 15-29: digit == 2),
+//                bit 30: code_prev[p] holds the code the pending F update must use,
+//                bit 31: material-contact candidate
+//   grid: node ids are brick-major, id = nodebrick * 64 + (lz * 16 + ly * 4 + lx)
+//     slot tables (two buffers): count[node] u8, code[S_CAP][node] u32 (ascending)
+//     P2G partials  [8 contributors][S_CAP][7][node] float  (m, p, dp)
+//     MUSL partials [8 contributors][S_CAP][4][node] float  (m, p~)
+#pragma once
+#include <stdint.h>
+
+#define TL_B 4                 // cells per brick edge
+#define TL_CELLS 64            // cells per brick
+#define TL_BOXN 125            // nodes of a brick's (TL_B + 1)^3 box
+#define TL_SCAP 8              // logical grids (slots) per node
+#define TL_BOX_SLOTS 512       // slots of one brick box held in LDS
+#define TL_MAX_TOOLS 4          // tools per scene (rigid-history slots 1..4; slot 0 = floor)
+#define TL_WG 512              // threads per brick workgroup: 8 waves = 8 parity classes
+
+#define TL_CODE_MASK 0x3FFFFFFFu
+#define TL_PREV_BIT 0x40000000u
+#define TL_CAND_BIT 0x80000000u
+
+// status bits (device, sticky)
+#define TL_ST_NONFINITE 1
+#define TL_ST_SLOT 2
+#define TL_ST_BOX 4
+#define TL_ST_LOOKUP 8
+#define TL_ST_CONTACT 16
+
+#define TL_PCAP 12             // persistent pair springs kept per particle
+
+// tool flags (same values as the ABI)
+#define TL_TOOL_LABELS 1u
+#define TL_TOOL_CONTACT 2u
+#define TL_TOOL_CUTTING 4u
+#define TL_TOOL_ADVANCE 8u
+
+struct DevBlade {
+    double xe[3], n[3], e[3], d[3], ve[3];
+    double half_len, half_width, b_back, b_lead;
+    int cut, new_cut;
+};
+
+// A tool as the kernels see it (device memory).  With TL_TOOL_ADVANCE the pose of
+// substep j is the stored pose translated by (j dt) times the velocity.
+struct DevTool {
+    DevBlade b;
+    double xB[3], vB[3];
+    float wB[3];
+    float invm;
+    unsigned flags;
+    int slot; // rigid-history slot 1..TL_MAX_TOOLS (0 is the floor)
+};
+
+// scalar parameters of a scene, passed to every kernel by value
+struct SceneK {
+    long long N;
+    int cx, cy, cz;       // cells
+    int cbx, cby, cbz;    // cell bricks
+    int nbx, nby, nbz;    // node bricks
+    long long NN;         // node ids = nbx*nby*nbz*64
+    double ox, oy, oz, dx, inv_dx_d;
+    float inv_dx;
+    float dt, beta, gx, gy, gz;
+    float nu;
+    int e_uniform, m_uniform, v_uniform;
+    float E0, m0, V0;
+    float s_R, s_n, gamma_k, gamma_c, mu_s, mu_d;
+    float Rmax;           // largest contact radius s_R V0^{1/3} / 2
+    int floor_on;
+    float floor_z;
+    float G_c, zeta, u_min;
+    int single_field;
+    int material_contact;
+    double dt_d;
+};
+
+// device pointers of a scene
+struct SceneD {
+    float* X;      // [3][N]
+    float* u;      // [3][N]
+    float* v;      // [3][N]
+    float* H;      // [9][N]
+    uint32_t* code;
+    uint32_t* code_prev;
+    float* D;
+    int* perm;     // sorted index -> caller's index
+    float* E;      // [N] or null
+    float* m;      // [N] or null
+    float* V0;     // [N] or null
+    int* cell_start;   // [n_bricks*64 + 1]
+    int* active;       // active brick ids
+    int n_active;
+    uint8_t* cnt[2];
+    uint32_t* scode[2];
+    float* p2g;    // [8][S][7][NN]
+    float* rs;     // [8][S][4][NN]
+    float* hist;   // rigid contact history [TL_MAX_TOOLS+1][4][N]: u_t xyz, stamp
+    float* aabb;   // [n_bricks][8]: min xyz, max xyz, max |v|, 0
+    float* wpart;  // [n_active][TL_MAX_TOOLS][6]
+    double* wacc;  // [TL_MAX_TOOLS][6]
+    float* Jmat;   // [3][N] material contact impulse (candidates only)
+    DevTool* tools;   // [TL_MAX_TOOLS] tools (or label-only blades) of the current call
+    int* status;
+    int* dirty;
+    // material contact
+    uint32_t* cmask;    // [cells] OR of the codes of each cell (sorted cell order)
+    uint8_t* cstatic;   // [cells] cell has an empty or out-of-grid neighbour
+    int* bcand;         // [bricks] brick holds a candidate
+    float* hbin;        // bin edge (device scalar)
+    unsigned long long* htab; // hash buckets: generation << 32 | head
+    uint32_t hmask;     // buckets - 1 (power of two)
+    int* hnext;         // [N] bucket list links
+    int* ph_n;          // [2][N] stamp << 8 | count of owned springs
+    int* ph_q;          // [2][N][TL_PCAP] partner of each spring
+    float* ph_u;        // [2][N][TL_PCAP][3] spring, oriented for the owner
+};

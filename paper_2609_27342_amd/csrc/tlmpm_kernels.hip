@@ -1,0 +1,1192 @@
+// tlmpm_kernels.hip -- gfx950 kernels of one TLMPM cutting substep.
+//
+// Work decomposition.  Particles are sorted into bricks of 4x4x4 reference cells;
+// inside a brick by cell parity class (8 classes of 8 cells that share no grid node)
+// and then by cell.  One 512-thread workgroup owns one brick: wave w holds parity
+// class w, lane (i, j) holds particle j of cell i of that class.  A brick touches
+// the 5x5x5 box of nodes around it.
+//
+// Particle-to-grid sums are gathers with a fixed order, without float atomics:
+//   1. every lane forms its particle's contribution to the 8 corner nodes of its
+//      cell;
+//   2. an 8-lane butterfly reduce-scatter leaves in lane (i, k) the sum of cell i's
+//      particles for corner k;
+//   3. the 8 waves add their per-node sums into LDS one class after another;
+//   4. the box sums are written as this brick's partial; a node's total is the sum
+//      of the partials of the (up to 8) bricks around it, formed in fixed order by
+//      the kernel that consumes it.
+//
+// Each node holds one slot (logical grid, Sec. III-D) per side code present in its
+// 8 incident cells, in ascending code order; coupling (Eq. 8) is done per node when
+// a box is finalized.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "tlmpm_common.h"
+
+#define DEV __device__ __forceinline__
+
+// ---------------------------------------------------------------------------- codes
+// A side code is held as two 15-bit masks: s1 has bit k set when digit k is 1, s2
+// when it is 2 (Eq. 7 in another basis).  Two codes conflict iff some cut has side
+// 1 in one and side 2 in the other (Sec. III-D).
+DEV bool codes_conflict(uint32_t a, uint32_t b)
+{
+    uint32_t a1 = a & 0x7FFFu, a2 = (a >> 15) & 0x7FFFu;
+    uint32_t b1 = b & 0x7FFFu, b2 = (b >> 15) & 0x7FFFu;
+    return ((a1 & b2) | (a2 & b1)) != 0u;
+}
+
+DEV uint32_t slot_key(const SceneK& S, uint32_t code) { return S.single_field ? 0u : (code & TL_CODE_MASK); }
+
+DEV int box_index(int X, int Y, int Z) { return (Z * 5 + Y) * 5 + X; }
+
+// Global node id of box node (X, Y, Z) of cell brick (bx, by, bz); -1 outside the grid.
+DEV long long box_gid(const SceneK& S, int bx, int by, int bz, int X, int Y, int Z)
+{
+    int gx = bx * TL_B + X, gy = by * TL_B + Y, gz = bz * TL_B + Z;
+    if (gx > S.cx || gy > S.cy || gz > S.cz) return -1;
+    long long nb = ((long long)(gz >> 2) * S.nby + (gy >> 2)) * S.nbx + (gx >> 2);
+    return (nb << 6) | ((gz & 3) * 16 + (gy & 3) * 4 + (gx & 3));
+}
+
+// ------------------------------------------------------------------- box slot table
+struct BoxTab {
+    int cnt[TL_BOXN];
+    int base[TL_BOXN + 1];
+    long long gid[TL_BOXN];
+    uint32_t code[TL_BOX_SLOTS];
+    unsigned char node_of[TL_BOX_SLOTS];
+};
+
+// Loads the slot table of a brick box into LDS.  Returns the number of box slots,
+// or -1 if they exceed TL_BOX_SLOTS (the whole block sees the same value).
+DEV int load_box(const SceneK& S, const uint8_t* cnt, const uint32_t* scode, int bx, int by, int bz, BoxTab& T,
+                 int* s_total)
+{
+    const int tid = threadIdx.x;
+    if (tid < TL_BOXN) {
+        int X = tid % 5, Y = (tid / 5) % 5, Z = tid / 25;
+        long long g = box_gid(S, bx, by, bz, X, Y, Z);
+        T.gid[tid] = g;
+        T.cnt[tid] = g >= 0 ? (int)cnt[g] : 0;
+    }
+    __syncthreads();
+    if (tid < 64) { // wave 0: exclusive scan of 125 counts, two per lane
+        int a = 2 * tid, b = 2 * tid + 1;
+        int va = a < TL_BOXN ? T.cnt[a] : 0;
+        int vb = b < TL_BOXN ? T.cnt[b] : 0;
+        int s = va + vb, incl = s;
+        for (int o = 1; o < 64; o <<= 1) {
+            int t = __shfl_up(incl, o, 64);
+            if (tid >= o) incl += t;
+        }
+        int excl = incl - s;
+        if (a < TL_BOXN) T.base[a] = excl;
+        if (b < TL_BOXN) T.base[b] = excl + va;
+        if (tid == 63) {
+            T.base[TL_BOXN] = incl;
+            *s_total = incl;
+        }
+    }
+    __syncthreads();
+    int total = *s_total;
+    if (total > TL_BOX_SLOTS) return -1;
+    if (tid < TL_BOXN) {
+        int c = T.cnt[tid], b0 = T.base[tid];
+        long long g = T.gid[tid];
+        for (int s = 0; s < c; s++) {
+            T.code[b0 + s] = scode[(long long)s * S.NN + g];
+            T.node_of[b0 + s] = (unsigned char)tid;
+        }
+    }
+    __syncthreads();
+    return total;
+}
+
+DEV int find_slot(const BoxTab& T, int bn, uint32_t key)
+{
+    int c = T.cnt[bn], b0 = T.base[bn];
+    if (c == 1) return T.code[b0] == key ? b0 : -1;
+    for (int s = 0; s < c; s++)
+        if (T.code[b0 + s] == key) return b0 + s;
+    return -1;
+}
+
+// Sum of one box slot over the bricks that contributed to its node, in fixed
+// contributor order.  part: [8][TL_SCAP][Q][NN].
+template <int Q>
+DEV void gather_slot(const SceneK& S, const float* __restrict__ part, const BoxTab& T, int q, int bx, int by, int bz,
+                     float* out)
+{
+    int bn = T.node_of[q];
+    int s = q - T.base[bn];
+    long long g = T.gid[bn];
+    int X = bn % 5, Y = (bn / 5) % 5, Z = bn / 25;
+    // home brick of the node and its local coordinates
+    int hx = bx + (X >> 2), hy = by + (Y >> 2), hz = bz + (Z >> 2);
+    int lx = X & 3, ly = Y & 3, lz = Z & 3;
+    for (int c = 0; c < Q; c++) out[c] = 0.0f;
+    for (int d = 0; d < 8; d++) {
+        int dx = d & 1, dy = (d >> 1) & 1, dz = (d >> 2) & 1;
+        if ((dx && lx) || (dy && ly) || (dz && lz)) continue;
+        int cbx = hx - dx, cby = hy - dy, cbz = hz - dz;
+        if (cbx < 0 || cby < 0 || cbz < 0 || cbx >= S.cbx || cby >= S.cby || cbz >= S.cbz) continue;
+        const float* pp = part + ((long long)(d * TL_SCAP + s) * Q) * S.NN + g;
+        for (int c = 0; c < Q; c++) out[c] += pp[(long long)c * S.NN];
+    }
+}
+
+// Compatibility coupling of one 3-vector field at a node with slots [b0, b0+c)
+// (Eq. 8): f_a += (1/M) sum_{b != a, compatible} (m_a f_b - m_b f_a), M = sum of
+// all slot masses; fields read from src (stride Q, offset off) and written to dst
+// (stride 3), all pre-exchange values.
+template <int Q>
+DEV void couple_node(const BoxTab& T, int b0, int c, const float* src, int off, float* dst)
+{
+    if (c == 1) {
+        for (int j = 0; j < 3; j++) dst[b0 * 3 + j] = src[b0 * Q + off + j];
+        return;
+    }
+    float M = 0.0f;
+    for (int a = 0; a < c; a++) M += src[(b0 + a) * Q];
+    float invM = M > 0.0f ? 1.0f / M : 0.0f;
+    for (int a = 0; a < c; a++) {
+        uint32_t ca = T.code[b0 + a];
+        float ma = src[(b0 + a) * Q];
+        float fa[3] = {src[(b0 + a) * Q + off], src[(b0 + a) * Q + off + 1], src[(b0 + a) * Q + off + 2]};
+        float acc[3] = {0.0f, 0.0f, 0.0f};
+        for (int b = 0; b < c; b++) {
+            if (b == a || codes_conflict(ca, T.code[b0 + b])) continue;
+            float mb = src[(b0 + b) * Q];
+            for (int j = 0; j < 3; j++) acc[j] += ma * src[(b0 + b) * Q + off + j] - mb * fa[j];
+        }
+        for (int j = 0; j < 3; j++) dst[(b0 + a) * 3 + j] = fa[j] + acc[j] * invM;
+    }
+}
+
+// ------------------------------------------------------------- particle geometry
+struct Lane {
+    int w, lane, i, j;
+    int cxl, cyl, czl; // cell inside the brick
+    int beg, count;    // particles of the cell
+};
+
+DEV Lane lane_of(const SceneD& D, int brick)
+{
+    Lane L;
+    int tid = threadIdx.x;
+    L.w = tid >> 6;
+    L.lane = tid & 63;
+    L.i = L.lane >> 3;
+    L.j = L.lane & 7;
+    L.cxl = 2 * (L.i & 1) + (L.w & 1);
+    L.cyl = 2 * ((L.i >> 1) & 1) + ((L.w >> 1) & 1);
+    L.czl = 2 * ((L.i >> 2) & 1) + ((L.w >> 2) & 1);
+    const int* cs = D.cell_start + (long long)brick * TL_CELLS + L.w * 8 + L.i;
+    L.beg = cs[0];
+    L.count = cs[1] - cs[0];
+    return L;
+}
+
+// fractional position inside the base cell (reading R1), in [0, 1]
+DEV void frac_of(const SceneK& S, const float* X, int gxc, int gyc, int gzc, float t[3])
+{
+    double q0 = ((double)X[0] - S.ox) * S.inv_dx_d - (double)gxc;
+    double q1 = ((double)X[1] - S.oy) * S.inv_dx_d - (double)gyc;
+    double q2 = ((double)X[2] - S.oz) * S.inv_dx_d - (double)gzc;
+    t[0] = fminf(fmaxf((float)q0, 0.0f), 1.0f);
+    t[1] = fminf(fmaxf((float)q1, 0.0f), 1.0f);
+    t[2] = fminf(fmaxf((float)q2, 0.0f), 1.0f);
+}
+
+DEV void corner_weights(const float t[3], int k, float& wx, float& wy, float& wz)
+{
+    wx = (k & 1) ? t[0] : 1.0f - t[0];
+    wy = (k & 2) ? t[1] : 1.0f - t[1];
+    wz = (k & 4) ? t[2] : 1.0f - t[2];
+}
+
+// --------------------------------------------------------- butterfly reduce-scatter
+// gen(k, out) produces this lane's contribution to corner k of its cell.  Result:
+// res[Q] = sum over the 8 lanes of the cell group of their corner-(lane & 7)
+// values.  Corners are generated in pairs so at most 4 x Q partial sums are live.
+template <int Q, class Gen>
+DEV void reduce_scatter8(Gen&& gen, float (&res)[Q], int j)
+{
+    float c1[4][Q];
+    const bool b2 = (j >> 2) & 1;
+#pragma unroll
+    for (int kk = 0; kk < 4; kk++) {
+        float lo[Q], hi[Q];
+        gen(kk, lo);
+        gen(kk | 4, hi);
+#pragma unroll
+        for (int q = 0; q < Q; q++) {
+            float send = b2 ? lo[q] : hi[q];
+            float keep = b2 ? hi[q] : lo[q];
+            c1[kk][q] = keep + __shfl_xor(send, 4, 64);
+        }
+    }
+    float c2[2][Q];
+    const bool b1 = (j >> 1) & 1;
+#pragma unroll
+    for (int kk = 0; kk < 2; kk++)
+#pragma unroll
+        for (int q = 0; q < Q; q++) {
+            float send = b1 ? c1[kk][q] : c1[kk | 2][q];
+            float keep = b1 ? c1[kk | 2][q] : c1[kk][q];
+            c2[kk][q] = keep + __shfl_xor(send, 2, 64);
+        }
+    const bool b0 = j & 1;
+#pragma unroll
+    for (int q = 0; q < Q; q++) {
+        float send = b0 ? c2[0][q] : c2[1][q];
+        float keep = b0 ? c2[1][q] : c2[0][q];
+        res[q] = keep + __shfl_xor(send, 1, 64);
+    }
+}
+
+// Adds a wave's per-node sums to the LDS box accumulator, one parity class after
+// another (fixed order).  Fast path: every cell of the wave holds one code.
+// Otherwise the codes present in the wave are processed in ascending order with
+// the other codes' contributions masked out.
+template <int Q, class Gen>
+DEV void accumulate_classes(const Lane& L, bool valid, uint32_t key, Gen&& gen, const BoxTab& T, float* acc,
+                            int* status)
+{
+    const int leader = L.lane & ~7;
+    uint32_t lkey = __shfl(key, leader, 64);
+    bool gvalid = __shfl((int)valid, leader, 64) != 0;
+    bool mixed = valid && key != lkey;
+    bool wave_mixed = __any(mixed);
+    float res[Q];
+    if (!wave_mixed) reduce_scatter8<Q>(gen, res, L.j);
+    const int bn = box_index(L.cxl + (L.j & 1), L.cyl + ((L.j >> 1) & 1), L.czl + ((L.j >> 2) & 1));
+    for (int phase = 0; phase < 8; phase++) {
+        __syncthreads();
+        if (L.w != phase) continue;
+        if (!wave_mixed) {
+            if (gvalid) {
+                int sl = find_slot(T, bn, lkey);
+                if (sl < 0)
+                    atomicOr(status, TL_ST_LOOKUP);
+                else
+                    for (int q = 0; q < Q; q++) acc[sl * Q + q] += res[q];
+            }
+        } else {
+            bool pending = valid;
+            while (__any(pending)) {
+                uint32_t mk = pending ? key : 0xFFFFFFFFu;
+                for (int o = 32; o >= 1; o >>= 1) {
+                    uint32_t t = (uint32_t)__shfl_xor((int)mk, o, 64);
+                    mk = t < mk ? t : mk;
+                }
+                const bool mine = pending && key == mk;
+                auto masked = [&](int k, float* out) {
+                    gen(k, out);
+#pragma unroll
+                    for (int q = 0; q < Q; q++) out[q] = mine ? out[q] : 0.0f;
+                };
+                reduce_scatter8<Q>(masked, res, L.j);
+                unsigned long long bal = __ballot(mine);
+                bool present = ((bal >> leader) & 0xFFull) != 0ull;
+                if (present) {
+                    int sl = find_slot(T, bn, mk);
+                    if (sl < 0)
+                        atomicOr(status, TL_ST_LOOKUP);
+                    else
+                        for (int q = 0; q < Q; q++) acc[sl * Q + q] += res[q];
+                }
+                pending = pending && !mine;
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// Writes the box accumulator as this brick's partial.  part: [8][TL_SCAP][Q][NN].
+template <int Q>
+DEV void write_partials(const SceneK& S, float* __restrict__ part, const BoxTab& T, int total, const float* acc)
+{
+    for (int q = threadIdx.x; q < total; q += blockDim.x) {
+        int bn = T.node_of[q];
+        int s = q - T.base[bn];
+        int X = bn % 5, Y = (bn / 5) % 5, Z = bn / 25;
+        int k = (X == 4) | ((Y == 4) << 1) | ((Z == 4) << 2);
+        float* pp = part + ((long long)(k * TL_SCAP + s) * Q) * S.NN + T.gid[bn];
+        for (int c = 0; c < Q; c++) pp[(long long)c * S.NN] = acc[q * Q + c];
+    }
+}
+
+// ------------------------------------------------------------- constitutive model
+// Compressible Neo-Hookean first Piola-Kirchhoff stress written in H = F - I so
+// that small strains keep their relative precision in FP32:
+//   cof(F) = (1 + tr H) I - H^T + cof(H),  J = 1 + tr H + I2(H) + det H,
+//   F - F^{-T} = [(I2 + det H) I + J H + H^T - cof(H)] / J,
+//   P = mu (F - F^{-T}) + lambda ln J F^{-T}.
+// Returns false when J <= 0 or the state is not finite.
+DEV bool neo_hookean(float E, float nu, const float* H, float* P)
+{
+    const float mu = E / (2.0f * (1.0f + nu));
+    const float lam = E * nu / ((1.0f + nu) * (1.0f - 2.0f * nu));
+    float cH[9];
+    cH[0] = H[4] * H[8] - H[5] * H[7];
+    cH[1] = H[5] * H[6] - H[3] * H[8];
+    cH[2] = H[3] * H[7] - H[4] * H[6];
+    cH[3] = H[2] * H[7] - H[1] * H[8];
+    cH[4] = H[0] * H[8] - H[2] * H[6];
+    cH[5] = H[1] * H[6] - H[0] * H[7];
+    cH[6] = H[1] * H[5] - H[2] * H[4];
+    cH[7] = H[2] * H[3] - H[0] * H[5];
+    cH[8] = H[0] * H[4] - H[1] * H[3];
+    const float trH = H[0] + H[4] + H[8];
+    const float I2 = cH[0] + cH[4] + cH[8];
+    const float I3 = H[0] * cH[0] + H[1] * cH[1] + H[2] * cH[2];
+    const float Jm1 = trH + (I2 + I3);
+    const float J = 1.0f + Jm1;
+    if (!(J > 0.0f) || !isfinite(J)) return false;
+    const float invJ = 1.0f / J;
+    const float lnJ = log1pf(Jm1);
+    const float e0 = I2 + I3;
+#pragma unroll
+    for (int r = 0; r < 3; r++)
+#pragma unroll
+        for (int s = 0; s < 3; s++) {
+            int rs = 3 * r + s, sr = 3 * s + r;
+            float id = (r == s) ? 1.0f : 0.0f;
+            float FmFiT = (id * e0 + J * H[rs] + H[sr] - cH[rs]) * invJ;
+            float FiT = (id * (1.0f + trH) - H[sr] + cH[rs]) * invJ;
+            P[rs] = mu * FmFiT + lam * lnJ * FiT;
+        }
+    return true;
+}
+
+// ------------------------------------------------------- history-based friction
+// Tangential spring transported to the current tangent plane (length kept), trial
+// force -k_t u - c_t v_t, stick below mu_s f_n, else slip at mu_d f_n with the
+// spring reset to match the applied force (Eq. 12).
+DEV void friction(const SceneK& S, const float vrel[3], const float n[3], float fn, float meff, float u[3],
+                  float ft[3])
+{
+    float dt = S.dt;
+    float un = u[0] * n[0] + u[1] * n[1] + u[2] * n[2];
+    float up[3] = {u[0] - un * n[0], u[1] - un * n[1], u[2] - un * n[2]};
+    float lu = sqrtf(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    float lp = sqrtf(up[0] * up[0] + up[1] * up[1] + up[2] * up[2]);
+    float sc = lp > 0.0f ? lu / lp : 0.0f;
+    float ut[3] = {up[0] * sc, up[1] * sc, up[2] * sc};
+    float vn = vrel[0] * n[0] + vrel[1] * n[1] + vrel[2] * n[2];
+    float vt[3] = {vrel[0] - vn * n[0], vrel[1] - vn * n[1], vrel[2] - vn * n[2]};
+    float kt = S.gamma_k * meff / (dt * dt);
+    float ct = 2.0f * S.gamma_c * sqrtf(meff * kt);
+    float ftr[3] = {-kt * ut[0] - ct * vt[0], -kt * ut[1] - ct * vt[1], -kt * ut[2] - ct * vt[2]};
+    float lf = sqrtf(ftr[0] * ftr[0] + ftr[1] * ftr[1] + ftr[2] * ftr[2]);
+    if (lf <= S.mu_s * fn) {
+        for (int a = 0; a < 3; a++) {
+            ft[a] = ftr[a];
+            u[a] = ut[a] + dt * vt[a];
+        }
+    } else {
+        float sl = S.mu_d * fn / lf;
+        for (int a = 0; a < 3; a++) {
+            ft[a] = ftr[a] * sl;
+            u[a] = -(ft[a] + ct * vt[a]) / kt;
+        }
+    }
+}
+
+// One rigid body against one particle (Eqs. 14-16, 5).  body 0 = floor, else tool.
+// Returns the impulse on the particle in J (added), updates D and the wrench sums.
+DEV void rigid_one(const SceneK& S, const SceneD& D, const DevTool* T, int slot, long long p, const float x[3],
+                   const float v[3], float m, float V0, float R, int stamp, double jdt, float J[3], float& Dp,
+                   float Dstart, float* wr)
+{
+    const float dt = S.dt;
+    double adv = (T && (T->flags & TL_TOOL_ADVANCE)) ? jdt : 0.0;
+    float xc[3], nB[3], phi, vB[3] = {0.0f, 0.0f, 0.0f}, arm[3] = {0.0f, 0.0f, 0.0f};
+    float invm = 0.0f;
+    if (!T) {
+        xc[0] = x[0];
+        xc[1] = x[1];
+        xc[2] = S.floor_z;
+        nB[0] = 0.0f;
+        nB[1] = 0.0f;
+        nB[2] = 1.0f;
+        phi = (x[2] - S.floor_z) - R;
+    } else {
+        const DevBlade& B = T->b;
+        float xe[3] = {(float)(B.xe[0] + adv * B.ve[0]), (float)(B.xe[1] + adv * B.ve[1]), (float)(B.xe[2] + adv * B.ve[2])};
+        float r[3] = {x[0] - xe[0], x[1] - xe[1], x[2] - xe[2]};
+        float e[3] = {(float)B.e[0], (float)B.e[1], (float)B.e[2]};
+        float d[3] = {(float)B.d[0], (float)B.d[1], (float)B.d[2]};
+        float al = r[0] * e[0] + r[1] * e[1] + r[2] * e[2];
+        float be = -(r[0] * d[0] + r[1] * d[1] + r[2] * d[2]);
+        al = fminf(fmaxf(al, -(float)B.half_len), (float)B.half_len);
+        be = fminf(fmaxf(be, 0.0f), (float)B.b_back);
+        float df[3];
+        for (int a = 0; a < 3; a++) {
+            xc[a] = xe[a] + al * e[a] - be * d[a];
+            df[a] = x[a] - xc[a];
+        }
+        float dist = sqrtf(df[0] * df[0] + df[1] * df[1] + df[2] * df[2]);
+        if (dist > 0.0f)
+            for (int a = 0; a < 3; a++) nB[a] = df[a] / dist;
+        else
+            for (int a = 0; a < 3; a++) nB[a] = (float)B.n[a];
+        phi = dist - R;
+        for (int a = 0; a < 3; a++) arm[a] = xc[a] - (float)(T->xB[a] + adv * T->vB[a]);
+        float wxr[3] = {T->wB[1] * arm[2] - T->wB[2] * arm[1], T->wB[2] * arm[0] - T->wB[0] * arm[2],
+                        T->wB[0] * arm[1] - T->wB[1] * arm[0]};
+        for (int a = 0; a < 3; a++) vB[a] = (float)T->vB[a] + wxr[a];
+        invm = T->invm;
+    }
+    float vrel[3] = {v[0] - vB[0], v[1] - vB[1], v[2] - vB[2]};
+    float vrn = vrel[0] * nB[0] + vrel[1] * nB[1] + vrel[2] * nB[2];
+    float phihat = phi + dt * fminf(vrn, 0.0f);
+    float meff = 1.0f / (1.0f / m + invm);
+    float Jn = S.s_n * meff / dt * fmaxf(-phihat, 0.0f);
+    if (!(Jn > 0.0f)) return;
+    float* h = D.hist + (long long)slot * 4 * S.N;
+    float u[3] = {0.0f, 0.0f, 0.0f};
+    if (__float_as_int(h[3 * S.N + p]) == stamp - 1) {
+        u[0] = h[p];
+        u[1] = h[S.N + p];
+        u[2] = h[2 * S.N + p];
+    }
+    float ft[3];
+    friction(S, vrel, nB, Jn / dt, meff, u, ft);
+    h[p] = u[0];
+    h[S.N + p] = u[1];
+    h[2 * S.N + p] = u[2];
+    h[3 * S.N + p] = __int_as_float(stamp);
+    float JpB[3] = {Jn * nB[0] + ft[0] * dt, Jn * nB[1] + ft[1] * dt, Jn * nB[2] + ft[2] * dt};
+    if (T && (T->flags & TL_TOOL_CUTTING)) {
+        const DevBlade& B = T->b;
+        float r[3] = {x[0] - (float)(B.xe[0] + adv * B.ve[0]), x[1] - (float)(B.xe[1] + adv * B.ve[1]),
+                      x[2] - (float)(B.xe[2] + adv * B.ve[2])};
+        float sv = r[0] * (float)B.n[0] + r[1] * (float)B.n[1] + r[2] * (float)B.n[2];
+        float lv = r[0] * (float)B.e[0] + r[1] * (float)B.e[1] + r[2] * (float)B.e[2];
+        float fv = r[0] * (float)B.d[0] + r[1] * (float)B.d[1] + r[2] * (float)B.d[2];
+        float uc = ((float)B.ve[0] - v[0]) * (float)B.d[0] + ((float)B.ve[1] - v[1]) * (float)B.d[1] +
+                   ((float)B.ve[2] - v[2]) * (float)B.d[2];
+        if (fabsf(sv) <= (float)B.half_width && fabsf(lv) <= (float)B.half_len && fv >= 0.0f &&
+            fv <= (float)B.b_lead && uc > S.u_min) {
+            float dd[3] = {(float)B.d[0], (float)B.d[1], (float)B.d[2]};
+            float Jc = fmaxf(JpB[0] * dd[0] + JpB[1] * dd[1] + JpB[2] * dd[2], 0.0f);
+            if (Dstart < 1.0f) {
+                float Wth = S.G_c * powf(V0, 2.0f / 3.0f) * (1.0f - S.zeta) / S.zeta;
+                Dp = fminf(Dp + Jc * uc / Wth, 1.0f);
+            } else {
+                for (int a = 0; a < 3; a++) JpB[a] -= Jc * dd[a];
+            }
+        }
+    }
+    for (int a = 0; a < 3; a++) J[a] += JpB[a];
+    if (wr) {
+        float Fb[3] = {-JpB[0] / dt, -JpB[1] / dt, -JpB[2] / dt};
+        wr[0] += Fb[0];
+        wr[1] += Fb[1];
+        wr[2] += Fb[2];
+        wr[3] += arm[1] * Fb[2] - arm[2] * Fb[1];
+        wr[4] += arm[2] * Fb[0] - arm[0] * Fb[2];
+        wr[5] += arm[0] * Fb[1] - arm[1] * Fb[0];
+    }
+}
+
+// Conservative test: can a particle of a brick with AABB [lo, hi] and speed bound
+// vmax touch the rectangle of tool T (or the floor) during this substep?
+DEV bool brick_near_tool(const SceneK& S, const float* bb, const DevTool* T, float Rmax, double jdt)
+{
+    float vmax = bb[6];
+    if (!T) return bb[2] - Rmax - S.dt * vmax - 1e-6f <= S.floor_z;
+    const DevBlade& B = T->b;
+    double adv = (T->flags & TL_TOOL_ADVANCE) ? jdt : 0.0;
+    float margin = Rmax + S.dt * (vmax + fabsf((float)T->vB[0]) + fabsf((float)T->vB[1]) + fabsf((float)T->vB[2])) +
+                   1e-5f;
+    float lo[3] = {1e30f, 1e30f, 1e30f}, hi[3] = {-1e30f, -1e30f, -1e30f};
+    for (int c = 0; c < 4; c++) {
+        float al = (c & 1) ? (float)B.half_len : -(float)B.half_len;
+        float be = (c & 2) ? (float)B.b_back : 0.0f;
+        for (int a = 0; a < 3; a++) {
+            float pt = (float)(B.xe[a] + adv * B.ve[a]) + al * (float)B.e[a] - be * (float)B.d[a];
+            lo[a] = fminf(lo[a], pt);
+            hi[a] = fmaxf(hi[a], pt);
+        }
+    }
+    for (int a = 0; a < 3; a++)
+        if (bb[a] > hi[a] + margin || bb[3 + a] < lo[a] - margin) return false;
+    return true;
+}
+
+// --------------------------------------------------------------------------- K_A
+// P2G kernel (one brick per workgroup).  If f_pending: finalize the remapped
+// velocities of the previous substep's MUSL re-scatter on the box (tables rs),
+// apply the deformation-gradient update and write F.  Then, if do_p2g: stress,
+// tool/floor contact, and the label-masked P2G of (m, p, dp) (Eq. 2 with external
+// and contact impulses, Eqs. 13, 16) into this brick's partials (tables cur).
+struct KA_Args {
+    int f_pending;
+    int do_p2g;
+    int tabs_differ;
+    int cur;      // current slot table buffer
+    int rsb;      // slot table buffer of the pending re-scatter
+    int stamp;    // contact-history stamp of this substep
+    int do_contact;
+    int n_tools;
+    int any_tool_contact;
+    double jdt;   // time since the stored tool pose (TL_TOOL_ADVANCE)
+};
+
+__global__ __launch_bounds__(TL_WG) void k_p2g(SceneK S, SceneD D, KA_Args A)
+{
+    __shared__ BoxTab Tc;
+    __shared__ BoxTab Tr;
+    __shared__ float s_vt[TL_BOX_SLOTS * 3];
+    __shared__ float s_buf[TL_BOX_SLOTS * 7];
+    __shared__ int s_total;
+    __shared__ int s_rounds;
+    __shared__ float s_wr[8][TL_MAX_TOOLS * 6];
+    __shared__ int s_near[TL_MAX_TOOLS + 1];
+
+    const int brick = D.active[blockIdx.x];
+    const int bx = brick % S.cbx, by = (brick / S.cbx) % S.cby, bz = brick / (S.cbx * S.cby);
+    const int tid = threadIdx.x;
+
+    const BoxTab* Tv = &Tr;
+    if (A.f_pending) {
+        int tot = load_box(S, D.cnt[A.rsb], D.scode[A.rsb], bx, by, bz, Tr, &s_total);
+        if (tot < 0) {
+            if (tid == 0) atomicOr(D.status, TL_ST_BOX);
+            return;
+        }
+        for (int q = tid; q < tot; q += TL_WG) {
+            float o[4];
+            gather_slot<4>(S, D.rs, Tr, q, bx, by, bz, o);
+            for (int c = 0; c < 4; c++) s_buf[q * 4 + c] = o[c];
+        }
+        __syncthreads();
+        if (tid < TL_BOXN && Tr.cnt[tid] > 0) {
+            int b0 = Tr.base[tid], c = Tr.cnt[tid];
+            couple_node<4>(Tr, b0, c, s_buf, 1, s_vt);
+            for (int a = 0; a < c; a++) {
+                float m = s_buf[(b0 + a) * 4];
+                float im = m > 0.0f ? 1.0f / m : 0.0f;
+                for (int jj = 0; jj < 3; jj++) s_vt[(b0 + a) * 3 + jj] *= im;
+            }
+        }
+        __syncthreads();
+    }
+    int total = 0;
+    if (A.do_p2g) {
+        if (A.tabs_differ || !A.f_pending) {
+            total = load_box(S, D.cnt[A.cur], D.scode[A.cur], bx, by, bz, Tc, &s_total);
+            if (total < 0) {
+                if (tid == 0) atomicOr(D.status, TL_ST_BOX);
+                return;
+            }
+        } else {
+            total = s_total;
+        }
+        for (int q = tid; q < total * 7; q += TL_WG) s_buf[q] = 0.0f;
+        if (tid <= TL_MAX_TOOLS) {
+            int nr = 0;
+            if (A.do_contact) {
+                const float* bb = D.aabb + (long long)brick * 8;
+                const float Rmax = S.Rmax;
+                if (tid == 0)
+                    nr = S.floor_on ? brick_near_tool(S, bb, nullptr, Rmax, A.jdt) : 0;
+                else if (tid - 1 < A.n_tools)
+                    nr = (D.tools[tid - 1].flags & TL_TOOL_CONTACT) ? brick_near_tool(S, bb, &D.tools[tid - 1], Rmax, A.jdt)
+                                                                    : 0;
+            }
+            s_near[tid] = nr;
+        }
+    }
+    const BoxTab& T = (A.do_p2g && (A.tabs_differ || !A.f_pending)) ? Tc : Tr;
+    if (tid == 0) s_rounds = 0;
+    __syncthreads();
+
+    Lane L = lane_of(D, brick);
+    if (L.j == 0) atomicMax(&s_rounds, (L.count + 7) >> 3);
+    __syncthreads();
+    const int rounds = s_rounds;
+    const int gxc = bx * TL_B + L.cxl, gyc = by * TL_B + L.cyl, gzc = bz * TL_B + L.czl;
+    const long long N = S.N;
+    const float dt = S.dt;
+    float wr[TL_MAX_TOOLS * 6];
+    const bool want_wrench = A.do_p2g && A.do_contact && A.any_tool_contact;
+#pragma unroll
+    for (int q = 0; q < TL_MAX_TOOLS * 6; q++) wr[q] = 0.0f;
+
+    for (int r = 0; r < rounds; r++) {
+        const int jj = 8 * r + L.j;
+        const bool valid = jj < L.count;
+        const long long p = L.beg + jj;
+        float t[3] = {0.0f, 0.0f, 0.0f};
+        uint32_t code = 0, key = 0;
+        float H[9];
+        float vel[3] = {0.0f, 0.0f, 0.0f};
+        float Xp[3] = {0.0f, 0.0f, 0.0f};
+        if (valid) {
+            Xp[0] = D.X[p];
+            Xp[1] = D.X[N + p];
+            Xp[2] = D.X[2 * N + p];
+            frac_of(S, Xp, gxc, gyc, gzc, t);
+            code = D.code[p];
+            key = slot_key(S, code);
+            for (int a = 0; a < 9; a++) H[a] = D.H[a * N + p];
+            if (A.do_p2g)
+                for (int a = 0; a < 3; a++) vel[a] = D.v[a * N + p];
+        }
+        // ---- deformation-gradient update from the remapped velocities (MUSL)
+        if (A.f_pending && valid) {
+            uint32_t kprev = (code & TL_PREV_BIT) ? slot_key(S, D.code_prev[p]) : key;
+            float Lg[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+            for (int k = 0; k < 8; k++) {
+                float wx, wy, wz;
+                corner_weights(t, k, wx, wy, wz);
+                if (wx * wy * wz == 0.0f) continue;
+                int bn = box_index(L.cxl + (k & 1), L.cyl + ((k >> 1) & 1), L.czl + ((k >> 2) & 1));
+                int sl = find_slot(Tr, bn, kprev);
+                if (sl < 0) {
+                    atomicOr(D.status, TL_ST_LOOKUP);
+                    continue;
+                }
+                float g0 = ((k & 1) ? S.inv_dx : -S.inv_dx) * wy * wz;
+                float g1 = ((k & 2) ? S.inv_dx : -S.inv_dx) * wx * wz;
+                float g2 = ((k & 4) ? S.inv_dx : -S.inv_dx) * wx * wy;
+                for (int a = 0; a < 3; a++) {
+                    float va = s_vt[sl * 3 + a];
+                    Lg[3 * a + 0] += va * g0;
+                    Lg[3 * a + 1] += va * g1;
+                    Lg[3 * a + 2] += va * g2;
+                }
+            }
+            bool fin = true;
+            for (int a = 0; a < 9; a++) {
+                H[a] += dt * Lg[a];
+                D.H[a * N + p] = H[a];
+                fin = fin && isfinite(H[a]);
+            }
+            if (!fin) atomicOr(D.status, TL_ST_NONFINITE);
+            if (code & TL_PREV_BIT) {
+                code &= ~TL_PREV_BIT;
+                D.code[p] = code;
+            }
+        }
+        if (!A.do_p2g) continue;
+        // ---- stress and external/contact impulses
+        float m = 0.0f, V0 = 0.0f, E = 0.0f;
+        float Pk[9];
+        float ext[3] = {0.0f, 0.0f, 0.0f};
+        if (valid) {
+            m = S.m_uniform ? S.m0 : D.m[p];
+            V0 = S.v_uniform ? S.V0 : D.V0[p];
+            E = S.e_uniform ? S.E0 : D.E[p];
+            if (!neo_hookean(E, S.nu, H, Pk)) {
+                atomicOr(D.status, TL_ST_NONFINITE);
+                for (int a = 0; a < 9; a++) Pk[a] = 0.0f;
+            }
+            float Jc[3] = {0.0f, 0.0f, 0.0f};
+            if (A.do_contact) {
+                bool anyn = false;
+                for (int b = 0; b <= A.n_tools; b++) anyn |= s_near[b] != 0;
+                if (anyn) {
+                    float up[3] = {D.u[p], D.u[N + p], D.u[2 * N + p]};
+                    float xcur[3] = {Xp[0] + up[0], Xp[1] + up[1], Xp[2] + up[2]};
+                    float R = 0.5f * S.s_R * cbrtf(V0);
+                    float Dp = D.D[p], Ds = Dp;
+                    if (s_near[0])
+                        rigid_one(S, D, nullptr, 0, p, xcur, vel, m, V0, R, A.stamp, A.jdt, Jc, Dp, Ds, nullptr);
+#pragma unroll
+                    for (int b = 0; b < TL_MAX_TOOLS; b++)
+                        if (b < A.n_tools && s_near[b + 1])
+                            rigid_one(S, D, &D.tools[b], 1 + b, p, xcur, vel, m, V0, R, A.stamp, A.jdt, Jc, Dp, Ds,
+                                      &wr[6 * b]);
+                    if (Dp != Ds) D.D[p] = Dp;
+                }
+            }
+            if (S.material_contact && (code & TL_CAND_BIT)) {
+                Jc[0] += D.Jmat[p];
+                Jc[1] += D.Jmat[N + p];
+                Jc[2] += D.Jmat[2 * N + p];
+            }
+            ext[0] = Jc[0] + dt * m * S.gx;
+            ext[1] = Jc[1] + dt * m * S.gy;
+            ext[2] = Jc[2] + dt * m * S.gz;
+        }
+        // A = -dt V0 P;  dp_k = A grad N_k + w_k ext  (Eq. 2); a zero weight contributes
+        // nothing (reading R7)
+        const float sA = -dt * V0;
+#pragma unroll
+        for (int a = 0; a < 9; a++) Pk[a] *= sA;
+        const float mm = valid ? m : 0.0f;
+        auto gen = [&](int k, float* o) {
+            float wx, wy, wz;
+            corner_weights(t, k, wx, wy, wz);
+            float w = wx * wy * wz;
+            float g0 = ((k & 1) ? S.inv_dx : -S.inv_dx) * wy * wz;
+            float g1 = ((k & 2) ? S.inv_dx : -S.inv_dx) * wx * wz;
+            float g2 = ((k & 4) ? S.inv_dx : -S.inv_dx) * wx * wy;
+            bool on = valid && w != 0.0f;
+            float wm = w * mm;
+            o[0] = wm;
+            o[1] = wm * vel[0];
+            o[2] = wm * vel[1];
+            o[3] = wm * vel[2];
+#pragma unroll
+            for (int a = 0; a < 3; a++) {
+                float f = Pk[3 * a] * g0 + Pk[3 * a + 1] * g1 + Pk[3 * a + 2] * g2 + w * ext[a];
+                o[4 + a] = on ? f : 0.0f;
+            }
+        };
+        accumulate_classes<7>(L, valid, key, gen, T, s_buf, D.status);
+    }
+    if (!A.do_p2g) return;
+    write_partials<7>(S, D.p2g, T, total, s_buf);
+    if (want_wrench) {
+        // deterministic block reduction of the wrench sums: wave tree, then waves in order
+#pragma unroll
+        for (int q = 0; q < TL_MAX_TOOLS * 6; q++) {
+            float val = wr[q];
+            for (int o = 32; o >= 1; o >>= 1) val += __shfl_xor(val, o, 64);
+            if (L.lane == 0) s_wr[L.w][q] = val;
+        }
+        __syncthreads();
+        if (tid < A.n_tools * 6) {
+            float acc = 0.0f;
+            for (int wv = 0; wv < 8; wv++) acc += s_wr[wv][tid];
+            D.wpart[(long long)blockIdx.x * (TL_MAX_TOOLS * 6) + tid] = acc;
+        }
+    }
+}
+
+// --------------------------------------------------------------------------- K_B
+// Grid update and G2P kernel (one brick per workgroup): finalize the box from the
+// P2G partials (sum over contributing bricks, coupling Eq. 8, velocities Eq. 9),
+// PIC/FLIP G2P of v and x (Eq. 17), then the MUSL re-scatter of m_p v_p^{n+1} into
+// this brick's partials.  Also records the brick's current AABB and speed bound.
+__global__ __launch_bounds__(TL_WG) void k_g2p(SceneK S, SceneD D, int cur)
+{
+    __shared__ BoxTab T;
+    __shared__ float s_sum[TL_BOX_SLOTS * 7];
+    __shared__ float s_grid[TL_BOX_SLOTS * 6];
+    __shared__ int s_total;
+    __shared__ int s_rounds;
+    __shared__ float s_bb[8][7];
+
+    const int brick = D.active[blockIdx.x];
+    const int bx = brick % S.cbx, by = (brick / S.cbx) % S.cby, bz = brick / (S.cbx * S.cby);
+    const int tid = threadIdx.x;
+    int total = load_box(S, D.cnt[cur], D.scode[cur], bx, by, bz, T, &s_total);
+    if (total < 0) {
+        if (tid == 0) atomicOr(D.status, TL_ST_BOX);
+        return;
+    }
+    for (int q = tid; q < total; q += TL_WG) {
+        float o[7];
+        gather_slot<7>(S, D.p2g, T, q, bx, by, bz, o);
+        for (int c = 0; c < 7; c++) s_sum[q * 7 + c] = o[c];
+    }
+    if (tid == 0) s_rounds = 0;
+    __syncthreads();
+    if (tid < TL_BOXN && T.cnt[tid] > 0) {
+        int b0 = T.base[tid], c = T.cnt[tid];
+        // s_grid[slot] = (p_bar, dp_bar) then divided by m: (v^n, dv)
+        float tmp[TL_SCAP * 3];
+        couple_node<7>(T, b0, c, s_sum, 1, s_grid); // p_bar -> s_grid[b0*3 ..] (stride 3)
+        for (int a = 0; a < c * 3; a++) tmp[a] = s_grid[b0 * 3 + a];
+        couple_node<7>(T, b0, c, s_sum, 4, s_grid); // dp_bar
+        for (int a = c - 1; a >= 0; a--) {
+            float m = s_sum[(b0 + a) * 7];
+            float im = m > 0.0f ? 1.0f / m : 0.0f;
+            float dpb[3] = {s_grid[(b0 + a) * 3], s_grid[(b0 + a) * 3 + 1], s_grid[(b0 + a) * 3 + 2]};
+            for (int jj = 0; jj < 3; jj++) {
+                s_grid[TL_BOX_SLOTS * 3 + (b0 + a) * 3 + jj] = dpb[jj] * im; // dv
+                s_grid[(b0 + a) * 3 + jj] = tmp[a * 3 + jj] * im;            // v^n
+            }
+        }
+    }
+    __syncthreads();
+    // the P2G sums are no longer needed: s_sum becomes the re-scatter accumulator
+    for (int q = tid; q < total * 4; q += TL_WG) s_sum[q] = 0.0f;
+
+    Lane L = lane_of(D, brick);
+    if (L.j == 0) atomicMax(&s_rounds, (L.count + 7) >> 3);
+    __syncthreads();
+    const int rounds = s_rounds;
+    const int gxc = bx * TL_B + L.cxl, gyc = by * TL_B + L.cyl, gzc = bz * TL_B + L.czl;
+    const long long N = S.N;
+    const float dt = S.dt, beta = S.beta;
+    float bb[7] = {1e30f, 1e30f, 1e30f, -1e30f, -1e30f, -1e30f, 0.0f};
+    const float* gv = s_grid;
+    const float* gdv = s_grid + TL_BOX_SLOTS * 3;
+    for (int r = 0; r < rounds; r++) {
+        const int jj = 8 * r + L.j;
+        const bool valid = jj < L.count;
+        const long long p = L.beg + jj;
+        float t[3] = {0.0f, 0.0f, 0.0f};
+        uint32_t key = 0;
+        float m = 0.0f, vn1[3] = {0.0f, 0.0f, 0.0f};
+        if (valid) {
+            float Xp[3] = {D.X[p], D.X[N + p], D.X[2 * N + p]};
+            frac_of(S, Xp, gxc, gyc, gzc, t);
+            key = slot_key(S, D.code[p]);
+            float v[3] = {D.v[p], D.v[N + p], D.v[2 * N + p]};
+            float u[3] = {D.u[p], D.u[N + p], D.u[2 * N + p]};
+            float av[3] = {0.0f, 0.0f, 0.0f}, ax[3] = {0.0f, 0.0f, 0.0f};
+            for (int k = 0; k < 8; k++) {
+                float wx, wy, wz;
+                corner_weights(t, k, wx, wy, wz);
+                float w = wx * wy * wz;
+                if (w == 0.0f) continue;
+                int bn = box_index(L.cxl + (k & 1), L.cyl + ((k >> 1) & 1), L.czl + ((k >> 2) & 1));
+                int sl = find_slot(T, bn, key);
+                if (sl < 0) {
+                    atomicOr(D.status, TL_ST_LOOKUP);
+                    continue;
+                }
+                for (int a = 0; a < 3; a++) {
+                    float vn = gv[sl * 3 + a], dv = gdv[sl * 3 + a];
+                    av[a] += w * ((1.0f - beta) * vn + dv);
+                    ax[a] += w * (vn + dv);
+                }
+            }
+            for (int a = 0; a < 3; a++) {
+                vn1[a] = beta * v[a] + av[a];
+                u[a] += dt * ax[a];
+                D.v[a * N + p] = vn1[a];
+                D.u[a * N + p] = u[a];
+                float xa = Xp[a] + u[a];
+                bb[a] = fminf(bb[a], xa);
+                bb[3 + a] = fmaxf(bb[3 + a], xa);
+            }
+            bb[6] = fmaxf(bb[6], sqrtf(vn1[0] * vn1[0] + vn1[1] * vn1[1] + vn1[2] * vn1[2]));
+            m = S.m_uniform ? S.m0 : D.m[p];
+        }
+        const float mm = valid ? m : 0.0f;
+        auto gen = [&](int k, float* o) {
+            float wx, wy, wz;
+            corner_weights(t, k, wx, wy, wz);
+            float w = wx * wy * wz * mm;
+            o[0] = w;
+            o[1] = w * vn1[0];
+            o[2] = w * vn1[1];
+            o[3] = w * vn1[2];
+        };
+        accumulate_classes<4>(L, valid, key, gen, T, s_sum, D.status);
+    }
+    write_partials<4>(S, D.rs, T, total, s_sum);
+    // brick AABB of x^{n+1} and speed bound (used to skip distant contact work)
+    for (int q = 0; q < 7; q++) {
+        float val = bb[q];
+        for (int o = 32; o >= 1; o >>= 1) {
+            float other = __shfl_xor(val, o, 64);
+            val = (q < 3) ? fminf(val, other) : fmaxf(val, other);
+        }
+        if (L.lane == 0) s_bb[L.w][q] = val;
+    }
+    __syncthreads();
+    if (tid < 7) {
+        float val = s_bb[0][tid];
+        for (int wv = 1; wv < 8; wv++) val = (tid < 3) ? fminf(val, s_bb[wv][tid]) : fmaxf(val, s_bb[wv][tid]);
+        D.aabb[(long long)brick * 8 + tid] = val;
+    }
+}
+
+// ------------------------------------------------------------------------ labels
+// Side-label pass (Eqs. 3, 4, 6).  FP64 predicates with a fixed evaluation order
+// and no contraction (the same order as the CPU reference), on x = X + u and v.
+// One brick per workgroup; a brick whose AABB cannot meet any band exits at once.
+DEV bool brick_near_band(const SceneK& S, const float* bb, const DevBlade& B)
+{
+    // band extents in (s, l, f); the rear bound grows by max(u_c dt, 0)
+    double ucmax = sqrt(B.ve[0] * B.ve[0] + B.ve[1] * B.ve[1] + B.ve[2] * B.ve[2]) + (double)bb[6];
+    double flo = -B.b_back - ucmax * S.dt_d - 1e-9, fhi = B.b_lead + 1e-9;
+    double smin = 1e300, smax = -1e300, lmin = 1e300, lmax = -1e300, fmn = 1e300, fmx = -1e300;
+    for (int c = 0; c < 8; c++) {
+        double pt[3] = {(double)bb[(c & 1) ? 3 : 0], (double)bb[(c & 2) ? 4 : 1], (double)bb[(c & 4) ? 5 : 2]};
+        double r[3] = {pt[0] - B.xe[0], pt[1] - B.xe[1], pt[2] - B.xe[2]};
+        double s = r[0] * B.n[0] + r[1] * B.n[1] + r[2] * B.n[2];
+        double l = r[0] * B.e[0] + r[1] * B.e[1] + r[2] * B.e[2];
+        double f = r[0] * B.d[0] + r[1] * B.d[1] + r[2] * B.d[2];
+        smin = fmin(smin, s);
+        smax = fmax(smax, s);
+        lmin = fmin(lmin, l);
+        lmax = fmax(lmax, l);
+        fmn = fmin(fmn, f);
+        fmx = fmax(fmx, f);
+    }
+    double h = B.half_width + 1e-9, L = B.half_len + 1e-9;
+    return !(smin > h || smax < -h || lmin > L || lmax < -L || fmn > fhi || fmx < flo);
+}
+
+DEV int label_digit(const double x[3], const double v[3], const DevBlade& B, double dt)
+{
+#pragma clang fp contract(off)
+    double r0 = x[0] - B.xe[0], r1 = x[1] - B.xe[1], r2 = x[2] - B.xe[2];
+    double s = (r0 * B.n[0] + r1 * B.n[1]) + r2 * B.n[2];
+    double l = (r0 * B.e[0] + r1 * B.e[1]) + r2 * B.e[2];
+    double f = (r0 * B.d[0] + r1 * B.d[1]) + r2 * B.d[2];
+    double uc = ((B.ve[0] - v[0]) * B.d[0] + (B.ve[1] - v[1]) * B.d[1]) + (B.ve[2] - v[2]) * B.d[2];
+    double lo = -B.b_back - fmax(uc * dt, 0.0);
+    bool in_band = fabs(s) <= B.half_width && fabs(l) <= B.half_len && lo <= f && f <= B.b_lead;
+    if (!in_band || !(f <= 0.0)) return 0;
+    return (s < 0.0) ? 1 : 2;
+}
+
+// Blade of tool b at this substep (TL_TOOL_ADVANCE translates the edge).
+DEV DevBlade blade_at(const DevTool& T, double jdt)
+{
+    DevBlade B = T.b;
+    if (T.flags & TL_TOOL_ADVANCE)
+        for (int a = 0; a < 3; a++) B.xe[a] = T.b.xe[a] + jdt * T.b.ve[a];
+    return B;
+}
+
+__global__ __launch_bounds__(256) void k_labels(SceneK S, SceneD D, int n_tools, double jdt, int mark_prev)
+{
+    __shared__ int s_go;
+    __shared__ DevBlade s_bl[TL_MAX_TOOLS];
+    __shared__ int s_nb;
+    const int brick = D.active[blockIdx.x];
+    const float* bb = D.aabb + (long long)brick * 8;
+    if (threadIdx.x == 0) {
+        int go = 0, nb = 0;
+        for (int b = 0; b < n_tools; b++) {
+            if (!(D.tools[b].flags & TL_TOOL_LABELS)) continue;
+            DevBlade B = blade_at(D.tools[b], jdt);
+            if (brick_near_band(S, bb, B)) {
+                s_bl[nb++] = B;
+                go = 1;
+            }
+        }
+        s_nb = nb;
+        s_go = go;
+    }
+    __syncthreads();
+    if (!s_go) return;
+    const long long N = S.N;
+    const int beg = D.cell_start[(long long)brick * TL_CELLS], end = D.cell_start[(long long)(brick + 1) * TL_CELLS];
+    bool any = false;
+    for (int p = beg + threadIdx.x; p < end; p += blockDim.x) {
+        uint32_t code = D.code[p];
+        uint32_t nc = code;
+        double x[3] = {(double)D.X[p] + (double)D.u[p], (double)D.X[N + p] + (double)D.u[N + p],
+                       (double)D.X[2 * N + p] + (double)D.u[2 * N + p]};
+        double v[3] = {(double)D.v[p], (double)D.v[N + p], (double)D.v[2 * N + p]};
+        for (int b = 0; b < s_nb; b++) {
+            const DevBlade& B = s_bl[b];
+            uint32_t bit1 = 1u << B.cut, bit2 = 1u << (15 + B.cut);
+            if (nc & (bit1 | bit2)) continue; // persistence: an assigned digit never changes
+            int dg = label_digit(x, v, B, S.dt_d);
+            if (dg == 1) nc |= bit1;
+            if (dg == 2) nc |= bit2;
+        }
+        if (nc != code) {
+            if (mark_prev && !(code & TL_PREV_BIT)) {
+                D.code_prev[p] = code & TL_CODE_MASK;
+                nc |= TL_PREV_BIT;
+            }
+            D.code[p] = nc;
+            any = true;
+        }
+    }
+    if (__syncthreads_or(any) && threadIdx.x == 0) *D.dirty = 1;
+}
+
+// ------------------------------------------------------------------- slot tables
+// For every node: the distinct codes of the particles in its 8 incident cells, in
+// ascending order (compact slots, Sec. III-G).  Skipped (count copied) when the
+// labels did not change since the source table was built.
+__global__ __launch_bounds__(256) void k_slots(SceneK S, SceneD D, int dst, int src, int force)
+{
+    const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= S.NN) return;
+    if (!force && !*D.dirty) {
+        if (dst != src) {
+            int c = D.cnt[src][id];
+            D.cnt[dst][id] = (uint8_t)c;
+            for (int s = 0; s < c; s++) D.scode[dst][s * S.NN + id] = D.scode[src][s * S.NN + id];
+        }
+        return;
+    }
+    long long nb = id >> 6;
+    int lid = (int)(id & 63);
+    int hx = (int)(nb % S.nbx), hy = (int)((nb / S.nbx) % S.nby), hz = (int)(nb / ((long long)S.nbx * S.nby));
+    int gx = hx * 4 + (lid & 3), gy = hy * 4 + ((lid >> 2) & 3), gz = hz * 4 + (lid >> 4);
+    uint32_t codes[TL_SCAP];
+    int c = 0;
+    bool over = false;
+    if (gx <= S.cx && gy <= S.cy && gz <= S.cz) {
+        for (int dz = 0; dz < 2; dz++)
+            for (int dy = 0; dy < 2; dy++)
+                for (int dx = 0; dx < 2; dx++) {
+                    int x = gx - dx, y = gy - dy, z = gz - dz;
+                    if (x < 0 || y < 0 || z < 0 || x >= S.cx || y >= S.cy || z >= S.cz) continue;
+                    long long brick = ((long long)(z >> 2) * S.cby + (y >> 2)) * S.cbx + (x >> 2);
+                    int lx = x & 3, ly = y & 3, lz = z & 3;
+                    int w = (lx & 1) | ((ly & 1) << 1) | ((lz & 1) << 2);
+                    int i = (lx >> 1) | ((ly >> 1) << 1) | ((lz >> 1) << 2);
+                    const int* cs = D.cell_start + brick * TL_CELLS + w * 8 + i;
+                    for (int p = cs[0]; p < cs[1]; p++) {
+                        uint32_t k = slot_key(S, D.code[p]);
+                        int pos = 0;
+                        while (pos < c && codes[pos] < k) pos++;
+                        if (pos < c && codes[pos] == k) continue;
+                        if (c == TL_SCAP) {
+                            over = true;
+                            continue;
+                        }
+                        for (int q = c; q > pos; q--) codes[q] = codes[q - 1];
+                        codes[pos] = k;
+                        c++;
+                    }
+                }
+    }
+    if (over) atomicOr(D.status, TL_ST_SLOT);
+    D.cnt[dst][id] = (uint8_t)c;
+    for (int s = 0; s < c; s++) D.scode[dst][s * S.NN + id] = codes[s];
+}
+
+// --------------------------------------------------------------- small kernels
+__global__ void k_fill_f32(float* p, long long n, float v)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_i32(int* p, long long n, int v)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// brick AABB from the current state (scene creation, after a state write)
+__global__ __launch_bounds__(256) void k_aabb(SceneK S, SceneD D)
+{
+    __shared__ float s_bb[4][7];
+    const int brick = D.active[blockIdx.x];
+    const long long N = S.N;
+    const int beg = D.cell_start[(long long)brick * TL_CELLS], end = D.cell_start[(long long)(brick + 1) * TL_CELLS];
+    float bb[7] = {1e30f, 1e30f, 1e30f, -1e30f, -1e30f, -1e30f, 0.0f};
+    for (int p = beg + threadIdx.x; p < end; p += blockDim.x) {
+        float sp = 0.0f;
+        for (int a = 0; a < 3; a++) {
+            float xa = D.X[a * N + p] + D.u[a * N + p];
+            bb[a] = fminf(bb[a], xa);
+            bb[3 + a] = fmaxf(bb[3 + a], xa);
+            sp += D.v[a * N + p] * D.v[a * N + p];
+        }
+        bb[6] = fmaxf(bb[6], sqrtf(sp));
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int q = 0; q < 7; q++) {
+        float val = bb[q];
+        for (int o = 32; o >= 1; o >>= 1) {
+            float other = __shfl_xor(val, o, 64);
+            val = (q < 3) ? fminf(val, other) : fmaxf(val, other);
+        }
+        if (lane == 0) s_bb[w][q] = val;
+    }
+    __syncthreads();
+    if (threadIdx.x < 7) {
+        int q = threadIdx.x;
+        float val = s_bb[0][q];
+        for (int wv = 1; wv < 4; wv++) val = (q < 3) ? fminf(val, s_bb[wv][q]) : fmaxf(val, s_bb[wv][q]);
+        D.aabb[(long long)brick * 8 + q] = val;
+    }
+}
+
+// Sum of the per-brick wrench partials in fixed order (one workgroup), added to the
+// interval accumulator in FP64.
+__global__ __launch_bounds__(256) void k_wrench(SceneD D, int n_tools)
+{
+    __shared__ double s[256];
+    for (int q = 0; q < n_tools * 6; q++) {
+        double acc = 0.0;
+        for (int b = threadIdx.x; b < D.n_active; b += blockDim.x)
+            acc += (double)D.wpart[(long long)b * (TL_MAX_TOOLS * 6) + q];
+        s[threadIdx.x] = acc;
+        __syncthreads();
+        for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+            if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) D.wacc[q] += s[0];
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------- launchers
+extern "C" {
+hipError_t tl_launch_p2g(const SceneK* S, const SceneD* D, int n_tools, int any_tool_contact, double jdt,
+                         int f_pending, int do_p2g, int tabs_differ, int cur, int rsb, int stamp, int do_contact,
+                         hipStream_t st)
+{
+    KA_Args A;
+    A.n_tools = n_tools;
+    A.any_tool_contact = any_tool_contact;
+    A.jdt = jdt;
+    A.f_pending = f_pending;
+    A.do_p2g = do_p2g;
+    A.tabs_differ = tabs_differ;
+    A.cur = cur;
+    A.rsb = rsb;
+    A.stamp = stamp;
+    A.do_contact = do_contact;
+    if (D->n_active == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_p2g, dim3(D->n_active), dim3(TL_WG), 0, st, *S, *D, A);
+    return hipGetLastError();
+}
+
+hipError_t tl_launch_g2p(const SceneK* S, const SceneD* D, int cur, hipStream_t st)
+{
+    if (D->n_active == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_g2p, dim3(D->n_active), dim3(TL_WG), 0, st, *S, *D, cur);
+    return hipGetLastError();
+}
+
+hipError_t tl_launch_labels(const SceneK* S, const SceneD* D, int n_tools, double jdt, int mark_prev, hipStream_t st)
+{
+    if (D->n_active == 0 || n_tools == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_labels, dim3(D->n_active), dim3(256), 0, st, *S, *D, n_tools, jdt, mark_prev);
+    return hipGetLastError();
+}
+
+hipError_t tl_launch_slots(const SceneK* S, const SceneD* D, int dst, int src, int force, hipStream_t st)
+{
+    long long nb = (S->NN + 255) / 256;
+    hipLaunchKernelGGL(k_slots, dim3((unsigned)nb), dim3(256), 0, st, *S, *D, dst, src, force);
+    return hipGetLastError();
+}
+
+hipError_t tl_launch_fill_f32(float* p, long long n, float v, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t tl_launch_fill_i32(int* p, long long n, int v, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t tl_launch_aabb(const SceneK* S, const SceneD* D, hipStream_t st)
+{
+    if (D->n_active == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_aabb, dim3(D->n_active), dim3(256), 0, st, *S, *D);
+    return hipGetLastError();
+}
+
+hipError_t tl_launch_wrench(const SceneD* D, int n_tools, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_wrench, dim3(1), dim3(256), 0, st, *D, n_tools);
+    return hipGetLastError();
+}
+}

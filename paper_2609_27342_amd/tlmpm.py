@@ -1,0 +1,276 @@
+"""Python binding of libtlmpm.so (argument marshalling only).
+
+Every step of the method runs in the HIP kernels behind the C ABI of
+include/tlmpm.h.  PyTorch provides the device workspace and the stream.  The
+library must be built (``python -m paper_2609_27342_amd.build``); importing this
+module on a machine without it raises.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtlmpm.so")
+
+OK, E_INVALID, E_NOMEM, E_DEVICE, E_SLOT_OVERFLOW, E_NONFINITE = range(6)
+TOOL_LABELS, TOOL_CONTACT, TOOL_CUTTING, TOOL_ADVANCE = 1, 2, 4, 8
+FIELD_X, FIELD_U, FIELD_V, FIELD_F, FIELD_CODE, FIELD_D, FIELD_DIGITS = 1, 2, 4, 8, 16, 32, 64
+MAX_TOOLS = 4
+
+
+class SceneDesc(C.Structure):
+    _fields_ = [
+        ("n", C.c_int64), ("X", C.c_void_p), ("v0", C.c_void_p), ("vol0", C.c_void_p),
+        ("mass", C.c_void_p), ("E", C.c_void_p),
+        ("vol0_uniform", C.c_float), ("mass_uniform", C.c_float), ("E_uniform", C.c_float),
+        ("nu", C.c_float), ("dx", C.c_double), ("origin", C.c_double * 3), ("cells", C.c_int32 * 3),
+        ("dt", C.c_double), ("gravity", C.c_float * 3), ("flip_beta", C.c_float),
+        ("s_R", C.c_float), ("s_n", C.c_float), ("gamma_k", C.c_float), ("gamma_c", C.c_float),
+        ("mu_s", C.c_float), ("mu_d", C.c_float),
+        ("material_contact", C.c_int32), ("floor_on", C.c_int32), ("floor_z", C.c_float),
+        ("G_c", C.c_float), ("zeta", C.c_float), ("u_min", C.c_float),
+        ("max_cuts", C.c_int32), ("single_field", C.c_int32),
+    ]
+
+
+class Blade(C.Structure):
+    _fields_ = [
+        ("cut_index", C.c_int32), ("new_cut", C.c_int32),
+        ("x_e", C.c_double * 3), ("n", C.c_double * 3), ("e", C.c_double * 3), ("d", C.c_double * 3),
+        ("v_e", C.c_double * 3), ("half_len", C.c_double), ("half_width", C.c_double),
+        ("b_back", C.c_double), ("b_lead", C.c_double),
+    ]
+
+
+class Tool(C.Structure):
+    _fields_ = [
+        ("blade", Blade), ("x_B", C.c_double * 3), ("v_B", C.c_double * 3), ("omega_B", C.c_double * 3),
+        ("w_B", C.c_double), ("flags", C.c_uint32), ("reserved", C.c_int32),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load libtlmpm.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libtlmpm.so is not built; run python -m paper_2609_27342_amd.build")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.tlmpm_scene_footprint.argtypes = [C.POINTER(SceneDesc), C.POINTER(C.c_size_t)]
+        L.tlmpm_create_scene.argtypes = [C.POINTER(SceneDesc), vp, C.c_size_t, vp, C.POINTER(vp)]
+        L.tlmpm_destroy_scene.argtypes = [vp]
+        L.tlmpm_assign_labels.argtypes = [vp, C.POINTER(Blade), C.c_int32]
+        L.tlmpm_step.argtypes = [vp, C.POINTER(Tool), C.c_int32, C.c_int32, C.POINTER(C.c_double)]
+        L.tlmpm_read_state.argtypes = [vp, C.c_uint32, C.POINTER(vp)]
+        L.tlmpm_write_state.argtypes = [vp, C.c_uint32, C.POINTER(vp)]
+        L.tlmpm_get_status.argtypes = [vp, C.POINTER(C.c_int32)]
+        L.tlmpm_slot_stats.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
+        L.tlmpm_profile_enable.argtypes = [vp, C.c_int32]
+        L.tlmpm_profile_read.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        L.tlmpm_last_error.restype = C.c_char_p
+        for f in ("tlmpm_scene_footprint", "tlmpm_create_scene", "tlmpm_destroy_scene", "tlmpm_assign_labels",
+                  "tlmpm_step", "tlmpm_read_state", "tlmpm_write_state", "tlmpm_get_status", "tlmpm_slot_stats",
+                  "tlmpm_profile_enable", "tlmpm_profile_read"):
+            getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+class TlmpmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"tlmpm status {code}: {msg}")
+        self.code = code
+
+
+def _check(code):
+    if code != OK:
+        raise TlmpmError(code, lib().tlmpm_last_error().decode())
+
+
+def _vec(dst, src):
+    src = np.asarray(src, np.float64)
+    for i in range(3):
+        dst[i] = float(src[i])
+
+
+def make_blade(b):
+    B = Blade()
+    B.cut_index = int(b["cut_index"])
+    B.new_cut = int(b.get("new_cut", 0))
+    for k in ("x_e", "n", "e", "d", "v_e"):
+        _vec(getattr(B, k), b[k])
+    for k in ("half_len", "half_width", "b_back", "b_lead"):
+        setattr(B, k, float(b[k]))
+    return B
+
+
+def make_tool(t):
+    T = Tool()
+    T.blade = make_blade(t["blade"])
+    for k in ("x_B", "v_B", "omega_B"):
+        _vec(getattr(T, k), t.get(k, (0.0, 0.0, 0.0)))
+    T.w_B = float(t.get("w_B", 0.0))
+    fl = 0
+    if t.get("labels"):
+        fl |= TOOL_LABELS
+    if t.get("contact"):
+        fl |= TOOL_CONTACT
+    if t.get("cutting"):
+        fl |= TOOL_CUTTING
+    if t.get("advance"):
+        fl |= TOOL_ADVANCE
+    T.flags = fl
+    return T
+
+
+def make_desc(scene, keep):
+    """SceneDesc from a workload scene dict; arrays kept alive in `keep`."""
+    p = scene["params"]
+    d = SceneDesc()
+    X = np.ascontiguousarray(scene["X"], np.float32)
+    keep.append(X)
+    d.n = X.shape[0]
+    d.X = X.ctypes.data
+    if scene.get("v0") is not None:
+        v0 = np.ascontiguousarray(scene["v0"], np.float32)
+        keep.append(v0)
+        d.v0 = v0.ctypes.data
+    for name, arr_key in (("vol0", "vol0"), ("mass", "mass"), ("E", "E")):
+        a = np.asarray(scene[arr_key], np.float32)
+        if a.ndim == 0 or np.all(a == a.flat[0]):
+            setattr(d, name + "_uniform" if name != "E" else "E_uniform", float(a.flat[0]))
+        else:
+            a = np.ascontiguousarray(a)
+            keep.append(a)
+            setattr(d, name, a.ctypes.data)
+    d.nu = float(p["nu"])
+    d.dx = float(p["dx"])
+    _vec(d.origin, p["origin"])
+    for i in range(3):
+        d.cells[i] = int(p["cells"][i])
+    d.dt = float(p["dt"])
+    g = p.get("gravity", (0.0, 0.0, -9.81))
+    for i in range(3):
+        d.gravity[i] = float(g[i])
+    d.flip_beta = float(p.get("flip_beta", 0.95))
+    for k in ("s_R", "s_n", "gamma_k", "gamma_c", "mu_s", "mu_d", "floor_z", "G_c", "zeta", "u_min"):
+        setattr(d, k, float(p[k]))
+    d.material_contact = int(p.get("material_contact", 0))
+    d.floor_on = int(p.get("floor_on", 0))
+    d.max_cuts = int(p.get("max_cuts", 4))
+    d.single_field = int(p.get("single_field", 0))
+    return d
+
+
+def footprint(scene):
+    keep = []
+    d = make_desc(scene, keep)
+    nb = C.c_size_t()
+    _check(lib().tlmpm_scene_footprint(C.byref(d), C.byref(nb)))
+    return nb.value
+
+
+class Scene:
+    """A scene resident on the current torch device.  `stream` is a torch stream
+    (default: the current one)."""
+
+    def __init__(self, scene, stream=None, workspace=None):
+        import torch
+        L = lib()
+        self._keep = []
+        self.desc = make_desc(scene, self._keep)
+        self.n = int(self.desc.n)
+        self.max_cuts = int(self.desc.max_cuts)
+        nb = C.c_size_t()
+        _check(L.tlmpm_scene_footprint(C.byref(self.desc), C.byref(nb)))
+        self.bytes = nb.value
+        if workspace is None:
+            workspace = torch.empty(self.bytes, dtype=torch.uint8, device="cuda")
+        assert workspace.numel() >= self.bytes and workspace.is_cuda
+        self.ws = workspace
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        _check(L.tlmpm_create_scene(C.byref(self.desc), C.c_void_p(workspace.data_ptr()), self.bytes,
+                                    C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            _check(lib().tlmpm_destroy_scene(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def assign_labels(self, blades):
+        arr = (Blade * max(1, len(blades)))(*[make_blade(b) for b in blades])
+        _check(lib().tlmpm_assign_labels(self.h, arr, len(blades)))
+
+    def step(self, tools=(), n_substeps=1, wrench=False):
+        nt = len(tools)
+        arr = (Tool * max(1, nt))(*[make_tool(t) for t in tools])
+        w = np.zeros((max(1, nt), 6))
+        wp = w.ctypes.data_as(C.POINTER(C.c_double)) if wrench else None
+        _check(lib().tlmpm_step(self.h, arr, nt, int(n_substeps), wp))
+        return w[:nt] if wrench else None
+
+    def read(self, fields=("u", "v", "F", "code", "D", "digits")):
+        n, K = self.n, self.max_cuts
+        spec = {"X": (FIELD_X, (n, 3), np.float32), "u": (FIELD_U, (n, 3), np.float32),
+                "v": (FIELD_V, (n, 3), np.float32), "F": (FIELD_F, (n, 3, 3), np.float32),
+                "code": (FIELD_CODE, (n,), np.uint64), "D": (FIELD_D, (n,), np.float32),
+                "digits": (FIELD_DIGITS, (n, K), np.uint8)}
+        order = sorted(fields, key=lambda f: spec[f][0])
+        mask = 0
+        outs = {}
+        for f in order:
+            bit, shape, dt = spec[f]
+            mask |= bit
+            outs[f] = np.zeros(shape, dt)
+        ptrs = (C.c_void_p * max(1, len(order)))(*[outs[f].ctypes.data for f in order])
+        _check(lib().tlmpm_read_state(self.h, mask, ptrs))
+        return outs
+
+    def write(self, **fields):
+        spec = {"u": (FIELD_U, np.float32), "v": (FIELD_V, np.float32), "F": (FIELD_F, np.float32),
+                "D": (FIELD_D, np.float32), "digits": (FIELD_DIGITS, np.uint8)}
+        order = sorted(fields, key=lambda f: spec[f][0])
+        mask = 0
+        keep = []
+        for f in order:
+            bit, dt = spec[f]
+            mask |= bit
+            keep.append(np.ascontiguousarray(fields[f], dt))
+        ptrs = (C.c_void_p * max(1, len(order)))(*[a.ctypes.data for a in keep])
+        _check(lib().tlmpm_write_state(self.h, mask, ptrs))
+
+    def status(self):
+        st = C.c_int32()
+        _check(lib().tlmpm_get_status(self.h, C.byref(st)))
+        return st.value
+
+    KERNEL_CLASSES = ("p2g", "g2p", "labels", "slots", "contact", "other")
+
+    def profile(self, enable=True):
+        _check(lib().tlmpm_profile_enable(self.h, int(bool(enable))))
+
+    def profile_read(self):
+        """{class: (total ms, launches)} since the last read (synchronises)."""
+        ms = (C.c_double * 6)()
+        cnt = (C.c_int64 * 6)()
+        _check(lib().tlmpm_profile_read(self.h, 6, ms, cnt))
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(self.KERNEL_CLASSES)}
+
+    def slot_stats(self):
+        tot = C.c_int64()
+        mx = C.c_int32()
+        _check(lib().tlmpm_slot_stats(self.h, C.byref(tot), C.byref(mx)))
+        return tot.value, mx.value

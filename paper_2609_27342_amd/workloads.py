@@ -249,5 +249,26 @@ def box_scene(n_cells=(6, 5, 4), dx=0.01, seed=0, E=1e4, nu=0.3, rho=1000.0, dt=
     return _finish("box", params, X, rho, E, rng, 1, lambda j: [], v0=v)
 
 
+def segments(scene, j0, j1):
+    """Split steps [j0, j1) into runs over which every tool moves at constant
+    velocity (the set of tools and their flags unchanged).  Yields (j, count,
+    tools at step j); a run starts a new cut only at its first step."""
+    def sig(tools):
+        return tuple((t["blade"]["cut_index"], t["labels"], t["contact"], t["cutting"],
+                      tuple(np.round(t["blade"]["v_e"], 12)), tuple(np.round(t["blade"]["n"], 12)))
+                     for t in tools)
+    j = j0
+    while j < j1:
+        tools = scene["tools_at"](j)
+        k = j + 1
+        while k < j1:
+            nxt = scene["tools_at"](k)
+            if sig(nxt) != sig(tools) or any(t["blade"]["new_cut"] for t in nxt):
+                break
+            k += 1
+        yield j, k - j, tools
+        j = k
+
+
 CONFIGS = {"small": small, "small-deep": lambda **k: small(deep=True, **k), "medium": medium,
            "large": large}

@@ -1,0 +1,41 @@
+"""The C ABI library loads and exports every entry point its header declares
+(no compute calls: runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tlmpm.h")
+LIB = os.path.join(ROOT, "paper_2609_27342_amd", "libtlmpm.so")
+
+
+def declared():
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(tlmpm_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_entry_points():
+    names = declared()
+    for n in ("tlmpm_create_scene", "tlmpm_assign_labels", "tlmpm_step", "tlmpm_read_state"):
+        assert n in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(LIB)
+    for n in declared():
+        assert hasattr(L, n), n
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_footprint_and_validation_without_gpu():
+    from paper_2609_27342_amd import tlmpm, workloads as W
+    s = W.small()
+    nb = tlmpm.footprint(s)
+    assert nb > s["X"].shape[0] * 100
+    bad = dict(s, params=dict(s["params"], max_cuts=99))
+    with pytest.raises(tlmpm.TlmpmError) as e:
+        tlmpm.footprint(bad)
+    assert e.value.code == tlmpm.E_INVALID

@@ -1,0 +1,183 @@
+"""GPU path (through the C ABI) against the FP64 oracle on the same seeded inputs.
+
+Tolerances: labels bit-exact; after one substep the FP32 state is within 1e-5 of
+the oracle relative to the field's largest value; after 100 substeps positions are
+within 1e-3 relative to the largest displacement.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2609_27342_amd import workloads as W
+
+from harness import disp_err, field_err, gpu_x, oracle_substep
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tl():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2609_27342_amd import tlmpm
+    tlmpm.lib()
+    return tlmpm
+
+
+def _print_case(name, **kw):
+    print(f"[case] {name} {kw}", flush=True)
+
+
+@pytest.mark.parametrize("deep", [False, True])
+def test_one_substep_parity(tl, deep):
+    s = W.small(deep=deep)
+    _print_case("one_substep", scene=s["name"], n=s["X"].shape[0])
+    g = tl.Scene(s)
+    o = oracle.OracleScene(s)
+    tools = s["tools_at"](0)
+    g.step(tools)
+    oracle_substep(o, tools)
+    a = g.read(("u", "v", "F", "digits"))
+    b = o.get()
+    assert np.array_equal(a["digits"], b["digits"])
+    assert field_err(gpu_x(a, s["X"]), b["x"]) < 1e-5
+    assert field_err(a["v"], b["v"]) < 1e-5
+    assert field_err(a["F"], b["F"]) < 1e-5
+    assert g.status() == 0
+    if deep:
+        tot, mx = g.slot_stats()
+        assert mx >= 2  # 0/1/2 mixes exist at step 1
+
+
+def test_labels_bit_exact_shared_input(tl):
+    """Reading R25(a): the oracle's label pass on the GPU's own FP32 state gives
+    the GPU's labels exactly, substep after substep."""
+    s = W.small(deep=True)
+    _print_case("labels_shared", scene=s["name"])
+    g = tl.Scene(s)
+    dt = s["params"]["dt"]
+    for j in range(0, 40, 3):
+        tools = s["tools_at"](j)
+        pre = g.read(("u", "v", "digits"))
+        g.assign_labels([t["blade"] for t in tools])
+        post = g.read(("digits",))["digits"]
+        ref = oracle.labels_on(s["X"], pre["u"], pre["v"], pre["digits"], [t["blade"] for t in tools], dt)
+        assert np.array_equal(post, ref), j
+        g.step([dict(t, labels=False) for t in tools])
+    assert (post != 0).sum() > 1000
+
+
+def test_hundred_substeps_positions(tl):
+    s = W.small(deep=True)
+    _print_case("hundred", scene=s["name"])
+    g = tl.Scene(s)
+    o = oracle.OracleScene(s)
+    for j in range(100):
+        tools = s["tools_at"](j)
+        g.step(tools)
+        oracle_substep(o, tools)
+    a = g.read(("u", "v", "digits"))
+    b = o.get()
+    mism = (a["digits"] != b["digits"]).sum()
+    assert mism <= 0.001 * a["digits"].size
+    assert disp_err(gpu_x(a, s["X"]), b["x"], s["X"]) < 1e-3
+    assert g.status() == 0
+
+
+def test_determinism_bitwise(tl):
+    s = W.small(deep=True)
+    outs = []
+    for _ in range(2):
+        g = tl.Scene(s)
+        for j in range(5):
+            g.step(s["tools_at"](j))
+        outs.append(g.read(("u", "v", "F")))
+    for k in outs[0]:
+        assert np.array_equal(outs[0][k], outs[1][k]), k
+
+
+@pytest.mark.parametrize("beta,cuts", [(0.0, 1), (0.95, 1), (1.0, 1), (0.95, 2)])
+def test_momentum_conservation_gpu(tl, beta, cuts):
+    """Prop. 1 on the GPU: no external force, random F, v and codes; total
+    momentum is kept to FP32 rounding and the state matches the oracle's.  With one
+    cut every particle draws a random digit (up to 3 logical grids per node); with
+    two cuts each half of the box draws one of the digits."""
+    s = W.box_scene(n_cells=(9, 7, 6), seed=12, floor_on=0, gravity=[0.0, 0.0, 0.0], flip_beta=beta,
+                    max_cuts=cuts)
+    n = s["X"].shape[0]
+    rng = np.random.default_rng(13)
+    F = (np.eye(3)[None] + 0.05 * rng.normal(size=(n, 3, 3))).astype(np.float32)
+    v = (rng.normal(size=(n, 3)) * 0.1).astype(np.float32)
+    dig = np.zeros((n, cuts), np.uint8)
+    if cuts == 1:
+        dig[:, 0] = rng.integers(0, 3, size=n)
+    else:
+        left = s["X"][:, 0] < 0.045
+        dig[left, 0] = rng.integers(0, 3, size=left.sum())
+        dig[~left, 1] = rng.integers(0, 3, size=(~left).sum())
+    _print_case("momentum", beta=beta, cuts=cuts, n=n)
+    g = tl.Scene(s)
+    g.write(v=v, F=F, digits=dig)
+    o = oracle.OracleScene(s)
+    o.set(v=v, F=F.reshape(n, 9), digits=dig)
+    m = s["mass"].astype(np.float64)
+    P0 = (m[:, None] * v).sum(axis=0)
+    scale = (m[:, None] * np.abs(v)).sum()
+    for _ in range(3):
+        g.step([])
+        o.step([])
+    assert g.status() == 0
+    a = g.read(("u", "v", "F"))
+    P1 = (m[:, None] * a["v"]).sum(axis=0)
+    assert np.abs(P1 - P0).max() < 1e-5 * scale
+    b = o.get()
+    assert field_err(a["v"], b["v"]) < 1e-5
+    assert field_err(a["F"], b["F"]) < 1e-5
+    assert field_err(gpu_x(a, s["X"]), b["x"]) < 1e-5
+
+
+def test_zero_exchange_gpu(tl):
+    """Opposite labels everywhere a node is shared: the resting half stays exactly
+    at rest (bitwise zero velocity and displacement)."""
+    s = W.box_scene(n_cells=(8, 4, 4), seed=16, floor_on=0, gravity=[0.0, 0.0, 0.0], max_cuts=1)
+    X = s["X"].astype(np.float64)
+    n = X.shape[0]
+    A = X[:, 0] < 0.04
+    rng = np.random.default_rng(17)
+    v = np.zeros((n, 3), np.float32)
+    v[A] = rng.normal(size=(A.sum(), 3)) * 0.2
+    F = np.tile(np.eye(3, dtype=np.float32), (n, 1, 1))
+    F[A] += (0.02 * rng.normal(size=(A.sum(), 3, 3))).astype(np.float32)
+    g = tl.Scene(s)
+    g.write(v=v, F=F, digits=np.where(A, 1, 2).astype(np.uint8)[:, None])
+    for _ in range(5):
+        g.step([])
+    a = g.read(("u", "v"))
+    assert np.all(a["v"][~A] == 0.0)
+    assert np.all(a["u"][~A] == 0.0)
+    assert np.abs(a["v"][A]).max() > 0.01
+
+
+def test_uniform_translation_gpu(tl):
+    v0 = (0.3, -0.2, 0.1)
+    s = W.box_scene(n_cells=(9, 6, 5), seed=14, floor_on=0, gravity=[0.0, 0.0, 0.0], v0=v0)
+    g = tl.Scene(s)
+    dt = s["params"]["dt"]
+    g.step([], n_substeps=4)
+    a = g.read(("u", "v", "F"))
+    vv = np.array(v0, np.float32).astype(np.float64)
+    assert np.abs(a["v"] - vv).max() < 1e-6
+    assert np.abs(a["F"] - np.eye(3)).max() < 1e-6
+    assert np.abs(a["u"] - 4 * dt * vv).max() < 1e-9
+
+
+def test_nonfinite_status(tl):
+    s = W.box_scene(n_cells=(5, 5, 5), seed=3, floor_on=0)
+    g = tl.Scene(s)
+    n = s["X"].shape[0]
+    F = np.tile(np.eye(3, dtype=np.float32), (n, 1, 1))
+    F[7] = -np.eye(3)  # det F < 0
+    g.write(F=F)
+    g.step([])
+    assert g.status() == tl.E_NONFINITE
