@@ -137,13 +137,14 @@ def small(seed=1, deep=False, steps=100):
 
 
 # -------------------------------------------------------------------------- medium
-def medium(seed=2, steps=8000, dx=0.002):
+def medium(seed=2, steps=8000, dx=0.002, z_start=0.038):
     """Curved cylinder: radius 0.018 m around a horizontal centreline arc of radius
     0.3 m and length 0.18 m (0.6 rad), resting on the floor; dx = 2 mm, 8 ppc,
     E = 5e4, nu = 0.3, rho = 1000, dt = 1e-4, material contact on.  Two vertical cuts
     normal to the centreline at +-3 cm of arc from the middle descend at 0.1 m/s from
     z = 0.038 to 0; after each cut the blade pushes along its normal (+n, then -n) at
-    0.1 m/s for 0.3 s and is removed."""
+    0.1 m/s for 0.3 s and is removed.  z_start < 0.036 starts the first cut with
+    the edge already inside the tube (labels and blade contact from step 0)."""
     Rc, rt, half_ang = 0.3, 0.018, 0.3
     cy = -Rc  # centre of curvature at (0, cy); the arc passes through (0, 0)
     rng = np.random.default_rng(seed)
@@ -160,7 +161,7 @@ def medium(seed=2, steps=8000, dx=0.002):
     X = jittered_lattice(lo, hi, dx, origin, inside, rng)
     params = base_params(dx, origin, cells, 1e-4, 0.3, material_contact=1, floor_on=1)
     dt = params["dt"]
-    t_cut = int(round(0.038 / 0.1 / dt))   # 3800 steps
+    t_cut = int(round(z_start / 0.1 / dt))  # 3800 steps from z = 0.038
     t_push = int(round(0.3 / dt))          # 3000 steps
     thetas = (-0.1, 0.1)
     pushes = (1.0, -1.0)
@@ -176,7 +177,7 @@ def medium(seed=2, steps=8000, dx=0.002):
             return []
         cpt, nrm = frame(thetas[k])
         if r < t_cut:
-            z = 0.038 - 0.1 * (r * dt)
+            z = z_start - 0.1 * (r * dt)
             bl = blade(k, (cpt[0], cpt[1], z), nrm, (0, 0, -1), (0, 0, -0.1), 0.075, 6 * dx, 0.05, dx,
                        new_cut=(r == 0))
             return [tool(bl, labels=True, contact=True, cutting=True)]
