@@ -64,7 +64,20 @@ def main():
     ap.add_argument("--workload", default=os.environ.get("TLMPM_BENCH_WORKLOAD", "medium"))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=200)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES bytes (5 times) and exit; used to scale "
+                         "hardware traffic counters")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        nb = args.copy_calibration
+        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": nb}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
                                    "described in the design notes, not built)"}))

@@ -18,8 +18,9 @@
 #include "tlmpm_common.h"
 
 extern "C" {
-hipError_t tl_launch_p2g(const SceneK*, const SceneD*, int, int, double, int, int, int, int, int, int, int,
-                         hipStream_t);
+hipError_t tl_launch_p2g(const SceneK*, const SceneD*, int, int, int, int, int, int, hipStream_t);
+hipError_t tl_launch_rigid(const SceneK*, const SceneD*, int, int, double, int, hipStream_t);
+hipError_t tl_launch_mixed(const SceneK*, const SceneD*, int, hipStream_t);
 hipError_t tl_launch_g2p(const SceneK*, const SceneD*, int, hipStream_t);
 hipError_t tl_launch_labels(const SceneK*, const SceneD*, int, double, int, hipStream_t);
 hipError_t tl_launch_slots(const SceneK*, const SceneD*, int, int, int, hipStream_t);
@@ -27,8 +28,8 @@ hipError_t tl_launch_fill_f32(float*, long long, float, hipStream_t);
 hipError_t tl_launch_fill_i32(int*, long long, int, hipStream_t);
 hipError_t tl_launch_aabb(const SceneK*, const SceneD*, hipStream_t);
 hipError_t tl_launch_wrench(const SceneD*, int, hipStream_t);
-hipError_t tl_launch_cellmask(const SceneK*, const SceneD*, long long, int, hipStream_t);
-hipError_t tl_launch_cand(const SceneK*, const SceneD*, hipStream_t);
+hipError_t tl_launch_cellmask(const SceneK*, const SceneD*, long long, int, int, hipStream_t);
+hipError_t tl_launch_cand(const SceneK*, const SceneD*, int, hipStream_t);
 hipError_t tl_launch_contact(const SceneK*, const SceneD*, unsigned, int, int, int, hipStream_t);
 }
 
@@ -129,7 +130,7 @@ Dims dims_of(const tlmpm_scene_desc* d)
 
 struct Offsets {
     size_t X, u, v, H, code, code_prev, D, perm, E, m, V0, cell_start, active, cnt0, cnt1, sc0, sc1, p2g, rs, hist,
-        aabb, wpart, wacc, Jmat, tools, status, dirty, cmask, cstatic, bcand, hbin, htab, hnext, ph_n, ph_q, ph_u,
+        aabb, wpart, wacc, Jmat, Jrig, brig, bmixed, tools, status, dirty, bdirty, pcell, cand_idx, cmask, cstatic, bcand, hbin, bcount, bids, cslot, brec, htab, hnext, orec, ph_n, ph_q, ph_u,
         total;
     uint32_t hmask;
 };
@@ -158,13 +159,16 @@ Offsets plan(const tlmpm_scene_desc* d)
     o.cnt1 = L.take((size_t)g.NN);
     o.sc0 = L.take((size_t)g.NN * TL_SCAP * 4);
     o.sc1 = L.take((size_t)g.NN * TL_SCAP * 4);
-    o.p2g = L.take((size_t)g.NN * 8 * TL_SCAP * 7 * f);
+    o.p2g = L.take((size_t)g.NN * 8 * TL_SCAP * 8 * f); // 7 components padded to 8
     o.rs = L.take((size_t)g.NN * 8 * TL_SCAP * 4 * f);
     o.hist = L.take((size_t)(TL_MAX_TOOLS + 1) * 4 * N * f);
     o.aabb = L.take((size_t)g.n_bricks * 8 * f);
     o.wpart = L.take((size_t)g.n_bricks * TL_MAX_TOOLS * 6 * f);
     o.wacc = L.take(TL_MAX_TOOLS * 6 * sizeof(double));
     o.Jmat = d->material_contact ? L.take(3 * N * f) : 0;
+    o.Jrig = L.take(3 * N * f);
+    o.brig = L.take((size_t)g.n_bricks * 4);
+    o.bmixed = L.take((size_t)g.n_bricks * 4);
     o.tools = L.take(TL_MAX_TOOLS * sizeof(DevTool));
     o.hmask = 0;
     if (d->material_contact) {
@@ -172,18 +176,26 @@ Offsets plan(const tlmpm_scene_desc* d)
         o.cmask = L.take(cells * 4);
         o.cstatic = L.take(cells);
         o.bcand = L.take((size_t)g.n_bricks * 4);
+        o.cand_idx = L.take(N * 4);
         o.hbin = L.take(4);
-        size_t buckets = 1024;
-        while (buckets < 2 * N) buckets <<= 1;
+        size_t buckets = 4096;
+        while (buckets < N / 2) buckets <<= 1;
         o.hmask = (uint32_t)(buckets - 1);
+        o.bcount = L.take(buckets * 4);
+        o.bids = L.take(buckets * TL_BCAP * 4);
+        o.cslot = L.take(N * 4);
+        o.brec = L.take(buckets * TL_BCAP * 48);
         o.htab = L.take(buckets * 8);
         o.hnext = L.take(N * 4);
+        o.orec = L.take(N * 48);
         o.ph_n = L.take(2 * N * 4);
         o.ph_q = L.take(2 * N * TL_PCAP * 4);
         o.ph_u = L.take(2 * N * TL_PCAP * 3 * f);
     }
     o.status = L.take(4);
     o.dirty = L.take(4);
+    o.bdirty = L.take((size_t)g.n_bricks * 4);
+    o.pcell = L.take(N * 4);
     o.total = L.take(0) + 256;
     return o;
 }
@@ -379,21 +391,32 @@ extern "C" tlmpm_status tlmpm_create_scene(const tlmpm_scene_desc* d, void* ws, 
     D.wpart = (float*)(base + o.wpart);
     D.wacc = (double*)(base + o.wacc);
     D.Jmat = d->material_contact ? (float*)(base + o.Jmat) : nullptr;
+    D.Jrig = (float*)(base + o.Jrig);
+    D.brig = (int*)(base + o.brig);
+    D.bmixed = (int*)(base + o.bmixed);
     D.tools = (DevTool*)(base + o.tools);
     if (d->material_contact) {
         D.cmask = (uint32_t*)(base + o.cmask);
         D.cstatic = (uint8_t*)(base + o.cstatic);
         D.bcand = (int*)(base + o.bcand);
+        D.cand_idx = (int*)(base + o.cand_idx);
         D.hbin = (float*)(base + o.hbin);
-        D.htab = (unsigned long long*)(base + o.htab);
         D.hmask = o.hmask;
+        D.bcount = (int*)(base + o.bcount);
+        D.bids = (int*)(base + o.bids);
+        D.cslot = (int*)(base + o.cslot);
+        D.brec = (float4*)(base + o.brec);
+        D.htab = (unsigned long long*)(base + o.htab);
         D.hnext = (int*)(base + o.hnext);
+        D.orec = (float4*)(base + o.orec);
         D.ph_n = (int*)(base + o.ph_n);
         D.ph_q = (int*)(base + o.ph_q);
         D.ph_u = (float*)(base + o.ph_u);
     }
     D.status = (int*)(base + o.status);
     D.dirty = (int*)(base + o.dirty);
+    D.bdirty = (int*)(base + o.bdirty);
+    D.pcell = (int*)(base + o.pcell);
 
     // sorted SoA host staging
     std::vector<float> h(3 * (size_t)N);
@@ -424,6 +447,11 @@ extern "C" tlmpm_status tlmpm_create_scene(const tlmpm_scene_desc* d, void* ws, 
         if (d->vol0 && (e = up1(D.V0, d->vol0)) != hipSuccess) return bail(e, "upload vol0");
         if ((e = hipMemcpyAsync(D.perm, perm.data(), N * 4, hipMemcpyHostToDevice, sc->st)) != hipSuccess)
             return bail(e, "upload perm");
+        std::vector<int> pc(N);
+        for (long long q = 0; q < N; q++) pc[q] = (int)key[perm[q]];
+        if ((e = hipMemcpyAsync(D.pcell, pc.data(), N * 4, hipMemcpyHostToDevice, sc->st)) != hipSuccess)
+            return bail(e, "upload cells");
+        if ((e = hipStreamSynchronize(sc->st)) != hipSuccess) return bail(e, "upload cells");
     }
     if ((e = hipMemcpyAsync(D.cell_start, cell_start.data(), cell_start.size() * 4, hipMemcpyHostToDevice, sc->st)) !=
         hipSuccess)
@@ -437,9 +465,9 @@ extern "C" tlmpm_status tlmpm_create_scene(const tlmpm_scene_desc* d, void* ws, 
     if ((e = tl_launch_slots(&K, &D, 0, 0, 1, sc->st)) != hipSuccess) return bail(e, "slot table");
     if ((e = tl_launch_aabb(&K, &D, sc->st)) != hipSuccess) return bail(e, "aabb");
     if (d->material_contact) {
-        if ((e = tl_launch_cellmask(&K, &D, g.n_bricks * TL_CELLS, 1, sc->st)) != hipSuccess)
+        if ((e = tl_launch_cellmask(&K, &D, g.n_bricks * TL_CELLS, 1, 1, sc->st)) != hipSuccess)
             return bail(e, "cell masks");
-        if ((e = tl_launch_cand(&K, &D, sc->st)) != hipSuccess) return bail(e, "candidates");
+        if ((e = tl_launch_cand(&K, &D, 1, sc->st)) != hipSuccess) return bail(e, "candidates");
     }
     if ((e = hipStreamSynchronize(sc->st)) != hipSuccess) return bail(e, "create");
     *out = sc;
@@ -485,13 +513,14 @@ extern "C" tlmpm_status tlmpm_destroy_scene(tlmpm_scene* sc)
     return TLMPM_OK;
 }
 
-// contact candidates after a change of side codes
-static tlmpm_status refresh_candidates(tlmpm_scene* sc)
+// contact candidates after a change of side codes (bricks flagged in bdirty, or
+// everything when forced)
+static tlmpm_status refresh_candidates(tlmpm_scene* sc, int force)
 {
     if (!sc->K.material_contact) return TLMPM_OK;
     ProfScope ps(sc, 4);
-    HIPCHK(tl_launch_cellmask(&sc->K, &sc->D, (long long)sc->n_bricks * TL_CELLS, 0, sc->st));
-    HIPCHK(tl_launch_cand(&sc->K, &sc->D, sc->st));
+    HIPCHK(tl_launch_cellmask(&sc->K, &sc->D, (long long)sc->n_bricks * TL_CELLS, 0, force, sc->st));
+    HIPCHK(tl_launch_cand(&sc->K, &sc->D, force, sc->st));
     return TLMPM_OK;
 }
 
@@ -508,14 +537,21 @@ static tlmpm_status label_pass(tlmpm_scene* sc, int n_tools, double jdt, bool an
         ProfScope ps(sc, 2);
         HIPCHK(tl_launch_labels(&sc->K, &D, n_tools, jdt, sc->f_pending ? 1 : 0, sc->st));
     }
+    {
+        ProfScope ps(sc, 3);
+        HIPCHK(tl_launch_mixed(&sc->K, &D, 0, sc->st));
+    }
     int dst = (sc->f_pending && sc->cur == sc->rsb) ? 1 - sc->cur : sc->cur;
     {
         ProfScope ps(sc, 3);
         HIPCHK(tl_launch_slots(&sc->K, &D, dst, sc->cur, 0, sc->st));
     }
-    HIPCHK(tl_launch_fill_i32(D.dirty, 1, 0, sc->st));
     sc->cur = dst;
-    return refresh_candidates(sc);
+    tlmpm_status rs = refresh_candidates(sc, 0);
+    if (rs) return rs;
+    HIPCHK(tl_launch_fill_i32(D.dirty, 1, 0, sc->st));
+    HIPCHK(tl_launch_fill_i32(D.bdirty, sc->n_bricks, 0, sc->st));
+    return TLMPM_OK;
 }
 
 static tlmpm_status upload_tools(tlmpm_scene* sc, const DevTool* t, int n)
@@ -549,7 +585,7 @@ extern "C" tlmpm_status tlmpm_assign_labels(tlmpm_scene* sc, const tlmpm_blade* 
 static tlmpm_status flush_F(tlmpm_scene* sc)
 {
     if (!sc->f_pending) return TLMPM_OK;
-    HIPCHK(tl_launch_p2g(&sc->K, &sc->D, 0, 0, 0.0, 1, 0, 0, sc->cur, sc->rsb, sc->stamp, 0, sc->st));
+    HIPCHK(tl_launch_p2g(&sc->K, &sc->D, 1, 0, 0, sc->cur, sc->rsb, 0, sc->st));
     sc->f_pending = false;
     return TLMPM_OK;
 }
@@ -606,15 +642,19 @@ extern "C" tlmpm_status tlmpm_step(tlmpm_scene* sc, const tlmpm_tool* tools, int
             HIPCHK(tl_launch_contact(&sc->K, &D, (unsigned)sc->stamp, sc->hist_buf, hnew, sc->stamp, sc->st));
             sc->hist_buf = hnew;
         }
-        const bool differ = sc->f_pending && sc->cur != sc->rsb;
-        {
-            ProfScope ps(sc, 0);
-            HIPCHK(tl_launch_p2g(&sc->K, &D, n_tools, any_contact_tool ? 1 : 0, jdt, sc->f_pending ? 1 : 0, 1,
-                                 differ ? 1 : 0, sc->cur, sc->rsb, sc->stamp, do_contact ? 1 : 0, sc->st));
+        if (do_contact) {
+            ProfScope ps(sc, 5);
+            HIPCHK(tl_launch_rigid(&sc->K, &D, n_tools, any_contact_tool ? 1 : 0, jdt, sc->stamp, sc->st));
         }
         if (any_contact_tool) {
             ProfScope ps(sc, 5);
             HIPCHK(tl_launch_wrench(&D, n_tools, sc->st));
+        }
+        const bool differ = sc->f_pending && sc->cur != sc->rsb;
+        {
+            ProfScope ps(sc, 0);
+            HIPCHK(tl_launch_p2g(&sc->K, &D, sc->f_pending ? 1 : 0, 1, differ ? 1 : 0, sc->cur, sc->rsb,
+                                 do_contact ? 1 : 0, sc->st));
         }
         {
             ProfScope ps(sc, 1);
@@ -766,9 +806,10 @@ extern "C" tlmpm_status tlmpm_write_state(tlmpm_scene* sc, uint32_t mask, const 
         HIPCHK(hipStreamSynchronize(sc->st));
     }
     if (codes_changed) {
+        HIPCHK(tl_launch_mixed(&sc->K, &D, 1, sc->st));
         HIPCHK(tl_launch_slots(&sc->K, &D, sc->cur, sc->cur, 1, sc->st));
         sc->rsb = sc->cur;
-        tlmpm_status rs = refresh_candidates(sc);
+        tlmpm_status rs = refresh_candidates(sc, 1);
         if (rs) return rs;
     }
     HIPCHK(tl_launch_aabb(&sc->K, &D, sc->st));

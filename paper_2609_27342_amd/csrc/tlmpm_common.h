@@ -8,8 +8,8 @@
 //                bit 31: material-contact candidate
 //   grid: node ids are brick-major, id = nodebrick * 64 + (lz * 16 + ly * 4 + lx)
 //     slot tables (two buffers): count[node] u8, code[S_CAP][node] u32 (ascending)
-//     P2G partials  [8 contributors][S_CAP][7][node] float  (m, p, dp)
-//     MUSL partials [8 contributors][S_CAP][4][node] float  (m, p~)
+//     P2G partials  [8 contributors][S_CAP][node][8] float  (m, p, dp, pad)
+//     MUSL partials [8 contributors][S_CAP][node][4] float  (m, p~)
 #pragma once
 #include <stdint.h>
 
@@ -33,6 +33,7 @@
 #define TL_ST_CONTACT 16
 
 #define TL_PCAP 12             // persistent pair springs kept per particle
+#define TL_BCAP 8              // candidate records stored inline per hash bucket
 
 // tool flags (same values as the ABI)
 #define TL_TOOL_LABELS 1u
@@ -98,24 +99,35 @@ struct SceneD {
     int n_active;
     uint8_t* cnt[2];
     uint32_t* scode[2];
-    float* p2g;    // [8][S][7][NN]
-    float* rs;     // [8][S][4][NN]
+    float* p2g;    // [8][S][NN][8]
+    float* rs;     // [8][S][NN][4]
     float* hist;   // rigid contact history [TL_MAX_TOOLS+1][4][N]: u_t xyz, stamp
     float* aabb;   // [n_bricks][8]: min xyz, max xyz, max |v|, 0
     float* wpart;  // [n_active][TL_MAX_TOOLS][6]
     double* wacc;  // [TL_MAX_TOOLS][6]
     float* Jmat;   // [3][N] material contact impulse (candidates only)
+    float* Jrig;   // [3][N] floor and tool impulse (bricks with brig set)
+    int* brig;     // [bricks] the brick was within reach of a rigid body this substep
+    int* bmixed;   // [bricks] a cell of the brick holds two side codes
     DevTool* tools;   // [TL_MAX_TOOLS] tools (or label-only blades) of the current call
     int* status;
     int* dirty;
+    int* bdirty;        // [bricks] side codes of the brick changed in the last label pass
+    int* pcell;         // [N] cell slot (sorted cell order) of every particle
     // material contact
     uint32_t* cmask;    // [cells] OR of the codes of each cell (sorted cell order)
     uint8_t* cstatic;   // [cells] cell has an empty or out-of-grid neighbour
-    int* bcand;         // [bricks] brick holds a candidate
+    int* bcand;         // [bricks] number of candidates of the brick
+    int* cand_idx;      // [N] candidates of each brick, stored over the brick's particle range
     float* hbin;        // bin edge (device scalar)
-    unsigned long long* htab; // hash buckets: generation << 32 | head
     uint32_t hmask;     // buckets - 1 (power of two)
-    int* hnext;         // [N] bucket list links
+    int* bcount;        // [buckets] entries of each bucket this substep (cleared per substep)
+    int* bids;          // [buckets][TL_BCAP] particle ids in arrival order
+    int* cslot;         // [N] arrival slot of a candidate in its bucket (-1: overflow)
+    float4* brec;       // [buckets][TL_BCAP][3] inline candidate records
+    unsigned long long* htab; // [buckets] overflow lists: generation << 32 | head
+    int* hnext;         // [N] overflow list links
+    float4* orec;       // [N][3] records of overflowing candidates
     int* ph_n;          // [2][N] stamp << 8 | count of owned springs
     int* ph_q;          // [2][N][TL_PCAP] partner of each spring
     float* ph_u;        // [2][N][TL_PCAP][3] spring, oriented for the owner

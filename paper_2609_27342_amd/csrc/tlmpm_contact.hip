@@ -20,7 +20,6 @@
 #include "tlmpm_common.h"
 
 #define DEV __device__ __forceinline__
-#define TL_MAXC 48
 
 DEV uint32_t ckey(const SceneK& S, uint32_t code) { return S.single_field ? 0u : (code & TL_CODE_MASK); }
 
@@ -52,11 +51,13 @@ DEV void slot_cell(const SceneK& S, long long cs, int& x, int& y, int& z)
     z = bz * TL_B + 2 * ((i >> 2) & 1) + ((w >> 2) & 1);
 }
 
-// per cell: OR of the particles' codes; at creation also the static surface flag
-__global__ void k_cellmask(SceneK S, SceneD D, long long n_slots, int with_static)
+// per cell: OR of the particles' codes; at creation also the static surface flag.
+// Without `force`, only the cells of bricks whose codes changed are recomputed.
+__global__ void k_cellmask(SceneK S, SceneD D, long long n_slots, int with_static, int force)
 {
     long long cs = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (cs >= n_slots) return;
+    if (!force && !D.bdirty[cs / TL_CELLS]) return;
     uint32_t m = 0;
     for (int p = D.cell_start[cs]; p < D.cell_start[cs + 1]; p++) m |= ckey(S, D.code[p]);
     D.cmask[cs] = m;
@@ -75,13 +76,30 @@ __global__ void k_cellmask(SceneK S, SceneD D, long long n_slots, int with_stati
     }
 }
 
-// candidate bit of every particle; per brick: whether it holds a candidate
-__global__ __launch_bounds__(256) void k_cand(SceneK S, SceneD D)
+// Candidate bit of every particle and the brick's candidate list (in particle
+// order, stored over the brick's particle range).  Without `force`, only bricks
+// next to a brick whose codes changed are recomputed.
+__global__ __launch_bounds__(256) void k_cand(SceneK S, SceneD D, int force)
 {
+    __shared__ uint32_t s_nm[TL_CELLS];
+    __shared__ int s_st[TL_CELLS];
+    __shared__ int s_go;
+    __shared__ int s_wave[4];
     const int brick = D.active[blockIdx.x];
     const int bx = brick % S.cbx, by = (brick / S.cbx) % S.cby, bz = brick / (S.cbx * S.cby);
-    bool any = false;
-    for (int c = threadIdx.x / 8; c < TL_CELLS; c += blockDim.x / 8) {
+    if (threadIdx.x == 0) {
+        int go = force;
+        for (int d = 0; d < 27 && !go; d++) {
+            int x = bx + d % 3 - 1, y = by + (d / 3) % 3 - 1, z = bz + d / 9 - 1;
+            if (x < 0 || y < 0 || z < 0 || x >= S.cbx || y >= S.cby || z >= S.cbz) continue;
+            go = D.bdirty[((long long)z * S.cby + y) * S.cbx + x];
+        }
+        s_go = go;
+    }
+    __syncthreads();
+    if (!s_go) return;
+    if (threadIdx.x < TL_CELLS) {
+        const int c = threadIdx.x;
         long long cs = (long long)brick * TL_CELLS + c;
         int w = c >> 3, i = c & 7;
         int x = bx * TL_B + 2 * (i & 1) + (w & 1);
@@ -94,17 +112,37 @@ __global__ __launch_bounds__(256) void k_cand(SceneK S, SceneD D)
                     long long o = cell_slot(S, x + dx, y + dy, z + dz);
                     if (o >= 0) nm |= D.cmask[o];
                 }
-        const bool st = D.cstatic[cs] != 0;
-        for (int p = D.cell_start[cs] + (threadIdx.x & 7); p < D.cell_start[cs + 1]; p += 8) {
+        s_nm[c] = nm;
+        s_st[c] = D.cstatic[cs];
+    }
+    __syncthreads();
+    const int beg = D.cell_start[(long long)brick * TL_CELLS], end = D.cell_start[(long long)(brick + 1) * TL_CELLS];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int base = 0;
+    for (int p0 = beg; p0 < end; p0 += blockDim.x) {
+        const int p = p0 + threadIdx.x;
+        bool cand = false;
+        if (p < end) {
+            int c = (int)(D.pcell[p] - (long long)brick * TL_CELLS);
             uint32_t code = D.code[p];
-            bool cand = st || cconflict(ckey(S, code), nm);
+            cand = s_st[c] || cconflict(ckey(S, code), s_nm[c]);
             uint32_t nc = cand ? (code | TL_CAND_BIT) : (code & ~TL_CAND_BIT);
             if (nc != code) D.code[p] = nc;
-            any |= cand;
         }
+        // ordered compaction: rank = candidates before p in this chunk
+        unsigned long long bal = __ballot(cand);
+        int in_wave = __popcll(bal & ((1ull << lane) - 1ull));
+        if (lane == 0) s_wave[wv] = __popcll(bal);
+        __syncthreads();
+        int before = base;
+        for (int k = 0; k < wv; k++) before += s_wave[k];
+        if (cand) D.cand_idx[beg + before + in_wave] = p;
+        int tot = 0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); k++) tot += s_wave[k];
+        base += tot;
+        __syncthreads();
     }
-    int a = __syncthreads_or(any);
-    if (threadIdx.x == 0) D.bcand[brick] = a;
+    if (threadIdx.x == 0) D.bcand[brick] = base;
 }
 
 // bin edge from the largest speed of any brick (conservative reach)
@@ -142,31 +180,86 @@ DEV void cur_pos(const SceneK& S, const SceneD& D, long long p, float x[3])
     x[2] = D.X[2 * S.N + p] + D.u[2 * S.N + p];
 }
 
+// Candidate record: {id, code, cell, R}, {x, m}, {v, 0} (three float4).
+DEV void make_rec(const SceneK& S, const SceneD& D, int p, const float x[3], float4 r[3])
+{
+    float m = S.m_uniform ? S.m0 : D.m[p];
+    float V0 = S.v_uniform ? S.V0 : D.V0[p];
+    r[0] = make_float4(__int_as_float(p), __uint_as_float(D.code[p]), __int_as_float(D.pcell[p]),
+                       0.5f * S.s_R * cbrtf(V0));
+    r[1] = make_float4(x[0], x[1], x[2], m);
+    r[2] = make_float4(D.v[p], D.v[S.N + p], D.v[2 * S.N + p], 0.0f);
+}
+
+// Bins the candidates of every brick, in two passes that make the content of a
+// bucket independent of arrival order.  Pass 1: slot = atomicAdd on the bucket
+// count; the first TL_BCAP ids are kept, later candidates go to a lock-free
+// overflow list (generation-stamped heads, never cleared).  Pass 2: each kept
+// candidate stores its record at its rank by particle index among the bucket's ids.
 __global__ __launch_bounds__(256) void k_bin_insert(SceneK S, SceneD D, unsigned gen)
 {
     const int brick = D.active[blockIdx.x];
-    if (!D.bcand[brick]) return;
+    const int nc = D.bcand[brick];
+    if (!nc) return;
     const float inv_h = 1.0f / D.hbin[0];
-    const int beg = D.cell_start[(long long)brick * TL_CELLS], end = D.cell_start[(long long)(brick + 1) * TL_CELLS];
-    for (int p = beg + threadIdx.x; p < end; p += blockDim.x) {
-        if (!(D.code[p] & TL_CAND_BIT)) continue;
+    const int beg = D.cell_start[(long long)brick * TL_CELLS];
+    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+        const int p = D.cand_idx[beg + c];
         float x[3];
         cur_pos(S, D, p, x);
         int b[3];
         bin_of(x, inv_h, b);
         uint32_t h = bin_hash(b[0], b[1], b[2], D.hmask);
-        unsigned long long* slot = (unsigned long long*)&D.htab[h];
-        unsigned long long old = *slot, nv;
-        do {
+        int slot = atomicAdd(&D.bcount[h], 1);
+        if (slot < TL_BCAP) {
+            D.bids[(long long)h * TL_BCAP + slot] = p;
+            D.cslot[p] = slot;
+            continue;
+        }
+        D.cslot[p] = -1;
+        float4 r[3];
+        make_rec(S, D, p, x, r);
+        float4* od = D.orec + (long long)p * 3;
+        od[0] = r[0];
+        od[1] = r[1];
+        od[2] = r[2];
+        unsigned long long* hs = (unsigned long long*)&D.htab[h];
+        unsigned long long old = *hs, nv;
+        while (true) {
             unsigned og = (unsigned)(old >> 32);
-            int head = (og == gen) ? (int)(old & 0xFFFFFFFFull) : -1;
-            D.hnext[p] = head;
-            __threadfence();
+            D.hnext[p] = (og == gen) ? (int)(old & 0xFFFFFFFFull) : -1;
             nv = ((unsigned long long)gen << 32) | (unsigned)p;
-            unsigned long long prev = atomicCAS(slot, old, nv);
+            unsigned long long prev = atomicCAS(hs, old, nv);
             if (prev == old) break;
             old = prev;
-        } while (true);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_bin_rank(SceneK S, SceneD D)
+{
+    const int brick = D.active[blockIdx.x];
+    const int nc = D.bcand[brick];
+    if (!nc) return;
+    const float inv_h = 1.0f / D.hbin[0];
+    const int beg = D.cell_start[(long long)brick * TL_CELLS];
+    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+        const int p = D.cand_idx[beg + c];
+        if (D.cslot[p] < 0) continue;
+        float x[3];
+        cur_pos(S, D, p, x);
+        int b[3];
+        bin_of(x, inv_h, b);
+        uint32_t h = bin_hash(b[0], b[1], b[2], D.hmask);
+        const int cnt = min(D.bcount[h], TL_BCAP);
+        int rank = 0;
+        for (int k = 0; k < cnt; k++) rank += D.bids[(long long)h * TL_BCAP + k] < p;
+        float4 r[3];
+        make_rec(S, D, p, x, r);
+        float4* dst = D.brec + ((long long)h * TL_BCAP + rank) * 3;
+        dst[0] = r[0];
+        dst[1] = r[1];
+        dst[2] = r[2];
     }
 }
 
@@ -204,6 +297,20 @@ struct PState {
     float x[3], v[3], m, R;
 };
 
+DEV PState pstate_of(const float4 r[3])
+{
+    PState s;
+    s.x[0] = r[1].x;
+    s.x[1] = r[1].y;
+    s.x[2] = r[1].z;
+    s.m = r[1].w;
+    s.v[0] = r[2].x;
+    s.v[1] = r[2].y;
+    s.v[2] = r[2].z;
+    s.R = r[0].w;
+    return s;
+}
+
 DEV PState load_pstate(const SceneK& S, const SceneD& D, long long p)
 {
     PState s;
@@ -240,124 +347,102 @@ DEV bool pair_impulse(const SceneK& S, const PState& o, const PState& r, float u
 
 DEV void ref_cell(const SceneK& S, const SceneD& D, long long p, int c[3])
 {
-    c[0] = (int)floor(((double)D.X[p] - S.ox) / S.dx);
-    c[1] = (int)floor(((double)D.X[S.N + p] - S.oy) / S.dx);
-    c[2] = (int)floor(((double)D.X[2 * S.N + p] - S.oz) / S.dx);
+    slot_cell(S, D.pcell[p], c[0], c[1], c[2]);
 }
 
 __global__ __launch_bounds__(128) void k_pairs(SceneK S, SceneD D, unsigned gen, int hold, int hnew, int stamp)
 {
     const int brick = D.active[blockIdx.x];
-    if (!D.bcand[brick]) return;
+    const int ncand = D.bcand[brick];
+    if (!ncand) return;
     const float inv_h = 1.0f / D.hbin[0];
     const long long N = S.N;
-    const int beg = D.cell_start[(long long)brick * TL_CELLS], end = D.cell_start[(long long)(brick + 1) * TL_CELLS];
-    for (int p = beg + threadIdx.x; p < end; p += blockDim.x) {
+    const int beg = D.cell_start[(long long)brick * TL_CELLS];
+    for (int ci = threadIdx.x; ci < ncand; ci += blockDim.x) {
+        const int p = D.cand_idx[beg + ci];
         uint32_t code = D.code[p];
-        if (!(code & TL_CAND_BIT)) continue;
         const uint32_t kp = ckey(S, code);
         PState sp = load_pstate(S, D, p);
         int cp[3];
         ref_cell(S, D, p, cp);
         int b[3];
         bin_of(sp.x, inv_h, b);
-        int nq = 0;
-        int qs[TL_MAXC];
-        float Js[TL_MAXC][3];
-        float Us[TL_MAXC][3];
-        for (int dz = -1; dz <= 1; dz++)
-            for (int dy = -1; dy <= 1; dy++)
-                for (int dx = -1; dx <= 1; dx++) {
-                    int bb[3] = {b[0] + dx, b[1] + dy, b[2] + dz};
-                    uint32_t h = bin_hash(bb[0], bb[1], bb[2], D.hmask);
-                    unsigned long long e = D.htab[h];
-                    if ((unsigned)(e >> 32) != gen) continue;
-                    for (int q = (int)(e & 0xFFFFFFFFull); q >= 0; q = D.hnext[q]) {
-                        if (q == p) continue;
-                        PState sq = load_pstate(S, D, q);
-                        int bq[3];
-                        bin_of(sq.x, inv_h, bq);
-                        if (bq[0] != bb[0] || bq[1] != bb[1] || bq[2] != bb[2]) continue; // hash collision
-                        uint32_t kq = ckey(S, D.code[q]);
-                        int cq[3];
-                        ref_cell(S, D, q, cq);
-                        bool near = abs(cp[0] - cq[0]) <= 1 && abs(cp[1] - cq[1]) <= 1 && abs(cp[2] - cq[2]) <= 1;
-                        if (near && !cconflict(kp, kq)) continue; // reading R17 exclusion
-                        const bool own = p < q;
-                        const int o = own ? p : q, r = own ? q : p;
-                        // owner's old spring for this partner
-                        float u[3] = {0.0f, 0.0f, 0.0f};
-                        int hdr = D.ph_n[(long long)hold * N + o];
-                        if ((hdr >> 8) == stamp - 1) {
-                            int cnt = hdr & 0xFF;
-                            const int* ql = D.ph_q + ((long long)hold * N + o) * TL_PCAP;
-                            for (int k = 0; k < cnt; k++)
-                                if (ql[k] == r) {
-                                    const float* ul = D.ph_u + (((long long)hold * N + o) * TL_PCAP + k) * 3;
-                                    u[0] = ul[0];
-                                    u[1] = ul[1];
-                                    u[2] = ul[2];
-                                    break;
-                                }
-                        }
-                        float J[3];
-                        bool hit = own ? pair_impulse(S, sp, sq, u, J) : pair_impulse(S, sq, sp, u, J);
-                        if (!hit) continue;
-                        if (nq == TL_MAXC) {
-                            atomicOr(D.status, TL_ST_CONTACT);
-                            continue;
-                        }
-                        qs[nq] = q;
-                        for (int a = 0; a < 3; a++) {
-                            Js[nq][a] = own ? J[a] : -J[a];
-                            Us[nq][a] = u[a];
-                        }
-                        nq++;
-                    }
-                }
-        // order by partner index, then sum (independent of the bucket list order)
-        for (int a = 1; a < nq; a++) {
-            int key = qs[a];
-            float j0 = Js[a][0], j1 = Js[a][1], j2 = Js[a][2], u0 = Us[a][0], u1 = Us[a][1], u2 = Us[a][2];
-            int c = a - 1;
-            while (c >= 0 && qs[c] > key) {
-                qs[c + 1] = qs[c];
-                Js[c + 1][0] = Js[c][0];
-                Js[c + 1][1] = Js[c][1];
-                Js[c + 1][2] = Js[c][2];
-                Us[c + 1][0] = Us[c][0];
-                Us[c + 1][1] = Us[c][1];
-                Us[c + 1][2] = Us[c][2];
-                c--;
-            }
-            qs[c + 1] = key;
-            Js[c + 1][0] = j0;
-            Js[c + 1][1] = j1;
-            Js[c + 1][2] = j2;
-            Us[c + 1][0] = u0;
-            Us[c + 1][1] = u1;
-            Us[c + 1][2] = u2;
-        }
+        // contacts are visited in a fixed order (bins, then records by particle
+        // index; overflow lists last), so the impulse sum is reproducible
         float Jt[3] = {0.0f, 0.0f, 0.0f};
         int nown = 0;
-        int* ql = D.ph_q + ((long long)hnew * N + p) * TL_PCAP;
-        float* ul = D.ph_u + ((long long)hnew * N + p) * TL_PCAP * 3;
-        for (int k = 0; k < nq; k++) {
-            Jt[0] += Js[k][0];
-            Jt[1] += Js[k][1];
-            Jt[2] += Js[k][2];
-            if (p < qs[k]) {
+        int* ql_new = D.ph_q + ((long long)hnew * N + p) * TL_PCAP;
+        float* ul_new = D.ph_u + ((long long)hnew * N + p) * TL_PCAP * 3;
+        auto visit = [&](const float4 rec[3], const int bb[3]) {
+            const int q = __float_as_int(rec[0].x);
+            if (q == p) return;
+            uint32_t kq = ckey(S, __float_as_uint(rec[0].y));
+            int cq[3];
+            slot_cell(S, __float_as_int(rec[0].z), cq[0], cq[1], cq[2]);
+            bool near = abs(cp[0] - cq[0]) <= 1 && abs(cp[1] - cq[1]) <= 1 && abs(cp[2] - cq[2]) <= 1;
+            if (near && !cconflict(kp, kq)) return; // reading R17 exclusion
+            PState sq = pstate_of(rec);
+            int bq[3];
+            bin_of(sq.x, inv_h, bq);
+            if (bq[0] != bb[0] || bq[1] != bb[1] || bq[2] != bb[2]) return; // hash collision
+            const bool own = p < q;
+            const int o = own ? p : q, r = own ? q : p;
+            // owner's old spring for this partner
+            float u[3] = {0.0f, 0.0f, 0.0f};
+            int hdr = D.ph_n[(long long)hold * N + o];
+            if ((hdr >> 8) == stamp - 1) {
+                int cnt = hdr & 0xFF;
+                const int* ql = D.ph_q + ((long long)hold * N + o) * TL_PCAP;
+                for (int k = 0; k < cnt; k++)
+                    if (ql[k] == r) {
+                        const float* ul = D.ph_u + (((long long)hold * N + o) * TL_PCAP + k) * 3;
+                        u[0] = ul[0];
+                        u[1] = ul[1];
+                        u[2] = ul[2];
+                        break;
+                    }
+            }
+            float J[3];
+            bool hit = own ? pair_impulse(S, sp, sq, u, J) : pair_impulse(S, sq, sp, u, J);
+            if (!hit) return;
+            const float sg = own ? 1.0f : -1.0f;
+            Jt[0] += sg * J[0];
+            Jt[1] += sg * J[1];
+            Jt[2] += sg * J[2];
+            if (own) {
                 if (nown < TL_PCAP) {
-                    ql[nown] = qs[k];
-                    ul[nown * 3 + 0] = Us[k][0];
-                    ul[nown * 3 + 1] = Us[k][1];
-                    ul[nown * 3 + 2] = Us[k][2];
+                    ql_new[nown] = q;
+                    ul_new[nown * 3 + 0] = u[0];
+                    ul_new[nown * 3 + 1] = u[1];
+                    ul_new[nown * 3 + 2] = u[2];
                     nown++;
                 } else {
                     atomicOr(D.status, TL_ST_CONTACT);
                 }
             }
-        }
+        };
+        for (int dz = -1; dz <= 1; dz++)
+            for (int dy = -1; dy <= 1; dy++)
+                for (int dx = -1; dx <= 1; dx++) {
+                    int bb[3] = {b[0] + dx, b[1] + dy, b[2] + dz};
+                    uint32_t h = bin_hash(bb[0], bb[1], bb[2], D.hmask);
+                    const int cnt = D.bcount[h];
+                    const int inl = cnt < TL_BCAP ? cnt : TL_BCAP;
+                    for (int k = 0; k < inl; k++) {
+                        const float4* src = D.brec + ((long long)h * TL_BCAP + k) * 3;
+                        float4 rec[3] = {src[0], src[1], src[2]};
+                        visit(rec, bb);
+                    }
+                    if (cnt > TL_BCAP) {
+                        unsigned long long e = D.htab[h];
+                        if ((unsigned)(e >> 32) == gen)
+                            for (int q = (int)(e & 0xFFFFFFFFull); q >= 0; q = D.hnext[q]) {
+                                const float4* src = D.orec + (long long)q * 3;
+                                float4 rec[3] = {src[0], src[1], src[2]};
+                                visit(rec, bb);
+                            }
+                    }
+                }
         D.ph_n[(long long)hnew * N + p] = (stamp << 8) | nown;
         D.Jmat[p] = Jt[0];
         D.Jmat[N + p] = Jt[1];
@@ -365,19 +450,26 @@ __global__ __launch_bounds__(128) void k_pairs(SceneK S, SceneD D, unsigned gen,
     }
 }
 
+__global__ void k_zero_i32(int* p, long long n)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
 extern "C" {
-hipError_t tl_launch_cellmask(const SceneK* S, const SceneD* D, long long n_slots, int with_static, hipStream_t st)
+hipError_t tl_launch_cellmask(const SceneK* S, const SceneD* D, long long n_slots, int with_static, int force,
+                              hipStream_t st)
 {
     if (n_slots <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_cellmask, dim3((unsigned)((n_slots + 255) / 256)), dim3(256), 0, st, *S, *D, n_slots,
-                       with_static);
+                       with_static, force);
     return hipGetLastError();
 }
 
-hipError_t tl_launch_cand(const SceneK* S, const SceneD* D, hipStream_t st)
+hipError_t tl_launch_cand(const SceneK* S, const SceneD* D, int force, hipStream_t st)
 {
     if (D->n_active == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_cand, dim3(D->n_active), dim3(256), 0, st, *S, *D);
+    hipLaunchKernelGGL(k_cand, dim3(D->n_active), dim3(256), 0, st, *S, *D, force);
     return hipGetLastError();
 }
 
@@ -388,7 +480,14 @@ hipError_t tl_launch_contact(const SceneK* S, const SceneD* D, unsigned gen, int
     hipLaunchKernelGGL(k_hsize, dim3(1), dim3(256), 0, st, *S, *D);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    long long nb = (long long)D->hmask + 1;
+    hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st, D->bcount, nb);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_bin_insert, dim3(D->n_active), dim3(256), 0, st, *S, *D, gen);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_bin_rank, dim3(D->n_active), dim3(256), 0, st, *S, *D);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_pairs, dim3(D->n_active), dim3(128), 0, st, *S, *D, gen, hold, hnew, stamp);

@@ -51,6 +51,15 @@ DEV long long box_gid(const SceneK& S, int bx, int by, int bz, int X, int Y, int
     return (nb << 6) | ((gz & 3) * 16 + (gy & 3) * 4 + (gx & 3));
 }
 
+// Workgroup barrier that orders LDS only: global loads issued before it stay in
+// flight (a full __syncthreads() would also wait for them).
+DEV void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // ------------------------------------------------------------------- box slot table
 struct BoxTab {
     int cnt[TL_BOXN];
@@ -60,10 +69,8 @@ struct BoxTab {
     unsigned char node_of[TL_BOX_SLOTS];
 };
 
-// Loads the slot table of a brick box into LDS.  Returns the number of box slots,
-// or -1 if they exceed TL_BOX_SLOTS (the whole block sees the same value).
-DEV int load_box(const SceneK& S, const uint8_t* cnt, const uint32_t* scode, int bx, int by, int bz, BoxTab& T,
-                 int* s_total)
+// Phase 1: slot counts of the 125 box nodes (threads < 125, no barrier).
+DEV void box_counts(const SceneK& S, const uint8_t* cnt, int bx, int by, int bz, BoxTab& T)
 {
     const int tid = threadIdx.x;
     if (tid < TL_BOXN) {
@@ -72,37 +79,40 @@ DEV int load_box(const SceneK& S, const uint8_t* cnt, const uint32_t* scode, int
         T.gid[tid] = g;
         T.cnt[tid] = g >= 0 ? (int)cnt[g] : 0;
     }
-    __syncthreads();
-    if (tid < 64) { // wave 0: exclusive scan of 125 counts, two per lane
-        int a = 2 * tid, b = 2 * tid + 1;
-        int va = a < TL_BOXN ? T.cnt[a] : 0;
-        int vb = b < TL_BOXN ? T.cnt[b] : 0;
-        int s = va + vb, incl = s;
-        for (int o = 1; o < 64; o <<= 1) {
-            int t = __shfl_up(incl, o, 64);
-            if (tid >= o) incl += t;
-        }
-        int excl = incl - s;
-        if (a < TL_BOXN) T.base[a] = excl;
-        if (b < TL_BOXN) T.base[b] = excl + va;
-        if (tid == 63) {
-            T.base[TL_BOXN] = incl;
-            *s_total = incl;
-        }
+}
+
+// Phase 2 (after a barrier): exclusive scan of the counts by wave `wave`.
+DEV void box_scan(BoxTab& T, int* s_total, int wave)
+{
+    const int tid = threadIdx.x;
+    if ((tid >> 6) != wave) return;
+    const int l = tid & 63;
+    int a = 2 * l, b = 2 * l + 1;
+    int va = a < TL_BOXN ? T.cnt[a] : 0;
+    int vb = b < TL_BOXN ? T.cnt[b] : 0;
+    int sum = va + vb, incl = sum;
+    for (int o = 1; o < 64; o <<= 1) {
+        int t = __shfl_up(incl, o, 64);
+        if (l >= o) incl += t;
     }
-    __syncthreads();
-    int total = *s_total;
-    if (total > TL_BOX_SLOTS) return -1;
-    if (tid < TL_BOXN) {
-        int c = T.cnt[tid], b0 = T.base[tid];
-        long long g = T.gid[tid];
-        for (int s = 0; s < c; s++) {
-            T.code[b0 + s] = scode[(long long)s * S.NN + g];
-            T.node_of[b0 + s] = (unsigned char)tid;
-        }
+    int excl = incl - sum;
+    if (a < TL_BOXN) T.base[a] = excl;
+    if (b < TL_BOXN) T.base[b] = excl + va;
+    if (l == 63) {
+        T.base[TL_BOXN] = incl;
+        *s_total = incl;
     }
-    __syncthreads();
-    return total;
+}
+
+// Phase 3 (after a barrier, threads < 125): codes of this thread's node.
+DEV void box_codes(const SceneK& S, const uint32_t* scode, BoxTab& T, int bn)
+{
+    int c = T.cnt[bn], b0 = T.base[bn];
+    long long g = T.gid[bn];
+    for (int s = 0; s < c; s++) {
+        T.code[b0 + s] = scode[(long long)s * S.NN + g];
+        T.node_of[b0 + s] = (unsigned char)bn;
+    }
 }
 
 DEV int find_slot(const BoxTab& T, int bn, uint32_t key)
@@ -114,27 +124,52 @@ DEV int find_slot(const BoxTab& T, int bn, uint32_t key)
     return -1;
 }
 
-// Sum of one box slot over the bricks that contributed to its node, in fixed
-// contributor order.  part: [8][TL_SCAP][Q][NN].
+// Partial arrays are [8 contributors][TL_SCAP slots][node][QP floats]: the Q
+// components of one node-slot are contiguous (QP = Q rounded up to 4 floats).
 template <int Q>
-DEV void gather_slot(const SceneK& S, const float* __restrict__ part, const BoxTab& T, int q, int bx, int by, int bz,
-                     float* out)
+struct QPad {
+    static constexpr int value = (Q + 3) & ~3;
+};
+
+// Sums of all slots of box node bn over the bricks that contributed to it, in
+// fixed contributor order, written to dst[slot * Q + c].
+template <int Q>
+DEV void gather_node(const SceneK& S, const float* __restrict__ part, const BoxTab& T, int bn, int bx, int by, int bz,
+                     float* dst)
 {
-    int bn = T.node_of[q];
-    int s = q - T.base[bn];
-    long long g = T.gid[bn];
-    int X = bn % 5, Y = (bn / 5) % 5, Z = bn / 25;
-    // home brick of the node and its local coordinates
-    int hx = bx + (X >> 2), hy = by + (Y >> 2), hz = bz + (Z >> 2);
-    int lx = X & 3, ly = Y & 3, lz = Z & 3;
-    for (int c = 0; c < Q; c++) out[c] = 0.0f;
+    constexpr int QP = QPad<Q>::value;
+    const int c = T.cnt[bn], b0 = T.base[bn];
+    const long long g = T.gid[bn];
+    const int X = bn % 5, Y = (bn / 5) % 5, Z = bn / 25;
+    const int hx = bx + (X >> 2), hy = by + (Y >> 2), hz = bz + (Z >> 2);
+    const int lx = X & 3, ly = Y & 3, lz = Z & 3;
+    unsigned valid = 0;
     for (int d = 0; d < 8; d++) {
         int dx = d & 1, dy = (d >> 1) & 1, dz = (d >> 2) & 1;
         if ((dx && lx) || (dy && ly) || (dz && lz)) continue;
         int cbx = hx - dx, cby = hy - dy, cbz = hz - dz;
         if (cbx < 0 || cby < 0 || cbz < 0 || cbx >= S.cbx || cby >= S.cby || cbz >= S.cbz) continue;
-        const float* pp = part + ((long long)(d * TL_SCAP + s) * Q) * S.NN + g;
-        for (int c = 0; c < Q; c++) out[c] += pp[(long long)c * S.NN];
+        valid |= 1u << d;
+    }
+    for (int s = 0; s < c; s++) {
+        float acc[QP];
+#pragma unroll
+        for (int q = 0; q < QP; q++) acc[q] = 0.0f;
+#pragma unroll
+        for (int d = 0; d < 8; d++) {
+            if (!(valid & (1u << d))) continue;
+            const float4* pp = (const float4*)(part + (((long long)(d * TL_SCAP + s)) * S.NN + g) * QP);
+#pragma unroll
+            for (int q4 = 0; q4 < QP / 4; q4++) {
+                float4 v4 = pp[q4];
+                acc[4 * q4 + 0] += v4.x;
+                acc[4 * q4 + 1] += v4.y;
+                acc[4 * q4 + 2] += v4.z;
+                acc[4 * q4 + 3] += v4.w;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < Q; q++) dst[(b0 + s) * Q + q] = acc[q];
     }
 }
 
@@ -249,23 +284,42 @@ DEV void reduce_scatter8(Gen&& gen, float (&res)[Q], int j)
 }
 
 // Adds a wave's per-node sums to the LDS box accumulator, one parity class after
-// another (fixed order).  Fast path: every cell of the wave holds one code.
-// Otherwise the codes present in the wave are processed in ascending order with
-// the other codes' contributions masked out.
-template <int Q, class Gen>
-DEV void accumulate_classes(const Lane& L, bool valid, uint32_t key, Gen&& gen, const BoxTab& T, float* acc,
+// another (fixed order).  The QA + QB components come from two generators (two
+// butterflies keep fewer partial sums live).  Fast path: every cell of the wave
+// holds one code.  Otherwise the codes present in the wave are processed in
+// ascending order with the other codes' contributions masked out.
+template <int QA, int QB, bool MIXED, class GA, class GB>
+DEV void accumulate_classes(const Lane& L, bool valid, uint32_t key, GA&& ga, GB&& gb, const BoxTab& T, float* acc,
                             int* status)
 {
+    constexpr int Q = QA + QB;
     const int leader = L.lane & ~7;
     uint32_t lkey = __shfl(key, leader, 64);
     bool gvalid = __shfl((int)valid, leader, 64) != 0;
     bool mixed = valid && key != lkey;
     bool wave_mixed = __any(mixed);
+    if (!MIXED) {
+        // bricks flagged uniform must not hold two codes in one cell
+        if (wave_mixed && L.lane == 0) atomicOr(status, TL_ST_LOOKUP);
+        wave_mixed = false;
+    }
     float res[Q];
-    if (!wave_mixed) reduce_scatter8<Q>(gen, res, L.j);
+    auto reduce_both = [&](auto&& fa, auto&& fb) {
+        float ra[QA];
+        reduce_scatter8<QA>(fa, ra, L.j);
+#pragma unroll
+        for (int q = 0; q < QA; q++) res[q] = ra[q];
+        if constexpr (QB > 0) {
+            float rb[QB];
+            reduce_scatter8<QB>(fb, rb, L.j);
+#pragma unroll
+            for (int q = 0; q < QB; q++) res[QA + q] = rb[q];
+        }
+    };
+    if (!wave_mixed) reduce_both(ga, gb);
     const int bn = box_index(L.cxl + (L.j & 1), L.cyl + ((L.j >> 1) & 1), L.czl + ((L.j >> 2) & 1));
     for (int phase = 0; phase < 8; phase++) {
-        __syncthreads();
+        lds_barrier();
         if (L.w != phase) continue;
         if (!wave_mixed) {
             if (gvalid) {
@@ -275,7 +329,7 @@ DEV void accumulate_classes(const Lane& L, bool valid, uint32_t key, Gen&& gen, 
                 else
                     for (int q = 0; q < Q; q++) acc[sl * Q + q] += res[q];
             }
-        } else {
+        } else if constexpr (MIXED) {
             bool pending = valid;
             while (__any(pending)) {
                 uint32_t mk = pending ? key : 0xFFFFFFFFu;
@@ -284,12 +338,17 @@ DEV void accumulate_classes(const Lane& L, bool valid, uint32_t key, Gen&& gen, 
                     mk = t < mk ? t : mk;
                 }
                 const bool mine = pending && key == mk;
-                auto masked = [&](int k, float* out) {
-                    gen(k, out);
+                auto ma = [&](int k, float* out) {
+                    ga(k, out);
 #pragma unroll
-                    for (int q = 0; q < Q; q++) out[q] = mine ? out[q] : 0.0f;
+                    for (int q = 0; q < QA; q++) out[q] = mine ? out[q] : 0.0f;
                 };
-                reduce_scatter8<Q>(masked, res, L.j);
+                auto mb = [&](int k, float* out) {
+                    gb(k, out);
+#pragma unroll
+                    for (int q = 0; q < QB; q++) out[q] = mine ? out[q] : 0.0f;
+                };
+                reduce_both(ma, mb);
                 unsigned long long bal = __ballot(mine);
                 bool present = ((bal >> leader) & 0xFFull) != 0ull;
                 if (present) {
@@ -303,20 +362,25 @@ DEV void accumulate_classes(const Lane& L, bool valid, uint32_t key, Gen&& gen, 
             }
         }
     }
-    __syncthreads();
+    lds_barrier();
 }
 
-// Writes the box accumulator as this brick's partial.  part: [8][TL_SCAP][Q][NN].
+// Writes the box accumulator as this brick's partial (layout of gather_node).
 template <int Q>
 DEV void write_partials(const SceneK& S, float* __restrict__ part, const BoxTab& T, int total, const float* acc)
 {
+    constexpr int QP = QPad<Q>::value;
     for (int q = threadIdx.x; q < total; q += blockDim.x) {
         int bn = T.node_of[q];
         int s = q - T.base[bn];
         int X = bn % 5, Y = (bn / 5) % 5, Z = bn / 25;
         int k = (X == 4) | ((Y == 4) << 1) | ((Z == 4) << 2);
-        float* pp = part + ((long long)(k * TL_SCAP + s) * Q) * S.NN + T.gid[bn];
-        for (int c = 0; c < Q; c++) pp[(long long)c * S.NN] = acc[q * Q + c];
+        float4* pp = (float4*)(part + (((long long)(k * TL_SCAP + s)) * S.NN + T.gid[bn]) * QP);
+        float v[QP];
+#pragma unroll
+        for (int c = 0; c < QP; c++) v[c] = c < Q ? acc[q * Q + c] : 0.0f;
+#pragma unroll
+        for (int q4 = 0; q4 < QP / 4; q4++) pp[q4] = make_float4(v[4 * q4], v[4 * q4 + 1], v[4 * q4 + 2], v[4 * q4 + 3]);
     }
 }
 
@@ -532,116 +596,190 @@ struct KA_Args {
     int tabs_differ;
     int cur;      // current slot table buffer
     int rsb;      // slot table buffer of the pending re-scatter
-    int stamp;    // contact-history stamp of this substep
-    int do_contact;
+    int rigid;    // k_rigid ran this substep
+};
+
+// --------------------------------------------------------------------- rigid contact
+// Floor and tool contact of every particle of bricks whose AABB can reach a rigid
+// body this substep (Eqs. 14-16, 5): impulses to Jrig, cutting progress D, contact
+// springs, and per-brick wrench sums (wave tree, then waves in order).
+struct KR_Args {
     int n_tools;
     int any_tool_contact;
+    int stamp;    // contact-history stamp of this substep
     double jdt;   // time since the stored tool pose (TL_TOOL_ADVANCE)
 };
 
+__global__ __launch_bounds__(256) void k_rigid(SceneK S, SceneD D, KR_Args A)
+{
+    __shared__ int s_near[TL_MAX_TOOLS + 1];
+    __shared__ int s_any;
+    __shared__ float s_wr[4][TL_MAX_TOOLS * 6];
+    const int brick = D.active[blockIdx.x];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const long long N = S.N;
+    if (tid <= TL_MAX_TOOLS) {
+        const float* bb = D.aabb + (long long)brick * 8;
+        int nr = 0;
+        if (tid == 0)
+            nr = S.floor_on ? brick_near_tool(S, bb, nullptr, S.Rmax, A.jdt) : 0;
+        else if (tid - 1 < A.n_tools)
+            nr = (D.tools[tid - 1].flags & TL_TOOL_CONTACT) ? brick_near_tool(S, bb, &D.tools[tid - 1], S.Rmax, A.jdt)
+                                                             : 0;
+        s_near[tid] = nr;
+    }
+    if (lane < TL_MAX_TOOLS * 6) s_wr[wv][lane] = 0.0f;
+    __syncthreads();
+    if (tid == 0) {
+        int any = 0;
+        for (int b = 0; b <= A.n_tools; b++) any |= s_near[b];
+        s_any = any;
+        D.brig[brick] = any;
+    }
+    __syncthreads();
+    const bool want_wrench = A.any_tool_contact != 0;
+    if (s_any) {
+        const int beg = D.cell_start[(long long)brick * TL_CELLS], end = D.cell_start[(long long)(brick + 1) * TL_CELLS];
+        for (int p0 = beg; p0 < end; p0 += blockDim.x) {
+            const int p = p0 + tid;
+            const bool valid = p < end;
+            float x[3] = {0.0f, 0.0f, 0.0f}, v[3] = {0.0f, 0.0f, 0.0f}, m = 0.0f, V0 = 0.0f, R = 0.0f, Dp = 0.0f;
+            float Jc[3] = {0.0f, 0.0f, 0.0f};
+            if (valid) {
+                for (int a = 0; a < 3; a++) {
+                    x[a] = D.X[a * N + p] + D.u[a * N + p];
+                    v[a] = D.v[a * N + p];
+                }
+                m = S.m_uniform ? S.m0 : D.m[p];
+                V0 = S.v_uniform ? S.V0 : D.V0[p];
+                R = 0.5f * S.s_R * cbrtf(V0);
+                Dp = D.D[p];
+                if (s_near[0]) rigid_one(S, D, nullptr, 0, p, x, v, m, V0, R, A.stamp, A.jdt, Jc, Dp, Dp, nullptr);
+            }
+            const float Ds = valid ? D.D[p] : 0.0f;
+            for (int b = 0; b < A.n_tools; b++) {
+                if (!s_near[b + 1]) continue;
+                float wr[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+                if (valid) rigid_one(S, D, &D.tools[b], 1 + b, p, x, v, m, V0, R, A.stamp, A.jdt, Jc, Dp, Ds, wr);
+                bool nz = wr[0] != 0.0f || wr[1] != 0.0f || wr[2] != 0.0f;
+                if (want_wrench && __any(nz)) {
+                    for (int q = 0; q < 6; q++) {
+                        float val = wr[q];
+                        for (int o = 32; o >= 1; o >>= 1) val += __shfl_xor(val, o, 64);
+                        if (lane == 0) s_wr[wv][b * 6 + q] += val;
+                    }
+                }
+            }
+            if (valid) {
+                D.Jrig[p] = Jc[0];
+                D.Jrig[N + p] = Jc[1];
+                D.Jrig[2 * N + p] = Jc[2];
+                if (Dp != Ds) D.D[p] = Dp;
+            }
+        }
+    }
+    if (want_wrench) {
+        __syncthreads();
+        if (tid < A.n_tools * 6) {
+            float acc = 0.0f;
+            for (int w = 0; w < 4; w++) acc += s_wr[w][tid];
+            D.wpart[(long long)blockIdx.x * (TL_MAX_TOOLS * 6) + tid] = acc;
+        }
+    }
+}
+
+template <bool MIXED>
 __global__ __launch_bounds__(TL_WG) void k_p2g(SceneK S, SceneD D, KA_Args A)
 {
     __shared__ BoxTab Tc;
     __shared__ BoxTab Tr;
     __shared__ float s_vt[TL_BOX_SLOTS * 3];
-    __shared__ float s_buf[TL_BOX_SLOTS * 7];
-    __shared__ int s_total;
+    __shared__ float s_rsum[TL_BOX_SLOTS * 4];
+    __shared__ float s_acc[TL_BOX_SLOTS * 7];
+    __shared__ int s_total_r, s_total_c;
     __shared__ int s_rounds;
-    __shared__ float s_wr[8][TL_MAX_TOOLS * 6];
-    __shared__ int s_near[TL_MAX_TOOLS + 1];
 
     const int brick = D.active[blockIdx.x];
+    if ((D.bmixed[brick] != 0) != MIXED) return; // the other variant handles this brick
     const int bx = brick % S.cbx, by = (brick / S.cbx) % S.cby, bz = brick / (S.cbx * S.cby);
     const int tid = threadIdx.x;
-
-    const BoxTab* Tv = &Tr;
-    if (A.f_pending) {
-        int tot = load_box(S, D.cnt[A.rsb], D.scode[A.rsb], bx, by, bz, Tr, &s_total);
-        if (tot < 0) {
-            if (tid == 0) atomicOr(D.status, TL_ST_BOX);
-            return;
-        }
-        for (int q = tid; q < tot; q += TL_WG) {
-            float o[4];
-            gather_slot<4>(S, D.rs, Tr, q, bx, by, bz, o);
-            for (int c = 0; c < 4; c++) s_buf[q * 4 + c] = o[c];
-        }
-        __syncthreads();
-        if (tid < TL_BOXN && Tr.cnt[tid] > 0) {
-            int b0 = Tr.base[tid], c = Tr.cnt[tid];
-            couple_node<4>(Tr, b0, c, s_buf, 1, s_vt);
-            for (int a = 0; a < c; a++) {
-                float m = s_buf[(b0 + a) * 4];
-                float im = m > 0.0f ? 1.0f / m : 0.0f;
-                for (int jj = 0; jj < 3; jj++) s_vt[(b0 + a) * 3 + jj] *= im;
-            }
-        }
-        __syncthreads();
-    }
-    int total = 0;
-    if (A.do_p2g) {
-        if (A.tabs_differ || !A.f_pending) {
-            total = load_box(S, D.cnt[A.cur], D.scode[A.cur], bx, by, bz, Tc, &s_total);
-            if (total < 0) {
-                if (tid == 0) atomicOr(D.status, TL_ST_BOX);
-                return;
-            }
-        } else {
-            total = s_total;
-        }
-        for (int q = tid; q < total * 7; q += TL_WG) s_buf[q] = 0.0f;
-        if (tid <= TL_MAX_TOOLS) {
-            int nr = 0;
-            if (A.do_contact) {
-                const float* bb = D.aabb + (long long)brick * 8;
-                const float Rmax = S.Rmax;
-                if (tid == 0)
-                    nr = S.floor_on ? brick_near_tool(S, bb, nullptr, Rmax, A.jdt) : 0;
-                else if (tid - 1 < A.n_tools)
-                    nr = (D.tools[tid - 1].flags & TL_TOOL_CONTACT) ? brick_near_tool(S, bb, &D.tools[tid - 1], Rmax, A.jdt)
-                                                                    : 0;
-            }
-            s_near[tid] = nr;
-        }
-    }
-    const BoxTab& T = (A.do_p2g && (A.tabs_differ || !A.f_pending)) ? Tc : Tr;
-    if (tid == 0) s_rounds = 0;
-    __syncthreads();
-
-    Lane L = lane_of(D, brick);
-    if (L.j == 0) atomicMax(&s_rounds, (L.count + 7) >> 3);
-    __syncthreads();
-    const int rounds = s_rounds;
-    const int gxc = bx * TL_B + L.cxl, gyc = by * TL_B + L.cyl, gzc = bz * TL_B + L.czl;
     const long long N = S.N;
     const float dt = S.dt;
-    float wr[TL_MAX_TOOLS * 6];
-    const bool want_wrench = A.do_p2g && A.do_contact && A.any_tool_contact;
+    const bool use_r = A.f_pending != 0;                               // finalize v~ (tables rs)
+    const bool use_c = A.do_p2g && (A.tabs_differ || !A.f_pending); // separate P2G tables
+
+    // ---- phase 1: cell index, box counts, brick-vs-tool tests, round-0 particle loads
+    Lane L = lane_of(D, brick);
+    if (use_r) box_counts(S, D.cnt[A.rsb], bx, by, bz, Tr);
+    if (use_c) box_counts(S, D.cnt[A.cur], bx, by, bz, Tc);
+    if (tid == 0) s_rounds = 0;
+    // floor/tool impulses were computed for this brick by k_rigid
+    const bool rig = A.do_p2g && A.rigid && D.brig[brick] != 0;
+    const int gxc = bx * TL_B + L.cxl, gyc = by * TL_B + L.cyl, gzc = bz * TL_B + L.czl;
+    bool valid = L.j < L.count;
+    long long p = L.beg + L.j;
+    float Xp[3] = {0.0f, 0.0f, 0.0f}, H[9], vel[3] = {0.0f, 0.0f, 0.0f};
+    uint32_t code = 0;
+    auto load_particle = [&]() {
+        Xp[0] = D.X[p];
+        Xp[1] = D.X[N + p];
+        Xp[2] = D.X[2 * N + p];
+        code = D.code[p];
 #pragma unroll
-    for (int q = 0; q < TL_MAX_TOOLS * 6; q++) wr[q] = 0.0f;
+        for (int a = 0; a < 9; a++) H[a] = D.H[a * N + p];
+        if (A.do_p2g)
+            for (int a = 0; a < 3; a++) vel[a] = D.v[a * N + p];
+    };
+    if (valid) load_particle();
+    lds_barrier();
+    if (L.j == 0) atomicMax(&s_rounds, (L.count + 7) >> 3);
+    if (use_r) box_scan(Tr, &s_total_r, 0);
+    if (use_c) box_scan(Tc, &s_total_c, 1);
+    lds_barrier();
+    const int total_r = use_r ? s_total_r : 0;
+    const int total_c = use_c ? s_total_c : total_r;
+    if (total_r > TL_BOX_SLOTS || total_c > TL_BOX_SLOTS) {
+        if (tid == 0) atomicOr(D.status, TL_ST_BOX);
+        return;
+    }
+    // ---- phase 3: per box node: codes, re-scatter sums, coupling, v~ (Eq. 8, MUSL)
+    if (tid < TL_BOXN) {
+        if (use_r) {
+            box_codes(S, D.scode[A.rsb], Tr, tid);
+            const int c = Tr.cnt[tid], b0 = Tr.base[tid];
+            if (c > 0) {
+                gather_node<4>(S, D.rs, Tr, tid, bx, by, bz, s_rsum);
+                couple_node<4>(Tr, b0, c, s_rsum, 1, s_vt);
+                for (int a = 0; a < c; a++) {
+                    float m = s_rsum[(b0 + a) * 4];
+                    float im = m > 0.0f ? 1.0f / m : 0.0f;
+                    for (int jj = 0; jj < 3; jj++) s_vt[(b0 + a) * 3 + jj] *= im;
+                }
+            }
+        }
+        if (use_c) box_codes(S, D.scode[A.cur], Tc, tid);
+    }
+    if (A.do_p2g)
+        for (int q = tid; q < total_c * 7; q += TL_WG) s_acc[q] = 0.0f;
+    lds_barrier();
+    const BoxTab& T = use_c ? Tc : Tr;
+    const int rounds = s_rounds;
 
     for (int r = 0; r < rounds; r++) {
-        const int jj = 8 * r + L.j;
-        const bool valid = jj < L.count;
-        const long long p = L.beg + jj;
+        if (r > 0) {
+            const int jj = 8 * r + L.j;
+            valid = jj < L.count;
+            p = L.beg + jj;
+            if (valid) load_particle();
+        }
         float t[3] = {0.0f, 0.0f, 0.0f};
-        uint32_t code = 0, key = 0;
-        float H[9];
-        float vel[3] = {0.0f, 0.0f, 0.0f};
-        float Xp[3] = {0.0f, 0.0f, 0.0f};
+        uint32_t key = 0;
         if (valid) {
-            Xp[0] = D.X[p];
-            Xp[1] = D.X[N + p];
-            Xp[2] = D.X[2 * N + p];
             frac_of(S, Xp, gxc, gyc, gzc, t);
-            code = D.code[p];
             key = slot_key(S, code);
-            for (int a = 0; a < 9; a++) H[a] = D.H[a * N + p];
-            if (A.do_p2g)
-                for (int a = 0; a < 3; a++) vel[a] = D.v[a * N + p];
         }
         // ---- deformation-gradient update from the remapped velocities (MUSL)
-        if (A.f_pending && valid) {
+        if (use_r && valid) {
             uint32_t kprev = (code & TL_PREV_BIT) ? slot_key(S, D.code_prev[p]) : key;
             float Lg[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
             for (int k = 0; k < 8; k++) {
@@ -680,7 +818,7 @@ __global__ __launch_bounds__(TL_WG) void k_p2g(SceneK S, SceneD D, KA_Args A)
         // ---- stress and external/contact impulses
         float m = 0.0f, V0 = 0.0f, E = 0.0f;
         float Pk[9];
-        float ext[3] = {0.0f, 0.0f, 0.0f};
+        float Jc[3] = {0.0f, 0.0f, 0.0f};
         if (valid) {
             m = S.m_uniform ? S.m0 : D.m[p];
             V0 = S.v_uniform ? S.V0 : D.V0[p];
@@ -689,24 +827,15 @@ __global__ __launch_bounds__(TL_WG) void k_p2g(SceneK S, SceneD D, KA_Args A)
                 atomicOr(D.status, TL_ST_NONFINITE);
                 for (int a = 0; a < 9; a++) Pk[a] = 0.0f;
             }
-            float Jc[3] = {0.0f, 0.0f, 0.0f};
-            if (A.do_contact) {
-                bool anyn = false;
-                for (int b = 0; b <= A.n_tools; b++) anyn |= s_near[b] != 0;
-                if (anyn) {
-                    float up[3] = {D.u[p], D.u[N + p], D.u[2 * N + p]};
-                    float xcur[3] = {Xp[0] + up[0], Xp[1] + up[1], Xp[2] + up[2]};
-                    float R = 0.5f * S.s_R * cbrtf(V0);
-                    float Dp = D.D[p], Ds = Dp;
-                    if (s_near[0])
-                        rigid_one(S, D, nullptr, 0, p, xcur, vel, m, V0, R, A.stamp, A.jdt, Jc, Dp, Ds, nullptr);
-#pragma unroll
-                    for (int b = 0; b < TL_MAX_TOOLS; b++)
-                        if (b < A.n_tools && s_near[b + 1])
-                            rigid_one(S, D, &D.tools[b], 1 + b, p, xcur, vel, m, V0, R, A.stamp, A.jdt, Jc, Dp, Ds,
-                                      &wr[6 * b]);
-                    if (Dp != Ds) D.D[p] = Dp;
-                }
+        } else {
+            for (int a = 0; a < 9; a++) Pk[a] = 0.0f;
+        }
+        float ext[3] = {0.0f, 0.0f, 0.0f};
+        if (valid) {
+            if (rig) { // floor and tool impulses of this substep (k_rigid)
+                Jc[0] += D.Jrig[p];
+                Jc[1] += D.Jrig[N + p];
+                Jc[2] += D.Jrig[2 * N + p];
             }
             if (S.material_contact && (code & TL_CAND_BIT)) {
                 Jc[0] += D.Jmat[p];
@@ -723,7 +852,16 @@ __global__ __launch_bounds__(TL_WG) void k_p2g(SceneK S, SceneD D, KA_Args A)
 #pragma unroll
         for (int a = 0; a < 9; a++) Pk[a] *= sA;
         const float mm = valid ? m : 0.0f;
-        auto gen = [&](int k, float* o) {
+        auto gen_mp = [&](int k, float* o) { // mass and momentum
+            float wx, wy, wz;
+            corner_weights(t, k, wx, wy, wz);
+            float wm = wx * wy * wz * mm;
+            o[0] = wm;
+            o[1] = wm * vel[0];
+            o[2] = wm * vel[1];
+            o[3] = wm * vel[2];
+        };
+        auto gen_dp = [&](int k, float* o) { // internal, external and contact impulse
             float wx, wy, wz;
             corner_weights(t, k, wx, wy, wz);
             float w = wx * wy * wz;
@@ -731,36 +869,16 @@ __global__ __launch_bounds__(TL_WG) void k_p2g(SceneK S, SceneD D, KA_Args A)
             float g1 = ((k & 2) ? S.inv_dx : -S.inv_dx) * wx * wz;
             float g2 = ((k & 4) ? S.inv_dx : -S.inv_dx) * wx * wy;
             bool on = valid && w != 0.0f;
-            float wm = w * mm;
-            o[0] = wm;
-            o[1] = wm * vel[0];
-            o[2] = wm * vel[1];
-            o[3] = wm * vel[2];
 #pragma unroll
             for (int a = 0; a < 3; a++) {
                 float f = Pk[3 * a] * g0 + Pk[3 * a + 1] * g1 + Pk[3 * a + 2] * g2 + w * ext[a];
-                o[4 + a] = on ? f : 0.0f;
+                o[a] = on ? f : 0.0f;
             }
         };
-        accumulate_classes<7>(L, valid, key, gen, T, s_buf, D.status);
+        accumulate_classes<4, 3, MIXED>(L, valid, key, gen_mp, gen_dp, T, s_acc, D.status);
     }
     if (!A.do_p2g) return;
-    write_partials<7>(S, D.p2g, T, total, s_buf);
-    if (want_wrench) {
-        // deterministic block reduction of the wrench sums: wave tree, then waves in order
-#pragma unroll
-        for (int q = 0; q < TL_MAX_TOOLS * 6; q++) {
-            float val = wr[q];
-            for (int o = 32; o >= 1; o >>= 1) val += __shfl_xor(val, o, 64);
-            if (L.lane == 0) s_wr[L.w][q] = val;
-        }
-        __syncthreads();
-        if (tid < A.n_tools * 6) {
-            float acc = 0.0f;
-            for (int wv = 0; wv < 8; wv++) acc += s_wr[wv][tid];
-            D.wpart[(long long)blockIdx.x * (TL_MAX_TOOLS * 6) + tid] = acc;
-        }
-    }
+    write_partials<7>(S, D.p2g, T, total_c, s_acc);
 }
 
 // --------------------------------------------------------------------------- K_B
@@ -768,74 +886,90 @@ __global__ __launch_bounds__(TL_WG) void k_p2g(SceneK S, SceneD D, KA_Args A)
 // P2G partials (sum over contributing bricks, coupling Eq. 8, velocities Eq. 9),
 // PIC/FLIP G2P of v and x (Eq. 17), then the MUSL re-scatter of m_p v_p^{n+1} into
 // this brick's partials.  Also records the brick's current AABB and speed bound.
+template <bool MIXED>
 __global__ __launch_bounds__(TL_WG) void k_g2p(SceneK S, SceneD D, int cur)
 {
     __shared__ BoxTab T;
     __shared__ float s_sum[TL_BOX_SLOTS * 7];
     __shared__ float s_grid[TL_BOX_SLOTS * 6];
+    __shared__ float s_acc[TL_BOX_SLOTS * 4];
     __shared__ int s_total;
     __shared__ int s_rounds;
     __shared__ float s_bb[8][7];
 
     const int brick = D.active[blockIdx.x];
+    if ((D.bmixed[brick] != 0) != MIXED) return; // the other variant handles this brick
     const int bx = brick % S.cbx, by = (brick / S.cbx) % S.cby, bz = brick / (S.cbx * S.cby);
     const int tid = threadIdx.x;
-    int total = load_box(S, D.cnt[cur], D.scode[cur], bx, by, bz, T, &s_total);
-    if (total < 0) {
+    const long long N = S.N;
+    const float dt = S.dt, beta = S.beta;
+
+    // ---- phase 1: cell index, box counts, round-0 particle loads
+    Lane L = lane_of(D, brick);
+    box_counts(S, D.cnt[cur], bx, by, bz, T);
+    if (tid == 0) s_rounds = 0;
+    const int gxc = bx * TL_B + L.cxl, gyc = by * TL_B + L.cyl, gzc = bz * TL_B + L.czl;
+    bool valid = L.j < L.count;
+    long long p = L.beg + L.j;
+    float Xp[3] = {0.0f, 0.0f, 0.0f}, v[3] = {0.0f, 0.0f, 0.0f}, u[3] = {0.0f, 0.0f, 0.0f};
+    uint32_t code = 0;
+    auto load_particle = [&]() {
+        for (int a = 0; a < 3; a++) {
+            Xp[a] = D.X[a * N + p];
+            v[a] = D.v[a * N + p];
+            u[a] = D.u[a * N + p];
+        }
+        code = D.code[p];
+    };
+    if (valid) load_particle();
+    lds_barrier();
+    if (L.j == 0) atomicMax(&s_rounds, (L.count + 7) >> 3);
+    box_scan(T, &s_total, 0);
+    lds_barrier();
+    const int total = s_total;
+    if (total > TL_BOX_SLOTS) {
         if (tid == 0) atomicOr(D.status, TL_ST_BOX);
         return;
     }
-    for (int q = tid; q < total; q += TL_WG) {
-        float o[7];
-        gather_slot<7>(S, D.p2g, T, q, bx, by, bz, o);
-        for (int c = 0; c < 7; c++) s_sum[q * 7 + c] = o[c];
-    }
-    if (tid == 0) s_rounds = 0;
-    __syncthreads();
-    if (tid < TL_BOXN && T.cnt[tid] > 0) {
-        int b0 = T.base[tid], c = T.cnt[tid];
-        // s_grid[slot] = (p_bar, dp_bar) then divided by m: (v^n, dv)
-        float tmp[TL_SCAP * 3];
-        couple_node<7>(T, b0, c, s_sum, 1, s_grid); // p_bar -> s_grid[b0*3 ..] (stride 3)
-        for (int a = 0; a < c * 3; a++) tmp[a] = s_grid[b0 * 3 + a];
-        couple_node<7>(T, b0, c, s_sum, 4, s_grid); // dp_bar
-        for (int a = c - 1; a >= 0; a--) {
-            float m = s_sum[(b0 + a) * 7];
-            float im = m > 0.0f ? 1.0f / m : 0.0f;
-            float dpb[3] = {s_grid[(b0 + a) * 3], s_grid[(b0 + a) * 3 + 1], s_grid[(b0 + a) * 3 + 2]};
-            for (int jj = 0; jj < 3; jj++) {
-                s_grid[TL_BOX_SLOTS * 3 + (b0 + a) * 3 + jj] = dpb[jj] * im; // dv
-                s_grid[(b0 + a) * 3 + jj] = tmp[a * 3 + jj] * im;            // v^n
+    // ---- phase 3: per box node: codes, P2G sums, coupling (Eq. 8), v^n and dv (Eq. 9)
+    if (tid < TL_BOXN) {
+        box_codes(S, D.scode[cur], T, tid);
+        const int c = T.cnt[tid], b0 = T.base[tid];
+        if (c > 0) {
+            gather_node<7>(S, D.p2g, T, tid, bx, by, bz, s_sum);
+            float* gvn = s_grid;
+            float* gdv = s_grid + TL_BOX_SLOTS * 3;
+            couple_node<7>(T, b0, c, s_sum, 1, gvn);
+            couple_node<7>(T, b0, c, s_sum, 4, gdv);
+            for (int a = 0; a < c; a++) {
+                float m = s_sum[(b0 + a) * 7];
+                float im = m > 0.0f ? 1.0f / m : 0.0f;
+                for (int jj = 0; jj < 3; jj++) {
+                    gvn[(b0 + a) * 3 + jj] *= im;
+                    gdv[(b0 + a) * 3 + jj] *= im;
+                }
             }
         }
     }
-    __syncthreads();
-    // the P2G sums are no longer needed: s_sum becomes the re-scatter accumulator
-    for (int q = tid; q < total * 4; q += TL_WG) s_sum[q] = 0.0f;
-
-    Lane L = lane_of(D, brick);
-    if (L.j == 0) atomicMax(&s_rounds, (L.count + 7) >> 3);
-    __syncthreads();
+    for (int q = tid; q < total * 4; q += TL_WG) s_acc[q] = 0.0f;
+    lds_barrier();
     const int rounds = s_rounds;
-    const int gxc = bx * TL_B + L.cxl, gyc = by * TL_B + L.cyl, gzc = bz * TL_B + L.czl;
-    const long long N = S.N;
-    const float dt = S.dt, beta = S.beta;
     float bb[7] = {1e30f, 1e30f, 1e30f, -1e30f, -1e30f, -1e30f, 0.0f};
     const float* gv = s_grid;
     const float* gdv = s_grid + TL_BOX_SLOTS * 3;
     for (int r = 0; r < rounds; r++) {
-        const int jj = 8 * r + L.j;
-        const bool valid = jj < L.count;
-        const long long p = L.beg + jj;
+        if (r > 0) {
+            const int jj = 8 * r + L.j;
+            valid = jj < L.count;
+            p = L.beg + jj;
+            if (valid) load_particle();
+        }
         float t[3] = {0.0f, 0.0f, 0.0f};
         uint32_t key = 0;
         float m = 0.0f, vn1[3] = {0.0f, 0.0f, 0.0f};
         if (valid) {
-            float Xp[3] = {D.X[p], D.X[N + p], D.X[2 * N + p]};
             frac_of(S, Xp, gxc, gyc, gzc, t);
-            key = slot_key(S, D.code[p]);
-            float v[3] = {D.v[p], D.v[N + p], D.v[2 * N + p]};
-            float u[3] = {D.u[p], D.u[N + p], D.u[2 * N + p]};
+            key = slot_key(S, code);
             float av[3] = {0.0f, 0.0f, 0.0f}, ax[3] = {0.0f, 0.0f, 0.0f};
             for (int k = 0; k < 8; k++) {
                 float wx, wy, wz;
@@ -856,10 +990,10 @@ __global__ __launch_bounds__(TL_WG) void k_g2p(SceneK S, SceneD D, int cur)
             }
             for (int a = 0; a < 3; a++) {
                 vn1[a] = beta * v[a] + av[a];
-                u[a] += dt * ax[a];
+                float un = u[a] + dt * ax[a];
                 D.v[a * N + p] = vn1[a];
-                D.u[a * N + p] = u[a];
-                float xa = Xp[a] + u[a];
+                D.u[a * N + p] = un;
+                float xa = Xp[a] + un;
                 bb[a] = fminf(bb[a], xa);
                 bb[3 + a] = fmaxf(bb[3 + a], xa);
             }
@@ -876,9 +1010,9 @@ __global__ __launch_bounds__(TL_WG) void k_g2p(SceneK S, SceneD D, int cur)
             o[2] = w * vn1[1];
             o[3] = w * vn1[2];
         };
-        accumulate_classes<4>(L, valid, key, gen, T, s_sum, D.status);
+        accumulate_classes<4, 0, MIXED>(L, valid, key, gen, gen, T, s_acc, D.status);
     }
-    write_partials<4>(S, D.rs, T, total, s_sum);
+    write_partials<4>(S, D.rs, T, total, s_acc);
     // brick AABB of x^{n+1} and speed bound (used to skip distant contact work)
     for (int q = 0; q < 7; q++) {
         float val = bb[q];
@@ -888,7 +1022,7 @@ __global__ __launch_bounds__(TL_WG) void k_g2p(SceneK S, SceneD D, int cur)
         }
         if (L.lane == 0) s_bb[L.w][q] = val;
     }
-    __syncthreads();
+    lds_barrier();
     if (tid < 7) {
         float val = s_bb[0][tid];
         for (int wv = 1; wv < 8; wv++) val = (tid < 3) ? fminf(val, s_bb[wv][tid]) : fmaxf(val, s_bb[wv][tid]);
@@ -994,7 +1128,10 @@ __global__ __launch_bounds__(256) void k_labels(SceneK S, SceneD D, int n_tools,
             any = true;
         }
     }
-    if (__syncthreads_or(any) && threadIdx.x == 0) *D.dirty = 1;
+    if (__syncthreads_or(any) && threadIdx.x == 0) {
+        *D.dirty = 1;
+        D.bdirty[brick] = 1;
+    }
 }
 
 // ------------------------------------------------------------------- slot tables
@@ -1005,7 +1142,19 @@ __global__ __launch_bounds__(256) void k_slots(SceneK S, SceneD D, int dst, int 
 {
     const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= S.NN) return;
-    if (!force && !*D.dirty) {
+    long long nb = id >> 6;
+    int lid = (int)(id & 63);
+    int hx = (int)(nb % S.nbx), hy = (int)((nb / S.nbx) % S.nby), hz = (int)(nb / ((long long)S.nbx * S.nby));
+    bool rebuild = force != 0;
+    if (!rebuild && *D.dirty) {
+        // a node depends on the cells of bricks h - {0,1}^3
+        for (int d = 0; d < 8 && !rebuild; d++) {
+            int bx = hx - (d & 1), by = hy - ((d >> 1) & 1), bz = hz - ((d >> 2) & 1);
+            if (bx < 0 || by < 0 || bz < 0 || bx >= S.cbx || by >= S.cby || bz >= S.cbz) continue;
+            rebuild = D.bdirty[((long long)bz * S.cby + by) * S.cbx + bx] != 0;
+        }
+    }
+    if (!rebuild) {
         if (dst != src) {
             int c = D.cnt[src][id];
             D.cnt[dst][id] = (uint8_t)c;
@@ -1013,9 +1162,6 @@ __global__ __launch_bounds__(256) void k_slots(SceneK S, SceneD D, int dst, int 
         }
         return;
     }
-    long long nb = id >> 6;
-    int lid = (int)(id & 63);
-    int hx = (int)(nb % S.nbx), hy = (int)((nb / S.nbx) % S.nby), hz = (int)(nb / ((long long)S.nbx * S.nby));
     int gx = hx * 4 + (lid & 3), gy = hy * 4 + ((lid >> 2) & 3), gz = hz * 4 + (lid >> 4);
     uint32_t codes[TL_SCAP];
     int c = 0;
@@ -1049,6 +1195,26 @@ __global__ __launch_bounds__(256) void k_slots(SceneK S, SceneD D, int dst, int 
     if (over) atomicOr(D.status, TL_ST_SLOT);
     D.cnt[dst][id] = (uint8_t)c;
     for (int s = 0; s < c; s++) D.scode[dst][s * S.NN + id] = codes[s];
+}
+
+// ------------------------------------------------------------- mixed-code bricks
+// A brick is "mixed" when one of its cells holds particles of two side codes; its
+// P2G/G2P run in the kernel variant that reduces one code at a time.  Recomputed
+// for bricks whose codes changed (or all, when forced).
+__global__ __launch_bounds__(256) void k_mixed(SceneK S, SceneD D, int force)
+{
+    const int brick = D.active[blockIdx.x];
+    if (!force && !D.bdirty[brick]) return;
+    bool mixed = false;
+    for (int c = threadIdx.x; c < TL_CELLS; c += blockDim.x) {
+        const int* cs = D.cell_start + (long long)brick * TL_CELLS + c;
+        const int b0 = cs[0], b1 = cs[1];
+        if (b1 <= b0) continue;
+        const uint32_t k0 = slot_key(S, D.code[b0]);
+        for (int p = b0 + 1; p < b1; p++) mixed |= slot_key(S, D.code[p]) != k0;
+    }
+    int m = __syncthreads_or(mixed);
+    if (threadIdx.x == 0) D.bmixed[brick] = m;
 }
 
 // --------------------------------------------------------------- small kernels
@@ -1100,52 +1266,64 @@ __global__ __launch_bounds__(256) void k_aabb(SceneK S, SceneD D)
     }
 }
 
-// Sum of the per-brick wrench partials in fixed order (one workgroup), added to the
-// interval accumulator in FP64.
-__global__ __launch_bounds__(256) void k_wrench(SceneD D, int n_tools)
+// Sum of the per-brick wrench partials in fixed order (one workgroup per force or
+// torque component), added to the interval accumulator in FP64.
+__global__ __launch_bounds__(256) void k_wrench(SceneD D)
 {
     __shared__ double s[256];
-    for (int q = 0; q < n_tools * 6; q++) {
-        double acc = 0.0;
-        for (int b = threadIdx.x; b < D.n_active; b += blockDim.x)
-            acc += (double)D.wpart[(long long)b * (TL_MAX_TOOLS * 6) + q];
-        s[threadIdx.x] = acc;
-        __syncthreads();
-        for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-            if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) D.wacc[q] += s[0];
+    const int q = blockIdx.x;
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < D.n_active; b += blockDim.x)
+        acc += (double)D.wpart[(long long)b * (TL_MAX_TOOLS * 6) + q];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
         __syncthreads();
     }
+    if (threadIdx.x == 0) D.wacc[q] += s[0];
 }
 
 // ------------------------------------------------------------------- launchers
 extern "C" {
-hipError_t tl_launch_p2g(const SceneK* S, const SceneD* D, int n_tools, int any_tool_contact, double jdt,
-                         int f_pending, int do_p2g, int tabs_differ, int cur, int rsb, int stamp, int do_contact,
-                         hipStream_t st)
+hipError_t tl_launch_rigid(const SceneK* S, const SceneD* D, int n_tools, int any_tool_contact, double jdt, int stamp,
+                           hipStream_t st)
 {
-    KA_Args A;
+    if (D->n_active == 0) return hipSuccess;
+    KR_Args A;
     A.n_tools = n_tools;
     A.any_tool_contact = any_tool_contact;
+    A.stamp = stamp;
     A.jdt = jdt;
+    hipLaunchKernelGGL(k_rigid, dim3(D->n_active), dim3(256), 0, st, *S, *D, A);
+    return hipGetLastError();
+}
+
+hipError_t tl_launch_p2g(const SceneK* S, const SceneD* D, int f_pending, int do_p2g, int tabs_differ, int cur, int rsb,
+                         int rigid, hipStream_t st)
+{
+    KA_Args A;
     A.f_pending = f_pending;
     A.do_p2g = do_p2g;
     A.tabs_differ = tabs_differ;
     A.cur = cur;
     A.rsb = rsb;
-    A.stamp = stamp;
-    A.do_contact = do_contact;
+    A.rigid = rigid;
     if (D->n_active == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_p2g, dim3(D->n_active), dim3(TL_WG), 0, st, *S, *D, A);
+    hipLaunchKernelGGL(k_p2g<false>, dim3(D->n_active), dim3(TL_WG), 0, st, *S, *D, A);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_p2g<true>, dim3(D->n_active), dim3(TL_WG), 0, st, *S, *D, A);
     return hipGetLastError();
 }
 
 hipError_t tl_launch_g2p(const SceneK* S, const SceneD* D, int cur, hipStream_t st)
 {
     if (D->n_active == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_g2p, dim3(D->n_active), dim3(TL_WG), 0, st, *S, *D, cur);
+    hipLaunchKernelGGL(k_g2p<false>, dim3(D->n_active), dim3(TL_WG), 0, st, *S, *D, cur);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_g2p<true>, dim3(D->n_active), dim3(TL_WG), 0, st, *S, *D, cur);
     return hipGetLastError();
 }
 
@@ -1177,6 +1355,13 @@ hipError_t tl_launch_fill_i32(int* p, long long n, int v, hipStream_t st)
     return hipGetLastError();
 }
 
+hipError_t tl_launch_mixed(const SceneK* S, const SceneD* D, int force, hipStream_t st)
+{
+    if (D->n_active == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mixed, dim3(D->n_active), dim3(256), 0, st, *S, *D, force);
+    return hipGetLastError();
+}
+
 hipError_t tl_launch_aabb(const SceneK* S, const SceneD* D, hipStream_t st)
 {
     if (D->n_active == 0) return hipSuccess;
@@ -1186,7 +1371,8 @@ hipError_t tl_launch_aabb(const SceneK* S, const SceneD* D, hipStream_t st)
 
 hipError_t tl_launch_wrench(const SceneD* D, int n_tools, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_wrench, dim3(1), dim3(256), 0, st, *D, n_tools);
+    if (n_tools <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_wrench, dim3(n_tools * 6), dim3(256), 0, st, *D);
     return hipGetLastError();
 }
 }
