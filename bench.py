@@ -27,7 +27,8 @@ HBM_PEAK_GBS = 8000.0
 #   whole substep (each persistent field read/written once)           -> 136 B
 ALG_BYTES = {"p2g": 100, "g2p": 64}
 ALG_STEP_BYTES = 136
-DEFAULTS = {"small": (100, 10), "small-deep": (100, 10), "medium": (2000, 100), "large": (200, 10)}
+DEFAULTS = {"small": (100, 10), "small-deep": (100, 10), "medium": (2000, 100), "large": (200, 10),
+            "batched": (100, 10)}
 
 
 def run_steps(g, scene, j0, j1):
@@ -54,6 +55,111 @@ def cpu_baseline(scene, budget_s=12.0, max_steps=400):
     n = scene["X"].shape[0]
     return {"value": n * steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
             "sample": f"first {steps} substeps of {scene['name']} ({n} particles), FP64 C oracle, 1 thread"}
+
+
+def roofline_of(prof, value, n, per_particle_extra=0):
+    """Roofline of the dominant kernel class from event timings {class: (ms, launches)}."""
+    kern = {k: {"ms_avg": (v[0] / v[1]) if v[1] else None, "launches": v[1]} for k, v in prof.items()}
+    dom = max(("p2g", "g2p"), key=lambda k: prof[k][0])
+    avg_s = prof[dom][0] / prof[dom][1] * 1e-3
+    per_particle = ALG_BYTES[dom] + (per_particle_extra if dom == "p2g" else 0)
+    achieved = per_particle * n / avg_s / 1e9
+    return {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "step_alg_frac": value * ALG_STEP_BYTES / (HBM_PEAK_GBS * 1e9), "kernels": kern}
+
+
+def batch_calls(scene, j0, j1):
+    """(tools, n_substeps) calls for steps [j0, j1) of a many-scene workload scene:
+    its tools move at constant velocity and start their cuts at step 0."""
+    adv = [dict(t, advance=True) for t in scene["tools_at"](j0)]
+    if j0 == 0 and j1 > 1:
+        return [(adv, 1)] + batch_calls(scene, 1, j1)
+    return [(adv, j1 - j0)] if j1 > j0 else []
+
+
+def bench_batched(args, K, Wm):
+    """The many-scene workload stepped (a) one scene at a time, each scene's K
+    substeps in one call, and (b) as one batch, every launch covering all scenes."""
+    import torch
+    from paper_2609_27342_amd import tlmpm, workloads as W
+    B = W.batched()
+    scenes = B["scenes"]
+    n = sum(s["X"].shape[0] for s in scenes)
+    torch.cuda.set_device(0)
+    print(f"[bench] workload=batched scenes={len(scenes)} n={n} warmup={Wm} steps={K}", file=sys.stderr, flush=True)
+
+    def fresh():
+        return [tlmpm.Scene(s) for s in scenes]
+
+    # (a) plain
+    gs = fresh()
+    for g, s in zip(gs, scenes):
+        for tools, cnt in batch_calls(s, 0, Wm):
+            g.step(tools, cnt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for g, s in zip(gs, scenes):
+        for tools, cnt in batch_calls(s, Wm, Wm + K):
+            g.step(tools, cnt)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    status_plain = max(g.status() for g in gs)
+    for g in gs:
+        g.close()
+    del gs
+    print(f"[bench] plain: {t_plain * 1e3 / K:.4f} ms/step", file=sys.stderr, flush=True)
+
+    # (b) batched
+    gs = fresh()
+    bt = tlmpm.Batch(gs)
+
+    def run(j0, j1):
+        per = [batch_calls(s, j0, j1) for s in scenes]
+        for c in range(len(per[0])):
+            bt.step([p[c][0] for p in per], per[0][c][1])
+
+    run(0, Wm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run(Wm, Wm + K)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    P = min(args.profile_steps, K)
+    bt.profile(True)
+    run(Wm + K, Wm + K + P)
+    prof = bt.profile_read()
+    bt.profile(False)
+    bt.close()
+    status = max(g.status() for g in gs)
+    value = n * K / t_batch
+    plain_value = n * K / t_plain
+    print(f"[bench] batched: {t_batch * 1e3 / K:.4f} ms/step, status={status}", file=sys.stderr, flush=True)
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(scenes[0])
+        cpu["sample"] = "scene 0 of the batch: " + cpu["sample"]
+    return {
+        "metric": "particle-steps/s per GPU",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": Wm,
+        "ms_per_step": t_batch * 1e3 / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "batched", "scenes": len(scenes), "particles": n, "dt": scenes[0]["params"]["dt"],
+                   "material_contact": True, "path": "batched",
+                   "plain": {"value": plain_value, "ms_per_step": t_plain * 1e3 / K, "status": status_plain},
+                   "batched_over_plain": value / plain_value},
+        "status": status,
+        "roofline": roofline_of(prof, value, n),
+        "cpu_baseline": cpu,
+    }
 
 
 def main():
@@ -89,6 +195,9 @@ def main():
     steps_d, warm_d = DEFAULTS.get(args.workload, (200, 10))
     K = args.steps if args.steps is not None else steps_d
     Wm = args.warmup if args.warmup is not None else warm_d
+    if args.workload == "batched":
+        print(json.dumps(bench_batched(args, K, max(Wm, 1))))
+        return
     scene = W.CONFIGS[args.workload]()
     n = scene["X"].shape[0]
     torch.cuda.set_device(0)
@@ -112,14 +221,7 @@ def main():
     run_steps(g, scene, Wm + K, Wm + K + P)
     prof = g.profile_read()
     g.profile(False)
-    kern = {k: {"ms_avg": (v[0] / v[1]) if v[1] else None, "launches": v[1]} for k, v in prof.items()}
-    dom = max(("p2g", "g2p"), key=lambda k: prof[k][0])
-    avg_s = prof[dom][0] / prof[dom][1] * 1e-3
-    per_particle = ALG_BYTES[dom] + (4 if (dom == "p2g" and scene["E"].min() != scene["E"].max()) else 0)
-    achieved = per_particle * n / avg_s / 1e9
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                "step_alg_frac": value * ALG_STEP_BYTES / (HBM_PEAK_GBS * 1e9), "kernels": kern}
+    roofline = roofline_of(prof, value, n, 4 if scene["E"].min() != scene["E"].max() else 0)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(scene)

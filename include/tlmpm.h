@@ -165,6 +165,51 @@ tlmpm_status tlmpm_slot_stats(tlmpm_scene* scene, int64_t* total_slots, int32_t*
 tlmpm_status tlmpm_profile_enable(tlmpm_scene* scene, int32_t enable);
 tlmpm_status tlmpm_profile_read(tlmpm_scene* scene, int32_t n_classes, double* ms, int64_t* launches);
 
+/* ---- Batches: many independent scenes advanced by shared launches.
+ * The substep is exactly that of tlmpm_step (Sec. III); a batch only groups the
+ * kernel launches of its member scenes, so each kernel launch covers the work items
+ * of every scene.  Results are bitwise those of stepping each scene alone with the
+ * same tools.
+ *   - Membership is fixed at creation.  While a batch is alive, its member scenes
+ *     refuse every single-scene call (TLMPM_E_INVALID); tlmpm_batch_destroy
+ *     synchronises and releases them.  A scene belongs to at most one batch.
+ *   - Device memory: one caller workspace of tlmpm_batch_footprint() bytes (the
+ *     per-scene parameter tables, the work-item lists and the per-call tool and
+ *     wrench arrays), kept alive until tlmpm_batch_destroy.  The batch also holds a
+ *     small pinned host staging area for the per-call tools.
+ *   - Streams: creation synchronises the member scenes' streams; afterwards all work
+ *     runs on the batch's stream. */
+typedef struct tlmpm_batch tlmpm_batch; /* opaque */
+
+#define TLMPM_MAX_TOOLS 4
+
+/* Device bytes of a batch over these scenes (n_scenes >= 1, no repeats, none in a
+ * live batch). */
+tlmpm_status tlmpm_batch_footprint(tlmpm_scene* const* scenes, int32_t n_scenes, size_t* device_bytes);
+
+/* Build a batch.  Scenes whose pending deformation-gradient update was left in a
+ * different slot-table state than the others first complete it alone. */
+tlmpm_status tlmpm_batch_create(tlmpm_scene* const* scenes, int32_t n_scenes, void* dev_workspace, size_t bytes,
+                                void* hip_stream, tlmpm_batch** out);
+
+tlmpm_status tlmpm_batch_destroy(tlmpm_batch* batch);
+
+/* n_substeps substeps of every member scene (as tlmpm_step).  tools: array of
+ * n_scenes * TLMPM_MAX_TOOLS records; scene s uses tools[s * TLMPM_MAX_TOOLS + t]
+ * for t < n_tools[s] (unused records are not read; tools may be NULL if every count
+ * is 0).  wrench: NULL, or [n_scenes][TLMPM_MAX_TOOLS][6] averaged per scene as in
+ * tlmpm_step (entries past a scene's tool count are 0); a non-NULL pointer
+ * synchronises.  Invalid tools of any scene fail the call before any launch. */
+tlmpm_status tlmpm_batch_step(tlmpm_batch* batch, const tlmpm_tool* tools, const int32_t* n_tools,
+                              int32_t n_substeps, double* wrench);
+
+/* Waits for the batch's queued work. */
+tlmpm_status tlmpm_batch_sync(tlmpm_batch* batch);
+
+/* Kernel timing of the batch's launches, as tlmpm_profile_enable / _read. */
+tlmpm_status tlmpm_batch_profile_enable(tlmpm_batch* batch, int32_t enable);
+tlmpm_status tlmpm_batch_profile_read(tlmpm_batch* batch, int32_t n_classes, double* ms, int64_t* launches);
+
 /* Text of the last error on the calling thread ("" if none). */
 const char* tlmpm_last_error(void);
 

@@ -10,6 +10,10 @@ SOURCES = [os.path.join(CSRC, "tlmpm_kernels.hip"), os.path.join(CSRC, "tlmpm_co
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
+         # multiply-adds fuse only within one source expression, so every kernel
+         # wrapper around a shared body rounds the same way (bitwise-equal results
+         # for one scene and for a batch)
+         "-ffp-contract=on",
          # packed FP32 instructions stay off: ordinary float code only
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]

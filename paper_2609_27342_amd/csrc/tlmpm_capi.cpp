@@ -18,19 +18,22 @@
 #include "tlmpm_common.h"
 
 extern "C" {
-hipError_t tl_launch_p2g(const SceneK*, const SceneD*, int, int, int, int, int, int, hipStream_t);
-hipError_t tl_launch_rigid(const SceneK*, const SceneD*, int, int, double, int, hipStream_t);
-hipError_t tl_launch_mixed(const SceneK*, const SceneD*, int, hipStream_t);
-hipError_t tl_launch_g2p(const SceneK*, const SceneD*, int, hipStream_t);
-hipError_t tl_launch_labels(const SceneK*, const SceneD*, int, double, int, hipStream_t);
-hipError_t tl_launch_slots(const SceneK*, const SceneD*, int, int, int, hipStream_t);
+hipError_t tl_launch_p2g(const TlLaunch*, int do_p2g, int tabs_differ, int cur, int rsb);
+hipError_t tl_launch_rigid(const TlLaunch*, int j);
+hipError_t tl_launch_mixed(const TlLaunch*, int force);
+hipError_t tl_launch_g2p(const TlLaunch*, int cur);
+hipError_t tl_launch_labels(const TlLaunch*, int j);
+hipError_t tl_launch_slots(const TlLaunch*, int dst, int src, int force);
+hipError_t tl_launch_aabb(const TlLaunch*);
+hipError_t tl_launch_wrench(const TlLaunch*);
+hipError_t tl_launch_resetD(const TlLaunch*);
+hipError_t tl_launch_clear_flags(const TlLaunch*);
+hipError_t tl_launch_clear_wacc(const TlLaunch*);
+hipError_t tl_launch_cellmask(const TlLaunch*, int with_static, int force);
+hipError_t tl_launch_cand(const TlLaunch*, int force);
+hipError_t tl_launch_contact(const TlLaunch*);
 hipError_t tl_launch_fill_f32(float*, long long, float, hipStream_t);
 hipError_t tl_launch_fill_i32(int*, long long, int, hipStream_t);
-hipError_t tl_launch_aabb(const SceneK*, const SceneD*, hipStream_t);
-hipError_t tl_launch_wrench(const SceneD*, int, hipStream_t);
-hipError_t tl_launch_cellmask(const SceneK*, const SceneD*, long long, int, int, hipStream_t);
-hipError_t tl_launch_cand(const SceneK*, const SceneD*, int, hipStream_t);
-hipError_t tl_launch_contact(const SceneK*, const SceneD*, unsigned, int, int, int, hipStream_t);
 }
 
 static thread_local std::string g_err;
@@ -47,6 +50,19 @@ static tlmpm_status fail(tlmpm_status st, const std::string& msg)
         if (e_ != hipSuccess) return fail(TLMPM_E_DEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
     } while (0)
 
+// Kernel timing (diagnostics): pairs of events around launches, per class.
+struct Timing {
+    bool on = false;
+    hipStream_t st = nullptr;
+    std::vector<hipEvent_t> pool;
+    std::vector<std::pair<int, int>> used; // (class, first event index)
+    size_t next = 0;
+    ~Timing()
+    {
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    }
+};
+
 struct tlmpm_scene {
     SceneK K;
     SceneD D;
@@ -55,41 +71,49 @@ struct tlmpm_scene {
     int n_bricks;
     int cur;       // slot table in use
     int rsb;       // slot table of the pending re-scatter
-    bool f_pending;
-    int stamp;
-    int hist_buf = 0;   // pair-spring buffer written last
+    bool f_pending; // host copy of the device flag D.ctr[1]
+    int in_batch = 0; // member of a live batch: single-scene calls are refused
     std::vector<int> active_host;
-    // kernel timing (diagnostics)
-    bool prof = false;
-    std::vector<hipEvent_t> ev_pool;
-    std::vector<std::pair<int, int>> ev_used; // (class, first event index)
-    size_t ev_next = 0;
+    Timing prof;
 };
 
-// Brackets one launch with events when profiling is on.
+// Brackets one launch with events when timing is on.
 struct ProfScope {
-    tlmpm_scene* sc;
+    Timing* tm;
     int cls;
     int idx = -1;
-    ProfScope(tlmpm_scene* s, int c) : sc(s), cls(c)
+    ProfScope(Timing* t, int c) : tm(t), cls(c)
     {
-        if (!sc->prof) return;
-        while (sc->ev_pool.size() < sc->ev_next + 2) {
+        if (!tm || !tm->on) return;
+        while (tm->pool.size() < tm->next + 2) {
             hipEvent_t e;
             if (hipEventCreate(&e) != hipSuccess) return;
-            sc->ev_pool.push_back(e);
+            tm->pool.push_back(e);
         }
-        idx = (int)sc->ev_next;
-        sc->ev_next += 2;
-        (void)hipEventRecord(sc->ev_pool[idx], sc->st);
+        idx = (int)tm->next;
+        tm->next += 2;
+        (void)hipEventRecord(tm->pool[idx], tm->st);
     }
     ~ProfScope()
     {
         if (idx < 0) return;
-        (void)hipEventRecord(sc->ev_pool[idx + 1], sc->st);
-        sc->ev_used.push_back({cls, idx});
+        (void)hipEventRecord(tm->pool[idx + 1], tm->st);
+        tm->used.push_back({cls, idx});
     }
 };
+
+static tlmpm_status timing_read(Timing& tm, int n_classes, double* ms, int64_t* launches);
+
+static TlLaunch single_launch(const tlmpm_scene* sc)
+{
+    TlLaunch L;
+    memset(&L, 0, sizeof(L));
+    L.S = &sc->K;
+    L.D = &sc->D;
+    L.any_material = sc->K.material_contact;
+    L.st = sc->st;
+    return L;
+}
 
 // ------------------------------------------------------------------- layout
 namespace {
@@ -130,7 +154,7 @@ Dims dims_of(const tlmpm_scene_desc* d)
 
 struct Offsets {
     size_t X, u, v, H, code, code_prev, D, perm, E, m, V0, cell_start, active, cnt0, cnt1, sc0, sc1, p2g, rs, hist,
-        aabb, wpart, wacc, Jmat, Jrig, brig, bmixed, tools, status, dirty, bdirty, pcell, cand_idx, cmask, cstatic, bcand, hbin, bcount, bids, cslot, brec, htab, hnext, orec, ph_n, ph_q, ph_u,
+        aabb, wpart, wacc, Jmat, Jrig, brig, bmixed, tools, tinfo, ctr, status, dirty, bdirty, pcell, cand_idx, cmask, cstatic, bcand, hbin, bcount, bids, cslot, brec, htab, hnext, orec, ph_n, ph_q, ph_u,
         total;
     uint32_t hmask;
 };
@@ -170,6 +194,8 @@ Offsets plan(const tlmpm_scene_desc* d)
     o.brig = L.take((size_t)g.n_bricks * 4);
     o.bmixed = L.take((size_t)g.n_bricks * 4);
     o.tools = L.take(TL_MAX_TOOLS * sizeof(DevTool));
+    o.tinfo = L.take(4 * 4);
+    o.ctr = L.take(4 * 4);
     o.hmask = 0;
     if (d->material_contact) {
         size_t cells = (size_t)g.n_bricks * TL_CELLS;
@@ -306,12 +332,12 @@ extern "C" tlmpm_status tlmpm_create_scene(const tlmpm_scene_desc* d, void* ws, 
 
     tlmpm_scene* sc = new tlmpm_scene();
     sc->st = (hipStream_t)hip_stream;
+    sc->prof.st = sc->st;
     sc->max_cuts = d->max_cuts;
     sc->n_bricks = (int)g.n_bricks;
     sc->cur = 0;
     sc->rsb = 0;
     sc->f_pending = false;
-    sc->stamp = 1;
     sc->active_host = active;
     SceneK& K = sc->K;
     memset(&K, 0, sizeof(K));
@@ -395,6 +421,8 @@ extern "C" tlmpm_status tlmpm_create_scene(const tlmpm_scene_desc* d, void* ws, 
     D.brig = (int*)(base + o.brig);
     D.bmixed = (int*)(base + o.bmixed);
     D.tools = (DevTool*)(base + o.tools);
+    D.tinfo = (int*)(base + o.tinfo);
+    D.ctr = (int*)(base + o.ctr);
     if (d->material_contact) {
         D.cmask = (uint32_t*)(base + o.cmask);
         D.cstatic = (uint8_t*)(base + o.cstatic);
@@ -462,107 +490,184 @@ extern "C" tlmpm_status tlmpm_create_scene(const tlmpm_scene_desc* d, void* ws, 
     // rigid-contact history stamps start invalid
     if ((e = tl_launch_fill_f32(D.hist, (long long)(TL_MAX_TOOLS + 1) * 4 * N, 0.0f, sc->st)) != hipSuccess)
         return bail(e, "init history");
-    if ((e = tl_launch_slots(&K, &D, 0, 0, 1, sc->st)) != hipSuccess) return bail(e, "slot table");
-    if ((e = tl_launch_aabb(&K, &D, sc->st)) != hipSuccess) return bail(e, "aabb");
+    // contact-history stamp 1 (stored stamps of 0 read as the previous substep's
+    // empty history), no F update pending
+    if ((e = tl_launch_fill_i32(D.ctr, 1, 1, sc->st)) != hipSuccess) return bail(e, "counters");
+    const TlLaunch L = single_launch(sc);
+    if ((e = tl_launch_slots(&L, 0, 0, 1)) != hipSuccess) return bail(e, "slot table");
+    if ((e = tl_launch_aabb(&L)) != hipSuccess) return bail(e, "aabb");
     if (d->material_contact) {
-        if ((e = tl_launch_cellmask(&K, &D, g.n_bricks * TL_CELLS, 1, 1, sc->st)) != hipSuccess)
-            return bail(e, "cell masks");
-        if ((e = tl_launch_cand(&K, &D, 1, sc->st)) != hipSuccess) return bail(e, "candidates");
+        if ((e = tl_launch_cellmask(&L, 1, 1)) != hipSuccess) return bail(e, "cell masks");
+        if ((e = tl_launch_cand(&L, 1)) != hipSuccess) return bail(e, "candidates");
     }
     if ((e = hipStreamSynchronize(sc->st)) != hipSuccess) return bail(e, "create");
     *out = sc;
     return TLMPM_OK;
 }
 
-extern "C" tlmpm_status tlmpm_profile_enable(tlmpm_scene* sc, int32_t enable)
+static tlmpm_status timing_read(Timing& tm, int n_classes, double* ms, int64_t* launches)
 {
-    if (!sc) return fail(TLMPM_E_INVALID, "null scene");
-    sc->prof = enable != 0;
-    return TLMPM_OK;
-}
-
-extern "C" tlmpm_status tlmpm_profile_read(tlmpm_scene* sc, int32_t n_classes, double* ms, int64_t* launches)
-{
-    if (!sc || n_classes < 0 || n_classes > 6 || (n_classes && (!ms || !launches)))
+    if (n_classes < 0 || n_classes > 6 || (n_classes && (!ms || !launches)))
         return fail(TLMPM_E_INVALID, "bad arguments");
-    HIPCHK(hipStreamSynchronize(sc->st));
+    HIPCHK(hipStreamSynchronize(tm.st));
     for (int c = 0; c < n_classes; c++) {
         ms[c] = 0.0;
         launches[c] = 0;
     }
-    for (auto& u : sc->ev_used) {
+    for (auto& u : tm.used) {
         float t = 0.0f;
-        HIPCHK(hipEventElapsedTime(&t, sc->ev_pool[u.second], sc->ev_pool[u.second + 1]));
+        HIPCHK(hipEventElapsedTime(&t, tm.pool[u.second], tm.pool[u.second + 1]));
         if (u.first < n_classes) {
             ms[u.first] += t;
             launches[u.first] += 1;
         }
     }
-    sc->ev_used.clear();
-    sc->ev_next = 0;
+    tm.used.clear();
+    tm.next = 0;
     return TLMPM_OK;
 }
 
-extern "C" tlmpm_status tlmpm_destroy_scene(tlmpm_scene* sc)
+extern "C" tlmpm_status tlmpm_profile_enable(tlmpm_scene* sc, int32_t enable)
 {
     if (!sc) return fail(TLMPM_E_INVALID, "null scene");
-    for (hipEvent_t e : sc->ev_pool) (void)hipEventDestroy(e);
+    sc->prof.on = enable != 0;
+    return TLMPM_OK;
+}
+
+extern "C" tlmpm_status tlmpm_profile_read(tlmpm_scene* sc, int32_t n_classes, double* ms, int64_t* launches)
+{
+    if (!sc) return fail(TLMPM_E_INVALID, "null scene");
+    return timing_read(sc->prof, n_classes, ms, launches);
+}
+
+static tlmpm_status refuse_batched(tlmpm_scene* sc);
+
+extern "C" tlmpm_status tlmpm_destroy_scene(tlmpm_scene* sc)
+{
+    if (tlmpm_status r = refuse_batched(sc)) return r;
     hipError_t e = hipStreamSynchronize(sc->st);
     delete sc;
     if (e != hipSuccess) return fail(TLMPM_E_DEVICE, std::string("destroy: ") + hipGetErrorString(e));
     return TLMPM_OK;
 }
 
-// contact candidates after a change of side codes (bricks flagged in bdirty, or
-// everything when forced)
-static tlmpm_status refresh_candidates(tlmpm_scene* sc, int force)
+// Host side of a run of substeps: the launch context (one scene or a batch) and the
+// slot-table bookkeeping shared by every scene it covers.
+struct Exec {
+    TlLaunch L;
+    Timing* prof;      // event timing of the launches, or null
+    int cur, rsb;      // slot table in use / of the pending re-scatter
+    bool pending;      // some scene has a pending F update
+};
+
+// label pass over the tools flagged TL_TOOL_LABELS (uploaded with their counts),
+// then slot-table maintenance and contact candidates of the bricks whose codes
+// changed (no host synchronisation)
+static tlmpm_status label_pass(Exec& X, int j, bool reset_D)
 {
-    if (!sc->K.material_contact) return TLMPM_OK;
-    ProfScope ps(sc, 4);
-    HIPCHK(tl_launch_cellmask(&sc->K, &sc->D, (long long)sc->n_bricks * TL_CELLS, 0, force, sc->st));
-    HIPCHK(tl_launch_cand(&sc->K, &sc->D, force, sc->st));
+    if (reset_D) {
+        ProfScope ps(X.prof, 5);
+        HIPCHK(tl_launch_resetD(&X.L));
+    }
+    {
+        ProfScope ps(X.prof, 2);
+        HIPCHK(tl_launch_labels(&X.L, j));
+    }
+    {
+        ProfScope ps(X.prof, 3);
+        HIPCHK(tl_launch_mixed(&X.L, 0));
+    }
+    // a pending F update still needs the tables of its re-scatter
+    const int dst = (X.pending && X.cur == X.rsb) ? 1 - X.cur : X.cur;
+    {
+        ProfScope ps(X.prof, 3);
+        HIPCHK(tl_launch_slots(&X.L, dst, X.cur, 0));
+    }
+    X.cur = dst;
+    if (X.L.any_material) {
+        ProfScope ps(X.prof, 4);
+        HIPCHK(tl_launch_cellmask(&X.L, 0, 0));
+        HIPCHK(tl_launch_cand(&X.L, 0));
+    }
+    HIPCHK(tl_launch_clear_flags(&X.L));
     return TLMPM_OK;
 }
 
-// label pass over the tools in D.tools flagged TL_TOOL_LABELS, then slot-table
-// maintenance (no host synchronisation)
-static tlmpm_status label_pass(tlmpm_scene* sc, int n_tools, double jdt, bool any_new)
+struct CallFlags {
+    bool any_labels = false, any_new = false, any_contact_tool = false, any_rigid = false;
+};
+
+// n_substeps substeps of the whole path
+static tlmpm_status run_substeps(Exec& X, int n_substeps, const CallFlags& f)
 {
-    SceneD& D = sc->D;
-    if (any_new) {
-        ProfScope ps(sc, 5);
-        HIPCHK(tl_launch_fill_f32(D.D, sc->K.N, 0.0f, sc->st));
+    if (f.any_contact_tool) HIPCHK(tl_launch_clear_wacc(&X.L));
+    for (int j = 0; j < n_substeps; j++) {
+        if (f.any_labels) {
+            tlmpm_status s = label_pass(X, j, f.any_new && j == 0);
+            if (s) return s;
+        }
+        if (X.L.any_material) {
+            ProfScope ps(X.prof, 4);
+            HIPCHK(tl_launch_contact(&X.L));
+        }
+        if (f.any_rigid) {
+            ProfScope ps(X.prof, 5);
+            HIPCHK(tl_launch_rigid(&X.L, j));
+        }
+        if (f.any_contact_tool) {
+            ProfScope ps(X.prof, 5);
+            HIPCHK(tl_launch_wrench(&X.L));
+        }
+        {
+            ProfScope ps(X.prof, 0);
+            HIPCHK(tl_launch_p2g(&X.L, 1, X.cur != X.rsb ? 1 : 0, X.cur, X.rsb));
+        }
+        {
+            ProfScope ps(X.prof, 1);
+            HIPCHK(tl_launch_g2p(&X.L, X.cur));
+        }
+        X.pending = true;
+        X.rsb = X.cur;
     }
-    {
-        ProfScope ps(sc, 2);
-        HIPCHK(tl_launch_labels(&sc->K, &D, n_tools, jdt, sc->f_pending ? 1 : 0, sc->st));
-    }
-    {
-        ProfScope ps(sc, 3);
-        HIPCHK(tl_launch_mixed(&sc->K, &D, 0, sc->st));
-    }
-    int dst = (sc->f_pending && sc->cur == sc->rsb) ? 1 - sc->cur : sc->cur;
-    {
-        ProfScope ps(sc, 3);
-        HIPCHK(tl_launch_slots(&sc->K, &D, dst, sc->cur, 0, sc->st));
-    }
-    sc->cur = dst;
-    tlmpm_status rs = refresh_candidates(sc, 0);
-    if (rs) return rs;
-    HIPCHK(tl_launch_fill_i32(D.dirty, 1, 0, sc->st));
-    HIPCHK(tl_launch_fill_i32(D.bdirty, sc->n_bricks, 0, sc->st));
     return TLMPM_OK;
 }
 
-static tlmpm_status upload_tools(tlmpm_scene* sc, const DevTool* t, int n)
+static Exec single_exec(tlmpm_scene* sc)
+{
+    Exec X;
+    X.L = single_launch(sc);
+    X.prof = &sc->prof;
+    X.cur = sc->cur;
+    X.rsb = sc->rsb;
+    X.pending = sc->f_pending;
+    return X;
+}
+
+static void single_done(tlmpm_scene* sc, const Exec& X)
+{
+    sc->cur = X.cur;
+    sc->rsb = X.rsb;
+    sc->f_pending = X.pending;
+}
+
+static tlmpm_status upload_tools(tlmpm_scene* sc, const DevTool* t, int n, const int tinfo[4])
 {
     if (n > 0) HIPCHK(hipMemcpyAsync(sc->D.tools, t, n * sizeof(DevTool), hipMemcpyHostToDevice, sc->st));
+    HIPCHK(hipMemcpyAsync(sc->D.tinfo, tinfo, 4 * sizeof(int), hipMemcpyHostToDevice, sc->st));
+    return TLMPM_OK;
+}
+
+static tlmpm_status refuse_batched(tlmpm_scene* sc)
+{
+    if (!sc) return fail(TLMPM_E_INVALID, "null scene");
+    if (sc->in_batch) return fail(TLMPM_E_INVALID, "scene belongs to a live batch (destroy the batch first)");
     return TLMPM_OK;
 }
 
 extern "C" tlmpm_status tlmpm_assign_labels(tlmpm_scene* sc, const tlmpm_blade* blades, int32_t n_blades)
 {
-    if (!sc || (n_blades > 0 && !blades) || n_blades < 0 || n_blades > TL_MAX_TOOLS)
+    if (tlmpm_status r = refuse_batched(sc)) return r;
+    if ((n_blades > 0 && !blades) || n_blades < 0 || n_blades > TL_MAX_TOOLS)
         return fail(TLMPM_E_INVALID, "bad arguments (at most 4 blades)");
     DevTool t[TL_MAX_TOOLS];
     memset(t, 0, sizeof(t));
@@ -577,41 +682,43 @@ extern "C" tlmpm_status tlmpm_assign_labels(tlmpm_scene* sc, const tlmpm_blade* 
         any_new |= B.new_cut != 0;
     }
     if (n_blades == 0) return TLMPM_OK;
-    tlmpm_status s = upload_tools(sc, t, n_blades);
+    const int tinfo[4] = {n_blades, 0, any_new ? 1 : 0, 0};
+    tlmpm_status s = upload_tools(sc, t, n_blades, tinfo);
     if (s) return s;
-    return label_pass(sc, n_blades, 0.0, any_new);
+    Exec X = single_exec(sc);
+    s = label_pass(X, 0, any_new);
+    single_done(sc, X);
+    return s;
 }
 
+// applies a pending F update on its own (before host access to the state)
 static tlmpm_status flush_F(tlmpm_scene* sc)
 {
     if (!sc->f_pending) return TLMPM_OK;
-    HIPCHK(tl_launch_p2g(&sc->K, &sc->D, 1, 0, 0, sc->cur, sc->rsb, 0, sc->st));
+    const TlLaunch L = single_launch(sc);
+    HIPCHK(tl_launch_p2g(&L, 0, sc->cur != sc->rsb ? 1 : 0, sc->cur, sc->rsb));
+    HIPCHK(tl_launch_fill_i32(sc->D.ctr + 1, 1, 0, sc->st));
     sc->f_pending = false;
     return TLMPM_OK;
 }
 
-extern "C" tlmpm_status tlmpm_step(tlmpm_scene* sc, const tlmpm_tool* tools, int32_t n_tools, int32_t n_substeps,
-                                   double* wrench)
+// checks the tools of one scene and converts them to the device form; returns the
+// per-call flags and the device tool info (count, any contact, new cut)
+static tlmpm_status convert_tools(const tlmpm_scene* sc, const tlmpm_tool* tools, int n_tools, DevTool* dtl,
+                                  int tinfo[4], CallFlags& f)
 {
-    if (!sc || n_tools < 0 || n_tools > TL_MAX_TOOLS || (n_tools > 0 && !tools) || n_substeps < 0)
-        return fail(TLMPM_E_INVALID, "bad arguments (at most 4 tools)");
-    for (int t = 0; t < n_tools; t++) {
-        const tlmpm_blade& B = tools[t].blade;
-        if (!frame_ok(B)) return fail(TLMPM_E_INVALID, "tool frame (n, e, d) must be orthonormal");
-        if ((tools[t].flags & TLMPM_TOOL_LABELS) && (B.cut_index < 0 || B.cut_index >= sc->max_cuts))
-            return fail(TLMPM_E_INVALID, "cut_index out of range");
-        if ((tools[t].flags & TLMPM_TOOL_ADVANCE) &&
-            (tools[t].omega_B[0] != 0 || tools[t].omega_B[1] != 0 || tools[t].omega_B[2] != 0))
-            return fail(TLMPM_E_INVALID, "TLMPM_TOOL_ADVANCE supports translating tools only");
-    }
-    SceneD& D = sc->D;
-    DevTool dtl[TL_MAX_TOOLS];
-    memset(dtl, 0, sizeof(dtl));
+    memset(dtl, 0, TL_MAX_TOOLS * sizeof(DevTool));
     bool any_contact_tool = false, any_labels = false, any_new = false;
     for (int t = 0; t < n_tools; t++) {
         const tlmpm_tool& T = tools[t];
+        const tlmpm_blade& B = T.blade;
+        if (!frame_ok(B)) return fail(TLMPM_E_INVALID, "tool frame (n, e, d) must be orthonormal");
+        if ((T.flags & TLMPM_TOOL_LABELS) && (B.cut_index < 0 || B.cut_index >= sc->max_cuts))
+            return fail(TLMPM_E_INVALID, "cut_index out of range");
+        if ((T.flags & TLMPM_TOOL_ADVANCE) && (T.omega_B[0] != 0 || T.omega_B[1] != 0 || T.omega_B[2] != 0))
+            return fail(TLMPM_E_INVALID, "TLMPM_TOOL_ADVANCE supports translating tools only");
         DevTool& o = dtl[t];
-        o.b = dev_blade(T.blade);
+        o.b = dev_blade(B);
         for (int a = 0; a < 3; a++) {
             o.xB[a] = T.x_B[a];
             o.vB[a] = T.v_B[a];
@@ -622,52 +729,40 @@ extern "C" tlmpm_status tlmpm_step(tlmpm_scene* sc, const tlmpm_tool* tools, int
         o.slot = 1 + t;
         any_contact_tool |= (T.flags & TLMPM_TOOL_CONTACT) != 0;
         any_labels |= (T.flags & TLMPM_TOOL_LABELS) != 0;
-        any_new |= (T.flags & TLMPM_TOOL_LABELS) && T.blade.new_cut;
+        any_new |= (T.flags & TLMPM_TOOL_LABELS) && B.new_cut;
     }
-    const bool do_contact = any_contact_tool || sc->K.floor_on;
-    {
-        tlmpm_status s = upload_tools(sc, dtl, n_tools);
-        if (s) return s;
-    }
-    if (any_contact_tool) HIPCHK(hipMemsetAsync(D.wacc, 0, TL_MAX_TOOLS * 6 * sizeof(double), sc->st));
-    for (int j = 0; j < n_substeps; j++) {
-        const double jdt = (double)j * sc->K.dt_d;
-        if (any_labels) {
-            tlmpm_status s = label_pass(sc, n_tools, jdt, any_new && j == 0);
-            if (s) return s;
-        }
-        if (sc->K.material_contact) {
-            ProfScope ps(sc, 4);
-            int hnew = 1 - sc->hist_buf;
-            HIPCHK(tl_launch_contact(&sc->K, &D, (unsigned)sc->stamp, sc->hist_buf, hnew, sc->stamp, sc->st));
-            sc->hist_buf = hnew;
-        }
-        if (do_contact) {
-            ProfScope ps(sc, 5);
-            HIPCHK(tl_launch_rigid(&sc->K, &D, n_tools, any_contact_tool ? 1 : 0, jdt, sc->stamp, sc->st));
-        }
-        if (any_contact_tool) {
-            ProfScope ps(sc, 5);
-            HIPCHK(tl_launch_wrench(&D, n_tools, sc->st));
-        }
-        const bool differ = sc->f_pending && sc->cur != sc->rsb;
-        {
-            ProfScope ps(sc, 0);
-            HIPCHK(tl_launch_p2g(&sc->K, &D, sc->f_pending ? 1 : 0, 1, differ ? 1 : 0, sc->cur, sc->rsb,
-                                 do_contact ? 1 : 0, sc->st));
-        }
-        {
-            ProfScope ps(sc, 1);
-            HIPCHK(tl_launch_g2p(&sc->K, &D, sc->cur, sc->st));
-        }
-        sc->f_pending = true;
-        sc->rsb = sc->cur;
-        sc->stamp++;
-    }
+    tinfo[0] = n_tools;
+    tinfo[1] = any_contact_tool ? 1 : 0;
+    tinfo[2] = any_new ? 1 : 0;
+    tinfo[3] = 0;
+    f.any_labels |= any_labels;
+    f.any_new |= any_new;
+    f.any_contact_tool |= any_contact_tool;
+    f.any_rigid |= any_contact_tool || sc->K.floor_on;
+    return TLMPM_OK;
+}
+
+extern "C" tlmpm_status tlmpm_step(tlmpm_scene* sc, const tlmpm_tool* tools, int32_t n_tools, int32_t n_substeps,
+                                   double* wrench)
+{
+    if (tlmpm_status r = refuse_batched(sc)) return r;
+    if (n_tools < 0 || n_tools > TL_MAX_TOOLS || (n_tools > 0 && !tools) || n_substeps < 0)
+        return fail(TLMPM_E_INVALID, "bad arguments (at most 4 tools)");
+    DevTool dtl[TL_MAX_TOOLS];
+    int tinfo[4];
+    CallFlags f;
+    tlmpm_status s = convert_tools(sc, tools, n_tools, dtl, tinfo, f);
+    if (s) return s;
+    s = upload_tools(sc, dtl, n_tools, tinfo);
+    if (s) return s;
+    Exec X = single_exec(sc);
+    s = run_substeps(X, n_substeps, f);
+    single_done(sc, X);
+    if (s) return s;
     if (wrench && n_tools > 0) {
         double acc[TL_MAX_TOOLS * 6];
-        if (any_contact_tool) {
-            HIPCHK(hipMemcpyAsync(acc, D.wacc, n_tools * 6 * sizeof(double), hipMemcpyDeviceToHost, sc->st));
+        if (f.any_contact_tool) {
+            HIPCHK(hipMemcpyAsync(acc, sc->D.wacc, n_tools * 6 * sizeof(double), hipMemcpyDeviceToHost, sc->st));
             HIPCHK(hipStreamSynchronize(sc->st));
         } else {
             for (int q = 0; q < n_tools * 6; q++) acc[q] = 0.0;
@@ -680,7 +775,8 @@ extern "C" tlmpm_status tlmpm_step(tlmpm_scene* sc, const tlmpm_tool* tools, int
 
 extern "C" tlmpm_status tlmpm_get_status(tlmpm_scene* sc, int32_t* status)
 {
-    if (!sc || !status) return fail(TLMPM_E_INVALID, "bad arguments");
+    if (tlmpm_status r = refuse_batched(sc)) return r;
+    if (!status) return fail(TLMPM_E_INVALID, "bad arguments");
     int st = 0;
     HIPCHK(hipMemcpyAsync(&st, sc->D.status, 4, hipMemcpyDeviceToHost, sc->st));
     HIPCHK(hipStreamSynchronize(sc->st));
@@ -704,7 +800,8 @@ static uint64_t code_to_ternary(uint32_t c, int K)
 
 extern "C" tlmpm_status tlmpm_read_state(tlmpm_scene* sc, uint32_t mask, void* const* out)
 {
-    if (!sc || (mask && !out)) return fail(TLMPM_E_INVALID, "bad arguments");
+    if (tlmpm_status r = refuse_batched(sc)) return r;
+    if (mask && !out) return fail(TLMPM_E_INVALID, "bad arguments");
     tlmpm_status s = flush_F(sc);
     if (s) return s;
     const long long N = sc->K.N;
@@ -758,7 +855,8 @@ extern "C" tlmpm_status tlmpm_read_state(tlmpm_scene* sc, uint32_t mask, void* c
 
 extern "C" tlmpm_status tlmpm_write_state(tlmpm_scene* sc, uint32_t mask, const void* const* in)
 {
-    if (!sc || (mask && !in)) return fail(TLMPM_E_INVALID, "bad arguments");
+    if (tlmpm_status r = refuse_batched(sc)) return r;
+    if (mask && !in) return fail(TLMPM_E_INVALID, "bad arguments");
     if (mask & (TLMPM_FIELD_X | TLMPM_FIELD_CODE)) return fail(TLMPM_E_INVALID, "X and CODE are not writable");
     tlmpm_status s = flush_F(sc);
     if (s) return s;
@@ -805,21 +903,24 @@ extern "C" tlmpm_status tlmpm_write_state(tlmpm_scene* sc, uint32_t mask, const 
         if (N) HIPCHK(hipMemcpyAsync(dstp, buf.data(), (size_t)comps * N * 4, hipMemcpyHostToDevice, sc->st));
         HIPCHK(hipStreamSynchronize(sc->st));
     }
+    const TlLaunch L = single_launch(sc);
     if (codes_changed) {
-        HIPCHK(tl_launch_mixed(&sc->K, &D, 1, sc->st));
-        HIPCHK(tl_launch_slots(&sc->K, &D, sc->cur, sc->cur, 1, sc->st));
+        HIPCHK(tl_launch_mixed(&L, 1));
+        HIPCHK(tl_launch_slots(&L, sc->cur, sc->cur, 1));
         sc->rsb = sc->cur;
-        tlmpm_status rs = refresh_candidates(sc, 1);
-        if (rs) return rs;
+        if (sc->K.material_contact) {
+            HIPCHK(tl_launch_cellmask(&L, 0, 1));
+            HIPCHK(tl_launch_cand(&L, 1));
+        }
     }
-    HIPCHK(tl_launch_aabb(&sc->K, &D, sc->st));
+    HIPCHK(tl_launch_aabb(&L));
     HIPCHK(hipStreamSynchronize(sc->st));
     return TLMPM_OK;
 }
 
 extern "C" tlmpm_status tlmpm_slot_stats(tlmpm_scene* sc, int64_t* total_slots, int32_t* max_per_node)
 {
-    if (!sc) return fail(TLMPM_E_INVALID, "null scene");
+    if (tlmpm_status r = refuse_batched(sc)) return r;
     std::vector<uint8_t> c(sc->K.NN);
     HIPCHK(hipMemcpyAsync(c.data(), sc->D.cnt[sc->cur], sc->K.NN, hipMemcpyDeviceToHost, sc->st));
     HIPCHK(hipStreamSynchronize(sc->st));
@@ -832,4 +933,278 @@ extern "C" tlmpm_status tlmpm_slot_stats(tlmpm_scene* sc, int64_t* total_slots, 
     if (total_slots) *total_slots = tot;
     if (max_per_node) *max_per_node = mx;
     return TLMPM_OK;
+}
+
+// ------------------------------------------------------------------- batches
+// Many scenes advanced together: one launch per kernel covers the work items of
+// every scene, listed as (scene, block) pairs.  Per-scene parameters stay in
+// device memory (SceneK / SceneD arrays); the tools of a call, their counts and the
+// wrench accumulators of all scenes sit in the batch's own arrays, so a call costs
+// one upload and (with a wrench) one download.
+namespace {
+struct BatchTools {
+    DevTool t[TL_MAX_TOOLS];
+    int tinfo[4];
+};
+
+struct BatchPlan {
+    size_t Ks, Ds, tools, wacc, items[TL_ITEM_KINDS], total;
+    int n_items[TL_ITEM_KINDS];
+};
+
+int ceil_div(long long a, int b) { return (int)((a + b - 1) / b); }
+
+// work items of each kind for one scene
+void scene_items(const tlmpm_scene* sc, int n[TL_ITEM_KINDS])
+{
+    const SceneK& K = sc->K;
+    const long long n_bricks = (long long)K.cbx * K.cby * K.cbz;
+    n[IT_BRICK] = sc->D.n_active;
+    n[IT_NODE] = ceil_div(K.NN, 256);
+    n[IT_CELL] = K.material_contact ? ceil_div(n_bricks * TL_CELLS, 256) : 0;
+    n[IT_BUCKET] = K.material_contact ? ceil_div((long long)sc->D.hmask + 1, 256) : 0;
+    n[IT_SCENE] = 1;
+    n[IT_WRENCH] = TL_MAX_TOOLS * 6;
+    n[IT_PART] = ceil_div(K.N, 256);
+    n[IT_BFLAG] = ceil_div(n_bricks, 256);
+}
+
+tlmpm_status batch_plan(tlmpm_scene* const* scenes, int n, BatchPlan& P)
+{
+    Layout L;
+    P.Ks = L.take((size_t)n * sizeof(SceneK));
+    P.Ds = L.take((size_t)n * sizeof(SceneD));
+    P.tools = L.take((size_t)n * sizeof(BatchTools));
+    P.wacc = L.take((size_t)n * TL_MAX_TOOLS * 6 * sizeof(double));
+    long long tot[TL_ITEM_KINDS] = {0};
+    for (int s = 0; s < n; s++) {
+        int c[TL_ITEM_KINDS];
+        scene_items(scenes[s], c);
+        for (int k = 0; k < TL_ITEM_KINDS; k++) tot[k] += c[k];
+    }
+    for (int k = 0; k < TL_ITEM_KINDS; k++) {
+        if (tot[k] >= (1LL << 31)) return fail(TLMPM_E_INVALID, "batch too large");
+        P.n_items[k] = (int)tot[k];
+        P.items[k] = L.take((size_t)tot[k] * sizeof(int2));
+    }
+    P.total = L.take(0) + 256;
+    return TLMPM_OK;
+}
+
+tlmpm_status check_members(tlmpm_scene* const* scenes, int n)
+{
+    if (n <= 0 || !scenes) return fail(TLMPM_E_INVALID, "a batch needs at least one scene");
+    for (int s = 0; s < n; s++) {
+        if (!scenes[s]) return fail(TLMPM_E_INVALID, "null scene in batch");
+        if (scenes[s]->in_batch) return fail(TLMPM_E_INVALID, "scene already belongs to a live batch");
+        for (int t = 0; t < s; t++)
+            if (scenes[t] == scenes[s]) return fail(TLMPM_E_INVALID, "scene listed twice in batch");
+    }
+    return TLMPM_OK;
+}
+} // namespace
+
+struct tlmpm_batch {
+    std::vector<tlmpm_scene*> sc;
+    hipStream_t st;
+    TlLaunch L;
+    BatchTools* d_tools;
+    double* d_wacc;
+    BatchTools* h_tools = nullptr; // pinned staging of the per-call tools
+    double* h_wacc = nullptr;
+    hipEvent_t up_done = nullptr;  // the last upload from h_tools finished
+    Timing prof;
+    int cur, rsb;
+    bool pending;
+};
+
+extern "C" tlmpm_status tlmpm_batch_footprint(tlmpm_scene* const* scenes, int32_t n_scenes, size_t* device_bytes)
+{
+    if (tlmpm_status r = check_members(scenes, n_scenes)) return r;
+    if (!device_bytes) return fail(TLMPM_E_INVALID, "null output");
+    BatchPlan P;
+    if (tlmpm_status r = batch_plan(scenes, n_scenes, P)) return r;
+    *device_bytes = P.total;
+    return TLMPM_OK;
+}
+
+extern "C" tlmpm_status tlmpm_batch_create(tlmpm_scene* const* scenes, int32_t n_scenes, void* ws, size_t bytes,
+                                           void* hip_stream, tlmpm_batch** out)
+{
+    if (tlmpm_status r = check_members(scenes, n_scenes)) return r;
+    if (!out) return fail(TLMPM_E_INVALID, "null output");
+    *out = nullptr;
+    BatchPlan P;
+    if (tlmpm_status r = batch_plan(scenes, n_scenes, P)) return r;
+    if (!ws || bytes < P.total) return fail(TLMPM_E_NOMEM, "workspace smaller than tlmpm_batch_footprint()");
+
+    // common slot-table state: that of the scenes with a pending F update (the
+    // first one's); scenes in another state apply their F update alone, and scenes
+    // without a pending update take their tables to the common buffer
+    int cur = scenes[0]->cur, rsb = scenes[0]->cur;
+    bool pending = false;
+    for (int s = 0; s < n_scenes; s++)
+        if (scenes[s]->f_pending) {
+            cur = scenes[s]->cur;
+            rsb = scenes[s]->rsb;
+            pending = true;
+            break;
+        }
+    for (int s = 0; s < n_scenes; s++) {
+        tlmpm_scene* sc = scenes[s];
+        if (sc->f_pending && (sc->cur != cur || sc->rsb != rsb))
+            if (tlmpm_status r = flush_F(sc)) return r;
+        if (!sc->f_pending && sc->cur != cur) {
+            const TlLaunch L1 = single_launch(sc);
+            HIPCHK(tl_launch_slots(&L1, cur, sc->cur, 0));
+            sc->cur = cur;
+        }
+        if (!sc->f_pending) sc->rsb = rsb;
+    }
+    for (int s = 0; s < n_scenes; s++) HIPCHK(hipStreamSynchronize(scenes[s]->st));
+
+    tlmpm_batch* b = new tlmpm_batch();
+    b->sc.assign(scenes, scenes + n_scenes);
+    b->st = (hipStream_t)hip_stream;
+    b->prof.st = b->st;
+    b->cur = cur;
+    b->rsb = rsb;
+    b->pending = pending;
+    char* base = (char*)ws;
+    b->d_tools = (BatchTools*)(base + P.tools);
+    b->d_wacc = (double*)(base + P.wacc);
+    TlLaunch& L = b->L;
+    memset(&L, 0, sizeof(L));
+    L.Ks = (const SceneK*)(base + P.Ks);
+    L.Ds = (const SceneD*)(base + P.Ds);
+    L.st = b->st;
+    std::vector<SceneK> hk(n_scenes);
+    std::vector<SceneD> hd(n_scenes);
+    std::vector<int2> items[TL_ITEM_KINDS];
+    for (int s = 0; s < n_scenes; s++) {
+        const tlmpm_scene* sc = scenes[s];
+        hk[s] = sc->K;
+        hd[s] = sc->D;
+        hd[s].tools = b->d_tools[s].t;
+        hd[s].tinfo = b->d_tools[s].tinfo;
+        hd[s].wacc = b->d_wacc + (size_t)s * TL_MAX_TOOLS * 6;
+        L.any_material |= sc->K.material_contact;
+        int c[TL_ITEM_KINDS];
+        scene_items(sc, c);
+        for (int k = 0; k < TL_ITEM_KINDS; k++)
+            for (int i = 0; i < c[k]; i++) items[k].push_back(make_int2(s, i));
+    }
+    auto bail = [&](hipError_t e, const char* what) {
+        if (b->h_tools) (void)hipHostFree(b->h_tools);
+        if (b->h_wacc) (void)hipHostFree(b->h_wacc);
+        if (b->up_done) (void)hipEventDestroy(b->up_done);
+        delete b;
+        return fail(TLMPM_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    };
+    hipError_t e;
+    if ((e = hipMemcpyAsync(base + P.Ks, hk.data(), n_scenes * sizeof(SceneK), hipMemcpyHostToDevice, b->st)) !=
+        hipSuccess)
+        return bail(e, "upload scene parameters");
+    if ((e = hipMemcpyAsync(base + P.Ds, hd.data(), n_scenes * sizeof(SceneD), hipMemcpyHostToDevice, b->st)) !=
+        hipSuccess)
+        return bail(e, "upload scene pointers");
+    for (int k = 0; k < TL_ITEM_KINDS; k++) {
+        L.items[k] = (const int2*)(base + P.items[k]);
+        L.n_items[k] = P.n_items[k];
+        if (!items[k].empty() &&
+            (e = hipMemcpyAsync(base + P.items[k], items[k].data(), items[k].size() * sizeof(int2),
+                                hipMemcpyHostToDevice, b->st)) != hipSuccess)
+            return bail(e, "upload work items");
+    }
+    if ((e = hipHostMalloc((void**)&b->h_tools, n_scenes * sizeof(BatchTools), hipHostMallocDefault)) != hipSuccess)
+        return bail(e, "pinned staging");
+    if ((e = hipHostMalloc((void**)&b->h_wacc, n_scenes * TL_MAX_TOOLS * 6 * sizeof(double), hipHostMallocDefault)) !=
+        hipSuccess)
+        return bail(e, "pinned staging");
+    if ((e = hipEventCreateWithFlags(&b->up_done, hipEventDisableTiming)) != hipSuccess) return bail(e, "event");
+    if ((e = hipStreamSynchronize(b->st)) != hipSuccess) return bail(e, "create batch");
+    for (tlmpm_scene* sc : b->sc) sc->in_batch = 1;
+    *out = b;
+    return TLMPM_OK;
+}
+
+extern "C" tlmpm_status tlmpm_batch_destroy(tlmpm_batch* b)
+{
+    if (!b) return fail(TLMPM_E_INVALID, "null batch");
+    hipError_t e = hipStreamSynchronize(b->st);
+    for (tlmpm_scene* sc : b->sc) sc->in_batch = 0;
+    (void)hipHostFree(b->h_tools);
+    (void)hipHostFree(b->h_wacc);
+    (void)hipEventDestroy(b->up_done);
+    delete b;
+    if (e != hipSuccess) return fail(TLMPM_E_DEVICE, std::string("destroy batch: ") + hipGetErrorString(e));
+    return TLMPM_OK;
+}
+
+extern "C" tlmpm_status tlmpm_batch_step(tlmpm_batch* b, const tlmpm_tool* tools, const int32_t* n_tools,
+                                         int32_t n_substeps, double* wrench)
+{
+    if (!b || !n_tools || n_substeps < 0) return fail(TLMPM_E_INVALID, "bad arguments");
+    const int n = (int)b->sc.size();
+    for (int s = 0; s < n; s++)
+        if (n_tools[s] < 0 || n_tools[s] > TL_MAX_TOOLS || (n_tools[s] > 0 && !tools))
+            return fail(TLMPM_E_INVALID, "bad tool count (at most 4 tools per scene)");
+    HIPCHK(hipEventSynchronize(b->up_done)); // staging free again
+    CallFlags f;
+    for (int s = 0; s < n; s++) {
+        tlmpm_status r = convert_tools(b->sc[s], n_tools[s] ? tools + (size_t)s * TL_MAX_TOOLS : nullptr, n_tools[s],
+                                       b->h_tools[s].t, b->h_tools[s].tinfo, f);
+        if (r) return fail(r, "scene " + std::to_string(s) + ": " + g_err);
+    }
+    HIPCHK(hipMemcpyAsync(b->d_tools, b->h_tools, n * sizeof(BatchTools), hipMemcpyHostToDevice, b->st));
+    HIPCHK(hipEventRecord(b->up_done, b->st));
+    Exec X;
+    X.L = b->L;
+    X.prof = &b->prof;
+    X.cur = b->cur;
+    X.rsb = b->rsb;
+    X.pending = b->pending;
+    tlmpm_status r = run_substeps(X, n_substeps, f);
+    b->cur = X.cur;
+    b->rsb = X.rsb;
+    b->pending = X.pending;
+    for (tlmpm_scene* sc : b->sc) {
+        sc->cur = X.cur;
+        sc->rsb = X.rsb;
+        if (n_substeps > 0) sc->f_pending = true;
+    }
+    if (r) return r;
+    if (wrench) {
+        const size_t per = TL_MAX_TOOLS * 6;
+        if (f.any_contact_tool) {
+            HIPCHK(hipMemcpyAsync(b->h_wacc, b->d_wacc, n * per * sizeof(double), hipMemcpyDeviceToHost, b->st));
+            HIPCHK(hipStreamSynchronize(b->st));
+        }
+        const double inv = n_substeps > 0 ? 1.0 / n_substeps : 0.0;
+        for (int s = 0; s < n; s++)
+            for (size_t q = 0; q < per; q++)
+                wrench[s * per + q] =
+                    (f.any_contact_tool && (int)q < n_tools[s] * 6) ? b->h_wacc[s * per + q] * inv : 0.0;
+    }
+    return TLMPM_OK;
+}
+
+extern "C" tlmpm_status tlmpm_batch_sync(tlmpm_batch* b)
+{
+    if (!b) return fail(TLMPM_E_INVALID, "null batch");
+    HIPCHK(hipStreamSynchronize(b->st));
+    return TLMPM_OK;
+}
+
+extern "C" tlmpm_status tlmpm_batch_profile_enable(tlmpm_batch* b, int32_t enable)
+{
+    if (!b) return fail(TLMPM_E_INVALID, "null batch");
+    b->prof.on = enable != 0;
+    return TLMPM_OK;
+}
+
+extern "C" tlmpm_status tlmpm_batch_profile_read(tlmpm_batch* b, int32_t n_classes, double* ms, int64_t* launches)
+{
+    if (!b) return fail(TLMPM_E_INVALID, "null batch");
+    return timing_read(b->prof, n_classes, ms, launches);
 }

@@ -110,6 +110,8 @@ struct SceneD {
     int* brig;     // [bricks] the brick was within reach of a rigid body this substep
     int* bmixed;   // [bricks] a cell of the brick holds two side codes
     DevTool* tools;   // [TL_MAX_TOOLS] tools (or label-only blades) of the current call
+    int* tinfo;       // [4] per call: number of tools, any tool with contact, new cut, unused
+    int* ctr;         // [4] persistent: contact-history stamp, F update pending, unused x2
     int* status;
     int* dirty;
     int* bdirty;        // [bricks] side codes of the brick changed in the last label pass
@@ -131,4 +133,19 @@ struct SceneD {
     int* ph_n;          // [2][N] stamp << 8 | count of owned springs
     int* ph_q;          // [2][N][TL_PCAP] partner of each spring
     float* ph_u;        // [2][N][TL_PCAP][3] spring, oriented for the owner
+};
+
+// Launch context: one scene (parameters by value) or a batch of scenes (device
+// arrays of SceneK / SceneD and, per kind of work item, a list of (scene, block)).
+enum { IT_BRICK = 0, IT_NODE, IT_CELL, IT_BUCKET, IT_SCENE, IT_WRENCH, IT_PART, IT_BFLAG, TL_ITEM_KINDS };
+
+struct TlLaunch {
+    const SceneK* S;   // single scene (host copies), or null in batch mode
+    const SceneD* D;
+    const SceneK* Ks;  // batch mode: device arrays
+    const SceneD* Ds;
+    const int2* items[TL_ITEM_KINDS];
+    int n_items[TL_ITEM_KINDS];
+    int any_material;  // some scene has material contact
+    hipStream_t st;
 };

@@ -53,9 +53,11 @@ DEV void slot_cell(const SceneK& S, long long cs, int& x, int& y, int& z)
 
 // per cell: OR of the particles' codes; at creation also the static surface flag.
 // Without `force`, only the cells of bricks whose codes changed are recomputed.
-__global__ void k_cellmask(SceneK S, SceneD D, long long n_slots, int with_static, int force)
+DEV void cellmask_body(const SceneK& S, const SceneD& D, int bi, int with_static, int force)
 {
-    long long cs = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (!S.material_contact) return;
+    const long long n_slots = (long long)S.cbx * S.cby * S.cbz * TL_CELLS;
+    long long cs = (long long)bi * blockDim.x + threadIdx.x;
     if (cs >= n_slots) return;
     if (!force && !D.bdirty[cs / TL_CELLS]) return;
     uint32_t m = 0;
@@ -79,13 +81,14 @@ __global__ void k_cellmask(SceneK S, SceneD D, long long n_slots, int with_stati
 // Candidate bit of every particle and the brick's candidate list (in particle
 // order, stored over the brick's particle range).  Without `force`, only bricks
 // next to a brick whose codes changed are recomputed.
-__global__ __launch_bounds__(256) void k_cand(SceneK S, SceneD D, int force)
+DEV void cand_body(const SceneK& S, const SceneD& D, int bi, int force)
 {
+    if (!S.material_contact) return;
     __shared__ uint32_t s_nm[TL_CELLS];
     __shared__ int s_st[TL_CELLS];
     __shared__ int s_go;
     __shared__ int s_wave[4];
-    const int brick = D.active[blockIdx.x];
+    const int brick = D.active[bi];
     const int bx = brick % S.cbx, by = (brick / S.cbx) % S.cby, bz = brick / (S.cbx * S.cby);
     if (threadIdx.x == 0) {
         int go = force;
@@ -146,8 +149,9 @@ __global__ __launch_bounds__(256) void k_cand(SceneK S, SceneD D, int force)
 }
 
 // bin edge from the largest speed of any brick (conservative reach)
-__global__ void k_hsize(SceneK S, SceneD D)
+DEV void hsize_body(const SceneK& S, const SceneD& D, int bi)
 {
+    if (!S.material_contact) return;
     __shared__ float s[256];
     float m = 0.0f;
     for (int b = threadIdx.x; b < D.n_active; b += blockDim.x) m = fmaxf(m, D.aabb[(long long)D.active[b] * 8 + 6]);
@@ -196,9 +200,19 @@ DEV void make_rec(const SceneK& S, const SceneD& D, int p, const float x[3], flo
 // count; the first TL_BCAP ids are kept, later candidates go to a lock-free
 // overflow list (generation-stamped heads, never cleared).  Pass 2: each kept
 // candidate stores its record at its rank by particle index among the bucket's ids.
-__global__ __launch_bounds__(256) void k_bin_insert(SceneK S, SceneD D, unsigned gen)
+// bucket counts of this substep start at zero
+DEV void bzero_body(const SceneK& S, const SceneD& D, int bi)
 {
-    const int brick = D.active[blockIdx.x];
+    if (!S.material_contact) return;
+    long long i = (long long)bi * blockDim.x + threadIdx.x;
+    if (i <= (long long)D.hmask) D.bcount[i] = 0;
+}
+
+DEV void bin_insert_body(const SceneK& S, const SceneD& D, int bi)
+{
+    if (!S.material_contact) return;
+    const unsigned gen = (unsigned)D.ctr[0];
+    const int brick = D.active[bi];
     const int nc = D.bcand[brick];
     if (!nc) return;
     const float inv_h = 1.0f / D.hbin[0];
@@ -236,9 +250,10 @@ __global__ __launch_bounds__(256) void k_bin_insert(SceneK S, SceneD D, unsigned
     }
 }
 
-__global__ __launch_bounds__(256) void k_bin_rank(SceneK S, SceneD D)
+DEV void bin_rank_body(const SceneK& S, const SceneD& D, int bi)
 {
-    const int brick = D.active[blockIdx.x];
+    if (!S.material_contact) return;
+    const int brick = D.active[bi];
     const int nc = D.bcand[brick];
     if (!nc) return;
     const float inv_h = 1.0f / D.hbin[0];
@@ -350,147 +365,185 @@ DEV void ref_cell(const SceneK& S, const SceneD& D, long long p, int c[3])
     slot_cell(S, D.pcell[p], c[0], c[1], c[2]);
 }
 
-__global__ __launch_bounds__(128) void k_pairs(SceneK S, SceneD D, unsigned gen, int hold, int hnew, int stamp)
+// Pair search and impulses.  32 lanes per candidate: lane d < 27 scans neighbour
+// bin d (records in particle-index order, then the bucket's overflow list) and sums
+// its contacts; the 27 lane sums are added by a fixed shuffle tree.  The owner of a
+// pair (lower sorted index) appends the new spring to its list; the list is only
+// searched by partner, so its order does not matter.
+DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
 {
-    const int brick = D.active[blockIdx.x];
+    if (!S.material_contact) return;
+    // history stamp of this substep; its parity selects the spring buffer written
+    const int stamp = D.ctr[0];
+    const unsigned gen = (unsigned)stamp;
+    const int hnew = stamp & 1, hold = hnew ^ 1;
+    __shared__ int s_nown[8];
+    const int brick = D.active[bi];
     const int ncand = D.bcand[brick];
     if (!ncand) return;
     const float inv_h = 1.0f / D.hbin[0];
     const long long N = S.N;
     const int beg = D.cell_start[(long long)brick * TL_CELLS];
-    for (int ci = threadIdx.x; ci < ncand; ci += blockDim.x) {
-        const int p = D.cand_idx[beg + ci];
-        uint32_t code = D.code[p];
-        const uint32_t kp = ckey(S, code);
-        PState sp = load_pstate(S, D, p);
-        int cp[3];
-        ref_cell(S, D, p, cp);
-        int b[3];
-        bin_of(sp.x, inv_h, b);
-        // contacts are visited in a fixed order (bins, then records by particle
-        // index; overflow lists last), so the impulse sum is reproducible
+    const int sub = threadIdx.x >> 5; // candidate slot of this lane group (8 per block)
+    const int d = threadIdx.x & 31;  // neighbour bin handled by this lane
+    for (int c0 = 0; c0 < ncand; c0 += 8) {
+        const int ci = c0 + sub;
+        const bool has = ci < ncand;
+        if (d == 0) s_nown[sub] = 0;
+        __syncthreads();
         float Jt[3] = {0.0f, 0.0f, 0.0f};
-        int nown = 0;
-        int* ql_new = D.ph_q + ((long long)hnew * N + p) * TL_PCAP;
-        float* ul_new = D.ph_u + ((long long)hnew * N + p) * TL_PCAP * 3;
-        auto visit = [&](const float4 rec[3], const int bb[3]) {
-            const int q = __float_as_int(rec[0].x);
-            if (q == p) return;
-            uint32_t kq = ckey(S, __float_as_uint(rec[0].y));
-            int cq[3];
-            slot_cell(S, __float_as_int(rec[0].z), cq[0], cq[1], cq[2]);
-            bool near = abs(cp[0] - cq[0]) <= 1 && abs(cp[1] - cq[1]) <= 1 && abs(cp[2] - cq[2]) <= 1;
-            if (near && !cconflict(kp, kq)) return; // reading R17 exclusion
-            PState sq = pstate_of(rec);
-            int bq[3];
-            bin_of(sq.x, inv_h, bq);
-            if (bq[0] != bb[0] || bq[1] != bb[1] || bq[2] != bb[2]) return; // hash collision
-            const bool own = p < q;
-            const int o = own ? p : q, r = own ? q : p;
-            // owner's old spring for this partner
-            float u[3] = {0.0f, 0.0f, 0.0f};
-            int hdr = D.ph_n[(long long)hold * N + o];
-            if ((hdr >> 8) == stamp - 1) {
-                int cnt = hdr & 0xFF;
-                const int* ql = D.ph_q + ((long long)hold * N + o) * TL_PCAP;
-                for (int k = 0; k < cnt; k++)
-                    if (ql[k] == r) {
-                        const float* ul = D.ph_u + (((long long)hold * N + o) * TL_PCAP + k) * 3;
-                        u[0] = ul[0];
-                        u[1] = ul[1];
-                        u[2] = ul[2];
-                        break;
-                    }
-            }
-            float J[3];
-            bool hit = own ? pair_impulse(S, sp, sq, u, J) : pair_impulse(S, sq, sp, u, J);
-            if (!hit) return;
-            const float sg = own ? 1.0f : -1.0f;
-            Jt[0] += sg * J[0];
-            Jt[1] += sg * J[1];
-            Jt[2] += sg * J[2];
-            if (own) {
-                if (nown < TL_PCAP) {
-                    ql_new[nown] = q;
-                    ul_new[nown * 3 + 0] = u[0];
-                    ul_new[nown * 3 + 1] = u[1];
-                    ul_new[nown * 3 + 2] = u[2];
-                    nown++;
-                } else {
-                    atomicOr(D.status, TL_ST_CONTACT);
+        int p = -1;
+        if (has) p = D.cand_idx[beg + ci];
+        if (has && d < 27) {
+            const uint32_t kp = ckey(S, D.code[p]);
+            PState sp = load_pstate(S, D, p);
+            int cp[3];
+            ref_cell(S, D, p, cp);
+            int b[3];
+            bin_of(sp.x, inv_h, b);
+            int* ql_new = D.ph_q + ((long long)hnew * N + p) * TL_PCAP;
+            float* ul_new = D.ph_u + ((long long)hnew * N + p) * TL_PCAP * 3;
+            const int bb[3] = {b[0] + d % 3 - 1, b[1] + (d / 3) % 3 - 1, b[2] + d / 9 - 1};
+            auto visit = [&](const float4 rec[3]) {
+                const int q = __float_as_int(rec[0].x);
+                if (q == p) return;
+                uint32_t kq = ckey(S, __float_as_uint(rec[0].y));
+                int cq[3];
+                slot_cell(S, __float_as_int(rec[0].z), cq[0], cq[1], cq[2]);
+                bool near = abs(cp[0] - cq[0]) <= 1 && abs(cp[1] - cq[1]) <= 1 && abs(cp[2] - cq[2]) <= 1;
+                if (near && !cconflict(kp, kq)) return; // reading R17 exclusion
+                PState sq = pstate_of(rec);
+                int bq[3];
+                bin_of(sq.x, inv_h, bq);
+                if (bq[0] != bb[0] || bq[1] != bb[1] || bq[2] != bb[2]) return; // hash collision
+                const bool own = p < q;
+                const int o = own ? p : q, r = own ? q : p;
+                // owner's old spring for this partner
+                float u[3] = {0.0f, 0.0f, 0.0f};
+                int hdr = D.ph_n[(long long)hold * N + o];
+                if ((hdr >> 8) == stamp - 1) {
+                    int cnt = hdr & 0xFF;
+                    const int* ql = D.ph_q + ((long long)hold * N + o) * TL_PCAP;
+                    for (int k = 0; k < cnt; k++)
+                        if (ql[k] == r) {
+                            const float* ul = D.ph_u + (((long long)hold * N + o) * TL_PCAP + k) * 3;
+                            u[0] = ul[0];
+                            u[1] = ul[1];
+                            u[2] = ul[2];
+                            break;
+                        }
                 }
+                float J[3];
+                bool hit = own ? pair_impulse(S, sp, sq, u, J) : pair_impulse(S, sq, sp, u, J);
+                if (!hit) return;
+                const float sg = own ? 1.0f : -1.0f;
+                Jt[0] += sg * J[0];
+                Jt[1] += sg * J[1];
+                Jt[2] += sg * J[2];
+                if (own) {
+                    int k = atomicAdd(&s_nown[sub], 1);
+                    if (k < TL_PCAP) {
+                        ql_new[k] = q;
+                        ul_new[k * 3 + 0] = u[0];
+                        ul_new[k * 3 + 1] = u[1];
+                        ul_new[k * 3 + 2] = u[2];
+                    } else {
+                        atomicOr(D.status, TL_ST_CONTACT);
+                    }
+                }
+            };
+            uint32_t h = bin_hash(bb[0], bb[1], bb[2], D.hmask);
+            const int cnt = D.bcount[h];
+            const int inl = cnt < TL_BCAP ? cnt : TL_BCAP;
+            for (int k = 0; k < inl; k++) {
+                const float4* src = D.brec + ((long long)h * TL_BCAP + k) * 3;
+                float4 rec[3] = {src[0], src[1], src[2]};
+                visit(rec);
             }
-        };
-        for (int dz = -1; dz <= 1; dz++)
-            for (int dy = -1; dy <= 1; dy++)
-                for (int dx = -1; dx <= 1; dx++) {
-                    int bb[3] = {b[0] + dx, b[1] + dy, b[2] + dz};
-                    uint32_t h = bin_hash(bb[0], bb[1], bb[2], D.hmask);
-                    const int cnt = D.bcount[h];
-                    const int inl = cnt < TL_BCAP ? cnt : TL_BCAP;
-                    for (int k = 0; k < inl; k++) {
-                        const float4* src = D.brec + ((long long)h * TL_BCAP + k) * 3;
+            if (cnt > TL_BCAP) {
+                unsigned long long e = D.htab[h];
+                if ((unsigned)(e >> 32) == gen)
+                    for (int q = (int)(e & 0xFFFFFFFFull); q >= 0; q = D.hnext[q]) {
+                        const float4* src = D.orec + (long long)q * 3;
                         float4 rec[3] = {src[0], src[1], src[2]};
-                        visit(rec, bb);
+                        visit(rec);
                     }
-                    if (cnt > TL_BCAP) {
-                        unsigned long long e = D.htab[h];
-                        if ((unsigned)(e >> 32) == gen)
-                            for (int q = (int)(e & 0xFFFFFFFFull); q >= 0; q = D.hnext[q]) {
-                                const float4* src = D.orec + (long long)q * 3;
-                                float4 rec[3] = {src[0], src[1], src[2]};
-                                visit(rec, bb);
-                            }
-                    }
-                }
-        D.ph_n[(long long)hnew * N + p] = (stamp << 8) | nown;
-        D.Jmat[p] = Jt[0];
-        D.Jmat[N + p] = Jt[1];
-        D.Jmat[2 * N + p] = Jt[2];
+            }
+        }
+        // fixed-order sum over the 32 lanes of the group
+        for (int a = 0; a < 3; a++)
+            for (int o = 16; o >= 1; o >>= 1) Jt[a] += __shfl_xor(Jt[a], o, 64);
+        __syncthreads();
+        if (has && d == 0) {
+            int nown = s_nown[sub];
+            D.ph_n[(long long)hnew * N + p] = (stamp << 8) | (nown < TL_PCAP ? nown : TL_PCAP);
+            D.Jmat[p] = Jt[0];
+            D.Jmat[N + p] = Jt[1];
+            D.Jmat[2 * N + p] = Jt[2];
+        }
     }
 }
 
-__global__ void k_zero_i32(int* p, long long n)
+#define TL_WRAP(NAME, PARAMS, ARGS)                                                                           \
+    __global__ __launch_bounds__(256) void k_##NAME(SceneK S, SceneD D PARAMS)                              \
+    {                                                                                                       \
+        NAME##_body(S, D, blockIdx.x ARGS);                                                                 \
+    }                                                                                                       \
+    __global__ __launch_bounds__(256) void k_##NAME##_b(const SceneK* __restrict__ Ks,                       \
+                                                        const SceneD* __restrict__ Ds,                       \
+                                                        const int2* __restrict__ it PARAMS)                  \
+    {                                                                                                       \
+        const int2 t = it[blockIdx.x];                                                                      \
+        NAME##_body(Ks[t.x], Ds[t.x], t.y ARGS);                                                            \
+    }
+#define TL_COMMA ,
+TL_WRAP(cellmask, TL_COMMA int with_static TL_COMMA int force, TL_COMMA with_static TL_COMMA force)
+TL_WRAP(cand, TL_COMMA int force, TL_COMMA force)
+TL_WRAP(hsize, , )
+TL_WRAP(bzero, , )
+TL_WRAP(bin_insert, , )
+TL_WRAP(bin_rank, , )
+TL_WRAP(pairs, , )
+
+template <class KP, class KB, class... Args>
+static hipError_t tl_run(const TlLaunch& L, int kind, int plain_blocks, KP kp, KB kb, Args... args)
 {
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0;
+    if (L.S) {
+        if (plain_blocks <= 0) return hipSuccess;
+        hipLaunchKernelGGL(kp, dim3(plain_blocks), dim3(256), 0, L.st, *L.S, *L.D, args...);
+    } else {
+        if (L.n_items[kind] <= 0) return hipSuccess;
+        hipLaunchKernelGGL(kb, dim3(L.n_items[kind]), dim3(256), 0, L.st, L.Ks, L.Ds, L.items[kind], args...);
+    }
+    return hipGetLastError();
 }
 
 extern "C" {
-hipError_t tl_launch_cellmask(const SceneK* S, const SceneD* D, long long n_slots, int with_static, int force,
-                              hipStream_t st)
+hipError_t tl_launch_cellmask(const TlLaunch* L, int with_static, int force)
 {
-    if (n_slots <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_cellmask, dim3((unsigned)((n_slots + 255) / 256)), dim3(256), 0, st, *S, *D, n_slots,
-                       with_static, force);
-    return hipGetLastError();
+    int nb = 0;
+    if (L->S) nb = (int)(((long long)L->S->cbx * L->S->cby * L->S->cbz * TL_CELLS + 255) / 256);
+    return tl_run(*L, IT_CELL, nb, k_cellmask, k_cellmask_b, with_static, force);
 }
 
-hipError_t tl_launch_cand(const SceneK* S, const SceneD* D, int force, hipStream_t st)
+hipError_t tl_launch_cand(const TlLaunch* L, int force)
 {
-    if (D->n_active == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_cand, dim3(D->n_active), dim3(256), 0, st, *S, *D, force);
-    return hipGetLastError();
+    return tl_run(*L, IT_BRICK, L->S ? L->D->n_active : 0, k_cand, k_cand_b, force);
 }
 
-hipError_t tl_launch_contact(const SceneK* S, const SceneD* D, unsigned gen, int hold, int hnew, int stamp,
-                             hipStream_t st)
+// one substep of pair search and impulses: bin size, bucket reset, binning, pairs
+hipError_t tl_launch_contact(const TlLaunch* L)
 {
-    if (D->n_active == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_hsize, dim3(1), dim3(256), 0, st, *S, *D);
-    hipError_t e = hipGetLastError();
+    const int nbrick = L->S ? L->D->n_active : 0;
+    if (L->S && nbrick == 0) return hipSuccess;
+    hipError_t e = tl_run(*L, IT_SCENE, 1, k_hsize, k_hsize_b);
     if (e != hipSuccess) return e;
-    long long nb = (long long)D->hmask + 1;
-    hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st, D->bcount, nb);
-    e = hipGetLastError();
+    e = tl_run(*L, IT_BUCKET, L->S ? (int)(((long long)L->D->hmask + 256) / 256) : 0, k_bzero, k_bzero_b);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_bin_insert, dim3(D->n_active), dim3(256), 0, st, *S, *D, gen);
-    e = hipGetLastError();
+    e = tl_run(*L, IT_BRICK, nbrick, k_bin_insert, k_bin_insert_b);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_bin_rank, dim3(D->n_active), dim3(256), 0, st, *S, *D);
-    e = hipGetLastError();
+    e = tl_run(*L, IT_BRICK, nbrick, k_bin_rank, k_bin_rank_b);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_pairs, dim3(D->n_active), dim3(128), 0, st, *S, *D, gen, hold, hnew, stamp);
-    return hipGetLastError();
+    return tl_run(*L, IT_BRICK, nbrick, k_pairs, k_pairs_b);
 }
 }

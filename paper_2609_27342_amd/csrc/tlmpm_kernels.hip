@@ -591,12 +591,10 @@ DEV bool brick_near_tool(const SceneK& S, const float* bb, const DevTool* T, flo
 // tool/floor contact, and the label-masked P2G of (m, p, dp) (Eq. 2 with external
 // and contact impulses, Eqs. 13, 16) into this brick's partials (tables cur).
 struct KA_Args {
-    int f_pending;
-    int do_p2g;
-    int tabs_differ;
-    int cur;      // current slot table buffer
-    int rsb;      // slot table buffer of the pending re-scatter
-    int rigid;    // k_rigid ran this substep
+    int do_p2g;      // 0: only the pending F update
+    int tabs_differ; // cur != rsb (applies to scenes with a pending F update)
+    int cur;         // current slot table buffer
+    int rsb;         // slot table buffer of the pending re-scatter
 };
 
 // --------------------------------------------------------------------- rigid contact
@@ -604,27 +602,28 @@ struct KA_Args {
 // body this substep (Eqs. 14-16, 5): impulses to Jrig, cutting progress D, contact
 // springs, and per-brick wrench sums (wave tree, then waves in order).
 struct KR_Args {
-    int n_tools;
-    int any_tool_contact;
-    int stamp;    // contact-history stamp of this substep
-    double jdt;   // time since the stored tool pose (TL_TOOL_ADVANCE)
+    int j; // substep index within the call (TL_TOOL_ADVANCE poses)
 };
 
-__global__ __launch_bounds__(256) void k_rigid(SceneK S, SceneD D, KR_Args A)
+DEV void rigid_body(const SceneK& S, const SceneD& D, int bi, KR_Args A)
 {
+    if (!S.floor_on && !D.tinfo[1]) return; // no rigid body touches this scene
+    const int n_tools = D.tinfo[0];
+    const int stamp = D.ctr[0];
+    const double jdt = (double)A.j * S.dt_d;
     __shared__ int s_near[TL_MAX_TOOLS + 1];
     __shared__ int s_any;
     __shared__ float s_wr[4][TL_MAX_TOOLS * 6];
-    const int brick = D.active[blockIdx.x];
+    const int brick = D.active[bi];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const long long N = S.N;
     if (tid <= TL_MAX_TOOLS) {
         const float* bb = D.aabb + (long long)brick * 8;
         int nr = 0;
         if (tid == 0)
-            nr = S.floor_on ? brick_near_tool(S, bb, nullptr, S.Rmax, A.jdt) : 0;
-        else if (tid - 1 < A.n_tools)
-            nr = (D.tools[tid - 1].flags & TL_TOOL_CONTACT) ? brick_near_tool(S, bb, &D.tools[tid - 1], S.Rmax, A.jdt)
+            nr = S.floor_on ? brick_near_tool(S, bb, nullptr, S.Rmax, jdt) : 0;
+        else if (tid - 1 < n_tools)
+            nr = (D.tools[tid - 1].flags & TL_TOOL_CONTACT) ? brick_near_tool(S, bb, &D.tools[tid - 1], S.Rmax, jdt)
                                                              : 0;
         s_near[tid] = nr;
     }
@@ -632,12 +631,12 @@ __global__ __launch_bounds__(256) void k_rigid(SceneK S, SceneD D, KR_Args A)
     __syncthreads();
     if (tid == 0) {
         int any = 0;
-        for (int b = 0; b <= A.n_tools; b++) any |= s_near[b];
+        for (int b = 0; b <= n_tools; b++) any |= s_near[b];
         s_any = any;
         D.brig[brick] = any;
     }
     __syncthreads();
-    const bool want_wrench = A.any_tool_contact != 0;
+    const bool want_wrench = D.tinfo[1] != 0;
     if (s_any) {
         const int beg = D.cell_start[(long long)brick * TL_CELLS], end = D.cell_start[(long long)(brick + 1) * TL_CELLS];
         for (int p0 = beg; p0 < end; p0 += blockDim.x) {
@@ -654,13 +653,13 @@ __global__ __launch_bounds__(256) void k_rigid(SceneK S, SceneD D, KR_Args A)
                 V0 = S.v_uniform ? S.V0 : D.V0[p];
                 R = 0.5f * S.s_R * cbrtf(V0);
                 Dp = D.D[p];
-                if (s_near[0]) rigid_one(S, D, nullptr, 0, p, x, v, m, V0, R, A.stamp, A.jdt, Jc, Dp, Dp, nullptr);
+                if (s_near[0]) rigid_one(S, D, nullptr, 0, p, x, v, m, V0, R, stamp, jdt, Jc, Dp, Dp, nullptr);
             }
             const float Ds = valid ? D.D[p] : 0.0f;
-            for (int b = 0; b < A.n_tools; b++) {
+            for (int b = 0; b < n_tools; b++) {
                 if (!s_near[b + 1]) continue;
                 float wr[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-                if (valid) rigid_one(S, D, &D.tools[b], 1 + b, p, x, v, m, V0, R, A.stamp, A.jdt, Jc, Dp, Ds, wr);
+                if (valid) rigid_one(S, D, &D.tools[b], 1 + b, p, x, v, m, V0, R, stamp, jdt, Jc, Dp, Ds, wr);
                 bool nz = wr[0] != 0.0f || wr[1] != 0.0f || wr[2] != 0.0f;
                 if (want_wrench && __any(nz)) {
                     for (int q = 0; q < 6; q++) {
@@ -680,16 +679,16 @@ __global__ __launch_bounds__(256) void k_rigid(SceneK S, SceneD D, KR_Args A)
     }
     if (want_wrench) {
         __syncthreads();
-        if (tid < A.n_tools * 6) {
+        if (tid < n_tools * 6) {
             float acc = 0.0f;
             for (int w = 0; w < 4; w++) acc += s_wr[w][tid];
-            D.wpart[(long long)blockIdx.x * (TL_MAX_TOOLS * 6) + tid] = acc;
+            D.wpart[(long long)bi * (TL_MAX_TOOLS * 6) + tid] = acc;
         }
     }
 }
 
 template <bool MIXED>
-__global__ __launch_bounds__(TL_WG) void k_p2g(SceneK S, SceneD D, KA_Args A)
+DEV void p2g_body(const SceneK& S, const SceneD& D, int bi, KA_Args A)
 {
     __shared__ BoxTab Tc;
     __shared__ BoxTab Tr;
@@ -699,14 +698,15 @@ __global__ __launch_bounds__(TL_WG) void k_p2g(SceneK S, SceneD D, KA_Args A)
     __shared__ int s_total_r, s_total_c;
     __shared__ int s_rounds;
 
-    const int brick = D.active[blockIdx.x];
+    const int brick = D.active[bi];
     if ((D.bmixed[brick] != 0) != MIXED) return; // the other variant handles this brick
     const int bx = brick % S.cbx, by = (brick / S.cbx) % S.cby, bz = brick / (S.cbx * S.cby);
     const int tid = threadIdx.x;
     const long long N = S.N;
     const float dt = S.dt;
-    const bool use_r = A.f_pending != 0;                               // finalize v~ (tables rs)
-    const bool use_c = A.do_p2g && (A.tabs_differ || !A.f_pending); // separate P2G tables
+    const bool fp = D.ctr[1] != 0;                              // F update of the last substep pending
+    const bool use_r = fp;                                            // finalize v~ (tables rs)
+    const bool use_c = A.do_p2g && ((A.tabs_differ && fp) || !fp); // separate P2G tables
 
     // ---- phase 1: cell index, box counts, brick-vs-tool tests, round-0 particle loads
     Lane L = lane_of(D, brick);
@@ -714,7 +714,7 @@ __global__ __launch_bounds__(TL_WG) void k_p2g(SceneK S, SceneD D, KA_Args A)
     if (use_c) box_counts(S, D.cnt[A.cur], bx, by, bz, Tc);
     if (tid == 0) s_rounds = 0;
     // floor/tool impulses were computed for this brick by k_rigid
-    const bool rig = A.do_p2g && A.rigid && D.brig[brick] != 0;
+    const bool rig = A.do_p2g && (S.floor_on || D.tinfo[1]) && D.brig[brick] != 0;
     const int gxc = bx * TL_B + L.cxl, gyc = by * TL_B + L.cyl, gzc = bz * TL_B + L.czl;
     bool valid = L.j < L.count;
     long long p = L.beg + L.j;
@@ -887,7 +887,7 @@ __global__ __launch_bounds__(TL_WG) void k_p2g(SceneK S, SceneD D, KA_Args A)
 // PIC/FLIP G2P of v and x (Eq. 17), then the MUSL re-scatter of m_p v_p^{n+1} into
 // this brick's partials.  Also records the brick's current AABB and speed bound.
 template <bool MIXED>
-__global__ __launch_bounds__(TL_WG) void k_g2p(SceneK S, SceneD D, int cur)
+DEV void g2p_body(const SceneK& S, const SceneD& D, int bi, int cur)
 {
     __shared__ BoxTab T;
     __shared__ float s_sum[TL_BOX_SLOTS * 7];
@@ -897,7 +897,13 @@ __global__ __launch_bounds__(TL_WG) void k_g2p(SceneK S, SceneD D, int cur)
     __shared__ int s_rounds;
     __shared__ float s_bb[8][7];
 
-    const int brick = D.active[blockIdx.x];
+    const int brick = D.active[bi];
+    if (!MIXED && bi == 0 && threadIdx.x == 0) {
+        // end of the substep for this scene: next history stamp, F update pending
+        // (no other kernel of the substep reads these after this point)
+        D.ctr[0] += 1;
+        D.ctr[1] = 1;
+    }
     if ((D.bmixed[brick] != 0) != MIXED) return; // the other variant handles this brick
     const int bx = brick % S.cbx, by = (brick / S.cbx) % S.cby, bz = brick / (S.cbx * S.cby);
     const int tid = threadIdx.x;
@@ -1080,12 +1086,15 @@ DEV DevBlade blade_at(const DevTool& T, double jdt)
     return B;
 }
 
-__global__ __launch_bounds__(256) void k_labels(SceneK S, SceneD D, int n_tools, double jdt, int mark_prev)
+DEV void labels_body(const SceneK& S, const SceneD& D, int bi, int j)
 {
+    const bool mark_prev = D.ctr[1] != 0; // keep the codes the pending F update needs
+    const int n_tools = D.tinfo[0];
+    const double jdt = (double)j * S.dt_d;
     __shared__ int s_go;
     __shared__ DevBlade s_bl[TL_MAX_TOOLS];
     __shared__ int s_nb;
-    const int brick = D.active[blockIdx.x];
+    const int brick = D.active[bi];
     const float* bb = D.aabb + (long long)brick * 8;
     if (threadIdx.x == 0) {
         int go = 0, nb = 0;
@@ -1138,9 +1147,9 @@ __global__ __launch_bounds__(256) void k_labels(SceneK S, SceneD D, int n_tools,
 // For every node: the distinct codes of the particles in its 8 incident cells, in
 // ascending order (compact slots, Sec. III-G).  Skipped (count copied) when the
 // labels did not change since the source table was built.
-__global__ __launch_bounds__(256) void k_slots(SceneK S, SceneD D, int dst, int src, int force)
+DEV void slots_body(const SceneK& S, const SceneD& D, int bi, int dst, int src, int force)
 {
-    const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long id = (long long)bi * blockDim.x + threadIdx.x;
     if (id >= S.NN) return;
     long long nb = id >> 6;
     int lid = (int)(id & 63);
@@ -1201,9 +1210,9 @@ __global__ __launch_bounds__(256) void k_slots(SceneK S, SceneD D, int dst, int 
 // A brick is "mixed" when one of its cells holds particles of two side codes; its
 // P2G/G2P run in the kernel variant that reduces one code at a time.  Recomputed
 // for bricks whose codes changed (or all, when forced).
-__global__ __launch_bounds__(256) void k_mixed(SceneK S, SceneD D, int force)
+DEV void mixed_body(const SceneK& S, const SceneD& D, int bi, int force)
 {
-    const int brick = D.active[blockIdx.x];
+    const int brick = D.active[bi];
     if (!force && !D.bdirty[brick]) return;
     bool mixed = false;
     for (int c = threadIdx.x; c < TL_CELLS; c += blockDim.x) {
@@ -1218,6 +1227,28 @@ __global__ __launch_bounds__(256) void k_mixed(SceneK S, SceneD D, int force)
 }
 
 // --------------------------------------------------------------- small kernels
+// D := 0 for a new cut (Sec. III-A), over particle block bi
+DEV void resetD_body(const SceneK& S, const SceneD& D, int bi)
+{
+    if (!D.tinfo[2]) return;
+    long long i = (long long)bi * blockDim.x + threadIdx.x;
+    if (i < S.N) D.D[i] = 0.0f;
+}
+
+// clears the label-change flags after the slot tables and candidates caught up
+DEV void clear_flags_body(const SceneK& S, const SceneD& D, int bi)
+{
+    long long i = (long long)bi * blockDim.x + threadIdx.x;
+    if (i < (long long)S.cbx * S.cby * S.cbz) D.bdirty[i] = 0;
+    if (bi == 0 && threadIdx.x == 0) *D.dirty = 0;
+}
+
+// clears the interval wrench accumulator
+DEV void clear_wacc_body(const SceneK& S, const SceneD& D, int bi)
+{
+    if (threadIdx.x < TL_MAX_TOOLS * 6) D.wacc[threadIdx.x] = 0.0;
+}
+
 __global__ void k_fill_f32(float* p, long long n, float v)
 {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1231,10 +1262,10 @@ __global__ void k_fill_i32(int* p, long long n, int v)
 }
 
 // brick AABB from the current state (scene creation, after a state write)
-__global__ __launch_bounds__(256) void k_aabb(SceneK S, SceneD D)
+DEV void aabb_body(const SceneK& S, const SceneD& D, int bi)
 {
     __shared__ float s_bb[4][7];
-    const int brick = D.active[blockIdx.x];
+    const int brick = D.active[bi];
     const long long N = S.N;
     const int beg = D.cell_start[(long long)brick * TL_CELLS], end = D.cell_start[(long long)(brick + 1) * TL_CELLS];
     float bb[7] = {1e30f, 1e30f, 1e30f, -1e30f, -1e30f, -1e30f, 0.0f};
@@ -1268,10 +1299,11 @@ __global__ __launch_bounds__(256) void k_aabb(SceneK S, SceneD D)
 
 // Sum of the per-brick wrench partials in fixed order (one workgroup per force or
 // torque component), added to the interval accumulator in FP64.
-__global__ __launch_bounds__(256) void k_wrench(SceneD D)
+DEV void wrench_body(const SceneK& S, const SceneD& D, int bi)
 {
     __shared__ double s[256];
-    const int q = blockIdx.x;
+    const int q = bi;
+    if (!D.tinfo[1] || q >= D.tinfo[0] * 6) return;
     double acc = 0.0;
     for (int b = threadIdx.x; b < D.n_active; b += blockDim.x)
         acc += (double)D.wpart[(long long)b * (TL_MAX_TOOLS * 6) + q];
@@ -1284,61 +1316,146 @@ __global__ __launch_bounds__(256) void k_wrench(SceneD D)
     if (threadIdx.x == 0) D.wacc[q] += s[0];
 }
 
-// ------------------------------------------------------------------- launchers
-extern "C" {
-hipError_t tl_launch_rigid(const SceneK* S, const SceneD* D, int n_tools, int any_tool_contact, double jdt, int stamp,
-                           hipStream_t st)
+// ------------------------------------------------------------------- kernels
+// Every body runs either for one scene (parameters by value, block = item) or for
+// a batch (block -> (scene, item) from a list).
+#define TL_WRAP(NAME, BOUNDS, PARAMS, ARGS)                                                                   \
+    __global__ __launch_bounds__(BOUNDS) void k_##NAME(SceneK S, SceneD D PARAMS)                           \
+    {                                                                                                       \
+        NAME##_body(S, D, blockIdx.x ARGS);                                                                 \
+    }                                                                                                       \
+    __global__ __launch_bounds__(BOUNDS) void k_##NAME##_b(const SceneK* __restrict__ Ks,                    \
+                                                           const SceneD* __restrict__ Ds,                    \
+                                                           const int2* __restrict__ it PARAMS)               \
+    {                                                                                                       \
+        const int2 t = it[blockIdx.x];                                                                      \
+        NAME##_body(Ks[t.x], Ds[t.x], t.y ARGS);                                                            \
+    }
+
+#define TL_COMMA ,
+TL_WRAP(rigid, 256, TL_COMMA KR_Args A, TL_COMMA A)
+TL_WRAP(labels, 256, TL_COMMA int j, TL_COMMA j)
+TL_WRAP(slots, 256, TL_COMMA int dst TL_COMMA int src TL_COMMA int force, TL_COMMA dst TL_COMMA src TL_COMMA force)
+TL_WRAP(mixed, 256, TL_COMMA int force, TL_COMMA force)
+TL_WRAP(aabb, 256, , )
+TL_WRAP(wrench, 256, , )
+TL_WRAP(resetD, 256, , )
+TL_WRAP(clear_flags, 256, , )
+TL_WRAP(clear_wacc, 64, , )
+
+template <bool MIXED>
+__global__ __launch_bounds__(TL_WG) void k_p2g(SceneK S, SceneD D, KA_Args A)
 {
-    if (D->n_active == 0) return hipSuccess;
-    KR_Args A;
-    A.n_tools = n_tools;
-    A.any_tool_contact = any_tool_contact;
-    A.stamp = stamp;
-    A.jdt = jdt;
-    hipLaunchKernelGGL(k_rigid, dim3(D->n_active), dim3(256), 0, st, *S, *D, A);
+    p2g_body<MIXED>(S, D, blockIdx.x, A);
+}
+template <bool MIXED>
+__global__ __launch_bounds__(TL_WG) void k_p2g_b(const SceneK* __restrict__ Ks, const SceneD* __restrict__ Ds,
+                                                 const int2* __restrict__ it, KA_Args A)
+{
+    const int2 t = it[blockIdx.x];
+    p2g_body<MIXED>(Ks[t.x], Ds[t.x], t.y, A);
+}
+template <bool MIXED>
+__global__ __launch_bounds__(TL_WG) void k_g2p(SceneK S, SceneD D, int cur)
+{
+    g2p_body<MIXED>(S, D, blockIdx.x, cur);
+}
+template <bool MIXED>
+__global__ __launch_bounds__(TL_WG) void k_g2p_b(const SceneK* __restrict__ Ks, const SceneD* __restrict__ Ds,
+                                                 const int2* __restrict__ it, int cur)
+{
+    const int2 t = it[blockIdx.x];
+    g2p_body<MIXED>(Ks[t.x], Ds[t.x], t.y, cur);
+}
+
+// ------------------------------------------------------------------- launchers
+template <class KP, class KB, class... Args>
+static hipError_t tl_run(const TlLaunch& L, int kind, int plain_blocks, int threads, KP kp, KB kb, Args... args)
+{
+    if (L.S) {
+        if (plain_blocks <= 0) return hipSuccess;
+        hipLaunchKernelGGL(kp, dim3(plain_blocks), dim3(threads), 0, L.st, *L.S, *L.D, args...);
+    } else {
+        if (L.n_items[kind] <= 0) return hipSuccess;
+        hipLaunchKernelGGL(kb, dim3(L.n_items[kind]), dim3(threads), 0, L.st, L.Ks, L.Ds, L.items[kind], args...);
+    }
     return hipGetLastError();
 }
 
-hipError_t tl_launch_p2g(const SceneK* S, const SceneD* D, int f_pending, int do_p2g, int tabs_differ, int cur, int rsb,
-                         int rigid, hipStream_t st)
+static int blocks_of(long long n, int per) { return (int)((n + per - 1) / per); }
+static int plain_bricks(const TlLaunch& L) { return L.S ? L.D->n_active : 0; }
+static int plain_nodes(const TlLaunch& L) { return L.S ? blocks_of(L.S->NN, 256) : 0; }
+static int plain_parts(const TlLaunch& L) { return L.S ? blocks_of(L.S->N, 256) : 0; }
+static int plain_bflags(const TlLaunch& L)
+{
+    return L.S ? blocks_of((long long)L.S->cbx * L.S->cby * L.S->cbz, 256) : 0;
+}
+
+extern "C" {
+hipError_t tl_launch_rigid(const TlLaunch* L, int j)
+{
+    KR_Args A;
+    A.j = j;
+    return tl_run(*L, IT_BRICK, plain_bricks(*L), 256, k_rigid, k_rigid_b, A);
+}
+
+hipError_t tl_launch_p2g(const TlLaunch* L, int do_p2g, int tabs_differ, int cur, int rsb)
 {
     KA_Args A;
-    A.f_pending = f_pending;
     A.do_p2g = do_p2g;
     A.tabs_differ = tabs_differ;
     A.cur = cur;
     A.rsb = rsb;
-    A.rigid = rigid;
-    if (D->n_active == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_p2g<false>, dim3(D->n_active), dim3(TL_WG), 0, st, *S, *D, A);
-    hipError_t e = hipGetLastError();
+    hipError_t e = tl_run(*L, IT_BRICK, plain_bricks(*L), TL_WG, k_p2g<false>, k_p2g_b<false>, A);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_p2g<true>, dim3(D->n_active), dim3(TL_WG), 0, st, *S, *D, A);
-    return hipGetLastError();
+    return tl_run(*L, IT_BRICK, plain_bricks(*L), TL_WG, k_p2g<true>, k_p2g_b<true>, A);
 }
 
-hipError_t tl_launch_g2p(const SceneK* S, const SceneD* D, int cur, hipStream_t st)
+hipError_t tl_launch_g2p(const TlLaunch* L, int cur)
 {
-    if (D->n_active == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_g2p<false>, dim3(D->n_active), dim3(TL_WG), 0, st, *S, *D, cur);
-    hipError_t e = hipGetLastError();
+    hipError_t e = tl_run(*L, IT_BRICK, plain_bricks(*L), TL_WG, k_g2p<false>, k_g2p_b<false>, cur);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_g2p<true>, dim3(D->n_active), dim3(TL_WG), 0, st, *S, *D, cur);
-    return hipGetLastError();
+    return tl_run(*L, IT_BRICK, plain_bricks(*L), TL_WG, k_g2p<true>, k_g2p_b<true>, cur);
 }
 
-hipError_t tl_launch_labels(const SceneK* S, const SceneD* D, int n_tools, double jdt, int mark_prev, hipStream_t st)
+hipError_t tl_launch_labels(const TlLaunch* L, int j)
 {
-    if (D->n_active == 0 || n_tools == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_labels, dim3(D->n_active), dim3(256), 0, st, *S, *D, n_tools, jdt, mark_prev);
-    return hipGetLastError();
+    return tl_run(*L, IT_BRICK, plain_bricks(*L), 256, k_labels, k_labels_b, j);
 }
 
-hipError_t tl_launch_slots(const SceneK* S, const SceneD* D, int dst, int src, int force, hipStream_t st)
+hipError_t tl_launch_slots(const TlLaunch* L, int dst, int src, int force)
 {
-    long long nb = (S->NN + 255) / 256;
-    hipLaunchKernelGGL(k_slots, dim3((unsigned)nb), dim3(256), 0, st, *S, *D, dst, src, force);
-    return hipGetLastError();
+    return tl_run(*L, IT_NODE, plain_nodes(*L), 256, k_slots, k_slots_b, dst, src, force);
+}
+
+hipError_t tl_launch_mixed(const TlLaunch* L, int force)
+{
+    return tl_run(*L, IT_BRICK, plain_bricks(*L), 256, k_mixed, k_mixed_b, force);
+}
+
+hipError_t tl_launch_aabb(const TlLaunch* L)
+{
+    return tl_run(*L, IT_BRICK, plain_bricks(*L), 256, k_aabb, k_aabb_b);
+}
+
+hipError_t tl_launch_wrench(const TlLaunch* L)
+{
+    return tl_run(*L, IT_WRENCH, L->S ? TL_MAX_TOOLS * 6 : 0, 256, k_wrench, k_wrench_b);
+}
+
+hipError_t tl_launch_resetD(const TlLaunch* L)
+{
+    return tl_run(*L, IT_PART, plain_parts(*L), 256, k_resetD, k_resetD_b);
+}
+
+hipError_t tl_launch_clear_flags(const TlLaunch* L)
+{
+    return tl_run(*L, IT_BFLAG, plain_bflags(*L), 256, k_clear_flags, k_clear_flags_b);
+}
+
+hipError_t tl_launch_clear_wacc(const TlLaunch* L)
+{
+    return tl_run(*L, IT_SCENE, L->S ? 1 : 0, 64, k_clear_wacc, k_clear_wacc_b);
 }
 
 hipError_t tl_launch_fill_f32(float* p, long long n, float v, hipStream_t st)
@@ -1352,27 +1469,6 @@ hipError_t tl_launch_fill_i32(int* p, long long n, int v, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
-    return hipGetLastError();
-}
-
-hipError_t tl_launch_mixed(const SceneK* S, const SceneD* D, int force, hipStream_t st)
-{
-    if (D->n_active == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_mixed, dim3(D->n_active), dim3(256), 0, st, *S, *D, force);
-    return hipGetLastError();
-}
-
-hipError_t tl_launch_aabb(const SceneK* S, const SceneD* D, hipStream_t st)
-{
-    if (D->n_active == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_aabb, dim3(D->n_active), dim3(256), 0, st, *S, *D);
-    return hipGetLastError();
-}
-
-hipError_t tl_launch_wrench(const SceneD* D, int n_tools, hipStream_t st)
-{
-    if (n_tools <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_wrench, dim3(n_tools * 6), dim3(256), 0, st, *D);
     return hipGetLastError();
 }
 }

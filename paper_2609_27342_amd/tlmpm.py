@@ -72,10 +72,19 @@ def lib():
         L.tlmpm_slot_stats.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
         L.tlmpm_profile_enable.argtypes = [vp, C.c_int32]
         L.tlmpm_profile_read.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        L.tlmpm_batch_footprint.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(C.c_size_t)]
+        L.tlmpm_batch_create.argtypes = [C.POINTER(vp), C.c_int32, vp, C.c_size_t, vp, C.POINTER(vp)]
+        L.tlmpm_batch_destroy.argtypes = [vp]
+        L.tlmpm_batch_step.argtypes = [vp, C.POINTER(Tool), C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_double)]
+        L.tlmpm_batch_sync.argtypes = [vp]
+        L.tlmpm_batch_profile_enable.argtypes = [vp, C.c_int32]
+        L.tlmpm_batch_profile_read.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.tlmpm_last_error.restype = C.c_char_p
         for f in ("tlmpm_scene_footprint", "tlmpm_create_scene", "tlmpm_destroy_scene", "tlmpm_assign_labels",
                   "tlmpm_step", "tlmpm_read_state", "tlmpm_write_state", "tlmpm_get_status", "tlmpm_slot_stats",
-                  "tlmpm_profile_enable", "tlmpm_profile_read"):
+                  "tlmpm_profile_enable", "tlmpm_profile_read", "tlmpm_batch_footprint", "tlmpm_batch_create",
+                  "tlmpm_batch_destroy", "tlmpm_batch_step", "tlmpm_batch_sync", "tlmpm_batch_profile_enable",
+                  "tlmpm_batch_profile_read"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -274,3 +283,74 @@ class Scene:
         mx = C.c_int32()
         _check(lib().tlmpm_slot_stats(self.h, C.byref(tot), C.byref(mx)))
         return tot.value, mx.value
+
+
+class Batch:
+    """Scenes advanced together by shared kernel launches.  While the batch is
+    open its scenes refuse single-scene calls; close() releases them."""
+
+    def __init__(self, scenes, stream=None, workspace=None):
+        import torch
+        L = lib()
+        self.scenes = list(scenes)
+        n = len(self.scenes)
+        self._hs = (C.c_void_p * max(1, n))(*[s.h for s in self.scenes])
+        nb = C.c_size_t()
+        _check(L.tlmpm_batch_footprint(self._hs, n, C.byref(nb)))
+        self.bytes = nb.value
+        if workspace is None:
+            workspace = torch.empty(self.bytes, dtype=torch.uint8, device="cuda")
+        assert workspace.numel() >= self.bytes and workspace.is_cuda
+        self.ws = workspace
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        _check(L.tlmpm_batch_create(self._hs, n, C.c_void_p(workspace.data_ptr()), self.bytes,
+                                    C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+        self._tools = (Tool * (MAX_TOOLS * max(1, n)))()
+        self._counts = (C.c_int32 * max(1, n))()
+
+    def close(self):
+        if getattr(self, "h", None):
+            _check(lib().tlmpm_batch_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def step(self, tools_per_scene, n_substeps=1, wrench=False):
+        """tools_per_scene: one list of tool dicts per scene.  Returns, with
+        wrench=True, an array [n_scenes][4][6] of interval-averaged wrenches."""
+        n = len(self.scenes)
+        assert len(tools_per_scene) == n
+        for s, tl in enumerate(tools_per_scene):
+            assert len(tl) <= MAX_TOOLS
+            self._counts[s] = len(tl)
+            for t, tool in enumerate(tl):
+                self._tools[s * MAX_TOOLS + t] = make_tool(tool)
+        w = np.zeros((max(1, n), MAX_TOOLS, 6))
+        wp = w.ctypes.data_as(C.POINTER(C.c_double)) if wrench else None
+        _check(lib().tlmpm_batch_step(self.h, self._tools, self._counts, int(n_substeps), wp))
+        return w[:n] if wrench else None
+
+    def sync(self):
+        _check(lib().tlmpm_batch_sync(self.h))
+
+    def profile(self, enable=True):
+        _check(lib().tlmpm_batch_profile_enable(self.h, int(bool(enable))))
+
+    def profile_read(self):
+        """{class: (total ms, launches)} since the last read (synchronises)."""
+        ms = (C.c_double * 6)()
+        cnt = (C.c_int64 * 6)()
+        _check(lib().tlmpm_batch_profile_read(self.h, 6, ms, cnt))
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(Scene.KERNEL_CLASSES)}

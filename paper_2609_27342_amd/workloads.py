@@ -231,6 +231,107 @@ def large(seed=3, steps=2000, dx=0.0015, box=(0.3, 0.2, 0.1)):
     return _finish("large", params, X, 1000.0, E, rng, steps, tools_at)
 
 
+# ------------------------------------------------------------------------- batched
+def _random_dir_down(rng):
+    """Unit vector, uniform on the sphere restricted to d_z <= -0.5."""
+    while True:
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        if d[2] <= -0.5:
+            return d
+
+
+def _exit_distance(p, w, lo, hi):
+    """Distance from p (inside the box [lo, hi]) along the unit vector w to the box
+    boundary."""
+    t = np.inf
+    for a in range(3):
+        if w[a] > 1e-12:
+            t = min(t, (hi[a] - p[a]) / w[a])
+        elif w[a] < -1e-12:
+            t = min(t, (lo[a] - p[a]) / w[a])
+    return float(t)
+
+
+def batch_scene(seed, index, n_target, dx=0.0025, steps=1000, dt=1e-4):
+    """One scene of the many-scene workload: a box (aspect ratios U[0.5, 2]) or a
+    horizontal cylinder (length / diameter U[1, 4]) with about n_target particles
+    at 8 per cell, resting on the floor; E log-uniform in [2e4, 1e5], nu = 0.3,
+    rho = 1000, floor and material contact on.  One to three blades, each its own
+    cut: descent direction d uniform with d_z <= -0.5, normal n uniform with n.d = 0,
+    speed U[0.05, 0.3] m/s, the edge starting on the body's bounding box on the ray
+    from an aim point (the centre moved by up to +-25 % of the extent per axis)
+    back along -d, half length = body diagonal.  All randomness comes from
+    (seed, index), so a scene is the same alone or in any batch."""
+    rng = np.random.default_rng([seed, index])
+    V = n_target * dx ** 3 / 8.0
+    if rng.uniform() < 0.5:
+        r1, r2 = rng.uniform(0.5, 2.0, size=2)
+        c = (V / (r1 * r2)) ** (1.0 / 3.0)
+        ext = np.array([r1 * c, r2 * c, c])
+
+        def inside(P):
+            return np.all((P >= 0.0) & (P <= ext), axis=1)
+        shape = "box"
+    else:
+        q = rng.uniform(1.0, 4.0)
+        r = (V / (2.0 * math.pi * q)) ** (1.0 / 3.0)
+        ext = np.array([2.0 * r * q, 2.0 * r, 2.0 * r])
+
+        def inside(P):
+            return (P[:, 0] >= 0.0) & (P[:, 0] <= ext[0]) & ((P[:, 1] - r) ** 2 + (P[:, 2] - r) ** 2 <= r * r)
+        shape = "cylinder"
+    lo = np.zeros(3)
+    origin, cells = _grid(lo, ext, dx, pad=1)
+    X = jittered_lattice(lo, ext, dx, origin, inside, rng)
+    E = float(np.exp(rng.uniform(math.log(2e4), math.log(1e5))))
+    params = base_params(dx, origin, cells, dt, 0.3, material_contact=1, floor_on=1)
+    n_bl = int(rng.integers(1, 4))
+    diag = float(np.linalg.norm(ext))
+    specs = []
+    for k in range(n_bl):
+        d = _random_dir_down(rng)
+        a = rng.normal(size=3)
+        n = a - np.dot(a, d) * d
+        n /= np.linalg.norm(n)
+        speed = rng.uniform(0.05, 0.3)
+        aim = 0.5 * ext + rng.uniform(-0.25, 0.25, size=3) * ext
+        start = aim - d * _exit_distance(aim, -d, lo, ext)
+        specs.append((k, start, n, d, speed))
+
+    def tools_at(j):
+        out = []
+        for k, start, n, d, speed in specs:
+            ve = speed * d
+            bl = blade(k, start + ve * (j * dt), n, d, ve, diag, 6 * dx, diag, dx, new_cut=(j == 0))
+            out.append(tool(bl, labels=True, contact=True, cutting=True))
+        return out
+
+    sc = _finish(f"batch-{index}-{shape}", params, X, 1000.0, E, rng, steps, tools_at)
+    sc["shape"] = shape
+    return sc
+
+
+def batch_sizes(seed=4, n_scenes=256, median=40000, sigma=0.7, lo=5000, hi=200000):
+    """Target particle counts: LogNormal(ln median, sigma) truncated to [lo, hi] by
+    resampling."""
+    rng = np.random.default_rng([seed, 1 << 20])
+    out = []
+    while len(out) < n_scenes:
+        v = float(np.exp(rng.normal(math.log(median), sigma)))
+        if lo <= v <= hi:
+            out.append(int(round(v)))
+    return out
+
+
+def batched(seed=4, n_scenes=256, steps=1000, median=40000, lo=5000, hi=200000):
+    """The many-scene workload: n_scenes independent batch_scene()s (about 12.5M
+    particles in total at the defaults)."""
+    sizes = batch_sizes(seed, n_scenes, median, lo=lo, hi=hi)
+    return dict(name="batched", scenes=[batch_scene(seed, i, n, steps=steps) for i, n in enumerate(sizes)],
+                steps=steps)
+
+
 # ------------------------------------------------------------------- generic pieces
 def box_scene(n_cells=(6, 5, 4), dx=0.01, seed=0, E=1e4, nu=0.3, rho=1000.0, dt=1e-4, v0=None,
               jitter=0.25, **kw):

@@ -39,3 +39,16 @@ def test_footprint_and_validation_without_gpu():
     with pytest.raises(tlmpm.TlmpmError) as e:
         tlmpm.footprint(bad)
     assert e.value.code == tlmpm.E_INVALID
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_batch_validation_without_gpu():
+    """Empty or null member lists are refused before any device call."""
+    L = ctypes.CDLL(LIB)
+    nb = ctypes.c_size_t()
+    assert L.tlmpm_batch_footprint(None, 0, ctypes.byref(nb)) == 1
+    arr = (ctypes.c_void_p * 2)(None, None)
+    assert L.tlmpm_batch_footprint(arr, 2, ctypes.byref(nb)) == 1
+    out = ctypes.c_void_p()
+    assert L.tlmpm_batch_create(None, 0, None, ctypes.c_size_t(0), None, ctypes.byref(out)) == 1
+    assert L.tlmpm_batch_step(None, None, None, 1, None) == 1
