@@ -17,6 +17,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -162,6 +164,47 @@ def bench_batched(args, K, Wm):
     }
 
 
+def bench_served(args):
+    """Continuous batching of arriving rollouts (Poisson arrivals, HBM-budget
+    admission); latency from arrival to result."""
+    import torch
+    from paper_2609_27342_amd import serve, workloads as W
+    torch.cuda.set_device(0)
+    reqs = W.served(seed=5, n_requests=args.requests, rate=args.rate, tick=args.tick)
+    build = lambda r: W.served_request(r["seed"], r["index"], r["n_target"], r["horizon"], r["tick"])
+    # warm the kernels and the allocator on one small request
+    warm = W.served(seed=6, n_requests=1, n_range=(20000, 20000), horizon_s=(0.02, 0.02), tick=args.tick)
+    serve.Server(build, args.budget_gb * 1e9, tick=args.tick).run(warm, realtime=False)
+    torch.cuda.synchronize()
+    log = lambda m: print(m, file=sys.stderr, flush=True)
+    srv = serve.Server(build, args.budget_gb * 1e9, tick=args.tick)
+    st = srv.run(reqs, realtime=True, log=log if args.verbose else None)
+    status = max(r["status"] for r in srv.results.values())
+    mean_work = np.mean([r["n"] * r["steps"] for r in srv.results.values()])
+    return {
+        "metric": "particle-steps/s per GPU",
+        "value": st["throughput"],
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": int(st["iterations"]),
+        "warmup": 1,
+        "ms_per_step": st["wall_s"] * 1e3 / max(1, st["iterations"]),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "served", "requests": st["requests"], "rate_per_s": args.rate, "tick": args.tick,
+                   "budget_gb": args.budget_gb, "path": "served",
+                   "latency_s": {"p50": st["p50_s"], "p99": st["p99_s"]},
+                   "mean_batch": st["mean_batch"], "wall_s": st["wall_s"],
+                   "capacity_requests_per_s": st["throughput"] / mean_work},
+        "status": status,
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -170,6 +213,11 @@ def main():
     ap.add_argument("--workload", default=os.environ.get("TLMPM_BENCH_WORKLOAD", "medium"))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=200)
+    ap.add_argument("--requests", type=int, default=100, help="served: number of requests")
+    ap.add_argument("--rate", type=float, default=40.0, help="served: Poisson arrival rate per second")
+    ap.add_argument("--tick", type=int, default=100, help="served: substeps per batched iteration")
+    ap.add_argument("--budget-gb", type=float, default=200.0, help="served: device bytes for running rollouts")
+    ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (5 times) and exit; used to scale "
                          "hardware traffic counters")
@@ -195,6 +243,9 @@ def main():
     steps_d, warm_d = DEFAULTS.get(args.workload, (200, 10))
     K = args.steps if args.steps is not None else steps_d
     Wm = args.warmup if args.warmup is not None else warm_d
+    if args.workload == "served":
+        print(json.dumps(bench_served(args)))
+        return
     if args.workload == "batched":
         print(json.dumps(bench_batched(args, K, max(Wm, 1))))
         return

@@ -73,6 +73,8 @@ typedef struct {
     float G_c, zeta, u_min;    /* cutting-work threshold parameters (Eq. 5) */
     int32_t max_cuts;          /* K, number of ternary digits (1..15) */
     int32_t single_field;      /* 1: ignore codes (one logical grid), a negative control */
+    int32_t slot_capacity;     /* logical grids per node (compact slots, Sec. III-G), 1..16; 0 = 8.
+                                  More distinct codes at a node set TLMPM_E_SLOT_OVERFLOW. */
 } tlmpm_scene_desc;
 
 /* A blade record: the cut frame of Eq. 3 and the band of Eq. 4.  (n, e, d) must be

@@ -154,12 +154,44 @@ Dims dims_of(const tlmpm_scene_desc* d)
 
 struct Offsets {
     size_t X, u, v, H, code, code_prev, D, perm, E, m, V0, cell_start, active, cnt0, cnt1, sc0, sc1, p2g, rs, hist,
-        aabb, wpart, wacc, Jmat, Jrig, brig, bmixed, tools, tinfo, ctr, status, dirty, bdirty, pcell, cand_idx, cmask, cstatic, bcand, hbin, bcount, bids, cslot, brec, htab, hnext, orec, ph_n, ph_q, ph_u,
+        aabb, wpart, wacc, Jmat, Jrig, brig, bmixed, tools, tinfo, ctr, bact, status, dirty, bdirty, pcell, cand_idx, cmask, cstatic, bcand, hbin, bcount, bids, cslot, brec, htab, hnext, orec, ph_n, ph_q, ph_u,
         total;
     uint32_t hmask;
 };
 
-Offsets plan(const tlmpm_scene_desc* d)
+int slot_cap(const tlmpm_scene_desc* d) { return d->slot_capacity > 0 ? d->slot_capacity : 8; }
+
+// reference cell of particle p (FP64), false if it lies outside the grid
+bool cell_of(const tlmpm_scene_desc* d, long long p, int c[3])
+{
+    for (int a = 0; a < 3; a++) {
+        double q = ((double)d->X[3 * p + a] - d->origin[a]) / d->dx;
+        double fl = std::floor(q);
+        if (!(fl >= 0.0) || fl >= (double)d->cells[a]) return false;
+        c[a] = (int)fl;
+    }
+    return true;
+}
+
+// number of bricks that hold a particle
+long long count_active(const tlmpm_scene_desc* d)
+{
+    Dims g = dims_of(d);
+    std::vector<uint8_t> occ((size_t)g.n_bricks, 0);
+    long long n = 0;
+    for (long long p = 0; p < g.N; p++) {
+        int c[3];
+        if (!cell_of(d, p, c)) continue;
+        long long b = ((long long)(c[2] >> 2) * g.cby + (c[1] >> 2)) * g.cbx + (c[0] >> 2);
+        if (!occ[b]) {
+            occ[b] = 1;
+            n++;
+        }
+    }
+    return n;
+}
+
+Offsets plan(const tlmpm_scene_desc* d, long long n_active)
 {
     Dims g = dims_of(d);
     Layout L;
@@ -181,10 +213,12 @@ Offsets plan(const tlmpm_scene_desc* d)
     o.active = L.take((size_t)g.n_bricks * 4);
     o.cnt0 = L.take((size_t)g.NN);
     o.cnt1 = L.take((size_t)g.NN);
-    o.sc0 = L.take((size_t)g.NN * TL_SCAP * 4);
-    o.sc1 = L.take((size_t)g.NN * TL_SCAP * 4);
-    o.p2g = L.take((size_t)g.NN * 8 * TL_SCAP * 8 * f); // 7 components padded to 8
-    o.rs = L.take((size_t)g.NN * 8 * TL_SCAP * 4 * f);
+    const size_t scap = slot_cap(d);
+    o.sc0 = L.take((size_t)g.NN * scap * 4);
+    o.sc1 = L.take((size_t)g.NN * scap * 4);
+    o.p2g = L.take((size_t)n_active * scap * TL_BOXN * 8 * f); // 7 components padded to 8
+    o.rs = L.take((size_t)n_active * scap * TL_BOXN * 4 * f);
+    o.bact = L.take((size_t)g.n_bricks * 4);
     o.hist = L.take((size_t)(TL_MAX_TOOLS + 1) * 4 * N * f);
     o.aabb = L.take((size_t)g.n_bricks * 8 * f);
     o.wpart = L.take((size_t)g.n_bricks * TL_MAX_TOOLS * 6 * f);
@@ -235,6 +269,8 @@ tlmpm_status validate(const tlmpm_scene_desc* d)
     for (int a = 0; a < 3; a++)
         if (d->cells[a] <= 0 || d->cells[a] > 1 << 16) return fail(TLMPM_E_INVALID, "cells out of range");
     if (d->max_cuts < 1 || d->max_cuts > 15) return fail(TLMPM_E_INVALID, "max_cuts must be in 1..15");
+    if (d->slot_capacity < 0 || d->slot_capacity > TL_SCAP_MAX)
+        return fail(TLMPM_E_INVALID, "slot_capacity must be in 0..16 (0: 8)");
     if (!(d->nu > -1.0f && d->nu < 0.5f)) return fail(TLMPM_E_INVALID, "nu must be in (-1, 0.5)");
     if (!d->vol0 && !(d->vol0_uniform > 0.0f)) return fail(TLMPM_E_INVALID, "vol0_uniform must be positive");
     if (!d->mass && !(d->mass_uniform > 0.0f)) return fail(TLMPM_E_INVALID, "mass_uniform must be positive");
@@ -284,7 +320,7 @@ extern "C" tlmpm_status tlmpm_scene_footprint(const tlmpm_scene_desc* desc, size
     tlmpm_status s = validate(desc);
     if (s) return s;
     if (!device_bytes) return fail(TLMPM_E_INVALID, "null output");
-    *device_bytes = plan(desc).total;
+    *device_bytes = plan(desc, count_active(desc)).total;
     return TLMPM_OK;
 }
 
@@ -295,8 +331,6 @@ extern "C" tlmpm_status tlmpm_create_scene(const tlmpm_scene_desc* d, void* ws, 
     if (s) return s;
     if (!out) return fail(TLMPM_E_INVALID, "null output");
     *out = nullptr;
-    Offsets o = plan(d);
-    if (!ws || bytes < o.total) return fail(TLMPM_E_NOMEM, "workspace smaller than tlmpm_scene_footprint()");
     Dims g = dims_of(d);
     const long long N = g.N;
 
@@ -305,13 +339,8 @@ extern "C" tlmpm_status tlmpm_create_scene(const tlmpm_scene_desc* d, void* ws, 
     std::vector<int> cnt((size_t)g.n_bricks * TL_CELLS + 1, 0);
     for (long long p = 0; p < N; p++) {
         int c[3];
-        for (int a = 0; a < 3; a++) {
-            double q = ((double)d->X[3 * p + a] - d->origin[a]) / d->dx;
-            double fl = std::floor(q);
-            if (!(fl >= 0.0) || fl >= (double)d->cells[a])
-                return fail(TLMPM_E_INVALID, "particle " + std::to_string(p) + " lies outside the reference grid");
-            c[a] = (int)fl;
-        }
+        if (!cell_of(d, p, c))
+            return fail(TLMPM_E_INVALID, "particle " + std::to_string(p) + " lies outside the reference grid");
         long long brick = ((long long)(c[2] >> 2) * g.cby + (c[1] >> 2)) * g.cbx + (c[0] >> 2);
         int lx = c[0] & 3, ly = c[1] & 3, lz = c[2] & 3;
         int w = (lx & 1) | ((ly & 1) << 1) | ((lz & 1) << 2);
@@ -326,9 +355,14 @@ extern "C" tlmpm_status tlmpm_create_scene(const tlmpm_scene_desc* d, void* ws, 
         std::vector<int> fill(cnt.begin(), cnt.end() - 1);
         for (long long p = 0; p < N; p++) perm[fill[key[p]]++] = (int)p; // stable counting sort
     }
-    std::vector<int> active;
+    std::vector<int> active, bact((size_t)g.n_bricks, -1);
     for (long long b = 0; b < g.n_bricks; b++)
-        if (cell_start[(b + 1) * TL_CELLS] > cell_start[b * TL_CELLS]) active.push_back((int)b);
+        if (cell_start[(b + 1) * TL_CELLS] > cell_start[b * TL_CELLS]) {
+            bact[b] = (int)active.size();
+            active.push_back((int)b);
+        }
+    Offsets o = plan(d, (long long)active.size());
+    if (!ws || bytes < o.total) return fail(TLMPM_E_NOMEM, "workspace smaller than tlmpm_scene_footprint()");
 
     tlmpm_scene* sc = new tlmpm_scene();
     sc->st = (hipStream_t)hip_stream;
@@ -384,6 +418,7 @@ extern "C" tlmpm_status tlmpm_create_scene(const tlmpm_scene_desc* d, void* ws, 
     K.u_min = d->u_min;
     K.single_field = d->single_field;
     K.material_contact = d->material_contact;
+    K.scap = slot_cap(d);
     float vmax0 = d->vol0_uniform;
     if (d->vol0)
         for (long long p = 0; p < N; p++) vmax0 = std::max(vmax0, d->vol0[p]);
@@ -422,6 +457,7 @@ extern "C" tlmpm_status tlmpm_create_scene(const tlmpm_scene_desc* d, void* ws, 
     D.bmixed = (int*)(base + o.bmixed);
     D.tools = (DevTool*)(base + o.tools);
     D.tinfo = (int*)(base + o.tinfo);
+    D.bact = (int*)(base + o.bact);
     D.ctr = (int*)(base + o.ctr);
     if (d->material_contact) {
         D.cmask = (uint32_t*)(base + o.cmask);
@@ -487,6 +523,8 @@ extern "C" tlmpm_status tlmpm_create_scene(const tlmpm_scene_desc* d, void* ws, 
     if (!active.empty() &&
         (e = hipMemcpyAsync(D.active, active.data(), active.size() * 4, hipMemcpyHostToDevice, sc->st)) != hipSuccess)
         return bail(e, "upload bricks");
+    if ((e = hipMemcpyAsync(D.bact, bact.data(), bact.size() * 4, hipMemcpyHostToDevice, sc->st)) != hipSuccess)
+        return bail(e, "upload brick index");
     // rigid-contact history stamps start invalid
     if ((e = tl_launch_fill_f32(D.hist, (long long)(TL_MAX_TOOLS + 1) * 4 * N, 0.0f, sc->st)) != hipSuccess)
         return bail(e, "init history");

@@ -16,7 +16,7 @@
 #define TL_B 4                 // cells per brick edge
 #define TL_CELLS 64            // cells per brick
 #define TL_BOXN 125            // nodes of a brick's (TL_B + 1)^3 box
-#define TL_SCAP 8              // logical grids (slots) per node
+#define TL_SCAP_MAX 16         // largest per-node capacity of logical grids (slots)
 #define TL_BOX_SLOTS 512       // slots of one brick box held in LDS
 #define TL_MAX_TOOLS 4          // tools per scene (rigid-history slots 1..4; slot 0 = floor)
 #define TL_WG 512              // threads per brick workgroup: 8 waves = 8 parity classes
@@ -78,6 +78,7 @@ struct SceneK {
     float G_c, zeta, u_min;
     int single_field;
     int material_contact;
+    int scap;         // slot capacity per node (<= TL_SCAP_MAX)
     double dt_d;
 };
 
@@ -99,8 +100,9 @@ struct SceneD {
     int n_active;
     uint8_t* cnt[2];
     uint32_t* scode[2];
-    float* p2g;    // [8][S][NN][8]
-    float* rs;     // [8][S][NN][4]
+    float* p2g;    // [active brick][scap][125 box nodes][8]: each brick's P2G box sums
+    float* rs;     // [active brick][scap][125 box nodes][4]: each brick's re-scatter box sums
+    int* bact;     // [bricks] active index of a brick, -1 if it holds no particle
     float* hist;   // rigid contact history [TL_MAX_TOOLS+1][4][N]: u_t xyz, stamp
     float* aabb;   // [n_bricks][8]: min xyz, max xyz, max |v|, 0
     float* wpart;  // [n_active][TL_MAX_TOOLS][6]

@@ -124,8 +124,10 @@ DEV int find_slot(const BoxTab& T, int bn, uint32_t key)
     return -1;
 }
 
-// Partial arrays are [8 contributors][TL_SCAP slots][node][QP floats]: the Q
-// components of one node-slot are contiguous (QP = Q rounded up to 4 floats).
+// Partial arrays hold every active brick's sums over its 5x5x5 box of nodes:
+// [active brick][slot][box node][QP floats], the Q components of one node-slot
+// contiguous (QP = Q rounded up to 4 floats).  A node's slot index is global (the
+// node's slot table), so all bricks that share the node use the same slot.
 template <int Q>
 struct QPad {
     static constexpr int value = (Q + 3) & ~3;
@@ -134,21 +136,28 @@ struct QPad {
 // Sums of all slots of box node bn over the bricks that contributed to it, in
 // fixed contributor order, written to dst[slot * Q + c].
 template <int Q>
-DEV void gather_node(const SceneK& S, const float* __restrict__ part, const BoxTab& T, int bn, int bx, int by, int bz,
-                     float* dst)
+DEV void gather_node(const SceneK& S, const SceneD& D, const float* __restrict__ part, const BoxTab& T, int bn, int bx,
+                     int by, int bz, float* dst)
 {
     constexpr int QP = QPad<Q>::value;
     const int c = T.cnt[bn], b0 = T.base[bn];
-    const long long g = T.gid[bn];
     const int X = bn % 5, Y = (bn / 5) % 5, Z = bn / 25;
     const int hx = bx + (X >> 2), hy = by + (Y >> 2), hz = bz + (Z >> 2);
     const int lx = X & 3, ly = Y & 3, lz = Z & 3;
+    // contributor d: the brick at home - (d & 1, d >> 1 & 1, d >> 2 & 1), which
+    // holds the node at box position (l + 4 * offset)
+    long long cbase[8];
     unsigned valid = 0;
     for (int d = 0; d < 8; d++) {
         int dx = d & 1, dy = (d >> 1) & 1, dz = (d >> 2) & 1;
+        cbase[d] = 0;
         if ((dx && lx) || (dy && ly) || (dz && lz)) continue;
         int cbx = hx - dx, cby = hy - dy, cbz = hz - dz;
         if (cbx < 0 || cby < 0 || cbz < 0 || cbx >= S.cbx || cby >= S.cby || cbz >= S.cbz) continue;
+        const int ai = D.bact[((long long)cbz * S.cby + cby) * S.cbx + cbx];
+        if (ai < 0) continue;
+        const int pn = (lx + 4 * dx) + 5 * (ly + 4 * dy) + 25 * (lz + 4 * dz);
+        cbase[d] = (long long)ai * S.scap * TL_BOXN + pn;
         valid |= 1u << d;
     }
     for (int s = 0; s < c; s++) {
@@ -158,7 +167,7 @@ DEV void gather_node(const SceneK& S, const float* __restrict__ part, const BoxT
 #pragma unroll
         for (int d = 0; d < 8; d++) {
             if (!(valid & (1u << d))) continue;
-            const float4* pp = (const float4*)(part + (((long long)(d * TL_SCAP + s)) * S.NN + g) * QP);
+            const float4* pp = (const float4*)(part + (cbase[d] + (long long)s * TL_BOXN) * QP);
 #pragma unroll
             for (int q4 = 0; q4 < QP / 4; q4++) {
                 float4 v4 = pp[q4];
@@ -367,15 +376,13 @@ DEV void accumulate_classes(const Lane& L, bool valid, uint32_t key, GA&& ga, GB
 
 // Writes the box accumulator as this brick's partial (layout of gather_node).
 template <int Q>
-DEV void write_partials(const SceneK& S, float* __restrict__ part, const BoxTab& T, int total, const float* acc)
+DEV void write_partials(const SceneK& S, float* __restrict__ part, int bi, const BoxTab& T, int total, const float* acc)
 {
     constexpr int QP = QPad<Q>::value;
     for (int q = threadIdx.x; q < total; q += blockDim.x) {
         int bn = T.node_of[q];
         int s = q - T.base[bn];
-        int X = bn % 5, Y = (bn / 5) % 5, Z = bn / 25;
-        int k = (X == 4) | ((Y == 4) << 1) | ((Z == 4) << 2);
-        float4* pp = (float4*)(part + (((long long)(k * TL_SCAP + s)) * S.NN + T.gid[bn]) * QP);
+        float4* pp = (float4*)(part + (((long long)bi * S.scap + s) * TL_BOXN + bn) * QP);
         float v[QP];
 #pragma unroll
         for (int c = 0; c < QP; c++) v[c] = c < Q ? acc[q * Q + c] : 0.0f;
@@ -748,7 +755,7 @@ DEV void p2g_body(const SceneK& S, const SceneD& D, int bi, KA_Args A)
             box_codes(S, D.scode[A.rsb], Tr, tid);
             const int c = Tr.cnt[tid], b0 = Tr.base[tid];
             if (c > 0) {
-                gather_node<4>(S, D.rs, Tr, tid, bx, by, bz, s_rsum);
+                gather_node<4>(S, D, D.rs, Tr, tid, bx, by, bz, s_rsum);
                 couple_node<4>(Tr, b0, c, s_rsum, 1, s_vt);
                 for (int a = 0; a < c; a++) {
                     float m = s_rsum[(b0 + a) * 4];
@@ -878,7 +885,7 @@ DEV void p2g_body(const SceneK& S, const SceneD& D, int bi, KA_Args A)
         accumulate_classes<4, 3, MIXED>(L, valid, key, gen_mp, gen_dp, T, s_acc, D.status);
     }
     if (!A.do_p2g) return;
-    write_partials<7>(S, D.p2g, T, total_c, s_acc);
+    write_partials<7>(S, D.p2g, bi, T, total_c, s_acc);
 }
 
 // --------------------------------------------------------------------------- K_B
@@ -942,7 +949,7 @@ DEV void g2p_body(const SceneK& S, const SceneD& D, int bi, int cur)
         box_codes(S, D.scode[cur], T, tid);
         const int c = T.cnt[tid], b0 = T.base[tid];
         if (c > 0) {
-            gather_node<7>(S, D.p2g, T, tid, bx, by, bz, s_sum);
+            gather_node<7>(S, D, D.p2g, T, tid, bx, by, bz, s_sum);
             float* gvn = s_grid;
             float* gdv = s_grid + TL_BOX_SLOTS * 3;
             couple_node<7>(T, b0, c, s_sum, 1, gvn);
@@ -1018,7 +1025,7 @@ DEV void g2p_body(const SceneK& S, const SceneD& D, int bi, int cur)
         };
         accumulate_classes<4, 0, MIXED>(L, valid, key, gen, gen, T, s_acc, D.status);
     }
-    write_partials<4>(S, D.rs, T, total, s_acc);
+    write_partials<4>(S, D.rs, bi, T, total, s_acc);
     // brick AABB of x^{n+1} and speed bound (used to skip distant contact work)
     for (int q = 0; q < 7; q++) {
         float val = bb[q];
@@ -1172,7 +1179,7 @@ DEV void slots_body(const SceneK& S, const SceneD& D, int bi, int dst, int src, 
         return;
     }
     int gx = hx * 4 + (lid & 3), gy = hy * 4 + ((lid >> 2) & 3), gz = hz * 4 + (lid >> 4);
-    uint32_t codes[TL_SCAP];
+    uint32_t codes[TL_SCAP_MAX];
     int c = 0;
     bool over = false;
     if (gx <= S.cx && gy <= S.cy && gz <= S.cz) {
@@ -1191,7 +1198,7 @@ DEV void slots_body(const SceneK& S, const SceneD& D, int bi, int dst, int src, 
                         int pos = 0;
                         while (pos < c && codes[pos] < k) pos++;
                         if (pos < c && codes[pos] == k) continue;
-                        if (c == TL_SCAP) {
+                        if (c == S.scap) {
                             over = true;
                             continue;
                         }

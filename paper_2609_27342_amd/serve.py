@@ -1,0 +1,134 @@
+"""Continuous batching of cutting rollouts on one GPU.
+
+Requests (a scene and its tool schedule over a horizon of substeps) arrive over
+time.  A request is admitted when its device footprint (tlmpm_scene_footprint)
+fits the HBM budget; every admitted request advances by one tick of substeps per
+iteration through one batched step (tlmpm_batch_step), so each kernel launch
+covers all running rollouts.  The batch is rebuilt whenever a rollout finishes or
+starts.  New scenes are built on a second stream while the current tick runs.
+
+The tool schedule of a request is constant over each tick: its tools at the
+first substep of the tick, moved by TLMPM_TOOL_ADVANCE within the tick.
+"""
+import time
+
+import numpy as np
+
+from . import tlmpm
+
+
+class Rollout:
+    def __init__(self, req, scene_dict, scene, arrival, admitted):
+        self.req = req
+        self.sd = scene_dict
+        self.scene = scene
+        self.arrival = arrival
+        self.admitted = admitted
+        self.done_steps = 0
+        self.horizon = int(scene_dict["steps"])
+        self.n = int(scene_dict["X"].shape[0])
+
+    def tools(self, tick):
+        return [dict(t, advance=True) for t in self.sd["tools_at"](self.done_steps)]
+
+
+class Server:
+    """budget_bytes: device bytes that running rollouts may hold; tick: substeps
+    per iteration; build(req) -> scene dict of a request."""
+
+    def __init__(self, build, budget_bytes, tick=100, max_batch=256, read_fields=("u", "D", "digits")):
+        import torch
+        self.torch = torch
+        self.build = build
+        self.budget = int(budget_bytes)
+        self.tick = int(tick)
+        self.max_batch = int(max_batch)
+        self.read_fields = tuple(read_fields)
+        self.stream = torch.cuda.current_stream()
+        self.create_stream = torch.cuda.Stream()
+        self.results = {}
+
+    def _admit(self, queue, active, used, now_fn):
+        """Builds scenes for queued requests (FIFO) while they fit."""
+        admitted = []
+        while queue and len(active) + len(admitted) < self.max_batch:
+            req, sd, nbytes = queue[0]
+            if sd is None:
+                sd = self.build(req)
+                nbytes = tlmpm.footprint(sd)
+                queue[0] = (req, sd, nbytes)
+            if used + nbytes > self.budget and (active or admitted):
+                break
+            queue.pop(0)
+            with self.torch.cuda.stream(self.create_stream):
+                ws = self.torch.empty(nbytes, dtype=self.torch.uint8, device="cuda")
+                g = tlmpm.Scene(sd, stream=self.create_stream, workspace=ws)
+            admitted.append(Rollout(req, sd, g, req["_arrival_wall"], now_fn()))
+            used += nbytes
+        return admitted, used
+
+    def run(self, requests, realtime=True, log=None):
+        """Serves `requests` (dicts with 'arrival' seconds and whatever build()
+        needs).  realtime=False admits every request at time zero.  Returns stats
+        (latency percentiles from arrival to result, throughput) and fills
+        self.results[index] with the final fields and timestamps."""
+        t0 = time.perf_counter()
+        now = lambda: time.perf_counter() - t0
+        pending = sorted(requests, key=lambda r: r["arrival"])
+        queue = []  # (req, scene dict or None, bytes)
+        active = []
+        used = 0
+        batch = None
+        lat = {}
+        work = 0
+        iters = 0
+        sizes = []
+        while pending or queue or active:
+            tnow = now()
+            while pending and (not realtime or pending[0]["arrival"] <= tnow):
+                r = dict(pending.pop(0))
+                r["_arrival_wall"] = r["arrival"] if realtime else 0.0
+                queue.append((r, None, 0))
+            if not active and not queue:
+                time.sleep(max(0.0, min(0.05, pending[0]["arrival"] - tnow)))
+                continue
+            # one tick of every running rollout (asynchronous)
+            if active:
+                tools = [ro.tools(self.tick) for ro in active]
+                batch.step(tools, self.tick)
+            # build newly admissible scenes while the tick runs
+            new, used = self._admit(queue, active, used, now)
+            if active:
+                batch.sync()
+                iters += 1
+                sizes.append(len(active))
+                for ro in active:
+                    ro.done_steps += self.tick
+                    work += ro.n * self.tick
+            finished = [ro for ro in active if ro.done_steps >= ro.horizon]
+            if finished or new:
+                if batch is not None:
+                    batch.close()
+                    batch = None
+                for ro in finished:
+                    out = ro.scene.read(self.read_fields)
+                    st = ro.scene.status()
+                    ro.scene.close()
+                    used -= ro.scene.bytes
+                    done = now()
+                    lat[ro.req["index"]] = done - ro.arrival
+                    self.results[ro.req["index"]] = dict(fields=out, status=st, n=ro.n, steps=ro.horizon,
+                                                         arrival=ro.arrival, admitted=ro.admitted, done=done)
+                    if log:
+                        log(f"[serve] t={done:.2f}s done request {ro.req['index']} n={ro.n} "
+                            f"steps={ro.horizon} latency={done - ro.arrival:.2f}s running={len(active) - 1}")
+                active = [ro for ro in active if ro.done_steps < ro.horizon] + new
+                if active:
+                    self.create_stream.synchronize()
+                    batch = tlmpm.Batch([ro.scene for ro in active], stream=self.stream)
+        wall = now()
+        L = np.array([lat[k] for k in sorted(lat)])
+        return dict(requests=len(L), wall_s=wall, particle_steps=work, throughput=work / wall if wall > 0 else 0.0,
+                    p50_s=float(np.percentile(L, 50)) if len(L) else None,
+                    p99_s=float(np.percentile(L, 99)) if len(L) else None,
+                    mean_batch=float(np.mean(sizes)) if sizes else 0.0, iterations=iters)

@@ -30,7 +30,7 @@ class SceneDesc(C.Structure):
         ("mu_s", C.c_float), ("mu_d", C.c_float),
         ("material_contact", C.c_int32), ("floor_on", C.c_int32), ("floor_z", C.c_float),
         ("G_c", C.c_float), ("zeta", C.c_float), ("u_min", C.c_float),
-        ("max_cuts", C.c_int32), ("single_field", C.c_int32),
+        ("max_cuts", C.c_int32), ("single_field", C.c_int32), ("slot_capacity", C.c_int32),
     ]
 
 
@@ -173,6 +173,7 @@ def make_desc(scene, keep):
     d.floor_on = int(p.get("floor_on", 0))
     d.max_cuts = int(p.get("max_cuts", 4))
     d.single_field = int(p.get("single_field", 0))
+    d.slot_capacity = int(p.get("slot_capacity", 0))
     return d
 
 

@@ -253,17 +253,10 @@ def _exit_distance(p, w, lo, hi):
     return float(t)
 
 
-def batch_scene(seed, index, n_target, dx=0.0025, steps=1000, dt=1e-4):
-    """One scene of the many-scene workload: a box (aspect ratios U[0.5, 2]) or a
-    horizontal cylinder (length / diameter U[1, 4]) with about n_target particles
-    at 8 per cell, resting on the floor; E log-uniform in [2e4, 1e5], nu = 0.3,
-    rho = 1000, floor and material contact on.  One to three blades, each its own
-    cut: descent direction d uniform with d_z <= -0.5, normal n uniform with n.d = 0,
-    speed U[0.05, 0.3] m/s, the edge starting on the body's bounding box on the ray
-    from an aim point (the centre moved by up to +-25 % of the extent per axis)
-    back along -d, half length = body diagonal.  All randomness comes from
-    (seed, index), so a scene is the same alone or in any batch."""
-    rng = np.random.default_rng([seed, index])
+def _random_body(rng, n_target, dx):
+    """A box (aspect ratios U[0.5, 2]) or a horizontal cylinder (length / diameter
+    U[1, 4]), p = 1/2, with about n_target particles at 8 per cell, resting on the
+    floor.  Returns (shape, extent, inside)."""
     V = n_target * dx ** 3 / 8.0
     if rng.uniform() < 0.5:
         r1, r2 = rng.uniform(0.5, 2.0, size=2)
@@ -272,44 +265,109 @@ def batch_scene(seed, index, n_target, dx=0.0025, steps=1000, dt=1e-4):
 
         def inside(P):
             return np.all((P >= 0.0) & (P <= ext), axis=1)
-        shape = "box"
-    else:
-        q = rng.uniform(1.0, 4.0)
-        r = (V / (2.0 * math.pi * q)) ** (1.0 / 3.0)
-        ext = np.array([2.0 * r * q, 2.0 * r, 2.0 * r])
+        return "box", ext, inside
+    q = rng.uniform(1.0, 4.0)
+    r = (V / (2.0 * math.pi * q)) ** (1.0 / 3.0)
+    ext = np.array([2.0 * r * q, 2.0 * r, 2.0 * r])
 
-        def inside(P):
-            return (P[:, 0] >= 0.0) & (P[:, 0] <= ext[0]) & ((P[:, 1] - r) ** 2 + (P[:, 2] - r) ** 2 <= r * r)
-        shape = "cylinder"
+    def inside(P):
+        return (P[:, 0] >= 0.0) & (P[:, 0] <= ext[0]) & ((P[:, 1] - r) ** 2 + (P[:, 2] - r) ** 2 <= r * r)
+    return "cylinder", ext, inside
+
+
+def _random_blade(rng, ext):
+    """Descent direction d uniform with d_z <= -0.5, normal n uniform with n.d = 0,
+    speed U[0.05, 0.3] m/s, edge start on the body's bounding box on the ray from an
+    aim point (the centre moved by up to +-25 % of the extent per axis) back along
+    -d.  Returns (start, n, d, speed)."""
+    d = _random_dir_down(rng)
+    a = rng.normal(size=3)
+    n = a - np.dot(a, d) * d
+    n /= np.linalg.norm(n)
+    speed = rng.uniform(0.05, 0.3)
+    aim = 0.5 * ext + rng.uniform(-0.25, 0.25, size=3) * ext
+    start = aim - d * _exit_distance(aim, -d, np.zeros(3), ext)
+    return start, n, d, speed
+
+
+def _random_scene(rng, n_target, dx, dt):
+    shape, ext, inside = _random_body(rng, n_target, dx)
     lo = np.zeros(3)
     origin, cells = _grid(lo, ext, dx, pad=1)
     X = jittered_lattice(lo, ext, dx, origin, inside, rng)
     E = float(np.exp(rng.uniform(math.log(2e4), math.log(1e5))))
-    params = base_params(dx, origin, cells, dt, 0.3, material_contact=1, floor_on=1)
-    n_bl = int(rng.integers(1, 4))
+    # up to four crossing cuts in a small body: room for 16 logical grids per node
+    params = base_params(dx, origin, cells, dt, 0.3, material_contact=1, floor_on=1, slot_capacity=16)
+    return shape, ext, X, E, params
+
+
+def _blade_tool(k, spec, j, j0, diag, dx, dt):
+    start, n, d, speed = spec
+    ve = speed * d
+    bl = blade(k, start + ve * ((j - j0) * dt), n, d, ve, diag, 6 * dx, diag, dx, new_cut=(j == j0))
+    return tool(bl, labels=True, contact=True, cutting=True)
+
+
+def batch_scene(seed, index, n_target, dx=0.0025, steps=1000, dt=1e-4):
+    """One scene of the many-scene workload: a random box or cylinder
+    (_random_body) with about n_target particles; E log-uniform in [2e4, 1e5],
+    nu = 0.3, rho = 1000, floor and material contact on; one to three simultaneous
+    blades (_random_blade), each its own cut, half length = body diagonal.  All
+    randomness comes from (seed, index), so a scene is the same alone or in any
+    batch."""
+    rng = np.random.default_rng([seed, index])
+    shape, ext, X, E, params = _random_scene(rng, n_target, dx, dt)
     diag = float(np.linalg.norm(ext))
-    specs = []
-    for k in range(n_bl):
-        d = _random_dir_down(rng)
-        a = rng.normal(size=3)
-        n = a - np.dot(a, d) * d
-        n /= np.linalg.norm(n)
-        speed = rng.uniform(0.05, 0.3)
-        aim = 0.5 * ext + rng.uniform(-0.25, 0.25, size=3) * ext
-        start = aim - d * _exit_distance(aim, -d, lo, ext)
-        specs.append((k, start, n, d, speed))
+    specs = [_random_blade(rng, ext) for _ in range(int(rng.integers(1, 4)))]
 
     def tools_at(j):
-        out = []
-        for k, start, n, d, speed in specs:
-            ve = speed * d
-            bl = blade(k, start + ve * (j * dt), n, d, ve, diag, 6 * dx, diag, dx, new_cut=(j == 0))
-            out.append(tool(bl, labels=True, contact=True, cutting=True))
-        return out
+        return [_blade_tool(k, sp, j, 0, diag, dx, dt) for k, sp in enumerate(specs)]
 
     sc = _finish(f"batch-{index}-{shape}", params, X, 1000.0, E, rng, steps, tools_at)
     sc["shape"] = shape
     return sc
+
+
+def served_request(seed, index, n_target, horizon_steps, tick, dx=0.0025, dt=1e-4):
+    """One request of the served workload: body, material and blades as
+    batch_scene, with one to four cuts made one after another, each in its own
+    window of the horizon (windows are whole ticks; a blade is withdrawn when its
+    window ends)."""
+    rng = np.random.default_rng([seed, index])
+    shape, ext, X, E, params = _random_scene(rng, n_target, dx, dt)
+    diag = float(np.linalg.norm(ext))
+    n_cuts = int(rng.integers(1, 5))
+    specs = [_random_blade(rng, ext) for _ in range(n_cuts)]
+    n_ticks = max(1, horizon_steps // tick)
+    bounds = [tick * ((n_ticks * k) // n_cuts) for k in range(n_cuts + 1)]
+
+    def tools_at(j):
+        for k in range(n_cuts):
+            if bounds[k] <= j < bounds[k + 1]:
+                return [_blade_tool(k, specs[k], j, bounds[k], diag, dx, dt)]
+        return []
+
+    sc = _finish(f"request-{index}-{shape}", params, X, 1000.0, E, rng, tick * n_ticks, tools_at)
+    sc["shape"] = shape
+    return sc
+
+
+def served(seed=5, n_requests=200, rate=40.0, n_range=(10000, 1000000), horizon_s=(0.05, 0.2), tick=100,
+           dt=1e-4):
+    """Arrivals of the served workload: Poisson at `rate` per second; per request a
+    log-uniform particle count in n_range and a horizon U[horizon_s] seconds
+    (rounded to whole ticks of `tick` substeps).  Returns a list of dicts
+    (index, arrival time, n_target, horizon steps); served_request() builds the
+    scene when the request is admitted."""
+    rng = np.random.default_rng([seed, 1 << 21])
+    t = 0.0
+    out = []
+    for i in range(n_requests):
+        t += rng.exponential(1.0 / rate)
+        n = int(round(math.exp(rng.uniform(math.log(n_range[0]), math.log(n_range[1])))))
+        h = max(tick, int(round(rng.uniform(*horizon_s) / dt / tick)) * tick)
+        out.append(dict(index=i, arrival=t, n_target=n, horizon=h, seed=seed, tick=tick))
+    return out
 
 
 def batch_sizes(seed=4, n_scenes=256, median=40000, sigma=0.7, lo=5000, hi=200000):
