@@ -73,8 +73,16 @@ struct tlmpm_scene {
     int rsb;       // slot table of the pending re-scatter
     bool f_pending; // host copy of the device flag D.ctr[1]
     int in_batch = 0; // member of a live batch: single-scene calls are refused
+    hipStream_t st2 = nullptr; // mixed-brick kernels beside the uniform ones
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     std::vector<int> active_host;
     Timing prof;
+    ~tlmpm_scene()
+    {
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_join) (void)hipEventDestroy(ev_join);
+        if (st2) (void)hipStreamDestroy(st2);
+    }
 };
 
 // Brackets one launch with events when timing is on.
@@ -112,6 +120,9 @@ static TlLaunch single_launch(const tlmpm_scene* sc)
     L.D = &sc->D;
     L.any_material = sc->K.material_contact;
     L.st = sc->st;
+    L.st2 = sc->st2;
+    L.ev_fork = sc->ev_fork;
+    L.ev_join = sc->ev_join;
     return L;
 }
 
@@ -154,7 +165,7 @@ Dims dims_of(const tlmpm_scene_desc* d)
 
 struct Offsets {
     size_t X, u, v, H, code, code_prev, D, perm, E, m, V0, cell_start, active, cnt0, cnt1, sc0, sc1, p2g, rs, hist,
-        aabb, wpart, wacc, Jmat, Jrig, brig, bmixed, tools, tinfo, ctr, bact, status, dirty, bdirty, pcell, cand_idx, cmask, cstatic, bcand, hbin, bcount, bids, cslot, brec, htab, hnext, orec, ph_n, ph_q, ph_u,
+        aabb, wpart, wacc, Jmat, Jrig, brig, bmixed, ccode, tools, tinfo, ctr, bact, status, dirty, bdirty, pcell, cand_idx, coff, gcand, cmask, cstatic, bcand, hbin, hmax, bcount, bids, cslot, brec, htab, hnext, orec, ph_n, ph_q, ph_u,
         total;
     uint32_t hmask;
 };
@@ -227,6 +238,7 @@ Offsets plan(const tlmpm_scene_desc* d, long long n_active)
     o.Jrig = L.take(3 * N * f);
     o.brig = L.take((size_t)g.n_bricks * 4);
     o.bmixed = L.take((size_t)g.n_bricks * 4);
+    o.ccode = L.take((size_t)g.n_bricks * TL_CELLS * 4);
     o.tools = L.take(TL_MAX_TOOLS * sizeof(DevTool));
     o.tinfo = L.take(4 * 4);
     o.ctr = L.take(4 * 4);
@@ -237,7 +249,10 @@ Offsets plan(const tlmpm_scene_desc* d, long long n_active)
         o.cstatic = L.take(cells);
         o.bcand = L.take((size_t)g.n_bricks * 4);
         o.cand_idx = L.take(N * 4);
+        o.coff = L.take(((size_t)n_active + 1) * 4);
+        o.gcand = L.take(N * 4);
         o.hbin = L.take(4);
+        o.hmax = L.take(4);
         size_t buckets = 4096;
         while (buckets < N / 2) buckets <<= 1;
         o.hmask = (uint32_t)(buckets - 1);
@@ -367,6 +382,12 @@ extern "C" tlmpm_status tlmpm_create_scene(const tlmpm_scene_desc* d, void* ws, 
     tlmpm_scene* sc = new tlmpm_scene();
     sc->st = (hipStream_t)hip_stream;
     sc->prof.st = sc->st;
+    if (hipStreamCreateWithFlags(&sc->st2, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&sc->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&sc->ev_join, hipEventDisableTiming) != hipSuccess) {
+        delete sc;
+        return fail(TLMPM_E_DEVICE, "stream or event creation failed");
+    }
     sc->max_cuts = d->max_cuts;
     sc->n_bricks = (int)g.n_bricks;
     sc->cur = 0;
@@ -419,6 +440,7 @@ extern "C" tlmpm_status tlmpm_create_scene(const tlmpm_scene_desc* d, void* ws, 
     K.single_field = d->single_field;
     K.material_contact = d->material_contact;
     K.scap = slot_cap(d);
+    K.pair_blocks = (int)std::min<long long>(4096, std::max<long long>(1, N / 128));
     float vmax0 = d->vol0_uniform;
     if (d->vol0)
         for (long long p = 0; p < N; p++) vmax0 = std::max(vmax0, d->vol0[p]);
@@ -455,6 +477,7 @@ extern "C" tlmpm_status tlmpm_create_scene(const tlmpm_scene_desc* d, void* ws, 
     D.Jrig = (float*)(base + o.Jrig);
     D.brig = (int*)(base + o.brig);
     D.bmixed = (int*)(base + o.bmixed);
+    D.ccode = (uint32_t*)(base + o.ccode);
     D.tools = (DevTool*)(base + o.tools);
     D.tinfo = (int*)(base + o.tinfo);
     D.bact = (int*)(base + o.bact);
@@ -464,7 +487,10 @@ extern "C" tlmpm_status tlmpm_create_scene(const tlmpm_scene_desc* d, void* ws, 
         D.cstatic = (uint8_t*)(base + o.cstatic);
         D.bcand = (int*)(base + o.bcand);
         D.cand_idx = (int*)(base + o.cand_idx);
+        D.coff = (int*)(base + o.coff);
+        D.gcand = (int*)(base + o.gcand);
         D.hbin = (float*)(base + o.hbin);
+        D.hmax = (int*)(base + o.hmax);
         D.hmask = o.hmask;
         D.bcount = (int*)(base + o.bcount);
         D.bids = (int*)(base + o.bids);
@@ -532,6 +558,7 @@ extern "C" tlmpm_status tlmpm_create_scene(const tlmpm_scene_desc* d, void* ws, 
     // empty history), no F update pending
     if ((e = tl_launch_fill_i32(D.ctr, 1, 1, sc->st)) != hipSuccess) return bail(e, "counters");
     const TlLaunch L = single_launch(sc);
+    if ((e = tl_launch_mixed(&L, 1)) != hipSuccess) return bail(e, "cell summaries");
     if ((e = tl_launch_slots(&L, 0, 0, 1)) != hipSuccess) return bail(e, "slot table");
     if ((e = tl_launch_aabb(&L)) != hipSuccess) return bail(e, "aabb");
     if (d->material_contact) {
@@ -1005,6 +1032,7 @@ void scene_items(const tlmpm_scene* sc, int n[TL_ITEM_KINDS])
     n[IT_WRENCH] = TL_MAX_TOOLS * 6;
     n[IT_PART] = ceil_div(K.N, 256);
     n[IT_BFLAG] = ceil_div(n_bricks, 256);
+    n[IT_PAIR] = K.material_contact ? K.pair_blocks : 0;
 }
 
 tlmpm_status batch_plan(tlmpm_scene* const* scenes, int n, BatchPlan& P)
@@ -1051,7 +1079,18 @@ struct tlmpm_batch {
     BatchTools* h_tools = nullptr; // pinned staging of the per-call tools
     double* h_wacc = nullptr;
     hipEvent_t up_done = nullptr;  // the last upload from h_tools finished
+    hipStream_t st2 = nullptr;     // mixed-brick kernels beside the uniform ones
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     Timing prof;
+    ~tlmpm_batch()
+    {
+        if (h_tools) (void)hipHostFree(h_tools);
+        if (h_wacc) (void)hipHostFree(h_wacc);
+        if (up_done) (void)hipEventDestroy(up_done);
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_join) (void)hipEventDestroy(ev_join);
+        if (st2) (void)hipStreamDestroy(st2);
+    }
     int cur, rsb;
     bool pending;
 };
@@ -1133,9 +1172,6 @@ extern "C" tlmpm_status tlmpm_batch_create(tlmpm_scene* const* scenes, int32_t n
             for (int i = 0; i < c[k]; i++) items[k].push_back(make_int2(s, i));
     }
     auto bail = [&](hipError_t e, const char* what) {
-        if (b->h_tools) (void)hipHostFree(b->h_tools);
-        if (b->h_wacc) (void)hipHostFree(b->h_wacc);
-        if (b->up_done) (void)hipEventDestroy(b->up_done);
         delete b;
         return fail(TLMPM_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
     };
@@ -1160,6 +1196,12 @@ extern "C" tlmpm_status tlmpm_batch_create(tlmpm_scene* const* scenes, int32_t n
         hipSuccess)
         return bail(e, "pinned staging");
     if ((e = hipEventCreateWithFlags(&b->up_done, hipEventDisableTiming)) != hipSuccess) return bail(e, "event");
+    if ((e = hipStreamCreateWithFlags(&b->st2, hipStreamNonBlocking)) != hipSuccess) return bail(e, "stream");
+    if ((e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming)) != hipSuccess) return bail(e, "event");
+    if ((e = hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming)) != hipSuccess) return bail(e, "event");
+    L.st2 = b->st2;
+    L.ev_fork = b->ev_fork;
+    L.ev_join = b->ev_join;
     if ((e = hipStreamSynchronize(b->st)) != hipSuccess) return bail(e, "create batch");
     for (tlmpm_scene* sc : b->sc) sc->in_batch = 1;
     *out = b;
@@ -1171,9 +1213,6 @@ extern "C" tlmpm_status tlmpm_batch_destroy(tlmpm_batch* b)
     if (!b) return fail(TLMPM_E_INVALID, "null batch");
     hipError_t e = hipStreamSynchronize(b->st);
     for (tlmpm_scene* sc : b->sc) sc->in_batch = 0;
-    (void)hipHostFree(b->h_tools);
-    (void)hipHostFree(b->h_wacc);
-    (void)hipEventDestroy(b->up_done);
     delete b;
     if (e != hipSuccess) return fail(TLMPM_E_DEVICE, std::string("destroy batch: ") + hipGetErrorString(e));
     return TLMPM_OK;

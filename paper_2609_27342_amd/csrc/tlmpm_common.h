@@ -32,7 +32,11 @@
 #define TL_ST_LOOKUP 8
 #define TL_ST_CONTACT 16
 
-#define TL_PCAP 12             // persistent pair springs kept per particle
+#define TL_CC_EMPTY 0xFFFFFFFEu // cell summary: no particle
+#define TL_CC_MIXED 0xFFFFFFFFu // cell summary: particles of two or more slot keys
+#define TL_PCAP 16             // persistent pair springs kept per particle (all its partners)
+#define TL_PLANES 8            // lanes per candidate in the pair search
+#define TL_PCAND 32            // candidates per pair-search block (256 threads)
 #define TL_BCAP 8              // candidate records stored inline per hash bucket
 
 // tool flags (same values as the ABI)
@@ -79,6 +83,7 @@ struct SceneK {
     int single_field;
     int material_contact;
     int scap;         // slot capacity per node (<= TL_SCAP_MAX)
+    int pair_blocks;  // blocks of the pair search (grid-stride over the candidates)
     double dt_d;
 };
 
@@ -105,12 +110,13 @@ struct SceneD {
     int* bact;     // [bricks] active index of a brick, -1 if it holds no particle
     float* hist;   // rigid contact history [TL_MAX_TOOLS+1][4][N]: u_t xyz, stamp
     float* aabb;   // [n_bricks][8]: min xyz, max xyz, max |v|, 0
-    float* wpart;  // [n_active][TL_MAX_TOOLS][6]
+    float* wpart;  // [TL_MAX_TOOLS * 6][n_active] per-brick wrench sums
     double* wacc;  // [TL_MAX_TOOLS][6]
     float* Jmat;   // [3][N] material contact impulse (candidates only)
     float* Jrig;   // [3][N] floor and tool impulse (bricks with brig set)
     int* brig;     // [bricks] the brick was within reach of a rigid body this substep
     int* bmixed;   // [bricks] a cell of the brick holds two side codes
+    uint32_t* ccode; // [bricks * 64] (sorted cell order) the one slot key of a cell, or TL_CC_*
     DevTool* tools;   // [TL_MAX_TOOLS] tools (or label-only blades) of the current call
     int* tinfo;       // [4] per call: number of tools, any tool with contact, new cut, unused
     int* ctr;         // [4] persistent: contact-history stamp, F update pending, unused x2
@@ -121,9 +127,12 @@ struct SceneD {
     // material contact
     uint32_t* cmask;    // [cells] OR of the codes of each cell (sorted cell order)
     uint8_t* cstatic;   // [cells] cell has an empty or out-of-grid neighbour
-    int* bcand;         // [bricks] number of candidates of the brick
+    int* bcand;         // [active bricks] number of candidates of the brick
     int* cand_idx;      // [N] candidates of each brick, stored over the brick's particle range
+    int* coff;          // [active bricks + 1] first global candidate index of each active brick
+    int* gcand;         // [N] all candidates, brick by brick (rewritten by each binning pass)
     float* hbin;        // bin edge (device scalar)
+    int* hmax;          // largest brick speed bound, float bits (device scalar)
     uint32_t hmask;     // buckets - 1 (power of two)
     int* bcount;        // [buckets] entries of each bucket this substep (cleared per substep)
     int* bids;          // [buckets][TL_BCAP] particle ids in arrival order
@@ -134,12 +143,12 @@ struct SceneD {
     float4* orec;       // [N][3] records of overflowing candidates
     int* ph_n;          // [2][N] stamp << 8 | count of owned springs
     int* ph_q;          // [2][N][TL_PCAP] partner of each spring
-    float* ph_u;        // [2][N][TL_PCAP][3] spring, oriented for the owner
+    float* ph_u;        // [2][N][TL_PCAP][3] spring, oriented for the pair's lower index
 };
 
 // Launch context: one scene (parameters by value) or a batch of scenes (device
 // arrays of SceneK / SceneD and, per kind of work item, a list of (scene, block)).
-enum { IT_BRICK = 0, IT_NODE, IT_CELL, IT_BUCKET, IT_SCENE, IT_WRENCH, IT_PART, IT_BFLAG, TL_ITEM_KINDS };
+enum { IT_BRICK = 0, IT_NODE, IT_CELL, IT_BUCKET, IT_SCENE, IT_WRENCH, IT_PART, IT_BFLAG, IT_PAIR, TL_ITEM_KINDS };
 
 struct TlLaunch {
     const SceneK* S;   // single scene (host copies), or null in batch mode
@@ -150,4 +159,8 @@ struct TlLaunch {
     int n_items[TL_ITEM_KINDS];
     int any_material;  // some scene has material contact
     hipStream_t st;
+    // optional second stream for the mixed-brick variants, which then run beside
+    // the uniform-brick ones (fork / join events; null: one stream)
+    hipStream_t st2;
+    hipEvent_t ev_fork, ev_join;
 };

@@ -6,15 +6,17 @@
 // cell iff (s1_p & OR s2) | (s2_p & OR s1) != 0.
 //
 // Pairs are found in the current configuration: candidates are hashed into bins
-// of edge h >= every contact reach (R_p + R_q + dt |v_p - v_q|); each hash bucket
-// is a list built with 64-bit compare-and-swap on (generation, head), so the table
-// is never cleared.  A pair is evaluated by both particles with the same operands
+// of edge h >= every contact reach (R_p + R_q + dt |v_p - v_q|); a hash bucket
+// holds up to TL_BCAP inline records, placed by rank of particle index, and an
+// overflow list built with 64-bit compare-and-swap on (generation, head), so the
+// table is never cleared.  A pair is evaluated by both particles with the same operands
 // (the lower sorted index first), so the two impulses are exact negatives; each
-// particle sorts its contacts by partner index before summing, which makes the
-// result independent of the list order.  The tangential spring of a pair is kept
-// by its lower index in a per-particle list (double buffered, stamped by substep).
+// particle sums its contacts in a fixed order (bins, then ranks in the bin), which
+// makes the result independent of arrival order.  The tangential spring of a pair
+// is kept in both particles' lists (double buffered, stamped by substep).
 #include <hip/hip_runtime.h>
 #include <math.h>
+#include <limits.h>
 #include <stdint.h>
 
 #include "tlmpm_common.h"
@@ -145,26 +147,29 @@ DEV void cand_body(const SceneK& S, const SceneD& D, int bi, int force)
         base += tot;
         __syncthreads();
     }
-    if (threadIdx.x == 0) D.bcand[brick] = base;
+    if (threadIdx.x == 0) D.bcand[bi] = base;
 }
 
 // bin edge from the largest speed of any brick (conservative reach)
-DEV void hsize_body(const SceneK& S, const SceneD& D, int bi)
+// largest particle speed bound of the bricks (block bi covers bricks
+// [256 bi, 256 bi + 256)); the maximum of non-negative floats is taken on their
+// bit patterns, so the result does not depend on the order of the atomics
+DEV void hmax_body(const SceneK& S, const SceneD& D, int bi)
 {
     if (!S.material_contact) return;
-    __shared__ float s[256];
-    float m = 0.0f;
-    for (int b = threadIdx.x; b < D.n_active; b += blockDim.x) m = fmaxf(m, D.aabb[(long long)D.active[b] * 8 + 6]);
-    s[threadIdx.x] = m;
-    __syncthreads();
-    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) s[threadIdx.x] = fmaxf(s[threadIdx.x], s[threadIdx.x + o]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        float h = (2.0f * S.Rmax + 2.0f * S.dt * s[0]) * 1.001f + 1e-7f;
-        D.hbin[0] = fmaxf(h, 0.25f * (float)S.dx);
-    }
+    const long long b = (long long)bi * blockDim.x + threadIdx.x;
+    const long long nb = (long long)S.cbx * S.cby * S.cbz;
+    float m = b < nb ? D.aabb[b * 8 + 6] : 0.0f;
+    for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0 && m > 0.0f) atomicMax(D.hmax, __float_as_int(m));
+}
+
+// bin edge from the largest speed (conservative reach of every pair)
+DEV float bin_edge(const SceneK& S, const SceneD& D)
+{
+    const float vmax = __int_as_float(*D.hmax);
+    const float h = (2.0f * S.Rmax + 2.0f * S.dt * vmax) * 1.001f + 1e-7f;
+    return fmaxf(h, 0.25f * (float)S.dx);
 }
 
 DEV void bin_of(const float x[3], float inv_h, int b[3])
@@ -174,7 +179,11 @@ DEV void bin_of(const float x[3], float inv_h, int b[3])
 
 DEV uint32_t bin_hash(int i, int j, int k, uint32_t mask)
 {
-    return (((uint32_t)i * 73856093u) ^ ((uint32_t)j * 19349663u) ^ ((uint32_t)k * 83492791u)) & mask;
+    // 4x4x4 blocks of bins share 64 consecutive buckets, so the 27 bins around a
+    // particle touch few cache lines; the block coordinates are hashed
+    const uint32_t hb = ((uint32_t)(i >> 2) * 73856093u) ^ ((uint32_t)(j >> 2) * 19349663u) ^
+                        ((uint32_t)(k >> 2) * 83492791u);
+    return ((hb << 6) | (uint32_t)((i & 3) | ((j & 3) << 2) | ((k & 3) << 4))) & mask;
 }
 
 DEV void cur_pos(const SceneK& S, const SceneD& D, long long p, float x[3])
@@ -206,6 +215,7 @@ DEV void bzero_body(const SceneK& S, const SceneD& D, int bi)
     if (!S.material_contact) return;
     long long i = (long long)bi * blockDim.x + threadIdx.x;
     if (i <= (long long)D.hmask) D.bcount[i] = 0;
+    if (i == 0) *D.hmax = 0;
 }
 
 DEV void bin_insert_body(const SceneK& S, const SceneD& D, int bi)
@@ -213,12 +223,16 @@ DEV void bin_insert_body(const SceneK& S, const SceneD& D, int bi)
     if (!S.material_contact) return;
     const unsigned gen = (unsigned)D.ctr[0];
     const int brick = D.active[bi];
-    const int nc = D.bcand[brick];
+    const float hb = bin_edge(S, D);
+    if (bi == 0 && threadIdx.x == 0) D.hbin[0] = hb; // for the ranking and pair passes
+    const int nc = D.bcand[bi];
     if (!nc) return;
-    const float inv_h = 1.0f / D.hbin[0];
+    const float inv_h = 1.0f / hb;
     const int beg = D.cell_start[(long long)brick * TL_CELLS];
+    const int g0 = D.coff[bi];
     for (int c = threadIdx.x; c < nc; c += blockDim.x) {
         const int p = D.cand_idx[beg + c];
+        D.gcand[g0 + c] = p;
         float x[3];
         cur_pos(S, D, p, x);
         int b[3];
@@ -254,7 +268,7 @@ DEV void bin_rank_body(const SceneK& S, const SceneD& D, int bi)
 {
     if (!S.material_contact) return;
     const int brick = D.active[bi];
-    const int nc = D.bcand[brick];
+    const int nc = D.bcand[bi];
     if (!nc) return;
     const float inv_h = 1.0f / D.hbin[0];
     const int beg = D.cell_start[(long long)brick * TL_CELLS];
@@ -365,11 +379,15 @@ DEV void ref_cell(const SceneK& S, const SceneD& D, long long p, int c[3])
     slot_cell(S, D.pcell[p], c[0], c[1], c[2]);
 }
 
-// Pair search and impulses.  32 lanes per candidate: lane d < 27 scans neighbour
-// bin d (records in particle-index order, then the bucket's overflow list) and sums
-// its contacts; the 27 lane sums are added by a fixed shuffle tree.  The owner of a
-// pair (lower sorted index) appends the new spring to its list; the list is only
-// searched by partner, so its order does not matter.
+// Pair search and impulses over all candidates of the scene (grid-stride over the
+// global candidate list).  TL_PLANES lanes per candidate: lane l scans neighbour
+// bins l, l + 8, l + 16, l + 24 (of 27; records in particle-index order, then the
+// bucket's overflow list) and sums its contacts; the lane sums are added by a fixed
+// shuffle tree.  The tangential spring of a pair is kept by both particles (each
+// in its own list, oriented for the pair's lower index): both sides evaluate the
+// pair with the same operands, so the two copies stay equal and no particle reads
+// its partner's list.  A list is only searched by partner, so its order does not
+// matter.
 DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
 {
     if (!S.material_contact) return;
@@ -377,24 +395,39 @@ DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
     const int stamp = D.ctr[0];
     const unsigned gen = (unsigned)stamp;
     const int hnew = stamp & 1, hold = hnew ^ 1;
-    __shared__ int s_nown[8];
-    const int brick = D.active[bi];
-    const int ncand = D.bcand[brick];
-    if (!ncand) return;
+    __shared__ int s_q[TL_PCAND][TL_PCAP];
+    __shared__ float s_u[TL_PCAND][TL_PCAP][3];
+    __shared__ int s_nold[TL_PCAND], s_nnew[TL_PCAND];
+    const int total = D.coff[D.n_active];
     const float inv_h = 1.0f / D.hbin[0];
     const long long N = S.N;
-    const int beg = D.cell_start[(long long)brick * TL_CELLS];
-    const int sub = threadIdx.x >> 5; // candidate slot of this lane group (8 per block)
-    const int d = threadIdx.x & 31;  // neighbour bin handled by this lane
-    for (int c0 = 0; c0 < ncand; c0 += 8) {
-        const int ci = c0 + sub;
-        const bool has = ci < ncand;
-        if (d == 0) s_nown[sub] = 0;
+    const int sub = threadIdx.x / TL_PLANES; // candidate of this lane group
+    const int l = threadIdx.x % TL_PLANES;   // lane in the group
+    const int stride = S.pair_blocks * TL_PCAND;
+    for (int c0 = bi * TL_PCAND; c0 < total; c0 += stride) {
+        const int g = c0 + sub;
+        const bool has = g < total;
+        const int p = has ? D.gcand[g] : -1;
+        // the candidate's springs of the last substep, staged in LDS
+        int nold = 0;
+        if (has) {
+            const int hdr = D.ph_n[(long long)hold * N + p];
+            if ((hdr >> 8) == stamp - 1) nold = min(hdr & 0xFF, TL_PCAP);
+        }
+        for (int k = l; k < nold; k += TL_PLANES) {
+            const long long e = (long long)hold * N * TL_PCAP + (long long)p * TL_PCAP + k;
+            s_q[sub][k] = D.ph_q[e];
+            s_u[sub][k][0] = D.ph_u[e * 3 + 0];
+            s_u[sub][k][1] = D.ph_u[e * 3 + 1];
+            s_u[sub][k][2] = D.ph_u[e * 3 + 2];
+        }
+        if (l == 0) {
+            s_nold[sub] = nold;
+            s_nnew[sub] = 0;
+        }
         __syncthreads();
         float Jt[3] = {0.0f, 0.0f, 0.0f};
-        int p = -1;
-        if (has) p = D.cand_idx[beg + ci];
-        if (has && d < 27) {
+        if (has) {
             const uint32_t kp = ckey(S, D.code[p]);
             PState sp = load_pstate(S, D, p);
             int cp[3];
@@ -403,7 +436,7 @@ DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
             bin_of(sp.x, inv_h, b);
             int* ql_new = D.ph_q + ((long long)hnew * N + p) * TL_PCAP;
             float* ul_new = D.ph_u + ((long long)hnew * N + p) * TL_PCAP * 3;
-            const int bb[3] = {b[0] + d % 3 - 1, b[1] + (d / 3) % 3 - 1, b[2] + d / 9 - 1};
+            int bb[3];
             auto visit = [&](const float4 rec[3]) {
                 const int q = __float_as_int(rec[0].x);
                 if (q == p) return;
@@ -417,22 +450,15 @@ DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
                 bin_of(sq.x, inv_h, bq);
                 if (bq[0] != bb[0] || bq[1] != bb[1] || bq[2] != bb[2]) return; // hash collision
                 const bool own = p < q;
-                const int o = own ? p : q, r = own ? q : p;
-                // owner's old spring for this partner
+                // the pair's spring of the last substep
                 float u[3] = {0.0f, 0.0f, 0.0f};
-                int hdr = D.ph_n[(long long)hold * N + o];
-                if ((hdr >> 8) == stamp - 1) {
-                    int cnt = hdr & 0xFF;
-                    const int* ql = D.ph_q + ((long long)hold * N + o) * TL_PCAP;
-                    for (int k = 0; k < cnt; k++)
-                        if (ql[k] == r) {
-                            const float* ul = D.ph_u + (((long long)hold * N + o) * TL_PCAP + k) * 3;
-                            u[0] = ul[0];
-                            u[1] = ul[1];
-                            u[2] = ul[2];
-                            break;
-                        }
-                }
+                for (int k = 0; k < s_nold[sub]; k++)
+                    if (s_q[sub][k] == q) {
+                        u[0] = s_u[sub][k][0];
+                        u[1] = s_u[sub][k][1];
+                        u[2] = s_u[sub][k][2];
+                        break;
+                    }
                 float J[3];
                 bool hit = own ? pair_impulse(S, sp, sq, u, J) : pair_impulse(S, sq, sp, u, J);
                 if (!hit) return;
@@ -440,48 +466,94 @@ DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
                 Jt[0] += sg * J[0];
                 Jt[1] += sg * J[1];
                 Jt[2] += sg * J[2];
-                if (own) {
-                    int k = atomicAdd(&s_nown[sub], 1);
-                    if (k < TL_PCAP) {
-                        ql_new[k] = q;
-                        ul_new[k * 3 + 0] = u[0];
-                        ul_new[k * 3 + 1] = u[1];
-                        ul_new[k * 3 + 2] = u[2];
-                    } else {
-                        atomicOr(D.status, TL_ST_CONTACT);
-                    }
+                int k = atomicAdd(&s_nnew[sub], 1);
+                if (k < TL_PCAP) {
+                    ql_new[k] = q;
+                    ul_new[k * 3 + 0] = u[0];
+                    ul_new[k * 3 + 1] = u[1];
+                    ul_new[k * 3 + 2] = u[2];
+                } else {
+                    atomicOr(D.status, TL_ST_CONTACT);
                 }
             };
-            uint32_t h = bin_hash(bb[0], bb[1], bb[2], D.hmask);
-            const int cnt = D.bcount[h];
-            const int inl = cnt < TL_BCAP ? cnt : TL_BCAP;
-            for (int k = 0; k < inl; k++) {
-                const float4* src = D.brec + ((long long)h * TL_BCAP + k) * 3;
-                float4 rec[3] = {src[0], src[1], src[2]};
-                visit(rec);
-            }
-            if (cnt > TL_BCAP) {
-                unsigned long long e = D.htab[h];
-                if ((unsigned)(e >> 32) == gen)
-                    for (int q = (int)(e & 0xFFFFFFFFull); q >= 0; q = D.hnext[q]) {
-                        const float4* src = D.orec + (long long)q * 3;
-                        float4 rec[3] = {src[0], src[1], src[2]};
-                        visit(rec);
+            for (int d = l; d < 27; d += TL_PLANES) {
+                bb[0] = b[0] + d % 3 - 1;
+                bb[1] = b[1] + (d / 3) % 3 - 1;
+                bb[2] = b[2] + d / 9 - 1;
+                uint32_t h = bin_hash(bb[0], bb[1], bb[2], D.hmask);
+                const int cnt = D.bcount[h];
+                const int inl = cnt < TL_BCAP ? cnt : TL_BCAP;
+                for (int k = 0; k < inl; k++) {
+                    const float4* src = D.brec + ((long long)h * TL_BCAP + k) * 3;
+                    float4 rec[3] = {src[0], src[1], src[2]};
+                    visit(rec);
+                }
+                if (cnt > TL_BCAP) {
+                    // overflow list (rare): visited in increasing particle index
+                    unsigned long long e = D.htab[h];
+                    if ((unsigned)(e >> 32) == gen) {
+                        const int head = (int)(e & 0xFFFFFFFFull);
+                        int last = -1;
+                        while (true) {
+                            int best = INT_MAX;
+                            for (int q = head; q >= 0; q = D.hnext[q])
+                                if (q > last && q < best) best = q;
+                            if (best == INT_MAX) break;
+                            const float4* src = D.orec + (long long)best * 3;
+                            float4 rec[3] = {src[0], src[1], src[2]};
+                            visit(rec);
+                            last = best;
+                        }
                     }
+                }
             }
         }
-        // fixed-order sum over the 32 lanes of the group
+        // fixed-order sum over the lanes of the group
         for (int a = 0; a < 3; a++)
-            for (int o = 16; o >= 1; o >>= 1) Jt[a] += __shfl_xor(Jt[a], o, 64);
+            for (int o = TL_PLANES / 2; o >= 1; o >>= 1) Jt[a] += __shfl_xor(Jt[a], o, 64);
         __syncthreads();
-        if (has && d == 0) {
-            int nown = s_nown[sub];
-            D.ph_n[(long long)hnew * N + p] = (stamp << 8) | (nown < TL_PCAP ? nown : TL_PCAP);
+        if (has && l == 0) {
+            const int nn = s_nnew[sub];
+            D.ph_n[(long long)hnew * N + p] = (stamp << 8) | (nn < TL_PCAP ? nn : TL_PCAP);
             D.Jmat[p] = Jt[0];
             D.Jmat[N + p] = Jt[1];
             D.Jmat[2 * N + p] = Jt[2];
         }
     }
+}
+
+// First global candidate index of every active brick (exclusive scan of the
+// candidate counts in active-brick order), one block of TL_SCAN_T threads per
+// scene; each thread scans a contiguous run of bricks.
+#define TL_SCAN_T 1024
+DEV void cscan_body(const SceneK& S, const SceneD& D, int bi)
+{
+    if (!S.material_contact) return;
+    __shared__ int s_w[TL_SCAN_T / 64];
+    const int n = D.n_active;
+    const int per = (n + TL_SCAN_T - 1) / TL_SCAN_T;
+    const int i0 = threadIdx.x * per, i1 = min(n, i0 + per);
+    int loc = 0;
+#pragma unroll 8
+    for (int i = i0; i < i1; i++) loc += D.bcand[i];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int incl = loc;
+    for (int o = 1; o < 64; o <<= 1) {
+        int t = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += t;
+    }
+    if (lane == 63) s_w[wv] = incl;
+    __syncthreads();
+    int before = 0;
+    for (int w = 0; w < wv; w++) before += s_w[w];
+    int run = before + incl - loc;
+#pragma unroll 8
+    for (int i = i0; i < i1; i++) {
+        const int c = D.bcand[i];
+        D.coff[i] = run;
+        run += c;
+    }
+    if (threadIdx.x == TL_SCAN_T - 1) D.coff[n] = run;
 }
 
 #define TL_WRAP(NAME, PARAMS, ARGS)                                                                           \
@@ -499,23 +571,36 @@ DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
 #define TL_COMMA ,
 TL_WRAP(cellmask, TL_COMMA int with_static TL_COMMA int force, TL_COMMA with_static TL_COMMA force)
 TL_WRAP(cand, TL_COMMA int force, TL_COMMA force)
-TL_WRAP(hsize, , )
+TL_WRAP(hmax, , )
 TL_WRAP(bzero, , )
 TL_WRAP(bin_insert, , )
 TL_WRAP(bin_rank, , )
 TL_WRAP(pairs, , )
+__global__ __launch_bounds__(TL_SCAN_T) void k_cscan(SceneK S, SceneD D) { cscan_body(S, D, 0); }
+__global__ __launch_bounds__(TL_SCAN_T) void k_cscan_b(const SceneK* __restrict__ Ks, const SceneD* __restrict__ Ds,
+                                                       const int2* __restrict__ it)
+{
+    const int2 t = it[blockIdx.x];
+    cscan_body(Ks[t.x], Ds[t.x], t.y);
+}
+
+template <class KP, class KB, class... Args>
+static hipError_t tl_run_t(const TlLaunch& L, int kind, int plain_blocks, int threads, KP kp, KB kb, Args... args)
+{
+    if (L.S) {
+        if (plain_blocks <= 0) return hipSuccess;
+        hipLaunchKernelGGL(kp, dim3(plain_blocks), dim3(threads), 0, L.st, *L.S, *L.D, args...);
+    } else {
+        if (L.n_items[kind] <= 0) return hipSuccess;
+        hipLaunchKernelGGL(kb, dim3(L.n_items[kind]), dim3(threads), 0, L.st, L.Ks, L.Ds, L.items[kind], args...);
+    }
+    return hipGetLastError();
+}
 
 template <class KP, class KB, class... Args>
 static hipError_t tl_run(const TlLaunch& L, int kind, int plain_blocks, KP kp, KB kb, Args... args)
 {
-    if (L.S) {
-        if (plain_blocks <= 0) return hipSuccess;
-        hipLaunchKernelGGL(kp, dim3(plain_blocks), dim3(256), 0, L.st, *L.S, *L.D, args...);
-    } else {
-        if (L.n_items[kind] <= 0) return hipSuccess;
-        hipLaunchKernelGGL(kb, dim3(L.n_items[kind]), dim3(256), 0, L.st, L.Ks, L.Ds, L.items[kind], args...);
-    }
-    return hipGetLastError();
+    return tl_run_t(L, kind, plain_blocks, 256, kp, kb, args...);
 }
 
 extern "C" {
@@ -526,24 +611,28 @@ hipError_t tl_launch_cellmask(const TlLaunch* L, int with_static, int force)
     return tl_run(*L, IT_CELL, nb, k_cellmask, k_cellmask_b, with_static, force);
 }
 
+// candidate bits and lists, then the global candidate offsets
 hipError_t tl_launch_cand(const TlLaunch* L, int force)
 {
-    return tl_run(*L, IT_BRICK, L->S ? L->D->n_active : 0, k_cand, k_cand_b, force);
+    hipError_t e = tl_run(*L, IT_BRICK, L->S ? L->D->n_active : 0, k_cand, k_cand_b, force);
+    if (e != hipSuccess) return e;
+    return tl_run_t(*L, IT_SCENE, 1, TL_SCAN_T, k_cscan, k_cscan_b);
 }
 
-// one substep of pair search and impulses: bin size, bucket reset, binning, pairs
+// one substep of pair search and impulses: bucket reset, bin size, binning, pairs
 hipError_t tl_launch_contact(const TlLaunch* L)
 {
     const int nbrick = L->S ? L->D->n_active : 0;
     if (L->S && nbrick == 0) return hipSuccess;
-    hipError_t e = tl_run(*L, IT_SCENE, 1, k_hsize, k_hsize_b);
+    hipError_t e = tl_run(*L, IT_BUCKET, L->S ? (int)(((long long)L->D->hmask + 256) / 256) : 0, k_bzero, k_bzero_b);
     if (e != hipSuccess) return e;
-    e = tl_run(*L, IT_BUCKET, L->S ? (int)(((long long)L->D->hmask + 256) / 256) : 0, k_bzero, k_bzero_b);
+    const long long nbr = L->S ? (long long)L->S->cbx * L->S->cby * L->S->cbz : 0;
+    e = tl_run(*L, IT_BFLAG, (int)((nbr + 255) / 256), k_hmax, k_hmax_b);
     if (e != hipSuccess) return e;
     e = tl_run(*L, IT_BRICK, nbrick, k_bin_insert, k_bin_insert_b);
     if (e != hipSuccess) return e;
     e = tl_run(*L, IT_BRICK, nbrick, k_bin_rank, k_bin_rank_b);
     if (e != hipSuccess) return e;
-    return tl_run(*L, IT_BRICK, nbrick, k_pairs, k_pairs_b);
+    return tl_run(*L, IT_PAIR, L->S ? L->S->pair_blocks : 0, k_pairs, k_pairs_b);
 }
 }

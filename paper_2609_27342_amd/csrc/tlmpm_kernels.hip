@@ -135,14 +135,24 @@ struct QPad {
 
 // Sums of all slots of box node bn over the bricks that contributed to it, in
 // fixed contributor order, written to dst[slot * Q + c].
+// Active indices of the 27 bricks around (bx, by, bz) (-1: none), by threads
+// [TL_BOXN, TL_BOXN + 27) of the block; read after the next barrier.
+DEV void load_neighbours(const SceneK& S, const SceneD& D, int bx, int by, int bz, int* nb)
+{
+    const int t = (int)threadIdx.x - TL_BOXN;
+    if (t < 0 || t >= 27) return;
+    const int x = bx + t % 3 - 1, y = by + (t / 3) % 3 - 1, z = bz + t / 9 - 1;
+    nb[t] = (x < 0 || y < 0 || z < 0 || x >= S.cbx || y >= S.cby || z >= S.cbz)
+                ? -1
+                : D.bact[((long long)z * S.cby + y) * S.cbx + x];
+}
+
 template <int Q>
-DEV void gather_node(const SceneK& S, const SceneD& D, const float* __restrict__ part, const BoxTab& T, int bn, int bx,
-                     int by, int bz, float* dst)
+DEV void gather_node(const SceneK& S, const int* nb, const float* __restrict__ part, const BoxTab& T, int bn, float* dst)
 {
     constexpr int QP = QPad<Q>::value;
     const int c = T.cnt[bn], b0 = T.base[bn];
     const int X = bn % 5, Y = (bn / 5) % 5, Z = bn / 25;
-    const int hx = bx + (X >> 2), hy = by + (Y >> 2), hz = bz + (Z >> 2);
     const int lx = X & 3, ly = Y & 3, lz = Z & 3;
     // contributor d: the brick at home - (d & 1, d >> 1 & 1, d >> 2 & 1), which
     // holds the node at box position (l + 4 * offset)
@@ -152,9 +162,8 @@ DEV void gather_node(const SceneK& S, const SceneD& D, const float* __restrict__
         int dx = d & 1, dy = (d >> 1) & 1, dz = (d >> 2) & 1;
         cbase[d] = 0;
         if ((dx && lx) || (dy && ly) || (dz && lz)) continue;
-        int cbx = hx - dx, cby = hy - dy, cbz = hz - dz;
-        if (cbx < 0 || cby < 0 || cbz < 0 || cbx >= S.cbx || cby >= S.cby || cbz >= S.cbz) continue;
-        const int ai = D.bact[((long long)cbz * S.cby + cby) * S.cbx + cbx];
+        // brick offset from this one: (X >> 2) - dx per axis, in -1..1
+        const int ai = nb[((Z >> 2) - dz + 1) * 9 + ((Y >> 2) - dy + 1) * 3 + ((X >> 2) - dx + 1)];
         if (ai < 0) continue;
         const int pn = (lx + 4 * dx) + 5 * (ly + 4 * dy) + 25 * (lz + 4 * dz);
         cbase[d] = (long long)ai * S.scap * TL_BOXN + pn;
@@ -689,7 +698,7 @@ DEV void rigid_body(const SceneK& S, const SceneD& D, int bi, KR_Args A)
         if (tid < n_tools * 6) {
             float acc = 0.0f;
             for (int w = 0; w < 4; w++) acc += s_wr[w][tid];
-            D.wpart[(long long)bi * (TL_MAX_TOOLS * 6) + tid] = acc;
+            D.wpart[(long long)tid * D.n_active + bi] = acc;
         }
     }
 }
@@ -703,6 +712,7 @@ DEV void p2g_body(const SceneK& S, const SceneD& D, int bi, KA_Args A)
     __shared__ float s_rsum[TL_BOX_SLOTS * 4];
     __shared__ float s_acc[TL_BOX_SLOTS * 7];
     __shared__ int s_total_r, s_total_c;
+    __shared__ int s_nb[27];
     __shared__ int s_rounds;
 
     const int brick = D.active[bi];
@@ -718,6 +728,7 @@ DEV void p2g_body(const SceneK& S, const SceneD& D, int bi, KA_Args A)
     // ---- phase 1: cell index, box counts, brick-vs-tool tests, round-0 particle loads
     Lane L = lane_of(D, brick);
     if (use_r) box_counts(S, D.cnt[A.rsb], bx, by, bz, Tr);
+    if (use_r) load_neighbours(S, D, bx, by, bz, s_nb);
     if (use_c) box_counts(S, D.cnt[A.cur], bx, by, bz, Tc);
     if (tid == 0) s_rounds = 0;
     // floor/tool impulses were computed for this brick by k_rigid
@@ -755,7 +766,7 @@ DEV void p2g_body(const SceneK& S, const SceneD& D, int bi, KA_Args A)
             box_codes(S, D.scode[A.rsb], Tr, tid);
             const int c = Tr.cnt[tid], b0 = Tr.base[tid];
             if (c > 0) {
-                gather_node<4>(S, D, D.rs, Tr, tid, bx, by, bz, s_rsum);
+                gather_node<4>(S, s_nb, D.rs, Tr, tid, s_rsum);
                 couple_node<4>(Tr, b0, c, s_rsum, 1, s_vt);
                 for (int a = 0; a < c; a++) {
                     float m = s_rsum[(b0 + a) * 4];
@@ -901,6 +912,7 @@ DEV void g2p_body(const SceneK& S, const SceneD& D, int bi, int cur)
     __shared__ float s_grid[TL_BOX_SLOTS * 6];
     __shared__ float s_acc[TL_BOX_SLOTS * 4];
     __shared__ int s_total;
+    __shared__ int s_nb[27];
     __shared__ int s_rounds;
     __shared__ float s_bb[8][7];
 
@@ -920,6 +932,7 @@ DEV void g2p_body(const SceneK& S, const SceneD& D, int bi, int cur)
     // ---- phase 1: cell index, box counts, round-0 particle loads
     Lane L = lane_of(D, brick);
     box_counts(S, D.cnt[cur], bx, by, bz, T);
+    load_neighbours(S, D, bx, by, bz, s_nb);
     if (tid == 0) s_rounds = 0;
     const int gxc = bx * TL_B + L.cxl, gyc = by * TL_B + L.cyl, gzc = bz * TL_B + L.czl;
     bool valid = L.j < L.count;
@@ -949,7 +962,7 @@ DEV void g2p_body(const SceneK& S, const SceneD& D, int bi, int cur)
         box_codes(S, D.scode[cur], T, tid);
         const int c = T.cnt[tid], b0 = T.base[tid];
         if (c > 0) {
-            gather_node<7>(S, D, D.p2g, T, tid, bx, by, bz, s_sum);
+            gather_node<7>(S, s_nb, D.p2g, T, tid, s_sum);
             float* gvn = s_grid;
             float* gdv = s_grid + TL_BOX_SLOTS * 3;
             couple_node<7>(T, b0, c, s_sum, 1, gvn);
@@ -1162,13 +1175,16 @@ DEV void slots_body(const SceneK& S, const SceneD& D, int bi, int dst, int src, 
     int lid = (int)(id & 63);
     int hx = (int)(nb % S.nbx), hy = (int)((nb / S.nbx) % S.nby), hz = (int)(nb / ((long long)S.nbx * S.nby));
     bool rebuild = force != 0;
-    if (!rebuild && *D.dirty) {
+    if (!rebuild) {
         // a node depends on the cells of bricks h - {0,1}^3
-        for (int d = 0; d < 8 && !rebuild; d++) {
+        int any = 0;
+#pragma unroll
+        for (int d = 0; d < 8; d++) {
             int bx = hx - (d & 1), by = hy - ((d >> 1) & 1), bz = hz - ((d >> 2) & 1);
             if (bx < 0 || by < 0 || bz < 0 || bx >= S.cbx || by >= S.cby || bz >= S.cbz) continue;
-            rebuild = D.bdirty[((long long)bz * S.cby + by) * S.cbx + bx] != 0;
+            any |= D.bdirty[((long long)bz * S.cby + by) * S.cbx + bx];
         }
+        rebuild = any != 0;
     }
     if (!rebuild) {
         if (dst != src) {
@@ -1182,31 +1198,43 @@ DEV void slots_body(const SceneK& S, const SceneD& D, int bi, int dst, int src, 
     uint32_t codes[TL_SCAP_MAX];
     int c = 0;
     bool over = false;
+    auto insert = [&](uint32_t k) {
+        int pos = 0;
+        while (pos < c && codes[pos] < k) pos++;
+        if (pos < c && codes[pos] == k) return;
+        if (c == S.scap) {
+            over = true;
+            return;
+        }
+        for (int q = c; q > pos; q--) codes[q] = codes[q - 1];
+        codes[pos] = k;
+        c++;
+    };
     if (gx <= S.cx && gy <= S.cy && gz <= S.cz) {
-        for (int dz = 0; dz < 2; dz++)
-            for (int dy = 0; dy < 2; dy++)
-                for (int dx = 0; dx < 2; dx++) {
-                    int x = gx - dx, y = gy - dy, z = gz - dz;
-                    if (x < 0 || y < 0 || z < 0 || x >= S.cx || y >= S.cy || z >= S.cz) continue;
-                    long long brick = ((long long)(z >> 2) * S.cby + (y >> 2)) * S.cbx + (x >> 2);
-                    int lx = x & 3, ly = y & 3, lz = z & 3;
-                    int w = (lx & 1) | ((ly & 1) << 1) | ((lz & 1) << 2);
-                    int i = (lx >> 1) | ((ly >> 1) << 1) | ((lz >> 1) << 2);
-                    const int* cs = D.cell_start + brick * TL_CELLS + w * 8 + i;
-                    for (int p = cs[0]; p < cs[1]; p++) {
-                        uint32_t k = slot_key(S, D.code[p]);
-                        int pos = 0;
-                        while (pos < c && codes[pos] < k) pos++;
-                        if (pos < c && codes[pos] == k) continue;
-                        if (c == S.scap) {
-                            over = true;
-                            continue;
-                        }
-                        for (int q = c; q > pos; q--) codes[q] = codes[q - 1];
-                        codes[pos] = k;
-                        c++;
-                    }
-                }
+        // the 8 incident cells: their one-key summaries, all loaded before use
+        long long cell[8];
+        uint32_t cc[8];
+#pragma unroll
+        for (int d = 0; d < 8; d++) {
+            int x = gx - (d & 1), y = gy - ((d >> 1) & 1), z = gz - ((d >> 2) & 1);
+            cell[d] = -1;
+            cc[d] = TL_CC_EMPTY;
+            if (x < 0 || y < 0 || z < 0 || x >= S.cx || y >= S.cy || z >= S.cz) continue;
+            long long brick = ((long long)(z >> 2) * S.cby + (y >> 2)) * S.cbx + (x >> 2);
+            int lx = x & 3, ly = y & 3, lz = z & 3;
+            int w = (lx & 1) | ((ly & 1) << 1) | ((lz & 1) << 2);
+            int i = (lx >> 1) | ((ly >> 1) << 1) | ((lz >> 1) << 2);
+            cell[d] = brick * TL_CELLS + w * 8 + i;
+            cc[d] = D.ccode[cell[d]];
+        }
+        for (int d = 0; d < 8; d++) {
+            if (cc[d] == TL_CC_EMPTY) continue;
+            if (cc[d] != TL_CC_MIXED) {
+                insert(cc[d]);
+                continue;
+            }
+            for (int p = D.cell_start[cell[d]]; p < D.cell_start[cell[d] + 1]; p++) insert(slot_key(S, D.code[p]));
+        }
     }
     if (over) atomicOr(D.status, TL_ST_SLOT);
     D.cnt[dst][id] = (uint8_t)c;
@@ -1223,11 +1251,17 @@ DEV void mixed_body(const SceneK& S, const SceneD& D, int bi, int force)
     if (!force && !D.bdirty[brick]) return;
     bool mixed = false;
     for (int c = threadIdx.x; c < TL_CELLS; c += blockDim.x) {
-        const int* cs = D.cell_start + (long long)brick * TL_CELLS + c;
-        const int b0 = cs[0], b1 = cs[1];
-        if (b1 <= b0) continue;
+        const long long cs = (long long)brick * TL_CELLS + c;
+        const int b0 = D.cell_start[cs], b1 = D.cell_start[cs + 1];
+        if (b1 <= b0) {
+            D.ccode[cs] = TL_CC_EMPTY;
+            continue;
+        }
         const uint32_t k0 = slot_key(S, D.code[b0]);
-        for (int p = b0 + 1; p < b1; p++) mixed |= slot_key(S, D.code[p]) != k0;
+        bool cm = false;
+        for (int p = b0 + 1; p < b1; p++) cm |= slot_key(S, D.code[p]) != k0;
+        D.ccode[cs] = cm ? TL_CC_MIXED : k0;
+        mixed |= cm;
     }
     int m = __syncthreads_or(mixed);
     if (threadIdx.x == 0) D.bmixed[brick] = m;
@@ -1311,10 +1345,19 @@ DEV void wrench_body(const SceneK& S, const SceneD& D, int bi)
     __shared__ double s[256];
     const int q = bi;
     if (!D.tinfo[1] || q >= D.tinfo[0] * 6) return;
-    double acc = 0.0;
-    for (int b = threadIdx.x; b < D.n_active; b += blockDim.x)
-        acc += (double)D.wpart[(long long)b * (TL_MAX_TOOLS * 6) + q];
-    s[threadIdx.x] = acc;
+    // four independent running sums per thread, combined in a fixed order
+    const float* w = D.wpart + (long long)q * D.n_active;
+    const int n = D.n_active, T = blockDim.x;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int b = threadIdx.x;
+    for (; b + 3 * T < n; b += 4 * T) {
+        a0 += (double)w[b];
+        a1 += (double)w[b + T];
+        a2 += (double)w[b + 2 * T];
+        a3 += (double)w[b + 3 * T];
+    }
+    for (; b < n; b += T) a0 += (double)w[b];
+    s[threadIdx.x] = (a0 + a1) + (a2 + a3);
     __syncthreads();
     for (int o = blockDim.x / 2; o > 0; o >>= 1) {
         if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
@@ -1398,6 +1441,26 @@ static int plain_bflags(const TlLaunch& L)
     return L.S ? blocks_of((long long)L.S->cbx * L.S->cby * L.S->cbz, 256) : 0;
 }
 
+// Runs f(uniform launch context) and g(mixed launch context): on the second stream
+// when there is one (fork after the work queued so far, join before what follows).
+template <class F, class G>
+static hipError_t fork_join(const TlLaunch& L, F&& f, G&& g)
+{
+    if (!L.st2) {
+        hipError_t e = f(L);
+        return e != hipSuccess ? e : g(L);
+    }
+    TlLaunch L2 = L;
+    L2.st = L.st2;
+    hipError_t e = hipEventRecord(L.ev_fork, L.st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(L.st2, L.ev_fork, 0);
+    if (e == hipSuccess) e = g(L2);
+    if (e == hipSuccess) e = hipEventRecord(L.ev_join, L.st2);
+    if (e == hipSuccess) e = f(L);
+    if (e == hipSuccess) e = hipStreamWaitEvent(L.st, L.ev_join, 0);
+    return e;
+}
+
 extern "C" {
 hipError_t tl_launch_rigid(const TlLaunch* L, int j)
 {
@@ -1413,16 +1476,18 @@ hipError_t tl_launch_p2g(const TlLaunch* L, int do_p2g, int tabs_differ, int cur
     A.tabs_differ = tabs_differ;
     A.cur = cur;
     A.rsb = rsb;
-    hipError_t e = tl_run(*L, IT_BRICK, plain_bricks(*L), TL_WG, k_p2g<false>, k_p2g_b<false>, A);
-    if (e != hipSuccess) return e;
-    return tl_run(*L, IT_BRICK, plain_bricks(*L), TL_WG, k_p2g<true>, k_p2g_b<true>, A);
+    const int nb = plain_bricks(*L);
+    return fork_join(
+        *L, [&](const TlLaunch& X) { return tl_run(X, IT_BRICK, nb, TL_WG, k_p2g<false>, k_p2g_b<false>, A); },
+        [&](const TlLaunch& X) { return tl_run(X, IT_BRICK, nb, TL_WG, k_p2g<true>, k_p2g_b<true>, A); });
 }
 
 hipError_t tl_launch_g2p(const TlLaunch* L, int cur)
 {
-    hipError_t e = tl_run(*L, IT_BRICK, plain_bricks(*L), TL_WG, k_g2p<false>, k_g2p_b<false>, cur);
-    if (e != hipSuccess) return e;
-    return tl_run(*L, IT_BRICK, plain_bricks(*L), TL_WG, k_g2p<true>, k_g2p_b<true>, cur);
+    const int nb = plain_bricks(*L);
+    return fork_join(
+        *L, [&](const TlLaunch& X) { return tl_run(X, IT_BRICK, nb, TL_WG, k_g2p<false>, k_g2p_b<false>, cur); },
+        [&](const TlLaunch& X) { return tl_run(X, IT_BRICK, nb, TL_WG, k_g2p<true>, k_g2p_b<true>, cur); });
 }
 
 hipError_t tl_launch_labels(const TlLaunch* L, int j)
