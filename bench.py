@@ -59,7 +59,32 @@ def cpu_baseline(scene, budget_s=12.0, max_steps=400):
             "sample": f"first {steps} substeps of {scene['name']} ({n} particles), FP64 C oracle, 1 thread"}
 
 
-def roofline_of(prof, value, n, per_particle_extra=0):
+def kernel_source_hash():
+    """First 16 hex digits of the sha256 of the kernel sources (the key under which
+    measured hardware traffic is stored in profiles/traffic.json)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("tlmpm_common.h", "tlmpm_kernels.hip", "tlmpm_contact.hip"):
+        with open(os.path.join(ROOT, "paper_2609_27342_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, cls):
+    """HBM bytes per launch of a kernel class from the committed rocprofv3 counter
+    summary, or None when it was taken on other kernel sources or workloads."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("source_hash") != kernel_source_hash():
+        return None
+    rec = t.get("workloads", {}).get(workload, {}).get(cls)
+    return rec["bytes"] if rec else None
+
+
+def roofline_of(prof, value, n, per_particle_extra=0, workload=None):
     """Roofline of the dominant kernel class from event timings {class: (ms, launches)}."""
     kern = {k: {"ms_avg": (v[0] / v[1]) if v[1] else None, "launches": v[1]} for k, v in prof.items()}
     dom = max(("p2g", "g2p"), key=lambda k: prof[k][0])
@@ -67,7 +92,8 @@ def roofline_of(prof, value, n, per_particle_extra=0):
     per_particle = ALG_BYTES[dom] + (per_particle_extra if dom == "p2g" else 0)
     achieved = per_particle * n / avg_s / 1e9
     return {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(workload, dom) if workload else None,
+            "alg_bytes_per_launch": per_particle * n,
             "step_alg_frac": value * ALG_STEP_BYTES / (HBM_PEAK_GBS * 1e9), "kernels": kern}
 
 
@@ -159,7 +185,7 @@ def bench_batched(args, K, Wm):
                    "plain": {"value": plain_value, "ms_per_step": t_plain * 1e3 / K, "status": status_plain},
                    "batched_over_plain": value / plain_value},
         "status": status,
-        "roofline": roofline_of(prof, value, n),
+        "roofline": roofline_of(prof, value, n, 0, "batched"),
         "cpu_baseline": cpu,
     }
 
@@ -272,7 +298,7 @@ def main():
     run_steps(g, scene, Wm + K, Wm + K + P)
     prof = g.profile_read()
     g.profile(False)
-    roofline = roofline_of(prof, value, n, 4 if scene["E"].min() != scene["E"].max() else 0)
+    roofline = roofline_of(prof, value, n, 4 if scene["E"].min() != scene["E"].max() else 0, args.workload)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(scene)

@@ -146,6 +146,26 @@ struct SceneD {
     float* ph_u;        // [2][N][TL_PCAP][3] spring, oriented for the pair's lower index
 };
 
+// Value of lane (lane ^ M), M in {1, 2, 4}, by DPP row moves (no LDS traffic):
+// quad permutations for 1 and 2; for 4, lanes with bit 2 clear read lane + 4
+// (row shift left) and the others lane - 4 (row shift right), all within a row of
+// 16 lanes.
+template <int M>
+__device__ __forceinline__ float lane_xor(float v)
+{
+    const int x = __float_as_int(v);
+    if constexpr (M == 1) {
+        return __int_as_float(__builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, true));
+    } else if constexpr (M == 2) {
+        return __int_as_float(__builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, true));
+    } else {
+        static_assert(M == 4, "lane_xor: 1, 2 or 4");
+        const int up = __builtin_amdgcn_mov_dpp(x, 0x104, 0xF, 0xF, true);
+        const int dn = __builtin_amdgcn_mov_dpp(x, 0x114, 0xF, 0xF, true);
+        return __int_as_float((threadIdx.x & 4) ? dn : up);
+    }
+}
+
 // Launch context: one scene (parameters by value) or a batch of scenes (device
 // arrays of SceneK / SceneD and, per kind of work item, a list of (scene, block)).
 enum { IT_BRICK = 0, IT_NODE, IT_CELL, IT_BUCKET, IT_SCENE, IT_WRENCH, IT_PART, IT_BFLAG, IT_PAIR, TL_ITEM_KINDS };

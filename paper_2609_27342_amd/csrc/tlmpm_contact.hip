@@ -399,7 +399,11 @@ DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
     __shared__ float s_u[TL_PCAND][TL_PCAP][3];
     __shared__ int s_nold[TL_PCAND], s_nnew[TL_PCAND];
     const int total = D.coff[D.n_active];
-    const float inv_h = 1.0f / D.hbin[0];
+    const float hb = D.hbin[0];
+    const float inv_h = 1.0f / hb;
+    // no pair farther apart than the bin edge can touch this substep: the edge
+    // exceeds R_p + R_q + dt |v_p - v_q| for every pair (see bin_edge)
+    const float reach2 = hb * hb;
     const long long N = S.N;
     const int sub = threadIdx.x / TL_PLANES; // candidate of this lane group
     const int l = threadIdx.x % TL_PLANES;   // lane in the group
@@ -440,6 +444,10 @@ DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
             auto visit = [&](const float4 rec[3]) {
                 const int q = __float_as_int(rec[0].x);
                 if (q == p) return;
+                {
+                    const float ex = sp.x[0] - rec[1].x, ey = sp.x[1] - rec[1].y, ez = sp.x[2] - rec[1].z;
+                    if (ex * ex + ey * ey + ez * ez >= reach2) return;
+                }
                 uint32_t kq = ckey(S, __float_as_uint(rec[0].y));
                 int cq[3];
                 slot_cell(S, __float_as_int(rec[0].z), cq[0], cq[1], cq[2]);
@@ -510,7 +518,12 @@ DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
         }
         // fixed-order sum over the lanes of the group
         for (int a = 0; a < 3; a++)
-            for (int o = TL_PLANES / 2; o >= 1; o >>= 1) Jt[a] += __shfl_xor(Jt[a], o, 64);
+        {
+            static_assert(TL_PLANES == 8, "the lane sum below covers 8 lanes");
+            Jt[a] += lane_xor<4>(Jt[a]);
+            Jt[a] += lane_xor<2>(Jt[a]);
+            Jt[a] += lane_xor<1>(Jt[a]);
+        }
         __syncthreads();
         if (has && l == 0) {
             const int nn = s_nnew[sub];

@@ -279,7 +279,7 @@ DEV void reduce_scatter8(Gen&& gen, float (&res)[Q], int j)
         for (int q = 0; q < Q; q++) {
             float send = b2 ? lo[q] : hi[q];
             float keep = b2 ? hi[q] : lo[q];
-            c1[kk][q] = keep + __shfl_xor(send, 4, 64);
+            c1[kk][q] = keep + lane_xor<4>(send);
         }
     }
     float c2[2][Q];
@@ -290,14 +290,14 @@ DEV void reduce_scatter8(Gen&& gen, float (&res)[Q], int j)
         for (int q = 0; q < Q; q++) {
             float send = b1 ? c1[kk][q] : c1[kk | 2][q];
             float keep = b1 ? c1[kk | 2][q] : c1[kk][q];
-            c2[kk][q] = keep + __shfl_xor(send, 2, 64);
+            c2[kk][q] = keep + lane_xor<2>(send);
         }
     const bool b0 = j & 1;
 #pragma unroll
     for (int q = 0; q < Q; q++) {
         float send = b0 ? c2[0][q] : c2[1][q];
         float keep = b0 ? c2[1][q] : c2[0][q];
-        res[q] = keep + __shfl_xor(send, 1, 64);
+        res[q] = keep + lane_xor<1>(send);
     }
 }
 
@@ -1042,10 +1042,11 @@ DEV void g2p_body(const SceneK& S, const SceneD& D, int bi, int cur)
     // brick AABB of x^{n+1} and speed bound (used to skip distant contact work)
     for (int q = 0; q < 7; q++) {
         float val = bb[q];
-        for (int o = 32; o >= 1; o >>= 1) {
-            float other = __shfl_xor(val, o, 64);
-            val = (q < 3) ? fminf(val, other) : fmaxf(val, other);
-        }
+        auto mm = [&](float other) { val = (q < 3) ? fminf(val, other) : fmaxf(val, other); };
+        mm(lane_xor<1>(val));
+        mm(lane_xor<2>(val));
+        mm(lane_xor<4>(val));
+        for (int o = 8; o <= 32; o <<= 1) mm(__shfl_xor(val, o, 64));
         if (L.lane == 0) s_bb[L.w][q] = val;
     }
     lds_barrier();
