@@ -73,16 +73,8 @@ struct tlmpm_scene {
     int rsb;       // slot table of the pending re-scatter
     bool f_pending; // host copy of the device flag D.ctr[1]
     int in_batch = 0; // member of a live batch: single-scene calls are refused
-    hipStream_t st2 = nullptr; // mixed-brick kernels beside the uniform ones
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     std::vector<int> active_host;
     Timing prof;
-    ~tlmpm_scene()
-    {
-        if (ev_fork) (void)hipEventDestroy(ev_fork);
-        if (ev_join) (void)hipEventDestroy(ev_join);
-        if (st2) (void)hipStreamDestroy(st2);
-    }
 };
 
 // Brackets one launch with events when timing is on.
@@ -120,9 +112,6 @@ static TlLaunch single_launch(const tlmpm_scene* sc)
     L.D = &sc->D;
     L.any_material = sc->K.material_contact;
     L.st = sc->st;
-    L.st2 = sc->st2;
-    L.ev_fork = sc->ev_fork;
-    L.ev_join = sc->ev_join;
     return L;
 }
 
@@ -165,7 +154,7 @@ Dims dims_of(const tlmpm_scene_desc* d)
 
 struct Offsets {
     size_t X, u, v, H, code, code_prev, D, perm, E, m, V0, cell_start, active, cnt0, cnt1, sc0, sc1, p2g, rs, hist,
-        aabb, wpart, wacc, Jmat, Jrig, brig, bmixed, ccode, tools, tinfo, ctr, bact, status, dirty, bdirty, pcell, cand_idx, coff, gcand, cmask, cstatic, bcand, hbin, hmax, bcount, bids, cslot, brec, htab, hnext, orec, ph_n, ph_q, ph_u,
+        aabb, wpart, wacc, Jmat, Jrig, brig, bmixed, ccode, gmeta, gperm, bround, tools, tinfo, ctr, bact, status, dirty, bdirty, pcell, cand_idx, coff, gcand, cmask, cstatic, bcand, hbin, hmax, bcount, bids, cslot, brec, htab, hnext, orec, ph_n, ph_q, ph_u,
         total;
     uint32_t hmask;
 };
@@ -239,6 +228,9 @@ Offsets plan(const tlmpm_scene_desc* d, long long n_active)
     o.brig = L.take((size_t)g.n_bricks * 4);
     o.bmixed = L.take((size_t)g.n_bricks * 4);
     o.ccode = L.take((size_t)g.n_bricks * TL_CELLS * 4);
+    o.gmeta = L.take((size_t)n_active * TL_CELLS * TL_GMAX * 4);
+    o.gperm = L.take(N * 4);
+    o.bround = L.take((size_t)n_active * 4);
     o.tools = L.take(TL_MAX_TOOLS * sizeof(DevTool));
     o.tinfo = L.take(4 * 4);
     o.ctr = L.take(4 * 4);
@@ -382,12 +374,7 @@ extern "C" tlmpm_status tlmpm_create_scene(const tlmpm_scene_desc* d, void* ws, 
     tlmpm_scene* sc = new tlmpm_scene();
     sc->st = (hipStream_t)hip_stream;
     sc->prof.st = sc->st;
-    if (hipStreamCreateWithFlags(&sc->st2, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&sc->ev_fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&sc->ev_join, hipEventDisableTiming) != hipSuccess) {
-        delete sc;
-        return fail(TLMPM_E_DEVICE, "stream or event creation failed");
-    }
+
     sc->max_cuts = d->max_cuts;
     sc->n_bricks = (int)g.n_bricks;
     sc->cur = 0;
@@ -478,6 +465,9 @@ extern "C" tlmpm_status tlmpm_create_scene(const tlmpm_scene_desc* d, void* ws, 
     D.brig = (int*)(base + o.brig);
     D.bmixed = (int*)(base + o.bmixed);
     D.ccode = (uint32_t*)(base + o.ccode);
+    D.gmeta = (int*)(base + o.gmeta);
+    D.gperm = (int*)(base + o.gperm);
+    D.bround = (int*)(base + o.bround);
     D.tools = (DevTool*)(base + o.tools);
     D.tinfo = (int*)(base + o.tinfo);
     D.bact = (int*)(base + o.bact);
@@ -1079,17 +1069,12 @@ struct tlmpm_batch {
     BatchTools* h_tools = nullptr; // pinned staging of the per-call tools
     double* h_wacc = nullptr;
     hipEvent_t up_done = nullptr;  // the last upload from h_tools finished
-    hipStream_t st2 = nullptr;     // mixed-brick kernels beside the uniform ones
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     Timing prof;
     ~tlmpm_batch()
     {
         if (h_tools) (void)hipHostFree(h_tools);
         if (h_wacc) (void)hipHostFree(h_wacc);
         if (up_done) (void)hipEventDestroy(up_done);
-        if (ev_fork) (void)hipEventDestroy(ev_fork);
-        if (ev_join) (void)hipEventDestroy(ev_join);
-        if (st2) (void)hipStreamDestroy(st2);
     }
     int cur, rsb;
     bool pending;
@@ -1196,12 +1181,7 @@ extern "C" tlmpm_status tlmpm_batch_create(tlmpm_scene* const* scenes, int32_t n
         hipSuccess)
         return bail(e, "pinned staging");
     if ((e = hipEventCreateWithFlags(&b->up_done, hipEventDisableTiming)) != hipSuccess) return bail(e, "event");
-    if ((e = hipStreamCreateWithFlags(&b->st2, hipStreamNonBlocking)) != hipSuccess) return bail(e, "stream");
-    if ((e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming)) != hipSuccess) return bail(e, "event");
-    if ((e = hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming)) != hipSuccess) return bail(e, "event");
-    L.st2 = b->st2;
-    L.ev_fork = b->ev_fork;
-    L.ev_join = b->ev_join;
+
     if ((e = hipStreamSynchronize(b->st)) != hipSuccess) return bail(e, "create batch");
     for (tlmpm_scene* sc : b->sc) sc->in_batch = 1;
     *out = b;

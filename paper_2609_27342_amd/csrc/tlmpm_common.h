@@ -34,6 +34,7 @@
 
 #define TL_CC_EMPTY 0xFFFFFFFEu // cell summary: no particle
 #define TL_CC_MIXED 0xFFFFFFFFu // cell summary: particles of two or more slot keys
+#define TL_GMAX 8              // same-code groups (of <= 8 particles) per cell in a mixed brick
 #define TL_PCAP 16             // persistent pair springs kept per particle (all its partners)
 #define TL_PLANES 8            // lanes per candidate in the pair search
 #define TL_PCAND 32            // candidates per pair-search block (256 threads)
@@ -117,6 +118,9 @@ struct SceneD {
     int* brig;     // [bricks] the brick was within reach of a rigid body this substep
     int* bmixed;   // [bricks] a cell of the brick holds two side codes
     uint32_t* ccode; // [bricks * 64] (sorted cell order) the one slot key of a cell, or TL_CC_*
+    int* gmeta;      // [active bricks][64 cells][TL_GMAX] groups of a mixed brick: offset << 4 | count
+    int* gperm;      // [N] particles of mixed bricks in group order, over each cell's range
+    int* bround;     // [active bricks] rounds (largest group count of a cell) of a mixed brick
     DevTool* tools;   // [TL_MAX_TOOLS] tools (or label-only blades) of the current call
     int* tinfo;       // [4] per call: number of tools, any tool with contact, new cut, unused
     int* ctr;         // [4] persistent: contact-history stamp, F update pending, unused x2
@@ -179,8 +183,4 @@ struct TlLaunch {
     int n_items[TL_ITEM_KINDS];
     int any_material;  // some scene has material contact
     hipStream_t st;
-    // optional second stream for the mixed-brick variants, which then run beside
-    // the uniform-brick ones (fork / join events; null: one stream)
-    hipStream_t st2;
-    hipEvent_t ev_fork, ev_join;
 };

@@ -243,6 +243,25 @@ DEV Lane lane_of(const SceneD& D, int brick)
     return L;
 }
 
+// Particle of this lane in round r.  Bricks whose cells each hold one code take
+// particle 8 r + j of the lane's cell; bricks with a mixed cell take particle j of
+// the cell's r-th same-code group (group table built when the codes change).
+DEV bool lane_particle(const SceneD& D, int bi, bool grouped, const Lane& L, int r, long long& p)
+{
+    if (!grouped) {
+        const int jj = 8 * r + L.j;
+        p = L.beg + (jj < L.count ? jj : 0);
+        return jj < L.count;
+    }
+    p = L.beg;
+    if (r >= TL_GMAX) return false;
+    const int m = D.gmeta[((long long)bi * TL_CELLS + L.w * 8 + L.i) * TL_GMAX + r];
+    const int cnt = m & 15, off = m >> 4;
+    if (L.j >= cnt) return false;
+    p = D.gperm[L.beg + off + L.j];
+    return true;
+}
+
 // fractional position inside the base cell (reading R1), in [0, 1]
 DEV void frac_of(const SceneK& S, const float* X, int gxc, int gyc, int gzc, float t[3])
 {
@@ -303,82 +322,39 @@ DEV void reduce_scatter8(Gen&& gen, float (&res)[Q], int j)
 
 // Adds a wave's per-node sums to the LDS box accumulator, one parity class after
 // another (fixed order).  The QA + QB components come from two generators (two
-// butterflies keep fewer partial sums live).  Fast path: every cell of the wave
-// holds one code.  Otherwise the codes present in the wave are processed in
-// ascending order with the other codes' contributions masked out.
-template <int QA, int QB, bool MIXED, class GA, class GB>
+// butterflies keep fewer partial sums live).  Every 8-lane group holds particles
+// of one code (bricks with a mixed cell are processed in same-code groups).
+template <int QA, int QB, class GA, class GB>
 DEV void accumulate_classes(const Lane& L, bool valid, uint32_t key, GA&& ga, GB&& gb, const BoxTab& T, float* acc,
                             int* status)
 {
     constexpr int Q = QA + QB;
     const int leader = L.lane & ~7;
-    uint32_t lkey = __shfl(key, leader, 64);
-    bool gvalid = __shfl((int)valid, leader, 64) != 0;
-    bool mixed = valid && key != lkey;
-    bool wave_mixed = __any(mixed);
-    if (!MIXED) {
-        // bricks flagged uniform must not hold two codes in one cell
-        if (wave_mixed && L.lane == 0) atomicOr(status, TL_ST_LOOKUP);
-        wave_mixed = false;
-    }
+    const uint32_t lkey = __shfl(key, leader, 64);
+    const bool gvalid = __shfl((int)valid, leader, 64) != 0;
+    if (__any(valid && key != lkey) && L.lane == 0) atomicOr(status, TL_ST_LOOKUP);
     float res[Q];
-    auto reduce_both = [&](auto&& fa, auto&& fb) {
+    {
         float ra[QA];
-        reduce_scatter8<QA>(fa, ra, L.j);
+        reduce_scatter8<QA>(ga, ra, L.j);
 #pragma unroll
         for (int q = 0; q < QA; q++) res[q] = ra[q];
         if constexpr (QB > 0) {
             float rb[QB];
-            reduce_scatter8<QB>(fb, rb, L.j);
+            reduce_scatter8<QB>(gb, rb, L.j);
 #pragma unroll
             for (int q = 0; q < QB; q++) res[QA + q] = rb[q];
         }
-    };
-    if (!wave_mixed) reduce_both(ga, gb);
+    }
     const int bn = box_index(L.cxl + (L.j & 1), L.cyl + ((L.j >> 1) & 1), L.czl + ((L.j >> 2) & 1));
     for (int phase = 0; phase < 8; phase++) {
         lds_barrier();
-        if (L.w != phase) continue;
-        if (!wave_mixed) {
-            if (gvalid) {
-                int sl = find_slot(T, bn, lkey);
-                if (sl < 0)
-                    atomicOr(status, TL_ST_LOOKUP);
-                else
-                    for (int q = 0; q < Q; q++) acc[sl * Q + q] += res[q];
-            }
-        } else if constexpr (MIXED) {
-            bool pending = valid;
-            while (__any(pending)) {
-                uint32_t mk = pending ? key : 0xFFFFFFFFu;
-                for (int o = 32; o >= 1; o >>= 1) {
-                    uint32_t t = (uint32_t)__shfl_xor((int)mk, o, 64);
-                    mk = t < mk ? t : mk;
-                }
-                const bool mine = pending && key == mk;
-                auto ma = [&](int k, float* out) {
-                    ga(k, out);
-#pragma unroll
-                    for (int q = 0; q < QA; q++) out[q] = mine ? out[q] : 0.0f;
-                };
-                auto mb = [&](int k, float* out) {
-                    gb(k, out);
-#pragma unroll
-                    for (int q = 0; q < QB; q++) out[q] = mine ? out[q] : 0.0f;
-                };
-                reduce_both(ma, mb);
-                unsigned long long bal = __ballot(mine);
-                bool present = ((bal >> leader) & 0xFFull) != 0ull;
-                if (present) {
-                    int sl = find_slot(T, bn, mk);
-                    if (sl < 0)
-                        atomicOr(status, TL_ST_LOOKUP);
-                    else
-                        for (int q = 0; q < Q; q++) acc[sl * Q + q] += res[q];
-                }
-                pending = pending && !mine;
-            }
-        }
+        if (L.w != phase || !gvalid) continue;
+        int sl = find_slot(T, bn, lkey);
+        if (sl < 0)
+            atomicOr(status, TL_ST_LOOKUP);
+        else
+            for (int q = 0; q < Q; q++) acc[sl * Q + q] += res[q];
     }
     lds_barrier();
 }
@@ -703,7 +679,6 @@ DEV void rigid_body(const SceneK& S, const SceneD& D, int bi, KR_Args A)
     }
 }
 
-template <bool MIXED>
 DEV void p2g_body(const SceneK& S, const SceneD& D, int bi, KA_Args A)
 {
     __shared__ BoxTab Tc;
@@ -716,7 +691,7 @@ DEV void p2g_body(const SceneK& S, const SceneD& D, int bi, KA_Args A)
     __shared__ int s_rounds;
 
     const int brick = D.active[bi];
-    if ((D.bmixed[brick] != 0) != MIXED) return; // the other variant handles this brick
+    const bool grouped = D.bmixed[brick] != 0; // a cell holds two codes: same-code groups
     const int bx = brick % S.cbx, by = (brick / S.cbx) % S.cby, bz = brick / (S.cbx * S.cby);
     const int tid = threadIdx.x;
     const long long N = S.N;
@@ -734,8 +709,8 @@ DEV void p2g_body(const SceneK& S, const SceneD& D, int bi, KA_Args A)
     // floor/tool impulses were computed for this brick by k_rigid
     const bool rig = A.do_p2g && (S.floor_on || D.tinfo[1]) && D.brig[brick] != 0;
     const int gxc = bx * TL_B + L.cxl, gyc = by * TL_B + L.cyl, gzc = bz * TL_B + L.czl;
-    bool valid = L.j < L.count;
-    long long p = L.beg + L.j;
+    long long p = L.beg;
+    bool valid = lane_particle(D, bi, grouped, L, 0, p);
     float Xp[3] = {0.0f, 0.0f, 0.0f}, H[9], vel[3] = {0.0f, 0.0f, 0.0f};
     uint32_t code = 0;
     auto load_particle = [&]() {
@@ -750,7 +725,11 @@ DEV void p2g_body(const SceneK& S, const SceneD& D, int bi, KA_Args A)
     };
     if (valid) load_particle();
     lds_barrier();
-    if (L.j == 0) atomicMax(&s_rounds, (L.count + 7) >> 3);
+    if (grouped) {
+        if (tid == 0) s_rounds = D.bround[bi];
+    } else if (L.j == 0) {
+        atomicMax(&s_rounds, (L.count + 7) >> 3);
+    }
     if (use_r) box_scan(Tr, &s_total_r, 0);
     if (use_c) box_scan(Tc, &s_total_c, 1);
     lds_barrier();
@@ -785,9 +764,7 @@ DEV void p2g_body(const SceneK& S, const SceneD& D, int bi, KA_Args A)
 
     for (int r = 0; r < rounds; r++) {
         if (r > 0) {
-            const int jj = 8 * r + L.j;
-            valid = jj < L.count;
-            p = L.beg + jj;
+            valid = lane_particle(D, bi, grouped, L, r, p);
             if (valid) load_particle();
         }
         float t[3] = {0.0f, 0.0f, 0.0f};
@@ -893,7 +870,7 @@ DEV void p2g_body(const SceneK& S, const SceneD& D, int bi, KA_Args A)
                 o[a] = on ? f : 0.0f;
             }
         };
-        accumulate_classes<4, 3, MIXED>(L, valid, key, gen_mp, gen_dp, T, s_acc, D.status);
+        accumulate_classes<4, 3>(L, valid, key, gen_mp, gen_dp, T, s_acc, D.status);
     }
     if (!A.do_p2g) return;
     write_partials<7>(S, D.p2g, bi, T, total_c, s_acc);
@@ -904,7 +881,6 @@ DEV void p2g_body(const SceneK& S, const SceneD& D, int bi, KA_Args A)
 // P2G partials (sum over contributing bricks, coupling Eq. 8, velocities Eq. 9),
 // PIC/FLIP G2P of v and x (Eq. 17), then the MUSL re-scatter of m_p v_p^{n+1} into
 // this brick's partials.  Also records the brick's current AABB and speed bound.
-template <bool MIXED>
 DEV void g2p_body(const SceneK& S, const SceneD& D, int bi, int cur)
 {
     __shared__ BoxTab T;
@@ -917,13 +893,13 @@ DEV void g2p_body(const SceneK& S, const SceneD& D, int bi, int cur)
     __shared__ float s_bb[8][7];
 
     const int brick = D.active[bi];
-    if (!MIXED && bi == 0 && threadIdx.x == 0) {
+    if (bi == 0 && threadIdx.x == 0) {
         // end of the substep for this scene: next history stamp, F update pending
         // (no other kernel of the substep reads these after this point)
         D.ctr[0] += 1;
         D.ctr[1] = 1;
     }
-    if ((D.bmixed[brick] != 0) != MIXED) return; // the other variant handles this brick
+    const bool grouped = D.bmixed[brick] != 0; // a cell holds two codes: same-code groups
     const int bx = brick % S.cbx, by = (brick / S.cbx) % S.cby, bz = brick / (S.cbx * S.cby);
     const int tid = threadIdx.x;
     const long long N = S.N;
@@ -935,8 +911,8 @@ DEV void g2p_body(const SceneK& S, const SceneD& D, int bi, int cur)
     load_neighbours(S, D, bx, by, bz, s_nb);
     if (tid == 0) s_rounds = 0;
     const int gxc = bx * TL_B + L.cxl, gyc = by * TL_B + L.cyl, gzc = bz * TL_B + L.czl;
-    bool valid = L.j < L.count;
-    long long p = L.beg + L.j;
+    long long p = L.beg;
+    bool valid = lane_particle(D, bi, grouped, L, 0, p);
     float Xp[3] = {0.0f, 0.0f, 0.0f}, v[3] = {0.0f, 0.0f, 0.0f}, u[3] = {0.0f, 0.0f, 0.0f};
     uint32_t code = 0;
     auto load_particle = [&]() {
@@ -949,7 +925,11 @@ DEV void g2p_body(const SceneK& S, const SceneD& D, int bi, int cur)
     };
     if (valid) load_particle();
     lds_barrier();
-    if (L.j == 0) atomicMax(&s_rounds, (L.count + 7) >> 3);
+    if (grouped) {
+        if (tid == 0) s_rounds = D.bround[bi];
+    } else if (L.j == 0) {
+        atomicMax(&s_rounds, (L.count + 7) >> 3);
+    }
     box_scan(T, &s_total, 0);
     lds_barrier();
     const int total = s_total;
@@ -985,9 +965,7 @@ DEV void g2p_body(const SceneK& S, const SceneD& D, int bi, int cur)
     const float* gdv = s_grid + TL_BOX_SLOTS * 3;
     for (int r = 0; r < rounds; r++) {
         if (r > 0) {
-            const int jj = 8 * r + L.j;
-            valid = jj < L.count;
-            p = L.beg + jj;
+            valid = lane_particle(D, bi, grouped, L, r, p);
             if (valid) load_particle();
         }
         float t[3] = {0.0f, 0.0f, 0.0f};
@@ -1036,7 +1014,7 @@ DEV void g2p_body(const SceneK& S, const SceneD& D, int bi, int cur)
             o[2] = w * vn1[1];
             o[3] = w * vn1[2];
         };
-        accumulate_classes<4, 0, MIXED>(L, valid, key, gen, gen, T, s_acc, D.status);
+        accumulate_classes<4, 0>(L, valid, key, gen, gen, T, s_acc, D.status);
     }
     write_partials<4>(S, D.rs, bi, T, total, s_acc);
     // brick AABB of x^{n+1} and speed bound (used to skip distant contact work)
@@ -1243,13 +1221,17 @@ DEV void slots_body(const SceneK& S, const SceneD& D, int bi, int dst, int src, 
 }
 
 // ------------------------------------------------------------- mixed-code bricks
-// A brick is "mixed" when one of its cells holds particles of two side codes; its
-// P2G/G2P run in the kernel variant that reduces one code at a time.  Recomputed
-// for bricks whose codes changed (or all, when forced).
+// Per cell of a brick whose codes changed (or of every brick, when forced): the
+// one slot key of its particles (or empty / mixed).  A brick with a mixed cell
+// gets a group table: each of its cells lists its particles by ascending key
+// (input order within a key) in gperm over the cell's range, cut into groups of at
+// most 8 same-key particles; P2G and G2P then take one group per cell and round.
 DEV void mixed_body(const SceneK& S, const SceneD& D, int bi, int force)
 {
+    __shared__ int s_rounds;
     const int brick = D.active[bi];
     if (!force && !D.bdirty[brick]) return;
+    if (threadIdx.x == 0) s_rounds = 1;
     bool mixed = false;
     for (int c = threadIdx.x; c < TL_CELLS; c += blockDim.x) {
         const long long cs = (long long)brick * TL_CELLS + c;
@@ -1264,8 +1246,47 @@ DEV void mixed_body(const SceneK& S, const SceneD& D, int bi, int force)
         D.ccode[cs] = cm ? TL_CC_MIXED : k0;
         mixed |= cm;
     }
-    int m = __syncthreads_or(mixed);
+    const int m = __syncthreads_or(mixed);
     if (threadIdx.x == 0) D.bmixed[brick] = m;
+    if (!m) return;
+    if (threadIdx.x < TL_CELLS) {
+        const int c = threadIdx.x; // cell slot w * 8 + i
+        const long long cs = (long long)brick * TL_CELLS + c;
+        const int b0 = D.cell_start[cs], b1 = D.cell_start[cs + 1];
+        int* meta = D.gmeta + ((long long)bi * TL_CELLS + c) * TL_GMAX;
+        int ng = 0, pos = 0;
+        uint32_t last = 0;
+        bool first = true;
+        while (pos < b1 - b0) {
+            uint32_t kmin = 0xFFFFFFFFu; // smallest key above the last one
+            for (int p = b0; p < b1; p++) {
+                const uint32_t k = slot_key(S, D.code[p]);
+                if ((first || k > last) && k < kmin) kmin = k;
+            }
+            int gstart = pos;
+            for (int p = b0; p < b1; p++) {
+                if (slot_key(S, D.code[p]) != kmin) continue;
+                D.gperm[b0 + pos] = p;
+                pos++;
+                if (pos - gstart == 8) {
+                    if (ng < TL_GMAX) meta[ng] = (gstart << 4) | 8;
+                    ng++;
+                    gstart = pos;
+                }
+            }
+            if (pos > gstart) {
+                if (ng < TL_GMAX) meta[ng] = (gstart << 4) | (pos - gstart);
+                ng++;
+            }
+            last = kmin;
+            first = false;
+        }
+        for (int g = ng; g < TL_GMAX; g++) meta[g] = 0;
+        if (ng > TL_GMAX) atomicOr(D.status, TL_ST_BOX);
+        atomicMax(&s_rounds, ng < TL_GMAX ? ng : TL_GMAX);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) D.bround[bi] = s_rounds;
 }
 
 // --------------------------------------------------------------- small kernels
@@ -1394,29 +1415,19 @@ TL_WRAP(resetD, 256, , )
 TL_WRAP(clear_flags, 256, , )
 TL_WRAP(clear_wacc, 64, , )
 
-template <bool MIXED>
-__global__ __launch_bounds__(TL_WG) void k_p2g(SceneK S, SceneD D, KA_Args A)
-{
-    p2g_body<MIXED>(S, D, blockIdx.x, A);
-}
-template <bool MIXED>
+__global__ __launch_bounds__(TL_WG) void k_p2g(SceneK S, SceneD D, KA_Args A) { p2g_body(S, D, blockIdx.x, A); }
 __global__ __launch_bounds__(TL_WG) void k_p2g_b(const SceneK* __restrict__ Ks, const SceneD* __restrict__ Ds,
                                                  const int2* __restrict__ it, KA_Args A)
 {
     const int2 t = it[blockIdx.x];
-    p2g_body<MIXED>(Ks[t.x], Ds[t.x], t.y, A);
+    p2g_body(Ks[t.x], Ds[t.x], t.y, A);
 }
-template <bool MIXED>
-__global__ __launch_bounds__(TL_WG) void k_g2p(SceneK S, SceneD D, int cur)
-{
-    g2p_body<MIXED>(S, D, blockIdx.x, cur);
-}
-template <bool MIXED>
+__global__ __launch_bounds__(TL_WG) void k_g2p(SceneK S, SceneD D, int cur) { g2p_body(S, D, blockIdx.x, cur); }
 __global__ __launch_bounds__(TL_WG) void k_g2p_b(const SceneK* __restrict__ Ks, const SceneD* __restrict__ Ds,
                                                  const int2* __restrict__ it, int cur)
 {
     const int2 t = it[blockIdx.x];
-    g2p_body<MIXED>(Ks[t.x], Ds[t.x], t.y, cur);
+    g2p_body(Ks[t.x], Ds[t.x], t.y, cur);
 }
 
 // ------------------------------------------------------------------- launchers
@@ -1442,26 +1453,6 @@ static int plain_bflags(const TlLaunch& L)
     return L.S ? blocks_of((long long)L.S->cbx * L.S->cby * L.S->cbz, 256) : 0;
 }
 
-// Runs f(uniform launch context) and g(mixed launch context): on the second stream
-// when there is one (fork after the work queued so far, join before what follows).
-template <class F, class G>
-static hipError_t fork_join(const TlLaunch& L, F&& f, G&& g)
-{
-    if (!L.st2) {
-        hipError_t e = f(L);
-        return e != hipSuccess ? e : g(L);
-    }
-    TlLaunch L2 = L;
-    L2.st = L.st2;
-    hipError_t e = hipEventRecord(L.ev_fork, L.st);
-    if (e == hipSuccess) e = hipStreamWaitEvent(L.st2, L.ev_fork, 0);
-    if (e == hipSuccess) e = g(L2);
-    if (e == hipSuccess) e = hipEventRecord(L.ev_join, L.st2);
-    if (e == hipSuccess) e = f(L);
-    if (e == hipSuccess) e = hipStreamWaitEvent(L.st, L.ev_join, 0);
-    return e;
-}
-
 extern "C" {
 hipError_t tl_launch_rigid(const TlLaunch* L, int j)
 {
@@ -1477,18 +1468,12 @@ hipError_t tl_launch_p2g(const TlLaunch* L, int do_p2g, int tabs_differ, int cur
     A.tabs_differ = tabs_differ;
     A.cur = cur;
     A.rsb = rsb;
-    const int nb = plain_bricks(*L);
-    return fork_join(
-        *L, [&](const TlLaunch& X) { return tl_run(X, IT_BRICK, nb, TL_WG, k_p2g<false>, k_p2g_b<false>, A); },
-        [&](const TlLaunch& X) { return tl_run(X, IT_BRICK, nb, TL_WG, k_p2g<true>, k_p2g_b<true>, A); });
+    return tl_run(*L, IT_BRICK, plain_bricks(*L), TL_WG, k_p2g, k_p2g_b, A);
 }
 
 hipError_t tl_launch_g2p(const TlLaunch* L, int cur)
 {
-    const int nb = plain_bricks(*L);
-    return fork_join(
-        *L, [&](const TlLaunch& X) { return tl_run(X, IT_BRICK, nb, TL_WG, k_g2p<false>, k_g2p_b<false>, cur); },
-        [&](const TlLaunch& X) { return tl_run(X, IT_BRICK, nb, TL_WG, k_g2p<true>, k_g2p_b<true>, cur); });
+    return tl_run(*L, IT_BRICK, plain_bricks(*L), TL_WG, k_g2p, k_g2p_b, cur);
 }
 
 hipError_t tl_launch_labels(const TlLaunch* L, int j)
