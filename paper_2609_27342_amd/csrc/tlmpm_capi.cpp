@@ -27,7 +27,6 @@ hipError_t tl_launch_slots(const TlLaunch*, int dst, int src, int force);
 hipError_t tl_launch_aabb(const TlLaunch*);
 hipError_t tl_launch_wrench(const TlLaunch*);
 hipError_t tl_launch_resetD(const TlLaunch*);
-hipError_t tl_launch_clear_flags(const TlLaunch*);
 hipError_t tl_launch_clear_wacc(const TlLaunch*);
 hipError_t tl_launch_cellmask(const TlLaunch*, int with_static, int force);
 hipError_t tl_launch_cand(const TlLaunch*, int force);
@@ -639,12 +638,10 @@ static tlmpm_status label_pass(Exec& X, int j, bool reset_D)
         HIPCHK(tl_launch_slots(&X.L, dst, X.cur, 0));
     }
     X.cur = dst;
-    if (X.L.any_material) {
+    if (X.L.any_material) { // cell code masks come with the cell summaries (k_mixed)
         ProfScope ps(X.prof, 4);
-        HIPCHK(tl_launch_cellmask(&X.L, 0, 0));
         HIPCHK(tl_launch_cand(&X.L, 0));
     }
-    HIPCHK(tl_launch_clear_flags(&X.L));
     return TLMPM_OK;
 }
 
@@ -963,10 +960,7 @@ extern "C" tlmpm_status tlmpm_write_state(tlmpm_scene* sc, uint32_t mask, const 
         HIPCHK(tl_launch_mixed(&L, 1));
         HIPCHK(tl_launch_slots(&L, sc->cur, sc->cur, 1));
         sc->rsb = sc->cur;
-        if (sc->K.material_contact) {
-            HIPCHK(tl_launch_cellmask(&L, 0, 1));
-            HIPCHK(tl_launch_cand(&L, 1));
-        }
+        if (sc->K.material_contact) HIPCHK(tl_launch_cand(&L, 1));
     }
     HIPCHK(tl_launch_aabb(&L));
     HIPCHK(hipStreamSynchronize(sc->st));

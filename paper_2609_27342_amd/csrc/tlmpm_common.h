@@ -136,7 +136,7 @@ struct SceneD {
     int* coff;          // [active bricks + 1] first global candidate index of each active brick
     int* gcand;         // [N] all candidates, brick by brick (rewritten by each binning pass)
     float* hbin;        // bin edge (device scalar)
-    int* hmax;          // largest brick speed bound, float bits (device scalar)
+    int* hmax;          // largest brick speed bound of this substep (float bits)
     uint32_t hmask;     // buckets - 1 (power of two)
     int* bcount;        // [buckets] entries of each bucket this substep (cleared per substep)
     int* bids;          // [buckets][TL_BCAP] particle ids in arrival order

@@ -61,7 +61,7 @@ DEV void cellmask_body(const SceneK& S, const SceneD& D, int bi, int with_static
     const long long n_slots = (long long)S.cbx * S.cby * S.cbz * TL_CELLS;
     long long cs = (long long)bi * blockDim.x + threadIdx.x;
     if (cs >= n_slots) return;
-    if (!force && !D.bdirty[cs / TL_CELLS]) return;
+    if (!force && D.bdirty[cs / TL_CELLS] != D.ctr[0]) return;
     uint32_t m = 0;
     for (int p = D.cell_start[cs]; p < D.cell_start[cs + 1]; p++) m |= ckey(S, D.code[p]);
     D.cmask[cs] = m;
@@ -83,26 +83,43 @@ DEV void cellmask_body(const SceneK& S, const SceneD& D, int bi, int with_static
 // Candidate bit of every particle and the brick's candidate list (in particle
 // order, stored over the brick's particle range).  Without `force`, only bricks
 // next to a brick whose codes changed are recomputed.
-DEV void cand_body(const SceneK& S, const SceneD& D, int bi, int force)
+// First global candidate index of every active brick (exclusive scan of the
+// candidate counts in active-brick order) by one block; each thread scans a
+// contiguous run of bricks.
+DEV void scan_offsets(const SceneD& D)
 {
-    if (!S.material_contact) return;
-    __shared__ uint32_t s_nm[TL_CELLS];
-    __shared__ int s_st[TL_CELLS];
-    __shared__ int s_go;
-    __shared__ int s_wave[4];
-    const int brick = D.active[bi];
-    const int bx = brick % S.cbx, by = (brick / S.cbx) % S.cby, bz = brick / (S.cbx * S.cby);
-    if (threadIdx.x == 0) {
-        int go = force;
-        for (int d = 0; d < 27 && !go; d++) {
-            int x = bx + d % 3 - 1, y = by + (d / 3) % 3 - 1, z = bz + d / 9 - 1;
-            if (x < 0 || y < 0 || z < 0 || x >= S.cbx || y >= S.cby || z >= S.cbz) continue;
-            go = D.bdirty[((long long)z * S.cby + y) * S.cbx + x];
-        }
-        s_go = go;
+    __shared__ int s_w[16];
+    const int n = D.n_active;
+    const int T = blockDim.x;
+    const int per = (n + T - 1) / T;
+    const int i0 = threadIdx.x * per, i1 = min(n, i0 + per);
+    int loc = 0;
+#pragma unroll 8
+    for (int i = i0; i < i1; i++) loc += D.bcand[i];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int incl = loc;
+    for (int o = 1; o < 64; o <<= 1) {
+        int t = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += t;
     }
+    if (lane == 63) s_w[wv] = incl;
     __syncthreads();
-    if (!s_go) return;
+    int before = 0;
+    for (int w = 0; w < wv; w++) before += s_w[w];
+    int run = before + incl - loc;
+#pragma unroll 8
+    for (int i = i0; i < i1; i++) {
+        const int c = D.bcand[i];
+        D.coff[i] = run;
+        run += c;
+    }
+    if (threadIdx.x == T - 1) D.coff[n] = run;
+}
+
+// candidate bits and the ordered candidate list of one brick
+DEV void cand_brick(const SceneK& S, const SceneD& D, int bi, int brick, int bx, int by, int bz, uint32_t* s_nm,
+                    int* s_st, int* s_wave)
+{
     if (threadIdx.x < TL_CELLS) {
         const int c = threadIdx.x;
         long long cs = (long long)brick * TL_CELLS + c;
@@ -150,19 +167,34 @@ DEV void cand_body(const SceneK& S, const SceneD& D, int bi, int force)
     if (threadIdx.x == 0) D.bcand[bi] = base;
 }
 
-// bin edge from the largest speed of any brick (conservative reach)
-// largest particle speed bound of the bricks (block bi covers bricks
-// [256 bi, 256 bi + 256)); the maximum of non-negative floats is taken on their
-// bit patterns, so the result does not depend on the order of the atomics
-DEV void hmax_body(const SceneK& S, const SceneD& D, int bi)
+DEV void cand_body(const SceneK& S, const SceneD& D, int bi, int force)
 {
     if (!S.material_contact) return;
-    const long long b = (long long)bi * blockDim.x + threadIdx.x;
-    const long long nb = (long long)S.cbx * S.cby * S.cbz;
-    float m = b < nb ? D.aabb[b * 8 + 6] : 0.0f;
-    for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
-    if ((threadIdx.x & 63) == 0 && m > 0.0f) atomicMax(D.hmax, __float_as_int(m));
+    __shared__ uint32_t s_nm[TL_CELLS];
+    __shared__ int s_st[TL_CELLS];
+    __shared__ int s_wave[4];
+    const int stamp = D.ctr[0];
+    const int brick = D.active[bi];
+    const int bx = brick % S.cbx, by = (brick / S.cbx) % S.cby, bz = brick / (S.cbx * S.cby);
+    // recompute when a brick of the 3x3x3 neighbourhood changed codes in this pass
+    int near_change = 0;
+    if (threadIdx.x < 27) {
+        const int d = threadIdx.x;
+        const int x = bx + d % 3 - 1, y = by + (d / 3) % 3 - 1, z = bz + d / 9 - 1;
+        if (x >= 0 && y >= 0 && z >= 0 && x < S.cbx && y < S.cby && z < S.cbz)
+            near_change = D.bdirty[((long long)z * S.cby + y) * S.cbx + x] == stamp;
+    }
+    const bool go = __syncthreads_or(near_change) || force;
+    if (go) cand_brick(S, D, bi, brick, bx, by, bz, s_nm, s_st, s_wave);
 }
+
+// one block of TL_SCAN_T threads per scene
+#define TL_SCAN_T 1024
+DEV void cscan_body(const SceneK& S, const SceneD& D, int bi)
+{
+    if (S.material_contact) scan_offsets(D);
+}
+
 
 // bin edge from the largest speed (conservative reach of every pair)
 DEV float bin_edge(const SceneK& S, const SceneD& D)
@@ -215,7 +247,15 @@ DEV void bzero_body(const SceneK& S, const SceneD& D, int bi)
     if (!S.material_contact) return;
     long long i = (long long)bi * blockDim.x + threadIdx.x;
     if (i <= (long long)D.hmask) D.bcount[i] = 0;
-    if (i == 0) *D.hmax = 0;
+    // largest brick speed bound (grid-stride over the bricks, one atomic per
+    // block); the maximum of non-negative floats is taken on their bit patterns, so
+    // it does not depend on the order of the atomics.  Reset by the ranking pass.
+    const long long nb = (long long)S.cbx * S.cby * S.cbz;
+    float m = 0.0f;
+    const long long stride = ((long long)D.hmask + 256) / 256 * blockDim.x; // this scene's blocks
+    for (long long b = i; b < nb; b += stride) m = fmaxf(m, D.aabb[b * 8 + 6]);
+    for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0 && m > 0.0f) atomicMax(D.hmax, __float_as_int(m));
 }
 
 DEV void bin_insert_body(const SceneK& S, const SceneD& D, int bi)
@@ -267,6 +307,7 @@ DEV void bin_insert_body(const SceneK& S, const SceneD& D, int bi)
 DEV void bin_rank_body(const SceneK& S, const SceneD& D, int bi)
 {
     if (!S.material_contact) return;
+    if (bi == 0 && threadIdx.x == 0) *D.hmax = 0; // binning read it; next substep gathers anew
     const int brick = D.active[bi];
     const int nc = D.bcand[bi];
     if (!nc) return;
@@ -535,40 +576,6 @@ DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
     }
 }
 
-// First global candidate index of every active brick (exclusive scan of the
-// candidate counts in active-brick order), one block of TL_SCAN_T threads per
-// scene; each thread scans a contiguous run of bricks.
-#define TL_SCAN_T 1024
-DEV void cscan_body(const SceneK& S, const SceneD& D, int bi)
-{
-    if (!S.material_contact) return;
-    __shared__ int s_w[TL_SCAN_T / 64];
-    const int n = D.n_active;
-    const int per = (n + TL_SCAN_T - 1) / TL_SCAN_T;
-    const int i0 = threadIdx.x * per, i1 = min(n, i0 + per);
-    int loc = 0;
-#pragma unroll 8
-    for (int i = i0; i < i1; i++) loc += D.bcand[i];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    int incl = loc;
-    for (int o = 1; o < 64; o <<= 1) {
-        int t = __shfl_up(incl, o, 64);
-        if (lane >= o) incl += t;
-    }
-    if (lane == 63) s_w[wv] = incl;
-    __syncthreads();
-    int before = 0;
-    for (int w = 0; w < wv; w++) before += s_w[w];
-    int run = before + incl - loc;
-#pragma unroll 8
-    for (int i = i0; i < i1; i++) {
-        const int c = D.bcand[i];
-        D.coff[i] = run;
-        run += c;
-    }
-    if (threadIdx.x == TL_SCAN_T - 1) D.coff[n] = run;
-}
-
 #define TL_WRAP(NAME, PARAMS, ARGS)                                                                           \
     __global__ __launch_bounds__(256) void k_##NAME(SceneK S, SceneD D PARAMS)                              \
     {                                                                                                       \
@@ -584,7 +591,6 @@ DEV void cscan_body(const SceneK& S, const SceneD& D, int bi)
 #define TL_COMMA ,
 TL_WRAP(cellmask, TL_COMMA int with_static TL_COMMA int force, TL_COMMA with_static TL_COMMA force)
 TL_WRAP(cand, TL_COMMA int force, TL_COMMA force)
-TL_WRAP(hmax, , )
 TL_WRAP(bzero, , )
 TL_WRAP(bin_insert, , )
 TL_WRAP(bin_rank, , )
@@ -596,6 +602,7 @@ __global__ __launch_bounds__(TL_SCAN_T) void k_cscan_b(const SceneK* __restrict_
     const int2 t = it[blockIdx.x];
     cscan_body(Ks[t.x], Ds[t.x], t.y);
 }
+
 
 template <class KP, class KB, class... Args>
 static hipError_t tl_run_t(const TlLaunch& L, int kind, int plain_blocks, int threads, KP kp, KB kb, Args... args)
@@ -638,9 +645,6 @@ hipError_t tl_launch_contact(const TlLaunch* L)
     const int nbrick = L->S ? L->D->n_active : 0;
     if (L->S && nbrick == 0) return hipSuccess;
     hipError_t e = tl_run(*L, IT_BUCKET, L->S ? (int)(((long long)L->D->hmask + 256) / 256) : 0, k_bzero, k_bzero_b);
-    if (e != hipSuccess) return e;
-    const long long nbr = L->S ? (long long)L->S->cbx * L->S->cby * L->S->cbz : 0;
-    e = tl_run(*L, IT_BFLAG, (int)((nbr + 255) / 256), k_hmax, k_hmax_b);
     if (e != hipSuccess) return e;
     e = tl_run(*L, IT_BRICK, nbrick, k_bin_insert, k_bin_insert_b);
     if (e != hipSuccess) return e;

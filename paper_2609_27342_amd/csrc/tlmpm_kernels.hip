@@ -1137,8 +1137,8 @@ DEV void labels_body(const SceneK& S, const SceneD& D, int bi, int j)
         }
     }
     if (__syncthreads_or(any) && threadIdx.x == 0) {
-        *D.dirty = 1;
-        D.bdirty[brick] = 1;
+        // label-change flags carry the substep stamp: no clearing pass needed
+        D.bdirty[brick] = D.ctr[0];
     }
 }
 
@@ -1154,6 +1154,7 @@ DEV void slots_body(const SceneK& S, const SceneD& D, int bi, int dst, int src, 
     int lid = (int)(id & 63);
     int hx = (int)(nb % S.nbx), hy = (int)((nb / S.nbx) % S.nby), hz = (int)(nb / ((long long)S.nbx * S.nby));
     bool rebuild = force != 0;
+    const int stamp = D.ctr[0];
     if (!rebuild) {
         // a node depends on the cells of bricks h - {0,1}^3
         int any = 0;
@@ -1161,7 +1162,7 @@ DEV void slots_body(const SceneK& S, const SceneD& D, int bi, int dst, int src, 
         for (int d = 0; d < 8; d++) {
             int bx = hx - (d & 1), by = hy - ((d >> 1) & 1), bz = hz - ((d >> 2) & 1);
             if (bx < 0 || by < 0 || bz < 0 || bx >= S.cbx || by >= S.cby || bz >= S.cbz) continue;
-            any |= D.bdirty[((long long)bz * S.cby + by) * S.cbx + bx];
+            any |= D.bdirty[((long long)bz * S.cby + by) * S.cbx + bx] == stamp;
         }
         rebuild = any != 0;
     }
@@ -1230,7 +1231,7 @@ DEV void mixed_body(const SceneK& S, const SceneD& D, int bi, int force)
 {
     __shared__ int s_rounds;
     const int brick = D.active[bi];
-    if (!force && !D.bdirty[brick]) return;
+    if (!force && D.bdirty[brick] != D.ctr[0]) return;
     if (threadIdx.x == 0) s_rounds = 1;
     bool mixed = false;
     for (int c = threadIdx.x; c < TL_CELLS; c += blockDim.x) {
@@ -1238,12 +1239,19 @@ DEV void mixed_body(const SceneK& S, const SceneD& D, int bi, int force)
         const int b0 = D.cell_start[cs], b1 = D.cell_start[cs + 1];
         if (b1 <= b0) {
             D.ccode[cs] = TL_CC_EMPTY;
+            if (S.material_contact) D.cmask[cs] = 0;
             continue;
         }
         const uint32_t k0 = slot_key(S, D.code[b0]);
         bool cm = false;
-        for (int p = b0 + 1; p < b1; p++) cm |= slot_key(S, D.code[p]) != k0;
+        uint32_t orm = k0; // OR of the codes of the cell (material contact candidates)
+        for (int p = b0 + 1; p < b1; p++) {
+            const uint32_t k = slot_key(S, D.code[p]);
+            cm |= k != k0;
+            orm |= k;
+        }
         D.ccode[cs] = cm ? TL_CC_MIXED : k0;
+        if (S.material_contact) D.cmask[cs] = orm;
         mixed |= cm;
     }
     const int m = __syncthreads_or(mixed);
@@ -1296,14 +1304,6 @@ DEV void resetD_body(const SceneK& S, const SceneD& D, int bi)
     if (!D.tinfo[2]) return;
     long long i = (long long)bi * blockDim.x + threadIdx.x;
     if (i < S.N) D.D[i] = 0.0f;
-}
-
-// clears the label-change flags after the slot tables and candidates caught up
-DEV void clear_flags_body(const SceneK& S, const SceneD& D, int bi)
-{
-    long long i = (long long)bi * blockDim.x + threadIdx.x;
-    if (i < (long long)S.cbx * S.cby * S.cbz) D.bdirty[i] = 0;
-    if (bi == 0 && threadIdx.x == 0) *D.dirty = 0;
 }
 
 // clears the interval wrench accumulator
@@ -1412,7 +1412,6 @@ TL_WRAP(mixed, 256, TL_COMMA int force, TL_COMMA force)
 TL_WRAP(aabb, 256, , )
 TL_WRAP(wrench, 256, , )
 TL_WRAP(resetD, 256, , )
-TL_WRAP(clear_flags, 256, , )
 TL_WRAP(clear_wacc, 64, , )
 
 __global__ __launch_bounds__(TL_WG) void k_p2g(SceneK S, SceneD D, KA_Args A) { p2g_body(S, D, blockIdx.x, A); }
@@ -1504,11 +1503,6 @@ hipError_t tl_launch_wrench(const TlLaunch* L)
 hipError_t tl_launch_resetD(const TlLaunch* L)
 {
     return tl_run(*L, IT_PART, plain_parts(*L), 256, k_resetD, k_resetD_b);
-}
-
-hipError_t tl_launch_clear_flags(const TlLaunch* L)
-{
-    return tl_run(*L, IT_BFLAG, plain_bflags(*L), 256, k_clear_flags, k_clear_flags_b);
 }
 
 hipError_t tl_launch_clear_wacc(const TlLaunch* L)
