@@ -153,7 +153,7 @@ Dims dims_of(const tlmpm_scene_desc* d)
 
 struct Offsets {
     size_t X, u, v, H, code, code_prev, D, perm, E, m, V0, cell_start, active, cnt0, cnt1, sc0, sc1, p2g, rs, hist,
-        aabb, wpart, wacc, Jmat, Jrig, brig, bmixed, ccode, gmeta, gperm, bround, tools, tinfo, ctr, bact, status, dirty, bdirty, pcell, cand_idx, coff, gcand, cmask, cstatic, bcand, hbin, hmax, bcount, bids, cslot, brec, htab, hnext, orec, ph_n, ph_q, ph_u,
+        aabb, wpart, wacc, Jmat, Jrig, brig, bmixed, ccode, ckeys, gmeta, gperm, bround, tools, tinfo, ctr, bact, status, dirty, bdirty, pcell, cand_idx, coff, gcand, cmask, cstatic, bcand, hbin, hmax, bcount, bids, cslot, brec, htab, hnext, orec, ph_n, ph_q, ph_u,
         total;
     uint32_t hmask;
 };
@@ -227,6 +227,7 @@ Offsets plan(const tlmpm_scene_desc* d, long long n_active)
     o.brig = L.take((size_t)g.n_bricks * 4);
     o.bmixed = L.take((size_t)g.n_bricks * 4);
     o.ccode = L.take((size_t)g.n_bricks * TL_CELLS * 4);
+    o.ckeys = L.take((size_t)g.n_bricks * TL_CELLS * TL_CKEYS * 4);
     o.gmeta = L.take((size_t)n_active * TL_CELLS * TL_GMAX * 4);
     o.gperm = L.take(N * 4);
     o.bround = L.take((size_t)n_active * 4);
@@ -464,6 +465,7 @@ extern "C" tlmpm_status tlmpm_create_scene(const tlmpm_scene_desc* d, void* ws, 
     D.brig = (int*)(base + o.brig);
     D.bmixed = (int*)(base + o.bmixed);
     D.ccode = (uint32_t*)(base + o.ccode);
+    D.ckeys = (uint32_t*)(base + o.ckeys);
     D.gmeta = (int*)(base + o.gmeta);
     D.gperm = (int*)(base + o.gperm);
     D.bround = (int*)(base + o.bround);

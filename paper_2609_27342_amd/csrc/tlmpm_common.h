@@ -33,7 +33,9 @@
 #define TL_ST_CONTACT 16
 
 #define TL_CC_EMPTY 0xFFFFFFFEu // cell summary: no particle
-#define TL_CC_MIXED 0xFFFFFFFFu // cell summary: particles of two or more slot keys
+#define TL_CC_MIXED 0xFFFFFFFFu // cell summary: more than TL_CKEYS slot keys (scan the particles)
+#define TL_CC_FEW 0xC0000000u   // cell summary: TL_CC_FEW | n, 2 <= n <= TL_CKEYS keys listed in ckeys
+#define TL_CKEYS 4
 #define TL_GMAX 8              // same-code groups (of <= 8 particles) per cell in a mixed brick
 #define TL_PCAP 16             // persistent pair springs kept per particle (all its partners)
 #define TL_PLANES 8            // lanes per candidate in the pair search
@@ -118,6 +120,7 @@ struct SceneD {
     int* brig;     // [bricks] the brick was within reach of a rigid body this substep
     int* bmixed;   // [bricks] a cell of the brick holds two side codes
     uint32_t* ccode; // [bricks * 64] (sorted cell order) the one slot key of a cell, or TL_CC_*
+    uint32_t* ckeys; // [bricks * 64][TL_CKEYS] ascending keys of a cell summarised as TL_CC_FEW
     int* gmeta;      // [active bricks][64 cells][TL_GMAX] groups of a mixed brick: offset << 4 | count
     int* gperm;      // [N] particles of mixed bricks in group order, over each cell's range
     int* bround;     // [active bricks] rounds (largest group count of a cell) of a mixed brick

@@ -1209,11 +1209,19 @@ DEV void slots_body(const SceneK& S, const SceneD& D, int bi, int dst, int src, 
         }
         for (int d = 0; d < 8; d++) {
             if (cc[d] == TL_CC_EMPTY) continue;
-            if (cc[d] != TL_CC_MIXED) {
+            if (cc[d] < TL_CC_FEW) {
                 insert(cc[d]);
-                continue;
+            } else if (cc[d] != TL_CC_MIXED) {
+                const int n = (int)(cc[d] & 7u);
+                uint32_t kk[TL_CKEYS];
+#pragma unroll
+                for (int k = 0; k < TL_CKEYS; k++) kk[k] = k < n ? D.ckeys[cell[d] * TL_CKEYS + k] : 0u;
+#pragma unroll
+                for (int k = 0; k < TL_CKEYS; k++)
+                    if (k < n) insert(kk[k]);
+            } else {
+                for (int p = D.cell_start[cell[d]]; p < D.cell_start[cell[d] + 1]; p++) insert(slot_key(S, D.code[p]));
             }
-            for (int p = D.cell_start[cell[d]]; p < D.cell_start[cell[d] + 1]; p++) insert(slot_key(S, D.code[p]));
         }
     }
     if (over) atomicOr(D.status, TL_ST_SLOT);
@@ -1243,14 +1251,37 @@ DEV void mixed_body(const SceneK& S, const SceneD& D, int bi, int force)
             continue;
         }
         const uint32_t k0 = slot_key(S, D.code[b0]);
-        bool cm = false;
         uint32_t orm = k0; // OR of the codes of the cell (material contact candidates)
+        uint32_t ks[TL_CKEYS] = {k0, 0u, 0u, 0u};
+        int nk = 1;
+        bool many = false;
+#pragma unroll 4
         for (int p = b0 + 1; p < b1; p++) {
             const uint32_t k = slot_key(S, D.code[p]);
-            cm |= k != k0;
             orm |= k;
+            // distinct keys in ascending order (insertion; at most TL_CKEYS kept)
+            bool seen = false;
+#pragma unroll
+            for (int q = 0; q < TL_CKEYS; q++) seen |= q < nk && ks[q] == k;
+            if (seen) continue;
+            if (nk == TL_CKEYS) {
+                many = true;
+                continue;
+            }
+#pragma unroll
+            for (int q = TL_CKEYS - 1; q > 0; q--)
+                if (q <= nk && ks[q - 1] > k) {
+                    ks[q] = ks[q - 1];
+                    ks[q - 1] = k;
+                } else if (q == nk) {
+                    ks[q] = k;
+                }
+            nk++;
         }
-        D.ccode[cs] = cm ? TL_CC_MIXED : k0;
+        const bool cm = nk > 1 || many;
+        D.ccode[cs] = !cm ? k0 : (many ? TL_CC_MIXED : (TL_CC_FEW | (uint32_t)nk));
+        if (cm && !many)
+            for (int q = 0; q < nk; q++) D.ckeys[cs * TL_CKEYS + q] = ks[q];
         if (S.material_contact) D.cmask[cs] = orm;
         mixed |= cm;
     }
