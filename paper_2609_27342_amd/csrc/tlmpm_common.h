@@ -17,7 +17,7 @@
 #define TL_CELLS 64            // cells per brick
 #define TL_BOXN 125            // nodes of a brick's (TL_B + 1)^3 box
 #define TL_SCAP_MAX 16         // largest per-node capacity of logical grids (slots)
-#define TL_BOX_SLOTS 512       // slots of one brick box held in LDS
+#define TL_BOX_SLOTS 640       // slots of one brick box held in LDS
 #define TL_MAX_TOOLS 4          // tools per scene (rigid-history slots 1..4; slot 0 = floor)
 #define TL_WG 512              // threads per brick workgroup: 8 waves = 8 parity classes
 

@@ -156,7 +156,7 @@ DEV void gather_node(const SceneK& S, const int* nb, const float* __restrict__ p
     const int lx = X & 3, ly = Y & 3, lz = Z & 3;
     // contributor d: the brick at home - (d & 1, d >> 1 & 1, d >> 2 & 1), which
     // holds the node at box position (l + 4 * offset)
-    long long cbase[8];
+    unsigned cbase[8]; // node-slot record index of each contributor (32 bits; checked at creation)
     unsigned valid = 0;
     for (int d = 0; d < 8; d++) {
         int dx = d & 1, dy = (d >> 1) & 1, dz = (d >> 2) & 1;
@@ -166,7 +166,7 @@ DEV void gather_node(const SceneK& S, const int* nb, const float* __restrict__ p
         const int ai = nb[((Z >> 2) - dz + 1) * 9 + ((Y >> 2) - dy + 1) * 3 + ((X >> 2) - dx + 1)];
         if (ai < 0) continue;
         const int pn = (lx + 4 * dx) + 5 * (ly + 4 * dy) + 25 * (lz + 4 * dz);
-        cbase[d] = (long long)ai * S.scap * TL_BOXN + pn;
+        cbase[d] = (unsigned)ai * (unsigned)(S.scap * TL_BOXN) + (unsigned)pn;
         valid |= 1u << d;
     }
     for (int s = 0; s < c; s++) {
@@ -176,7 +176,7 @@ DEV void gather_node(const SceneK& S, const int* nb, const float* __restrict__ p
 #pragma unroll
         for (int d = 0; d < 8; d++) {
             if (!(valid & (1u << d))) continue;
-            const float4* pp = (const float4*)(part + (cbase[d] + (long long)s * TL_BOXN) * QP);
+            const float4* pp = (const float4*)(part + (size_t)(cbase[d] + (unsigned)(s * TL_BOXN)) * QP);
 #pragma unroll
             for (int q4 = 0; q4 < QP / 4; q4++) {
                 float4 v4 = pp[q4];
@@ -1445,9 +1445,13 @@ TL_WRAP(wrench, 256, , )
 TL_WRAP(resetD, 256, , )
 TL_WRAP(clear_wacc, 64, , )
 
-__global__ __launch_bounds__(TL_WG) void k_p2g(SceneK S, SceneD D, KA_Args A) { p2g_body(S, D, blockIdx.x, A); }
-__global__ __launch_bounds__(TL_WG) void k_p2g_b(const SceneK* __restrict__ Ks, const SceneD* __restrict__ Ds,
-                                                 const int2* __restrict__ it, KA_Args A)
+// at most 80 VGPRs: three 512-thread workgroups per CU
+__global__ __launch_bounds__(TL_WG) __attribute__((amdgpu_waves_per_eu(6))) void k_p2g(SceneK S, SceneD D, KA_Args A)
+{
+    p2g_body(S, D, blockIdx.x, A);
+}
+__global__ __launch_bounds__(TL_WG) __attribute__((amdgpu_waves_per_eu(6))) void k_p2g_b(
+    const SceneK* __restrict__ Ks, const SceneD* __restrict__ Ds, const int2* __restrict__ it, KA_Args A)
 {
     const int2 t = it[blockIdx.x];
     p2g_body(Ks[t.x], Ds[t.x], t.y, A);
