@@ -225,15 +225,18 @@ DEV void cur_pos(const SceneK& S, const SceneD& D, long long p, float x[3])
     x[2] = D.X[2 * S.N + p] + D.u[2 * S.N + p];
 }
 
-// Candidate record: {id, code, cell, R}, {x, m}, {v, 0} (three float4).
+// Candidate record: {id, code, reference cell x | y << 16, R}, {x, m}, {v, cell z}
+// (three float4; cells per axis are below 2^16).
 DEV void make_rec(const SceneK& S, const SceneD& D, int p, const float x[3], float4 r[3])
 {
     float m = S.m_uniform ? S.m0 : D.m[p];
     float V0 = S.v_uniform ? S.V0 : D.V0[p];
-    r[0] = make_float4(__int_as_float(p), __uint_as_float(D.code[p]), __int_as_float(D.pcell[p]),
+    int c[3];
+    slot_cell(S, D.pcell[p], c[0], c[1], c[2]); // reference cell, packed 16 + 16 bits and 16 bits
+    r[0] = make_float4(__int_as_float(p), __uint_as_float(D.code[p]), __int_as_float(c[0] | (c[1] << 16)),
                        0.5f * S.s_R * cbrtf(V0));
     r[1] = make_float4(x[0], x[1], x[2], m);
-    r[2] = make_float4(D.v[p], D.v[S.N + p], D.v[2 * S.N + p], 0.0f);
+    r[2] = make_float4(D.v[p], D.v[S.N + p], D.v[2 * S.N + p], __int_as_float(c[2]));
 }
 
 // Bins the candidates of every brick, in two passes that make the content of a
@@ -491,7 +494,12 @@ DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
                 }
                 uint32_t kq = ckey(S, __float_as_uint(rec[0].y));
                 int cq[3];
-                slot_cell(S, __float_as_int(rec[0].z), cq[0], cq[1], cq[2]);
+                {
+                    const int xy = __float_as_int(rec[0].z);
+                    cq[0] = xy & 0xFFFF;
+                    cq[1] = (xy >> 16) & 0xFFFF;
+                    cq[2] = __float_as_int(rec[2].w);
+                }
                 bool near = abs(cp[0] - cq[0]) <= 1 && abs(cp[1] - cq[1]) <= 1 && abs(cp[2] - cq[2]) <= 1;
                 if (near && !cconflict(kp, kq)) return; // reading R17 exclusion
                 PState sq = pstate_of(rec);
