@@ -153,6 +153,18 @@ struct SceneD {
     float* ph_u;        // [2][N][TL_PCAP][3] spring, oriented for the pair's lower index
 };
 
+// Workgroups are dealt to the 8 XCDs (each with its own L2) round-robin by
+// dispatch index.  xcd_order(b, G) maps dispatch index b of G to a work index such
+// that the workgroups of one XCD take one contiguous range of work items, so
+// neighbouring items share an L2.  Used by the batched P2G / G2P launches, whose
+// many small scenes fit the L2s (measured faster there; slower for one large
+// scene, which keeps the dispatch order).
+__device__ __forceinline__ int xcd_order(int b, int G)
+{
+    const int r = b & 7, q = G >> 3, extra = G & 7;
+    return r * q + (r < extra ? r : extra) + (b >> 3);
+}
+
 // Value of lane (lane ^ M), M in {1, 2, 4}, by DPP row moves (no LDS traffic):
 // quad permutations for 1 and 2; for 4, lanes with bit 2 clear read lane + 4
 // (row shift left) and the others lane - 4 (row shift right), all within a row of

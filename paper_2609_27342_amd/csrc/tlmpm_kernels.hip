@@ -1453,14 +1453,17 @@ __global__ __launch_bounds__(TL_WG) __attribute__((amdgpu_waves_per_eu(6))) void
 __global__ __launch_bounds__(TL_WG) __attribute__((amdgpu_waves_per_eu(6))) void k_p2g_b(
     const SceneK* __restrict__ Ks, const SceneD* __restrict__ Ds, const int2* __restrict__ it, KA_Args A)
 {
-    const int2 t = it[blockIdx.x];
+    const int2 t = it[xcd_order(blockIdx.x, gridDim.x)];
     p2g_body(Ks[t.x], Ds[t.x], t.y, A);
 }
-__global__ __launch_bounds__(TL_WG) void k_g2p(SceneK S, SceneD D, int cur) { g2p_body(S, D, blockIdx.x, cur); }
+__global__ __launch_bounds__(TL_WG) void k_g2p(SceneK S, SceneD D, int cur)
+{
+    g2p_body(S, D, blockIdx.x, cur);
+}
 __global__ __launch_bounds__(TL_WG) void k_g2p_b(const SceneK* __restrict__ Ks, const SceneD* __restrict__ Ds,
                                                  const int2* __restrict__ it, int cur)
 {
-    const int2 t = it[blockIdx.x];
+    const int2 t = it[xcd_order(blockIdx.x, gridDim.x)];
     g2p_body(Ks[t.x], Ds[t.x], t.y, cur);
 }
 
