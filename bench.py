@@ -141,6 +141,7 @@ def bench_batched(args, K, Wm):
     # (b) batched
     gs = fresh()
     bt = tlmpm.Batch(gs)
+    bt.graphs(args.graphs)
 
     def run(j0, j1):
         per = [batch_calls(s, j0, j1) for s in scenes]
@@ -181,7 +182,7 @@ def bench_batched(args, K, Wm):
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "batched", "scenes": len(scenes), "particles": n, "dt": scenes[0]["params"]["dt"],
-                   "material_contact": True, "path": "batched",
+                   "material_contact": True, "path": "batched+graph" if args.graphs else "batched",
                    "plain": {"value": plain_value, "ms_per_step": t_plain * 1e3 / K, "status": status_plain},
                    "batched_over_plain": value / plain_value},
         "status": status,
@@ -244,6 +245,8 @@ def main():
     ap.add_argument("--tick", type=int, default=100, help="served: substeps per batched iteration")
     ap.add_argument("--budget-gb", type=float, default=200.0, help="served: device bytes for running rollouts")
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--graphs", action="store_true",
+                    help="replay pairs of substeps as captured HIP graphs (tlmpm_set_graphs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (5 times) and exit; used to scale "
                          "hardware traffic counters")
@@ -279,7 +282,9 @@ def main():
     n = scene["X"].shape[0]
     torch.cuda.set_device(0)
     g = tlmpm.Scene(scene)
-    print(f"[bench] workload={args.workload} n={n} warmup={Wm} steps={K}", file=sys.stderr, flush=True)
+    g.graphs(args.graphs)
+    print(f"[bench] workload={args.workload} n={n} warmup={Wm} steps={K} graphs={args.graphs}", file=sys.stderr,
+          flush=True)
     run_steps(g, scene, 0, Wm)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -316,7 +321,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "particles": n, "dt": scene["params"]["dt"],
-                   "material_contact": bool(scene["params"]["material_contact"]), "path": "plain"},
+                   "material_contact": bool(scene["params"]["material_contact"]),
+                   "path": "graph" if args.graphs else "plain"},
         "status": status,
         "roofline": roofline,
         "cpu_baseline": cpu,

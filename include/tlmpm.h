@@ -159,6 +159,15 @@ tlmpm_status tlmpm_get_status(tlmpm_scene* scene, int32_t* status);
  * largest count at one node (Sec. III-G, compact slots).  Synchronises. */
 tlmpm_status tlmpm_slot_stats(tlmpm_scene* scene, int64_t* total_slots, int32_t* max_per_node);
 
+/* HIP graph replay of substeps.  While enabled, a tlmpm_step of n >= 3 substeps
+ * runs its first substep as plain launches and the following pairs of substeps as
+ * replays of a captured graph of those launches (one graph per combination of
+ * label pass, tool contact and rigid contact, built on first use and kept until
+ * the scene is destroyed).  Results are bitwise those of plain launches; every
+ * per-substep value the kernels read is in device memory.  Off while kernel timing
+ * is on.  Default: off. */
+tlmpm_status tlmpm_set_graphs(tlmpm_scene* scene, int32_t enable);
+
 /* Kernel timing (diagnostics).  While enabled, every kernel the scene launches is
  * bracketed by HIP events on the scene's stream.  tlmpm_profile_read synchronises
  * and returns, per kernel class (0 P2G, 1 grid update + G2P, 2 labels, 3 slot
@@ -207,6 +216,9 @@ tlmpm_status tlmpm_batch_step(tlmpm_batch* batch, const tlmpm_tool* tools, const
 
 /* Waits for the batch's queued work. */
 tlmpm_status tlmpm_batch_sync(tlmpm_batch* batch);
+
+/* HIP graph replay of the batch's substeps, as tlmpm_set_graphs. */
+tlmpm_status tlmpm_batch_set_graphs(tlmpm_batch* batch, int32_t enable);
 
 /* Kernel timing of the batch's launches, as tlmpm_profile_enable / _read. */
 tlmpm_status tlmpm_batch_profile_enable(tlmpm_batch* batch, int32_t enable);

@@ -19,15 +19,15 @@
 
 extern "C" {
 hipError_t tl_launch_p2g(const TlLaunch*, int do_p2g, int tabs_differ, int cur, int rsb);
-hipError_t tl_launch_rigid(const TlLaunch*, int j);
+hipError_t tl_launch_rigid(const TlLaunch*);
 hipError_t tl_launch_mixed(const TlLaunch*, int force);
 hipError_t tl_launch_g2p(const TlLaunch*, int cur);
-hipError_t tl_launch_labels(const TlLaunch*, int j);
+hipError_t tl_launch_labels(const TlLaunch*);
 hipError_t tl_launch_slots(const TlLaunch*, int dst, int src, int force);
 hipError_t tl_launch_aabb(const TlLaunch*);
 hipError_t tl_launch_wrench(const TlLaunch*);
 hipError_t tl_launch_resetD(const TlLaunch*);
-hipError_t tl_launch_clear_wacc(const TlLaunch*);
+hipError_t tl_launch_call_start(const TlLaunch*);
 hipError_t tl_launch_cellmask(const TlLaunch*, int with_static, int force);
 hipError_t tl_launch_cand(const TlLaunch*, int force);
 hipError_t tl_launch_contact(const TlLaunch*);
@@ -48,6 +48,21 @@ static tlmpm_status fail(tlmpm_status st, const std::string& msg)
         hipError_t e_ = (expr);                                                                           \
         if (e_ != hipSuccess) return fail(TLMPM_E_DEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
     } while (0)
+
+// Captured pairs of substeps, by the host-side choices they were recorded with
+// (label pass, tool contact, rigid contact, slot-table buffer in use).  Every
+// per-substep value the kernels need is in device memory (substep index, stamps,
+// tools), so a replay equals the launches it was captured from.
+struct GraphCache {
+    bool on = false;
+    hipStream_t cap = nullptr; // capture stream (the caller's may be the null stream)
+    std::vector<std::pair<int, hipGraphExec_t>> e;
+    ~GraphCache()
+    {
+        for (auto& x : e) (void)hipGraphExecDestroy(x.second);
+        if (cap) (void)hipStreamDestroy(cap);
+    }
+};
 
 // Kernel timing (diagnostics): pairs of events around launches, per class.
 struct Timing {
@@ -74,6 +89,7 @@ struct tlmpm_scene {
     int in_batch = 0; // member of a live batch: single-scene calls are refused
     std::vector<int> active_host;
     Timing prof;
+    GraphCache graphs;
 };
 
 // Brackets one launch with events when timing is on.
@@ -583,6 +599,13 @@ static tlmpm_status timing_read(Timing& tm, int n_classes, double* ms, int64_t* 
     return TLMPM_OK;
 }
 
+extern "C" tlmpm_status tlmpm_set_graphs(tlmpm_scene* sc, int32_t enable)
+{
+    if (!sc) return fail(TLMPM_E_INVALID, "null scene");
+    sc->graphs.on = enable != 0;
+    return TLMPM_OK;
+}
+
 extern "C" tlmpm_status tlmpm_profile_enable(tlmpm_scene* sc, int32_t enable)
 {
     if (!sc) return fail(TLMPM_E_INVALID, "null scene");
@@ -619,7 +642,7 @@ struct Exec {
 // label pass over the tools flagged TL_TOOL_LABELS (uploaded with their counts),
 // then slot-table maintenance and contact candidates of the bricks whose codes
 // changed (no host synchronisation)
-static tlmpm_status label_pass(Exec& X, int j, bool reset_D)
+static tlmpm_status label_pass(Exec& X, bool reset_D)
 {
     if (reset_D) {
         ProfScope ps(X.prof, 5);
@@ -627,7 +650,7 @@ static tlmpm_status label_pass(Exec& X, int j, bool reset_D)
     }
     {
         ProfScope ps(X.prof, 2);
-        HIPCHK(tl_launch_labels(&X.L, j));
+        HIPCHK(tl_launch_labels(&X.L));
     }
     {
         ProfScope ps(X.prof, 3);
@@ -651,37 +674,97 @@ struct CallFlags {
     bool any_labels = false, any_new = false, any_contact_tool = false, any_rigid = false;
 };
 
-// n_substeps substeps of the whole path
-static tlmpm_status run_substeps(Exec& X, int n_substeps, const CallFlags& f)
+// one substep of the whole path
+static tlmpm_status one_substep(Exec& X, const CallFlags& f, bool first)
 {
-    if (f.any_contact_tool) HIPCHK(tl_launch_clear_wacc(&X.L));
-    for (int j = 0; j < n_substeps; j++) {
-        if (f.any_labels) {
-            tlmpm_status s = label_pass(X, j, f.any_new && j == 0);
+    if (f.any_labels) {
+        tlmpm_status s = label_pass(X, f.any_new && first);
+        if (s) return s;
+    }
+    if (X.L.any_material) {
+        ProfScope ps(X.prof, 4);
+        HIPCHK(tl_launch_contact(&X.L));
+    }
+    if (f.any_rigid) {
+        ProfScope ps(X.prof, 5);
+        HIPCHK(tl_launch_rigid(&X.L));
+    }
+    if (f.any_contact_tool) {
+        ProfScope ps(X.prof, 5);
+        HIPCHK(tl_launch_wrench(&X.L));
+    }
+    {
+        ProfScope ps(X.prof, 0);
+        HIPCHK(tl_launch_p2g(&X.L, 1, X.cur != X.rsb ? 1 : 0, X.cur, X.rsb));
+    }
+    {
+        ProfScope ps(X.prof, 1);
+        HIPCHK(tl_launch_g2p(&X.L, X.cur));
+    }
+    X.pending = true;
+    X.rsb = X.cur;
+    return TLMPM_OK;
+}
+
+static tlmpm_status pair_graph(Exec& X, const CallFlags& f, GraphCache& gc, hipGraphExec_t* out)
+{
+    const int key = (f.any_labels ? 1 : 0) | (f.any_contact_tool ? 2 : 0) | (f.any_rigid ? 4 : 0) | (X.cur << 3);
+    for (auto& x : gc.e)
+        if (x.first == key) {
+            *out = x.second;
+            return TLMPM_OK;
+        }
+    if (!gc.cap) HIPCHK(hipStreamCreateWithFlags(&gc.cap, hipStreamNonBlocking));
+    // record the launches on the capture stream (nothing runs); replays go to the
+    // scene's stream, ordered after the work queued there
+    Exec Y = X;
+    Y.prof = nullptr;
+    Y.L.st = gc.cap;
+    HIPCHK(hipStreamBeginCapture(Y.L.st, hipStreamCaptureModeThreadLocal));
+    tlmpm_status s = one_substep(Y, f, false);
+    if (!s) s = one_substep(Y, f, false);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(Y.L.st, &g);
+    if (s) {
+        if (g) (void)hipGraphDestroy(g);
+        return s;
+    }
+    if (e != hipSuccess) return fail(TLMPM_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    if (Y.cur != X.cur || Y.rsb != X.rsb) {
+        (void)hipGraphDestroy(g);
+        return fail(TLMPM_E_DEVICE, "graph capture: slot-table state not periodic");
+    }
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiateWithFlags(&ex, g, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(TLMPM_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+    gc.e.push_back({key, ex});
+    *out = ex;
+    return TLMPM_OK;
+}
+
+// n_substeps substeps of the whole path.  With graphs on (and no kernel timing),
+// the substeps after the first run as replays of a captured pair of substeps.
+static tlmpm_status run_substeps(Exec& X, int n_substeps, const CallFlags& f, GraphCache* gc = nullptr)
+{
+    HIPCHK(tl_launch_call_start(&X.L)); // substep index 0, interval wrench cleared
+    int j = 0;
+    if (n_substeps > 0) {
+        tlmpm_status s = one_substep(X, f, true);
+        if (s) return s;
+        j = 1;
+    }
+    if (gc && gc->on && !(X.prof && X.prof->on) && X.pending && X.cur == X.rsb) {
+        for (; j + 2 <= n_substeps; j += 2) {
+            hipGraphExec_t ex = nullptr;
+            tlmpm_status s = pair_graph(X, f, *gc, &ex);
             if (s) return s;
+            HIPCHK(hipGraphLaunch(ex, X.L.st));
         }
-        if (X.L.any_material) {
-            ProfScope ps(X.prof, 4);
-            HIPCHK(tl_launch_contact(&X.L));
-        }
-        if (f.any_rigid) {
-            ProfScope ps(X.prof, 5);
-            HIPCHK(tl_launch_rigid(&X.L, j));
-        }
-        if (f.any_contact_tool) {
-            ProfScope ps(X.prof, 5);
-            HIPCHK(tl_launch_wrench(&X.L));
-        }
-        {
-            ProfScope ps(X.prof, 0);
-            HIPCHK(tl_launch_p2g(&X.L, 1, X.cur != X.rsb ? 1 : 0, X.cur, X.rsb));
-        }
-        {
-            ProfScope ps(X.prof, 1);
-            HIPCHK(tl_launch_g2p(&X.L, X.cur));
-        }
-        X.pending = true;
-        X.rsb = X.cur;
+    }
+    for (; j < n_substeps; j++) {
+        tlmpm_status s = one_substep(X, f, false);
+        if (s) return s;
     }
     return TLMPM_OK;
 }
@@ -740,7 +823,7 @@ extern "C" tlmpm_status tlmpm_assign_labels(tlmpm_scene* sc, const tlmpm_blade* 
     tlmpm_status s = upload_tools(sc, t, n_blades, tinfo);
     if (s) return s;
     Exec X = single_exec(sc);
-    s = label_pass(X, 0, any_new);
+    s = label_pass(X, any_new);
     single_done(sc, X);
     return s;
 }
@@ -810,7 +893,7 @@ extern "C" tlmpm_status tlmpm_step(tlmpm_scene* sc, const tlmpm_tool* tools, int
     s = upload_tools(sc, dtl, n_tools, tinfo);
     if (s) return s;
     Exec X = single_exec(sc);
-    s = run_substeps(X, n_substeps, f);
+    s = run_substeps(X, n_substeps, f, &sc->graphs);
     single_done(sc, X);
     if (s) return s;
     if (wrench && n_tools > 0) {
@@ -1066,6 +1149,7 @@ struct tlmpm_batch {
     double* h_wacc = nullptr;
     hipEvent_t up_done = nullptr;  // the last upload from h_tools finished
     Timing prof;
+    GraphCache graphs;
     ~tlmpm_batch()
     {
         if (h_tools) (void)hipHostFree(h_tools);
@@ -1217,7 +1301,7 @@ extern "C" tlmpm_status tlmpm_batch_step(tlmpm_batch* b, const tlmpm_tool* tools
     X.cur = b->cur;
     X.rsb = b->rsb;
     X.pending = b->pending;
-    tlmpm_status r = run_substeps(X, n_substeps, f);
+    tlmpm_status r = run_substeps(X, n_substeps, f, &b->graphs);
     b->cur = X.cur;
     b->rsb = X.rsb;
     b->pending = X.pending;
@@ -1260,4 +1344,11 @@ extern "C" tlmpm_status tlmpm_batch_profile_read(tlmpm_batch* b, int32_t n_class
 {
     if (!b) return fail(TLMPM_E_INVALID, "null batch");
     return timing_read(b->prof, n_classes, ms, launches);
+}
+
+extern "C" tlmpm_status tlmpm_batch_set_graphs(tlmpm_batch* b, int32_t enable)
+{
+    if (!b) return fail(TLMPM_E_INVALID, "null batch");
+    b->graphs.on = enable != 0;
+    return TLMPM_OK;
 }

@@ -593,16 +593,12 @@ struct KA_Args {
 // Floor and tool contact of every particle of bricks whose AABB can reach a rigid
 // body this substep (Eqs. 14-16, 5): impulses to Jrig, cutting progress D, contact
 // springs, and per-brick wrench sums (wave tree, then waves in order).
-struct KR_Args {
-    int j; // substep index within the call (TL_TOOL_ADVANCE poses)
-};
-
-DEV void rigid_body(const SceneK& S, const SceneD& D, int bi, KR_Args A)
+DEV void rigid_body(const SceneK& S, const SceneD& D, int bi)
 {
     if (!S.floor_on && !D.tinfo[1]) return; // no rigid body touches this scene
     const int n_tools = D.tinfo[0];
     const int stamp = D.ctr[0];
-    const double jdt = (double)A.j * S.dt_d;
+    const double jdt = (double)D.ctr[2] * S.dt_d; // substep of the call (TL_TOOL_ADVANCE poses)
     __shared__ int s_near[TL_MAX_TOOLS + 1];
     __shared__ int s_any;
     __shared__ float s_wr[4][TL_MAX_TOOLS * 6];
@@ -898,6 +894,7 @@ DEV void g2p_body(const SceneK& S, const SceneD& D, int bi, int cur)
         // (no other kernel of the substep reads these after this point)
         D.ctr[0] += 1;
         D.ctr[1] = 1;
+        D.ctr[2] += 1;
     }
     const bool grouped = D.bmixed[brick] != 0; // a cell holds two codes: same-code groups
     const int bx = brick % S.cbx, by = (brick / S.cbx) % S.cby, bz = brick / (S.cbx * S.cby);
@@ -1085,11 +1082,11 @@ DEV DevBlade blade_at(const DevTool& T, double jdt)
     return B;
 }
 
-DEV void labels_body(const SceneK& S, const SceneD& D, int bi, int j)
+DEV void labels_body(const SceneK& S, const SceneD& D, int bi)
 {
     const bool mark_prev = D.ctr[1] != 0; // keep the codes the pending F update needs
     const int n_tools = D.tinfo[0];
-    const double jdt = (double)j * S.dt_d;
+    const double jdt = (double)D.ctr[2] * S.dt_d; // substep of the call (TL_TOOL_ADVANCE poses)
     __shared__ int s_go;
     __shared__ DevBlade s_bl[TL_MAX_TOOLS];
     __shared__ int s_nb;
@@ -1337,10 +1334,12 @@ DEV void resetD_body(const SceneK& S, const SceneD& D, int bi)
     if (i < S.N) D.D[i] = 0.0f;
 }
 
-// clears the interval wrench accumulator
-DEV void clear_wacc_body(const SceneK& S, const SceneD& D, int bi)
+// start of a call: substep index 0 and (with tool contact) a cleared interval
+// wrench accumulator
+DEV void call_start_body(const SceneK& S, const SceneD& D, int bi)
 {
-    if (threadIdx.x < TL_MAX_TOOLS * 6) D.wacc[threadIdx.x] = 0.0;
+    if (threadIdx.x == 0) D.ctr[2] = 0;
+    if (D.tinfo[1] && threadIdx.x < TL_MAX_TOOLS * 6) D.wacc[threadIdx.x] = 0.0;
 }
 
 __global__ void k_fill_f32(float* p, long long n, float v)
@@ -1436,14 +1435,14 @@ DEV void wrench_body(const SceneK& S, const SceneD& D, int bi)
     }
 
 #define TL_COMMA ,
-TL_WRAP(rigid, 256, TL_COMMA KR_Args A, TL_COMMA A)
-TL_WRAP(labels, 256, TL_COMMA int j, TL_COMMA j)
+TL_WRAP(rigid, 256, , )
+TL_WRAP(labels, 256, , )
 TL_WRAP(slots, 256, TL_COMMA int dst TL_COMMA int src TL_COMMA int force, TL_COMMA dst TL_COMMA src TL_COMMA force)
 TL_WRAP(mixed, 256, TL_COMMA int force, TL_COMMA force)
 TL_WRAP(aabb, 256, , )
 TL_WRAP(wrench, 256, , )
 TL_WRAP(resetD, 256, , )
-TL_WRAP(clear_wacc, 64, , )
+TL_WRAP(call_start, 64, , )
 
 // at most 80 VGPRs: three 512-thread workgroups per CU
 __global__ __launch_bounds__(TL_WG) __attribute__((amdgpu_waves_per_eu(6))) void k_p2g(SceneK S, SceneD D, KA_Args A)
@@ -1491,11 +1490,9 @@ static int plain_bflags(const TlLaunch& L)
 }
 
 extern "C" {
-hipError_t tl_launch_rigid(const TlLaunch* L, int j)
+hipError_t tl_launch_rigid(const TlLaunch* L)
 {
-    KR_Args A;
-    A.j = j;
-    return tl_run(*L, IT_BRICK, plain_bricks(*L), 256, k_rigid, k_rigid_b, A);
+    return tl_run(*L, IT_BRICK, plain_bricks(*L), 256, k_rigid, k_rigid_b);
 }
 
 hipError_t tl_launch_p2g(const TlLaunch* L, int do_p2g, int tabs_differ, int cur, int rsb)
@@ -1513,9 +1510,9 @@ hipError_t tl_launch_g2p(const TlLaunch* L, int cur)
     return tl_run(*L, IT_BRICK, plain_bricks(*L), TL_WG, k_g2p, k_g2p_b, cur);
 }
 
-hipError_t tl_launch_labels(const TlLaunch* L, int j)
+hipError_t tl_launch_labels(const TlLaunch* L)
 {
-    return tl_run(*L, IT_BRICK, plain_bricks(*L), 256, k_labels, k_labels_b, j);
+    return tl_run(*L, IT_BRICK, plain_bricks(*L), 256, k_labels, k_labels_b);
 }
 
 hipError_t tl_launch_slots(const TlLaunch* L, int dst, int src, int force)
@@ -1543,9 +1540,9 @@ hipError_t tl_launch_resetD(const TlLaunch* L)
     return tl_run(*L, IT_PART, plain_parts(*L), 256, k_resetD, k_resetD_b);
 }
 
-hipError_t tl_launch_clear_wacc(const TlLaunch* L)
+hipError_t tl_launch_call_start(const TlLaunch* L)
 {
-    return tl_run(*L, IT_SCENE, L->S ? 1 : 0, 64, k_clear_wacc, k_clear_wacc_b);
+    return tl_run(*L, IT_SCENE, L->S ? 1 : 0, 64, k_call_start, k_call_start_b);
 }
 
 hipError_t tl_launch_fill_f32(float* p, long long n, float v, hipStream_t st)

@@ -78,13 +78,15 @@ def lib():
         L.tlmpm_batch_step.argtypes = [vp, C.POINTER(Tool), C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_double)]
         L.tlmpm_batch_sync.argtypes = [vp]
         L.tlmpm_batch_profile_enable.argtypes = [vp, C.c_int32]
+        L.tlmpm_set_graphs.argtypes = [vp, C.c_int32]
+        L.tlmpm_batch_set_graphs.argtypes = [vp, C.c_int32]
         L.tlmpm_batch_profile_read.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.tlmpm_last_error.restype = C.c_char_p
         for f in ("tlmpm_scene_footprint", "tlmpm_create_scene", "tlmpm_destroy_scene", "tlmpm_assign_labels",
                   "tlmpm_step", "tlmpm_read_state", "tlmpm_write_state", "tlmpm_get_status", "tlmpm_slot_stats",
                   "tlmpm_profile_enable", "tlmpm_profile_read", "tlmpm_batch_footprint", "tlmpm_batch_create",
                   "tlmpm_batch_destroy", "tlmpm_batch_step", "tlmpm_batch_sync", "tlmpm_batch_profile_enable",
-                  "tlmpm_batch_profile_read"):
+                  "tlmpm_batch_profile_read", "tlmpm_set_graphs", "tlmpm_batch_set_graphs"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -269,6 +271,10 @@ class Scene:
 
     KERNEL_CLASSES = ("p2g", "g2p", "labels", "slots", "contact", "other")
 
+    def graphs(self, enable=True):
+        """Replay pairs of substeps as captured HIP graphs (bitwise the same results)."""
+        _check(lib().tlmpm_set_graphs(self.h, int(bool(enable))))
+
     def profile(self, enable=True):
         _check(lib().tlmpm_profile_enable(self.h, int(bool(enable))))
 
@@ -345,6 +351,9 @@ class Batch:
 
     def sync(self):
         _check(lib().tlmpm_batch_sync(self.h))
+
+    def graphs(self, enable=True):
+        _check(lib().tlmpm_batch_set_graphs(self.h, int(bool(enable))))
 
     def profile(self, enable=True):
         _check(lib().tlmpm_batch_profile_enable(self.h, int(bool(enable))))
