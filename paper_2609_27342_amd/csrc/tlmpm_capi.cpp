@@ -652,10 +652,7 @@ static tlmpm_status label_pass(Exec& X, bool reset_D)
         ProfScope ps(X.prof, 2);
         HIPCHK(tl_launch_labels(&X.L));
     }
-    {
-        ProfScope ps(X.prof, 3);
-        HIPCHK(tl_launch_mixed(&X.L, 0));
-    }
+    // (cell summaries of the bricks whose codes changed come with the label pass)
     // a pending F update still needs the tables of its re-scatter
     const int dst = (X.pending && X.cur == X.rsb) ? 1 - X.cur : X.cur;
     {

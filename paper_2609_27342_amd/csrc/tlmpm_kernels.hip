@@ -1032,6 +1032,110 @@ DEV void g2p_body(const SceneK& S, const SceneD& D, int bi, int cur)
     }
 }
 
+// ------------------------------------------------------------- mixed-code bricks
+// Per cell of a brick whose codes changed (or of every brick, when forced): the
+// one slot key of its particles (or empty / mixed).  A brick with a mixed cell
+// gets a group table: each of its cells lists its particles by ascending key
+// (input order within a key) in gperm over the cell's range, cut into groups of at
+// most 8 same-key particles; P2G and G2P then take one group per cell and round.
+DEV void cell_summaries(const SceneK& S, const SceneD& D, int bi, int brick)
+{
+    __shared__ int s_rounds;
+    if (threadIdx.x == 0) s_rounds = 1;
+    bool mixed = false;
+    for (int c = threadIdx.x; c < TL_CELLS; c += blockDim.x) {
+        const long long cs = (long long)brick * TL_CELLS + c;
+        const int b0 = D.cell_start[cs], b1 = D.cell_start[cs + 1];
+        if (b1 <= b0) {
+            D.ccode[cs] = TL_CC_EMPTY;
+            if (S.material_contact) D.cmask[cs] = 0;
+            continue;
+        }
+        const uint32_t k0 = slot_key(S, D.code[b0]);
+        uint32_t orm = k0; // OR of the codes of the cell (material contact candidates)
+        uint32_t ks[TL_CKEYS] = {k0, 0u, 0u, 0u};
+        int nk = 1;
+        bool many = false;
+#pragma unroll 4
+        for (int p = b0 + 1; p < b1; p++) {
+            const uint32_t k = slot_key(S, D.code[p]);
+            orm |= k;
+            // distinct keys in ascending order (insertion; at most TL_CKEYS kept)
+            bool seen = false;
+#pragma unroll
+            for (int q = 0; q < TL_CKEYS; q++) seen |= q < nk && ks[q] == k;
+            if (seen) continue;
+            if (nk == TL_CKEYS) {
+                many = true;
+                continue;
+            }
+#pragma unroll
+            for (int q = TL_CKEYS - 1; q > 0; q--)
+                if (q <= nk && ks[q - 1] > k) {
+                    ks[q] = ks[q - 1];
+                    ks[q - 1] = k;
+                } else if (q == nk) {
+                    ks[q] = k;
+                }
+            nk++;
+        }
+        const bool cm = nk > 1 || many;
+        D.ccode[cs] = !cm ? k0 : (many ? TL_CC_MIXED : (TL_CC_FEW | (uint32_t)nk));
+        if (cm && !many)
+            for (int q = 0; q < nk; q++) D.ckeys[cs * TL_CKEYS + q] = ks[q];
+        if (S.material_contact) D.cmask[cs] = orm;
+        mixed |= cm;
+    }
+    const int m = __syncthreads_or(mixed);
+    if (threadIdx.x == 0) D.bmixed[brick] = m;
+    if (!m) return;
+    if (threadIdx.x < TL_CELLS) {
+        const int c = threadIdx.x; // cell slot w * 8 + i
+        const long long cs = (long long)brick * TL_CELLS + c;
+        const int b0 = D.cell_start[cs], b1 = D.cell_start[cs + 1];
+        int* meta = D.gmeta + ((long long)bi * TL_CELLS + c) * TL_GMAX;
+        int ng = 0, pos = 0;
+        uint32_t last = 0;
+        bool first = true;
+        while (pos < b1 - b0) {
+            uint32_t kmin = 0xFFFFFFFFu; // smallest key above the last one
+            for (int p = b0; p < b1; p++) {
+                const uint32_t k = slot_key(S, D.code[p]);
+                if ((first || k > last) && k < kmin) kmin = k;
+            }
+            int gstart = pos;
+            for (int p = b0; p < b1; p++) {
+                if (slot_key(S, D.code[p]) != kmin) continue;
+                D.gperm[b0 + pos] = p;
+                pos++;
+                if (pos - gstart == 8) {
+                    if (ng < TL_GMAX) meta[ng] = (gstart << 4) | 8;
+                    ng++;
+                    gstart = pos;
+                }
+            }
+            if (pos > gstart) {
+                if (ng < TL_GMAX) meta[ng] = (gstart << 4) | (pos - gstart);
+                ng++;
+            }
+            last = kmin;
+            first = false;
+        }
+        for (int g = ng; g < TL_GMAX; g++) meta[g] = 0;
+        if (ng > TL_GMAX) atomicOr(D.status, TL_ST_BOX);
+        atomicMax(&s_rounds, ng < TL_GMAX ? ng : TL_GMAX);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) D.bround[bi] = s_rounds;
+}
+
+DEV void mixed_body(const SceneK& S, const SceneD& D, int bi, int force)
+{
+    const int brick = D.active[bi];
+    if (!force && D.bdirty[brick] != D.ctr[0]) return;
+    cell_summaries(S, D, bi, brick);
+}
+
 // ------------------------------------------------------------------------ labels
 // Side-label pass (Eqs. 3, 4, 6).  FP64 predicates with a fixed evaluation order
 // and no contraction (the same order as the CPU reference), on x = X + u and v.
@@ -1133,9 +1237,11 @@ DEV void labels_body(const SceneK& S, const SceneD& D, int bi)
             any = true;
         }
     }
-    if (__syncthreads_or(any) && threadIdx.x == 0) {
+    if (__syncthreads_or(any)) {
         // label-change flags carry the substep stamp: no clearing pass needed
-        D.bdirty[brick] = D.ctr[0];
+        if (threadIdx.x == 0) D.bdirty[brick] = D.ctr[0];
+        __syncthreads(); // the new codes of the brick, visible to the whole block
+        cell_summaries(S, D, bi, brick);
     }
 }
 
@@ -1224,105 +1330,6 @@ DEV void slots_body(const SceneK& S, const SceneD& D, int bi, int dst, int src, 
     if (over) atomicOr(D.status, TL_ST_SLOT);
     D.cnt[dst][id] = (uint8_t)c;
     for (int s = 0; s < c; s++) D.scode[dst][s * S.NN + id] = codes[s];
-}
-
-// ------------------------------------------------------------- mixed-code bricks
-// Per cell of a brick whose codes changed (or of every brick, when forced): the
-// one slot key of its particles (or empty / mixed).  A brick with a mixed cell
-// gets a group table: each of its cells lists its particles by ascending key
-// (input order within a key) in gperm over the cell's range, cut into groups of at
-// most 8 same-key particles; P2G and G2P then take one group per cell and round.
-DEV void mixed_body(const SceneK& S, const SceneD& D, int bi, int force)
-{
-    __shared__ int s_rounds;
-    const int brick = D.active[bi];
-    if (!force && D.bdirty[brick] != D.ctr[0]) return;
-    if (threadIdx.x == 0) s_rounds = 1;
-    bool mixed = false;
-    for (int c = threadIdx.x; c < TL_CELLS; c += blockDim.x) {
-        const long long cs = (long long)brick * TL_CELLS + c;
-        const int b0 = D.cell_start[cs], b1 = D.cell_start[cs + 1];
-        if (b1 <= b0) {
-            D.ccode[cs] = TL_CC_EMPTY;
-            if (S.material_contact) D.cmask[cs] = 0;
-            continue;
-        }
-        const uint32_t k0 = slot_key(S, D.code[b0]);
-        uint32_t orm = k0; // OR of the codes of the cell (material contact candidates)
-        uint32_t ks[TL_CKEYS] = {k0, 0u, 0u, 0u};
-        int nk = 1;
-        bool many = false;
-#pragma unroll 4
-        for (int p = b0 + 1; p < b1; p++) {
-            const uint32_t k = slot_key(S, D.code[p]);
-            orm |= k;
-            // distinct keys in ascending order (insertion; at most TL_CKEYS kept)
-            bool seen = false;
-#pragma unroll
-            for (int q = 0; q < TL_CKEYS; q++) seen |= q < nk && ks[q] == k;
-            if (seen) continue;
-            if (nk == TL_CKEYS) {
-                many = true;
-                continue;
-            }
-#pragma unroll
-            for (int q = TL_CKEYS - 1; q > 0; q--)
-                if (q <= nk && ks[q - 1] > k) {
-                    ks[q] = ks[q - 1];
-                    ks[q - 1] = k;
-                } else if (q == nk) {
-                    ks[q] = k;
-                }
-            nk++;
-        }
-        const bool cm = nk > 1 || many;
-        D.ccode[cs] = !cm ? k0 : (many ? TL_CC_MIXED : (TL_CC_FEW | (uint32_t)nk));
-        if (cm && !many)
-            for (int q = 0; q < nk; q++) D.ckeys[cs * TL_CKEYS + q] = ks[q];
-        if (S.material_contact) D.cmask[cs] = orm;
-        mixed |= cm;
-    }
-    const int m = __syncthreads_or(mixed);
-    if (threadIdx.x == 0) D.bmixed[brick] = m;
-    if (!m) return;
-    if (threadIdx.x < TL_CELLS) {
-        const int c = threadIdx.x; // cell slot w * 8 + i
-        const long long cs = (long long)brick * TL_CELLS + c;
-        const int b0 = D.cell_start[cs], b1 = D.cell_start[cs + 1];
-        int* meta = D.gmeta + ((long long)bi * TL_CELLS + c) * TL_GMAX;
-        int ng = 0, pos = 0;
-        uint32_t last = 0;
-        bool first = true;
-        while (pos < b1 - b0) {
-            uint32_t kmin = 0xFFFFFFFFu; // smallest key above the last one
-            for (int p = b0; p < b1; p++) {
-                const uint32_t k = slot_key(S, D.code[p]);
-                if ((first || k > last) && k < kmin) kmin = k;
-            }
-            int gstart = pos;
-            for (int p = b0; p < b1; p++) {
-                if (slot_key(S, D.code[p]) != kmin) continue;
-                D.gperm[b0 + pos] = p;
-                pos++;
-                if (pos - gstart == 8) {
-                    if (ng < TL_GMAX) meta[ng] = (gstart << 4) | 8;
-                    ng++;
-                    gstart = pos;
-                }
-            }
-            if (pos > gstart) {
-                if (ng < TL_GMAX) meta[ng] = (gstart << 4) | (pos - gstart);
-                ng++;
-            }
-            last = kmin;
-            first = false;
-        }
-        for (int g = ng; g < TL_GMAX; g++) meta[g] = 0;
-        if (ng > TL_GMAX) atomicOr(D.status, TL_ST_BOX);
-        atomicMax(&s_rounds, ng < TL_GMAX ? ng : TL_GMAX);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) D.bround[bi] = s_rounds;
 }
 
 // --------------------------------------------------------------- small kernels
