@@ -324,7 +324,8 @@ DEV void reduce_scatter8(Gen&& gen, float (&res)[Q], int j)
 // another (fixed order).  The QA + QB components come from two generators (two
 // butterflies keep fewer partial sums live).  Every 8-lane group holds particles
 // of one code (bricks with a mixed cell are processed in same-code groups).
-template <int QA, int QB, class GA, class GB>
+// Component q of the generated values is stored at (q + ROT) mod Q of a slot.
+template <int QA, int QB, int ROT = 0, class GA, class GB>
 DEV void accumulate_classes(const Lane& L, bool valid, uint32_t key, GA&& ga, GB&& gb, const BoxTab& T, float* acc,
                             int* status)
 {
@@ -354,7 +355,8 @@ DEV void accumulate_classes(const Lane& L, bool valid, uint32_t key, GA&& ga, GB
         if (sl < 0)
             atomicOr(status, TL_ST_LOOKUP);
         else
-            for (int q = 0; q < Q; q++) acc[sl * Q + q] += res[q];
+#pragma unroll
+            for (int q = 0; q < Q; q++) acc[sl * Q + (q + ROT) % Q] += res[q];
     }
     lds_barrier();
 }
@@ -866,7 +868,9 @@ DEV void p2g_body(const SceneK& S, const SceneD& D, int bi, KA_Args A)
                 o[a] = on ? f : 0.0f;
             }
         };
-        accumulate_classes<4, 3>(L, valid, key, gen_mp, gen_dp, T, s_acc, D.status);
+        // impulses first: their butterfly then runs while fewer values are live;
+        // stored as (m, m v, dp) like the other order
+        accumulate_classes<3, 4, 4>(L, valid, key, gen_dp, gen_mp, T, s_acc, D.status);
     }
     if (!A.do_p2g) return;
     write_partials<7>(S, D.p2g, bi, T, total_c, s_acc);
