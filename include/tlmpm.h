@@ -159,6 +159,13 @@ tlmpm_status tlmpm_get_status(tlmpm_scene* scene, int32_t* status);
  * largest count at one node (Sec. III-G, compact slots).  Synchronises. */
 tlmpm_status tlmpm_slot_stats(tlmpm_scene* scene, int64_t* total_slots, int32_t* max_per_node);
 
+/* Diagnostics of the material-contact search of the last substep (Sec. III-E):
+ * out[0] contact candidates, out[1] hash buckets, out[2] occupied buckets,
+ * out[3] buckets holding more candidates than their inline records, out[4] the
+ * largest bucket count, out[5] the bin edge in metres.  All zero without material
+ * contact.  Synchronises. */
+tlmpm_status tlmpm_contact_stats(tlmpm_scene* scene, double out[6]);
+
 /* HIP graph replay of substeps.  While enabled, a tlmpm_step of n >= 3 substeps
  * runs its first substep as plain launches and the following pairs of substeps as
  * replays of a captured graph of those launches (one graph per combination of

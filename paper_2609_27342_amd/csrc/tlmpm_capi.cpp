@@ -169,7 +169,7 @@ Dims dims_of(const tlmpm_scene_desc* d)
 
 struct Offsets {
     size_t X, u, v, H, code, code_prev, D, perm, E, m, V0, cell_start, active, cnt0, cnt1, sc0, sc1, p2g, rs, hist,
-        aabb, wpart, wacc, Jmat, Jrig, brig, bmixed, ccode, ckeys, gmeta, gperm, bround, tools, tinfo, ctr, bact, status, dirty, bdirty, pcell, cand_idx, coff, gcand, cmask, cstatic, bcand, hbin, hmax, bcount, bids, cslot, brec, htab, hnext, orec, ph_n, ph_q, ph_u,
+        aabb, wpart, wacc, Jmat, Jrig, brig, bmixed, ccode, ckeys, gmeta, gperm, bround, tools, tinfo, ctr, bact, status, dirty, bdirty, pcell, cand_idx, coff, cmask, cstatic, bcand, hbin, hmax, bcount, bids, bsort, cslot, crec, htab, hnext, ph_n, ph_q, ph_u,
         total;
     uint32_t hmask;
 };
@@ -258,7 +258,6 @@ Offsets plan(const tlmpm_scene_desc* d, long long n_active)
         o.bcand = L.take((size_t)g.n_bricks * 4);
         o.cand_idx = L.take(N * 4);
         o.coff = L.take(((size_t)n_active + 1) * 4);
-        o.gcand = L.take(N * 4);
         o.hbin = L.take(4);
         o.hmax = L.take(4);
         size_t buckets = 4096;
@@ -266,11 +265,11 @@ Offsets plan(const tlmpm_scene_desc* d, long long n_active)
         o.hmask = (uint32_t)(buckets - 1);
         o.bcount = L.take(buckets * 4);
         o.bids = L.take(buckets * TL_BCAP * 4);
+        o.bsort = L.take(buckets * TL_BCAP * 4);
         o.cslot = L.take(N * 4);
-        o.brec = L.take(buckets * TL_BCAP * 48);
+        o.crec = L.take(N * 48);
         o.htab = L.take(buckets * 8);
         o.hnext = L.take(N * 4);
-        o.orec = L.take(N * 48);
         o.ph_n = L.take(2 * N * 4);
         o.ph_q = L.take(2 * N * TL_PCAP * 4);
         o.ph_u = L.take(2 * N * TL_PCAP * 3 * f);
@@ -495,17 +494,16 @@ extern "C" tlmpm_status tlmpm_create_scene(const tlmpm_scene_desc* d, void* ws, 
         D.bcand = (int*)(base + o.bcand);
         D.cand_idx = (int*)(base + o.cand_idx);
         D.coff = (int*)(base + o.coff);
-        D.gcand = (int*)(base + o.gcand);
         D.hbin = (float*)(base + o.hbin);
         D.hmax = (int*)(base + o.hmax);
         D.hmask = o.hmask;
         D.bcount = (int*)(base + o.bcount);
         D.bids = (int*)(base + o.bids);
+        D.bsort = (int*)(base + o.bsort);
         D.cslot = (int*)(base + o.cslot);
-        D.brec = (float4*)(base + o.brec);
+        D.crec = (float4*)(base + o.crec);
         D.htab = (unsigned long long*)(base + o.htab);
         D.hnext = (int*)(base + o.hnext);
-        D.orec = (float4*)(base + o.orec);
         D.ph_n = (int*)(base + o.ph_n);
         D.ph_q = (int*)(base + o.ph_q);
         D.ph_u = (float*)(base + o.ph_u);
@@ -1063,6 +1061,36 @@ extern "C" tlmpm_status tlmpm_slot_stats(tlmpm_scene* sc, int64_t* total_slots, 
     }
     if (total_slots) *total_slots = tot;
     if (max_per_node) *max_per_node = mx;
+    return TLMPM_OK;
+}
+
+extern "C" tlmpm_status tlmpm_contact_stats(tlmpm_scene* sc, double out[6])
+{
+    if (!out) return fail(TLMPM_E_INVALID, "null output");
+    if (tlmpm_status r = refuse_batched(sc)) return r;
+    for (int i = 0; i < 6; i++) out[i] = 0.0;
+    if (!sc->K.material_contact) return TLMPM_OK;
+    const size_t nb = (size_t)sc->D.hmask + 1;
+    std::vector<int> cnt(nb);
+    int total = 0;
+    float hb = 0.0f;
+    HIPCHK(hipMemcpyAsync(cnt.data(), sc->D.bcount, nb * 4, hipMemcpyDeviceToHost, sc->st));
+    HIPCHK(hipMemcpyAsync(&total, sc->D.coff + sc->D.n_active, 4, hipMemcpyDeviceToHost, sc->st));
+    HIPCHK(hipMemcpyAsync(&hb, sc->D.hbin, 4, hipMemcpyDeviceToHost, sc->st));
+    HIPCHK(hipStreamSynchronize(sc->st));
+    long long used = 0, over = 0;
+    int mx = 0;
+    for (int c : cnt) {
+        used += c > 0;
+        over += c > TL_BCAP;
+        mx = std::max(mx, c);
+    }
+    out[0] = total;
+    out[1] = (double)nb;
+    out[2] = (double)used;
+    out[3] = (double)over;
+    out[4] = mx;
+    out[5] = hb;
     return TLMPM_OK;
 }
 

@@ -137,17 +137,16 @@ struct SceneD {
     int* bcand;         // [active bricks] number of candidates of the brick
     int* cand_idx;      // [N] candidates of each brick, stored over the brick's particle range
     int* coff;          // [active bricks + 1] first global candidate index of each active brick
-    int* gcand;         // [N] all candidates, brick by brick (rewritten by each binning pass)
     float* hbin;        // bin edge (device scalar)
     int* hmax;          // largest brick speed bound of this substep (float bits)
     uint32_t hmask;     // buckets - 1 (power of two)
     int* bcount;        // [buckets] entries of each bucket this substep (cleared per substep)
-    int* bids;          // [buckets][TL_BCAP] particle ids in arrival order
-    int* cslot;         // [N] arrival slot of a candidate in its bucket (-1: overflow)
-    float4* brec;       // [buckets][TL_BCAP][3] inline candidate records
+    int* bids;          // [buckets][TL_BCAP] global candidate indices in arrival order
+    int* bsort;         // [buckets][TL_BCAP] the same indices in increasing order
+    int* cslot;         // [N] arrival slot of a global candidate in its bucket (-1: overflow)
+    float4* crec;       // [N][3] record of each global candidate (dense, brick by brick)
     unsigned long long* htab; // [buckets] overflow lists: generation << 32 | head
-    int* hnext;         // [N] overflow list links
-    float4* orec;       // [N][3] records of overflowing candidates
+    int* hnext;         // [N] overflow list links (global candidate indices)
     int* ph_n;          // [2][N] stamp << 8 | count of owned springs
     int* ph_q;          // [2][N][TL_PCAP] partner of each spring
     float* ph_u;        // [2][N][TL_PCAP][3] spring, oriented for the pair's lower index

@@ -6,10 +6,12 @@
 // cell iff (s1_p & OR s2) | (s2_p & OR s1) != 0.
 //
 // Pairs are found in the current configuration: candidates are hashed into bins
-// of edge h >= every contact reach (R_p + R_q + dt |v_p - v_q|); a hash bucket
-// holds up to TL_BCAP inline records, placed by rank of particle index, and an
-// overflow list built with 64-bit compare-and-swap on (generation, head), so the
-// table is never cleared.  A pair is evaluated by both particles with the same operands
+// of edge h >= every contact reach (R_p + R_q + dt |v_p - v_q|).  Each candidate's
+// record (position, velocity, mass, radius, code, reference cell) is written once
+// into a dense array indexed by its global candidate number, which follows the
+// particle order; a hash bucket holds up to TL_BCAP of these numbers, sorted, and
+// an overflow list built with 64-bit compare-and-swap on (generation, head), so
+// the table is never cleared.  A pair is evaluated by both particles with the same operands
 // (the lower sorted index first), so the two impulses are exact negatives; each
 // particle sums its contacts in a fixed order (bins, then ranks in the bin), which
 // makes the result independent of arrival order.  The tangential spring of a pair
@@ -240,10 +242,11 @@ DEV void make_rec(const SceneK& S, const SceneD& D, int p, const float x[3], flo
 }
 
 // Bins the candidates of every brick, in two passes that make the content of a
-// bucket independent of arrival order.  Pass 1: slot = atomicAdd on the bucket
-// count; the first TL_BCAP ids are kept, later candidates go to a lock-free
-// overflow list (generation-stamped heads, never cleared).  Pass 2: each kept
-// candidate stores its record at its rank by particle index among the bucket's ids.
+// bucket independent of arrival order.  Pass 1: each candidate writes its record
+// at its global number g; slot = atomicAdd on the bucket count; the first TL_BCAP
+// numbers are kept in arrival order, later candidates go to a lock-free overflow
+// list (generation-stamped heads, never cleared).  Pass 2: each kept candidate
+// stores g at its rank among the bucket's numbers.
 // bucket counts of this substep start at zero
 DEV void bzero_body(const SceneK& S, const SceneD& D, int bi)
 {
@@ -275,31 +278,31 @@ DEV void bin_insert_body(const SceneK& S, const SceneD& D, int bi)
     const int g0 = D.coff[bi];
     for (int c = threadIdx.x; c < nc; c += blockDim.x) {
         const int p = D.cand_idx[beg + c];
-        D.gcand[g0 + c] = p;
+        const int g = g0 + c;
         float x[3];
         cur_pos(S, D, p, x);
+        float4 r[3];
+        make_rec(S, D, p, x, r);
+        float4* dst = D.crec + (long long)g * 3;
+        dst[0] = r[0];
+        dst[1] = r[1];
+        dst[2] = r[2];
         int b[3];
         bin_of(x, inv_h, b);
         uint32_t h = bin_hash(b[0], b[1], b[2], D.hmask);
         int slot = atomicAdd(&D.bcount[h], 1);
         if (slot < TL_BCAP) {
-            D.bids[(long long)h * TL_BCAP + slot] = p;
-            D.cslot[p] = slot;
+            D.bids[(long long)h * TL_BCAP + slot] = g;
+            D.cslot[g] = slot;
             continue;
         }
-        D.cslot[p] = -1;
-        float4 r[3];
-        make_rec(S, D, p, x, r);
-        float4* od = D.orec + (long long)p * 3;
-        od[0] = r[0];
-        od[1] = r[1];
-        od[2] = r[2];
+        D.cslot[g] = -1;
         unsigned long long* hs = (unsigned long long*)&D.htab[h];
         unsigned long long old = *hs, nv;
         while (true) {
             unsigned og = (unsigned)(old >> 32);
-            D.hnext[p] = (og == gen) ? (int)(old & 0xFFFFFFFFull) : -1;
-            nv = ((unsigned long long)gen << 32) | (unsigned)p;
+            D.hnext[g] = (og == gen) ? (int)(old & 0xFFFFFFFFull) : -1;
+            nv = ((unsigned long long)gen << 32) | (unsigned)g;
             unsigned long long prev = atomicCAS(hs, old, nv);
             if (prev == old) break;
             old = prev;
@@ -311,28 +314,22 @@ DEV void bin_rank_body(const SceneK& S, const SceneD& D, int bi)
 {
     if (!S.material_contact) return;
     if (bi == 0 && threadIdx.x == 0) *D.hmax = 0; // binning read it; next substep gathers anew
-    const int brick = D.active[bi];
     const int nc = D.bcand[bi];
     if (!nc) return;
     const float inv_h = 1.0f / D.hbin[0];
-    const int beg = D.cell_start[(long long)brick * TL_CELLS];
+    const int g0 = D.coff[bi];
     for (int c = threadIdx.x; c < nc; c += blockDim.x) {
-        const int p = D.cand_idx[beg + c];
-        if (D.cslot[p] < 0) continue;
-        float x[3];
-        cur_pos(S, D, p, x);
+        const int g = g0 + c;
+        if (D.cslot[g] < 0) continue;
+        const float4 xr = D.crec[(long long)g * 3 + 1];
+        const float x[3] = {xr.x, xr.y, xr.z};
         int b[3];
         bin_of(x, inv_h, b);
         uint32_t h = bin_hash(b[0], b[1], b[2], D.hmask);
         const int cnt = min(D.bcount[h], TL_BCAP);
         int rank = 0;
-        for (int k = 0; k < cnt; k++) rank += D.bids[(long long)h * TL_BCAP + k] < p;
-        float4 r[3];
-        make_rec(S, D, p, x, r);
-        float4* dst = D.brec + ((long long)h * TL_BCAP + rank) * 3;
-        dst[0] = r[0];
-        dst[1] = r[1];
-        dst[2] = r[2];
+        for (int k = 0; k < cnt; k++) rank += D.bids[(long long)h * TL_BCAP + k] < g;
+        D.bsort[(long long)h * TL_BCAP + rank] = g;
     }
 }
 
@@ -384,17 +381,13 @@ DEV PState pstate_of(const float4 r[3])
     return s;
 }
 
-DEV PState load_pstate(const SceneK& S, const SceneD& D, long long p)
+// reference cell of a record (x | y << 16 in the first vector, z in the third)
+DEV void rec_cell(const float4 r[3], int c[3])
 {
-    PState s;
-    cur_pos(S, D, p, s.x);
-    s.v[0] = D.v[p];
-    s.v[1] = D.v[S.N + p];
-    s.v[2] = D.v[2 * S.N + p];
-    s.m = S.m_uniform ? S.m0 : D.m[p];
-    float V0 = S.v_uniform ? S.V0 : D.V0[p];
-    s.R = 0.5f * S.s_R * cbrtf(V0);
-    return s;
+    const int xy = __float_as_int(r[0].z);
+    c[0] = xy & 0xFFFF;
+    c[1] = (xy >> 16) & 0xFFFF;
+    c[2] = __float_as_int(r[2].w);
 }
 
 // Pair impulse on the owner o (lower index) from r, Eqs. 10-12; u is the owner's
@@ -416,11 +409,6 @@ DEV bool pair_impulse(const SceneK& S, const PState& o, const PState& r, float u
     friction_f(S, vrel, n, fn, meff, u, ft);
     for (int a = 0; a < 3; a++) J[a] = (fn * n[a] + ft[a]) * dt;
     return true;
-}
-
-DEV void ref_cell(const SceneK& S, const SceneD& D, long long p, int c[3])
-{
-    slot_cell(S, D.pcell[p], c[0], c[1], c[2]);
 }
 
 // Pair search and impulses over all candidates of the scene (grid-stride over the
@@ -455,7 +443,14 @@ DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
     for (int c0 = bi * TL_PCAND; c0 < total; c0 += stride) {
         const int g = c0 + sub;
         const bool has = g < total;
-        const int p = has ? D.gcand[g] : -1;
+        float4 rp[3];
+        if (has) {
+            const float4* src = D.crec + (long long)g * 3;
+            rp[0] = src[0];
+            rp[1] = src[1];
+            rp[2] = src[2];
+        }
+        const int p = has ? __float_as_int(rp[0].x) : -1;
         // the candidate's springs of the last substep, staged in LDS
         int nold = 0;
         if (has) {
@@ -476,10 +471,10 @@ DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
         __syncthreads();
         float Jt[3] = {0.0f, 0.0f, 0.0f};
         if (has) {
-            const uint32_t kp = ckey(S, D.code[p]);
-            PState sp = load_pstate(S, D, p);
+            const uint32_t kp = ckey(S, __float_as_uint(rp[0].y));
+            const PState sp = pstate_of(rp);
             int cp[3];
-            ref_cell(S, D, p, cp);
+            rec_cell(rp, cp);
             int b[3];
             bin_of(sp.x, inv_h, b);
             int* ql_new = D.ph_q + ((long long)hnew * N + p) * TL_PCAP;
@@ -494,12 +489,7 @@ DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
                 }
                 uint32_t kq = ckey(S, __float_as_uint(rec[0].y));
                 int cq[3];
-                {
-                    const int xy = __float_as_int(rec[0].z);
-                    cq[0] = xy & 0xFFFF;
-                    cq[1] = (xy >> 16) & 0xFFFF;
-                    cq[2] = __float_as_int(rec[2].w);
-                }
+                rec_cell(rec, cq);
                 bool near = abs(cp[0] - cq[0]) <= 1 && abs(cp[1] - cq[1]) <= 1 && abs(cp[2] - cq[2]) <= 1;
                 if (near && !cconflict(kp, kq)) return; // reading R17 exclusion
                 PState sq = pstate_of(rec);
@@ -541,12 +531,13 @@ DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
                 const int cnt = D.bcount[h];
                 const int inl = cnt < TL_BCAP ? cnt : TL_BCAP;
                 for (int k = 0; k < inl; k++) {
-                    const float4* src = D.brec + ((long long)h * TL_BCAP + k) * 3;
+                    const float4* src = D.crec + (long long)D.bsort[(long long)h * TL_BCAP + k] * 3;
                     float4 rec[3] = {src[0], src[1], src[2]};
                     visit(rec);
                 }
                 if (cnt > TL_BCAP) {
-                    // overflow list (rare): visited in increasing particle index
+                    // overflow list (rare): visited in increasing candidate number,
+                    // which is increasing particle index
                     unsigned long long e = D.htab[h];
                     if ((unsigned)(e >> 32) == gen) {
                         const int head = (int)(e & 0xFFFFFFFFull);
@@ -556,7 +547,7 @@ DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
                             for (int q = head; q >= 0; q = D.hnext[q])
                                 if (q > last && q < best) best = q;
                             if (best == INT_MAX) break;
-                            const float4* src = D.orec + (long long)best * 3;
+                            const float4* src = D.crec + (long long)best * 3;
                             float4 rec[3] = {src[0], src[1], src[2]};
                             visit(rec);
                             last = best;

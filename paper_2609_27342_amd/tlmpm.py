@@ -70,6 +70,7 @@ def lib():
         L.tlmpm_write_state.argtypes = [vp, C.c_uint32, C.POINTER(vp)]
         L.tlmpm_get_status.argtypes = [vp, C.POINTER(C.c_int32)]
         L.tlmpm_slot_stats.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
+        L.tlmpm_contact_stats.argtypes = [vp, C.POINTER(C.c_double)]
         L.tlmpm_profile_enable.argtypes = [vp, C.c_int32]
         L.tlmpm_profile_read.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.tlmpm_batch_footprint.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(C.c_size_t)]
@@ -83,7 +84,7 @@ def lib():
         L.tlmpm_batch_profile_read.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.tlmpm_last_error.restype = C.c_char_p
         for f in ("tlmpm_scene_footprint", "tlmpm_create_scene", "tlmpm_destroy_scene", "tlmpm_assign_labels",
-                  "tlmpm_step", "tlmpm_read_state", "tlmpm_write_state", "tlmpm_get_status", "tlmpm_slot_stats",
+                  "tlmpm_step", "tlmpm_read_state", "tlmpm_write_state", "tlmpm_get_status", "tlmpm_slot_stats", "tlmpm_contact_stats",
                   "tlmpm_profile_enable", "tlmpm_profile_read", "tlmpm_batch_footprint", "tlmpm_batch_create",
                   "tlmpm_batch_destroy", "tlmpm_batch_step", "tlmpm_batch_sync", "tlmpm_batch_profile_enable",
                   "tlmpm_batch_profile_read", "tlmpm_set_graphs", "tlmpm_batch_set_graphs"):
@@ -290,6 +291,15 @@ class Scene:
         mx = C.c_int32()
         _check(lib().tlmpm_slot_stats(self.h, C.byref(tot), C.byref(mx)))
         return tot.value, mx.value
+
+    def contact_stats(self):
+        """Material-contact search of the last substep: candidates, buckets,
+        occupied buckets, buckets beyond their inline records, largest bucket
+        count, bin edge (m)."""
+        out = (C.c_double * 6)()
+        _check(lib().tlmpm_contact_stats(self.h, out))
+        keys = ("candidates", "buckets", "occupied", "overflowing", "max_count", "bin_edge")
+        return {k: (out[i] if k == "bin_edge" else int(out[i])) for i, k in enumerate(keys)}
 
 
 class Batch:
