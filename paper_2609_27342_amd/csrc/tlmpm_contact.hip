@@ -420,6 +420,7 @@ DEV bool pair_impulse(const SceneK& S, const PState& o, const PState& r, float u
 // pair with the same operands, so the two copies stay equal and no particle reads
 // its partner's list.  A list is only searched by partner, so its order does not
 // matter.
+#define TL_PLIST 96 // compacted neighbour entries per candidate held in LDS
 DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
 {
     if (!S.material_contact) return;
@@ -430,6 +431,8 @@ DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
     __shared__ int s_q[TL_PCAND][TL_PCAP];
     __shared__ float s_u[TL_PCAND][TL_PCAP][3];
     __shared__ int s_nold[TL_PCAND], s_nnew[TL_PCAND];
+    __shared__ int s_ids[TL_PCAND][TL_PLIST];          // candidate numbers of the bins' entries
+    __shared__ unsigned char s_bin[TL_PCAND][TL_PLIST]; // which of the 27 bins each came from
     const int total = D.coff[D.n_active];
     const float hb = D.hbin[0];
     const float inv_h = 1.0f / hb;
@@ -451,6 +454,20 @@ DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
             rp[2] = src[2];
         }
         const int p = has ? __float_as_int(rp[0].x) : -1;
+        // this lane's bins: l, l + 8, l + 16, l + 24 of the 27 around the candidate
+        int bq[3] = {0, 0, 0};
+        if (has) {
+            const float xp[3] = {rp[1].x, rp[1].y, rp[1].z};
+            bin_of(xp, inv_h, bq);
+        }
+        uint32_t hq[4];
+        int cntq[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int d = l + TL_PLANES * j;
+            hq[j] = bin_hash(bq[0] + d % 3 - 1, bq[1] + (d / 3) % 3 - 1, bq[2] + d / 9 - 1, D.hmask);
+            cntq[j] = (has && d < 27) ? D.bcount[hq[j]] : 0;
+        }
         // the candidate's springs of the last substep, staged in LDS
         int nold = 0;
         if (has) {
@@ -468,6 +485,42 @@ DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
             s_nold[sub] = nold;
             s_nnew[sub] = 0;
         }
+        // inline entries of the 27 bins in bin order, compacted into one list per
+        // candidate (the first TL_PLIST of them; the rest are visited by the lane
+        // that owns their bin)
+        // list position of the first entry of bin d = l + 8 j: the entries of the
+        // rows j' < j in every lane, plus those of row j in the lanes below l
+        int pos[4], n_list = 0;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int c = min(cntq[j], TL_BCAP);
+            int incl = c;
+#pragma unroll
+            for (int o = 1; o < TL_PLANES; o <<= 1) {
+                const int t = __shfl_up(incl, o, TL_PLANES);
+                if (l >= o) incl += t;
+            }
+            pos[j] = n_list + incl - c;
+            n_list += __shfl(incl, TL_PLANES - 1, TL_PLANES);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int c = min(cntq[j], TL_BCAP);
+            if (c == 0) continue;
+            const int d = l + TL_PLANES * j;
+            const int4* row = (const int4*)(D.bsort + (long long)hq[j] * TL_BCAP);
+            const int4 a = row[0];
+            const int4 b = c > 4 ? row[1] : a;
+            const int e[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+            for (int k = 0; k < TL_BCAP; k++) {
+                const int at = pos[j] + k;
+                if (k < c && at < TL_PLIST) {
+                    s_ids[sub][at] = e[k];
+                    s_bin[sub][at] = (unsigned char)d;
+                }
+            }
+        }
         __syncthreads();
         float Jt[3] = {0.0f, 0.0f, 0.0f};
         if (has) {
@@ -475,12 +528,9 @@ DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
             const PState sp = pstate_of(rp);
             int cp[3];
             rec_cell(rp, cp);
-            int b[3];
-            bin_of(sp.x, inv_h, b);
             int* ql_new = D.ph_q + ((long long)hnew * N + p) * TL_PCAP;
             float* ul_new = D.ph_u + ((long long)hnew * N + p) * TL_PCAP * 3;
-            int bb[3];
-            auto visit = [&](const float4 rec[3]) {
+            auto visit = [&](const float4 rec[3], int d) {
                 const int q = __float_as_int(rec[0].x);
                 if (q == p) return;
                 {
@@ -493,9 +543,11 @@ DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
                 bool near = abs(cp[0] - cq[0]) <= 1 && abs(cp[1] - cq[1]) <= 1 && abs(cp[2] - cq[2]) <= 1;
                 if (near && !cconflict(kp, kq)) return; // reading R17 exclusion
                 PState sq = pstate_of(rec);
-                int bq[3];
-                bin_of(sq.x, inv_h, bq);
-                if (bq[0] != bb[0] || bq[1] != bb[1] || bq[2] != bb[2]) return; // hash collision
+                int bz[3];
+                bin_of(sq.x, inv_h, bz);
+                // hash collision: the entry's own bin is not the probed one
+                if (bz[0] != bq[0] + d % 3 - 1 || bz[1] != bq[1] + (d / 3) % 3 - 1 || bz[2] != bq[2] + d / 9 - 1)
+                    return;
                 const bool own = p < q;
                 // the pair's spring of the last substep
                 float u[3] = {0.0f, 0.0f, 0.0f};
@@ -523,22 +575,32 @@ DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
                     atomicOr(D.status, TL_ST_CONTACT);
                 }
             };
-            for (int d = l; d < 27; d += TL_PLANES) {
-                bb[0] = b[0] + d % 3 - 1;
-                bb[1] = b[1] + (d / 3) % 3 - 1;
-                bb[2] = b[2] + d / 9 - 1;
-                uint32_t h = bin_hash(bb[0], bb[1], bb[2], D.hmask);
-                const int cnt = D.bcount[h];
-                const int inl = cnt < TL_BCAP ? cnt : TL_BCAP;
-                for (int k = 0; k < inl; k++) {
-                    const float4* src = D.crec + (long long)D.bsort[(long long)h * TL_BCAP + k] * 3;
+            // the list, strided over the lanes, two independent records at a time
+            const int nl = min(n_list, TL_PLIST);
+            for (int i = l; i < nl; i += 2 * TL_PLANES) {
+                const int i2 = i + TL_PLANES;
+                const bool two = i2 < nl;
+                const float4* s1 = D.crec + (long long)s_ids[sub][i] * 3;
+                const float4* s2 = D.crec + (long long)s_ids[sub][two ? i2 : i] * 3;
+                float4 r1[3] = {s1[0], s1[1], s1[2]};
+                float4 r2[3] = {s2[0], s2[1], s2[2]};
+                visit(r1, s_bin[sub][i]);
+                if (two) visit(r2, s_bin[sub][i2]);
+            }
+            // entries beyond the list, then overflow lists (rare), by the bin's lane
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const int d = l + TL_PLANES * j;
+                if (d >= 27) break;
+                const int c = min(cntq[j], TL_BCAP);
+                for (int k = max(0, TL_PLIST - pos[j]); k < c; k++) {
+                    const float4* src = D.crec + (long long)D.bsort[(long long)hq[j] * TL_BCAP + k] * 3;
                     float4 rec[3] = {src[0], src[1], src[2]};
-                    visit(rec);
+                    visit(rec, d);
                 }
-                if (cnt > TL_BCAP) {
-                    // overflow list (rare): visited in increasing candidate number,
-                    // which is increasing particle index
-                    unsigned long long e = D.htab[h];
+                if (cntq[j] > TL_BCAP) {
+                    // visited in increasing candidate number (= particle index)
+                    unsigned long long e = D.htab[hq[j]];
                     if ((unsigned)(e >> 32) == gen) {
                         const int head = (int)(e & 0xFFFFFFFFull);
                         int last = -1;
@@ -549,7 +611,7 @@ DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
                             if (best == INT_MAX) break;
                             const float4* src = D.crec + (long long)best * 3;
                             float4 rec[3] = {src[0], src[1], src[2]};
-                            visit(rec);
+                            visit(rec, d);
                             last = best;
                         }
                     }
@@ -593,7 +655,17 @@ TL_WRAP(cand, TL_COMMA int force, TL_COMMA force)
 TL_WRAP(bzero, , )
 TL_WRAP(bin_insert, , )
 TL_WRAP(bin_rank, , )
-TL_WRAP(pairs, , )
+// at most 128 VGPRs: four waves per SIMD
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_pairs(SceneK S, SceneD D)
+{
+    pairs_body(S, D, blockIdx.x);
+}
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_pairs_b(
+    const SceneK* __restrict__ Ks, const SceneD* __restrict__ Ds, const int2* __restrict__ it)
+{
+    const int2 t = it[blockIdx.x];
+    pairs_body(Ks[t.x], Ds[t.x], t.y);
+}
 __global__ __launch_bounds__(TL_SCAN_T) void k_cscan(SceneK S, SceneD D) { cscan_body(S, D, 0); }
 __global__ __launch_bounds__(TL_SCAN_T) void k_cscan_b(const SceneK* __restrict__ Ks, const SceneD* __restrict__ Ds,
                                                        const int2* __restrict__ it)
