@@ -169,7 +169,7 @@ Dims dims_of(const tlmpm_scene_desc* d)
 
 struct Offsets {
     size_t X, u, v, H, code, code_prev, D, perm, E, m, V0, cell_start, active, cnt0, cnt1, sc0, sc1, p2g, rs, hist,
-        aabb, wpart, wacc, Jmat, Jrig, brig, bmixed, ccode, ckeys, gmeta, gperm, bround, tools, tinfo, ctr, bact, status, dirty, bdirty, pcell, cand_idx, coff, cmask, cstatic, bcand, hbin, hmax, bcount, bids, bsort, cslot, crec, htab, hnext, ph_n, ph_q, ph_u,
+        aabb, wpart, wacc, Jmat, Jrig, brig, bmixed, ccode, ckeys, gmeta, gperm, bround, tools, tinfo, ctr, bact, status, dirty, bdirty, pcell, cand_idx, coff, cmask, cstatic, bcand, hbin, hmax, bcount, bids, crec, htab, hnext, ph_n, ph_q, ph_u,
         total;
     uint32_t hmask;
 };
@@ -265,8 +265,6 @@ Offsets plan(const tlmpm_scene_desc* d, long long n_active)
         o.hmask = (uint32_t)(buckets - 1);
         o.bcount = L.take(buckets * 4);
         o.bids = L.take(buckets * TL_BCAP * 4);
-        o.bsort = L.take(buckets * TL_BCAP * 4);
-        o.cslot = L.take(N * 4);
         o.crec = L.take(N * 48);
         o.htab = L.take(buckets * 8);
         o.hnext = L.take(N * 4);
@@ -499,8 +497,6 @@ extern "C" tlmpm_status tlmpm_create_scene(const tlmpm_scene_desc* d, void* ws, 
         D.hmask = o.hmask;
         D.bcount = (int*)(base + o.bcount);
         D.bids = (int*)(base + o.bids);
-        D.bsort = (int*)(base + o.bsort);
-        D.cslot = (int*)(base + o.cslot);
         D.crec = (float4*)(base + o.crec);
         D.htab = (unsigned long long*)(base + o.htab);
         D.hnext = (int*)(base + o.hnext);

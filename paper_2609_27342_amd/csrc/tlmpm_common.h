@@ -142,8 +142,6 @@ struct SceneD {
     uint32_t hmask;     // buckets - 1 (power of two)
     int* bcount;        // [buckets] entries of each bucket this substep (cleared per substep)
     int* bids;          // [buckets][TL_BCAP] global candidate indices in arrival order
-    int* bsort;         // [buckets][TL_BCAP] the same indices in increasing order
-    int* cslot;         // [N] arrival slot of a global candidate in its bucket (-1: overflow)
     float4* crec;       // [N][3] record of each global candidate (dense, brick by brick)
     unsigned long long* htab; // [buckets] overflow lists: generation << 32 | head
     int* hnext;         // [N] overflow list links (global candidate indices)

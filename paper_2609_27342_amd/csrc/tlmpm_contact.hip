@@ -9,9 +9,10 @@
 // of edge h >= every contact reach (R_p + R_q + dt |v_p - v_q|).  Each candidate's
 // record (position, velocity, mass, radius, code, reference cell) is written once
 // into a dense array indexed by its global candidate number, which follows the
-// particle order; a hash bucket holds up to TL_BCAP of these numbers, sorted, and
-// an overflow list built with 64-bit compare-and-swap on (generation, head), so
-// the table is never cleared.  A pair is evaluated by both particles with the same operands
+// particle order; a hash bucket holds up to TL_BCAP of these numbers (in arrival
+// order, sorted by the pair pass when it reads them), and an overflow list built
+// with 64-bit compare-and-swap on (generation, head), so the table is never
+// cleared.  A pair is evaluated by both particles with the same operands
 // (the lower sorted index first), so the two impulses are exact negatives; each
 // particle sums its contacts in a fixed order (bins, then ranks in the bin), which
 // makes the result independent of arrival order.  The tangential spring of a pair
@@ -241,12 +242,11 @@ DEV void make_rec(const SceneK& S, const SceneD& D, int p, const float x[3], flo
     r[2] = make_float4(D.v[p], D.v[S.N + p], D.v[2 * S.N + p], __int_as_float(c[2]));
 }
 
-// Bins the candidates of every brick, in two passes that make the content of a
-// bucket independent of arrival order.  Pass 1: each candidate writes its record
-// at its global number g; slot = atomicAdd on the bucket count; the first TL_BCAP
-// numbers are kept in arrival order, later candidates go to a lock-free overflow
-// list (generation-stamped heads, never cleared).  Pass 2: each kept candidate
-// stores g at its rank among the bucket's numbers.
+// Bins the candidates of every brick: each candidate writes its record at its
+// global number g; slot = atomicAdd on the bucket count; the first TL_BCAP numbers
+// are kept in arrival order, later candidates go to a lock-free overflow list
+// (generation-stamped heads, never cleared).  The pair pass sorts a bucket's
+// numbers before use, so its result does not depend on the arrival order.
 // bucket counts of this substep start at zero
 DEV void bzero_body(const SceneK& S, const SceneD& D, int bi)
 {
@@ -255,7 +255,7 @@ DEV void bzero_body(const SceneK& S, const SceneD& D, int bi)
     if (i <= (long long)D.hmask) D.bcount[i] = 0;
     // largest brick speed bound (grid-stride over the bricks, one atomic per
     // block); the maximum of non-negative floats is taken on their bit patterns, so
-    // it does not depend on the order of the atomics.  Reset by the ranking pass.
+    // it does not depend on the order of the atomics.  Reset by the pair pass.
     const long long nb = (long long)S.cbx * S.cby * S.cbz;
     float m = 0.0f;
     const long long stride = ((long long)D.hmask + 256) / 256 * blockDim.x; // this scene's blocks
@@ -270,7 +270,7 @@ DEV void bin_insert_body(const SceneK& S, const SceneD& D, int bi)
     const unsigned gen = (unsigned)D.ctr[0];
     const int brick = D.active[bi];
     const float hb = bin_edge(S, D);
-    if (bi == 0 && threadIdx.x == 0) D.hbin[0] = hb; // for the ranking and pair passes
+    if (bi == 0 && threadIdx.x == 0) D.hbin[0] = hb; // for the pair pass
     const int nc = D.bcand[bi];
     if (!nc) return;
     const float inv_h = 1.0f / hb;
@@ -293,10 +293,8 @@ DEV void bin_insert_body(const SceneK& S, const SceneD& D, int bi)
         int slot = atomicAdd(&D.bcount[h], 1);
         if (slot < TL_BCAP) {
             D.bids[(long long)h * TL_BCAP + slot] = g;
-            D.cslot[g] = slot;
             continue;
         }
-        D.cslot[g] = -1;
         unsigned long long* hs = (unsigned long long*)&D.htab[h];
         unsigned long long old = *hs, nv;
         while (true) {
@@ -307,29 +305,6 @@ DEV void bin_insert_body(const SceneK& S, const SceneD& D, int bi)
             if (prev == old) break;
             old = prev;
         }
-    }
-}
-
-DEV void bin_rank_body(const SceneK& S, const SceneD& D, int bi)
-{
-    if (!S.material_contact) return;
-    if (bi == 0 && threadIdx.x == 0) *D.hmax = 0; // binning read it; next substep gathers anew
-    const int nc = D.bcand[bi];
-    if (!nc) return;
-    const float inv_h = 1.0f / D.hbin[0];
-    const int g0 = D.coff[bi];
-    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
-        const int g = g0 + c;
-        if (D.cslot[g] < 0) continue;
-        const float4 xr = D.crec[(long long)g * 3 + 1];
-        const float x[3] = {xr.x, xr.y, xr.z};
-        int b[3];
-        bin_of(x, inv_h, b);
-        uint32_t h = bin_hash(b[0], b[1], b[2], D.hmask);
-        const int cnt = min(D.bcount[h], TL_BCAP);
-        int rank = 0;
-        for (int k = 0; k < cnt; k++) rank += D.bids[(long long)h * TL_BCAP + k] < g;
-        D.bsort[(long long)h * TL_BCAP + rank] = g;
     }
 }
 
@@ -420,6 +395,36 @@ DEV bool pair_impulse(const SceneK& S, const PState& o, const PState& r, float u
 // pair with the same operands, so the two copies stay equal and no particle reads
 // its partner's list.  A list is only searched by partner, so its order does not
 // matter.
+// the first c (<= TL_BCAP) candidate numbers of bucket h in increasing order
+// (sorting network on eight values; unused places hold INT_MAX)
+DEV void bucket_sorted(const SceneD& D, uint32_t h, int c, int e[TL_BCAP])
+{
+    static_assert(TL_BCAP == 8, "the sorting network below covers 8 entries");
+    const int4* row = (const int4*)(D.bids + (long long)h * TL_BCAP);
+    const int4 a = row[0];
+    const int4 b = c > 4 ? row[1] : make_int4(INT_MAX, INT_MAX, INT_MAX, INT_MAX);
+    e[0] = a.x;
+    e[1] = c > 1 ? a.y : INT_MAX;
+    e[2] = c > 2 ? a.z : INT_MAX;
+    e[3] = c > 3 ? a.w : INT_MAX;
+    e[4] = b.x;
+    e[5] = c > 5 ? b.y : INT_MAX;
+    e[6] = c > 6 ? b.z : INT_MAX;
+    e[7] = c > 7 ? b.w : INT_MAX;
+    auto cx = [&](int i, int j) {
+        const int lo = min(e[i], e[j]), hi = max(e[i], e[j]);
+        e[i] = lo;
+        e[j] = hi;
+    };
+    cx(0, 1); cx(2, 3); cx(0, 2); cx(1, 3); cx(1, 2); // first four
+    if (c > 4) {
+        cx(4, 6); cx(5, 7); cx(4, 5); cx(6, 7); cx(5, 6); // last four (sorted 4 + 4, then merged)
+        cx(0, 4); cx(1, 5); cx(2, 6); cx(3, 7);
+        cx(2, 4); cx(3, 5);
+        cx(1, 2); cx(3, 4); cx(5, 6);
+    }
+}
+
 #define TL_PLIST 96 // compacted neighbour entries per candidate held in LDS
 DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
 {
@@ -428,6 +433,7 @@ DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
     const int stamp = D.ctr[0];
     const unsigned gen = (unsigned)stamp;
     const int hnew = stamp & 1, hold = hnew ^ 1;
+    if (bi == 0 && threadIdx.x == 0) *D.hmax = 0; // binning read it; next substep gathers anew
     __shared__ int s_q[TL_PCAND][TL_PCAP];
     __shared__ float s_u[TL_PCAND][TL_PCAP][3];
     __shared__ int s_nold[TL_PCAND], s_nnew[TL_PCAND];
@@ -460,13 +466,30 @@ DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
             const float xp[3] = {rp[1].x, rp[1].y, rp[1].z};
             bin_of(xp, inv_h, bq);
         }
+        // distances from the candidate to the faces of its own bin
+        float lo[3], hi[3];
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            const float xa = a == 0 ? rp[1].x : a == 1 ? rp[1].y : rp[1].z;
+            lo[a] = xa - (float)bq[a] * hb;
+            hi[a] = (float)(bq[a] + 1) * hb - xa;
+        }
         uint32_t hq[4];
         int cntq[4];
 #pragma unroll
         for (int j = 0; j < 4; j++) {
             const int d = l + TL_PLANES * j;
-            hq[j] = bin_hash(bq[0] + d % 3 - 1, bq[1] + (d / 3) % 3 - 1, bq[2] + d / 9 - 1, D.hmask);
-            cntq[j] = (has && d < 27) ? D.bcount[hq[j]] : 0;
+            const int o[3] = {d % 3 - 1, (d / 3) % 3 - 1, d / 9 - 1};
+            // a bin whose nearest point is farther than sqrt(0.999) h holds no
+            // partner: a contact needs a distance below h / 1.001 (see bin_edge)
+            float e2 = 0.0f;
+#pragma unroll
+            for (int a = 0; a < 3; a++) {
+                const float e = o[a] < 0 ? lo[a] : o[a] > 0 ? hi[a] : 0.0f;
+                e2 += e * e;
+            }
+            hq[j] = bin_hash(bq[0] + o[0], bq[1] + o[1], bq[2] + o[2], D.hmask);
+            cntq[j] = (has && d < 27 && e2 < 0.999f * reach2) ? D.bcount[hq[j]] : 0;
         }
         // the candidate's springs of the last substep, staged in LDS
         int nold = 0;
@@ -508,10 +531,8 @@ DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
             const int c = min(cntq[j], TL_BCAP);
             if (c == 0) continue;
             const int d = l + TL_PLANES * j;
-            const int4* row = (const int4*)(D.bsort + (long long)hq[j] * TL_BCAP);
-            const int4 a = row[0];
-            const int4 b = c > 4 ? row[1] : a;
-            const int e[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+            int e[TL_BCAP];
+            bucket_sorted(D, hq[j], c, e);
 #pragma unroll
             for (int k = 0; k < TL_BCAP; k++) {
                 const int at = pos[j] + k;
@@ -593,10 +614,16 @@ DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
                 const int d = l + TL_PLANES * j;
                 if (d >= 27) break;
                 const int c = min(cntq[j], TL_BCAP);
-                for (int k = max(0, TL_PLIST - pos[j]); k < c; k++) {
-                    const float4* src = D.crec + (long long)D.bsort[(long long)hq[j] * TL_BCAP + k] * 3;
-                    float4 rec[3] = {src[0], src[1], src[2]};
-                    visit(rec, d);
+                if (pos[j] + c > TL_PLIST) {
+                    int e[TL_BCAP];
+                    bucket_sorted(D, hq[j], c, e);
+#pragma unroll
+                    for (int k = 0; k < TL_BCAP; k++) {
+                        if (k >= c || pos[j] + k < TL_PLIST) continue;
+                        const float4* src = D.crec + (long long)e[k] * 3;
+                        float4 rec[3] = {src[0], src[1], src[2]};
+                        visit(rec, d);
+                    }
                 }
                 if (cntq[j] > TL_BCAP) {
                     // visited in increasing candidate number (= particle index)
@@ -654,7 +681,6 @@ TL_WRAP(cellmask, TL_COMMA int with_static TL_COMMA int force, TL_COMMA with_sta
 TL_WRAP(cand, TL_COMMA int force, TL_COMMA force)
 TL_WRAP(bzero, , )
 TL_WRAP(bin_insert, , )
-TL_WRAP(bin_rank, , )
 // at most 128 VGPRs: four waves per SIMD
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_pairs(SceneK S, SceneD D)
 {
@@ -710,7 +736,7 @@ hipError_t tl_launch_cand(const TlLaunch* L, int force)
     return tl_run_t(*L, IT_SCENE, 1, TL_SCAN_T, k_cscan, k_cscan_b);
 }
 
-// one substep of pair search and impulses: bucket reset, bin size, binning, pairs
+// one substep of pair search and impulses: bucket reset and bin size, binning, pairs
 hipError_t tl_launch_contact(const TlLaunch* L)
 {
     const int nbrick = L->S ? L->D->n_active : 0;
@@ -718,8 +744,6 @@ hipError_t tl_launch_contact(const TlLaunch* L)
     hipError_t e = tl_run(*L, IT_BUCKET, L->S ? (int)(((long long)L->D->hmask + 256) / 256) : 0, k_bzero, k_bzero_b);
     if (e != hipSuccess) return e;
     e = tl_run(*L, IT_BRICK, nbrick, k_bin_insert, k_bin_insert_b);
-    if (e != hipSuccess) return e;
-    e = tl_run(*L, IT_BRICK, nbrick, k_bin_rank, k_bin_rank_b);
     if (e != hipSuccess) return e;
     return tl_run(*L, IT_PAIR, L->S ? L->S->pair_blocks : 0, k_pairs, k_pairs_b);
 }
