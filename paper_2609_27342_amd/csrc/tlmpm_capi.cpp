@@ -236,7 +236,7 @@ Offsets plan(const tlmpm_scene_desc* d, long long n_active)
     o.bact = L.take((size_t)g.n_bricks * 4);
     o.hist = L.take((size_t)(TL_MAX_TOOLS + 1) * 4 * N * f);
     o.aabb = L.take((size_t)g.n_bricks * 8 * f);
-    o.wpart = L.take((size_t)g.n_bricks * TL_MAX_TOOLS * 6 * f);
+    o.wpart = L.take((size_t)g.n_bricks * TL_MAX_TOOLS * 6 * sizeof(double));
     o.wacc = L.take(TL_MAX_TOOLS * 6 * sizeof(double));
     o.Jmat = d->material_contact ? L.take(3 * N * f) : 0;
     o.Jrig = L.take(3 * N * f);
@@ -259,11 +259,11 @@ Offsets plan(const tlmpm_scene_desc* d, long long n_active)
         o.cand_idx = L.take(N * 4);
         o.coff = L.take(((size_t)n_active + 1) * 4);
         o.hbin = L.take(4);
-        o.hmax = L.take(4);
+        o.hmax = L.take(TL_HSLOTS * TL_HSTRIDE * 4);
         size_t buckets = 4096;
         while (buckets < N / 2) buckets <<= 1;
         o.hmask = (uint32_t)(buckets - 1);
-        o.bcount = L.take(buckets * 4);
+        o.bcount = L.take(2 * buckets * 4);
         o.bids = L.take(buckets * TL_BCAP * 4);
         o.crec = L.take(N * 48);
         o.htab = L.take(buckets * 8);
@@ -471,7 +471,7 @@ extern "C" tlmpm_status tlmpm_create_scene(const tlmpm_scene_desc* d, void* ws, 
     D.rs = (float*)(base + o.rs);
     D.hist = (float*)(base + o.hist);
     D.aabb = (float*)(base + o.aabb);
-    D.wpart = (float*)(base + o.wpart);
+    D.wpart = (double*)(base + o.wpart);
     D.wacc = (double*)(base + o.wacc);
     D.Jmat = d->material_contact ? (float*)(base + o.Jmat) : nullptr;
     D.Jrig = (float*)(base + o.Jrig);
@@ -680,10 +680,6 @@ static tlmpm_status one_substep(Exec& X, const CallFlags& f, bool first)
         ProfScope ps(X.prof, 5);
         HIPCHK(tl_launch_rigid(&X.L));
     }
-    if (f.any_contact_tool) {
-        ProfScope ps(X.prof, 5);
-        HIPCHK(tl_launch_wrench(&X.L));
-    }
     {
         ProfScope ps(X.prof, 0);
         HIPCHK(tl_launch_p2g(&X.L, 1, X.cur != X.rsb ? 1 : 0, X.cur, X.rsb));
@@ -756,6 +752,10 @@ static tlmpm_status run_substeps(Exec& X, int n_substeps, const CallFlags& f, Gr
     for (; j < n_substeps; j++) {
         tlmpm_status s = one_substep(X, f, false);
         if (s) return s;
+    }
+    if (f.any_contact_tool) { // the call's wrench from the per-brick sums
+        ProfScope ps(X.prof, 5);
+        HIPCHK(tl_launch_wrench(&X.L));
     }
     return TLMPM_OK;
 }
@@ -1038,6 +1038,8 @@ extern "C" tlmpm_status tlmpm_write_state(tlmpm_scene* sc, uint32_t mask, const 
         sc->rsb = sc->cur;
         if (sc->K.material_contact) HIPCHK(tl_launch_cand(&L, 1));
     }
+    // speed bounds of the new velocities replace those gathered by the last G2P
+    if (sc->K.material_contact) HIPCHK(tl_launch_fill_i32(sc->D.hmax, TL_HSLOTS * TL_HSTRIDE, 0, sc->st));
     HIPCHK(tl_launch_aabb(&L));
     HIPCHK(hipStreamSynchronize(sc->st));
     return TLMPM_OK;
@@ -1068,9 +1070,13 @@ extern "C" tlmpm_status tlmpm_contact_stats(tlmpm_scene* sc, double out[6])
     if (!sc->K.material_contact) return TLMPM_OK;
     const size_t nb = (size_t)sc->D.hmask + 1;
     std::vector<int> cnt(nb);
-    int total = 0;
+    int total = 0, stamp = 0;
     float hb = 0.0f;
-    HIPCHK(hipMemcpyAsync(cnt.data(), sc->D.bcount, nb * 4, hipMemcpyDeviceToHost, sc->st));
+    HIPCHK(hipMemcpyAsync(&stamp, sc->D.ctr, 4, hipMemcpyDeviceToHost, sc->st));
+    HIPCHK(hipStreamSynchronize(sc->st));
+    // counts of the last substep: the buffer of its stamp (the current one minus one)
+    const int* src = sc->D.bcount + (size_t)((stamp - 1) & 1) * nb;
+    HIPCHK(hipMemcpyAsync(cnt.data(), src, nb * 4, hipMemcpyDeviceToHost, sc->st));
     HIPCHK(hipMemcpyAsync(&total, sc->D.coff + sc->D.n_active, 4, hipMemcpyDeviceToHost, sc->st));
     HIPCHK(hipMemcpyAsync(&hb, sc->D.hbin, 4, hipMemcpyDeviceToHost, sc->st));
     HIPCHK(hipStreamSynchronize(sc->st));
@@ -1117,9 +1123,8 @@ void scene_items(const tlmpm_scene* sc, int n[TL_ITEM_KINDS])
     n[IT_BRICK] = sc->D.n_active;
     n[IT_NODE] = ceil_div(K.NN, 256);
     n[IT_CELL] = K.material_contact ? ceil_div(n_bricks * TL_CELLS, 256) : 0;
-    n[IT_BUCKET] = K.material_contact ? ceil_div((long long)sc->D.hmask + 1, 256) : 0;
-    n[IT_SCENE] = 1;
     n[IT_WRENCH] = TL_MAX_TOOLS * 6;
+    n[IT_SCENE] = 1;
     n[IT_PART] = ceil_div(K.N, 256);
     n[IT_BFLAG] = ceil_div(n_bricks, 256);
     n[IT_PAIR] = K.material_contact ? K.pair_blocks : 0;

@@ -38,6 +38,8 @@
 #define TL_CKEYS 4
 #define TL_GMAX 8              // same-code groups (of <= 8 particles) per cell in a mixed brick
 #define TL_PCAP 16             // persistent pair springs kept per particle (all its partners)
+#define TL_HSLOTS 64  // slots of the speed-bound maximum (spreads the atomics)
+#define TL_HSTRIDE 1  // ints between slots (consecutive: cheap to read in every binning block)
 #define TL_PLANES 8            // lanes per candidate in the pair search
 #define TL_PCAND 32            // candidates per pair-search block (256 threads)
 #define TL_BCAP 8              // candidate records stored inline per hash bucket
@@ -113,7 +115,7 @@ struct SceneD {
     int* bact;     // [bricks] active index of a brick, -1 if it holds no particle
     float* hist;   // rigid contact history [TL_MAX_TOOLS+1][4][N]: u_t xyz, stamp
     float* aabb;   // [n_bricks][8]: min xyz, max xyz, max |v|, 0
-    float* wpart;  // [TL_MAX_TOOLS * 6][n_active] per-brick wrench sums
+    double* wpart; // [TL_MAX_TOOLS * 6][n_active] per-brick wrench sums of the call so far
     double* wacc;  // [TL_MAX_TOOLS][6]
     float* Jmat;   // [3][N] material contact impulse (candidates only)
     float* Jrig;   // [3][N] floor and tool impulse (bricks with brig set)
@@ -138,9 +140,10 @@ struct SceneD {
     int* cand_idx;      // [N] candidates of each brick, stored over the brick's particle range
     int* coff;          // [active bricks + 1] first global candidate index of each active brick
     float* hbin;        // bin edge (device scalar)
-    int* hmax;          // largest brick speed bound of this substep (float bits)
+    int* hmax;          // [TL_HSLOTS] largest brick speed bounds for the next binning (float bits)
     uint32_t hmask;     // buckets - 1 (power of two)
-    int* bcount;        // [buckets] entries of each bucket this substep (cleared per substep)
+    int* bcount;        // [2][buckets] entries of each bucket (buffer = stamp parity; the
+                        // pair pass clears the other buffer for the next substep)
     int* bids;          // [buckets][TL_BCAP] global candidate indices in arrival order
     float4* crec;       // [N][3] record of each global candidate (dense, brick by brick)
     unsigned long long* htab; // [buckets] overflow lists: generation << 32 | head
@@ -184,7 +187,7 @@ __device__ __forceinline__ float lane_xor(float v)
 
 // Launch context: one scene (parameters by value) or a batch of scenes (device
 // arrays of SceneK / SceneD and, per kind of work item, a list of (scene, block)).
-enum { IT_BRICK = 0, IT_NODE, IT_CELL, IT_BUCKET, IT_SCENE, IT_WRENCH, IT_PART, IT_BFLAG, IT_PAIR, TL_ITEM_KINDS };
+enum { IT_BRICK = 0, IT_NODE, IT_CELL, IT_WRENCH, IT_SCENE, IT_PART, IT_BFLAG, IT_PAIR, TL_ITEM_KINDS };
 
 struct TlLaunch {
     const SceneK* S;   // single scene (host copies), or null in batch mode

@@ -199,10 +199,13 @@ DEV void cscan_body(const SceneK& S, const SceneD& D, int bi)
 }
 
 
-// bin edge from the largest speed (conservative reach of every pair)
+// bin edge from the largest speed (conservative reach of every pair); the speed
+// bounds of the bricks were gathered into TL_HSLOTS slots by the G2P pass
 DEV float bin_edge(const SceneK& S, const SceneD& D)
 {
-    const float vmax = __int_as_float(*D.hmax);
+    static_assert(TL_HSLOTS == 64, "one slot per lane of a wave");
+    float vmax = __int_as_float(D.hmax[(threadIdx.x & 63) * TL_HSTRIDE]);
+    for (int o = 32; o >= 1; o >>= 1) vmax = fmaxf(vmax, __shfl_xor(vmax, o, 64));
     const float h = (2.0f * S.Rmax + 2.0f * S.dt * vmax) * 1.001f + 1e-7f;
     return fmaxf(h, 0.25f * (float)S.dx);
 }
@@ -247,35 +250,20 @@ DEV void make_rec(const SceneK& S, const SceneD& D, int p, const float x[3], flo
 // are kept in arrival order, later candidates go to a lock-free overflow list
 // (generation-stamped heads, never cleared).  The pair pass sorts a bucket's
 // numbers before use, so its result does not depend on the arrival order.
-// bucket counts of this substep start at zero
-DEV void bzero_body(const SceneK& S, const SceneD& D, int bi)
-{
-    if (!S.material_contact) return;
-    long long i = (long long)bi * blockDim.x + threadIdx.x;
-    if (i <= (long long)D.hmask) D.bcount[i] = 0;
-    // largest brick speed bound (grid-stride over the bricks, one atomic per
-    // block); the maximum of non-negative floats is taken on their bit patterns, so
-    // it does not depend on the order of the atomics.  Reset by the pair pass.
-    const long long nb = (long long)S.cbx * S.cby * S.cbz;
-    float m = 0.0f;
-    const long long stride = ((long long)D.hmask + 256) / 256 * blockDim.x; // this scene's blocks
-    for (long long b = i; b < nb; b += stride) m = fmaxf(m, D.aabb[b * 8 + 6]);
-    for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
-    if ((threadIdx.x & 63) == 0 && m > 0.0f) atomicMax(D.hmax, __float_as_int(m));
-}
-
 DEV void bin_insert_body(const SceneK& S, const SceneD& D, int bi)
 {
     if (!S.material_contact) return;
     const unsigned gen = (unsigned)D.ctr[0];
     const int brick = D.active[bi];
+    const int nc = D.bcand[bi];
+    if (!nc && bi != 0) return;
     const float hb = bin_edge(S, D);
     if (bi == 0 && threadIdx.x == 0) D.hbin[0] = hb; // for the pair pass
-    const int nc = D.bcand[bi];
     if (!nc) return;
     const float inv_h = 1.0f / hb;
     const int beg = D.cell_start[(long long)brick * TL_CELLS];
     const int g0 = D.coff[bi];
+    int* bcount = D.bcount + (gen & 1u) * ((long long)D.hmask + 1); // this substep's counts
     for (int c = threadIdx.x; c < nc; c += blockDim.x) {
         const int p = D.cand_idx[beg + c];
         const int g = g0 + c;
@@ -290,7 +278,7 @@ DEV void bin_insert_body(const SceneK& S, const SceneD& D, int bi)
         int b[3];
         bin_of(x, inv_h, b);
         uint32_t h = bin_hash(b[0], b[1], b[2], D.hmask);
-        int slot = atomicAdd(&D.bcount[h], 1);
+        int slot = atomicAdd(&bcount[h], 1);
         if (slot < TL_BCAP) {
             D.bids[(long long)h * TL_BCAP + slot] = g;
             continue;
@@ -433,7 +421,17 @@ DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
     const int stamp = D.ctr[0];
     const unsigned gen = (unsigned)stamp;
     const int hnew = stamp & 1, hold = hnew ^ 1;
-    if (bi == 0 && threadIdx.x == 0) *D.hmax = 0; // binning read it; next substep gathers anew
+    // the binning has read the speed bounds: G2P gathers them anew for the next
+    // substep
+    if (bi == 0 && threadIdx.x < TL_HSLOTS) D.hmax[threadIdx.x * TL_HSTRIDE] = 0;
+    // bucket counts: this substep's buffer, and the other one cleared for the next
+    const long long nbk = (long long)D.hmask + 1;
+    const int* bcount = D.bcount + (stamp & 1) * nbk;
+    {
+        int* nxt = D.bcount + ((stamp + 1) & 1) * nbk;
+        for (long long i = (long long)bi * blockDim.x + threadIdx.x; i < nbk; i += (long long)S.pair_blocks * blockDim.x)
+            nxt[i] = 0;
+    }
     __shared__ int s_q[TL_PCAND][TL_PCAP];
     __shared__ float s_u[TL_PCAND][TL_PCAP][3];
     __shared__ int s_nold[TL_PCAND], s_nnew[TL_PCAND];
@@ -489,7 +487,7 @@ DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
                 e2 += e * e;
             }
             hq[j] = bin_hash(bq[0] + o[0], bq[1] + o[1], bq[2] + o[2], D.hmask);
-            cntq[j] = (has && d < 27 && e2 < 0.999f * reach2) ? D.bcount[hq[j]] : 0;
+            cntq[j] = (has && d < 27 && e2 < 0.999f * reach2) ? bcount[hq[j]] : 0;
         }
         // the candidate's springs of the last substep, staged in LDS
         int nold = 0;
@@ -679,7 +677,6 @@ DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
 #define TL_COMMA ,
 TL_WRAP(cellmask, TL_COMMA int with_static TL_COMMA int force, TL_COMMA with_static TL_COMMA force)
 TL_WRAP(cand, TL_COMMA int force, TL_COMMA force)
-TL_WRAP(bzero, , )
 TL_WRAP(bin_insert, , )
 // at most 128 VGPRs: four waves per SIMD
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_pairs(SceneK S, SceneD D)
@@ -736,14 +733,12 @@ hipError_t tl_launch_cand(const TlLaunch* L, int force)
     return tl_run_t(*L, IT_SCENE, 1, TL_SCAN_T, k_cscan, k_cscan_b);
 }
 
-// one substep of pair search and impulses: bucket reset and bin size, binning, pairs
+// one substep of pair search and impulses: binning, pairs
 hipError_t tl_launch_contact(const TlLaunch* L)
 {
     const int nbrick = L->S ? L->D->n_active : 0;
     if (L->S && nbrick == 0) return hipSuccess;
-    hipError_t e = tl_run(*L, IT_BUCKET, L->S ? (int)(((long long)L->D->hmask + 256) / 256) : 0, k_bzero, k_bzero_b);
-    if (e != hipSuccess) return e;
-    e = tl_run(*L, IT_BRICK, nbrick, k_bin_insert, k_bin_insert_b);
+    hipError_t e = tl_run(*L, IT_BRICK, nbrick, k_bin_insert, k_bin_insert_b);
     if (e != hipSuccess) return e;
     return tl_run(*L, IT_PAIR, L->S ? L->S->pair_blocks : 0, k_pairs, k_pairs_b);
 }

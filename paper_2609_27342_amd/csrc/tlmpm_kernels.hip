@@ -594,7 +594,8 @@ struct KA_Args {
 // --------------------------------------------------------------------- rigid contact
 // Floor and tool contact of every particle of bricks whose AABB can reach a rigid
 // body this substep (Eqs. 14-16, 5): impulses to Jrig, cutting progress D, contact
-// springs, and per-brick wrench sums (wave tree, then waves in order).
+// springs, and per-brick wrench sums added to those of the call (wave tree, then
+// waves in order).
 DEV void rigid_body(const SceneK& S, const SceneD& D, int bi)
 {
     if (!S.floor_on && !D.tinfo[1]) return; // no rigid body touches this scene
@@ -667,12 +668,12 @@ DEV void rigid_body(const SceneK& S, const SceneD& D, int bi)
             }
         }
     }
-    if (want_wrench) {
+    if (want_wrench && s_any) { // other bricks add nothing to the call's sums
         __syncthreads();
         if (tid < n_tools * 6) {
             float acc = 0.0f;
             for (int w = 0; w < 4; w++) acc += s_wr[w][tid];
-            D.wpart[(long long)tid * D.n_active + bi] = acc;
+            D.wpart[(long long)tid * D.n_active + bi] += (double)acc;
         }
     }
 }
@@ -1033,6 +1034,10 @@ DEV void g2p_body(const SceneK& S, const SceneD& D, int bi, int cur)
         float val = s_bb[0][tid];
         for (int wv = 1; wv < 8; wv++) val = (tid < 3) ? fminf(val, s_bb[wv][tid]) : fmaxf(val, s_bb[wv][tid]);
         D.aabb[(long long)brick * 8 + tid] = val;
+        // the next binning's bin edge needs the largest speed bound; the maximum
+        // of non-negative floats is taken on their bit patterns (order-independent)
+        if (tid == 6 && S.material_contact && val > 0.0f)
+            atomicMax(D.hmax + (bi & (TL_HSLOTS - 1)) * TL_HSTRIDE, __float_as_int(val));
     }
 }
 
@@ -1398,28 +1403,38 @@ DEV void aabb_body(const SceneK& S, const SceneD& D, int bi)
         float val = s_bb[0][q];
         for (int wv = 1; wv < 4; wv++) val = (q < 3) ? fminf(val, s_bb[wv][q]) : fmaxf(val, s_bb[wv][q]);
         D.aabb[(long long)brick * 8 + q] = val;
+        if (q == 6 && S.material_contact && val > 0.0f)
+            atomicMax(D.hmax + (bi & (TL_HSLOTS - 1)) * TL_HSTRIDE, __float_as_int(val));
     }
 }
 
-// Sum of the per-brick wrench partials in fixed order (one workgroup per force or
-// torque component), added to the interval accumulator in FP64.
+// Once per call: sum of the per-brick wrench partials accumulated over the call's
+// substeps, in fixed order (one workgroup per force or torque component: four
+// running sums per thread, a tree over the workgroup), added to the interval
+// accumulator; the partials are cleared for the next call.
 DEV void wrench_body(const SceneK& S, const SceneD& D, int bi)
 {
     __shared__ double s[256];
     const int q = bi;
     if (!D.tinfo[1] || q >= D.tinfo[0] * 6) return;
-    // four independent running sums per thread, combined in a fixed order
-    const float* w = D.wpart + (long long)q * D.n_active;
+    double* w = D.wpart + (long long)q * D.n_active;
     const int n = D.n_active, T = blockDim.x;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     int b = threadIdx.x;
     for (; b + 3 * T < n; b += 4 * T) {
-        a0 += (double)w[b];
-        a1 += (double)w[b + T];
-        a2 += (double)w[b + 2 * T];
-        a3 += (double)w[b + 3 * T];
+        a0 += w[b];
+        a1 += w[b + T];
+        a2 += w[b + 2 * T];
+        a3 += w[b + 3 * T];
+        w[b] = 0.0;
+        w[b + T] = 0.0;
+        w[b + 2 * T] = 0.0;
+        w[b + 3 * T] = 0.0;
     }
-    for (; b < n; b += T) a0 += (double)w[b];
+    for (; b < n; b += T) {
+        a0 += w[b];
+        w[b] = 0.0;
+    }
     s[threadIdx.x] = (a0 + a1) + (a2 + a3);
     __syncthreads();
     for (int o = blockDim.x / 2; o > 0; o >>= 1) {
