@@ -77,6 +77,27 @@ struct Timing {
     }
 };
 
+// A second stream for the launches of a substep that do not depend on the label
+// pass or the pair search (rigid contact, slot tables), joined before P2G.  Default
+// priority, created on first use.
+struct Fork {
+    hipStream_t aux = nullptr;
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr}; // start, labels done, aux done
+    hipError_t init()
+    {
+        if (aux) return hipSuccess;
+        hipError_t e = hipStreamCreateWithFlags(&aux, hipStreamNonBlocking);
+        for (int i = 0; i < 3 && e == hipSuccess; i++) e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
+        return e;
+    }
+    ~Fork()
+    {
+        for (hipEvent_t x : ev)
+            if (x) (void)hipEventDestroy(x);
+        if (aux) (void)hipStreamDestroy(aux);
+    }
+};
+
 struct tlmpm_scene {
     SceneK K;
     SceneD D;
@@ -90,6 +111,7 @@ struct tlmpm_scene {
     std::vector<int> active_host;
     Timing prof;
     GraphCache graphs;
+    Fork fork;
 };
 
 // Brackets one launch with events when timing is on.
@@ -631,12 +653,43 @@ struct Exec {
     Timing* prof;      // event timing of the launches, or null
     int cur, rsb;      // slot table in use / of the pending re-scatter
     bool pending;      // some scene has a pending F update
+    Fork* fork = nullptr; // second stream, or null (everything on L.st)
+};
+
+// launches on the second stream (after the main stream's work so far) when there
+// is one and timing is off; else on the main stream
+struct Side {
+    Exec& X;
+    TlLaunch La;
+    bool par, started = false;
+    explicit Side(Exec& x) : X(x), La(x.L)
+    {
+        par = X.fork && X.fork->aux && !(X.prof && X.prof->on);
+        if (par) La.st = X.fork->aux;
+    }
+    // the second stream waits for what the main stream has queued so far
+    hipError_t after_main(int ev)
+    {
+        if (!par) return hipSuccess;
+        started = true;
+        hipError_t e = hipEventRecord(X.fork->ev[ev], X.L.st);
+        return e != hipSuccess ? e : hipStreamWaitEvent(X.fork->aux, X.fork->ev[ev], 0);
+    }
+    // the main stream waits for the second stream's work
+    hipError_t join()
+    {
+        if (!started) return hipSuccess;
+        started = false;
+        hipError_t e = hipEventRecord(X.fork->ev[2], X.fork->aux);
+        return e != hipSuccess ? e : hipStreamWaitEvent(X.L.st, X.fork->ev[2], 0);
+    }
 };
 
 // label pass over the tools flagged TL_TOOL_LABELS (uploaded with their counts),
 // then slot-table maintenance and contact candidates of the bricks whose codes
-// changed (no host synchronisation)
-static tlmpm_status label_pass(Exec& X, bool reset_D)
+// changed (no host synchronisation).  With a side stream, the slot tables are built
+// there, beside the candidates.
+static tlmpm_status label_pass(Exec& X, bool reset_D, Side* side = nullptr)
 {
     if (reset_D) {
         ProfScope ps(X.prof, 5);
@@ -651,7 +704,10 @@ static tlmpm_status label_pass(Exec& X, bool reset_D)
     const int dst = (X.pending && X.cur == X.rsb) ? 1 - X.cur : X.cur;
     {
         ProfScope ps(X.prof, 3);
-        HIPCHK(tl_launch_slots(&X.L, dst, X.cur, 0));
+        // the slot tables read the cell summaries and the codes without the
+        // candidate bit, which the candidate pass may rewrite meanwhile
+        if (side) HIPCHK(side->after_main(1));
+        HIPCHK(tl_launch_slots(side ? &side->La : &X.L, dst, X.cur, 0));
     }
     X.cur = dst;
     if (X.L.any_material) { // cell code masks come with the cell summaries (k_mixed)
@@ -665,21 +721,37 @@ struct CallFlags {
     bool any_labels = false, any_new = false, any_contact_tool = false, any_rigid = false;
 };
 
-// one substep of the whole path
+// one substep of the whole path.  With material contact and a side stream, the
+// launches that do not depend on the pair search run beside it: rigid contact
+// (reads only the last substep's motion, the tools and the cutting progress, reset
+// first when a cut starts) from the start of the substep, the slot tables after the
+// label pass; P2G waits for them.
 static tlmpm_status one_substep(Exec& X, const CallFlags& f, bool first)
 {
+    Side side(X);
+    side.par = side.par && X.L.any_material;
+    const bool reset_D = f.any_labels && f.any_new && first;
+    if (reset_D) {
+        ProfScope ps(X.prof, 5);
+        HIPCHK(tl_launch_resetD(&X.L));
+    }
+    if (f.any_rigid && side.par) {
+        HIPCHK(side.after_main(0));
+        HIPCHK(tl_launch_rigid(&side.La));
+    }
     if (f.any_labels) {
-        tlmpm_status s = label_pass(X, f.any_new && first);
+        tlmpm_status s = label_pass(X, false, side.par ? &side : nullptr);
         if (s) return s;
     }
     if (X.L.any_material) {
         ProfScope ps(X.prof, 4);
         HIPCHK(tl_launch_contact(&X.L));
     }
-    if (f.any_rigid) {
+    if (f.any_rigid && !side.par) {
         ProfScope ps(X.prof, 5);
         HIPCHK(tl_launch_rigid(&X.L));
     }
+    HIPCHK(side.join());
     {
         ProfScope ps(X.prof, 0);
         HIPCHK(tl_launch_p2g(&X.L, 1, X.cur != X.rsb ? 1 : 0, X.cur, X.rsb));
@@ -765,6 +837,7 @@ static Exec single_exec(tlmpm_scene* sc)
     Exec X;
     X.L = single_launch(sc);
     X.prof = &sc->prof;
+    X.fork = &sc->fork;
     X.cur = sc->cur;
     X.rsb = sc->rsb;
     X.pending = sc->f_pending;
@@ -814,6 +887,7 @@ extern "C" tlmpm_status tlmpm_assign_labels(tlmpm_scene* sc, const tlmpm_blade* 
     tlmpm_status s = upload_tools(sc, t, n_blades, tinfo);
     if (s) return s;
     Exec X = single_exec(sc);
+    X.fork = nullptr;
     s = label_pass(X, any_new);
     single_done(sc, X);
     return s;
@@ -883,6 +957,7 @@ extern "C" tlmpm_status tlmpm_step(tlmpm_scene* sc, const tlmpm_tool* tools, int
     if (s) return s;
     s = upload_tools(sc, dtl, n_tools, tinfo);
     if (s) return s;
+    HIPCHK(sc->fork.init());
     Exec X = single_exec(sc);
     s = run_substeps(X, n_substeps, f, &sc->graphs);
     single_done(sc, X);
@@ -1176,6 +1251,7 @@ struct tlmpm_batch {
     hipEvent_t up_done = nullptr;  // the last upload from h_tools finished
     Timing prof;
     GraphCache graphs;
+    Fork fork;
     ~tlmpm_batch()
     {
         if (h_tools) (void)hipHostFree(h_tools);
@@ -1321,9 +1397,11 @@ extern "C" tlmpm_status tlmpm_batch_step(tlmpm_batch* b, const tlmpm_tool* tools
     }
     HIPCHK(hipMemcpyAsync(b->d_tools, b->h_tools, n * sizeof(BatchTools), hipMemcpyHostToDevice, b->st));
     HIPCHK(hipEventRecord(b->up_done, b->st));
+    HIPCHK(b->fork.init());
     Exec X;
     X.L = b->L;
     X.prof = &b->prof;
+    X.fork = &b->fork;
     X.cur = b->cur;
     X.rsb = b->rsb;
     X.pending = b->pending;
