@@ -29,7 +29,7 @@ HBM_PEAK_GBS = 8000.0
 #   whole substep (each persistent field read/written once)           -> 136 B
 ALG_BYTES = {"p2g": 100, "g2p": 64}
 ALG_STEP_BYTES = 136
-DEFAULTS = {"small": (100, 10), "small-deep": (100, 10), "medium": (2000, 100), "large": (200, 10),
+DEFAULTS = {"small": (100, 10), "small-deep": (100, 10), "medium": (3000, 300), "large": (200, 10),
             "batched": (100, 10)}
 
 
