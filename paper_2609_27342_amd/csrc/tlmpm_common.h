@@ -40,8 +40,10 @@
 #define TL_PCAP 16             // persistent pair springs kept per particle (all its partners)
 #define TL_HSLOTS 64  // slots of the speed-bound maximum (spreads the atomics)
 #define TL_HSTRIDE 1  // ints between slots (consecutive: cheap to read in every binning block)
-#define TL_PLANES 8            // lanes per candidate in the pair search
-#define TL_PCAND 32            // candidates per pair-search block (256 threads)
+#ifndef TL_PLANES
+#define TL_PLANES 8            // lanes per candidate in the pair search (4 or 8)
+#endif
+#define TL_PCAND (256 / TL_PLANES) // candidates per pair-search block (256 threads)
 #define TL_BCAP 8              // candidate records stored inline per hash bucket
 
 // tool flags (same values as the ABI)

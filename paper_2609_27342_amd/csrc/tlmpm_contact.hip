@@ -375,14 +375,16 @@ DEV bool pair_impulse(const SceneK& S, const PState& o, const PState& r, float u
 }
 
 // Pair search and impulses over all candidates of the scene (grid-stride over the
-// global candidate list).  TL_PLANES lanes per candidate: lane l scans neighbour
-// bins l, l + 8, l + 16, l + 24 (of 27; records in particle-index order, then the
-// bucket's overflow list) and sums its contacts; the lane sums are added by a fixed
-// shuffle tree.  The tangential spring of a pair is kept by both particles (each
-// in its own list, oriented for the pair's lower index): both sides evaluate the
-// pair with the same operands, so the two copies stay equal and no particle reads
-// its partner's list.  A list is only searched by partner, so its order does not
-// matter.
+// global candidate list).  TL_PLANES lanes per candidate: lane l fetches the counts
+// of neighbour bins l, l + TL_PLANES, ... (of 27); the bins' entries (in particle
+// index order) are compacted into one list per candidate in bin order, which the
+// lanes visit strided, then the buckets' overflow lists; each lane sums its
+// contacts and the lane sums are added by a fixed shuffle tree.  The tangential
+// spring of a pair is kept by both particles (each in its own list, oriented for
+// the pair's lower index): both sides evaluate the pair with the same operands, so
+// the two copies stay equal and no particle reads its partner's list.  A list is
+// only searched by partner, so its order does not matter.
+
 // the first c (<= TL_BCAP) candidate numbers of bucket h in increasing order
 // (sorting network on eight values; unused places hold INT_MAX)
 DEV void bucket_sorted(const SceneD& D, uint32_t h, int c, int e[TL_BCAP])
@@ -413,7 +415,7 @@ DEV void bucket_sorted(const SceneD& D, uint32_t h, int c, int e[TL_BCAP])
     }
 }
 
-#define TL_PLIST 96 // compacted neighbour entries per candidate held in LDS
+#define TL_PLIST (TL_PLANES == 8 ? 96 : 64) // compacted neighbour entries per candidate held in LDS
 DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
 {
     if (!S.material_contact) return;
@@ -446,6 +448,7 @@ DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
     const long long N = S.N;
     const int sub = threadIdx.x / TL_PLANES; // candidate of this lane group
     const int l = threadIdx.x % TL_PLANES;   // lane in the group
+    constexpr int NBL = (27 + TL_PLANES - 1) / TL_PLANES; // bins per lane
     const int stride = S.pair_blocks * TL_PCAND;
     for (int c0 = bi * TL_PCAND; c0 < total; c0 += stride) {
         const int g = c0 + sub;
@@ -458,7 +461,7 @@ DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
             rp[2] = src[2];
         }
         const int p = has ? __float_as_int(rp[0].x) : -1;
-        // this lane's bins: l, l + 8, l + 16, l + 24 of the 27 around the candidate
+        // this lane's bins: l, l + TL_PLANES, ... of the 27 around the candidate
         int bq[3] = {0, 0, 0};
         if (has) {
             const float xp[3] = {rp[1].x, rp[1].y, rp[1].z};
@@ -472,10 +475,10 @@ DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
             lo[a] = xa - (float)bq[a] * hb;
             hi[a] = (float)(bq[a] + 1) * hb - xa;
         }
-        uint32_t hq[4];
-        int cntq[4];
+        uint32_t hq[NBL];
+        int cntq[NBL];
 #pragma unroll
-        for (int j = 0; j < 4; j++) {
+        for (int j = 0; j < NBL; j++) {
             const int d = l + TL_PLANES * j;
             const int o[3] = {d % 3 - 1, (d / 3) % 3 - 1, d / 9 - 1};
             // a bin whose nearest point is farther than sqrt(0.999) h holds no
@@ -509,11 +512,11 @@ DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
         // inline entries of the 27 bins in bin order, compacted into one list per
         // candidate (the first TL_PLIST of them; the rest are visited by the lane
         // that owns their bin)
-        // list position of the first entry of bin d = l + 8 j: the entries of the
+        // list position of the first entry of bin d = l + TL_PLANES j: the entries of the
         // rows j' < j in every lane, plus those of row j in the lanes below l
-        int pos[4], n_list = 0;
+        int pos[NBL], n_list = 0;
 #pragma unroll
-        for (int j = 0; j < 4; j++) {
+        for (int j = 0; j < NBL; j++) {
             const int c = min(cntq[j], TL_BCAP);
             int incl = c;
 #pragma unroll
@@ -525,7 +528,7 @@ DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
             n_list += __shfl(incl, TL_PLANES - 1, TL_PLANES);
         }
 #pragma unroll
-        for (int j = 0; j < 4; j++) {
+        for (int j = 0; j < NBL; j++) {
             const int c = min(cntq[j], TL_BCAP);
             if (c == 0) continue;
             const int d = l + TL_PLANES * j;
@@ -608,7 +611,7 @@ DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
             }
             // entries beyond the list, then overflow lists (rare), by the bin's lane
 #pragma unroll
-            for (int j = 0; j < 4; j++) {
+            for (int j = 0; j < NBL; j++) {
                 const int d = l + TL_PLANES * j;
                 if (d >= 27) break;
                 const int c = min(cntq[j], TL_BCAP);
@@ -644,10 +647,9 @@ DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
             }
         }
         // fixed-order sum over the lanes of the group
-        for (int a = 0; a < 3; a++)
-        {
-            static_assert(TL_PLANES == 8, "the lane sum below covers 8 lanes");
-            Jt[a] += lane_xor<4>(Jt[a]);
+        for (int a = 0; a < 3; a++) {
+            static_assert(TL_PLANES == 4 || TL_PLANES == 8, "the lane sum below covers 4 or 8 lanes");
+            if constexpr (TL_PLANES == 8) Jt[a] += lane_xor<4>(Jt[a]);
             Jt[a] += lane_xor<2>(Jt[a]);
             Jt[a] += lane_xor<1>(Jt[a]);
         }

@@ -105,12 +105,23 @@ DEV void box_scan(BoxTab& T, int* s_total, int wave)
 }
 
 // Phase 3 (after a barrier, threads < 125): codes of this thread's node.
-DEV void box_codes(const SceneK& S, const uint32_t* scode, BoxTab& T, int bn)
+// The same in two steps, so that the code loads are in flight together with the
+// loads that follow (the partial gather): the first two codes of node bn into
+// registers, then into the table (further codes loaded there).
+DEV void codes_pre(const SceneK& S, const uint32_t* scode, const BoxTab& T, int bn, uint32_t pre[2])
 {
-    int c = T.cnt[bn], b0 = T.base[bn];
-    long long g = T.gid[bn];
+    const int c = T.cnt[bn];
+    const long long g = T.gid[bn];
+    pre[0] = c > 0 ? scode[g] : 0u;
+    pre[1] = c > 1 ? scode[S.NN + g] : 0u;
+}
+
+DEV void codes_put(const SceneK& S, const uint32_t* scode, BoxTab& T, int bn, const uint32_t pre[2])
+{
+    const int c = T.cnt[bn], b0 = T.base[bn];
+    const long long g = T.gid[bn];
     for (int s = 0; s < c; s++) {
-        T.code[b0 + s] = scode[(long long)s * S.NN + g];
+        T.code[b0 + s] = s == 0 ? pre[0] : s == 1 ? pre[1] : scode[(long long)s * S.NN + g];
         T.node_of[b0 + s] = (unsigned char)bn;
     }
 }
@@ -740,11 +751,14 @@ DEV void p2g_body(const SceneK& S, const SceneD& D, int bi, KA_Args A)
     }
     // ---- phase 3: per box node: codes, re-scatter sums, coupling, v~ (Eq. 8, MUSL)
     if (tid < TL_BOXN) {
+        uint32_t pre_r[2], pre_c[2];
+        if (use_r) codes_pre(S, D.scode[A.rsb], Tr, tid, pre_r);
+        if (use_c) codes_pre(S, D.scode[A.cur], Tc, tid, pre_c);
         if (use_r) {
-            box_codes(S, D.scode[A.rsb], Tr, tid);
             const int c = Tr.cnt[tid], b0 = Tr.base[tid];
+            if (c > 0) gather_node<4>(S, s_nb, D.rs, Tr, tid, s_rsum);
+            codes_put(S, D.scode[A.rsb], Tr, tid, pre_r);
             if (c > 0) {
-                gather_node<4>(S, s_nb, D.rs, Tr, tid, s_rsum);
                 couple_node<4>(Tr, b0, c, s_rsum, 1, s_vt);
                 for (int a = 0; a < c; a++) {
                     float m = s_rsum[(b0 + a) * 4];
@@ -753,7 +767,7 @@ DEV void p2g_body(const SceneK& S, const SceneD& D, int bi, KA_Args A)
                 }
             }
         }
-        if (use_c) box_codes(S, D.scode[A.cur], Tc, tid);
+        if (use_c) codes_put(S, D.scode[A.cur], Tc, tid, pre_c);
     }
     if (A.do_p2g)
         for (int q = tid; q < total_c * 7; q += TL_WG) s_acc[q] = 0.0f;
@@ -941,10 +955,12 @@ DEV void g2p_body(const SceneK& S, const SceneD& D, int bi, int cur)
     }
     // ---- phase 3: per box node: codes, P2G sums, coupling (Eq. 8), v^n and dv (Eq. 9)
     if (tid < TL_BOXN) {
-        box_codes(S, D.scode[cur], T, tid);
+        uint32_t pre[2];
+        codes_pre(S, D.scode[cur], T, tid, pre);
         const int c = T.cnt[tid], b0 = T.base[tid];
+        if (c > 0) gather_node<7>(S, s_nb, D.p2g, T, tid, s_sum);
+        codes_put(S, D.scode[cur], T, tid, pre);
         if (c > 0) {
-            gather_node<7>(S, s_nb, D.p2g, T, tid, s_sum);
             float* gvn = s_grid;
             float* gdv = s_grid + TL_BOX_SLOTS * 3;
             couple_node<7>(T, b0, c, s_sum, 1, gvn);
