@@ -180,25 +180,36 @@ DEV void gather_node(const SceneK& S, const int* nb, const float* __restrict__ p
         cbase[d] = (unsigned)ai * (unsigned)(S.scap * TL_BOXN) + (unsigned)pn;
         valid |= 1u << d;
     }
-    for (int s = 0; s < c; s++) {
-        float acc[QP];
+    // two slots per pass, so that the loads of both are in flight together
+    for (int s = 0; s < c; s += 2) {
+        const bool two = s + 1 < c;
+        float acc[2][QP];
 #pragma unroll
-        for (int q = 0; q < QP; q++) acc[q] = 0.0f;
+        for (int u = 0; u < 2; u++)
+#pragma unroll
+            for (int q = 0; q < QP; q++) acc[u][q] = 0.0f;
 #pragma unroll
         for (int d = 0; d < 8; d++) {
             if (!(valid & (1u << d))) continue;
-            const float4* pp = (const float4*)(part + (size_t)(cbase[d] + (unsigned)(s * TL_BOXN)) * QP);
 #pragma unroll
-            for (int q4 = 0; q4 < QP / 4; q4++) {
-                float4 v4 = pp[q4];
-                acc[4 * q4 + 0] += v4.x;
-                acc[4 * q4 + 1] += v4.y;
-                acc[4 * q4 + 2] += v4.z;
-                acc[4 * q4 + 3] += v4.w;
+            for (int u = 0; u < 2; u++) {
+                if (u == 1 && !two) continue;
+                const float4* pp = (const float4*)(part + (size_t)(cbase[d] + (unsigned)((s + u) * TL_BOXN)) * QP);
+#pragma unroll
+                for (int q4 = 0; q4 < QP / 4; q4++) {
+                    float4 v4 = pp[q4];
+                    acc[u][4 * q4 + 0] += v4.x;
+                    acc[u][4 * q4 + 1] += v4.y;
+                    acc[u][4 * q4 + 2] += v4.z;
+                    acc[u][4 * q4 + 3] += v4.w;
+                }
             }
         }
 #pragma unroll
-        for (int q = 0; q < Q; q++) dst[(b0 + s) * Q + q] = acc[q];
+        for (int q = 0; q < Q; q++) dst[(b0 + s) * Q + q] = acc[0][q];
+        if (two)
+#pragma unroll
+            for (int q = 0; q < Q; q++) dst[(b0 + s + 1) * Q + q] = acc[1][q];
     }
 }
 
