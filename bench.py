@@ -30,7 +30,7 @@ HBM_PEAK_GBS = 8000.0
 ALG_BYTES = {"p2g": 100, "g2p": 64}
 ALG_STEP_BYTES = 136
 DEFAULTS = {"small": (100, 10), "small-deep": (100, 10), "medium": (3000, 300), "large": (200, 10),
-            "batched": (100, 10)}
+            "batched": (100, 10), "knife": (600, 50)}
 
 
 def run_steps(g, scene, j0, j1):
@@ -191,6 +191,59 @@ def bench_batched(args, K, Wm):
     }
 
 
+def bench_knife(args, K, Wm):
+    """Two-way coupled knife (free rigid knife on a soft block): every interval the
+    knife's tool record is held over `interval` substeps, the interval-averaged
+    wrench comes back to the host and advances the knife; the timed region includes
+    those round trips."""
+    import torch
+    from paper_2609_27342_amd import tlmpm, workloads as W
+    from paper_2609_27342_amd.coupling import KnifeRollout
+    torch.cuda.set_device(0)
+    sc = W.knife()
+    n = sc["X"].shape[0]
+    iv = sc["knife"]["interval"]
+    g = tlmpm.Scene(sc)
+    g.graphs(args.graphs)
+    ro = KnifeRollout(g, sc)
+    ro.advance(max(1, Wm // iv))
+    torch.cuda.synchronize()
+    ki = max(1, K // iv)
+    t0 = time.perf_counter()
+    ro.advance(ki)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    steps = ki * iv
+    value = n * steps / (t1 - t0)
+    status = g.status()
+    P = max(1, min(args.profile_steps, K) // iv)
+    g.profile(True)
+    ro.advance(P)
+    prof = g.profile_read()
+    g.profile(False)
+    st = ro.body.state()
+    return {
+        "metric": "particle-steps/s per GPU",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": max(1, Wm // iv) * iv,
+        "ms_per_step": (t1 - t0) * 1e3 / steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "knife", "particles": n, "dt": sc["params"]["dt"], "interval": iv,
+                   "knife_mass": sc["knife"]["body"]["mass"], "path": "graph" if args.graphs else "plain",
+                   "knife_end": {"x": st["x"].tolist(), "v": st["v"].tolist(), "omega": st["omega"].tolist()}},
+        "status": status,
+        "roofline": roofline_of(prof, value, n, 0, None),
+        "cpu_baseline": None,
+    }
+
+
 def bench_served(args):
     """Continuous batching of arriving rollouts (Poisson arrivals, HBM-budget
     admission); latency from arrival to result."""
@@ -277,6 +330,9 @@ def main():
         return
     if args.workload == "batched":
         print(json.dumps(bench_batched(args, K, max(Wm, 1))))
+        return
+    if args.workload == "knife":
+        print(json.dumps(bench_knife(args, K, Wm)))
         return
     scene = W.CONFIGS[args.workload]()
     n = scene["X"].shape[0]

@@ -97,16 +97,24 @@ typedef struct {
 #define TLMPM_TOOL_CUTTING 4u  /* directional contact work and release (Eq. 5) */
 #define TLMPM_TOOL_ADVANCE 8u  /* translate the pose by dt * velocity after each substep */
 
-/* A kinematic rigid tool: the zero-thickness rectangle of its blade record,
- * |l| <= half_len along e and -b_back <= f <= 0 along d, in the plane s = 0. */
+/* A rigid tool: the zero-thickness rectangle of its blade record, |l| <= half_len
+ * along e and -b_back <= f <= 0 along d, in the plane s = 0, moving with the twist
+ * (v_B, omega_B) about x_B.  Its inverse effective mass at a contact point x_c
+ * along the contact normal n (Sec. III-F, rigid contact) is
+ *   w = w_B + inv_mass + (r x n) . inv_inertia (r x n),  r = x_c - x_B,
+ * so a kinematically prescribed tool has all three zero, and a free rigid body
+ * has x_B at its centre of mass, inv_mass = 1/M and inv_inertia = I^-1 in world
+ * axes (tlmpm_rigid_tool fills these from a tlmpm_rigid_body). */
 typedef struct {
     tlmpm_blade blade;
-    double x_B[3];     /* torque reference point of the tool (Eq. 16) */
+    double x_B[3];     /* torque reference point of the tool (Eq. 16); centre of mass */
     double v_B[3];     /* linear velocity */
     double omega_B[3]; /* angular velocity */
-    double w_B;        /* inverse effective mass along the normal; 0 = prescribed */
+    double w_B;        /* constant part of the inverse effective mass */
     uint32_t flags;    /* TLMPM_TOOL_* */
     int32_t reserved;
+    double inv_mass;       /* 1/M of a free tool, else 0 */
+    double inv_inertia[9]; /* world-frame inverse inertia about x_B, row major, else 0 */
 } tlmpm_tool;
 
 /* Device bytes a scene of this description needs (depends on n, cells and the
@@ -119,6 +127,38 @@ tlmpm_status tlmpm_create_scene(const tlmpm_scene_desc* desc, void* dev_workspac
                                 void* hip_stream, tlmpm_scene** out);
 
 tlmpm_status tlmpm_destroy_scene(tlmpm_scene* scene);
+
+/* ---- Two-way tool coupling (Sec. III-A, III-F, III-G).  The paper leaves the
+ * tool's rigid-body dynamics to an external solver that receives the interval-
+ * averaged wrench of tlmpm_step and returns the next pose and twist; these two
+ * host-only calls are such a solver for a free rigid tool (a knife released under
+ * gravity): tlmpm_rigid_step advances the body, tlmpm_rigid_tool turns it into the
+ * tool record of the next interval (pose and twist held over the interval). */
+typedef struct {
+    double x[3];       /* centre of mass, world */
+    double q[4];       /* orientation, unit quaternion (w, x, y, z), body -> world */
+    double v[3];       /* velocity of the centre of mass */
+    double omega[3];   /* angular velocity, world axes */
+    double mass;       /* M > 0 */
+    double inertia[3]; /* principal moments of inertia about the centre of mass (body axes) */
+} tlmpm_rigid_body;
+
+/* One step of length h > 0 of the Newton-Euler equations under the wrench
+ * [6] = (force, torque about x) and gravity, semi-implicit (symplectic) Euler:
+ *   v += h (F / M + g);  omega_b += h I^-1 (tau_b - omega_b x I omega_b) in body axes;
+ *   x += h v;  q += (h / 2) (0, omega) q, renormalised.
+ * TLMPM_E_INVALID for a null pointer, h <= 0, M or a moment <= 0, a zero or
+ * non-finite quaternion, or a non-finite result (the body is then unchanged). */
+tlmpm_status tlmpm_rigid_step(tlmpm_rigid_body* body, const double wrench[6], const double gravity[3], double h);
+
+/* Tool record of a blade fixed to the body: blade_body holds x_e, n, e, d in body
+ * axes relative to the centre of mass (its v_e is ignored) and the band sizes, cut
+ * index and new-cut flag, which are copied.  Output in world axes: x_e = x + R x_e,
+ * n, e, d rotated, v_e = v + omega x (x_e - x); x_B = x, v_B = v, omega_B = omega,
+ * w_B = 0, inv_mass = 1/M, inv_inertia = R diag(1/I) R^T; flags as given.
+ * TLMPM_E_INVALID for null pointers or a body that tlmpm_rigid_step would refuse. */
+tlmpm_status tlmpm_rigid_tool(const tlmpm_rigid_body* body, const tlmpm_blade* blade_body, uint32_t flags,
+                              tlmpm_tool* out);
 
 /* Side-label pass (Eqs. 3, 4, 6) on the stored x^n, v^n for each blade in turn.
  * Digits only go 0 -> 1 or 2.  A blade with new_cut first resets D to zero for

@@ -44,6 +44,7 @@ class Tool(C.Structure):
         ("blade", Blade), ("x_B", C.c_double * 3), ("v_B", C.c_double * 3),
         ("omega_B", C.c_double * 3), ("w_B", C.c_double),
         ("contact", C.c_int32), ("cutting", C.c_int32),
+        ("inv_mass", C.c_double), ("inv_inertia", C.c_double * 9),
     ]
 
 
@@ -131,6 +132,10 @@ def make_tool(t):
     for k in ("x_B", "v_B", "omega_B"):
         _vec3(getattr(T, k), np.asarray(t.get(k, (0.0, 0.0, 0.0)), dtype=np.float64))
     T.w_B = float(t.get("w_B", 0.0))
+    T.inv_mass = float(t.get("inv_mass", 0.0))
+    ii = np.asarray(t.get("inv_inertia", np.zeros(9)), dtype=np.float64).reshape(9)
+    for i in range(9):
+        T.inv_inertia[i] = float(ii[i])
     T.contact = int(t.get("contact", 1))
     T.cutting = int(t.get("cutting", 0))
     return T

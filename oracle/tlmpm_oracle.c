@@ -80,6 +80,8 @@ typedef struct {
     double w_B;        /* inverse effective mass, 0 for a prescribed tool */
     int32_t contact;   /* tool-material contact on */
     int32_t cutting;   /* directional contact work and release of Eq. 5 */
+    double inv_mass;   /* a free rigid tool: 1/M ... */
+    double inv_inertia[9]; /* ... and I^-1 about x_B in world axes (row major) */
 } orc_tool;
 
 /* ------------------------------------------------------------------------- */
@@ -550,10 +552,20 @@ static void rigid_contact(orc_scene* s, int body, const orc_tool* T, double* wre
                 vB[j] = T->v_B[j];
                 wB[j] = T->omega_B[j];
             }
-            invm = T->w_B;
         }
         /* relative velocity at the contact point and predicted gap (Eq. 14) */
         double arm[3] = {xc[0] - xB[0], xc[1] - xB[1], xc[2] - xB[2]}, wxr[3];
+        if (body > 0) {
+            /* inverse effective mass of the tool at x_c along n_B (Sec. III-F):
+             * the normal velocity change of the contact point per unit normal
+             * impulse, 1/M + (r x n) . I^-1 (r x n), plus a given constant part */
+            double rn[3], Irn[3];
+            cross3(arm, nB, rn);
+            for (int i = 0; i < 3; i++)
+                Irn[i] = T->inv_inertia[3 * i] * rn[0] + T->inv_inertia[3 * i + 1] * rn[1] +
+                         T->inv_inertia[3 * i + 2] * rn[2];
+            invm = T->w_B + T->inv_mass + dot3(rn, Irn);
+        }
         cross3(wB, arm, wxr);
         double vrel[3] = {v[0] - (vB[0] + wxr[0]), v[1] - (vB[1] + wxr[1]), v[2] - (vB[2] + wxr[2])};
         double vrn = dot3(vrel, nB);

@@ -927,6 +927,8 @@ static tlmpm_status convert_tools(const tlmpm_scene* sc, const tlmpm_tool* tools
             o.wB[a] = (float)T.omega_B[a];
         }
         o.invm = (float)T.w_B;
+        o.imass = (float)T.inv_mass;
+        for (int a = 0; a < 9; a++) o.iinv[a] = (float)T.inv_inertia[a];
         o.flags = T.flags;
         o.slot = 1 + t;
         any_contact_tool |= (T.flags & TLMPM_TOOL_CONTACT) != 0;
@@ -1168,6 +1170,131 @@ extern "C" tlmpm_status tlmpm_contact_stats(tlmpm_scene* sc, double out[6])
     out[3] = (double)over;
     out[4] = mx;
     out[5] = hb;
+    return TLMPM_OK;
+}
+
+// ------------------------------------------------------------- rigid tool body
+namespace {
+// rotation matrix (row major) of the unit quaternion (w, x, y, z)
+void quat_rot(const double q[4], double R[9])
+{
+    const double w = q[0], x = q[1], y = q[2], z = q[3];
+    R[0] = 1 - 2 * (y * y + z * z);
+    R[1] = 2 * (x * y - w * z);
+    R[2] = 2 * (x * z + w * y);
+    R[3] = 2 * (x * y + w * z);
+    R[4] = 1 - 2 * (x * x + z * z);
+    R[5] = 2 * (y * z - w * x);
+    R[6] = 2 * (x * z - w * y);
+    R[7] = 2 * (y * z + w * x);
+    R[8] = 1 - 2 * (x * x + y * y);
+}
+
+void mat_vec(const double M[9], const double a[3], double out[3])
+{
+    for (int i = 0; i < 3; i++) out[i] = M[3 * i] * a[0] + M[3 * i + 1] * a[1] + M[3 * i + 2] * a[2];
+}
+
+void mat_tvec(const double M[9], const double a[3], double out[3]) // M^T a
+{
+    for (int i = 0; i < 3; i++) out[i] = M[i] * a[0] + M[3 + i] * a[1] + M[6 + i] * a[2];
+}
+
+void cross(const double a[3], const double b[3], double out[3])
+{
+    out[0] = a[1] * b[2] - a[2] * b[1];
+    out[1] = a[2] * b[0] - a[0] * b[2];
+    out[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+bool body_ok(const tlmpm_rigid_body* b)
+{
+    if (!b || !(b->mass > 0.0) || !std::isfinite(b->mass)) return false;
+    double qq = 0.0;
+    for (int i = 0; i < 4; i++) qq += b->q[i] * b->q[i];
+    if (!(qq > 0.0) || !std::isfinite(qq)) return false;
+    for (int i = 0; i < 3; i++)
+        if (!(b->inertia[i] > 0.0) || !std::isfinite(b->inertia[i])) return false;
+    return true;
+}
+} // namespace
+
+extern "C" tlmpm_status tlmpm_rigid_step(tlmpm_rigid_body* body, const double wrench[6], const double gravity[3], double h)
+{
+    if (!body || !wrench || !gravity || !(h > 0.0)) return fail(TLMPM_E_INVALID, "bad arguments");
+    if (!body_ok(body)) return fail(TLMPM_E_INVALID, "body needs mass > 0, moments > 0 and a nonzero quaternion");
+    tlmpm_rigid_body b = *body;
+    double R[9];
+    quat_rot(b.q, R);
+    // linear momentum
+    for (int a = 0; a < 3; a++) b.v[a] += h * (wrench[a] / b.mass + gravity[a]);
+    // Euler's equations in body axes (explicit gyroscopic term)
+    double wb[3], tb[3], Iw[3], g[3];
+    mat_tvec(R, b.omega, wb);
+    mat_tvec(R, wrench + 3, tb);
+    for (int a = 0; a < 3; a++) Iw[a] = b.inertia[a] * wb[a];
+    cross(wb, Iw, g);
+    for (int a = 0; a < 3; a++) wb[a] += h * (tb[a] - g[a]) / b.inertia[a];
+    mat_vec(R, wb, b.omega);
+    // position and orientation from the new velocities
+    for (int a = 0; a < 3; a++) b.x[a] += h * b.v[a];
+    const double w = b.q[0], x = b.q[1], y = b.q[2], z = b.q[3];
+    const double* o = b.omega;
+    double dq[4] = {-(o[0] * x + o[1] * y + o[2] * z), o[0] * w + o[1] * z - o[2] * y, o[1] * w + o[2] * x - o[0] * z,
+                    o[2] * w + o[0] * y - o[1] * x}; // (0, omega) q
+    double nq = 0.0;
+    for (int i = 0; i < 4; i++) {
+        b.q[i] += 0.5 * h * dq[i];
+        nq += b.q[i] * b.q[i];
+    }
+    nq = std::sqrt(nq);
+    for (int i = 0; i < 4; i++) b.q[i] /= nq;
+    bool fin = true;
+    for (int a = 0; a < 3; a++) fin = fin && std::isfinite(b.x[a]) && std::isfinite(b.v[a]) && std::isfinite(b.omega[a]);
+    for (int i = 0; i < 4; i++) fin = fin && std::isfinite(b.q[i]);
+    if (!fin) return fail(TLMPM_E_INVALID, "rigid step not finite");
+    *body = b;
+    return TLMPM_OK;
+}
+
+extern "C" tlmpm_status tlmpm_rigid_tool(const tlmpm_rigid_body* body, const tlmpm_blade* bb, uint32_t flags,
+                                         tlmpm_tool* out)
+{
+    if (!bb || !out) return fail(TLMPM_E_INVALID, "null pointer");
+    if (!body_ok(body)) return fail(TLMPM_E_INVALID, "body needs mass > 0, moments > 0 and a nonzero quaternion");
+    double q[4], nq = 0.0;
+    for (int i = 0; i < 4; i++) nq += body->q[i] * body->q[i];
+    nq = std::sqrt(nq);
+    for (int i = 0; i < 4; i++) q[i] = body->q[i] / nq;
+    double R[9];
+    quat_rot(q, R);
+    tlmpm_tool t;
+    memset(&t, 0, sizeof(t));
+    t.blade = *bb;
+    double r[3];
+    mat_vec(R, bb->x_e, r);
+    mat_vec(R, bb->n, t.blade.n);
+    mat_vec(R, bb->e, t.blade.e);
+    mat_vec(R, bb->d, t.blade.d);
+    double wr[3];
+    cross(body->omega, r, wr);
+    for (int a = 0; a < 3; a++) {
+        t.blade.x_e[a] = body->x[a] + r[a];
+        t.blade.v_e[a] = body->v[a] + wr[a];
+        t.x_B[a] = body->x[a];
+        t.v_B[a] = body->v[a];
+        t.omega_B[a] = body->omega[a];
+    }
+    t.w_B = 0.0;
+    t.flags = flags;
+    t.inv_mass = 1.0 / body->mass;
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            double s = 0.0;
+            for (int k = 0; k < 3; k++) s += R[3 * i + k] * R[3 * j + k] / body->inertia[k];
+            t.inv_inertia[3 * i + j] = s;
+        }
+    *out = t;
     return TLMPM_OK;
 }
 

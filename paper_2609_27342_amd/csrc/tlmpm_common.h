@@ -64,7 +64,9 @@ struct DevTool {
     DevBlade b;
     double xB[3], vB[3];
     float wB[3];
-    float invm;
+    float invm;    // constant part of the inverse effective mass
+    float imass;   // 1/M of a free tool
+    float iinv[9]; // world-frame inverse inertia about xB
     unsigned flags;
     int slot; // rigid-history slot 1..TL_MAX_TOOLS (0 is the floor)
 };

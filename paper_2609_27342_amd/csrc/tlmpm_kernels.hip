@@ -520,7 +520,13 @@ DEV void rigid_one(const SceneK& S, const SceneD& D, const DevTool* T, int slot,
         float wxr[3] = {T->wB[1] * arm[2] - T->wB[2] * arm[1], T->wB[2] * arm[0] - T->wB[0] * arm[2],
                         T->wB[0] * arm[1] - T->wB[1] * arm[0]};
         for (int a = 0; a < 3; a++) vB[a] = (float)T->vB[a] + wxr[a];
-        invm = T->invm;
+        // inverse effective mass of the tool at xc along nB: w_B + 1/M + (r x n) . I^-1 (r x n)
+        const float cr[3] = {arm[1] * nB[2] - arm[2] * nB[1], arm[2] * nB[0] - arm[0] * nB[2],
+                             arm[0] * nB[1] - arm[1] * nB[0]};
+        float ang = 0.0f;
+        for (int a = 0; a < 3; a++)
+            ang += cr[a] * (T->iinv[3 * a] * cr[0] + T->iinv[3 * a + 1] * cr[1] + T->iinv[3 * a + 2] * cr[2]);
+        invm = T->invm + T->imass + ang;
     }
     float vrel[3] = {v[0] - vB[0], v[1] - vB[1], v[2] - vB[2]};
     float vrn = vrel[0] * nB[0] + vrel[1] * nB[1] + vrel[2] * nB[2];

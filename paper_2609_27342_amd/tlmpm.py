@@ -47,10 +47,18 @@ class Tool(C.Structure):
     _fields_ = [
         ("blade", Blade), ("x_B", C.c_double * 3), ("v_B", C.c_double * 3), ("omega_B", C.c_double * 3),
         ("w_B", C.c_double), ("flags", C.c_uint32), ("reserved", C.c_int32),
+        ("inv_mass", C.c_double), ("inv_inertia", C.c_double * 9),
     ]
 
 
 _lib = None
+
+
+class RigidBodyC(C.Structure):
+    _fields_ = [
+        ("x", C.c_double * 3), ("q", C.c_double * 4), ("v", C.c_double * 3), ("omega", C.c_double * 3),
+        ("mass", C.c_double), ("inertia", C.c_double * 3),
+    ]
 
 
 def lib():
@@ -71,6 +79,9 @@ def lib():
         L.tlmpm_get_status.argtypes = [vp, C.POINTER(C.c_int32)]
         L.tlmpm_slot_stats.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
         L.tlmpm_contact_stats.argtypes = [vp, C.POINTER(C.c_double)]
+        dp = C.POINTER(C.c_double)
+        L.tlmpm_rigid_step.argtypes = [C.POINTER(RigidBodyC), dp, dp, C.c_double]
+        L.tlmpm_rigid_tool.argtypes = [C.POINTER(RigidBodyC), C.POINTER(Blade), C.c_uint32, C.POINTER(Tool)]
         L.tlmpm_profile_enable.argtypes = [vp, C.c_int32]
         L.tlmpm_profile_read.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.tlmpm_batch_footprint.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(C.c_size_t)]
@@ -84,7 +95,7 @@ def lib():
         L.tlmpm_batch_profile_read.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.tlmpm_last_error.restype = C.c_char_p
         for f in ("tlmpm_scene_footprint", "tlmpm_create_scene", "tlmpm_destroy_scene", "tlmpm_assign_labels",
-                  "tlmpm_step", "tlmpm_read_state", "tlmpm_write_state", "tlmpm_get_status", "tlmpm_slot_stats", "tlmpm_contact_stats",
+                  "tlmpm_step", "tlmpm_read_state", "tlmpm_write_state", "tlmpm_get_status", "tlmpm_slot_stats", "tlmpm_contact_stats", "tlmpm_rigid_step", "tlmpm_rigid_tool",
                   "tlmpm_profile_enable", "tlmpm_profile_read", "tlmpm_batch_footprint", "tlmpm_batch_create",
                   "tlmpm_batch_destroy", "tlmpm_batch_step", "tlmpm_batch_sync", "tlmpm_batch_profile_enable",
                   "tlmpm_batch_profile_read", "tlmpm_set_graphs", "tlmpm_batch_set_graphs"):
@@ -127,6 +138,10 @@ def make_tool(t):
     for k in ("x_B", "v_B", "omega_B"):
         _vec(getattr(T, k), t.get(k, (0.0, 0.0, 0.0)))
     T.w_B = float(t.get("w_B", 0.0))
+    T.inv_mass = float(t.get("inv_mass", 0.0))
+    ii = np.asarray(t.get("inv_inertia", np.zeros(9)), dtype=np.float64).reshape(9)
+    for i in range(9):
+        T.inv_inertia[i] = float(ii[i])
     fl = 0
     if t.get("labels"):
         fl |= TOOL_LABELS
@@ -138,6 +153,53 @@ def make_tool(t):
         fl |= TOOL_ADVANCE
     T.flags = fl
     return T
+
+
+def tool_dict(T):
+    """Tool dict (the form Scene.step and Batch.step take) of a Tool structure."""
+    b = T.blade
+    blade = dict(cut_index=b.cut_index, new_cut=b.new_cut, half_len=b.half_len, half_width=b.half_width,
+                 b_back=b.b_back, b_lead=b.b_lead)
+    for k in ("x_e", "n", "e", "d", "v_e"):
+        blade[k] = np.array(getattr(b, k)[:], dtype=np.float64)
+    return dict(blade=blade, x_B=np.array(T.x_B[:]), v_B=np.array(T.v_B[:]), omega_B=np.array(T.omega_B[:]),
+                w_B=T.w_B, inv_mass=T.inv_mass, inv_inertia=np.array(T.inv_inertia[:]),
+                labels=bool(T.flags & TOOL_LABELS), contact=bool(T.flags & TOOL_CONTACT),
+                cutting=bool(T.flags & TOOL_CUTTING), advance=bool(T.flags & TOOL_ADVANCE))
+
+
+class RigidBody:
+    """A free rigid tool body (tlmpm_rigid_body): x (centre of mass), q (w, x, y, z),
+    v, omega (world), mass, principal inertia (body axes)."""
+
+    def __init__(self, x, q, v, omega, mass, inertia):
+        self.c = RigidBodyC()
+        _vec(self.c.x, x)
+        for i in range(4):
+            self.c.q[i] = float(q[i])
+        _vec(self.c.v, v)
+        _vec(self.c.omega, omega)
+        self.c.mass = float(mass)
+        _vec(self.c.inertia, inertia)
+
+    def step(self, wrench, gravity, h):
+        """tlmpm_rigid_step: advance by h under wrench (force, torque) and gravity."""
+        w = (C.c_double * 6)(*[float(a) for a in np.asarray(wrench, np.float64).reshape(6)])
+        g = (C.c_double * 3)(*[float(a) for a in np.asarray(gravity, np.float64).reshape(3)])
+        _check(lib().tlmpm_rigid_step(C.byref(self.c), w, g, float(h)))
+
+    def tool(self, blade_body, labels=True, contact=True, cutting=True):
+        """tlmpm_rigid_tool: the tool dict of a blade fixed to the body (blade_body in
+        body axes relative to the centre of mass)."""
+        B = make_blade(dict(blade_body, v_e=(0.0, 0.0, 0.0)))
+        fl = (TOOL_LABELS if labels else 0) | (TOOL_CONTACT if contact else 0) | (TOOL_CUTTING if cutting else 0)
+        T = Tool()
+        _check(lib().tlmpm_rigid_tool(C.byref(self.c), C.byref(B), fl, C.byref(T)))
+        return tool_dict(T)
+
+    def state(self):
+        return dict(x=np.array(self.c.x[:]), q=np.array(self.c.q[:]), v=np.array(self.c.v[:]),
+                    omega=np.array(self.c.omega[:]))
 
 
 def make_desc(scene, keep):

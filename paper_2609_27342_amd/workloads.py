@@ -430,5 +430,45 @@ def segments(scene, j0, j1):
         j = k
 
 
+def knife_blade_body(half_len, height, dx=0.002, new_cut=True):
+    """Blade of a knife plate in the plate's body frame (centre of mass at the
+    origin): edge along x at the bottom (z = -height / 2), front direction -z, plane
+    normal +y; band half width 6 dx, rear extent the plate height, lead dx."""
+    return blade(0, (0.0, 0.0, -0.5 * height), (0, 1, 0), (0, 0, -1), (0, 0, 0), half_len, 6 * dx, height, dx,
+                 new_cut=new_cut)
+
+
+def knife(dx=0.002, block=(0.08, 0.04, 0.04), seed=9, dt=1e-4, interval=10, steps=2000, tilt_deg=25.0,
+          drop=0.001, v_drop=0.3, mass=0.1, plate=(0.1, 0.03, 0.001)):
+    """Two-way coupled cutting (the paper's gravity-driven knife): a soft block
+    (E = 6 kPa, nu = 0.4, rho = 1100 kg/m^3, dx = 2 mm, 8 ppc: 102,400 particles for
+    the default 8 x 4 x 4 cm) on the floor, material contact on; a free 0.1 kg knife,
+    a plate of `plate` (length along the edge, height, thickness), tilted by
+    tilt_deg about its plane normal, its lowest edge point `drop` above the block and
+    moving down at v_drop, then moved by gravity and the material's reaction only.
+    The knife is updated every `interval` substeps from the interval-averaged wrench
+    (tlmpm_rigid_step); its tool record (tlmpm_rigid_tool) is held over the interval."""
+    rng = np.random.default_rng(seed)
+    hi = tuple(float(b) for b in block)
+    origin, cells = _grid((0, 0, 0), hi, dx, pad=1)
+
+    def inside(P):
+        return np.all((P >= 0.0) & (P <= np.asarray(hi)), axis=1)
+
+    X = jittered_lattice((0, 0, 0), hi, dx, origin, inside, rng)
+    params = base_params(dx, origin, cells, dt, 0.4, material_contact=1)
+    L, H, T = (float(a) for a in plate)
+    th = math.radians(tilt_deg)
+    # rotation about +y by th maps the +x end of the edge downwards
+    q = [math.cos(th / 2), 0.0, math.sin(th / 2), 0.0]
+    low = 0.5 * L * math.sin(th) + 0.5 * H * math.cos(th)  # centre of mass above the lowest edge point
+    x = [0.5 * hi[0], 0.5 * hi[1], hi[2] + drop + low]
+    inertia = [mass * (H * H + T * T) / 12.0, mass * (L * L + H * H) / 12.0, mass * (L * L + T * T) / 12.0]
+    body = dict(x=x, q=q, v=[0.0, 0.0, -float(v_drop)], omega=[0.0, 0.0, 0.0], mass=float(mass), inertia=inertia)
+    sc = _finish("knife", params, X, 1100.0, 6.0e3, rng, steps, None)
+    sc["knife"] = dict(body=body, blade=knife_blade_body(0.5 * L, H, dx), interval=int(interval))
+    return sc
+
+
 CONFIGS = {"small": small, "small-deep": lambda **k: small(deep=True, **k), "medium": medium,
            "large": large}
