@@ -75,6 +75,12 @@ typedef struct {
     int32_t single_field;      /* 1: ignore codes (one logical grid), a negative control */
     int32_t slot_capacity;     /* logical grids per node (compact slots, Sec. III-G), 1..16; 0 = 8.
                                   More distinct codes at a node set TLMPM_E_SLOT_OVERFLOW. */
+    int32_t material;          /* constitutive model (Sec. III-B): 0 compressible Neo-Hookean,
+                                  1 fixed-corotated, P = 2 mu (F - R) + lambda (J - 1) J F^-T */
+    float viscosity;           /* Newtonian viscosity eta >= 0 (Pa s): adds J eta (l + l^T) F^-T,
+                                  l = dF/dt F^-1 from the last deformation-gradient update */
+    float yield_stress;        /* von Mises yield stress (Pa) of the plasticity projection with
+                                  material 1; 0 = elastic */
 } tlmpm_scene_desc;
 
 /* A blade record: the cut frame of Eq. 3 and the band of Eq. 4.  (n, e, d) must be

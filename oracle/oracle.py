@@ -12,7 +12,7 @@ import numpy as np
 from .build import LIB, build
 
 __all__ = ["Params", "Blade", "Tool", "OracleScene", "lib", "shape", "neo_hookean_P",
-           "neo_hookean_psi", "conflict", "encode", "digit", "couple", "label_digit",
+           "neo_hookean_psi", "fcr_P", "fcr_psi", "polar", "visc_P", "conflict", "encode", "digit", "couple", "label_digit",
            "labels_on"]
 
 
@@ -25,7 +25,8 @@ class Params(C.Structure):
         ("gamma_c", C.c_double), ("mu_s", C.c_double), ("mu_d", C.c_double),
         ("material_contact", C.c_int32), ("floor_on", C.c_int32), ("floor_z", C.c_double),
         ("G_c", C.c_double), ("zeta", C.c_double), ("u_min", C.c_double),
-        ("single_field", C.c_int32), ("pad_", C.c_int32),
+        ("single_field", C.c_int32), ("material", C.c_int32),
+        ("viscosity", C.c_double), ("yield_stress", C.c_double),
     ]
 
 
@@ -73,6 +74,14 @@ def lib():
         L.orc_neo_hookean_P.argtypes = [C.c_double, C.c_double, dp, dp]
         L.orc_neo_hookean_psi.restype = C.c_double
         L.orc_neo_hookean_psi.argtypes = [C.c_double, C.c_double, dp]
+        L.orc_fcr_P.restype = C.c_int
+        L.orc_fcr_P.argtypes = [C.c_double, C.c_double, dp, dp]
+        L.orc_fcr_psi.restype = C.c_double
+        L.orc_fcr_psi.argtypes = [C.c_double, C.c_double, dp]
+        L.orc_polar.restype = C.c_int
+        L.orc_polar.argtypes = [dp, dp, dp]
+        L.orc_visc_P.restype = C.c_int
+        L.orc_visc_P.argtypes = [C.c_double, dp, dp, dp]
         L.orc_conflict.restype = C.c_int
         L.orc_conflict.argtypes = [C.c_uint64, C.c_uint64, C.c_int]
         L.orc_encode.restype = C.c_uint64
@@ -157,6 +166,9 @@ def make_params(p):
     P.material_contact = int(p.get("material_contact", 0))
     P.floor_on = int(p.get("floor_on", 0))
     P.single_field = int(p.get("single_field", 0))
+    P.material = int(p.get("material", 0))
+    P.viscosity = float(p.get("viscosity", 0.0))
+    P.yield_stress = float(p.get("yield_stress", 0.0))
     return P
 
 
@@ -280,6 +292,33 @@ def neo_hookean_P(E, nu, F):
 def neo_hookean_psi(E, nu, F):
     F = _f64(F, (9,))
     return lib().orc_neo_hookean_psi(float(E), float(nu), _dp(F))
+
+
+def fcr_P(E, nu, F):
+    F = _f64(F, (9,))
+    P = np.empty(9)
+    lib().orc_fcr_P(float(E), float(nu), _dp(F), _dp(P))
+    return P.reshape(3, 3)
+
+
+def fcr_psi(E, nu, F):
+    F = _f64(F, (9,))
+    return lib().orc_fcr_psi(float(E), float(nu), _dp(F))
+
+
+def polar(F):
+    F = _f64(F, (9,))
+    R, S = np.empty(9), np.empty(9)
+    if lib().orc_polar(_dp(F), _dp(R), _dp(S)):
+        raise ValueError("det F <= 0")
+    return R.reshape(3, 3), S.reshape(3, 3)
+
+
+def visc_P(eta, F, Fdot):
+    F, Fd = _f64(F, (9,)), _f64(Fdot, (9,))
+    P = np.empty(9)
+    lib().orc_visc_P(float(eta), _dp(F), _dp(Fd), _dp(P))
+    return P.reshape(3, 3)
 
 
 def conflict(a, b, K):

@@ -52,7 +52,9 @@ typedef struct {
     /* cutting resistance (Eq. 5) */
     double G_c, zeta, u_min;
     int32_t single_field; /* negative control: every particle scatters to one logical grid */
-    int32_t pad_;
+    int32_t material;     /* 0 Neo-Hookean, 1 fixed-corotated (Sec. III-B) */
+    double viscosity;     /* Newtonian viscosity eta (Pa s), 0 = none */
+    double yield_stress;  /* von Mises yield stress (Pa), 0 = elastic */
 } orc_params;
 
 /* A blade record: the cut frame of Eq. 3 and the band extents of Eq. 4. */
@@ -108,6 +110,7 @@ typedef struct orc_scene {
     long n;
     long nodes[3];
     double *X, *x, *v, *F; /* X,x,v: [n][3]; F: [n][9] row-major */
+    double* Fdot;          /* [n][9] rate of F of the last update (viscosity) */
     double *vol0, *mass, *E;
     uint8_t* dig;          /* [n][max_cuts] ternary digits */
     double* D;             /* cutting progress */
@@ -280,6 +283,152 @@ double orc_neo_hookean_psi(double E, double nu, const double* F)
 }
 
 /* ------------------------------------------------------------------------- */
+/* Fixed-corotated elasticity and Newtonian viscosity (Sec. III-B names them   */
+/* as the paper's material model; reading R31).                                */
+/* ------------------------------------------------------------------------- */
+/* Eigen-decomposition A = Q diag(lam) Q^T of a symmetric 3x3 matrix by cyclic  */
+/* Jacobi rotations (columns of Q are the eigenvectors).                       */
+static void sym_eig3(const double* A_in, double* lam, double* Q)
+{
+    double A[9];
+    memcpy(A, A_in, sizeof(A));
+    for (int i = 0; i < 9; i++) Q[i] = (i % 4 == 0) ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 60; sweep++) {
+        double off = A[1] * A[1] + A[2] * A[2] + A[5] * A[5];
+        double tot = off;
+        for (int i = 0; i < 3; i++) tot += A[4 * i] * A[4 * i];
+        if (off <= 1e-32 * tot || off == 0.0) break;
+        for (int pq = 0; pq < 3; pq++) {
+            int p = pq == 2 ? 1 : 0, q = pq == 0 ? 1 : 2;
+            double apq = A[3 * p + q];
+            if (apq == 0.0) continue;
+            /* rotation angle that zeroes A[p][q] */
+            double theta = (A[3 * q + q] - A[3 * p + p]) / (2.0 * apq);
+            double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+            double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+            /* A <- G^T A G, Q <- Q G with G the rotation in the (p, q) plane */
+            for (int k = 0; k < 3; k++) {
+                double akp = A[3 * k + p], akq = A[3 * k + q];
+                A[3 * k + p] = c * akp - sn * akq;
+                A[3 * k + q] = sn * akp + c * akq;
+            }
+            for (int k = 0; k < 3; k++) {
+                double apk = A[3 * p + k], aqk = A[3 * q + k];
+                A[3 * p + k] = c * apk - sn * aqk;
+                A[3 * q + k] = sn * apk + c * aqk;
+            }
+            for (int k = 0; k < 3; k++) {
+                double qkp = Q[3 * k + p], qkq = Q[3 * k + q];
+                Q[3 * k + p] = c * qkp - sn * qkq;
+                Q[3 * k + q] = sn * qkp + c * qkq;
+            }
+        }
+    }
+    for (int i = 0; i < 3; i++) lam[i] = A[4 * i];
+}
+
+/* Polar decomposition F = R S with S = (F^T F)^{1/2} symmetric positive       */
+/* definite and R = F S^{-1} a rotation (det F > 0).  Returns -1 otherwise.   */
+int orc_polar(const double* F, double* R, double* S)
+{
+    if (!(det3(F) > 0.0)) return -1;
+    double C[9], lam[3], Q[9];
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            double a = 0.0;
+            for (int k = 0; k < 3; k++) a += F[3 * k + i] * F[3 * k + j];
+            C[3 * i + j] = a;
+        }
+    sym_eig3(C, lam, Q);
+    double Si[9];
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            double a = 0.0, b = 0.0;
+            for (int k = 0; k < 3; k++) {
+                a += Q[3 * i + k] * sqrt(lam[k]) * Q[3 * j + k];
+                b += Q[3 * i + k] / sqrt(lam[k]) * Q[3 * j + k];
+            }
+            S[3 * i + j] = a;
+            Si[3 * i + j] = b;
+        }
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            double a = 0.0;
+            for (int k = 0; k < 3; k++) a += F[3 * i + k] * Si[3 * k + j];
+            R[3 * i + j] = a;
+        }
+    return 0;
+}
+
+static void cofactor3(const double* F, double* C)
+{
+    C[0] = F[4] * F[8] - F[5] * F[7];
+    C[1] = F[5] * F[6] - F[3] * F[8];
+    C[2] = F[3] * F[7] - F[4] * F[6];
+    C[3] = F[2] * F[7] - F[1] * F[8];
+    C[4] = F[0] * F[8] - F[2] * F[6];
+    C[5] = F[1] * F[6] - F[0] * F[7];
+    C[6] = F[1] * F[5] - F[2] * F[4];
+    C[7] = F[2] * F[3] - F[0] * F[5];
+    C[8] = F[0] * F[4] - F[1] * F[3];
+}
+
+/* Fixed-corotated first Piola-Kirchhoff stress P = 2 mu (F - R) + lambda (J - 1) */
+/* J F^{-T}, the derivative of psi = mu |F - R|^2 + lambda/2 (J - 1)^2.          */
+int orc_fcr_P(double E, double nu, const double* F, double* P)
+{
+    double mu, lam, R[9], S[9], C[9];
+    lame(E, nu, &mu, &lam);
+    if (orc_polar(F, R, S)) {
+        for (int i = 0; i < 9; i++) P[i] = NAN;
+        return -1;
+    }
+    double J = det3(F);
+    cofactor3(F, C); /* J F^{-T} */
+    for (int i = 0; i < 9; i++) P[i] = 2.0 * mu * (F[i] - R[i]) + lam * (J - 1.0) * C[i];
+    return 0;
+}
+
+double orc_fcr_psi(double E, double nu, const double* F)
+{
+    double mu, lam, R[9], S[9];
+    lame(E, nu, &mu, &lam);
+    if (orc_polar(F, R, S)) return NAN;
+    double a = 0.0;
+    for (int i = 0; i < 9; i++) a += (F[i] - R[i]) * (F[i] - R[i]);
+    double J = det3(F);
+    return mu * a + 0.5 * lam * (J - 1.0) * (J - 1.0);
+}
+
+/* Newtonian viscous first Piola-Kirchhoff stress: Cauchy stress eta (l + l^T)   */
+/* with l = Fdot F^{-1} the spatial velocity gradient, pulled back by J F^{-T}.  */
+int orc_visc_P(double eta, const double* F, const double* Fdot, double* P)
+{
+    double J = det3(F), C[9];
+    if (!(J > 0.0)) {
+        for (int i = 0; i < 9; i++) P[i] = NAN;
+        return -1;
+    }
+    cofactor3(F, C); /* J F^{-T}; F^{-1} = C^T / J */
+    double l[9], sg[9];
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            double a = 0.0;
+            for (int k = 0; k < 3; k++) a += Fdot[3 * i + k] * C[3 * j + k] / J;
+            l[3 * i + j] = a;
+        }
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) sg[3 * i + j] = eta * (l[3 * i + j] + l[3 * j + i]);
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            double a = 0.0;
+            for (int k = 0; k < 3; k++) a += sg[3 * i + k] * C[3 * k + j];
+            P[3 * i + j] = a;
+        }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Compatibility coupling at one node (Eq. 8).                                */
 /* S logical grids with masses m[a], codes[a] and a 3-vector field f[a]; the   */
 /* output is f_bar[a] = f[a] + (1/M) sum_{b != a, compatible} (m_a f_b - m_b f_a)*/
@@ -339,6 +488,7 @@ void orc_destroy(orc_scene* s)
     free(s->x);
     free(s->v);
     free(s->F);
+    free(s->Fdot);
     free(s->vol0);
     free(s->mass);
     free(s->E);
@@ -370,6 +520,7 @@ orc_scene* orc_create(const orc_params* P, long n, const double* X, const double
     s->x = (double*)malloc(sizeof(double) * 3 * (n + 1));
     s->v = (double*)calloc(3 * (n + 1), sizeof(double));
     s->F = (double*)malloc(sizeof(double) * 9 * (n + 1));
+    s->Fdot = (double*)calloc(9 * (n + 1), sizeof(double));
     s->vol0 = (double*)malloc(sizeof(double) * (n + 1));
     s->mass = (double*)malloc(sizeof(double) * (n + 1));
     s->E = (double*)malloc(sizeof(double) * (n + 1));
@@ -967,7 +1118,14 @@ int orc_step(orc_scene* s, const orc_tool* tools, int nt, double* wrench, int br
     double w[8], g[24];
     for (long p = 0; p < n; p++) {
         double Pk[9];
-        if (orc_neo_hookean_P(s->E[p], P->nu, &s->F[9 * p], Pk)) s->status = ORC_E_NONFINITE;
+        const int bad = P->material == 1 ? orc_fcr_P(s->E[p], P->nu, &s->F[9 * p], Pk)
+                                         : orc_neo_hookean_P(s->E[p], P->nu, &s->F[9 * p], Pk);
+        if (bad) s->status = ORC_E_NONFINITE;
+        if (P->viscosity > 0.0) {
+            double Pv[9];
+            if (orc_visc_P(P->viscosity, &s->F[9 * p], &s->Fdot[9 * p], Pv)) s->status = ORC_E_NONFINITE;
+            for (int i = 0; i < 9; i++) Pk[i] += Pv[i];
+        }
         orc_shape(P, &s->X[3 * p], node, w, g);
         uint64_t c = code_of(s, p);
         double mp = s->mass[p], V0 = s->vol0[p];
@@ -1042,6 +1200,7 @@ int orc_step(orc_scene* s, const orc_tool* tools, int nt, double* wrench, int br
         }
         double* F = &s->F[9 * p];
         for (int i = 0; i < 9; i++) F[i] += dt * L[i];
+        memcpy(&s->Fdot[9 * p], L, sizeof(L));
         double J = det3(F);
         int finite = 1;
         for (int i = 0; i < 9; i++) finite &= isfinite(F[i]);

@@ -141,6 +141,9 @@ struct ProfScope {
 
 static tlmpm_status timing_read(Timing& tm, int n_classes, double* ms, int64_t* launches);
 
+// the scene needs the general constitutive path of P2G
+static int general_path(const SceneK& K) { return K.material == 1 || K.visc > 0.0f || K.ystress > 0.0f; }
+
 static TlLaunch single_launch(const tlmpm_scene* sc)
 {
     TlLaunch L;
@@ -148,6 +151,7 @@ static TlLaunch single_launch(const tlmpm_scene* sc)
     L.S = &sc->K;
     L.D = &sc->D;
     L.any_material = sc->K.material_contact;
+    L.general = general_path(sc->K);
     L.st = sc->st;
     return L;
 }
@@ -191,7 +195,7 @@ Dims dims_of(const tlmpm_scene_desc* d)
 
 struct Offsets {
     size_t X, u, v, H, code, code_prev, D, perm, E, m, V0, cell_start, active, cnt0, cnt1, sc0, sc1, p2g, rs, hist,
-        aabb, wpart, wacc, Jmat, Jrig, brig, bmixed, ccode, ckeys, gmeta, gperm, bround, tools, tinfo, ctr, bact, status, dirty, bdirty, pcell, cand_idx, coff, cmask, cstatic, bcand, hbin, hmax, bcount, bids, crec, htab, hnext, ph_n, ph_q, ph_u,
+        aabb, wpart, Fdot, wacc, Jmat, Jrig, brig, bmixed, ccode, ckeys, gmeta, gperm, bround, tools, tinfo, ctr, bact, status, dirty, bdirty, pcell, cand_idx, coff, cmask, cstatic, bcand, hbin, hmax, bcount, bids, crec, htab, hnext, ph_n, ph_q, ph_u,
         total;
     uint32_t hmask;
 };
@@ -259,6 +263,7 @@ Offsets plan(const tlmpm_scene_desc* d, long long n_active)
     o.hist = L.take((size_t)(TL_MAX_TOOLS + 1) * 4 * N * f);
     o.aabb = L.take((size_t)g.n_bricks * 8 * f);
     o.wpart = L.take((size_t)g.n_bricks * TL_MAX_TOOLS * 6 * sizeof(double));
+    o.Fdot = d->viscosity > 0.0f ? L.take(9 * N * f) : 0;
     o.wacc = L.take(TL_MAX_TOOLS * 6 * sizeof(double));
     o.Jmat = d->material_contact ? L.take(3 * N * f) : 0;
     o.Jrig = L.take(3 * N * f);
@@ -313,6 +318,11 @@ tlmpm_status validate(const tlmpm_scene_desc* d)
     if (d->max_cuts < 1 || d->max_cuts > 15) return fail(TLMPM_E_INVALID, "max_cuts must be in 1..15");
     if (d->slot_capacity < 0 || d->slot_capacity > TL_SCAP_MAX)
         return fail(TLMPM_E_INVALID, "slot_capacity must be in 0..16 (0: 8)");
+    if (d->material != 0 && d->material != 1) return fail(TLMPM_E_INVALID, "material must be 0 or 1");
+    if (!(d->viscosity >= 0.0f) || !(d->yield_stress >= 0.0f))
+        return fail(TLMPM_E_INVALID, "viscosity and yield_stress must be >= 0");
+    if (d->yield_stress > 0.0f && d->material != 1)
+        return fail(TLMPM_E_INVALID, "the plasticity projection needs material 1 (fixed-corotated)");
     if (!(d->nu > -1.0f && d->nu < 0.5f)) return fail(TLMPM_E_INVALID, "nu must be in (-1, 0.5)");
     if (!d->vol0 && !(d->vol0_uniform > 0.0f)) return fail(TLMPM_E_INVALID, "vol0_uniform must be positive");
     if (!d->mass && !(d->mass_uniform > 0.0f)) return fail(TLMPM_E_INVALID, "mass_uniform must be positive");
@@ -462,6 +472,9 @@ extern "C" tlmpm_status tlmpm_create_scene(const tlmpm_scene_desc* d, void* ws, 
     K.single_field = d->single_field;
     K.material_contact = d->material_contact;
     K.scap = slot_cap(d);
+    K.material = d->material;
+    K.visc = d->viscosity;
+    K.ystress = d->yield_stress;
     K.pair_blocks = (int)std::min<long long>(4096, std::max<long long>(1, N / 128));
     float vmax0 = d->vol0_uniform;
     if (d->vol0)
@@ -494,6 +507,7 @@ extern "C" tlmpm_status tlmpm_create_scene(const tlmpm_scene_desc* d, void* ws, 
     D.hist = (float*)(base + o.hist);
     D.aabb = (float*)(base + o.aabb);
     D.wpart = (double*)(base + o.wpart);
+    D.Fdot = o.Fdot ? (float*)(base + o.Fdot) : nullptr;
     D.wacc = (double*)(base + o.wacc);
     D.Jmat = d->material_contact ? (float*)(base + o.Jmat) : nullptr;
     D.Jrig = (float*)(base + o.Jrig);
@@ -1460,6 +1474,7 @@ extern "C" tlmpm_status tlmpm_batch_create(tlmpm_scene* const* scenes, int32_t n
         hd[s].tinfo = b->d_tools[s].tinfo;
         hd[s].wacc = b->d_wacc + (size_t)s * TL_MAX_TOOLS * 6;
         L.any_material |= sc->K.material_contact;
+        L.general |= general_path(sc->K);
         int c[TL_ITEM_KINDS];
         scene_items(sc, c);
         for (int k = 0; k < TL_ITEM_KINDS; k++)

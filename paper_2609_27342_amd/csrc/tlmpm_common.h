@@ -92,6 +92,9 @@ struct SceneK {
     int single_field;
     int material_contact;
     int scap;         // slot capacity per node (<= TL_SCAP_MAX)
+    int material;     // 0 Neo-Hookean, 1 fixed-corotated
+    float visc;       // Newtonian viscosity
+    float ystress;    // von Mises yield stress (0: elastic)
     int pair_blocks;  // blocks of the pair search (grid-stride over the candidates)
     double dt_d;
 };
@@ -120,6 +123,7 @@ struct SceneD {
     float* hist;   // rigid contact history [TL_MAX_TOOLS+1][4][N]: u_t xyz, stamp
     float* aabb;   // [n_bricks][8]: min xyz, max xyz, max |v|, 0
     double* wpart; // [TL_MAX_TOOLS * 6][n_active] per-brick wrench sums of the call so far
+    float* Fdot;   // [9][N] rate of F of its last update (viscous scenes), else null
     double* wacc;  // [TL_MAX_TOOLS][6]
     float* Jmat;   // [3][N] material contact impulse (candidates only)
     float* Jrig;   // [3][N] floor and tool impulse (bricks with brig set)
@@ -201,5 +205,7 @@ struct TlLaunch {
     const int2* items[TL_ITEM_KINDS];
     int n_items[TL_ITEM_KINDS];
     int any_material;  // some scene has material contact
+    int general;       // some scene needs the general constitutive path (fixed-corotated,
+                       // viscosity or plasticity)
     hipStream_t st;
 };

@@ -443,6 +443,155 @@ DEV bool neo_hookean(float E, float nu, const float* H, float* P)
     return true;
 }
 
+// Fixed-corotated first Piola-Kirchhoff stress P = 2 mu (F - R) + lambda (J - 1)
+// J F^{-T} (Sec. III-B), F = R S the polar decomposition, in terms of H = F - I so
+// that small strains keep their precision in FP32: with E = F^T F - I = H + H^T +
+// H^T H = Q diag(e) Q^T (Jacobi rotations), S - I = Q diag(e / (sqrt(1 + e) + 1)) Q^T,
+// S^{-1} = Q diag(1 / sqrt(1 + e)) Q^T, R = F S^{-1} and F - R = R (S - I).
+// Returns false when J <= 0 or the state is not finite.
+DEV bool fixed_corotated(float E, float nu, const float* H, float* P)
+{
+    const float mu = E / (2.0f * (1.0f + nu));
+    const float lam = E * nu / ((1.0f + nu) * (1.0f - 2.0f * nu));
+    float A[9];
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            float a = H[3 * i + j] + H[3 * j + i];
+#pragma unroll
+            for (int k = 0; k < 3; k++) a += H[3 * k + i] * H[3 * k + j];
+            A[3 * i + j] = a;
+        }
+    float Q[9] = {1.0f, 0.0f, 0.0f, 0.0f, 1.0f, 0.0f, 0.0f, 0.0f, 1.0f};
+    // cyclic Jacobi sweeps (a fixed count: FP32 converges within four)
+#pragma unroll 1
+    for (int sweep = 0; sweep < 4; sweep++) {
+#pragma unroll
+        for (int pq = 0; pq < 3; pq++) {
+            const int p = pq == 2 ? 1 : 0, q = pq == 0 ? 1 : 2;
+            const float apq = A[3 * p + q];
+            if (apq == 0.0f) continue;
+            const float th = (A[3 * q + q] - A[3 * p + p]) / (2.0f * apq);
+            const float t = copysignf(1.0f, th) / (fabsf(th) + sqrtf(th * th + 1.0f));
+            const float c = 1.0f / sqrtf(t * t + 1.0f), sn = t * c;
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                const float akp = A[3 * k + p], akq = A[3 * k + q];
+                A[3 * k + p] = c * akp - sn * akq;
+                A[3 * k + q] = sn * akp + c * akq;
+            }
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                const float apk = A[3 * p + k], aqk = A[3 * q + k];
+                A[3 * p + k] = c * apk - sn * aqk;
+                A[3 * q + k] = sn * apk + c * aqk;
+            }
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                const float qkp = Q[3 * k + p], qkq = Q[3 * k + q];
+                Q[3 * k + p] = c * qkp - sn * qkq;
+                Q[3 * k + q] = sn * qkp + c * qkq;
+            }
+        }
+    }
+    float sm1[3], sinv[3];
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        const float e = A[4 * k], r = sqrtf(1.0f + e);
+        if (!(1.0f + e > 0.0f)) return false;
+        sm1[k] = e / (r + 1.0f);
+        sinv[k] = 1.0f / r;
+    }
+    float SmI[9], Si[9];
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            float a = 0.0f, b = 0.0f;
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                a += Q[3 * i + k] * sm1[k] * Q[3 * j + k];
+                b += Q[3 * i + k] * sinv[k] * Q[3 * j + k];
+            }
+            SmI[3 * i + j] = a;
+            Si[3 * i + j] = b;
+        }
+    float Rm[9];
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            float a = Si[3 * i + j];
+#pragma unroll
+            for (int k = 0; k < 3; k++) a += H[3 * i + k] * Si[3 * k + j];
+            Rm[3 * i + j] = a;
+        }
+    float cH[9];
+    cH[0] = H[4] * H[8] - H[5] * H[7];
+    cH[1] = H[5] * H[6] - H[3] * H[8];
+    cH[2] = H[3] * H[7] - H[4] * H[6];
+    cH[3] = H[2] * H[7] - H[1] * H[8];
+    cH[4] = H[0] * H[8] - H[2] * H[6];
+    cH[5] = H[1] * H[6] - H[0] * H[7];
+    cH[6] = H[1] * H[5] - H[2] * H[4];
+    cH[7] = H[2] * H[3] - H[0] * H[5];
+    cH[8] = H[0] * H[4] - H[1] * H[3];
+    const float trH = H[0] + H[4] + H[8];
+    const float I2 = cH[0] + cH[4] + cH[8];
+    const float I3 = H[0] * cH[0] + H[1] * cH[1] + H[2] * cH[2];
+    const float Jm1 = trH + (I2 + I3);
+    if (!(1.0f + Jm1 > 0.0f) || !isfinite(Jm1)) return false;
+#pragma unroll
+    for (int r = 0; r < 3; r++)
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            float fr = 0.0f; // (F - R)_rc = (R (S - I))_rc
+#pragma unroll
+            for (int k = 0; k < 3; k++) fr += Rm[3 * r + k] * SmI[3 * k + c];
+            const float cof = (r == c ? 1.0f + trH : 0.0f) - H[3 * c + r] + cH[3 * r + c]; // J F^{-T}
+            P[3 * r + c] = 2.0f * mu * fr + lam * Jm1 * cof;
+        }
+    return true;
+}
+
+// Adds the Newtonian viscous first Piola-Kirchhoff stress J eta (l + l^T) F^{-T},
+// l = Fdot F^{-1} (Sec. III-B), to P.  F = I + H with J > 0.
+DEV void add_viscous(float eta, const float* H, const float* Fdot, float* P)
+{
+    float C[9]; // J F^{-T}
+    C[0] = (1.0f + H[4]) * (1.0f + H[8]) - H[5] * H[7];
+    C[1] = H[5] * H[6] - H[3] * (1.0f + H[8]);
+    C[2] = H[3] * H[7] - (1.0f + H[4]) * H[6];
+    C[3] = H[2] * H[7] - H[1] * (1.0f + H[8]);
+    C[4] = (1.0f + H[0]) * (1.0f + H[8]) - H[2] * H[6];
+    C[5] = H[1] * H[6] - (1.0f + H[0]) * H[7];
+    C[6] = H[1] * H[5] - H[2] * (1.0f + H[4]);
+    C[7] = H[2] * H[3] - (1.0f + H[0]) * H[5];
+    C[8] = (1.0f + H[0]) * (1.0f + H[4]) - H[1] * H[3];
+    const float J = (1.0f + H[0]) * C[0] + H[1] * C[1] + H[2] * C[2];
+    const float iJ = 1.0f / J;
+    float l[9]; // Fdot F^{-1}, F^{-1} = C^T / J
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            float a = 0.0f;
+#pragma unroll
+            for (int k = 0; k < 3; k++) a += Fdot[3 * i + k] * C[3 * j + k];
+            l[3 * i + j] = a * iJ;
+        }
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            float a = 0.0f;
+#pragma unroll
+            for (int k = 0; k < 3; k++) a += eta * (l[3 * i + k] + l[3 * k + i]) * C[3 * k + j];
+            P[3 * i + j] += a;
+        }
+}
+
 // ------------------------------------------------------- history-based friction
 // Tangential spring transported to the current tangent plane (length kept), trial
 // force -k_t u - c_t v_t, stick below mu_s f_n, else slip at mu_d f_n with the
@@ -706,6 +855,9 @@ DEV void rigid_body(const SceneK& S, const SceneD& D, int bi)
     }
 }
 
+// MAT 0: Neo-Hookean only; MAT 1: the scene's material (Neo-Hookean or
+// fixed-corotated) with Newtonian viscosity.
+template <int MAT>
 DEV void p2g_body(const SceneK& S, const SceneD& D, int bi, KA_Args A)
 {
     __shared__ BoxTab Tc;
@@ -804,9 +956,9 @@ DEV void p2g_body(const SceneK& S, const SceneD& D, int bi, KA_Args A)
             key = slot_key(S, code);
         }
         // ---- deformation-gradient update from the remapped velocities (MUSL)
+        float Lg[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}; // dF/dt of the update
         if (use_r && valid) {
             uint32_t kprev = (code & TL_PREV_BIT) ? slot_key(S, D.code_prev[p]) : key;
-            float Lg[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
             for (int k = 0; k < 8; k++) {
                 float wx, wy, wz;
                 corner_weights(t, k, wx, wy, wz);
@@ -839,6 +991,19 @@ DEV void p2g_body(const SceneK& S, const SceneD& D, int bi, KA_Args A)
                 D.code[p] = code;
             }
         }
+        if constexpr (MAT == 1) {
+            // viscosity uses the rate of the last F update: kept for the substeps
+            // whose P2G has no pending update (the first, or after a state read)
+            if (S.visc > 0.0f && valid) {
+                if (use_r) {
+#pragma unroll
+                    for (int a = 0; a < 9; a++) D.Fdot[a * N + p] = Lg[a];
+                } else {
+#pragma unroll
+                    for (int a = 0; a < 9; a++) Lg[a] = D.Fdot[a * N + p];
+                }
+            }
+        }
         if (!A.do_p2g) continue;
         // ---- stress and external/contact impulses
         float m = 0.0f, V0 = 0.0f, E = 0.0f;
@@ -848,7 +1013,13 @@ DEV void p2g_body(const SceneK& S, const SceneD& D, int bi, KA_Args A)
             m = S.m_uniform ? S.m0 : D.m[p];
             V0 = S.v_uniform ? S.V0 : D.V0[p];
             E = S.e_uniform ? S.E0 : D.E[p];
-            if (!neo_hookean(E, S.nu, H, Pk)) {
+            bool ok;
+            if constexpr (MAT == 1)
+                ok = S.material == 1 ? fixed_corotated(E, S.nu, H, Pk) : neo_hookean(E, S.nu, H, Pk);
+            else
+                ok = neo_hookean(E, S.nu, H, Pk);
+            if (ok && MAT == 1 && S.visc > 0.0f) add_viscous(S.visc, H, Lg, Pk);
+            if (!ok) {
                 atomicOr(D.status, TL_ST_NONFINITE);
                 for (int a = 0; a < 9; a++) Pk[a] = 0.0f;
             }
@@ -1504,15 +1675,21 @@ TL_WRAP(resetD, 256, , )
 TL_WRAP(call_start, 64, , )
 
 // at most 80 VGPRs: three 512-thread workgroups per CU
-__global__ __launch_bounds__(TL_WG) __attribute__((amdgpu_waves_per_eu(6))) void k_p2g(SceneK S, SceneD D, KA_Args A)
+// Neo-Hookean: at most 80 VGPRs (three workgroups per CU); the general path (polar
+// decomposition) at most 128 (two)
+template <int MAT>
+__global__ __launch_bounds__(TL_WG) __attribute__((amdgpu_waves_per_eu(MAT == 0 ? 6 : 4))) void k_p2g(SceneK S,
+                                                                                                     SceneD D,
+                                                                                                     KA_Args A)
 {
-    p2g_body(S, D, blockIdx.x, A);
+    p2g_body<MAT>(S, D, blockIdx.x, A);
 }
-__global__ __launch_bounds__(TL_WG) __attribute__((amdgpu_waves_per_eu(6))) void k_p2g_b(
+template <int MAT>
+__global__ __launch_bounds__(TL_WG) __attribute__((amdgpu_waves_per_eu(MAT == 0 ? 6 : 4))) void k_p2g_b(
     const SceneK* __restrict__ Ks, const SceneD* __restrict__ Ds, const int2* __restrict__ it, KA_Args A)
 {
     const int2 t = it[xcd_order(blockIdx.x, gridDim.x)];
-    p2g_body(Ks[t.x], Ds[t.x], t.y, A);
+    p2g_body<MAT>(Ks[t.x], Ds[t.x], t.y, A);
 }
 __global__ __launch_bounds__(TL_WG) void k_g2p(SceneK S, SceneD D, int cur)
 {
@@ -1561,7 +1738,8 @@ hipError_t tl_launch_p2g(const TlLaunch* L, int do_p2g, int tabs_differ, int cur
     A.tabs_differ = tabs_differ;
     A.cur = cur;
     A.rsb = rsb;
-    return tl_run(*L, IT_BRICK, plain_bricks(*L), TL_WG, k_p2g, k_p2g_b, A);
+    if (L->general) return tl_run(*L, IT_BRICK, plain_bricks(*L), TL_WG, k_p2g<1>, k_p2g_b<1>, A);
+    return tl_run(*L, IT_BRICK, plain_bricks(*L), TL_WG, k_p2g<0>, k_p2g_b<0>, A);
 }
 
 hipError_t tl_launch_g2p(const TlLaunch* L, int cur)

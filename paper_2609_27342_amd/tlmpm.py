@@ -31,6 +31,7 @@ class SceneDesc(C.Structure):
         ("material_contact", C.c_int32), ("floor_on", C.c_int32), ("floor_z", C.c_float),
         ("G_c", C.c_float), ("zeta", C.c_float), ("u_min", C.c_float),
         ("max_cuts", C.c_int32), ("single_field", C.c_int32), ("slot_capacity", C.c_int32),
+        ("material", C.c_int32), ("viscosity", C.c_float), ("yield_stress", C.c_float),
     ]
 
 
@@ -239,6 +240,9 @@ def make_desc(scene, keep):
     d.max_cuts = int(p.get("max_cuts", 4))
     d.single_field = int(p.get("single_field", 0))
     d.slot_capacity = int(p.get("slot_capacity", 0))
+    d.material = int(p.get("material", 0))
+    d.viscosity = float(p.get("viscosity", 0.0))
+    d.yield_stress = float(p.get("yield_stress", 0.0))
     return d
 
 
