@@ -12,7 +12,7 @@ import numpy as np
 from .build import LIB, build
 
 __all__ = ["Params", "Blade", "Tool", "OracleScene", "lib", "shape", "neo_hookean_P",
-           "neo_hookean_psi", "fcr_P", "fcr_psi", "polar", "visc_P", "conflict", "encode", "digit", "couple", "label_digit",
+           "neo_hookean_psi", "fcr_P", "fcr_psi", "polar", "visc_P", "vm_project", "conflict", "encode", "digit", "couple", "label_digit",
            "labels_on"]
 
 
@@ -80,6 +80,8 @@ def lib():
         L.orc_fcr_psi.argtypes = [C.c_double, C.c_double, dp]
         L.orc_polar.restype = C.c_int
         L.orc_polar.argtypes = [dp, dp, dp]
+        L.orc_vm_project.restype = C.c_int
+        L.orc_vm_project.argtypes = [C.c_double, C.c_double, C.c_double, dp, dp]
         L.orc_visc_P.restype = C.c_int
         L.orc_visc_P.argtypes = [C.c_double, dp, dp, dp]
         L.orc_conflict.restype = C.c_int
@@ -312,6 +314,16 @@ def polar(F):
     if lib().orc_polar(_dp(F), _dp(R), _dp(S)):
         raise ValueError("det F <= 0")
     return R.reshape(3, 3), S.reshape(3, 3)
+
+
+def vm_project(E, nu, sigma_y, Fe):
+    """(projected F_e, yielded) of the von Mises projection."""
+    Fe = _f64(Fe, (9,))
+    out = np.empty(9)
+    r = lib().orc_vm_project(float(E), float(nu), float(sigma_y), _dp(Fe), _dp(out))
+    if r < 0:
+        raise ValueError("det F_e <= 0")
+    return out.reshape(3, 3), bool(r)
 
 
 def visc_P(eta, F, Fdot):

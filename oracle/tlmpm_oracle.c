@@ -111,6 +111,7 @@ typedef struct orc_scene {
     long nodes[3];
     double *X, *x, *v, *F; /* X,x,v: [n][3]; F: [n][9] row-major */
     double* Fdot;          /* [n][9] rate of F of the last update (viscosity) */
+    double* Fpi;           /* [n][9] inverse plastic deformation gradient F_p^{-1} */
     double *vol0, *mass, *E;
     uint8_t* dig;          /* [n][max_cuts] ternary digits */
     double* D;             /* cutting progress */
@@ -400,6 +401,77 @@ double orc_fcr_psi(double E, double nu, const double* F)
     return mu * a + 0.5 * lam * (J - 1.0) * (J - 1.0);
 }
 
+static void matmul3(const double* A, const double* B, double* C)
+{
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            double a = 0.0;
+            for (int k = 0; k < 3; k++) a += A[3 * i + k] * B[3 * k + j];
+            C[3 * i + j] = a;
+        }
+}
+
+/* von Mises projection of an elastic deformation gradient (reading R32): with    */
+/* F_e = U diag(sigma) V^T and Hencky strain eps = ln sigma, the deviatoric part   */
+/* of the Kirchhoff stress of the logarithmic model, 2 mu dev(eps), is scaled back */
+/* onto the cylinder |2 mu dev(eps)| = sqrt(2/3) sigma_y; the volumetric part is   */
+/* kept.  Writes the projected F_e; returns 1 if it yielded, 0 if not, -1 if det  */
+/* F_e <= 0.                                                                       */
+int orc_vm_project(double E, double nu, double sigma_y, const double* Fe, double* Fe_new)
+{
+    double mu, lam;
+    lame(E, nu, &mu, &lam);
+    memcpy(Fe_new, Fe, sizeof(double) * 9);
+    if (!(det3(Fe) > 0.0)) return -1;
+    double C[9], ev[3], V[9];
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            double a = 0.0;
+            for (int k = 0; k < 3; k++) a += Fe[3 * k + i] * Fe[3 * k + j];
+            C[3 * i + j] = a;
+        }
+    sym_eig3(C, ev, V);
+    double sg[3], eps[3];
+    for (int k = 0; k < 3; k++) {
+        sg[k] = sqrt(ev[k]);
+        eps[k] = log(sg[k]);
+    }
+    double tr = (eps[0] + eps[1] + eps[2]) / 3.0, dev[3], nd = 0.0;
+    for (int k = 0; k < 3; k++) {
+        dev[k] = eps[k] - tr;
+        nd += dev[k] * dev[k];
+    }
+    nd = sqrt(nd);
+    const double lim = sqrt(2.0 / 3.0) * sigma_y;
+    if (!(2.0 * mu * nd > lim)) return 0;
+    const double scale = lim / (2.0 * mu * nd);
+    /* U = F_e V diag(1/sigma); F_e_new = U diag(exp(eps_new)) V^T */
+    double U[9];
+    for (int i = 0; i < 3; i++)
+        for (int k = 0; k < 3; k++) {
+            double a = 0.0;
+            for (int j = 0; j < 3; j++) a += Fe[3 * i + j] * V[3 * j + k];
+            U[3 * i + k] = a / sg[k];
+        }
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            double a = 0.0;
+            for (int k = 0; k < 3; k++) a += U[3 * i + k] * exp(tr + scale * dev[k]) * V[3 * j + k];
+            Fe_new[3 * i + j] = a;
+        }
+    return 1;
+}
+
+static int inv3(const double* A, double* Ai)
+{
+    double C[9], d = det3(A);
+    if (d == 0.0) return -1;
+    cofactor3(A, C);
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) Ai[3 * i + j] = C[3 * j + i] / d;
+    return 0;
+}
+
 /* Newtonian viscous first Piola-Kirchhoff stress: Cauchy stress eta (l + l^T)   */
 /* with l = Fdot F^{-1} the spatial velocity gradient, pulled back by J F^{-T}.  */
 int orc_visc_P(double eta, const double* F, const double* Fdot, double* P)
@@ -489,6 +561,7 @@ void orc_destroy(orc_scene* s)
     free(s->v);
     free(s->F);
     free(s->Fdot);
+    free(s->Fpi);
     free(s->vol0);
     free(s->mass);
     free(s->E);
@@ -521,6 +594,9 @@ orc_scene* orc_create(const orc_params* P, long n, const double* X, const double
     s->v = (double*)calloc(3 * (n + 1), sizeof(double));
     s->F = (double*)malloc(sizeof(double) * 9 * (n + 1));
     s->Fdot = (double*)calloc(9 * (n + 1), sizeof(double));
+    s->Fpi = (double*)calloc(9 * (n + 1), sizeof(double));
+    for (long p = 0; p < n; p++)
+        for (int i = 0; i < 3; i++) s->Fpi[9 * p + 4 * i] = 1.0;
     s->vol0 = (double*)malloc(sizeof(double) * (n + 1));
     s->mass = (double*)malloc(sizeof(double) * (n + 1));
     s->E = (double*)malloc(sizeof(double) * (n + 1));
@@ -1118,8 +1194,22 @@ int orc_step(orc_scene* s, const orc_tool* tools, int nt, double* wrench, int br
     double w[8], g[24];
     for (long p = 0; p < n; p++) {
         double Pk[9];
-        const int bad = P->material == 1 ? orc_fcr_P(s->E[p], P->nu, &s->F[9 * p], Pk)
-                                         : orc_neo_hookean_P(s->E[p], P->nu, &s->F[9 * p], Pk);
+        int bad;
+        if (P->material == 1 && P->yield_stress > 0.0) {
+            /* P = P_fcr(F_e) F_p^{-T}, F_e = F F_p^{-1} (reading R32) */
+            double Fe[9], Pe[9];
+            matmul3(&s->F[9 * p], &s->Fpi[9 * p], Fe);
+            bad = orc_fcr_P(s->E[p], P->nu, Fe, Pe);
+            for (int i = 0; i < 3; i++)
+                for (int j = 0; j < 3; j++) {
+                    double a = 0.0;
+                    for (int k = 0; k < 3; k++) a += Pe[3 * i + k] * s->Fpi[9 * p + 3 * j + k];
+                    Pk[3 * i + j] = a;
+                }
+        } else {
+            bad = P->material == 1 ? orc_fcr_P(s->E[p], P->nu, &s->F[9 * p], Pk)
+                                   : orc_neo_hookean_P(s->E[p], P->nu, &s->F[9 * p], Pk);
+        }
         if (bad) s->status = ORC_E_NONFINITE;
         if (P->viscosity > 0.0) {
             double Pv[9];
@@ -1201,6 +1291,13 @@ int orc_step(orc_scene* s, const orc_tool* tools, int nt, double* wrench, int br
         double* F = &s->F[9 * p];
         for (int i = 0; i < 9; i++) F[i] += dt * L[i];
         memcpy(&s->Fdot[9 * p], L, sizeof(L));
+        if (P->material == 1 && P->yield_stress > 0.0 && det3(F) > 0.0) {
+            /* plasticity projection of the trial F_e = F F_p^{-1}; F_p^{-1} = F^{-1} F_e */
+            double Fe[9], Fen[9], Fi[9];
+            matmul3(F, &s->Fpi[9 * p], Fe);
+            if (orc_vm_project(s->E[p], P->nu, P->yield_stress, Fe, Fen) == 1 && inv3(F, Fi) == 0)
+                matmul3(Fi, Fen, &s->Fpi[9 * p]);
+        }
         double J = det3(F);
         int finite = 1;
         for (int i = 0; i < 9; i++) finite &= isfinite(F[i]);

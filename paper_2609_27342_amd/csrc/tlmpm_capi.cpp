@@ -195,7 +195,7 @@ Dims dims_of(const tlmpm_scene_desc* d)
 
 struct Offsets {
     size_t X, u, v, H, code, code_prev, D, perm, E, m, V0, cell_start, active, cnt0, cnt1, sc0, sc1, p2g, rs, hist,
-        aabb, wpart, Fdot, wacc, Jmat, Jrig, brig, bmixed, ccode, ckeys, gmeta, gperm, bround, tools, tinfo, ctr, bact, status, dirty, bdirty, pcell, cand_idx, coff, cmask, cstatic, bcand, hbin, hmax, bcount, bids, crec, htab, hnext, ph_n, ph_q, ph_u,
+        aabb, wpart, Fdot, Gp, wacc, Jmat, Jrig, brig, bmixed, ccode, ckeys, gmeta, gperm, bround, tools, tinfo, ctr, bact, status, dirty, bdirty, pcell, cand_idx, coff, cmask, cstatic, bcand, hbin, hmax, bcount, bids, crec, htab, hnext, ph_n, ph_q, ph_u,
         total;
     uint32_t hmask;
 };
@@ -264,6 +264,7 @@ Offsets plan(const tlmpm_scene_desc* d, long long n_active)
     o.aabb = L.take((size_t)g.n_bricks * 8 * f);
     o.wpart = L.take((size_t)g.n_bricks * TL_MAX_TOOLS * 6 * sizeof(double));
     o.Fdot = d->viscosity > 0.0f ? L.take(9 * N * f) : 0;
+    o.Gp = d->yield_stress > 0.0f ? L.take(9 * N * f) : 0;
     o.wacc = L.take(TL_MAX_TOOLS * 6 * sizeof(double));
     o.Jmat = d->material_contact ? L.take(3 * N * f) : 0;
     o.Jrig = L.take(3 * N * f);
@@ -508,6 +509,7 @@ extern "C" tlmpm_status tlmpm_create_scene(const tlmpm_scene_desc* d, void* ws, 
     D.aabb = (float*)(base + o.aabb);
     D.wpart = (double*)(base + o.wpart);
     D.Fdot = o.Fdot ? (float*)(base + o.Fdot) : nullptr;
+    D.Gp = o.Gp ? (float*)(base + o.Gp) : nullptr;
     D.wacc = (double*)(base + o.wacc);
     D.Jmat = d->material_contact ? (float*)(base + o.Jmat) : nullptr;
     D.Jrig = (float*)(base + o.Jrig);

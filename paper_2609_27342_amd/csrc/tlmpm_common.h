@@ -124,6 +124,7 @@ struct SceneD {
     float* aabb;   // [n_bricks][8]: min xyz, max xyz, max |v|, 0
     double* wpart; // [TL_MAX_TOOLS * 6][n_active] per-brick wrench sums of the call so far
     float* Fdot;   // [9][N] rate of F of its last update (viscous scenes), else null
+    float* Gp;     // [9][N] F_p^{-1} - I (plastic scenes), else null
     double* wacc;  // [TL_MAX_TOOLS][6]
     float* Jmat;   // [3][N] material contact impulse (candidates only)
     float* Jrig;   // [3][N] floor and tool impulse (bricks with brig set)

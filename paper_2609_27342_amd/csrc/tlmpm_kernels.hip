@@ -592,6 +592,101 @@ DEV void add_viscous(float eta, const float* H, const float* Fdot, float* P)
         }
 }
 
+// von Mises plasticity projection (Sec. III-B; reading R32) of the trial elastic
+// deformation gradient F_e = F F_p^{-1} = I + K: with F_e^T F_e - I = K + K^T +
+// K^T K = V diag(e) V^T, Hencky strain eps = log1p(e) / 2, the deviatoric part is
+// scaled back onto |2 mu dev(eps)| = sqrt(2/3) sigma_y (volume kept).  The
+// projected F_e = F_e M with M = V diag(exp(eps_new - eps)) V^T, so F_p^{-1} = I +
+// G becomes (I + G) M.  Updates G and K; returns whether it yielded.
+DEV bool vm_project(float E, float nu, float sigma_y, float* K, float* G)
+{
+    const float mu = E / (2.0f * (1.0f + nu));
+    float A[9];
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            float a = K[3 * i + j] + K[3 * j + i];
+#pragma unroll
+            for (int k = 0; k < 3; k++) a += K[3 * k + i] * K[3 * k + j];
+            A[3 * i + j] = a;
+        }
+    float V[9] = {1.0f, 0.0f, 0.0f, 0.0f, 1.0f, 0.0f, 0.0f, 0.0f, 1.0f};
+#pragma unroll 1
+    for (int sweep = 0; sweep < 4; sweep++) {
+#pragma unroll
+        for (int pq = 0; pq < 3; pq++) {
+            const int p = pq == 2 ? 1 : 0, q = pq == 0 ? 1 : 2;
+            const float apq = A[3 * p + q];
+            if (apq == 0.0f) continue;
+            const float th = (A[3 * q + q] - A[3 * p + p]) / (2.0f * apq);
+            const float t = copysignf(1.0f, th) / (fabsf(th) + sqrtf(th * th + 1.0f));
+            const float c = 1.0f / sqrtf(t * t + 1.0f), sn = t * c;
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                const float akp = A[3 * k + p], akq = A[3 * k + q];
+                A[3 * k + p] = c * akp - sn * akq;
+                A[3 * k + q] = sn * akp + c * akq;
+            }
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                const float apk = A[3 * p + k], aqk = A[3 * q + k];
+                A[3 * p + k] = c * apk - sn * aqk;
+                A[3 * q + k] = sn * apk + c * aqk;
+            }
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                const float vkp = V[3 * k + p], vkq = V[3 * k + q];
+                V[3 * k + p] = c * vkp - sn * vkq;
+                V[3 * k + q] = sn * vkp + c * vkq;
+            }
+        }
+    }
+    float eps[3];
+#pragma unroll
+    for (int k = 0; k < 3; k++) eps[k] = 0.5f * log1pf(A[4 * k]);
+    const float tr = (eps[0] + eps[1] + eps[2]) * (1.0f / 3.0f);
+    float dev[3], nd = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        dev[k] = eps[k] - tr;
+        nd += dev[k] * dev[k];
+    }
+    nd = sqrtf(nd);
+    const float lim = 0.816496580927726f * sigma_y; // sqrt(2/3)
+    if (!(2.0f * mu * nd > lim)) return false;
+    const float scale = lim / (2.0f * mu * nd);
+    float d[3];
+#pragma unroll
+    for (int k = 0; k < 3; k++) d[k] = expm1f((scale - 1.0f) * dev[k]);
+    float Mm[9]; // M - I
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) Mm[3 * i + j] = V[3 * i] * d[0] * V[3 * j] + V[3 * i + 1] * d[1] * V[3 * j + 1] +
+                                                    V[3 * i + 2] * d[2] * V[3 * j + 2];
+    float Gn[9], Kn[9];
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            float g = G[3 * i + j] + Mm[3 * i + j], k = K[3 * i + j] + Mm[3 * i + j];
+#pragma unroll
+            for (int m = 0; m < 3; m++) {
+                g += G[3 * i + m] * Mm[3 * m + j];
+                k += K[3 * i + m] * Mm[3 * m + j];
+            }
+            Gn[3 * i + j] = g;
+            Kn[3 * i + j] = k;
+        }
+#pragma unroll
+    for (int a = 0; a < 9; a++) {
+        G[a] = Gn[a];
+        K[a] = Kn[a];
+    }
+    return true;
+}
+
 // ------------------------------------------------------- history-based friction
 // Tangential spring transported to the current tangent plane (length kept), trial
 // force -k_t u - c_t v_t, stick below mu_s f_n, else slip at mu_d f_n with the
@@ -991,6 +1086,30 @@ DEV void p2g_body(const SceneK& S, const SceneD& D, int bi, KA_Args A)
                 D.code[p] = code;
             }
         }
+        // plasticity: F_p^{-1} = I + Gp; projection after each F update
+        float Gp[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        if constexpr (MAT == 1) {
+            if (S.ystress > 0.0f && valid) {
+#pragma unroll
+                for (int a = 0; a < 9; a++) Gp[a] = D.Gp[a * N + p];
+                if (use_r) {
+                    float K[9]; // F_e - I = H + Gp + H Gp
+#pragma unroll
+                    for (int i = 0; i < 3; i++)
+#pragma unroll
+                        for (int j = 0; j < 3; j++) {
+                            float k = H[3 * i + j] + Gp[3 * i + j];
+#pragma unroll
+                            for (int m = 0; m < 3; m++) k += H[3 * i + m] * Gp[3 * m + j];
+                            K[3 * i + j] = k;
+                        }
+                    const float Ey = S.e_uniform ? S.E0 : D.E[p];
+                    if (vm_project(Ey, S.nu, S.ystress, K, Gp))
+#pragma unroll
+                        for (int a = 0; a < 9; a++) D.Gp[a * N + p] = Gp[a];
+                }
+            }
+        }
         if constexpr (MAT == 1) {
             // viscosity uses the rate of the last F update: kept for the substeps
             // whose P2G has no pending update (the first, or after a state read)
@@ -1014,10 +1133,35 @@ DEV void p2g_body(const SceneK& S, const SceneD& D, int bi, KA_Args A)
             V0 = S.v_uniform ? S.V0 : D.V0[p];
             E = S.e_uniform ? S.E0 : D.E[p];
             bool ok;
-            if constexpr (MAT == 1)
-                ok = S.material == 1 ? fixed_corotated(E, S.nu, H, Pk) : neo_hookean(E, S.nu, H, Pk);
-            else
+            if constexpr (MAT == 1) {
+                if (S.ystress > 0.0f) {
+                    // P = P_fcr(F_e) F_p^{-T}, F_e - I = H + Gp + H Gp, F_p^{-1} = I + Gp
+                    float K[9], Pe[9];
+#pragma unroll
+                    for (int i = 0; i < 3; i++)
+#pragma unroll
+                        for (int j = 0; j < 3; j++) {
+                            float k = H[3 * i + j] + Gp[3 * i + j];
+#pragma unroll
+                            for (int m = 0; m < 3; m++) k += H[3 * i + m] * Gp[3 * m + j];
+                            K[3 * i + j] = k;
+                        }
+                    ok = fixed_corotated(E, S.nu, K, Pe);
+#pragma unroll
+                    for (int i = 0; i < 3; i++)
+#pragma unroll
+                        for (int j = 0; j < 3; j++) {
+                            float a = Pe[3 * i + j];
+#pragma unroll
+                            for (int m = 0; m < 3; m++) a += Pe[3 * i + m] * Gp[3 * j + m];
+                            Pk[3 * i + j] = a;
+                        }
+                } else {
+                    ok = S.material == 1 ? fixed_corotated(E, S.nu, H, Pk) : neo_hookean(E, S.nu, H, Pk);
+                }
+            } else {
                 ok = neo_hookean(E, S.nu, H, Pk);
+            }
             if (ok && MAT == 1 && S.visc > 0.0f) add_viscous(S.visc, H, Lg, Pk);
             if (!ok) {
                 atomicOr(D.status, TL_ST_NONFINITE);

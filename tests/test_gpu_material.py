@@ -1,5 +1,6 @@
-"""The paper's material model (Sec. III-B, reading R31) on the GPU path against the
-FP64 oracle: fixed-corotated elasticity with Newtonian viscosity.
+"""The paper's material model (Sec. III-B, readings R31, R32) on the GPU path against
+the FP64 oracle: fixed-corotated elasticity with Newtonian viscosity and von Mises
+plasticity.
 
 Tolerances as in test_gpu_parity: after one substep the FP32 state is within 1e-5
 of the oracle relative to the field's largest value, after 60 substeps positions
@@ -33,10 +34,10 @@ def _scene(viscosity=5.0, yield_stress=0.0):
     return s
 
 
-@pytest.mark.parametrize("viscosity", [0.0, 5.0])
-def test_fcr_one_substep_and_rollout(tl, viscosity):
-    s = _scene(viscosity)
-    print(f"[case] fcr viscosity={viscosity} n={s['X'].shape[0]}", flush=True)
+@pytest.mark.parametrize("viscosity,yield_stress", [(0.0, 0.0), (5.0, 0.0), (0.0, 300.0), (5.0, 300.0)])
+def test_fcr_one_substep_and_rollout(tl, viscosity, yield_stress):
+    s = _scene(viscosity, yield_stress)
+    print(f"[case] fcr viscosity={viscosity} yield={yield_stress} n={s['X'].shape[0]}", flush=True)
     g = tl.Scene(s)
     o = oracle.OracleScene(s)
     t0 = s["tools_at"](0)
@@ -54,7 +55,7 @@ def test_fcr_one_substep_and_rollout(tl, viscosity):
     a, b = g.read(("u", "v")), o.get()
     assert g.status() == 0
     e = disp_err(gpu_x(a, s["X"]), b["x"], s["X"])
-    print(f"[fcr] viscosity={viscosity} disp_err after 60 substeps {e:.2e}", flush=True)
+    print(f"[fcr] viscosity={viscosity} yield={yield_stress} disp_err after 60 substeps {e:.2e}", flush=True)
     assert e < 1e-3
 
 
@@ -80,6 +81,32 @@ def test_state_read_keeps_the_viscous_rate(tl):
         g1.step(tools)
         g2.step(tools)
         if j in (5, 11):
+            g2.read(("F",))
+    a, b = g1.read(("u", "v", "F")), g2.read(("u", "v", "F"))
+    for f in ("u", "v", "F"):
+        assert np.array_equal(a[f], b[f]), f
+
+
+def test_plasticity_engages(tl):
+    """The cube sagging under gravity yields at 300 Pa: the plastic rollout ends
+    elsewhere than the elastic one (and the oracle agrees, above)."""
+    s0, s1 = _scene(0.0, 0.0), _scene(0.0, 300.0)
+    g0, g1 = tl.Scene(s0), tl.Scene(s1)
+    for j in range(60):
+        g0.step(s0["tools_at"](j))
+        g1.step(s1["tools_at"](j))
+    d = np.abs(g0.read(("u",))["u"] - g1.read(("u",))["u"]).max()
+    assert d > 1e-7
+
+
+def test_state_read_keeps_the_plastic_state(tl):
+    s = _scene(5.0, 300.0)
+    g1, g2 = tl.Scene(s), tl.Scene(s)
+    for j in range(30):
+        tools = s["tools_at"](j)
+        g1.step(tools)
+        g2.step(tools)
+        if j in (7, 19):
             g2.read(("F",))
     a, b = g1.read(("u", "v", "F")), g2.read(("u", "v", "F"))
     for f in ("u", "v", "F"):

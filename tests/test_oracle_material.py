@@ -2,7 +2,9 @@
 paper's material model, Sec. III-B; reading R31) against the mathematics: the polar
 decomposition from an SVD (a library routine), zero stress at rotations,
 objectivity and isotropy, the stress as the derivative of the energy, the small-
-strain (Hooke) limit, closed-form viscous stresses."""
+strain (Hooke) limit, closed-form viscous stresses; and of its von Mises projection
+(reading R32) against a projection computed from numpy's SVD, its invariances and
+its elastic limit."""
 import numpy as np
 import pytest
 
@@ -123,3 +125,75 @@ def test_fcr_scene_uniform_translation_and_rest():
     assert np.allclose(st["v"], [0.3, -0.1, 0.2], atol=1e-12)
     assert np.allclose(st["x"] - x0, 5 * 1e-4 * np.array([0.3, -0.1, 0.2]), atol=1e-12)
     assert np.allclose(st["F"], np.eye(3), atol=1e-12)
+
+
+# ------------------------------------------------------------------ plasticity (R32)
+SY = 2.0e3  # yield stress of the paper's throwing-knife block
+
+
+def test_vm_projection_below_yield_is_identity():
+    Fe = np.diag([1.01, 0.995, 1.0 / (1.01 * 0.995)])
+    Fn, yielded = oracle.vm_project(E, NU, SY, Fe)
+    assert not yielded and np.array_equal(Fn, Fe)
+
+
+def test_vm_projection_closed_form_from_svd():
+    """Beyond yield the projected F_e keeps the singular vectors and the volume,
+    and its deviatoric Hencky strain lies on the yield surface, scaled from the
+    trial one: computed here from numpy's SVD."""
+    rng = np.random.default_rng(7)
+    for _ in range(20):
+        Fe = _rand_F(rng, 0.25)
+        U, s, Vt = np.linalg.svd(Fe)
+        eps = np.log(s)
+        dev = eps - eps.mean()
+        if 2 * MU * np.linalg.norm(dev) <= np.sqrt(2 / 3) * SY:
+            continue
+        scale = np.sqrt(2 / 3) * SY / (2 * MU * np.linalg.norm(dev))
+        expect = U @ np.diag(np.exp(eps.mean() + scale * dev)) @ Vt
+        Fn, yielded = oracle.vm_project(E, NU, SY, Fe)
+        assert yielded
+        assert np.allclose(Fn, expect, atol=1e-12)
+        assert abs(np.linalg.det(Fn) - np.linalg.det(Fe)) < 1e-12
+        sn = np.linalg.svd(Fn, compute_uv=False)
+        dn = np.log(sn) - np.log(sn).mean()
+        assert abs(2 * MU * np.linalg.norm(dn) - np.sqrt(2 / 3) * SY) < 1e-9 * SY
+
+
+def test_vm_projection_rotation_equivariance():
+    rng = np.random.default_rng(8)
+    Fe, Q1, Q2 = _rand_F(rng, 0.3), _rand_rot(rng), _rand_rot(rng)
+    Fn, _ = oracle.vm_project(E, NU, SY, Fe)
+    Fr, _ = oracle.vm_project(E, NU, SY, Q1 @ Fe @ Q2)
+    assert np.allclose(Fr, Q1 @ Fn @ Q2, atol=1e-12)
+
+
+def test_unreachable_yield_reproduces_elastic_scene():
+    """With a yield stress no state reaches, the plastic model (F_e = F F_p^-1 with
+    F_p = I) gives the fixed-corotated scene bitwise."""
+    from paper_2609_27342_amd import workloads as W
+    def run(ys):
+        sc = W.box_scene(n_cells=(3, 3, 3), dx=0.01, E=E, nu=NU, v0=(0.0, 0.0, -0.5))
+        sc["params"].update(material=1, yield_stress=ys)
+        o = oracle.OracleScene(sc)
+        for _ in range(8):
+            o.step([])
+        return o.get()
+    a, b = run(0.0), run(1e12)
+    for k in ("x", "v", "F"):
+        assert np.array_equal(a[k], b[k])
+
+
+def test_yielding_scene_departs_from_elastic():
+    """A block dropped on the floor with a low yield stress deforms plastically:
+    its state departs from the elastic one."""
+    from paper_2609_27342_amd import workloads as W
+    def run(ys):
+        sc = W.box_scene(n_cells=(3, 3, 3), dx=0.01, E=E, nu=NU, v0=(0.0, 0.0, -2.0))
+        sc["params"].update(material=1, yield_stress=ys, floor_z=-0.005)
+        o = oracle.OracleScene(sc)
+        for _ in range(40):
+            o.step([])
+        return o.get()
+    a, b = run(0.0), run(50.0)
+    assert np.abs(a["x"] - b["x"]).max() > 1e-6
