@@ -30,7 +30,7 @@ HBM_PEAK_GBS = 8000.0
 ALG_BYTES = {"p2g": 100, "g2p": 64}
 ALG_STEP_BYTES = 136
 DEFAULTS = {"small": (100, 10), "small-deep": (100, 10), "medium": (3000, 300), "large": (200, 10),
-            "batched": (100, 10), "knife": (600, 50)}
+            "batched": (100, 10), "knife": (600, 50), "thrown-knives": (300, 20)}
 
 
 def run_steps(g, scene, j0, j1):
@@ -200,9 +200,9 @@ def bench_knife(args, K, Wm):
     from paper_2609_27342_amd import tlmpm, workloads as W
     from paper_2609_27342_amd.coupling import KnifeRollout
     torch.cuda.set_device(0)
-    sc = W.knife()
+    sc = W.knife() if args.workload == "knife" else W.thrown_knives()
     n = sc["X"].shape[0]
-    iv = sc["knife"]["interval"]
+    iv = sc["knife"]["interval"] if "knife" in sc else sc["knives"]["interval"]
     g = tlmpm.Scene(sc)
     g.graphs(args.graphs)
     ro = KnifeRollout(g, sc)
@@ -221,7 +221,8 @@ def bench_knife(args, K, Wm):
     ro.advance(P)
     prof = g.profile_read()
     g.profile(False)
-    st = ro.body.state()
+    ends = [b.state() for b in ro.bodies]
+    mass = sc["knife"]["body"]["mass"] if "knife" in sc else [k["body"]["mass"] for k in sc["knives"]["bodies"]]
     return {
         "metric": "particle-steps/s per GPU",
         "value": value,
@@ -235,13 +236,27 @@ def bench_knife(args, K, Wm):
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "knife", "particles": n, "dt": sc["params"]["dt"], "interval": iv,
-                   "knife_mass": sc["knife"]["body"]["mass"], "path": "graph" if args.graphs else "plain",
-                   "knife_end": {"x": st["x"].tolist(), "v": st["v"].tolist(), "omega": st["omega"].tolist()}},
+        "config": {"workload": args.workload, "particles": n, "dt": sc["params"]["dt"], "interval": iv,
+                   "material": sc["params"].get("material", 0), "yield_stress": sc["params"].get("yield_stress", 0.0),
+                   "knife_mass": mass, "path": "graph" if args.graphs else "plain",
+                   "knife_end": [{"x": st["x"].tolist(), "v": st["v"].tolist(), "omega": st["omega"].tolist()}
+                                 for st in ends]},
         "status": status,
-        "roofline": roofline_of(prof, value, n, 0, None),
+        "roofline": roofline_of(prof, value, n, material_extra_bytes(sc["params"]), None),
         "cpu_baseline": None,
     }
+
+
+def material_extra_bytes(params):
+    """P2G bytes per particle beyond the Neo-Hookean path: the plastic state F_p^-1
+    read (36 B; written only where the particle yields), the viscous rate Fdot read
+    and written (72 B)."""
+    extra = 0
+    if params.get("material", 0) == 1 and params.get("yield_stress", 0.0) > 0.0:
+        extra += 36
+    if params.get("material", 0) == 1 and params.get("viscosity", 0.0) > 0.0:
+        extra += 72
+    return extra
 
 
 def bench_served(args):
@@ -331,7 +346,7 @@ def main():
     if args.workload == "batched":
         print(json.dumps(bench_batched(args, K, max(Wm, 1))))
         return
-    if args.workload == "knife":
+    if args.workload in ("knife", "thrown-knives"):
         print(json.dumps(bench_knife(args, K, Wm)))
         return
     scene = W.CONFIGS[args.workload]()

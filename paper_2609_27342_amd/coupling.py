@@ -1,34 +1,45 @@
-"""Two-way coupling of a free rigid knife and the TLMPM scene (Sec. III-A, III-F,
-III-G): every interval, the knife's tool record (pose and twist, mass properties)
-is held over `interval` substeps of tlmpm_step, whose interval-averaged wrench then
-advances the knife (tlmpm_rigid_step).  The first interval starts the cut."""
+"""Two-way coupling of free rigid knives and the TLMPM scene (Sec. III-A, III-F,
+III-G): every interval, each knife's tool record (pose and twist, mass properties)
+is held over `interval` substeps of tlmpm_step, whose interval-averaged wrench per
+tool then advances each knife (tlmpm_rigid_step).  The first interval starts the
+cuts."""
 import numpy as np
 
 from . import tlmpm
 
 
 class KnifeRollout:
-    """scene: a tlmpm.Scene; sc: the scene dict of workloads.knife (its "knife"
-    entry gives the body, the blade in body axes and the interval)."""
+    """scene: a tlmpm.Scene; sc: a scene dict with a "knife" entry (one knife: its
+    body, blade in body axes and interval, as workloads.knife gives) or a "knives"
+    entry (workloads.thrown_knives: a list of body/blade pairs and one interval)."""
 
     def __init__(self, scene, sc):
-        k = sc["knife"]
+        if "knives" in sc:
+            ks, iv = sc["knives"]["bodies"], sc["knives"]["interval"]
+        else:
+            ks, iv = [sc["knife"]], sc["knife"]["interval"]
         self.scene = scene
-        self.body = tlmpm.RigidBody(**k["body"])
-        self.blade = dict(k["blade"])
-        self.interval = int(k["interval"])
+        self.bodies = [tlmpm.RigidBody(**k["body"]) for k in ks]
+        self.blades = [dict(k["blade"]) for k in ks]
+        self.body = self.bodies[0]
+        self.interval = int(iv)
         self.dt = float(sc["params"]["dt"])
         self.gravity = np.asarray(sc["params"]["gravity"], np.float64)
         self.done = 0  # intervals so far
 
+    def tools(self):
+        return [b.tool(dict(bl, new_cut=int(self.done == 0))) for b, bl in zip(self.bodies, self.blades)]
+
     def tool(self):
-        return self.body.tool(dict(self.blade, new_cut=int(self.done == 0)))
+        return self.tools()[0]
 
     def advance(self, n_intervals=1):
-        """n_intervals intervals; returns the last interval-averaged wrench."""
-        w = None
+        """n_intervals intervals; returns the last interval-averaged wrench of the
+        first knife (of every knife: last_wrenches)."""
         for _ in range(n_intervals):
-            w = self.scene.step([self.tool()], self.interval, wrench=True)[0]
-            self.body.step(w, self.gravity, self.interval * self.dt)
+            ws = self.scene.step(self.tools(), self.interval, wrench=True)
+            for b, w in zip(self.bodies, ws):
+                b.step(w, self.gravity, self.interval * self.dt)
+            self.last_wrenches = ws
             self.done += 1
-        return w
+        return self.last_wrenches[0]
