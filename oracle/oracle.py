@@ -26,7 +26,7 @@ class Params(C.Structure):
         ("material_contact", C.c_int32), ("floor_on", C.c_int32), ("floor_z", C.c_double),
         ("G_c", C.c_double), ("zeta", C.c_double), ("u_min", C.c_double),
         ("single_field", C.c_int32), ("material", C.c_int32),
-        ("viscosity", C.c_double), ("yield_stress", C.c_double),
+        ("viscosity", C.c_double), ("yield_stress", C.c_double), ("stencil", C.c_int32), ("pad_", C.c_int32),
     ]
 
 
@@ -171,6 +171,7 @@ def make_params(p):
     P.material = int(p.get("material", 0))
     P.viscosity = float(p.get("viscosity", 0.0))
     P.yield_stress = float(p.get("yield_stress", 0.0))
+    P.stencil = int(p.get("stencil", 0))
     return P
 
 
@@ -258,7 +259,7 @@ class OracleScene:
         return lib().orc_last_pairs(self.h)
 
     def grid_dump(self):
-        cap = 8 * self.n + 8
+        cap = 27 * self.n + 8
         node = np.empty(cap, np.int64)
         code = np.empty(cap, np.uint64)
         m = np.empty(cap)
@@ -273,15 +274,17 @@ class OracleScene:
 # --- primitives, for the pins -------------------------------------------------
 
 def shape(params, X):
-    """(node[8], w[8], grad[8,3]) of the trilinear stencil at reference point X."""
+    """(node[k], w[k], grad[k,3]) of the stencil at reference point X: k = 8 for the
+    trilinear hat, 27 for the quadratic B-spline (params stencil = 1)."""
     P = make_params(params) if isinstance(params, dict) else params
     X = _f64(X, (3,))
-    node = (C.c_long * 8)()
-    w = np.empty(8)
-    g = np.empty((8, 3))
+    k = 27 if P.stencil == 1 else 8
+    node = (C.c_long * 27)()
+    w = np.empty(27)
+    g = np.empty((27, 3))
     if lib().orc_shape(C.byref(P), _dp(X), node, _dp(w), _dp(g)):
         raise ValueError("outside grid")
-    return np.array(list(node)), w, g
+    return np.array(list(node))[:k], w[:k].copy(), g[:k].copy()
 
 
 def neo_hookean_P(E, nu, F):

@@ -55,6 +55,8 @@ typedef struct {
     int32_t material;     /* 0 Neo-Hookean, 1 fixed-corotated (Sec. III-B) */
     double viscosity;     /* Newtonian viscosity eta (Pa s), 0 = none */
     double yield_stress;  /* von Mises yield stress (Pa), 0 = elastic */
+    int32_t stencil;      /* 0 trilinear (8 nodes), 1 quadratic B-spline (27 nodes) */
+    int32_t pad_;
 } orc_params;
 
 /* A blade record: the cut frame of Eq. 3 and the band extents of Eq. 4. */
@@ -183,8 +185,9 @@ int orc_conflict(uint64_t a, uint64_t b, int K)
 /* Interpolation in the reference configuration (Eq. 1).                      */
 /* Reading R1: trilinear hat (linear B-spline) over the 8 corners of the base  */
 /* cell floor((X - origin)/dx); weights (1-t, t) and derivatives (-1/dx, 1/dx) */
-/* per axis.  Pinned by partition of unity, zero gradient sum and finite       */
-/* differences of the weights.                                                 */
+/* per axis.  Reading R33 adds the quadratic B-spline over 27 nodes.  Pinned  */
+/* by partition of unity, zero gradient sum, linear reproduction, the closed   */
+/* form of each weight and finite differences of the weights.                  */
 /* ------------------------------------------------------------------------- */
 static int base_cell(const orc_params* P, const double* X, int* base, double* t)
 {
@@ -198,8 +201,57 @@ static int base_cell(const orc_params* P, const double* X, int* base, double* t)
     return 0;
 }
 
+/* Quadratic B-spline of the node distance r (in cells): 3/4 - r^2 for |r| < 1/2,  */
+/* (3/2 - |r|)^2 / 2 for 1/2 <= |r| < 3/2, else 0 (reading R33), and its derivative.*/
+static double bspline2(double r)
+{
+    double a = fabs(r);
+    if (a < 0.5) return 0.75 - a * a;
+    if (a < 1.5) return 0.5 * (1.5 - a) * (1.5 - a);
+    return 0.0;
+}
+
+static double bspline2_d(double r)
+{
+    double a = fabs(r), sg = r < 0.0 ? -1.0 : 1.0;
+    if (a < 0.5) return -2.0 * r;
+    if (a < 1.5) return -sg * (1.5 - a);
+    return 0.0;
+}
+
+/* 27-node stencil: the nodes base .. base + 2 per axis with base = floor(q - 1/2), */
+/* q = (X - origin)/dx; each weight is the B-spline of the node's own distance.    */
+static int shape_quadratic(const orc_params* P, const double* X, long* node, double* w, double* grad)
+{
+    int base[3];
+    double q[3];
+    for (int a = 0; a < 3; a++) {
+        q[a] = (X[a] - P->origin[a]) / P->dx;
+        base[a] = (int)floor(q[a] - 0.5);
+        if (base[a] < 0 || base[a] + 2 > P->cells[a]) return -1;
+    }
+    long nx = P->cells[0] + 1, ny = P->cells[1] + 1;
+    int k = 0;
+    for (int c = 0; c < 3; c++)
+        for (int b = 0; b < 3; b++)
+            for (int a = 0; a < 3; a++, k++) {
+                double rx = q[0] - (base[0] + a), ry = q[1] - (base[1] + b), rz = q[2] - (base[2] + c);
+                double wx = bspline2(rx), wy = bspline2(ry), wz = bspline2(rz);
+                w[k] = wx * wy * wz;
+                grad[3 * k + 0] = bspline2_d(rx) / P->dx * wy * wz;
+                grad[3 * k + 1] = wx * bspline2_d(ry) / P->dx * wz;
+                grad[3 * k + 2] = wx * wy * bspline2_d(rz) / P->dx;
+                if (node) node[k] = ((long)(base[2] + c) * ny + (base[1] + b)) * nx + (base[0] + a);
+            }
+    return 0;
+}
+
+/* Nodes of the stencil: 8 (trilinear) or 27 (quadratic B-spline). */
+int orc_stencil_nodes(const orc_params* P) { return P->stencil == 1 ? 27 : 8; }
+
 int orc_shape(const orc_params* P, const double* X, long* node, double* w, double* grad)
 {
+    if (P->stencil == 1) return shape_quadratic(P, X, node, w, grad);
     int base[3];
     double t[3];
     if (base_cell(P, X, base, t)) return -1;
@@ -612,7 +664,9 @@ orc_scene* orc_create(const orc_params* P, long n, const double* X, const double
         int base[3];
         double t[3];
         for (int a = 0; a < 3; a++) s->X[3 * p + a] = s->x[3 * p + a] = X[3 * p + a];
-        if (base_cell(P, &s->X[3 * p], base, t)) {
+        long nd[27];
+        double wq[27], gq[81];
+        if (base_cell(P, &s->X[3 * p], base, t) || orc_shape(P, &s->X[3 * p], nd, wq, gq)) {
             orc_destroy(s);
             return NULL;
         }
@@ -1185,13 +1239,14 @@ int orc_step(orc_scene* s, const orc_tool* tools, int nt, double* wrench, int br
     /* 2. label-masked P2G (Eq. 2) with gravity and contact impulses */
     long nn = s->nodes[0] * s->nodes[1] * s->nodes[2];
     memset(s->head, 0, sizeof(node_entry*) * nn);
-    if (s->cap_pool < 8 * n + 8) {
-        s->cap_pool = 8 * n + 8;
+    const int ns = orc_stencil_nodes(P);
+    if (s->cap_pool < ns * n + 8) {
+        s->cap_pool = ns * n + 8;
         s->pool = (node_entry*)realloc(s->pool, sizeof(node_entry) * s->cap_pool);
     }
     s->n_pool = 0;
-    long node[8];
-    double w[8], g[24];
+    long node[27];
+    double w[27], g[81];
     for (long p = 0; p < n; p++) {
         double Pk[9];
         int bad;
@@ -1221,7 +1276,7 @@ int orc_step(orc_scene* s, const orc_tool* tools, int nt, double* wrench, int br
         double mp = s->mass[p], V0 = s->vol0[p];
         double ext[3];
         for (int j = 0; j < 3; j++) ext[j] = s->J[3 * p + j] + dt * mp * P->gravity[j];
-        for (int k = 0; k < 8; k++) {
+        for (int k = 0; k < ns; k++) {
             if (w[k] == 0.0) continue; /* reading R7: no contribution, no slot */
             node_entry* e = get_entry(s, node[k], c);
             e->m += w[k] * mp;
@@ -1242,7 +1297,7 @@ int orc_step(orc_scene* s, const orc_tool* tools, int nt, double* wrench, int br
         orc_shape(P, &s->X[3 * p], node, w, g);
         uint64_t c = code_of(s, p);
         double acc_v[3] = {0, 0, 0}, acc_x[3] = {0, 0, 0};
-        for (int k = 0; k < 8; k++) {
+        for (int k = 0; k < ns; k++) {
             if (w[k] == 0.0) continue;
             node_entry* e = find_entry(s, node[k], c);
             for (int j = 0; j < 3; j++) {
@@ -1265,7 +1320,7 @@ int orc_step(orc_scene* s, const orc_tool* tools, int nt, double* wrench, int br
     for (long p = 0; p < n; p++) {
         orc_shape(P, &s->X[3 * p], node, w, g);
         uint64_t c = code_of(s, p);
-        for (int k = 0; k < 8; k++) {
+        for (int k = 0; k < ns; k++) {
             if (w[k] == 0.0) continue;
             node_entry* e = find_entry(s, node[k], c);
             for (int j = 0; j < 3; j++) e->pt[j] += w[k] * s->mass[p] * s->v[3 * p + j];
@@ -1282,7 +1337,7 @@ int orc_step(orc_scene* s, const orc_tool* tools, int nt, double* wrench, int br
         orc_shape(P, &s->X[3 * p], node, w, g);
         uint64_t c = code_of(s, p);
         double L[9] = {0};
-        for (int k = 0; k < 8; k++) {
+        for (int k = 0; k < ns; k++) {
             if (w[k] == 0.0) continue;
             node_entry* e = find_entry(s, node[k], c);
             for (int a = 0; a < 3; a++)
