@@ -28,6 +28,8 @@ HBM_PEAK_GBS = 8000.0
 #   G2P kernel: read X 12, code 4, u 12, v 12; write u 12, v 12       ->  64 B
 #   whole substep (each persistent field read/written once)           -> 136 B
 ALG_BYTES = {"p2g": 100, "g2p": 64}
+# quadratic stencil: P2G reads X, code, v and F (64 B); the F update is a kernel of its own
+ALG_BYTES_QUAD = {"p2g": 64, "g2p": 64}
 ALG_STEP_BYTES = 136
 DEFAULTS = {"small": (100, 10), "small-deep": (100, 10), "medium": (3000, 300), "large": (200, 10),
             "batched": (100, 10), "knife": (600, 50), "thrown-knives": (300, 20)}
@@ -64,7 +66,7 @@ def kernel_source_hash():
     measured hardware traffic is stored in profiles/traffic.json)."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("tlmpm_common.h", "tlmpm_kernels.hip", "tlmpm_contact.hip"):
+    for f in ("tlmpm_common.h", "tlmpm_device.h", "tlmpm_kernels.hip", "tlmpm_contact.hip", "tlmpm_quad.hip"):
         with open(os.path.join(ROOT, "paper_2609_27342_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -84,12 +86,13 @@ def measured_traffic(workload, cls):
     return rec["bytes"] if rec else None
 
 
-def roofline_of(prof, value, n, per_particle_extra=0, workload=None):
+def roofline_of(prof, value, n, per_particle_extra=0, workload=None, alg=None):
     """Roofline of the dominant kernel class from event timings {class: (ms, launches)}."""
+    alg = alg or ALG_BYTES
     kern = {k: {"ms_avg": (v[0] / v[1]) if v[1] else None, "launches": v[1]} for k, v in prof.items()}
     dom = max(("p2g", "g2p"), key=lambda k: prof[k][0])
     avg_s = prof[dom][0] / prof[dom][1] * 1e-3
-    per_particle = ALG_BYTES[dom] + (per_particle_extra if dom == "p2g" else 0)
+    per_particle = alg[dom] + (per_particle_extra if dom == "p2g" else 0)
     achieved = per_particle * n / avg_s / 1e9
     return {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(workload, dom) if workload else None,
@@ -374,7 +377,9 @@ def main():
     run_steps(g, scene, Wm + K, Wm + K + P)
     prof = g.profile_read()
     g.profile(False)
-    roofline = roofline_of(prof, value, n, 4 if scene["E"].min() != scene["E"].max() else 0, args.workload)
+    quad = scene["params"].get("stencil", 0) == 1
+    roofline = roofline_of(prof, value, n, 4 if scene["E"].min() != scene["E"].max() else 0, args.workload,
+                           ALG_BYTES_QUAD if quad else None)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(scene)
@@ -393,6 +398,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "particles": n, "dt": scene["params"]["dt"],
                    "material_contact": bool(scene["params"]["material_contact"]),
+                   "stencil": "quadratic" if quad else "trilinear",
                    "path": "graph" if args.graphs else "plain"},
         "status": status,
         "roofline": roofline,

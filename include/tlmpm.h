@@ -81,6 +81,12 @@ typedef struct {
                                   l = dF/dt F^-1 from the last deformation-gradient update */
     float yield_stress;        /* von Mises yield stress (Pa) of the plasticity projection with
                                   material 1; 0 = elastic */
+    int32_t stencil;           /* interpolation of Eq. 1: 0 trilinear hat over the base cell's 8
+                                  corners, 1 quadratic B-spline over 27 nodes (base node
+                                  floor(q - 1/2), q = (X - origin)/dx).  The quadratic stencil
+                                  needs every particle at least half a cell inside the grid and
+                                  runs one scene per call (batches refuse it); its sums use
+                                  floating-point atomics (not bitwise reproducible). */
 } tlmpm_scene_desc;
 
 /* A blade record: the cut frame of Eq. 3 and the band of Eq. 4.  (n, e, d) must be

@@ -6,7 +6,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtlmpm.so")
 SOURCES = [os.path.join(CSRC, "tlmpm_kernels.hip"), os.path.join(CSRC, "tlmpm_contact.hip"),
-           os.path.join(CSRC, "tlmpm_capi.cpp")]
+           os.path.join(CSRC, "tlmpm_quad.hip"), os.path.join(CSRC, "tlmpm_capi.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
@@ -21,6 +21,7 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
 
 def build(force=True, verbose=False):
     newest = max(os.path.getmtime(p) for p in SOURCES + [os.path.join(CSRC, "tlmpm_common.h"),
+                                                          os.path.join(CSRC, "tlmpm_device.h"),
                                                           os.path.join(HERE, "..", "include", "tlmpm.h")])
     if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= newest:
         return LIB

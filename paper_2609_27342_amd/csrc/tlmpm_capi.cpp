@@ -33,6 +33,7 @@ hipError_t tl_launch_cand(const TlLaunch*, int force);
 hipError_t tl_launch_contact(const TlLaunch*);
 hipError_t tl_launch_fill_f32(float*, long long, float, hipStream_t);
 hipError_t tl_launch_fill_i32(int*, long long, int, hipStream_t);
+hipError_t tl_launch_quad(const TlLaunch*, int par, int stage);
 }
 
 static thread_local std::string g_err;
@@ -196,7 +197,7 @@ Dims dims_of(const tlmpm_scene_desc* d)
 struct Offsets {
     size_t X, u, v, H, code, code_prev, D, perm, E, m, V0, cell_start, active, cnt0, cnt1, sc0, sc1, p2g, rs, hist,
         aabb, wpart, Fdot, Gp, wacc, Jmat, Jrig, brig, bmixed, ccode, ckeys, gmeta, gperm, bround, tools, tinfo, ctr, bact, status, dirty, bdirty, pcell, cand_idx, coff, cmask, cstatic, bcand, hbin, hmax, bcount, bids, crec, htab, hnext, ph_n, ph_q, ph_u,
-        total;
+        qcode, qacc, qrs, qnodes, total;
     uint32_t hmask;
 };
 
@@ -304,6 +305,12 @@ Offsets plan(const tlmpm_scene_desc* d, long long n_active)
     o.dirty = L.take(4);
     o.bdirty = L.take((size_t)g.n_bricks * 4);
     o.pcell = L.take(N * 4);
+    if (d->stencil == 1) {
+        o.qcode = L.take(2 * (size_t)g.NN * scap * 4);
+        o.qacc = L.take((size_t)g.NN * scap * 8 * f);
+        o.qrs = L.take((size_t)g.NN * scap * 4 * f);
+        o.qnodes = L.take((size_t)std::min<long long>(g.NN, n_active * 343) * 4);
+    }
     o.total = L.take(0) + 256;
     return o;
 }
@@ -324,6 +331,16 @@ tlmpm_status validate(const tlmpm_scene_desc* d)
         return fail(TLMPM_E_INVALID, "viscosity and yield_stress must be >= 0");
     if (d->yield_stress > 0.0f && d->material != 1)
         return fail(TLMPM_E_INVALID, "the plasticity projection needs material 1 (fixed-corotated)");
+    if (d->stencil != 0 && d->stencil != 1) return fail(TLMPM_E_INVALID, "stencil must be 0 or 1");
+    if (d->stencil == 1)
+        for (long long p = 0; p < d->n; p++)
+            for (int a = 0; a < 3; a++) {
+                const double q = ((double)d->X[3 * p + a] - d->origin[a]) / d->dx;
+                const double b = std::floor(q - 0.5);
+                if (!(b >= 0.0) || b + 2.0 > (double)d->cells[a])
+                    return fail(TLMPM_E_INVALID, "particle " + std::to_string(p) +
+                                                     ": the quadratic stencil needs half a cell of grid around it");
+            }
     if (!(d->nu > -1.0f && d->nu < 0.5f)) return fail(TLMPM_E_INVALID, "nu must be in (-1, 0.5)");
     if (!d->vol0 && !(d->vol0_uniform > 0.0f)) return fail(TLMPM_E_INVALID, "vol0_uniform must be positive");
     if (!d->mass && !(d->mass_uniform > 0.0f)) return fail(TLMPM_E_INVALID, "mass_uniform must be positive");
@@ -477,6 +494,7 @@ extern "C" tlmpm_status tlmpm_create_scene(const tlmpm_scene_desc* d, void* ws, 
     K.visc = d->viscosity;
     K.ystress = d->yield_stress;
     K.pair_blocks = (int)std::min<long long>(4096, std::max<long long>(1, N / 128));
+    K.stencil = d->stencil;
     float vmax0 = d->vol0_uniform;
     if (d->vol0)
         for (long long p = 0; p < N; p++) vmax0 = std::max(vmax0, d->vol0[p]);
@@ -546,6 +564,29 @@ extern "C" tlmpm_status tlmpm_create_scene(const tlmpm_scene_desc* d, void* ws, 
     D.dirty = (int*)(base + o.dirty);
     D.bdirty = (int*)(base + o.bdirty);
     D.pcell = (int*)(base + o.pcell);
+    std::vector<int> qnodes;
+    if (d->stencil == 1) {
+        D.qcode = (uint32_t*)(base + o.qcode);
+        D.qacc = (float*)(base + o.qacc);
+        D.qrs = (float*)(base + o.qrs);
+        D.qnodes = (int*)(base + o.qnodes);
+        // nodes of the 7x7x7 boxes (from 4 b - 1) of the active bricks, brick-major ids
+        std::vector<uint8_t> mark((size_t)g.NN, 0);
+        for (int b : active) {
+            const int bx = b % g.cbx, by = (b / g.cbx) % g.cby, bz = b / (g.cbx * g.cby);
+            for (int z = 0; z < 7; z++)
+                for (int y = 0; y < 7; y++)
+                    for (int x = 0; x < 7; x++) {
+                        const int gx = bx * TL_B - 1 + x, gy = by * TL_B - 1 + y, gz = bz * TL_B - 1 + z;
+                        if (gx < 0 || gy < 0 || gz < 0 || gx > g.cx || gy > g.cy || gz > g.cz) continue;
+                        const long long nb = ((long long)(gz >> 2) * g.nby + (gy >> 2)) * g.nbx + (gx >> 2);
+                        mark[(size_t)((nb << 6) | ((gz & 3) * 16 + (gy & 3) * 4 + (gx & 3)))] = 1;
+                    }
+        }
+        for (long long i = 0; i < g.NN; i++)
+            if (mark[(size_t)i]) qnodes.push_back((int)i);
+        D.n_qnodes = (int)qnodes.size();
+    }
 
     // sorted SoA host staging
     std::vector<float> h(3 * (size_t)N);
@@ -590,6 +631,14 @@ extern "C" tlmpm_status tlmpm_create_scene(const tlmpm_scene_desc* d, void* ws, 
         return bail(e, "upload bricks");
     if ((e = hipMemcpyAsync(D.bact, bact.data(), bact.size() * 4, hipMemcpyHostToDevice, sc->st)) != hipSuccess)
         return bail(e, "upload brick index");
+    if (d->stencil == 1) {
+        if (!qnodes.empty() && (e = hipMemcpyAsync(D.qnodes, qnodes.data(), qnodes.size() * 4, hipMemcpyHostToDevice,
+                                                   sc->st)) != hipSuccess)
+            return bail(e, "upload stencil nodes");
+        if ((e = tl_launch_fill_i32((int*)D.qcode, 2 * g.NN * K.scap, -1, sc->st)) != hipSuccess)
+            return bail(e, "init node slots");
+        if ((e = hipStreamSynchronize(sc->st)) != hipSuccess) return bail(e, "upload stencil nodes");
+    }
     // rigid-contact history stamps start invalid
     if ((e = tl_launch_fill_f32(D.hist, (long long)(TL_MAX_TOOLS + 1) * 4 * N, 0.0f, sc->st)) != hipSuccess)
         return bail(e, "init history");
@@ -742,8 +791,51 @@ struct CallFlags {
 // (reads only the last substep's motion, the tools and the cutting progress, reset
 // first when a cut starts) from the start of the substep, the slot tables after the
 // label pass; P2G waits for them.
+// one substep with the quadratic stencil: labels and contact as in the trilinear
+// path, then the transfers of tlmpm_quad.hip with the node tables of parity X.cur
+// (flipped every substep); the F update completes inside the substep.
+static tlmpm_status one_substep_quad(Exec& X, const CallFlags& f, bool first)
+{
+    Side side(X);
+    side.par = side.par && X.L.any_material;
+    if (f.any_labels && f.any_new && first) {
+        ProfScope ps(X.prof, 5);
+        HIPCHK(tl_launch_resetD(&X.L));
+    }
+    if (f.any_rigid && side.par) {
+        HIPCHK(side.after_main(0));
+        HIPCHK(tl_launch_rigid(&side.La));
+    }
+    if (f.any_labels) {
+        ProfScope ps(X.prof, 2);
+        HIPCHK(tl_launch_labels(&X.L));
+    }
+    {
+        ProfScope ps(X.prof, 3);
+        HIPCHK(tl_launch_quad(&X.L, X.cur, 0));
+    }
+    if (X.L.any_material) {
+        ProfScope ps(X.prof, 4);
+        if (f.any_labels) HIPCHK(tl_launch_cand(&X.L, 0));
+        HIPCHK(tl_launch_contact(&X.L));
+    }
+    if (f.any_rigid && !side.par) {
+        ProfScope ps(X.prof, 5);
+        HIPCHK(tl_launch_rigid(&X.L));
+    }
+    HIPCHK(side.join());
+    const int cls[6] = {3, 0, 5, 1, 5, 5};
+    for (int stage = 1; stage < 6; stage++) {
+        ProfScope ps(X.prof, cls[stage]);
+        HIPCHK(tl_launch_quad(&X.L, X.cur, stage));
+    }
+    X.cur = 1 - X.cur;
+    return TLMPM_OK;
+}
+
 static tlmpm_status one_substep(Exec& X, const CallFlags& f, bool first)
 {
+    if (X.L.S && X.L.S->stencil == 1) return one_substep_quad(X, f, first);
     Side side(X);
     side.par = side.par && X.L.any_material;
     const bool reset_D = f.any_labels && f.any_new && first;
@@ -1375,6 +1467,8 @@ tlmpm_status check_members(tlmpm_scene* const* scenes, int n)
     if (n <= 0 || !scenes) return fail(TLMPM_E_INVALID, "a batch needs at least one scene");
     for (int s = 0; s < n; s++) {
         if (!scenes[s]) return fail(TLMPM_E_INVALID, "null scene in batch");
+        if (scenes[s]->K.stencil == 1)
+            return fail(TLMPM_E_INVALID, "scenes with the quadratic stencil run one per call (not in a batch)");
         if (scenes[s]->in_batch) return fail(TLMPM_E_INVALID, "scene already belongs to a live batch");
         for (int t = 0; t < s; t++)
             if (scenes[t] == scenes[s]) return fail(TLMPM_E_INVALID, "scene listed twice in batch");

@@ -96,6 +96,7 @@ struct SceneK {
     float visc;       // Newtonian viscosity
     float ystress;    // von Mises yield stress (0: elastic)
     int pair_blocks;  // blocks of the pair search (grid-stride over the candidates)
+    int stencil;      // 0 trilinear (8 nodes), 1 quadratic B-spline (27 nodes)
     double dt_d;
 };
 
@@ -160,6 +161,12 @@ struct SceneD {
     int* ph_n;          // [2][N] stamp << 8 | count of owned springs
     int* ph_q;          // [2][N][TL_PCAP] partner of each spring
     float* ph_u;        // [2][N][TL_PCAP][3] spring, oriented for the pair's lower index
+    // quadratic stencil
+    uint32_t* qcode;    // [2][scap][NN] side keys of the node slots by substep parity (~0u: free)
+    float* qacc;        // [NN][scap][8] P2G sums m, p, dp; after the grid update m, v^n, dv
+    float* qrs;         // [NN][scap][4] re-scatter sums of m v^{n+1}; after the remap v~
+    int* qnodes;        // nodes of the 7x7x7 boxes of the active bricks (ascending)
+    int n_qnodes;
 };
 
 // Workgroups are dealt to the 8 XCDs (each with its own L2) round-robin by

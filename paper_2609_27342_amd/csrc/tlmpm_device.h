@@ -1,0 +1,321 @@
+// tlmpm_device.h -- device functions shared by the trilinear (tlmpm_kernels.hip)
+// and quadratic (tlmpm_quad.hip) transfer kernels: side codes, the LDS barrier and
+// the constitutive models.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "tlmpm_common.h"
+
+#define DEV __device__ __forceinline__
+
+// ---------------------------------------------------------------------------- codes
+// A side code is held as two 15-bit masks: s1 has bit k set when digit k is 1, s2
+// when it is 2 (Eq. 7 in another basis).  Two codes conflict iff some cut has side
+// 1 in one and side 2 in the other (Sec. III-D).
+DEV bool codes_conflict(uint32_t a, uint32_t b)
+{
+    uint32_t a1 = a & 0x7FFFu, a2 = (a >> 15) & 0x7FFFu;
+    uint32_t b1 = b & 0x7FFFu, b2 = (b >> 15) & 0x7FFFu;
+    return ((a1 & b2) | (a2 & b1)) != 0u;
+}
+
+DEV uint32_t slot_key(const SceneK& S, uint32_t code) { return S.single_field ? 0u : (code & TL_CODE_MASK); }
+
+// Workgroup barrier that orders LDS only: global loads issued before it stay in
+// flight (a full __syncthreads() would also wait for them).
+DEV void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// ------------------------------------------------------------- constitutive model
+// Compressible Neo-Hookean first Piola-Kirchhoff stress written in H = F - I so
+// that small strains keep their relative precision in FP32:
+//   cof(F) = (1 + tr H) I - H^T + cof(H),  J = 1 + tr H + I2(H) + det H,
+//   F - F^{-T} = [(I2 + det H) I + J H + H^T - cof(H)] / J,
+//   P = mu (F - F^{-T}) + lambda ln J F^{-T}.
+// Returns false when J <= 0 or the state is not finite.
+DEV bool neo_hookean(float E, float nu, const float* H, float* P)
+{
+    const float mu = E / (2.0f * (1.0f + nu));
+    const float lam = E * nu / ((1.0f + nu) * (1.0f - 2.0f * nu));
+    float cH[9];
+    cH[0] = H[4] * H[8] - H[5] * H[7];
+    cH[1] = H[5] * H[6] - H[3] * H[8];
+    cH[2] = H[3] * H[7] - H[4] * H[6];
+    cH[3] = H[2] * H[7] - H[1] * H[8];
+    cH[4] = H[0] * H[8] - H[2] * H[6];
+    cH[5] = H[1] * H[6] - H[0] * H[7];
+    cH[6] = H[1] * H[5] - H[2] * H[4];
+    cH[7] = H[2] * H[3] - H[0] * H[5];
+    cH[8] = H[0] * H[4] - H[1] * H[3];
+    const float trH = H[0] + H[4] + H[8];
+    const float I2 = cH[0] + cH[4] + cH[8];
+    const float I3 = H[0] * cH[0] + H[1] * cH[1] + H[2] * cH[2];
+    const float Jm1 = trH + (I2 + I3);
+    const float J = 1.0f + Jm1;
+    if (!(J > 0.0f) || !isfinite(J)) return false;
+    const float invJ = 1.0f / J;
+    const float lnJ = log1pf(Jm1);
+    const float e0 = I2 + I3;
+#pragma unroll
+    for (int r = 0; r < 3; r++)
+#pragma unroll
+        for (int s = 0; s < 3; s++) {
+            int rs = 3 * r + s, sr = 3 * s + r;
+            float id = (r == s) ? 1.0f : 0.0f;
+            float FmFiT = (id * e0 + J * H[rs] + H[sr] - cH[rs]) * invJ;
+            float FiT = (id * (1.0f + trH) - H[sr] + cH[rs]) * invJ;
+            P[rs] = mu * FmFiT + lam * lnJ * FiT;
+        }
+    return true;
+}
+
+// Fixed-corotated first Piola-Kirchhoff stress P = 2 mu (F - R) + lambda (J - 1)
+// J F^{-T} (Sec. III-B), F = R S the polar decomposition, in terms of H = F - I so
+// that small strains keep their precision in FP32: with E = F^T F - I = H + H^T +
+// H^T H = Q diag(e) Q^T (Jacobi rotations), S - I = Q diag(e / (sqrt(1 + e) + 1)) Q^T,
+// S^{-1} = Q diag(1 / sqrt(1 + e)) Q^T, R = F S^{-1} and F - R = R (S - I).
+// Returns false when J <= 0 or the state is not finite.
+DEV bool fixed_corotated(float E, float nu, const float* H, float* P)
+{
+    const float mu = E / (2.0f * (1.0f + nu));
+    const float lam = E * nu / ((1.0f + nu) * (1.0f - 2.0f * nu));
+    float A[9];
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            float a = H[3 * i + j] + H[3 * j + i];
+#pragma unroll
+            for (int k = 0; k < 3; k++) a += H[3 * k + i] * H[3 * k + j];
+            A[3 * i + j] = a;
+        }
+    float Q[9] = {1.0f, 0.0f, 0.0f, 0.0f, 1.0f, 0.0f, 0.0f, 0.0f, 1.0f};
+    // cyclic Jacobi sweeps (a fixed count: FP32 converges within four)
+#pragma unroll 1
+    for (int sweep = 0; sweep < 4; sweep++) {
+#pragma unroll
+        for (int pq = 0; pq < 3; pq++) {
+            const int p = pq == 2 ? 1 : 0, q = pq == 0 ? 1 : 2;
+            const float apq = A[3 * p + q];
+            if (apq == 0.0f) continue;
+            const float th = (A[3 * q + q] - A[3 * p + p]) / (2.0f * apq);
+            const float t = copysignf(1.0f, th) / (fabsf(th) + sqrtf(th * th + 1.0f));
+            const float c = 1.0f / sqrtf(t * t + 1.0f), sn = t * c;
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                const float akp = A[3 * k + p], akq = A[3 * k + q];
+                A[3 * k + p] = c * akp - sn * akq;
+                A[3 * k + q] = sn * akp + c * akq;
+            }
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                const float apk = A[3 * p + k], aqk = A[3 * q + k];
+                A[3 * p + k] = c * apk - sn * aqk;
+                A[3 * q + k] = sn * apk + c * aqk;
+            }
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                const float qkp = Q[3 * k + p], qkq = Q[3 * k + q];
+                Q[3 * k + p] = c * qkp - sn * qkq;
+                Q[3 * k + q] = sn * qkp + c * qkq;
+            }
+        }
+    }
+    float sm1[3], sinv[3];
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        const float e = A[4 * k], r = sqrtf(1.0f + e);
+        if (!(1.0f + e > 0.0f)) return false;
+        sm1[k] = e / (r + 1.0f);
+        sinv[k] = 1.0f / r;
+    }
+    float SmI[9], Si[9];
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            float a = 0.0f, b = 0.0f;
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                a += Q[3 * i + k] * sm1[k] * Q[3 * j + k];
+                b += Q[3 * i + k] * sinv[k] * Q[3 * j + k];
+            }
+            SmI[3 * i + j] = a;
+            Si[3 * i + j] = b;
+        }
+    float Rm[9];
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            float a = Si[3 * i + j];
+#pragma unroll
+            for (int k = 0; k < 3; k++) a += H[3 * i + k] * Si[3 * k + j];
+            Rm[3 * i + j] = a;
+        }
+    float cH[9];
+    cH[0] = H[4] * H[8] - H[5] * H[7];
+    cH[1] = H[5] * H[6] - H[3] * H[8];
+    cH[2] = H[3] * H[7] - H[4] * H[6];
+    cH[3] = H[2] * H[7] - H[1] * H[8];
+    cH[4] = H[0] * H[8] - H[2] * H[6];
+    cH[5] = H[1] * H[6] - H[0] * H[7];
+    cH[6] = H[1] * H[5] - H[2] * H[4];
+    cH[7] = H[2] * H[3] - H[0] * H[5];
+    cH[8] = H[0] * H[4] - H[1] * H[3];
+    const float trH = H[0] + H[4] + H[8];
+    const float I2 = cH[0] + cH[4] + cH[8];
+    const float I3 = H[0] * cH[0] + H[1] * cH[1] + H[2] * cH[2];
+    const float Jm1 = trH + (I2 + I3);
+    if (!(1.0f + Jm1 > 0.0f) || !isfinite(Jm1)) return false;
+#pragma unroll
+    for (int r = 0; r < 3; r++)
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            float fr = 0.0f; // (F - R)_rc = (R (S - I))_rc
+#pragma unroll
+            for (int k = 0; k < 3; k++) fr += Rm[3 * r + k] * SmI[3 * k + c];
+            const float cof = (r == c ? 1.0f + trH : 0.0f) - H[3 * c + r] + cH[3 * r + c]; // J F^{-T}
+            P[3 * r + c] = 2.0f * mu * fr + lam * Jm1 * cof;
+        }
+    return true;
+}
+
+// Adds the Newtonian viscous first Piola-Kirchhoff stress J eta (l + l^T) F^{-T},
+// l = Fdot F^{-1} (Sec. III-B), to P.  F = I + H with J > 0.
+DEV void add_viscous(float eta, const float* H, const float* Fdot, float* P)
+{
+    float C[9]; // J F^{-T}
+    C[0] = (1.0f + H[4]) * (1.0f + H[8]) - H[5] * H[7];
+    C[1] = H[5] * H[6] - H[3] * (1.0f + H[8]);
+    C[2] = H[3] * H[7] - (1.0f + H[4]) * H[6];
+    C[3] = H[2] * H[7] - H[1] * (1.0f + H[8]);
+    C[4] = (1.0f + H[0]) * (1.0f + H[8]) - H[2] * H[6];
+    C[5] = H[1] * H[6] - (1.0f + H[0]) * H[7];
+    C[6] = H[1] * H[5] - H[2] * (1.0f + H[4]);
+    C[7] = H[2] * H[3] - (1.0f + H[0]) * H[5];
+    C[8] = (1.0f + H[0]) * (1.0f + H[4]) - H[1] * H[3];
+    const float J = (1.0f + H[0]) * C[0] + H[1] * C[1] + H[2] * C[2];
+    const float iJ = 1.0f / J;
+    float l[9]; // Fdot F^{-1}, F^{-1} = C^T / J
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            float a = 0.0f;
+#pragma unroll
+            for (int k = 0; k < 3; k++) a += Fdot[3 * i + k] * C[3 * j + k];
+            l[3 * i + j] = a * iJ;
+        }
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            float a = 0.0f;
+#pragma unroll
+            for (int k = 0; k < 3; k++) a += eta * (l[3 * i + k] + l[3 * k + i]) * C[3 * k + j];
+            P[3 * i + j] += a;
+        }
+}
+
+// von Mises plasticity projection (Sec. III-B; reading R32) of the trial elastic
+// deformation gradient F_e = F F_p^{-1} = I + K: with F_e^T F_e - I = K + K^T +
+// K^T K = V diag(e) V^T, Hencky strain eps = log1p(e) / 2, the deviatoric part is
+// scaled back onto |2 mu dev(eps)| = sqrt(2/3) sigma_y (volume kept).  The
+// projected F_e = F_e M with M = V diag(exp(eps_new - eps)) V^T, so F_p^{-1} = I +
+// G becomes (I + G) M.  Updates G and K; returns whether it yielded.
+DEV bool vm_project(float E, float nu, float sigma_y, float* K, float* G)
+{
+    const float mu = E / (2.0f * (1.0f + nu));
+    float A[9];
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            float a = K[3 * i + j] + K[3 * j + i];
+#pragma unroll
+            for (int k = 0; k < 3; k++) a += K[3 * k + i] * K[3 * k + j];
+            A[3 * i + j] = a;
+        }
+    float V[9] = {1.0f, 0.0f, 0.0f, 0.0f, 1.0f, 0.0f, 0.0f, 0.0f, 1.0f};
+#pragma unroll 1
+    for (int sweep = 0; sweep < 4; sweep++) {
+#pragma unroll
+        for (int pq = 0; pq < 3; pq++) {
+            const int p = pq == 2 ? 1 : 0, q = pq == 0 ? 1 : 2;
+            const float apq = A[3 * p + q];
+            if (apq == 0.0f) continue;
+            const float th = (A[3 * q + q] - A[3 * p + p]) / (2.0f * apq);
+            const float t = copysignf(1.0f, th) / (fabsf(th) + sqrtf(th * th + 1.0f));
+            const float c = 1.0f / sqrtf(t * t + 1.0f), sn = t * c;
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                const float akp = A[3 * k + p], akq = A[3 * k + q];
+                A[3 * k + p] = c * akp - sn * akq;
+                A[3 * k + q] = sn * akp + c * akq;
+            }
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                const float apk = A[3 * p + k], aqk = A[3 * q + k];
+                A[3 * p + k] = c * apk - sn * aqk;
+                A[3 * q + k] = sn * apk + c * aqk;
+            }
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                const float vkp = V[3 * k + p], vkq = V[3 * k + q];
+                V[3 * k + p] = c * vkp - sn * vkq;
+                V[3 * k + q] = sn * vkp + c * vkq;
+            }
+        }
+    }
+    float eps[3];
+#pragma unroll
+    for (int k = 0; k < 3; k++) eps[k] = 0.5f * log1pf(A[4 * k]);
+    const float tr = (eps[0] + eps[1] + eps[2]) * (1.0f / 3.0f);
+    float dev[3], nd = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        dev[k] = eps[k] - tr;
+        nd += dev[k] * dev[k];
+    }
+    nd = sqrtf(nd);
+    const float lim = 0.816496580927726f * sigma_y; // sqrt(2/3)
+    if (!(2.0f * mu * nd > lim)) return false;
+    const float scale = lim / (2.0f * mu * nd);
+    float d[3];
+#pragma unroll
+    for (int k = 0; k < 3; k++) d[k] = expm1f((scale - 1.0f) * dev[k]);
+    float Mm[9]; // M - I
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) Mm[3 * i + j] = V[3 * i] * d[0] * V[3 * j] + V[3 * i + 1] * d[1] * V[3 * j + 1] +
+                                                    V[3 * i + 2] * d[2] * V[3 * j + 2];
+    float Gn[9], Kn[9];
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            float g = G[3 * i + j] + Mm[3 * i + j], k = K[3 * i + j] + Mm[3 * i + j];
+#pragma unroll
+            for (int m = 0; m < 3; m++) {
+                g += G[3 * i + m] * Mm[3 * m + j];
+                k += K[3 * i + m] * Mm[3 * m + j];
+            }
+            Gn[3 * i + j] = g;
+            Kn[3 * i + j] = k;
+        }
+#pragma unroll
+    for (int a = 0; a < 9; a++) {
+        G[a] = Gn[a];
+        K[a] = Kn[a];
+    }
+    return true;
+}
+

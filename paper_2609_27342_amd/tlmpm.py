@@ -32,6 +32,7 @@ class SceneDesc(C.Structure):
         ("G_c", C.c_float), ("zeta", C.c_float), ("u_min", C.c_float),
         ("max_cuts", C.c_int32), ("single_field", C.c_int32), ("slot_capacity", C.c_int32),
         ("material", C.c_int32), ("viscosity", C.c_float), ("yield_stress", C.c_float),
+        ("stencil", C.c_int32),
     ]
 
 
@@ -243,6 +244,7 @@ def make_desc(scene, keep):
     d.material = int(p.get("material", 0))
     d.viscosity = float(p.get("viscosity", 0.0))
     d.yield_stress = float(p.get("yield_stress", 0.0))
+    d.stencil = int(p.get("stencil", 0))
     return d
 
 

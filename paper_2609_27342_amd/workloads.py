@@ -518,5 +518,13 @@ def thrown_knives(dx=0.002, block=(0.12, 0.04, 0.04), seed=11, dt=1e-4, interval
     return sc
 
 
+def quadratic(scene):
+    """The same scene on the 27-node quadratic B-spline stencil (reading R33)."""
+    scene["params"] = dict(scene["params"], stencil=1)
+    scene["name"] = scene.get("name", "") + "-quad"
+    return scene
+
+
 CONFIGS = {"small": small, "small-deep": lambda **k: small(deep=True, **k), "medium": medium,
+           "medium-quad": lambda **k: quadratic(medium(**k)), "large-quad": lambda **k: quadratic(large(**k)),
            "large": large}

@@ -42,6 +42,24 @@ def test_footprint_and_validation_without_gpu():
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_quadratic_stencil_validation_without_gpu():
+    """The 27-node stencil needs half a cell of grid around every particle; other
+    stencil values are refused."""
+    from paper_2609_27342_amd import tlmpm, workloads as W
+    s = W.small()
+    q = dict(s, params=dict(s["params"], stencil=1))
+    assert tlmpm.footprint(q) > tlmpm.footprint(s)
+    X = s["X"].copy()
+    X[0, 0] = s["params"]["origin"][0] + 0.3 * s["params"]["dx"]
+    with pytest.raises(tlmpm.TlmpmError) as e:
+        tlmpm.footprint(dict(q, X=X))
+    assert e.value.code == tlmpm.E_INVALID
+    tlmpm.footprint(dict(s, X=X))  # the trilinear stencil accepts it
+    with pytest.raises(tlmpm.TlmpmError):
+        tlmpm.footprint(dict(s, params=dict(s["params"], stencil=2)))
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
 def test_batch_validation_without_gpu():
     """Empty or null member lists are refused before any device call."""
     L = ctypes.CDLL(LIB)
