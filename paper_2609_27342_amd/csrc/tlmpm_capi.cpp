@@ -197,7 +197,7 @@ Dims dims_of(const tlmpm_scene_desc* d)
 struct Offsets {
     size_t X, u, v, H, code, code_prev, D, perm, E, m, V0, cell_start, active, cnt0, cnt1, sc0, sc1, p2g, rs, hist,
         aabb, wpart, Fdot, Gp, wacc, Jmat, Jrig, brig, bmixed, ccode, ckeys, gmeta, gperm, bround, tools, tinfo, ctr, bact, status, dirty, bdirty, pcell, cand_idx, coff, cmask, cstatic, bcand, hbin, hmax, bcount, bids, crec, htab, hnext, ph_n, ph_q, ph_u,
-        qcode, qacc, qrs, qnodes, total;
+        qcode, qacc, qrs, qnodes, qround, qmap, total;
     uint32_t hmask;
 };
 
@@ -213,6 +213,40 @@ bool cell_of(const tlmpm_scene_desc* d, long long p, int c[3])
         c[a] = (int)fl;
     }
     return true;
+}
+
+// Lane map of the quadratic stencil: particle p goes to thread h * 64 + l of its
+// brick's workgroup, l its cell slot in the brick (sorted order), h its half pattern
+// (bit a set when floor(q_a - 1/2) = floor(q_a), q = (X - origin)/dx: the upper half
+// of the cell along axis a, the same FP64 formula as the oracle's stencil); a cell
+// with several particles of one pattern gives them successive rounds.  Fills
+// lane[p] = h * 64 + l and round[p] when asked; returns the rounds of each brick
+// (indexed by brick id, 0 for empty bricks).
+std::vector<int> quad_rounds(const tlmpm_scene_desc* d, std::vector<int>* lane, std::vector<int>* round)
+{
+    Dims g = dims_of(d);
+    std::vector<int> rounds((size_t)g.n_bricks, 0);
+    std::vector<uint16_t> cnt((size_t)g.n_bricks * 512, 0);
+    if (lane) lane->assign((size_t)g.N, -1);
+    if (round) round->assign((size_t)g.N, 0);
+    for (long long p = 0; p < g.N; p++) {
+        int c[3], h = 0;
+        if (!cell_of(d, p, c)) continue;
+        for (int a = 0; a < 3; a++) {
+            const double q = ((double)d->X[3 * p + a] - d->origin[a]) / d->dx;
+            if (std::floor(q - 0.5) == std::floor(q)) h |= 1 << a;
+        }
+        const long long brick = ((long long)(c[2] >> 2) * g.cby + (c[1] >> 2)) * g.cbx + (c[0] >> 2);
+        const int lx = c[0] & 3, ly = c[1] & 3, lz = c[2] & 3;
+        const int w = (lx & 1) | ((ly & 1) << 1) | ((lz & 1) << 2);
+        const int i = (lx >> 1) | ((ly >> 1) << 1) | ((lz >> 1) << 2);
+        const int l = w * 8 + i, slot = h * 64 + l;
+        const int r = cnt[(size_t)brick * 512 + slot]++;
+        rounds[(size_t)brick] = std::max(rounds[(size_t)brick], r + 1);
+        if (lane) (*lane)[(size_t)p] = slot;
+        if (round) (*round)[(size_t)p] = r;
+    }
+    return rounds;
 }
 
 // number of bricks that hold a particle
@@ -310,6 +344,10 @@ Offsets plan(const tlmpm_scene_desc* d, long long n_active)
         o.qacc = L.take((size_t)g.NN * scap * 8 * f);
         o.qrs = L.take((size_t)g.NN * scap * 4 * f);
         o.qnodes = L.take((size_t)std::min<long long>(g.NN, n_active * 343) * 4);
+        long long total = 0;
+        for (int r : quad_rounds(d, nullptr, nullptr)) total += r;
+        o.qround = L.take(((size_t)n_active + 1) * 4);
+        o.qmap = L.take((size_t)total * TL_WG * 4);
     }
     o.total = L.take(0) + 256;
     return o;
@@ -586,6 +624,8 @@ extern "C" tlmpm_status tlmpm_create_scene(const tlmpm_scene_desc* d, void* ws, 
         for (long long i = 0; i < g.NN; i++)
             if (mark[(size_t)i]) qnodes.push_back((int)i);
         D.n_qnodes = (int)qnodes.size();
+        D.qround = (int*)(base + o.qround);
+        D.qmap = (int*)(base + o.qmap);
     }
 
     // sorted SoA host staging
@@ -631,7 +671,24 @@ extern "C" tlmpm_status tlmpm_create_scene(const tlmpm_scene_desc* d, void* ws, 
         return bail(e, "upload bricks");
     if ((e = hipMemcpyAsync(D.bact, bact.data(), bact.size() * 4, hipMemcpyHostToDevice, sc->st)) != hipSuccess)
         return bail(e, "upload brick index");
+    std::vector<int> qround, qmap;
     if (d->stencil == 1) {
+        std::vector<int> lane, round;
+        const std::vector<int> rounds = quad_rounds(d, &lane, &round);
+        qround.assign(active.size() + 1, 0);
+        for (size_t b = 0; b < active.size(); b++) qround[b + 1] = qround[b] + rounds[(size_t)active[b]];
+        qmap.assign((size_t)qround.back() * TL_WG, -1);
+        for (long long q = 0; q < N; q++) { // q: device (sorted) index
+            const long long p = perm[(size_t)q];
+            const int b = bact[(size_t)(key[(size_t)p] / TL_CELLS)];
+            qmap[((size_t)qround[(size_t)b] + round[(size_t)p]) * TL_WG + lane[(size_t)p]] = (int)q;
+        }
+        if ((e = hipMemcpyAsync(D.qround, qround.data(), qround.size() * 4, hipMemcpyHostToDevice, sc->st)) !=
+            hipSuccess)
+            return bail(e, "upload lane map");
+        if (!qmap.empty() &&
+            (e = hipMemcpyAsync(D.qmap, qmap.data(), qmap.size() * 4, hipMemcpyHostToDevice, sc->st)) != hipSuccess)
+            return bail(e, "upload lane map");
         if (!qnodes.empty() && (e = hipMemcpyAsync(D.qnodes, qnodes.data(), qnodes.size() * 4, hipMemcpyHostToDevice,
                                                    sc->st)) != hipSuccess)
             return bail(e, "upload stencil nodes");

@@ -167,6 +167,8 @@ struct SceneD {
     float* qrs;         // [NN][scap][4] re-scatter sums of m v^{n+1}; after the remap v~
     int* qnodes;        // nodes of the 7x7x7 boxes of the active bricks (ascending)
     int n_qnodes;
+    int* qround;        // [active bricks + 1] first lane-map round of each brick
+    int* qmap;          // [rounds][512] particle of thread h * 64 + l: cell slot l, half pattern h (-1: none)
 };
 
 // Workgroups are dealt to the 8 XCDs (each with its own L2) round-robin by

@@ -9,10 +9,18 @@
 //
 // Logical grids (Sec. III-D) are slots of a per-node table of side keys, built each
 // substep from the keys that reach the node: two tables alternate by substep
-// parity, the table of one substep cleared during the next.  Sums go first into
-// LDS, per brick, side key and box node (floating-point atomics), then once per
-// (node, slot) into HBM (floating-point atomics): results agree with the fixed-
-// order trilinear path to rounding but are not bitwise reproducible.
+// parity, the table of one substep cleared during the next.
+//
+// Lanes.  Thread h * 64 + l of a brick workgroup holds, in each round, a particle
+// of the brick's cell l whose position inside the cell has half pattern h (bit a
+// set: upper half along axis a); the host builds this map once (reference
+// positions do not move), with more rounds where a cell holds two particles of
+// one pattern.  A wave's particles then lie in distinct cells with one pattern, so
+// their base nodes, and the nodes of any one stencil offset, are distinct: the
+// waves take turns adding into the brick's LDS box sums with plain
+// read-modify-writes, no atomics.  The box sums go once per (node, slot) into HBM
+// with floating-point atomics (up to 8 bricks share a node): results agree with
+// the fixed-order trilinear path to rounding but are not bitwise reproducible.
 #include <hip/hip_runtime.h>
 #include <hip/amd_detail/amd_hip_unsafe_atomics.h>
 #include <math.h>
@@ -41,19 +49,18 @@ DEV long long q_box_gid(const SceneK& S, int bx, int by, int bz, int bn)
     return q_gid(S, bx * TL_B - 1 + bn % TL_QBOX, by * TL_B - 1 + (bn / TL_QBOX) % TL_QBOX, bz * TL_B - 1 + bn / 49);
 }
 
-// grid cell of a particle from its cell slot (sorted order: brick, parity class, cell)
-DEV void q_cell(const SceneK& S, int cs, int c[3])
+// grid cell of cell slot l (0..63, sorted order: parity class, cell) of brick (bx, by, bz)
+DEV void q_cell(int bx, int by, int bz, int l, int c[3])
 {
-    const int brick = cs / TL_CELLS, r = cs % TL_CELLS, w = r >> 3, i = r & 7;
-    const int bx = brick % S.cbx, by = (brick / S.cbx) % S.cby, bz = brick / (S.cbx * S.cby);
+    const int w = l >> 3, i = l & 7;
     c[0] = bx * TL_B + 2 * (i & 1) + (w & 1);
     c[1] = by * TL_B + 2 * ((i >> 1) & 1) + ((w >> 1) & 1);
     c[2] = bz * TL_B + 2 * ((i >> 2) & 1) + ((w >> 2) & 1);
 }
 
-// Quadratic B-spline weights and derivatives per axis (reading R33).  The position
-// inside the particle's cell decides the base node (in FP64); f = q - base lies in
-// [1/2, 3/2) and the node distances are f, f - 1, f - 2:
+// Quadratic B-spline weights and derivatives per axis (reading R33).  The half of
+// the cell the particle lies in (decided once on the host, in FP64) gives the base
+// node; f = q - base lies in [1/2, 3/2) and the node distances are f, f - 1, f - 2:
 //   N = (3/2 - f)^2 / 2,  3/4 - (f - 1)^2,  (f - 1/2)^2 / 2.
 struct QStencil {
     int lo[3];        // base node per axis
@@ -61,14 +68,14 @@ struct QStencil {
     float g[3][3];    // derivative / dx
 };
 
-DEV void q_stencil(const SceneK& S, const float* X, const int c[3], QStencil& Q)
+DEV void q_stencil(const SceneK& S, const float* X, const int c[3], int h, QStencil& Q)
 {
     const double o[3] = {S.ox, S.oy, S.oz};
 #pragma unroll
     for (int a = 0; a < 3; a++) {
         double t = ((double)X[a] - o[a]) * S.inv_dx_d - (double)c[a];
         t = fmin(fmax(t, 0.0), 1.0);
-        const bool low = t < 0.5;
+        const bool low = ((h >> a) & 1) == 0; // the host's FP64 decision t < 1/2
         Q.lo[a] = low ? c[a] - 1 : c[a];
         const float f = (float)(low ? t + 1.0 : t);
         const float d0 = 1.5f - f, d1 = f - 1.0f, d2 = f - 0.5f;
@@ -129,10 +136,64 @@ DEV void q_couple(int c, const float* m, const uint32_t* codes, float (*f)[3])
         for (int j = 0; j < 3; j++) f[a][j] = out[a][j];
 }
 
-// particle handled by thread tid in chunk r of a brick's range: wave w takes
-// particle w of every run of 8, so that the lanes of a wave lie in different cells
-// (their LDS atomics rarely meet on one address)
-DEV int q_particle_index(int tid, int r) { return r * TL_QWG + (tid & 63) * 8 + (tid >> 6); }
+// particle of this thread in round r of active brick bi (-1: none)
+DEV int q_particle(const SceneD& D, int bi, int r)
+{
+    return D.qmap[(size_t)(D.qround[bi] + r) * TL_QWG + threadIdx.x];
+}
+
+DEV int q_rounds(const SceneD& D, int bi) { return D.qround[bi + 1] - D.qround[bi]; }
+
+// element i (0..2) of a 3-array by selects, so that a rolled loop keeps the array
+// in registers
+DEV float q_pick(const float (&a)[3], int i) { return i == 0 ? a[0] : (i == 1 ? a[1] : a[2]); }
+
+// index of a key already in the brick's LDS key list; -1 if absent
+DEV int q_key_lookup(const uint32_t* s_keys, uint32_t key)
+{
+    for (int k = 0; k < TL_SCAP_MAX; k++) {
+        const uint32_t c = s_keys[k];
+        if (c == key) return k;
+        if (c == TL_QEMPTY) return -1;
+    }
+    return -1;
+}
+
+// registers the side keys of a brick's particles in its LDS key list (call between
+// barriers)
+DEV void q_register_keys(const SceneK& S, const SceneD& D, int bi, uint32_t* s_keys)
+{
+    const int rounds = q_rounds(D, bi);
+    for (int r = 0; r < rounds; r++) {
+        const int p = q_particle(D, bi, r);
+        if (p < 0) continue;
+        if (q_key_index(s_keys, slot_key(S, D.code[p])) < 0) atomicOr(D.status, TL_ST_BOX);
+    }
+}
+
+// loads Q floats per node slot (from src, stride QS, offset off) for the first
+// TL_QK keys of the brick over its box into dst[key][box node][Q]; absent slots
+// read as zero
+template <int Q, int QS, int OFF>
+DEV void q_load_box(const SceneK& S, const uint32_t* tab, const float* src, int bx, int by, int bz,
+                    const uint32_t* s_keys, float* dst)
+{
+    for (int t = threadIdx.x; t < TL_QK * TL_QBOXN; t += TL_QWG) {
+        const uint32_t key = s_keys[t / TL_QBOXN];
+        if (key == TL_QEMPTY) continue;
+        const long long g = q_box_gid(S, bx, by, bz, t % TL_QBOXN);
+        const int s = g >= 0 ? q_find(S, tab, g, key) : -1;
+        float* o = dst + (size_t)t * Q;
+        if (s < 0) {
+#pragma unroll
+            for (int c = 0; c < Q; c++) o[c] = 0.0f;
+            continue;
+        }
+        const float* a = src + ((size_t)g * S.scap + s) * QS + OFF;
+#pragma unroll
+        for (int c = 0; c < Q; c++) o[c] = a[c];
+    }
+}
 
 // ------------------------------------------------------------------ slot tables
 // Per active brick: clears the other parity's table over its box, then inserts the
@@ -160,24 +221,22 @@ __global__ __launch_bounds__(TL_QWG) void k_q_slots(SceneK S, SceneD D, int par)
     }
     if (tid < TL_SCAP_MAX) s_keys[tid] = TL_QEMPTY;
     __syncthreads();
-    const int beg = D.cell_start[(long long)brick * TL_CELLS], end = D.cell_start[(long long)brick * TL_CELLS + TL_CELLS];
-    const int n = end - beg;
     const long long N = S.N;
-    for (int r = 0; r * TL_QWG < n; r++) {
-        const int idx = q_particle_index(tid, r);
-        if (idx >= n) continue;
-        const int p = beg + idx;
+    const int rounds = q_rounds(D, bi), h = tid >> 6;
+    int c[3];
+    q_cell(bx, by, bz, tid & 63, c);
+    for (int r = 0; r < rounds; r++) {
+        const int p = q_particle(D, bi, r);
+        if (p < 0) continue;
         const uint32_t key = slot_key(S, D.code[p]);
         const int k = q_key_index(s_keys, key);
         if (k < 0) {
             atomicOr(D.status, TL_ST_BOX);
             continue;
         }
-        int c[3];
-        q_cell(S, D.pcell[p], c);
         const float X[3] = {D.X[p], D.X[N + p], D.X[2 * N + p]};
         QStencil Q;
-        q_stencil(S, X, c, Q);
+        q_stencil(S, X, c, h, Q);
         const int ox = Q.lo[0] - (bx * TL_B - 1), oy = Q.lo[1] - (by * TL_B - 1), oz = Q.lo[2] - (bz * TL_B - 1);
 #pragma unroll
         for (int cz = 0; cz < 3; cz++)
@@ -263,134 +322,160 @@ __global__ __launch_bounds__(TL_QWG) void k_q_p2g(SceneK S, SceneD D, int par)
     for (int t = tid; t < TL_QK * TL_QBOXN * 7; t += TL_QWG) s_acc[t] = 0.0f;
     if (tid < TL_SCAP_MAX) s_keys[tid] = TL_QEMPTY;
     __syncthreads();
-    const int beg = D.cell_start[(long long)brick * TL_CELLS], end = D.cell_start[(long long)brick * TL_CELLS + TL_CELLS];
-    const int n = end - beg;
     const long long N = S.N;
     const float dt = S.dt;
     const bool rig = (S.floor_on || D.tinfo[1]) && D.brig[brick] != 0;
-    for (int r = 0; r * TL_QWG < n; r++) {
-        const int idx = q_particle_index(tid, r);
-        if (idx >= n) continue;
-        const int p = beg + idx;
-        const uint32_t code = D.code[p];
-        const uint32_t key = slot_key(S, code);
-        const int k = q_key_index(s_keys, key);
-        if (k < 0) {
-            atomicOr(D.status, TL_ST_BOX);
-            continue;
+    const int rounds = q_rounds(D, bi), h = tid >> 6;
+    int c[3];
+    q_cell(bx, by, bz, tid & 63, c);
+    for (int r = 0; r < rounds; r++) {
+        const int p = q_particle(D, bi, r);
+        bool valid = p >= 0;
+        int k = -1;
+        uint32_t key = 0;
+        float m = 0.0f, vel[3] = {0.0f, 0.0f, 0.0f}, ext[3] = {0.0f, 0.0f, 0.0f};
+        float Pk[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        QStencil Q = {};
+        if (valid) {
+            const uint32_t code = D.code[p];
+            key = slot_key(S, code);
+            k = q_key_index(s_keys, key);
+            if (k < 0) atomicOr(D.status, TL_ST_BOX);
+            valid = k >= 0;
         }
-        float H[9], vel[3];
-        const float X[3] = {D.X[p], D.X[N + p], D.X[2 * N + p]};
+        if (valid) {
+            float H[9];
+            const uint32_t code = D.code[p];
+            const float X[3] = {D.X[p], D.X[N + p], D.X[2 * N + p]};
 #pragma unroll
-        for (int a = 0; a < 9; a++) H[a] = D.H[a * N + p];
+            for (int a = 0; a < 9; a++) H[a] = D.H[a * N + p];
 #pragma unroll
-        for (int a = 0; a < 3; a++) vel[a] = D.v[a * N + p];
-        const float m = S.m_uniform ? S.m0 : D.m[p];
-        const float V0 = S.v_uniform ? S.V0 : D.V0[p];
-        const float E = S.e_uniform ? S.E0 : D.E[p];
-        float Pk[9];
-        bool ok;
-        if constexpr (MAT == 1) {
-            if (S.ystress > 0.0f) {
-                // P = P_fcr(F_e) F_p^{-T}, F_e - I = H + Gp + H Gp, F_p^{-1} = I + Gp
-                float Gp[9], K[9], Pe[9];
+            for (int a = 0; a < 3; a++) vel[a] = D.v[a * N + p];
+            m = S.m_uniform ? S.m0 : D.m[p];
+            const float V0 = S.v_uniform ? S.V0 : D.V0[p];
+            const float E = S.e_uniform ? S.E0 : D.E[p];
+            bool ok;
+            if constexpr (MAT == 1) {
+                if (S.ystress > 0.0f) {
+                    // P = P_fcr(F_e) F_p^{-T}, F_e - I = H + Gp + H Gp, F_p^{-1} = I + Gp
+                    float Gp[9], K[9], Pe[9];
 #pragma unroll
-                for (int a = 0; a < 9; a++) Gp[a] = D.Gp[a * N + p];
+                    for (int a = 0; a < 9; a++) Gp[a] = D.Gp[a * N + p];
 #pragma unroll
-                for (int i = 0; i < 3; i++)
+                    for (int i = 0; i < 3; i++)
 #pragma unroll
-                    for (int j = 0; j < 3; j++) {
-                        float kk = H[3 * i + j] + Gp[3 * i + j];
+                        for (int j = 0; j < 3; j++) {
+                            float kk = H[3 * i + j] + Gp[3 * i + j];
 #pragma unroll
-                        for (int l = 0; l < 3; l++) kk += H[3 * i + l] * Gp[3 * l + j];
-                        K[3 * i + j] = kk;
-                    }
-                ok = fixed_corotated(E, S.nu, K, Pe);
-#pragma unroll
-                for (int i = 0; i < 3; i++)
-#pragma unroll
-                    for (int j = 0; j < 3; j++) {
-                        float a = Pe[3 * i + j];
-#pragma unroll
-                        for (int l = 0; l < 3; l++) a += Pe[3 * i + l] * Gp[3 * j + l];
-                        Pk[3 * i + j] = a;
-                    }
-            } else {
-                ok = S.material == 1 ? fixed_corotated(E, S.nu, H, Pk) : neo_hookean(E, S.nu, H, Pk);
-            }
-            if (ok && S.visc > 0.0f) {
-                float Fd[9];
-#pragma unroll
-                for (int a = 0; a < 9; a++) Fd[a] = D.Fdot[a * N + p];
-                add_viscous(S.visc, H, Fd, Pk);
-            }
-        } else {
-            ok = neo_hookean(E, S.nu, H, Pk);
-        }
-        if (!ok) {
-            atomicOr(D.status, TL_ST_NONFINITE);
-#pragma unroll
-            for (int a = 0; a < 9; a++) Pk[a] = 0.0f;
-        }
-        float Jc[3] = {0.0f, 0.0f, 0.0f};
-        if (rig) {
-            Jc[0] += D.Jrig[p];
-            Jc[1] += D.Jrig[N + p];
-            Jc[2] += D.Jrig[2 * N + p];
-        }
-        if (S.material_contact && (code & TL_CAND_BIT)) {
-            Jc[0] += D.Jmat[p];
-            Jc[1] += D.Jmat[N + p];
-            Jc[2] += D.Jmat[2 * N + p];
-        }
-        const float ext[3] = {Jc[0] + dt * m * S.gx, Jc[1] + dt * m * S.gy, Jc[2] + dt * m * S.gz};
-        const float sA = -dt * V0;
-#pragma unroll
-        for (int a = 0; a < 9; a++) Pk[a] *= sA;
-        int c[3];
-        q_cell(S, D.pcell[p], c);
-        QStencil Q;
-        q_stencil(S, X, c, Q);
-        const int ox = Q.lo[0] - (bx * TL_B - 1), oy = Q.lo[1] - (by * TL_B - 1), oz = Q.lo[2] - (bz * TL_B - 1);
-#pragma unroll
-        for (int cz = 0; cz < 3; cz++)
-#pragma unroll
-            for (int cy = 0; cy < 3; cy++) {
-                const float wyz = Q.w[1][cy] * Q.w[2][cz];
-#pragma unroll
-                for (int cx = 0; cx < 3; cx++) {
-                    const float w = Q.w[0][cx] * wyz;
-                    if (w == 0.0f) continue;
-                    const float g0 = Q.g[0][cx] * wyz;
-                    const float g1 = Q.w[0][cx] * Q.g[1][cy] * Q.w[2][cz];
-                    const float g2 = Q.w[0][cx] * Q.w[1][cy] * Q.g[2][cz];
-                    float val[7];
-                    val[0] = w * m;
-                    val[1] = val[0] * vel[0];
-                    val[2] = val[0] * vel[1];
-                    val[3] = val[0] * vel[2];
-#pragma unroll
-                    for (int a = 0; a < 3; a++) val[4 + a] = Pk[3 * a] * g0 + Pk[3 * a + 1] * g1 + Pk[3 * a + 2] * g2 + w * ext[a];
-                    const int bn = ((oz + cz) * TL_QBOX + oy + cy) * TL_QBOX + ox + cx;
-                    if (k < TL_QK) {
-                        float* d = s_acc + ((size_t)k * TL_QBOXN + bn) * 7;
-#pragma unroll
-                        for (int q = 0; q < 7; q++) atomicAdd(d + q, val[q]);
-                    } else {
-                        const long long g = q_box_gid(S, bx, by, bz, bn);
-                        const int s = g >= 0 ? q_find(S, tab, g, key) : -1;
-                        if (s < 0) {
-                            atomicOr(D.status, TL_ST_LOOKUP);
-                            continue;
+                            for (int l = 0; l < 3; l++) kk += H[3 * i + l] * Gp[3 * l + j];
+                            K[3 * i + j] = kk;
                         }
-                        float* o = D.qacc + ((size_t)g * S.scap + s) * 8;
+                    ok = fixed_corotated(E, S.nu, K, Pe);
 #pragma unroll
-                        for (int q = 0; q < 7; q++) unsafeAtomicAdd(o + q, val[q]);
-                    }
+                    for (int i = 0; i < 3; i++)
+#pragma unroll
+                        for (int j = 0; j < 3; j++) {
+                            float a = Pe[3 * i + j];
+#pragma unroll
+                            for (int l = 0; l < 3; l++) a += Pe[3 * i + l] * Gp[3 * j + l];
+                            Pk[3 * i + j] = a;
+                        }
+                } else {
+                    ok = S.material == 1 ? fixed_corotated(E, S.nu, H, Pk) : neo_hookean(E, S.nu, H, Pk);
                 }
+                if (ok && S.visc > 0.0f) {
+                    float Fd[9];
+#pragma unroll
+                    for (int a = 0; a < 9; a++) Fd[a] = D.Fdot[a * N + p];
+                    add_viscous(S.visc, H, Fd, Pk);
+                }
+            } else {
+                ok = neo_hookean(E, S.nu, H, Pk);
             }
+            if (!ok) {
+                atomicOr(D.status, TL_ST_NONFINITE);
+#pragma unroll
+                for (int a = 0; a < 9; a++) Pk[a] = 0.0f;
+            }
+            float Jc[3] = {0.0f, 0.0f, 0.0f};
+            if (rig) {
+                Jc[0] += D.Jrig[p];
+                Jc[1] += D.Jrig[N + p];
+                Jc[2] += D.Jrig[2 * N + p];
+            }
+            if (S.material_contact && (code & TL_CAND_BIT)) {
+                Jc[0] += D.Jmat[p];
+                Jc[1] += D.Jmat[N + p];
+                Jc[2] += D.Jmat[2 * N + p];
+            }
+#pragma unroll
+            for (int a = 0; a < 3; a++) ext[a] = Jc[a] + dt * m * (a == 0 ? S.gx : a == 1 ? S.gy : S.gz);
+            const float sA = -dt * V0;
+#pragma unroll
+            for (int a = 0; a < 9; a++) Pk[a] *= sA;
+            q_stencil(S, X, c, h, Q);
+        }
+        const int ox = Q.lo[0] - (bx * TL_B - 1), oy = Q.lo[1] - (by * TL_B - 1), oz = Q.lo[2] - (bz * TL_B - 1);
+        // the 7 sums of node (cx, cy, cz): m, m v, and the impulse A grad N + w ext
+        auto node_vals = [&](int cx, int cy, int cz, float* val) {
+            const float wx = q_pick(Q.w[0], cx), wy = q_pick(Q.w[1], cy), wz = q_pick(Q.w[2], cz);
+            const float w = wx * wy * wz;
+            const float g0 = q_pick(Q.g[0], cx) * wy * wz;
+            const float g1 = wx * q_pick(Q.g[1], cy) * wz;
+            const float g2 = wx * wy * q_pick(Q.g[2], cz);
+            val[0] = w * m;
+            val[1] = val[0] * vel[0];
+            val[2] = val[0] * vel[1];
+            val[3] = val[0] * vel[2];
+#pragma unroll
+            for (int a = 0; a < 3; a++) val[4 + a] = Pk[3 * a] * g0 + Pk[3 * a + 1] * g1 + Pk[3 * a + 2] * g2 + w * ext[a];
+            return w != 0.0f; // reading R7: a zero weight contributes nothing
+        };
+        if (valid && k >= TL_QK) {
+            // more side keys in this brick than LDS holds: straight to the node slots
+#pragma unroll 1
+            for (int t = 0; t < 27; t++) {
+                const int cx = t % 3, cy = (t / 3) % 3, cz = t / 9;
+                float val[7];
+                if (!node_vals(cx, cy, cz, val)) continue;
+                const long long g = q_gid(S, Q.lo[0] + cx, Q.lo[1] + cy, Q.lo[2] + cz);
+                const int s = g >= 0 ? q_find(S, tab, g, key) : -1;
+                if (s < 0) {
+                    atomicOr(D.status, TL_ST_LOOKUP);
+                    continue;
+                }
+                float* o = D.qacc + ((size_t)g * S.scap + s) * 8;
+#pragma unroll
+                for (int q = 0; q < 7; q++) unsafeAtomicAdd(o + q, val[q]);
+            }
+        }
+        // the waves take turns: within one wave the nodes of a stencil offset are
+        // distinct, so plain read-modify-writes of the LDS sums do not collide
+        const bool fast = valid && k < TL_QK;
+        float* d0 = s_acc + (size_t)(fast ? k : 0) * TL_QBOXN * 7;
+        // wave h passes h barriers, adds its sums, then passes the other 8 - h
+        for (int t = 0; t < h; t++) lds_barrier();
+        {
+            if (fast) {
+#pragma unroll
+                for (int cz = 0; cz < 3; cz++)
+#pragma unroll
+                    for (int cy = 0; cy < 3; cy++)
+#pragma unroll
+                        for (int cx = 0; cx < 3; cx++) {
+                            float val[7];
+                            if (!node_vals(cx, cy, cz, val)) continue;
+                            float* d = d0 + (((oz + cz) * TL_QBOX + oy + cy) * TL_QBOX + ox + cx) * 7;
+#pragma unroll
+                            for (int q = 0; q < 7; q++) d[q] += val[q];
+                        }
+                    // one row of nodes at a time: keeps the compiler from hoisting all
+                    // 189 reads (and their registers) to the top
+                    asm volatile("" ::: "memory");
+            }
+        }
+        for (int t = h; t < TL_QWG / 64; t++) lds_barrier();
     }
-    __syncthreads();
     q_flush<7, 8>(S, D, tab, D.qacc, bx, by, bz, s_keys, s_acc);
 }
 
@@ -470,11 +555,13 @@ __global__ __launch_bounds__(256) void k_q_remap(SceneK S, SceneD D, int par)
 }
 
 // ---------------------------------------------------------------------------- G2P
-// Per active brick: PIC/FLIP update of v and x from the grid (Eq. 17), the MUSL
-// re-scatter of m_p v_p^{n+1}, and the brick's AABB and speed bound.
+// Per active brick: the box's grid velocities (v^n, dv) of its first TL_QK side
+// keys into LDS, PIC/FLIP update of v and x (Eq. 17), the MUSL re-scatter of
+// m_p v_p^{n+1}, and the brick's AABB and speed bound.
 __global__ __launch_bounds__(TL_QWG) void k_q_g2p(SceneK S, SceneD D, int par)
 {
     __shared__ uint32_t s_keys[TL_SCAP_MAX];
+    __shared__ float s_grid[TL_QK * TL_QBOXN * 6];
     __shared__ float s_acc[TL_QK * TL_QBOXN * 3];
     __shared__ float s_bb[TL_QWG / 64][7];
     const int bi = blockIdx.x, tid = threadIdx.x;
@@ -490,34 +577,57 @@ __global__ __launch_bounds__(TL_QWG) void k_q_g2p(SceneK S, SceneD D, int par)
     for (int t = tid; t < TL_QK * TL_QBOXN * 3; t += TL_QWG) s_acc[t] = 0.0f;
     if (tid < TL_SCAP_MAX) s_keys[tid] = TL_QEMPTY;
     __syncthreads();
-    const int beg = D.cell_start[(long long)brick * TL_CELLS], end = D.cell_start[(long long)brick * TL_CELLS + TL_CELLS];
-    const int n = end - beg;
+    q_register_keys(S, D, bi, s_keys);
+    __syncthreads();
+    q_load_box<6, 8, 1>(S, tab, D.qacc, bx, by, bz, s_keys, s_grid);
+    __syncthreads();
     const long long N = S.N;
     const float dt = S.dt, beta = S.beta;
+    const int rounds = q_rounds(D, bi), h = tid >> 6;
+    int c[3];
+    q_cell(bx, by, bz, tid & 63, c);
     float bb[7] = {1e30f, 1e30f, 1e30f, -1e30f, -1e30f, -1e30f, 0.0f};
-    for (int r = 0; r * TL_QWG < n; r++) {
-        const int idx = q_particle_index(tid, r);
-        if (idx >= n) continue;
-        const int p = beg + idx;
-        const uint32_t key = slot_key(S, D.code[p]);
-        const int k = q_key_index(s_keys, key);
-        if (k < 0) {
-            atomicOr(D.status, TL_ST_BOX);
-            continue;
+    for (int r = 0; r < rounds; r++) {
+        const int p = q_particle(D, bi, r);
+        int k = -1;
+        uint32_t key = 0;
+        if (p >= 0) {
+            key = slot_key(S, D.code[p]);
+            k = q_key_lookup(s_keys, key); // -1 was flagged when the keys were registered
         }
-        const float X[3] = {D.X[p], D.X[N + p], D.X[2 * N + p]};
-        int c[3];
-        q_cell(S, D.pcell[p], c);
-        QStencil Q;
-        q_stencil(S, X, c, Q);
-        float av[3] = {0.0f, 0.0f, 0.0f}, ax[3] = {0.0f, 0.0f, 0.0f};
+        const bool valid = k >= 0;
+        float m = 0.0f, vn1[3] = {0.0f, 0.0f, 0.0f};
+        QStencil Q = {};
+        if (valid) {
+            const float X[3] = {D.X[p], D.X[N + p], D.X[2 * N + p]};
+            q_stencil(S, X, c, h, Q);
+            float av[3] = {0.0f, 0.0f, 0.0f}, ax[3] = {0.0f, 0.0f, 0.0f};
+            auto add_node = [&](float w, const float* vn, const float* dv) {
 #pragma unroll
-        for (int cz = 0; cz < 3; cz++)
+                for (int j = 0; j < 3; j++) {
+                    av[j] += w * ((1.0f - beta) * vn[j] + dv[j]);
+                    ax[j] += w * (vn[j] + dv[j]);
+                }
+            };
+            if (k < TL_QK) {
+                const int ox = Q.lo[0] - (bx * TL_B - 1), oy = Q.lo[1] - (by * TL_B - 1), oz = Q.lo[2] - (bz * TL_B - 1);
+                const float* g0 = s_grid + (size_t)k * TL_QBOXN * 6;
 #pragma unroll
-            for (int cy = 0; cy < 3; cy++)
+                for (int cz = 0; cz < 3; cz++)
 #pragma unroll
-                for (int cx = 0; cx < 3; cx++) {
-                    const float w = Q.w[0][cx] * Q.w[1][cy] * Q.w[2][cz];
+                    for (int cy = 0; cy < 3; cy++)
+#pragma unroll
+                        for (int cx = 0; cx < 3; cx++) {
+                            const float w = Q.w[0][cx] * Q.w[1][cy] * Q.w[2][cz];
+                            if (w == 0.0f) continue;
+                            const float* a = g0 + (((oz + cz) * TL_QBOX + oy + cy) * TL_QBOX + ox + cx) * 6;
+                            add_node(w, a, a + 3);
+                        }
+            } else {
+#pragma unroll 1
+                for (int t = 0; t < 27; t++) {
+                    const int cx = t % 3, cy = (t / 3) % 3, cz = t / 9;
+                    const float w = q_pick(Q.w[0], cx) * q_pick(Q.w[1], cy) * q_pick(Q.w[2], cz);
                     if (w == 0.0f) continue;
                     const long long g = q_gid(S, Q.lo[0] + cx, Q.lo[1] + cy, Q.lo[2] + cz);
                     const int s = g >= 0 ? q_find(S, tab, g, key) : -1;
@@ -526,53 +636,63 @@ __global__ __launch_bounds__(TL_QWG) void k_q_g2p(SceneK S, SceneD D, int par)
                         continue;
                     }
                     const float* a = D.qacc + ((size_t)g * S.scap + s) * 8;
-                    const float4 a0 = *(const float4*)a, a1 = *(const float4*)(a + 4);
-                    const float vn[3] = {a0.y, a0.z, a0.w}, dv[3] = {a1.x, a1.y, a1.z};
-#pragma unroll
-                    for (int j = 0; j < 3; j++) {
-                        av[j] += w * ((1.0f - beta) * vn[j] + dv[j]);
-                        ax[j] += w * (vn[j] + dv[j]);
-                    }
+                    add_node(w, a + 1, a + 4);
                 }
-        float vn1[3];
+            }
 #pragma unroll
-        for (int j = 0; j < 3; j++) {
-            vn1[j] = beta * D.v[j * N + p] + av[j];
-            const float un = D.u[j * N + p] + dt * ax[j];
-            D.v[j * N + p] = vn1[j];
-            D.u[j * N + p] = un;
-            const float xa = X[j] + un;
-            bb[j] = fminf(bb[j], xa);
-            bb[3 + j] = fmaxf(bb[3 + j], xa);
+            for (int j = 0; j < 3; j++) {
+                vn1[j] = beta * D.v[j * N + p] + av[j];
+                const float un = D.u[j * N + p] + dt * ax[j];
+                D.v[j * N + p] = vn1[j];
+                D.u[j * N + p] = un;
+                const float xa = X[j] + un;
+                bb[j] = fminf(bb[j], xa);
+                bb[3 + j] = fmaxf(bb[3 + j], xa);
+            }
+            bb[6] = fmaxf(bb[6], sqrtf(vn1[0] * vn1[0] + vn1[1] * vn1[1] + vn1[2] * vn1[2]));
+            m = S.m_uniform ? S.m0 : D.m[p];
         }
-        bb[6] = fmaxf(bb[6], sqrtf(vn1[0] * vn1[0] + vn1[1] * vn1[1] + vn1[2] * vn1[2]));
-        const float m = S.m_uniform ? S.m0 : D.m[p];
-        const int ox = Q.lo[0] - (bx * TL_B - 1), oy = Q.lo[1] - (by * TL_B - 1), oz = Q.lo[2] - (bz * TL_B - 1);
-#pragma unroll
-        for (int cz = 0; cz < 3; cz++)
-#pragma unroll
-            for (int cy = 0; cy < 3; cy++)
-#pragma unroll
-                for (int cx = 0; cx < 3; cx++) {
-                    const float wm = Q.w[0][cx] * Q.w[1][cy] * Q.w[2][cz] * m;
-                    if (wm == 0.0f) continue;
-                    const int bn = ((oz + cz) * TL_QBOX + oy + cy) * TL_QBOX + ox + cx;
-                    if (k < TL_QK) {
-                        float* d = s_acc + ((size_t)k * TL_QBOXN + bn) * 3;
-#pragma unroll
-                        for (int j = 0; j < 3; j++) atomicAdd(d + j, wm * vn1[j]);
-                    } else {
-                        const long long g = q_box_gid(S, bx, by, bz, bn);
-                        const int s = g >= 0 ? q_find(S, tab, g, key) : -1;
-                        if (s < 0) {
-                            atomicOr(D.status, TL_ST_LOOKUP);
-                            continue;
-                        }
-                        float* o = D.qrs + ((size_t)g * S.scap + s) * 4;
-#pragma unroll
-                        for (int j = 0; j < 3; j++) unsafeAtomicAdd(o + j, wm * vn1[j]);
-                    }
+        if (valid && k >= TL_QK) {
+#pragma unroll 1
+            for (int t = 0; t < 27; t++) {
+                const int cx = t % 3, cy = (t / 3) % 3, cz = t / 9;
+                const float wm = q_pick(Q.w[0], cx) * q_pick(Q.w[1], cy) * q_pick(Q.w[2], cz) * m;
+                if (wm == 0.0f) continue;
+                const long long g = q_gid(S, Q.lo[0] + cx, Q.lo[1] + cy, Q.lo[2] + cz);
+                const int s = g >= 0 ? q_find(S, tab, g, key) : -1;
+                if (s < 0) {
+                    atomicOr(D.status, TL_ST_LOOKUP);
+                    continue;
                 }
+                float* o = D.qrs + ((size_t)g * S.scap + s) * 4;
+#pragma unroll
+                for (int j = 0; j < 3; j++) unsafeAtomicAdd(o + j, wm * vn1[j]);
+            }
+        }
+        // MUSL re-scatter of m v^{n+1}: the waves take turns (see the P2G)
+        const bool fast = valid && k < TL_QK;
+        const int ox = Q.lo[0] - (bx * TL_B - 1), oy = Q.lo[1] - (by * TL_B - 1), oz = Q.lo[2] - (bz * TL_B - 1);
+        float* d0 = s_acc + (size_t)(fast ? k : 0) * TL_QBOXN * 3;
+        // wave h passes h barriers, adds its sums, then passes the other 8 - h
+        for (int t = 0; t < h; t++) lds_barrier();
+        {
+            if (fast) {
+#pragma unroll
+                for (int cz = 0; cz < 3; cz++)
+#pragma unroll
+                    for (int cy = 0; cy < 3; cy++)
+#pragma unroll
+                        for (int cx = 0; cx < 3; cx++) {
+                            const float wm = Q.w[0][cx] * Q.w[1][cy] * Q.w[2][cz] * m;
+                            if (wm == 0.0f) continue;
+                            float* d = d0 + (((oz + cz) * TL_QBOX + oy + cy) * TL_QBOX + ox + cx) * 3;
+#pragma unroll
+                            for (int j = 0; j < 3; j++) d[j] += wm * vn1[j];
+                        }
+                    asm volatile("" ::: "memory");
+            }
+        }
+        for (int t = h; t < TL_QWG / 64; t++) lds_barrier();
     }
     // brick AABB of x^{n+1} and speed bound (used to skip distant contact work)
     const int lane = tid & 63, wv = tid >> 6;
@@ -596,79 +716,108 @@ __global__ __launch_bounds__(TL_QWG) void k_q_g2p(SceneK S, SceneD D, int par)
 }
 
 // --------------------------------------------------------------- F update (MUSL)
-// Per particle: F += dt sum_i v~_i (x) grad N_i with the particle's own slots; the
+// Per active brick: the box's remapped velocities of its first TL_QK side keys into
+// LDS, then per particle F += dt sum_i v~_i (x) grad N_i with its own slots; the
 // rate is kept for viscosity and the plastic projection follows (MAT 1).
 template <int MAT>
-__global__ __launch_bounds__(256) void k_q_F(SceneK S, SceneD D, int par)
+__global__ __launch_bounds__(TL_QWG) void k_q_F(SceneK S, SceneD D, int par)
 {
-    const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
-    const long long N = S.N;
-    if (p >= N) return;
+    __shared__ uint32_t s_keys[TL_SCAP_MAX];
+    __shared__ float s_vt[TL_QK * TL_QBOXN * 3];
+    const int bi = blockIdx.x, tid = threadIdx.x;
+    const int brick = D.active[bi];
+    const int bx = brick % S.cbx, by = (brick / S.cbx) % S.cby, bz = brick / (S.cbx * S.cby);
     const uint32_t* tab = q_table(S, D, par);
-    const uint32_t key = slot_key(S, D.code[p]);
-    const float X[3] = {D.X[p], D.X[N + p], D.X[2 * N + p]};
+    if (tid < TL_SCAP_MAX) s_keys[tid] = TL_QEMPTY;
+    __syncthreads();
+    q_register_keys(S, D, bi, s_keys);
+    __syncthreads();
+    q_load_box<3, 4, 0>(S, tab, D.qrs, bx, by, bz, s_keys, s_vt);
+    __syncthreads();
+    const long long N = S.N;
+    const float dt = S.dt;
+    const int rounds = q_rounds(D, bi), h = tid >> 6;
     int c[3];
-    q_cell(S, D.pcell[p], c);
-    QStencil Q;
-    q_stencil(S, X, c, Q);
-    float Lg[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    q_cell(bx, by, bz, tid & 63, c);
+    for (int r = 0; r < rounds; r++) {
+        const int p = q_particle(D, bi, r);
+        if (p < 0) continue;
+        const uint32_t key = slot_key(S, D.code[p]);
+        const int k = q_key_lookup(s_keys, key);
+        if (k < 0) continue;
+        const float X[3] = {D.X[p], D.X[N + p], D.X[2 * N + p]};
+        QStencil Q;
+        q_stencil(S, X, c, h, Q);
+        float Lg[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        auto add_node = [&](float g0, float g1, float g2, const float* v) {
 #pragma unroll
-    for (int cz = 0; cz < 3; cz++)
+            for (int a = 0; a < 3; a++) {
+                Lg[3 * a + 0] += v[a] * g0;
+                Lg[3 * a + 1] += v[a] * g1;
+                Lg[3 * a + 2] += v[a] * g2;
+            }
+        };
+        if (k < TL_QK) {
+            const int ox = Q.lo[0] - (bx * TL_B - 1), oy = Q.lo[1] - (by * TL_B - 1), oz = Q.lo[2] - (bz * TL_B - 1);
+            const float* v0 = s_vt + (size_t)k * TL_QBOXN * 3;
 #pragma unroll
-        for (int cy = 0; cy < 3; cy++)
+            for (int cz = 0; cz < 3; cz++)
 #pragma unroll
-            for (int cx = 0; cx < 3; cx++) {
-                const float w = Q.w[0][cx] * Q.w[1][cy] * Q.w[2][cz];
-                if (w == 0.0f) continue;
+                for (int cy = 0; cy < 3; cy++)
+#pragma unroll
+                    for (int cx = 0; cx < 3; cx++) {
+                        if (Q.w[0][cx] * Q.w[1][cy] * Q.w[2][cz] == 0.0f) continue;
+                        add_node(Q.g[0][cx] * Q.w[1][cy] * Q.w[2][cz], Q.w[0][cx] * Q.g[1][cy] * Q.w[2][cz],
+                                 Q.w[0][cx] * Q.w[1][cy] * Q.g[2][cz],
+                                 v0 + (((oz + cz) * TL_QBOX + oy + cy) * TL_QBOX + ox + cx) * 3);
+                    }
+        } else {
+#pragma unroll 1
+            for (int t = 0; t < 27; t++) {
+                const int cx = t % 3, cy = (t / 3) % 3, cz = t / 9;
+                const float wx = q_pick(Q.w[0], cx), wy = q_pick(Q.w[1], cy), wz = q_pick(Q.w[2], cz);
+                if (wx * wy * wz == 0.0f) continue;
                 const long long g = q_gid(S, Q.lo[0] + cx, Q.lo[1] + cy, Q.lo[2] + cz);
                 const int s = g >= 0 ? q_find(S, tab, g, key) : -1;
                 if (s < 0) {
                     atomicOr(D.status, TL_ST_LOOKUP);
                     continue;
                 }
-                const float4 vt = *(const float4*)(D.qrs + ((size_t)g * S.scap + s) * 4);
-                const float g0 = Q.g[0][cx] * Q.w[1][cy] * Q.w[2][cz];
-                const float g1 = Q.w[0][cx] * Q.g[1][cy] * Q.w[2][cz];
-                const float g2 = Q.w[0][cx] * Q.w[1][cy] * Q.g[2][cz];
-                const float v[3] = {vt.x, vt.y, vt.z};
-#pragma unroll
-                for (int a = 0; a < 3; a++) {
-                    Lg[3 * a + 0] += v[a] * g0;
-                    Lg[3 * a + 1] += v[a] * g1;
-                    Lg[3 * a + 2] += v[a] * g2;
-                }
+                add_node(q_pick(Q.g[0], cx) * wy * wz, wx * q_pick(Q.g[1], cy) * wz, wx * wy * q_pick(Q.g[2], cz),
+                         D.qrs + ((size_t)g * S.scap + s) * 4);
             }
-    const float dt = S.dt;
-    float H[9];
-    bool fin = true;
+        }
+        float H[9];
+        bool fin = true;
 #pragma unroll
-    for (int a = 0; a < 9; a++) {
-        H[a] = D.H[a * N + p] + dt * Lg[a];
-        D.H[a * N + p] = H[a];
-        fin = fin && isfinite(H[a]);
-    }
-    if (!fin) atomicOr(D.status, TL_ST_NONFINITE);
-    if constexpr (MAT == 1) {
-        if (S.visc > 0.0f)
+        for (int a = 0; a < 9; a++) {
+            H[a] = D.H[a * N + p] + dt * Lg[a];
+            D.H[a * N + p] = H[a];
+            fin = fin && isfinite(H[a]);
+        }
+        if (!fin) atomicOr(D.status, TL_ST_NONFINITE);
+        if constexpr (MAT == 1) {
+            if (S.visc > 0.0f)
 #pragma unroll
-            for (int a = 0; a < 9; a++) D.Fdot[a * N + p] = Lg[a];
-        if (S.ystress > 0.0f) {
-            float Gp[9], K[9];
+                for (int a = 0; a < 9; a++) D.Fdot[a * N + p] = Lg[a];
+            if (S.ystress > 0.0f) {
+                float Gp[9], K[9];
 #pragma unroll
-            for (int a = 0; a < 9; a++) Gp[a] = D.Gp[a * N + p];
+                for (int a = 0; a < 9; a++) Gp[a] = D.Gp[a * N + p];
 #pragma unroll
-            for (int i = 0; i < 3; i++)
+                for (int i = 0; i < 3; i++)
 #pragma unroll
-                for (int j = 0; j < 3; j++) {
-                    float kk = H[3 * i + j] + Gp[3 * i + j];
+                    for (int j = 0; j < 3; j++) {
+                        float kk = H[3 * i + j] + Gp[3 * i + j];
 #pragma unroll
-                    for (int l = 0; l < 3; l++) kk += H[3 * i + l] * Gp[3 * l + j];
-                    K[3 * i + j] = kk;
-                }
-            const float E = S.e_uniform ? S.E0 : D.E[p];
-            if (vm_project(E, S.nu, S.ystress, K, Gp))
+                        for (int l = 0; l < 3; l++) kk += H[3 * i + l] * Gp[3 * l + j];
+                        K[3 * i + j] = kk;
+                    }
+                const float E = S.e_uniform ? S.E0 : D.E[p];
+                if (vm_project(E, S.nu, S.ystress, K, Gp))
 #pragma unroll
-                for (int a = 0; a < 9; a++) D.Gp[a * N + p] = Gp[a];
+                    for (int a = 0; a < 9; a++) D.Gp[a * N + p] = Gp[a];
+            }
         }
     }
 }
@@ -704,15 +853,12 @@ hipError_t tl_launch_quad(const TlLaunch* L, int par, int stage)
     case 4:
         if (nn) k_q_remap<<<nn, 256, 0, L->st>>>(S, D, par);
         break;
-    case 5: {
-        const long long blocks = (S.N + 255) / 256;
-        if (blocks == 0) break;
+    case 5:
         if (L->general)
-            k_q_F<1><<<(unsigned)blocks, 256, 0, L->st>>>(S, D, par);
+            k_q_F<1><<<nb, TL_QWG, 0, L->st>>>(S, D, par);
         else
-            k_q_F<0><<<(unsigned)blocks, 256, 0, L->st>>>(S, D, par);
+            k_q_F<0><<<nb, TL_QWG, 0, L->st>>>(S, D, par);
         break;
-    }
     default:
         return hipErrorInvalidValue;
     }
