@@ -16,9 +16,12 @@
 // set: upper half along axis a); the host builds this map once (reference
 // positions do not move), with more rounds where a cell holds two particles of
 // one pattern.  A wave's particles then lie in distinct cells with one pattern, so
-// their base nodes, and the nodes of any one stencil offset, are distinct: the
-// waves take turns adding into the brick's LDS box sums with plain
-// read-modify-writes, no atomics.  The box sums go once per (node, slot) into HBM
+// their base nodes, and the nodes of any one stencil offset, are distinct, and
+// all of them lie in a 6x6x6 region fixed by the pattern.  For the brick's first
+// side key each wave adds into its own LDS region with plain read-modify-writes
+// (no atomics, no barriers); the regions are summed in wave order when the box
+// goes out.  Further side keys of a brick (bricks on a cut) use LDS atomics, and
+// beyond TL_QK keys HBM atomics.  The box sums go once per (node, slot) into HBM
 // with floating-point atomics (up to 8 bricks share a node): results agree with
 // the fixed-order trilinear path to rounding but are not bitwise reproducible.
 #include <hip/hip_runtime.h>
@@ -34,6 +37,7 @@
 #define TL_QK 4           // side keys of a brick summed in LDS; further keys go to HBM directly
 #define TL_QWG 512        // threads of a brick workgroup
 #define TL_QEMPTY 0xFFFFFFFFu
+#define TL_QREG 216       // nodes of one wave's 6x6x6 region (its 64 cells' stencils)
 
 // brick-major id of grid node (gx, gy, gz); -1 outside the grid
 DEV long long q_gid(const SceneK& S, int gx, int gy, int gz)
@@ -278,17 +282,35 @@ __global__ __launch_bounds__(TL_QWG) void k_q_slots(SceneK S, SceneD D, int par)
     }
 }
 
-// add the per-key LDS box sums (Q values per node) of a brick into the node slots
-// in HBM (stride QS floats per slot, offset off)
+// adds a brick's LDS sums (Q values per node) into the node slots in HBM (stride
+// QS floats per slot): the first key's sums from the 8 wave regions, in wave order
+// (wave h holds box node (X, Y, Z) at region (X, Y, Z) - 1 + low(h), low = 1 on the
+// axes of the lower half), the other keys' sums from s_acc [key - 1][box node]
 template <int Q, int QS>
 DEV void q_flush(const SceneK& S, const SceneD& D, const uint32_t* tab, float* dst, int bx, int by, int bz,
-                 const uint32_t* s_keys, const float* s_acc)
+                 const uint32_t* s_keys, const float* s_wv, const float* s_acc)
 {
     for (int t = threadIdx.x; t < TL_QK * TL_QBOXN; t += TL_QWG) {
         const int k = t / TL_QBOXN, bn = t % TL_QBOXN;
         const uint32_t key = s_keys[k];
         if (key == TL_QEMPTY) continue;
-        const float* v = s_acc + (size_t)t * Q;
+        float v[Q];
+        if (k == 0) {
+            const int X = bn % TL_QBOX, Y = (bn / TL_QBOX) % TL_QBOX, Z = bn / 49;
+#pragma unroll
+            for (int c = 0; c < Q; c++) v[c] = 0.0f;
+#pragma unroll
+            for (int h = 0; h < 8; h++) {
+                const int rx = X - (h & 1), ry = Y - ((h >> 1) & 1), rz = Z - ((h >> 2) & 1);
+                if (rx < 0 || ry < 0 || rz < 0 || rx > 5 || ry > 5 || rz > 5) continue;
+                const float* w = s_wv + ((size_t)h * TL_QREG + (rz * 6 + ry) * 6 + rx) * Q;
+#pragma unroll
+                for (int c = 0; c < Q; c++) v[c] += w[c];
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < Q; c++) v[c] = s_acc[((size_t)(k - 1) * TL_QBOXN + bn) * Q + c];
+        }
         bool any = false;
 #pragma unroll
         for (int c = 0; c < Q; c++) any = any || v[c] != 0.0f;
@@ -314,12 +336,14 @@ template <int MAT>
 __global__ __launch_bounds__(TL_QWG) void k_q_p2g(SceneK S, SceneD D, int par)
 {
     __shared__ uint32_t s_keys[TL_SCAP_MAX];
-    __shared__ float s_acc[TL_QK * TL_QBOXN * 7];
+    __shared__ float s_wv[8 * TL_QREG * 7];
+    __shared__ float s_acc[(TL_QK - 1) * TL_QBOXN * 7];
     const int bi = blockIdx.x, tid = threadIdx.x;
     const int brick = D.active[bi];
     const int bx = brick % S.cbx, by = (brick / S.cbx) % S.cby, bz = brick / (S.cbx * S.cby);
     const uint32_t* tab = q_table(S, D, par);
-    for (int t = tid; t < TL_QK * TL_QBOXN * 7; t += TL_QWG) s_acc[t] = 0.0f;
+    for (int t = tid; t < 8 * TL_QREG * 7; t += TL_QWG) s_wv[t] = 0.0f;
+    for (int t = tid; t < (TL_QK - 1) * TL_QBOXN * 7; t += TL_QWG) s_acc[t] = 0.0f;
     if (tid < TL_SCAP_MAX) s_keys[tid] = TL_QEMPTY;
     __syncthreads();
     const long long N = S.N;
@@ -449,34 +473,41 @@ __global__ __launch_bounds__(TL_QWG) void k_q_p2g(SceneK S, SceneD D, int par)
                 for (int q = 0; q < 7; q++) unsafeAtomicAdd(o + q, val[q]);
             }
         }
-        // the waves take turns: within one wave the nodes of a stencil offset are
-        // distinct, so plain read-modify-writes of the LDS sums do not collide
-        const bool fast = valid && k < TL_QK;
-        float* d0 = s_acc + (size_t)(fast ? k : 0) * TL_QBOXN * 7;
-        // wave h passes h barriers, adds its sums, then passes the other 8 - h
-        for (int t = 0; t < h; t++) lds_barrier();
-        {
-            if (fast) {
+        if (valid && k == 0) {
+            // own region of this wave: the lanes' nodes of one offset are distinct
+            const int rx = c[0] - bx * TL_B, ry = c[1] - by * TL_B, rz = c[2] - bz * TL_B;
+            float* d0 = s_wv + (size_t)h * TL_QREG * 7;
 #pragma unroll
-                for (int cz = 0; cz < 3; cz++)
+            for (int cz = 0; cz < 3; cz++)
 #pragma unroll
-                    for (int cy = 0; cy < 3; cy++)
+                for (int cy = 0; cy < 3; cy++) {
 #pragma unroll
-                        for (int cx = 0; cx < 3; cx++) {
-                            float val[7];
-                            if (!node_vals(cx, cy, cz, val)) continue;
-                            float* d = d0 + (((oz + cz) * TL_QBOX + oy + cy) * TL_QBOX + ox + cx) * 7;
+                    for (int cx = 0; cx < 3; cx++) {
+                        float val[7];
+                        if (!node_vals(cx, cy, cz, val)) continue;
+                        float* d = d0 + (((rz + cz) * 6 + ry + cy) * 6 + rx + cx) * 7;
 #pragma unroll
-                            for (int q = 0; q < 7; q++) d[q] += val[q];
-                        }
+                        for (int q = 0; q < 7; q++) d[q] += val[q];
+                    }
                     // one row of nodes at a time: keeps the compiler from hoisting all
                     // 189 reads (and their registers) to the top
                     asm volatile("" ::: "memory");
+                }
+        } else if (valid && k < TL_QK) {
+            float* d0 = s_acc + (size_t)(k - 1) * TL_QBOXN * 7;
+#pragma unroll 1
+            for (int t = 0; t < 27; t++) {
+                const int cx = t % 3, cy = (t / 3) % 3, cz = t / 9;
+                float val[7];
+                if (!node_vals(cx, cy, cz, val)) continue;
+                float* d = d0 + (((oz + cz) * TL_QBOX + oy + cy) * TL_QBOX + ox + cx) * 7;
+#pragma unroll
+                for (int q = 0; q < 7; q++) atomicAdd(d + q, val[q]);
             }
         }
-        for (int t = h; t < TL_QWG / 64; t++) lds_barrier();
     }
-    q_flush<7, 8>(S, D, tab, D.qacc, bx, by, bz, s_keys, s_acc);
+    __syncthreads();
+    q_flush<7, 8>(S, D, tab, D.qacc, bx, by, bz, s_keys, s_wv, s_acc);
 }
 
 // ---------------------------------------------------------------- node kernels
@@ -562,7 +593,8 @@ __global__ __launch_bounds__(TL_QWG) void k_q_g2p(SceneK S, SceneD D, int par)
 {
     __shared__ uint32_t s_keys[TL_SCAP_MAX];
     __shared__ float s_grid[TL_QK * TL_QBOXN * 6];
-    __shared__ float s_acc[TL_QK * TL_QBOXN * 3];
+    __shared__ float s_wv[8 * TL_QREG * 3];
+    __shared__ float s_acc[(TL_QK - 1) * TL_QBOXN * 3];
     __shared__ float s_bb[TL_QWG / 64][7];
     const int bi = blockIdx.x, tid = threadIdx.x;
     const int brick = D.active[bi];
@@ -574,7 +606,8 @@ __global__ __launch_bounds__(TL_QWG) void k_q_g2p(SceneK S, SceneD D, int par)
     }
     const int bx = brick % S.cbx, by = (brick / S.cbx) % S.cby, bz = brick / (S.cbx * S.cby);
     const uint32_t* tab = q_table(S, D, par);
-    for (int t = tid; t < TL_QK * TL_QBOXN * 3; t += TL_QWG) s_acc[t] = 0.0f;
+    for (int t = tid; t < 8 * TL_QREG * 3; t += TL_QWG) s_wv[t] = 0.0f;
+    for (int t = tid; t < (TL_QK - 1) * TL_QBOXN * 3; t += TL_QWG) s_acc[t] = 0.0f;
     if (tid < TL_SCAP_MAX) s_keys[tid] = TL_QEMPTY;
     __syncthreads();
     q_register_keys(S, D, bi, s_keys);
@@ -669,30 +702,35 @@ __global__ __launch_bounds__(TL_QWG) void k_q_g2p(SceneK S, SceneD D, int par)
                 for (int j = 0; j < 3; j++) unsafeAtomicAdd(o + j, wm * vn1[j]);
             }
         }
-        // MUSL re-scatter of m v^{n+1}: the waves take turns (see the P2G)
-        const bool fast = valid && k < TL_QK;
-        const int ox = Q.lo[0] - (bx * TL_B - 1), oy = Q.lo[1] - (by * TL_B - 1), oz = Q.lo[2] - (bz * TL_B - 1);
-        float* d0 = s_acc + (size_t)(fast ? k : 0) * TL_QBOXN * 3;
-        // wave h passes h barriers, adds its sums, then passes the other 8 - h
-        for (int t = 0; t < h; t++) lds_barrier();
-        {
-            if (fast) {
+        // MUSL re-scatter of m v^{n+1} (wave regions as in the P2G)
+        if (valid && k == 0) {
+            const int rx = c[0] - bx * TL_B, ry = c[1] - by * TL_B, rz = c[2] - bz * TL_B;
+            float* d0 = s_wv + (size_t)h * TL_QREG * 3;
 #pragma unroll
-                for (int cz = 0; cz < 3; cz++)
+            for (int cz = 0; cz < 3; cz++)
 #pragma unroll
-                    for (int cy = 0; cy < 3; cy++)
+                for (int cy = 0; cy < 3; cy++)
 #pragma unroll
-                        for (int cx = 0; cx < 3; cx++) {
-                            const float wm = Q.w[0][cx] * Q.w[1][cy] * Q.w[2][cz] * m;
-                            if (wm == 0.0f) continue;
-                            float* d = d0 + (((oz + cz) * TL_QBOX + oy + cy) * TL_QBOX + ox + cx) * 3;
+                    for (int cx = 0; cx < 3; cx++) {
+                        const float wm = Q.w[0][cx] * Q.w[1][cy] * Q.w[2][cz] * m;
+                        if (wm == 0.0f) continue;
+                        float* d = d0 + (((rz + cz) * 6 + ry + cy) * 6 + rx + cx) * 3;
 #pragma unroll
-                            for (int j = 0; j < 3; j++) d[j] += wm * vn1[j];
-                        }
-                    asm volatile("" ::: "memory");
+                        for (int j = 0; j < 3; j++) d[j] += wm * vn1[j];
+                    }
+        } else if (valid && k < TL_QK) {
+            const int ox = Q.lo[0] - (bx * TL_B - 1), oy = Q.lo[1] - (by * TL_B - 1), oz = Q.lo[2] - (bz * TL_B - 1);
+            float* d0 = s_acc + (size_t)(k - 1) * TL_QBOXN * 3;
+#pragma unroll 1
+            for (int t = 0; t < 27; t++) {
+                const int cx = t % 3, cy = (t / 3) % 3, cz = t / 9;
+                const float wm = q_pick(Q.w[0], cx) * q_pick(Q.w[1], cy) * q_pick(Q.w[2], cz) * m;
+                if (wm == 0.0f) continue;
+                float* d = d0 + (((oz + cz) * TL_QBOX + oy + cy) * TL_QBOX + ox + cx) * 3;
+#pragma unroll
+                for (int j = 0; j < 3; j++) atomicAdd(d + j, wm * vn1[j]);
             }
         }
-        for (int t = h; t < TL_QWG / 64; t++) lds_barrier();
     }
     // brick AABB of x^{n+1} and speed bound (used to skip distant contact work)
     const int lane = tid & 63, wv = tid >> 6;
@@ -712,7 +750,7 @@ __global__ __launch_bounds__(TL_QWG) void k_q_g2p(SceneK S, SceneD D, int par)
         if (tid == 6 && S.material_contact && val > 0.0f)
             atomicMax(D.hmax + (bi & (TL_HSLOTS - 1)) * TL_HSTRIDE, __float_as_int(val));
     }
-    q_flush<3, 4>(S, D, tab, D.qrs, bx, by, bz, s_keys, s_acc);
+    q_flush<3, 4>(S, D, tab, D.qrs, bx, by, bz, s_keys, s_wv, s_acc);
 }
 
 // --------------------------------------------------------------- F update (MUSL)
