@@ -191,6 +191,58 @@ DEV void gather_node(const SceneK& S, const int* nb, const float* __restrict__ p
     }
 }
 
+// The same sums formed by the 4 threads u = 0..3 of a quad (lanes 4 bn .. 4 bn + 3):
+// thread u loads contributors u and u + 4, the quad adds its 4 partial sums ((0 + 1)
+// + (2 + 3), a fixed order) and thread 0 writes them.
+template <int Q>
+DEV void gather_node4(const SceneK& S, const int* nb, const float* __restrict__ part, const BoxTab& T, int bn, int u,
+                      float* dst)
+{
+    constexpr int QP = QPad<Q>::value;
+    const int c = T.cnt[bn], b0 = T.base[bn];
+    const int X = bn % 5, Y = (bn / 5) % 5, Z = bn / 25;
+    const int lx = X & 3, ly = Y & 3, lz = Z & 3;
+    unsigned cbase[2] = {0u, 0u};
+    unsigned valid = 0;
+#pragma unroll
+    for (int e = 0; e < 2; e++) {
+        const int d = u + 4 * e;
+        const int dx = d & 1, dy = (d >> 1) & 1, dz = (d >> 2) & 1;
+        if ((dx && lx) || (dy && ly) || (dz && lz)) continue;
+        const int ai = nb[((Z >> 2) - dz + 1) * 9 + ((Y >> 2) - dy + 1) * 3 + ((X >> 2) - dx + 1)];
+        if (ai < 0) continue;
+        const int pn = (lx + 4 * dx) + 5 * (ly + 4 * dy) + 25 * (lz + 4 * dz);
+        cbase[e] = (unsigned)ai * (unsigned)(S.scap * TL_BOXN) + (unsigned)pn;
+        valid |= 1u << e;
+    }
+    for (int s = 0; s < c; s++) {
+        float acc[QP];
+#pragma unroll
+        for (int q = 0; q < QP; q++) acc[q] = 0.0f;
+#pragma unroll
+        for (int e = 0; e < 2; e++) {
+            if (!(valid & (1u << e))) continue;
+            const float4* pp = (const float4*)(part + (size_t)(cbase[e] + (unsigned)(s * TL_BOXN)) * QP);
+#pragma unroll
+            for (int q4 = 0; q4 < QP / 4; q4++) {
+                const float4 v4 = pp[q4];
+                acc[4 * q4 + 0] += v4.x;
+                acc[4 * q4 + 1] += v4.y;
+                acc[4 * q4 + 2] += v4.z;
+                acc[4 * q4 + 3] += v4.w;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < Q; q++) {
+            acc[q] += lane_xor<1>(acc[q]);
+            acc[q] += lane_xor<2>(acc[q]);
+        }
+        if (u == 0)
+#pragma unroll
+            for (int q = 0; q < Q; q++) dst[(b0 + s) * Q + q] = acc[q];
+    }
+}
+
 // Compatibility coupling of one 3-vector field at a node with slots [b0, b0+c)
 // (Eq. 8): f_a += (1/M) sum_{b != a, compatible} (m_a f_b - m_b f_a), M = sum of
 // all slot masses; fields read from src (stride Q, offset off) and written to dst
@@ -705,15 +757,17 @@ DEV void p2g_body(const SceneK& S, const SceneD& D, int bi, KA_Args A)
         return;
     }
     // ---- phase 3: per box node: codes, re-scatter sums, coupling, v~ (Eq. 8, MUSL)
-    if (tid < TL_BOXN) {
+    // (4 threads per node: the quad of lanes 4 bn .. 4 bn + 3)
+    if ((tid >> 2) < TL_BOXN) {
+        const int bn = tid >> 2, u = tid & 3;
         uint32_t pre_r[2], pre_c[2];
-        if (use_r) codes_pre(S, D.scode[A.rsb], Tr, tid, pre_r);
-        if (use_c) codes_pre(S, D.scode[A.cur], Tc, tid, pre_c);
+        if (u == 0 && use_r) codes_pre(S, D.scode[A.rsb], Tr, bn, pre_r);
+        if (u == 0 && use_c) codes_pre(S, D.scode[A.cur], Tc, bn, pre_c);
         if (use_r) {
-            const int c = Tr.cnt[tid], b0 = Tr.base[tid];
-            if (c > 0) gather_node<4>(S, s_nb, D.rs, Tr, tid, s_rsum);
-            codes_put(S, D.scode[A.rsb], Tr, tid, pre_r);
-            if (c > 0) {
+            const int c = Tr.cnt[bn], b0 = Tr.base[bn];
+            if (c > 0) gather_node4<4>(S, s_nb, D.rs, Tr, bn, u, s_rsum);
+            if (u == 0) codes_put(S, D.scode[A.rsb], Tr, bn, pre_r);
+            if (u == 0 && c > 0) {
                 couple_node<4>(Tr, b0, c, s_rsum, 1, s_vt);
                 for (int a = 0; a < c; a++) {
                     float m = s_rsum[(b0 + a) * 4];
@@ -722,7 +776,7 @@ DEV void p2g_body(const SceneK& S, const SceneD& D, int bi, KA_Args A)
                 }
             }
         }
-        if (use_c) codes_put(S, D.scode[A.cur], Tc, tid, pre_c);
+        if (u == 0 && use_c) codes_put(S, D.scode[A.cur], Tc, bn, pre_c);
     }
     if (A.do_p2g)
         for (int q = tid; q < total_c * 7; q += TL_WG) s_acc[q] = 0.0f;
@@ -977,13 +1031,14 @@ DEV void g2p_body(const SceneK& S, const SceneD& D, int bi, int cur)
         return;
     }
     // ---- phase 3: per box node: codes, P2G sums, coupling (Eq. 8), v^n and dv (Eq. 9)
-    if (tid < TL_BOXN) {
+    if ((tid >> 2) < TL_BOXN) {
+        const int bn = tid >> 2, u = tid & 3;
         uint32_t pre[2];
-        codes_pre(S, D.scode[cur], T, tid, pre);
-        const int c = T.cnt[tid], b0 = T.base[tid];
-        if (c > 0) gather_node<7>(S, s_nb, D.p2g, T, tid, s_sum);
-        codes_put(S, D.scode[cur], T, tid, pre);
-        if (c > 0) {
+        if (u == 0) codes_pre(S, D.scode[cur], T, bn, pre);
+        const int c = T.cnt[bn], b0 = T.base[bn];
+        if (c > 0) gather_node4<7>(S, s_nb, D.p2g, T, bn, u, s_sum);
+        if (u == 0) codes_put(S, D.scode[cur], T, bn, pre);
+        if (u == 0 && c > 0) {
             float* gvn = s_grid;
             float* gdv = s_grid + TL_BOX_SLOTS * 3;
             couple_node<7>(T, b0, c, s_sum, 1, gvn);
