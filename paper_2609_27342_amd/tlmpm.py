@@ -218,7 +218,9 @@ def make_desc(scene, keep):
         d.v0 = v0.ctypes.data
     for name, arr_key in (("vol0", "vol0"), ("mass", "mass"), ("E", "E")):
         a = np.asarray(scene[arr_key], np.float32)
-        if a.ndim == 0 or np.all(a == a.flat[0]):
+        if a.size == 0:  # no particles: any positive uniform value
+            setattr(d, name + "_uniform" if name != "E" else "E_uniform", 1.0)
+        elif a.ndim == 0 or np.all(a == a.flat[0]):
             setattr(d, name + "_uniform" if name != "E" else "E_uniform", float(a.flat[0]))
         else:
             a = np.ascontiguousarray(a)
