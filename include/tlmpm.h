@@ -11,6 +11,9 @@
  *   - compatibility coupling and the grid update (Sec. III-D, Eqs. 8, 9);
  *   - PIC/FLIP G2P of v and x, MUSL re-scatter with the same coupling and the
  *     deformation-gradient update (Sec. III-B, App. Eq. 17).
+ * Per scene: Neo-Hookean or fixed-corotated elasticity with Newtonian viscosity and
+ * von Mises plasticity (Sec. III-B), trilinear or quadratic B-spline interpolation
+ * (Eq. 1), prescribed or free (two-way coupled) tools (Sec. III-A, III-F).
  *
  * Conventions
  *   - Every call returns a tlmpm_status; nothing throws across the ABI.  The text of
@@ -180,7 +183,7 @@ tlmpm_status tlmpm_assign_labels(tlmpm_scene* scene, const tlmpm_blade* blades, 
 /* n_substeps TLMPM substeps.  Each substep: label pass for tools with
  * TLMPM_TOOL_LABELS, contact, P2G, coupling, grid update, G2P, re-scatter; the
  * deformation-gradient update of a substep is completed lazily by the next one
- * (or by tlmpm_read_state).  The tool pose is held fixed over the substeps unless
+ * (or by tlmpm_read_state; with the quadratic stencil within the substep).  The tool pose is held fixed over the substeps unless
  * TLMPM_TOOL_ADVANCE is set.  wrench: NULL, or [n_tools][6] (force, torque on each
  * tool) averaged over the substeps so that it carries the same impulse (Sec.
  * III-G); a non-NULL pointer synchronises. */
