@@ -139,3 +139,28 @@ def test_batch_membership_rules(tl):
     gs[0].step([], 1)
     with pytest.raises(tl.TlmpmError):
         tl.Batch([gs[0], gs[0]])
+
+
+def test_batch_isolates_a_failing_scene(tl):
+    """A state with det F < 0 written into one member makes that scene report
+    TLMPM_E_NONFINITE; its batch-mates run on and equal their runs alone bitwise."""
+    scenes = _scenes()[:3]
+    K = 10
+    _print_case("batch_isolates_failure", n=[s["X"].shape[0] for s in scenes], steps=K)
+    alone = {}
+    for i in (0, 2):
+        g, ws = _run_alone(tl, scenes[i], 0, K)
+        assert g.status() == 0
+        alone[i] = g.read(FIELDS)
+        g.close()
+    gs = [tl.Scene(s) for s in scenes]
+    n1 = scenes[1]["X"].shape[0]
+    F = np.tile(np.eye(3, dtype=np.float32), (n1, 1, 1))
+    F[n1 // 2] = -np.eye(3)
+    gs[1].write(F=F)
+    with tl.Batch(gs) as b:
+        _run_batch(tl, b, scenes, 0, K)
+    assert gs[1].status() == tl.E_NONFINITE
+    for i in (0, 2):
+        assert gs[i].status() == 0
+        _same(gs[i].read(FIELDS), alone[i])
