@@ -195,7 +195,8 @@ Dims dims_of(const tlmpm_scene_desc* d)
 }
 
 struct Offsets {
-    size_t X, u, v, H, code, code_prev, D, perm, E, m, V0, cell_start, active, cnt0, cnt1, sc0, sc1, p2g, rs, hist,
+    size_t X, u, v, H, code, code_prev, D, perm, E, m, V0, cell_start, active, cnt0, cnt1, sc0, sc1, p2g, rs, p2g_x,
+        rs_x, xp2g, xrs, aabb_x, xlist, xin, xg, hist,
         aabb, wpart, Fdot, Gp, wacc, Jmat, Jrig, brig, bmixed, ccode, ckeys, gmeta, gperm, bround, tools, tinfo, ctr, bact, status, dirty, bdirty, pcell, cand_idx, coff, cmask, cstatic, bcand, hbin, hmax, bcount, bids, crec, htab, hnext, ph_n, ph_q, ph_u,
         qcode, qacc, qrs, qnodes, qround, qmap, total;
     uint32_t hmask;
@@ -294,6 +295,14 @@ Offsets plan(const tlmpm_scene_desc* d, long long n_active)
     o.sc1 = L.take((size_t)g.NN * scap * 4);
     o.p2g = L.take((size_t)n_active * scap * TL_BOXN * 8 * f); // 7 components padded to 8
     o.rs = L.take((size_t)n_active * scap * TL_BOXN * 4 * f);
+    o.p2g_x = L.take((size_t)n_active * scap * TL_BOXN * 8 * f);
+    o.rs_x = L.take((size_t)n_active * scap * TL_BOXN * 4 * f);
+    o.xp2g = L.take((size_t)n_active * 4);
+    o.xrs = L.take((size_t)n_active * 4);
+    o.aabb_x = L.take((size_t)g.n_bricks * 8 * f);
+    o.xlist = L.take((size_t)n_active * 4);
+    o.xin = L.take((size_t)n_active * 4);
+    o.xg = L.take(4);
     o.bact = L.take((size_t)g.n_bricks * 4);
     o.hist = L.take((size_t)(TL_MAX_TOOLS + 1) * 4 * N * f);
     o.aabb = L.take((size_t)g.n_bricks * 8 * f);
@@ -533,6 +542,14 @@ extern "C" tlmpm_status tlmpm_create_scene(const tlmpm_scene_desc* d, void* ws, 
     K.ystress = d->yield_stress;
     K.pair_blocks = (int)std::min<long long>(4096, std::max<long long>(1, N / 128));
     K.stencil = d->stencil;
+    // workgroups for the later rounds of bricks with a mixed cell: a quarter of the
+    // bricks, at most 256 (with more mixed bricks no brick is split).  Only scenes of
+    // 256 to 4096 active bricks split: their launches are about one round of
+    // workgroups on the GPU, so a brick with extra rounds lengthens the whole launch;
+    // smaller scenes (batches) and larger ones measured slower with the extra launch
+    // slots than the rounds cost.
+    const size_t na = active.size();
+    K.xcap = (na >= 256 && na <= 4096) ? (int)std::min<size_t>(256, na / 4) : 0;
     float vmax0 = d->vol0_uniform;
     if (d->vol0)
         for (long long p = 0; p < N; p++) vmax0 = std::max(vmax0, d->vol0[p]);
@@ -561,6 +578,14 @@ extern "C" tlmpm_status tlmpm_create_scene(const tlmpm_scene_desc* d, void* ws, 
     D.scode[1] = (uint32_t*)(base + o.sc1);
     D.p2g = (float*)(base + o.p2g);
     D.rs = (float*)(base + o.rs);
+    D.p2g_x = (float*)(base + o.p2g_x);
+    D.rs_x = (float*)(base + o.rs_x);
+    D.xp2g = (int*)(base + o.xp2g);
+    D.xrs = (int*)(base + o.xrs);
+    D.aabb_x = (float*)(base + o.aabb_x);
+    D.xlist = (int*)(base + o.xlist);
+    D.xin = (int*)(base + o.xin);
+    D.xg = (int*)(base + o.xg);
     D.hist = (float*)(base + o.hist);
     D.aabb = (float*)(base + o.aabb);
     D.wpart = (double*)(base + o.wpart);
@@ -1275,6 +1300,9 @@ extern "C" tlmpm_status tlmpm_write_state(tlmpm_scene* sc, uint32_t mask, const 
     }
     const TlLaunch L = single_launch(sc);
     if (codes_changed) {
+        // the list of bricks with a mixed cell is rebuilt with the summaries
+        HIPCHK(tl_launch_fill_i32(sc->D.xin, sc->D.n_active, 0, sc->st));
+        HIPCHK(tl_launch_fill_i32(sc->D.ctr + 3, 1, 0, sc->st));
         HIPCHK(tl_launch_mixed(&L, 1));
         HIPCHK(tl_launch_slots(&L, sc->cur, sc->cur, 1));
         sc->rsb = sc->cur;
@@ -1495,6 +1523,7 @@ void scene_items(const tlmpm_scene* sc, int n[TL_ITEM_KINDS])
     n[IT_PART] = ceil_div(K.N, 256);
     n[IT_BFLAG] = ceil_div(n_bricks, 256);
     n[IT_PAIR] = K.material_contact ? K.pair_blocks : 0;
+    n[IT_XBRICK] = sc->D.n_active > 0 ? K.xcap : 0;
 }
 
 tlmpm_status batch_plan(tlmpm_scene* const* scenes, int n, BatchPlan& P)

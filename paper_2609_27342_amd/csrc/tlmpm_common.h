@@ -97,6 +97,7 @@ struct SceneK {
     float ystress;    // von Mises yield stress (0: elastic)
     int pair_blocks;  // blocks of the pair search (grid-stride over the candidates)
     int stencil;      // 0 trilinear (8 nodes), 1 quadratic B-spline (27 nodes)
+    int xcap;         // workgroups for the later rounds of mixed bricks (used while xlist fits)
     double dt_d;
 };
 
@@ -120,6 +121,14 @@ struct SceneD {
     uint32_t* scode[2];
     float* p2g;    // [active brick][scap][125 box nodes][8]: each brick's P2G box sums
     float* rs;     // [active brick][scap][125 box nodes][4]: each brick's re-scatter box sums
+    float* p2g_x;  // the same two for the later same-code rounds of a split brick
+    float* rs_x;
+    int* xp2g;     // [active brick] p2g_x holds this substep's sums of the brick (split)
+    int* xrs;      // [active brick] rs_x (and aabb_x) hold the brick's last G2P sums (split)
+    float* aabb_x; // [n_bricks][8] box of a split brick's later rounds
+    int* xlist;    // [active brick] active indices of the bricks with a mixed cell (count: ctr[3])
+    int* xin;      // [active brick] the brick is in xlist
+    int* xg;       // [1] the last G2P split the mixed bricks (rs_x, xrs, aabb_x in use)
     int* bact;     // [bricks] active index of a brick, -1 if it holds no particle
     float* hist;   // rigid contact history [TL_MAX_TOOLS+1][4][N]: u_t xyz, stamp
     float* aabb;   // [n_bricks][8]: min xyz, max xyz, max |v|, 0
@@ -138,7 +147,8 @@ struct SceneD {
     int* bround;     // [active bricks] rounds (largest group count of a cell) of a mixed brick
     DevTool* tools;   // [TL_MAX_TOOLS] tools (or label-only blades) of the current call
     int* tinfo;       // [4] per call: number of tools, any tool with contact, new cut, unused
-    int* ctr;         // [4] persistent: contact-history stamp, F update pending, unused x2
+    int* ctr;         // [4] persistent: contact-history stamp, F update pending, substep of the
+                      // call, number of bricks in xlist
     int* status;
     int* dirty;
     int* bdirty;        // [bricks] side codes of the brick changed in the last label pass
@@ -205,7 +215,7 @@ __device__ __forceinline__ float lane_xor(float v)
 
 // Launch context: one scene (parameters by value) or a batch of scenes (device
 // arrays of SceneK / SceneD and, per kind of work item, a list of (scene, block)).
-enum { IT_BRICK = 0, IT_NODE, IT_CELL, IT_WRENCH, IT_SCENE, IT_PART, IT_BFLAG, IT_PAIR, TL_ITEM_KINDS };
+enum { IT_BRICK = 0, IT_NODE, IT_CELL, IT_WRENCH, IT_SCENE, IT_PART, IT_BFLAG, IT_PAIR, IT_XBRICK, TL_ITEM_KINDS };
 
 struct TlLaunch {
     const SceneK* S;   // single scene (host copies), or null in batch mode

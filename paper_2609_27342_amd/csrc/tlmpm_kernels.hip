@@ -122,8 +122,6 @@ struct QPad {
     static constexpr int value = (Q + 3) & ~3;
 };
 
-// Sums of all slots of box node bn over the bricks that contributed to it, in
-// fixed contributor order, written to dst[slot * Q + c].
 // Active indices of the 27 bricks around (bx, by, bz) (-1: none), by threads
 // [TL_BOXN, TL_BOXN + 27) of the block; read after the next barrier.
 DEV void load_neighbours(const SceneK& S, const SceneD& D, int bx, int by, int bz, int* nb)
@@ -136,74 +134,23 @@ DEV void load_neighbours(const SceneK& S, const SceneD& D, int bx, int by, int b
                 : D.bact[((long long)z * S.cby + y) * S.cbx + x];
 }
 
+// Sums of all slots of box node bn over the bricks that contributed to it, written
+// to dst[slot * Q + c], formed by the 4 threads u = 0..3 of a quad (lanes 4 bn ..
+// 4 bn + 3): contributor d is the brick at home - (d & 1, d >> 1 & 1, d >> 2 & 1),
+// which holds the node at box position (l + 4 * offset); thread u loads contributors u
+// and u + 4 (each its first partial plus, where xflag is set, the partial of its later
+// same-code rounds), the quad adds its 4 sums ((0 + 1) + (2 + 3)) and thread 0
+// writes them.  The order is fixed: results are bitwise reproducible.
 template <int Q>
-DEV void gather_node(const SceneK& S, const int* nb, const float* __restrict__ part, const BoxTab& T, int bn, float* dst)
-{
-    constexpr int QP = QPad<Q>::value;
-    const int c = T.cnt[bn], b0 = T.base[bn];
-    const int X = bn % 5, Y = (bn / 5) % 5, Z = bn / 25;
-    const int lx = X & 3, ly = Y & 3, lz = Z & 3;
-    // contributor d: the brick at home - (d & 1, d >> 1 & 1, d >> 2 & 1), which
-    // holds the node at box position (l + 4 * offset)
-    unsigned cbase[8]; // node-slot record index of each contributor (32 bits; checked at creation)
-    unsigned valid = 0;
-    for (int d = 0; d < 8; d++) {
-        int dx = d & 1, dy = (d >> 1) & 1, dz = (d >> 2) & 1;
-        cbase[d] = 0;
-        if ((dx && lx) || (dy && ly) || (dz && lz)) continue;
-        // brick offset from this one: (X >> 2) - dx per axis, in -1..1
-        const int ai = nb[((Z >> 2) - dz + 1) * 9 + ((Y >> 2) - dy + 1) * 3 + ((X >> 2) - dx + 1)];
-        if (ai < 0) continue;
-        const int pn = (lx + 4 * dx) + 5 * (ly + 4 * dy) + 25 * (lz + 4 * dz);
-        cbase[d] = (unsigned)ai * (unsigned)(S.scap * TL_BOXN) + (unsigned)pn;
-        valid |= 1u << d;
-    }
-    // two slots per pass, so that the loads of both are in flight together
-    for (int s = 0; s < c; s += 2) {
-        const bool two = s + 1 < c;
-        float acc[2][QP];
-#pragma unroll
-        for (int u = 0; u < 2; u++)
-#pragma unroll
-            for (int q = 0; q < QP; q++) acc[u][q] = 0.0f;
-#pragma unroll
-        for (int d = 0; d < 8; d++) {
-            if (!(valid & (1u << d))) continue;
-#pragma unroll
-            for (int u = 0; u < 2; u++) {
-                if (u == 1 && !two) continue;
-                const float4* pp = (const float4*)(part + (size_t)(cbase[d] + (unsigned)((s + u) * TL_BOXN)) * QP);
-#pragma unroll
-                for (int q4 = 0; q4 < QP / 4; q4++) {
-                    float4 v4 = pp[q4];
-                    acc[u][4 * q4 + 0] += v4.x;
-                    acc[u][4 * q4 + 1] += v4.y;
-                    acc[u][4 * q4 + 2] += v4.z;
-                    acc[u][4 * q4 + 3] += v4.w;
-                }
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < Q; q++) dst[(b0 + s) * Q + q] = acc[0][q];
-        if (two)
-#pragma unroll
-            for (int q = 0; q < Q; q++) dst[(b0 + s + 1) * Q + q] = acc[1][q];
-    }
-}
-
-// The same sums formed by the 4 threads u = 0..3 of a quad (lanes 4 bn .. 4 bn + 3):
-// thread u loads contributors u and u + 4, the quad adds its 4 partial sums ((0 + 1)
-// + (2 + 3), a fixed order) and thread 0 writes them.
-template <int Q>
-DEV void gather_node4(const SceneK& S, const int* nb, const float* __restrict__ part, const BoxTab& T, int bn, int u,
-                      float* dst)
+DEV void gather_node4(const SceneK& S, const int* nb, const float* __restrict__ part, const float* __restrict__ xpart,
+                      const int* __restrict__ xflag, const BoxTab& T, int bn, int u, float* dst)
 {
     constexpr int QP = QPad<Q>::value;
     const int c = T.cnt[bn], b0 = T.base[bn];
     const int X = bn % 5, Y = (bn / 5) % 5, Z = bn / 25;
     const int lx = X & 3, ly = Y & 3, lz = Z & 3;
     unsigned cbase[2] = {0u, 0u};
-    unsigned valid = 0;
+    unsigned valid = 0, extra = 0;
 #pragma unroll
     for (int e = 0; e < 2; e++) {
         const int d = u + 4 * e;
@@ -214,6 +161,7 @@ DEV void gather_node4(const SceneK& S, const int* nb, const float* __restrict__ 
         const int pn = (lx + 4 * dx) + 5 * (ly + 4 * dy) + 25 * (lz + 4 * dz);
         cbase[e] = (unsigned)ai * (unsigned)(S.scap * TL_BOXN) + (unsigned)pn;
         valid |= 1u << e;
+        if (xflag && xflag[ai]) extra |= 1u << e;
     }
     for (int s = 0; s < c; s++) {
         float acc[QP];
@@ -222,14 +170,28 @@ DEV void gather_node4(const SceneK& S, const int* nb, const float* __restrict__ 
 #pragma unroll
         for (int e = 0; e < 2; e++) {
             if (!(valid & (1u << e))) continue;
-            const float4* pp = (const float4*)(part + (size_t)(cbase[e] + (unsigned)(s * TL_BOXN)) * QP);
+            const size_t rec = (size_t)(cbase[e] + (unsigned)(s * TL_BOXN)) * QP;
+            const float4* pp = (const float4*)(part + rec);
+            float4 v4[QP / 4];
+#pragma unroll
+            for (int q4 = 0; q4 < QP / 4; q4++) v4[q4] = pp[q4];
+            if (extra & (1u << e)) {
+                const float4* xp = (const float4*)(xpart + rec);
+#pragma unroll
+                for (int q4 = 0; q4 < QP / 4; q4++) {
+                    const float4 x4 = xp[q4];
+                    v4[q4].x += x4.x;
+                    v4[q4].y += x4.y;
+                    v4[q4].z += x4.z;
+                    v4[q4].w += x4.w;
+                }
+            }
 #pragma unroll
             for (int q4 = 0; q4 < QP / 4; q4++) {
-                const float4 v4 = pp[q4];
-                acc[4 * q4 + 0] += v4.x;
-                acc[4 * q4 + 1] += v4.y;
-                acc[4 * q4 + 2] += v4.z;
-                acc[4 * q4 + 3] += v4.w;
+                acc[4 * q4 + 0] += v4[q4].x;
+                acc[4 * q4 + 1] += v4[q4].y;
+                acc[4 * q4 + 2] += v4[q4].z;
+                acc[4 * q4 + 3] += v4[q4].w;
             }
         }
 #pragma unroll
@@ -413,7 +375,7 @@ DEV void accumulate_classes(const Lane& L, bool valid, uint32_t key, GA&& ga, GB
     lds_barrier();
 }
 
-// Writes the box accumulator as this brick's partial (layout of gather_node).
+// Writes the box accumulator as this brick's partial (layout of gather_node4).
 template <int Q>
 DEV void write_partials(const SceneK& S, float* __restrict__ part, int bi, const BoxTab& T, int total, const float* acc)
 {
@@ -570,6 +532,29 @@ DEV void rigid_one(const SceneK& S, const SceneD& D, const DevTool* T, int slot,
 
 // Conservative test: can a particle of a brick with AABB [lo, hi] and speed bound
 // vmax touch the rectangle of tool T (or the floor) during this substep?
+// Current AABB and speed bound of an active brick: the box written by its G2P, joined
+// with that of its second workgroup when the brick was split
+DEV void brick_aabb(const SceneK& S, const SceneD& D, int bi, int brick, float bb[7])
+{
+    const float* a = D.aabb + (long long)brick * 8;
+    if (S.xcap == 0) { // the scene never splits
+#pragma unroll
+        for (int q = 0; q < 7; q++) bb[q] = a[q];
+        return;
+    }
+    // all loads issued together, then the join
+    const float* x = D.aabb_x + (long long)brick * 8;
+    float ra[7], rx[7];
+#pragma unroll
+    for (int q = 0; q < 7; q++) {
+        ra[q] = a[q];
+        rx[q] = x[q];
+    }
+    const bool join = D.xg[0] != 0 && D.xrs[bi] != 0;
+#pragma unroll
+    for (int q = 0; q < 7; q++) bb[q] = !join ? ra[q] : (q < 3 ? fminf(ra[q], rx[q]) : fmaxf(ra[q], rx[q]));
+}
+
 DEV bool brick_near_tool(const SceneK& S, const float* bb, const DevTool* T, float Rmax, double jdt)
 {
     float vmax = bb[6];
@@ -624,7 +609,8 @@ DEV void rigid_body(const SceneK& S, const SceneD& D, int bi)
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const long long N = S.N;
     if (tid <= TL_MAX_TOOLS) {
-        const float* bb = D.aabb + (long long)brick * 8;
+        float bb[7];
+        brick_aabb(S, D, bi, brick, bb);
         int nr = 0;
         if (tid == 0)
             nr = S.floor_on ? brick_near_tool(S, bb, nullptr, S.Rmax, jdt) : 0;
@@ -695,8 +681,12 @@ DEV void rigid_body(const SceneK& S, const SceneD& D, int bi)
 
 // MAT 0: Neo-Hookean only; MAT 1: the scene's material (Neo-Hookean or
 // fixed-corotated) with Newtonian viscosity.
-template <int MAT>
-DEV void p2g_body(const SceneK& S, const SceneD& D, int bi, KA_Args A)
+// part 0 takes the brick's first same-code round (all rounds unless the brick is
+// split), part 1 the later rounds of a split brick (a brick whose cells hold two
+// codes and need more than one round): the two run as separate workgroups, each
+// with its own box partial, so that such bricks do not lengthen the launch.
+template <int MAT, bool SPLIT>
+DEV void p2g_body(const SceneK& S, const SceneD& D, int bi, KA_Args A, int part)
 {
     __shared__ BoxTab Tc;
     __shared__ BoxTab Tr;
@@ -707,8 +697,13 @@ DEV void p2g_body(const SceneK& S, const SceneD& D, int bi, KA_Args A)
     __shared__ int s_nb[27];
     __shared__ int s_rounds;
 
+    const int nround = SPLIT ? D.bround[bi] : 0; // rounds of a brick with a mixed cell, else 0
+    if (SPLIT && part == 1 && nround <= 1) return;
     const int brick = D.active[bi];
     const bool grouped = D.bmixed[brick] != 0; // a cell holds two codes: same-code groups
+    // (all mixed bricks split, or none: the decision does not depend on list order)
+    const bool split = SPLIT && grouped && nround > 1 && S.xcap > 0 && D.ctr[3] <= S.xcap;
+    const int r0 = part; // first round of this workgroup
     const int bx = brick % S.cbx, by = (brick / S.cbx) % S.cby, bz = brick / (S.cbx * S.cby);
     const int tid = threadIdx.x;
     const long long N = S.N;
@@ -716,6 +711,7 @@ DEV void p2g_body(const SceneK& S, const SceneD& D, int bi, KA_Args A)
     const bool fp = D.ctr[1] != 0;                              // F update of the last substep pending
     const bool use_r = fp;                                            // finalize v~ (tables rs)
     const bool use_c = A.do_p2g && ((A.tabs_differ && fp) || !fp); // separate P2G tables
+    const bool xg_rs = SPLIT && D.xg[0] != 0; // the last G2P split bricks: their second re-scatter sums
 
     // ---- phase 1: cell index, box counts, brick-vs-tool tests, round-0 particle loads
     Lane L = lane_of(D, brick);
@@ -727,7 +723,7 @@ DEV void p2g_body(const SceneK& S, const SceneD& D, int bi, KA_Args A)
     const bool rig = A.do_p2g && (S.floor_on || D.tinfo[1]) && D.brig[brick] != 0;
     const int gxc = bx * TL_B + L.cxl, gyc = by * TL_B + L.cyl, gzc = bz * TL_B + L.czl;
     long long p = L.beg;
-    bool valid = lane_particle(D, bi, grouped, L, 0, p);
+    bool valid = lane_particle(D, bi, grouped, L, r0, p);
     float Xp[3] = {0.0f, 0.0f, 0.0f}, H[9], vel[3] = {0.0f, 0.0f, 0.0f};
     uint32_t code = 0;
     auto load_particle = [&]() {
@@ -765,7 +761,7 @@ DEV void p2g_body(const SceneK& S, const SceneD& D, int bi, KA_Args A)
         if (u == 0 && use_c) codes_pre(S, D.scode[A.cur], Tc, bn, pre_c);
         if (use_r) {
             const int c = Tr.cnt[bn], b0 = Tr.base[bn];
-            if (c > 0) gather_node4<4>(S, s_nb, D.rs, Tr, bn, u, s_rsum);
+            if (c > 0) gather_node4<4>(S, s_nb, D.rs, D.rs_x, xg_rs ? D.xrs : nullptr, Tr, bn, u, s_rsum);
             if (u == 0) codes_put(S, D.scode[A.rsb], Tr, bn, pre_r);
             if (u == 0 && c > 0) {
                 couple_node<4>(Tr, b0, c, s_rsum, 1, s_vt);
@@ -782,10 +778,10 @@ DEV void p2g_body(const SceneK& S, const SceneD& D, int bi, KA_Args A)
         for (int q = tid; q < total_c * 7; q += TL_WG) s_acc[q] = 0.0f;
     lds_barrier();
     const BoxTab& T = use_c ? Tc : Tr;
-    const int rounds = s_rounds;
+    const int rounds = (split && part == 0) ? 1 : s_rounds;
 
-    for (int r = 0; r < rounds; r++) {
-        if (r > 0) {
+    for (int r = r0; r < rounds; r++) {
+        if (r > r0) {
             valid = lane_particle(D, bi, grouped, L, r, p);
             if (valid) load_particle();
         }
@@ -965,7 +961,8 @@ DEV void p2g_body(const SceneK& S, const SceneD& D, int bi, KA_Args A)
         accumulate_classes<3, 4, 4>(L, valid, key, gen_dp, gen_mp, T, s_acc, D.status);
     }
     if (!A.do_p2g) return;
-    write_partials<7>(S, D.p2g, bi, T, total_c, s_acc);
+    if (SPLIT && part == 0 && tid == 0) D.xp2g[bi] = split ? 1 : 0;
+    write_partials<7>(S, part ? D.p2g_x : D.p2g, bi, T, total_c, s_acc);
 }
 
 // --------------------------------------------------------------------------- K_B
@@ -973,7 +970,8 @@ DEV void p2g_body(const SceneK& S, const SceneD& D, int bi, KA_Args A)
 // P2G partials (sum over contributing bricks, coupling Eq. 8, velocities Eq. 9),
 // PIC/FLIP G2P of v and x (Eq. 17), then the MUSL re-scatter of m_p v_p^{n+1} into
 // this brick's partials.  Also records the brick's current AABB and speed bound.
-DEV void g2p_body(const SceneK& S, const SceneD& D, int bi, int cur)
+template <bool SPLIT>
+DEV void g2p_body(const SceneK& S, const SceneD& D, int bi, int cur, int part)
 {
     __shared__ BoxTab T;
     __shared__ float s_sum[TL_BOX_SLOTS * 7];
@@ -984,15 +982,23 @@ DEV void g2p_body(const SceneK& S, const SceneD& D, int bi, int cur)
     __shared__ int s_rounds;
     __shared__ float s_bb[8][7];
 
+    const int nround = SPLIT ? D.bround[bi] : 0; // rounds of a brick with a mixed cell, else 0
+    if (SPLIT && part == 1 && nround <= 1) return; // (split bricks as in the P2G)
     const int brick = D.active[bi];
-    if (bi == 0 && threadIdx.x == 0) {
+    if (bi == 0 && part == 0 && threadIdx.x == 0) {
         // end of the substep for this scene: next history stamp, F update pending
-        // (no other kernel of the substep reads these after this point)
+        // (no other kernel of the substep reads these after this point); whether this
+        // G2P splits its mixed bricks (read by the next P2G and box tests)
         D.ctr[0] += 1;
         D.ctr[1] = 1;
         D.ctr[2] += 1;
+        if (SPLIT) D.xg[0] = (S.xcap > 0 && D.ctr[3] > 0 && D.ctr[3] <= S.xcap) ? 1 : 0;
     }
     const bool grouped = D.bmixed[brick] != 0; // a cell holds two codes: same-code groups
+    // this substep's P2G split its mixed bricks (a scene without split workgroups never)
+    const bool xsplit = SPLIT && S.xcap > 0 && D.ctr[3] > 0 && D.ctr[3] <= S.xcap;
+    const bool split = grouped && nround > 1 && xsplit;
+    const int r0 = part;
     const int bx = brick % S.cbx, by = (brick / S.cbx) % S.cby, bz = brick / (S.cbx * S.cby);
     const int tid = threadIdx.x;
     const long long N = S.N;
@@ -1005,7 +1011,7 @@ DEV void g2p_body(const SceneK& S, const SceneD& D, int bi, int cur)
     if (tid == 0) s_rounds = 0;
     const int gxc = bx * TL_B + L.cxl, gyc = by * TL_B + L.cyl, gzc = bz * TL_B + L.czl;
     long long p = L.beg;
-    bool valid = lane_particle(D, bi, grouped, L, 0, p);
+    bool valid = lane_particle(D, bi, grouped, L, r0, p);
     float Xp[3] = {0.0f, 0.0f, 0.0f}, v[3] = {0.0f, 0.0f, 0.0f}, u[3] = {0.0f, 0.0f, 0.0f};
     uint32_t code = 0;
     auto load_particle = [&]() {
@@ -1036,7 +1042,7 @@ DEV void g2p_body(const SceneK& S, const SceneD& D, int bi, int cur)
         uint32_t pre[2];
         if (u == 0) codes_pre(S, D.scode[cur], T, bn, pre);
         const int c = T.cnt[bn], b0 = T.base[bn];
-        if (c > 0) gather_node4<7>(S, s_nb, D.p2g, T, bn, u, s_sum);
+        if (c > 0) gather_node4<7>(S, s_nb, D.p2g, D.p2g_x, xsplit ? D.xp2g : nullptr, T, bn, u, s_sum);
         if (u == 0) codes_put(S, D.scode[cur], T, bn, pre);
         if (u == 0 && c > 0) {
             float* gvn = s_grid;
@@ -1055,12 +1061,12 @@ DEV void g2p_body(const SceneK& S, const SceneD& D, int bi, int cur)
     }
     for (int q = tid; q < total * 4; q += TL_WG) s_acc[q] = 0.0f;
     lds_barrier();
-    const int rounds = s_rounds;
+    const int rounds = (split && part == 0) ? 1 : s_rounds;
     float bb[7] = {1e30f, 1e30f, 1e30f, -1e30f, -1e30f, -1e30f, 0.0f};
     const float* gv = s_grid;
     const float* gdv = s_grid + TL_BOX_SLOTS * 3;
-    for (int r = 0; r < rounds; r++) {
-        if (r > 0) {
+    for (int r = r0; r < rounds; r++) {
+        if (r > r0) {
             valid = lane_particle(D, bi, grouped, L, r, p);
             if (valid) load_particle();
         }
@@ -1112,8 +1118,11 @@ DEV void g2p_body(const SceneK& S, const SceneD& D, int bi, int cur)
         };
         accumulate_classes<4, 0>(L, valid, key, gen, gen, T, s_acc, D.status);
     }
-    write_partials<4>(S, D.rs, bi, T, total, s_acc);
-    // brick AABB of x^{n+1} and speed bound (used to skip distant contact work)
+    if (SPLIT && part == 0 && tid == 0) D.xrs[bi] = split ? 1 : 0;
+    write_partials<4>(S, part ? D.rs_x : D.rs, bi, T, total, s_acc);
+    // brick AABB of x^{n+1} and speed bound (used to skip distant contact work); a
+    // split brick's second workgroup keeps the box of its particles apart
+    // (brick_aabb joins the two)
     for (int q = 0; q < 7; q++) {
         float val = bb[q];
         auto mm = [&](float other) { val = (q < 3) ? fminf(val, other) : fmaxf(val, other); };
@@ -1127,7 +1136,7 @@ DEV void g2p_body(const SceneK& S, const SceneD& D, int bi, int cur)
     if (tid < 7) {
         float val = s_bb[0][tid];
         for (int wv = 1; wv < 8; wv++) val = (tid < 3) ? fminf(val, s_bb[wv][tid]) : fmaxf(val, s_bb[wv][tid]);
-        D.aabb[(long long)brick * 8 + tid] = val;
+        (part ? D.aabb_x : D.aabb)[(long long)brick * 8 + tid] = val;
         // the next binning's bin edge needs the largest speed bound; the maximum
         // of non-negative floats is taken on their bit patterns (order-independent)
         if (tid == 6 && S.material_contact && val > 0.0f)
@@ -1190,7 +1199,15 @@ DEV void cell_summaries(const SceneK& S, const SceneD& D, int bi, int brick)
         mixed |= cm;
     }
     const int m = __syncthreads_or(mixed);
-    if (threadIdx.x == 0) D.bmixed[brick] = m;
+    if (threadIdx.x == 0) {
+        D.bmixed[brick] = m;
+        if (!m) {
+            D.bround[bi] = 0; // no split workgroup for this brick
+        } else if (S.xcap > 0 && !D.xin[bi]) { // (codes only gain digits: once mixed, always mixed)
+            D.xin[bi] = 1;
+            D.xlist[atomicAdd(D.ctr + 3, 1)] = bi;
+        }
+    }
     if (!m) return;
     if (threadIdx.x < TL_CELLS) {
         const int c = threadIdx.x; // cell slot w * 8 + i
@@ -1298,8 +1315,9 @@ DEV void labels_body(const SceneK& S, const SceneD& D, int bi)
     __shared__ DevBlade s_bl[TL_MAX_TOOLS];
     __shared__ int s_nb;
     const int brick = D.active[bi];
-    const float* bb = D.aabb + (long long)brick * 8;
     if (threadIdx.x == 0) {
+        float bb[7];
+        brick_aabb(S, D, bi, brick, bb);
         int go = 0, nb = 0;
         for (int b = 0; b < n_tools; b++) {
             if (!(D.tools[b].flags & TL_TOOL_LABELS)) continue;
@@ -1567,29 +1585,82 @@ TL_WRAP(call_start, 64, , )
 // at most 80 VGPRs: three 512-thread workgroups per CU
 // Neo-Hookean: at most 80 VGPRs (three workgroups per CU); the general path (polar
 // decomposition) at most 128 (two)
-template <int MAT>
+// P2G and G2P launch, ahead of the one workgroup per brick, S.xcap workgroups for the
+// later rounds of the bricks in xlist (dispatched first so that these long ones start
+// early).  Bricks are split only while all mixed bricks of the scene have such a
+// workgroup (at most S.xcap of them); otherwise every brick keeps all its rounds, so
+// the results do not depend on the order of xlist.  Block b -> (active index, part);
+// -1: nothing to do.
+DEV int brick_of_block(const SceneK& S, const SceneD& D, int b, int j, int& part)
+{
+    if (j < 0) {
+        part = 0;
+        return b;
+    }
+    part = 1;
+    const int count = D.ctr[3];
+    return (j < count && count <= S.xcap) ? D.xlist[j] : -1;
+}
+
+// SPLIT false: one workgroup per brick, every brick keeps all its rounds (scenes with
+// S.xcap = 0, and batches of such scenes); true: the xcap extra workgroups first.
+template <int MAT, bool SPLIT>
 __global__ __launch_bounds__(TL_WG) __attribute__((amdgpu_waves_per_eu(MAT == 0 ? 6 : 4))) void k_p2g(SceneK S,
                                                                                                      SceneD D,
                                                                                                      KA_Args A)
 {
-    p2g_body<MAT>(S, D, blockIdx.x, A);
+    const int b = blockIdx.x;
+    if constexpr (!SPLIT) {
+        p2g_body<MAT, false>(S, D, b, A, 0);
+    } else {
+        int part;
+        const int bi = brick_of_block(S, D, b - S.xcap, b < S.xcap ? b : -1, part);
+        if (bi >= 0) p2g_body<MAT, true>(S, D, bi, A, part);
+    }
 }
-template <int MAT>
+template <int MAT, bool SPLIT>
 __global__ __launch_bounds__(TL_WG) __attribute__((amdgpu_waves_per_eu(MAT == 0 ? 6 : 4))) void k_p2g_b(
-    const SceneK* __restrict__ Ks, const SceneD* __restrict__ Ds, const int2* __restrict__ it, KA_Args A)
+    const SceneK* __restrict__ Ks, const SceneD* __restrict__ Ds, const int2* __restrict__ it,
+    const int2* __restrict__ xit, int nx, KA_Args A)
 {
-    const int2 t = it[xcd_order(blockIdx.x, gridDim.x)];
-    p2g_body<MAT>(Ks[t.x], Ds[t.x], t.y, A);
+    const int b = blockIdx.x;
+    if constexpr (!SPLIT) {
+        const int2 t = it[xcd_order(b, gridDim.x)];
+        p2g_body<MAT, false>(Ks[t.x], Ds[t.x], t.y, A, 0);
+    } else {
+        const int2 t = b < nx ? xit[b] : it[xcd_order(b - nx, gridDim.x - nx)];
+        int part;
+        const int bi = brick_of_block(Ks[t.x], Ds[t.x], t.y, b < nx ? t.y : -1, part);
+        if (bi >= 0) p2g_body<MAT, true>(Ks[t.x], Ds[t.x], bi, A, part);
+    }
 }
+template <bool SPLIT>
 __global__ __launch_bounds__(TL_WG) void k_g2p(SceneK S, SceneD D, int cur)
 {
-    g2p_body(S, D, blockIdx.x, cur);
+    const int b = blockIdx.x;
+    if constexpr (!SPLIT) {
+        g2p_body<false>(S, D, b, cur, 0);
+    } else {
+        int part;
+        const int bi = brick_of_block(S, D, b - S.xcap, b < S.xcap ? b : -1, part);
+        if (bi >= 0) g2p_body<true>(S, D, bi, cur, part);
+    }
 }
+template <bool SPLIT>
 __global__ __launch_bounds__(TL_WG) void k_g2p_b(const SceneK* __restrict__ Ks, const SceneD* __restrict__ Ds,
-                                                 const int2* __restrict__ it, int cur)
+                                                 const int2* __restrict__ it, const int2* __restrict__ xit, int nx,
+                                                 int cur)
 {
-    const int2 t = it[xcd_order(blockIdx.x, gridDim.x)];
-    g2p_body(Ks[t.x], Ds[t.x], t.y, cur);
+    const int b = blockIdx.x;
+    if constexpr (!SPLIT) {
+        const int2 t = it[xcd_order(b, gridDim.x)];
+        g2p_body<false>(Ks[t.x], Ds[t.x], t.y, cur, 0);
+    } else {
+        const int2 t = b < nx ? xit[b] : it[xcd_order(b - nx, gridDim.x - nx)];
+        int part;
+        const int bi = brick_of_block(Ks[t.x], Ds[t.x], t.y, b < nx ? t.y : -1, part);
+        if (bi >= 0) g2p_body<true>(Ks[t.x], Ds[t.x], bi, cur, part);
+    }
 }
 
 // ------------------------------------------------------------------- launchers
@@ -1602,6 +1673,30 @@ static hipError_t tl_run(const TlLaunch& L, int kind, int plain_blocks, int thre
     } else {
         if (L.n_items[kind] <= 0) return hipSuccess;
         hipLaunchKernelGGL(kb, dim3(L.n_items[kind]), dim3(threads), 0, L.st, L.Ks, L.Ds, L.items[kind], args...);
+    }
+    return hipGetLastError();
+}
+
+// one workgroup per brick, plus (split kernels) the workgroups of the split bricks'
+// later rounds
+template <class KP, class KB, class KPX, class KBX, class... Args>
+static hipError_t tl_run_split(const TlLaunch& L, KP kp, KB kb, KPX kpx, KBX kbx, Args... args)
+{
+    if (L.S) {
+        if (L.D->n_active <= 0) return hipSuccess;
+        if (L.S->xcap > 0)
+            hipLaunchKernelGGL(kpx, dim3(L.S->xcap + L.D->n_active), dim3(TL_WG), 0, L.st, *L.S, *L.D, args...);
+        else
+            hipLaunchKernelGGL(kp, dim3(L.D->n_active), dim3(TL_WG), 0, L.st, *L.S, *L.D, args...);
+    } else {
+        if (L.n_items[IT_BRICK] <= 0) return hipSuccess;
+        const int nx = L.n_items[IT_XBRICK];
+        if (nx > 0)
+            hipLaunchKernelGGL(kbx, dim3(nx + L.n_items[IT_BRICK]), dim3(TL_WG), 0, L.st, L.Ks, L.Ds,
+                               L.items[IT_BRICK], L.items[IT_XBRICK], nx, args...);
+        else
+            hipLaunchKernelGGL(kb, dim3(L.n_items[IT_BRICK]), dim3(TL_WG), 0, L.st, L.Ks, L.Ds, L.items[IT_BRICK],
+                               L.items[IT_XBRICK], 0, args...);
     }
     return hipGetLastError();
 }
@@ -1628,13 +1723,14 @@ hipError_t tl_launch_p2g(const TlLaunch* L, int do_p2g, int tabs_differ, int cur
     A.tabs_differ = tabs_differ;
     A.cur = cur;
     A.rsb = rsb;
-    if (L->general) return tl_run(*L, IT_BRICK, plain_bricks(*L), TL_WG, k_p2g<1>, k_p2g_b<1>, A);
-    return tl_run(*L, IT_BRICK, plain_bricks(*L), TL_WG, k_p2g<0>, k_p2g_b<0>, A);
+    if (L->general)
+        return tl_run_split(*L, k_p2g<1, false>, k_p2g_b<1, false>, k_p2g<1, true>, k_p2g_b<1, true>, A);
+    return tl_run_split(*L, k_p2g<0, false>, k_p2g_b<0, false>, k_p2g<0, true>, k_p2g_b<0, true>, A);
 }
 
 hipError_t tl_launch_g2p(const TlLaunch* L, int cur)
 {
-    return tl_run(*L, IT_BRICK, plain_bricks(*L), TL_WG, k_g2p, k_g2p_b, cur);
+    return tl_run_split(*L, k_g2p<false>, k_g2p_b<false>, k_g2p<true>, k_g2p_b<true>, cur);
 }
 
 hipError_t tl_launch_labels(const TlLaunch* L)

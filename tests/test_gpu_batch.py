@@ -164,3 +164,25 @@ def test_batch_isolates_a_failing_scene(tl):
     for i in (0, 2):
         assert gs[i].status() == 0
         _same(gs[i].read(FIELDS), alone[i])
+
+
+def test_batch_equals_alone_with_split_bricks(tl):
+    """Scenes of 256+ bricks run their mixed bricks' later rounds in workgroups of
+    their own, alone and in a batch (with a small scene that does not): the batch
+    still equals the runs alone bitwise."""
+    scenes = [W.batch_scene(11, 0, 120000, steps=40), W.batch_scene(11, 1, 4000, steps=40),
+              W.batch_scene(11, 2, 200000, steps=40)]
+    K = 20
+    _print_case("batch_split", n=[s["X"].shape[0] for s in scenes], steps=K)
+    alone = []
+    for s in scenes:
+        g, ws = _run_alone(tl, s, 0, K)
+        assert g.status() == 0
+        alone.append(g.read(FIELDS))
+        g.close()
+    gs = [tl.Scene(s) for s in scenes]
+    with tl.Batch(gs) as b:
+        _run_batch(tl, b, scenes, 0, K)
+    for i, g in enumerate(gs):
+        assert g.status() == 0, i
+        _same(g.read(FIELDS), alone[i])
