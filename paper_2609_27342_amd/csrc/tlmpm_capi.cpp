@@ -544,12 +544,12 @@ extern "C" tlmpm_status tlmpm_create_scene(const tlmpm_scene_desc* d, void* ws, 
     K.stencil = d->stencil;
     // workgroups for the later rounds of bricks with a mixed cell: a quarter of the
     // bricks, at most 256 (with more mixed bricks no brick is split).  Only scenes of
-    // 256 to 4096 active bricks split: their launches are about one round of
+    // 512 to 4096 active bricks split: their launches are about one round of
     // workgroups on the GPU, so a brick with extra rounds lengthens the whole launch;
-    // smaller scenes (batches) and larger ones measured slower with the extra launch
-    // slots than the rounds cost.
+    // smaller scenes (the many-scene batches) and larger ones measured slower with the
+    // extra launch slots than the rounds cost.
     const size_t na = active.size();
-    K.xcap = (na >= 256 && na <= 4096) ? (int)std::min<size_t>(256, na / 4) : 0;
+    K.xcap = (na >= 512 && na <= 4096) ? (int)std::min<size_t>(256, na / 4) : 0;
     float vmax0 = d->vol0_uniform;
     if (d->vol0)
         for (long long p = 0; p < N; p++) vmax0 = std::max(vmax0, d->vol0[p]);

@@ -167,11 +167,11 @@ def test_batch_isolates_a_failing_scene(tl):
 
 
 def test_batch_equals_alone_with_split_bricks(tl):
-    """Scenes of 256+ bricks run their mixed bricks' later rounds in workgroups of
+    """Scenes of 512+ bricks run their mixed bricks' later rounds in workgroups of
     their own, alone and in a batch (with a small scene that does not): the batch
     still equals the runs alone bitwise."""
-    scenes = [W.batch_scene(11, 0, 120000, steps=40), W.batch_scene(11, 1, 4000, steps=40),
-              W.batch_scene(11, 2, 200000, steps=40)]
+    scenes = [W.batch_scene(11, 0, 280000, steps=40), W.batch_scene(11, 1, 4000, steps=40),
+              W.batch_scene(11, 2, 320000, steps=40)]
     K = 20
     _print_case("batch_split", n=[s["X"].shape[0] for s in scenes], steps=K)
     alone = []
