@@ -31,6 +31,8 @@ hipError_t tl_launch_call_start(const TlLaunch*);
 hipError_t tl_launch_cellmask(const TlLaunch*, int with_static, int force);
 hipError_t tl_launch_cand(const TlLaunch*, int force);
 hipError_t tl_launch_contact(const TlLaunch*);
+hipError_t tl_launch_labels_rigid(const TlLaunch*);
+hipError_t tl_launch_contact_slots(const TlLaunch*, int dst, int src);
 hipError_t tl_launch_fill_f32(float*, long long, float, hipStream_t);
 hipError_t tl_launch_fill_i32(int*, long long, int, hipStream_t);
 hipError_t tl_launch_quad(const TlLaunch*, int par, int stage);
@@ -915,33 +917,59 @@ static tlmpm_status one_substep_quad(Exec& X, const CallFlags& f, bool first)
     return TLMPM_OK;
 }
 
+// A substep of one scene with a label pass, untimed: one stream, with the label pass
+// and rigid contact in one launch and the slot tables in the launch of the pair
+// search (each pair touches disjoint arrays), instead of the second stream, whose
+// fork and join events cost more than the launches they overlap.  Batches keep the
+// second stream: their launches are long, and the fused pair launch measured slower.
+static tlmpm_status fused_label_substep(Exec& X, const CallFlags& f)
+{
+    HIPCHK(f.any_rigid ? tl_launch_labels_rigid(&X.L) : tl_launch_labels(&X.L));
+    // a pending F update still needs the tables of its re-scatter
+    const int dst = (X.pending && X.cur == X.rsb) ? 1 - X.cur : X.cur;
+    if (X.L.any_material) {
+        HIPCHK(tl_launch_cand(&X.L, 0));
+        HIPCHK(tl_launch_contact_slots(&X.L, dst, X.cur));
+    } else {
+        HIPCHK(tl_launch_slots(&X.L, dst, X.cur, 0));
+    }
+    X.cur = dst;
+    return TLMPM_OK;
+}
+
 static tlmpm_status one_substep(Exec& X, const CallFlags& f, bool first)
 {
     if (X.L.S && X.L.S->stencil == 1) return one_substep_quad(X, f, first);
+    const bool fused = f.any_labels && X.L.S && !(X.prof && X.prof->on);
     Side side(X);
-    side.par = side.par && X.L.any_material;
+    side.par = side.par && X.L.any_material && !fused;
     const bool reset_D = f.any_labels && f.any_new && first;
     if (reset_D) {
         ProfScope ps(X.prof, 5);
         HIPCHK(tl_launch_resetD(&X.L));
     }
-    if (f.any_rigid && side.par) {
-        HIPCHK(side.after_main(0));
-        HIPCHK(tl_launch_rigid(&side.La));
-    }
-    if (f.any_labels) {
-        tlmpm_status s = label_pass(X, false, side.par ? &side : nullptr);
+    if (fused) {
+        tlmpm_status s = fused_label_substep(X, f);
         if (s) return s;
+    } else {
+        if (f.any_rigid && side.par) {
+            HIPCHK(side.after_main(0));
+            HIPCHK(tl_launch_rigid(&side.La));
+        }
+        if (f.any_labels) {
+            tlmpm_status s = label_pass(X, false, side.par ? &side : nullptr);
+            if (s) return s;
+        }
+        if (X.L.any_material) {
+            ProfScope ps(X.prof, 4);
+            HIPCHK(tl_launch_contact(&X.L));
+        }
+        if (f.any_rigid && !side.par) {
+            ProfScope ps(X.prof, 5);
+            HIPCHK(tl_launch_rigid(&X.L));
+        }
+        HIPCHK(side.join());
     }
-    if (X.L.any_material) {
-        ProfScope ps(X.prof, 4);
-        HIPCHK(tl_launch_contact(&X.L));
-    }
-    if (f.any_rigid && !side.par) {
-        ProfScope ps(X.prof, 5);
-        HIPCHK(tl_launch_rigid(&X.L));
-    }
-    HIPCHK(side.join());
     {
         ProfScope ps(X.prof, 0);
         HIPCHK(tl_launch_p2g(&X.L, 1, X.cur != X.rsb ? 1 : 0, X.cur, X.rsb));

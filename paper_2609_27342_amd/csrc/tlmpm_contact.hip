@@ -23,8 +23,7 @@
 #include <stdint.h>
 
 #include "tlmpm_common.h"
-
-#define DEV __device__ __forceinline__
+#include "tlmpm_device.h"
 
 DEV uint32_t ckey(const SceneK& S, uint32_t code) { return S.single_field ? 0u : (code & TL_CODE_MASK); }
 
@@ -691,6 +690,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     const int2 t = it[blockIdx.x];
     pairs_body(Ks[t.x], Ds[t.x], t.y);
 }
+// The slot-table pass and the pair search in one launch: the first nn blocks build
+// slot tables (dispatched first: the pair blocks alone fill the chip, and stride over
+// the candidates whenever they start), the others search pairs.  The two touch
+// disjoint arrays (the slot pass reads the codes without the candidate bit), so they
+// need no order; one launch replaces a second stream and the events that fork and
+// join it.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_pairs_slots(SceneK S, SceneD D,
+                                                                                           int nn, int dst, int src)
+{
+    if ((int)blockIdx.x < nn)
+        slots_body(S, D, blockIdx.x, dst, src, 0);
+    else
+        pairs_body(S, D, blockIdx.x - nn);
+}
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_pairs_slots_b(
+    const SceneK* __restrict__ Ks, const SceneD* __restrict__ Ds, const int2* __restrict__ itn,
+    const int2* __restrict__ itp, int nn, int dst, int src)
+{
+    const bool sl = (int)blockIdx.x < nn;
+    const int2 t = sl ? itn[blockIdx.x] : itp[blockIdx.x - nn];
+    if (sl)
+        slots_body(Ks[t.x], Ds[t.x], t.y, dst, src, 0);
+    else
+        pairs_body(Ks[t.x], Ds[t.x], t.y);
+}
 __global__ __launch_bounds__(TL_SCAN_T) void k_cscan(SceneK S, SceneD D) { cscan_body(S, D, 0); }
 __global__ __launch_bounds__(TL_SCAN_T) void k_cscan_b(const SceneK* __restrict__ Ks, const SceneD* __restrict__ Ds,
                                                        const int2* __restrict__ it)
@@ -743,5 +767,31 @@ hipError_t tl_launch_contact(const TlLaunch* L)
     hipError_t e = tl_run(*L, IT_BRICK, nbrick, k_bin_insert, k_bin_insert_b);
     if (e != hipSuccess) return e;
     return tl_run(*L, IT_PAIR, L->S ? L->S->pair_blocks : 0, k_pairs, k_pairs_b);
+}
+
+hipError_t tl_launch_slots(const TlLaunch* L, int dst, int src, int force);
+
+// binning, then pairs together with the slot tables dst (built from src)
+hipError_t tl_launch_contact_slots(const TlLaunch* L, int dst, int src)
+{
+    int np, nn;
+    if (L->S) {
+        const int nbrick = L->D->n_active;
+        if (nbrick == 0) return tl_launch_slots(L, dst, src, 0);
+        np = L->S->pair_blocks;
+        nn = (int)((L->S->NN + 255) / 256);
+    } else {
+        np = L->n_items[IT_PAIR];
+        nn = L->n_items[IT_NODE];
+    }
+    hipError_t e = tl_run(*L, IT_BRICK, L->S ? L->D->n_active : 0, k_bin_insert, k_bin_insert_b);
+    if (e != hipSuccess) return e;
+    if (np + nn <= 0) return hipSuccess;
+    if (L->S)
+        hipLaunchKernelGGL(k_pairs_slots, dim3(nn + np), dim3(256), 0, L->st, *L->S, *L->D, nn, dst, src);
+    else
+        hipLaunchKernelGGL(k_pairs_slots_b, dim3(nn + np), dim3(256), 0, L->st, L->Ks, L->Ds, L->items[IT_NODE],
+                           L->items[IT_PAIR], nn, dst, src);
+    return hipGetLastError();
 }
 }

@@ -1,6 +1,7 @@
 // tlmpm_device.h -- device functions shared by the trilinear (tlmpm_kernels.hip)
-// and quadratic (tlmpm_quad.hip) transfer kernels: side codes, the LDS barrier and
-// the constitutive models.
+// and quadratic (tlmpm_quad.hip) transfer kernels and the contact kernels
+// (tlmpm_contact.hip): side codes, the LDS barrier, the constitutive models and the
+// slot-table pass (launched alone or beside the pair search).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -319,3 +320,89 @@ DEV bool vm_project(float E, float nu, float sigma_y, float* K, float* G)
     return true;
 }
 
+// ------------------------------------------------------------------- slot tables
+// For every node: the distinct codes of the particles in its 8 incident cells, in
+// ascending order (compact slots, Sec. III-G).  Skipped (count copied) when the
+// labels did not change since the source table was built.
+DEV void slots_body(const SceneK& S, const SceneD& D, int bi, int dst, int src, int force)
+{
+    const long long id = (long long)bi * blockDim.x + threadIdx.x;
+    if (id >= S.NN) return;
+    long long nb = id >> 6;
+    int lid = (int)(id & 63);
+    int hx = (int)(nb % S.nbx), hy = (int)((nb / S.nbx) % S.nby), hz = (int)(nb / ((long long)S.nbx * S.nby));
+    bool rebuild = force != 0;
+    const int stamp = D.ctr[0];
+    if (!rebuild) {
+        // a node depends on the cells of bricks h - {0,1}^3
+        int any = 0;
+#pragma unroll
+        for (int d = 0; d < 8; d++) {
+            int bx = hx - (d & 1), by = hy - ((d >> 1) & 1), bz = hz - ((d >> 2) & 1);
+            if (bx < 0 || by < 0 || bz < 0 || bx >= S.cbx || by >= S.cby || bz >= S.cbz) continue;
+            any |= D.bdirty[((long long)bz * S.cby + by) * S.cbx + bx] == stamp;
+        }
+        rebuild = any != 0;
+    }
+    if (!rebuild) {
+        if (dst != src) {
+            int c = D.cnt[src][id];
+            D.cnt[dst][id] = (uint8_t)c;
+            for (int s = 0; s < c; s++) D.scode[dst][s * S.NN + id] = D.scode[src][s * S.NN + id];
+        }
+        return;
+    }
+    int gx = hx * 4 + (lid & 3), gy = hy * 4 + ((lid >> 2) & 3), gz = hz * 4 + (lid >> 4);
+    uint32_t codes[TL_SCAP_MAX];
+    int c = 0;
+    bool over = false;
+    auto insert = [&](uint32_t k) {
+        int pos = 0;
+        while (pos < c && codes[pos] < k) pos++;
+        if (pos < c && codes[pos] == k) return;
+        if (c == S.scap) {
+            over = true;
+            return;
+        }
+        for (int q = c; q > pos; q--) codes[q] = codes[q - 1];
+        codes[pos] = k;
+        c++;
+    };
+    if (gx <= S.cx && gy <= S.cy && gz <= S.cz) {
+        // the 8 incident cells: their one-key summaries, all loaded before use
+        long long cell[8];
+        uint32_t cc[8];
+#pragma unroll
+        for (int d = 0; d < 8; d++) {
+            int x = gx - (d & 1), y = gy - ((d >> 1) & 1), z = gz - ((d >> 2) & 1);
+            cell[d] = -1;
+            cc[d] = TL_CC_EMPTY;
+            if (x < 0 || y < 0 || z < 0 || x >= S.cx || y >= S.cy || z >= S.cz) continue;
+            long long brick = ((long long)(z >> 2) * S.cby + (y >> 2)) * S.cbx + (x >> 2);
+            int lx = x & 3, ly = y & 3, lz = z & 3;
+            int w = (lx & 1) | ((ly & 1) << 1) | ((lz & 1) << 2);
+            int i = (lx >> 1) | ((ly >> 1) << 1) | ((lz >> 1) << 2);
+            cell[d] = brick * TL_CELLS + w * 8 + i;
+            cc[d] = D.ccode[cell[d]];
+        }
+        for (int d = 0; d < 8; d++) {
+            if (cc[d] == TL_CC_EMPTY) continue;
+            if (cc[d] < TL_CC_FEW) {
+                insert(cc[d]);
+            } else if (cc[d] != TL_CC_MIXED) {
+                const int n = (int)(cc[d] & 7u);
+                uint32_t kk[TL_CKEYS];
+#pragma unroll
+                for (int k = 0; k < TL_CKEYS; k++) kk[k] = k < n ? D.ckeys[cell[d] * TL_CKEYS + k] : 0u;
+#pragma unroll
+                for (int k = 0; k < TL_CKEYS; k++)
+                    if (k < n) insert(kk[k]);
+            } else {
+                for (int p = D.cell_start[cell[d]]; p < D.cell_start[cell[d] + 1]; p++) insert(slot_key(S, D.code[p]));
+            }
+        }
+    }
+    if (over) atomicOr(D.status, TL_ST_SLOT);
+    D.cnt[dst][id] = (uint8_t)c;
+    for (int s = 0; s < c; s++) D.scode[dst][s * S.NN + id] = codes[s];
+}

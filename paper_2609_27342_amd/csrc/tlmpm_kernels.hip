@@ -1366,93 +1366,6 @@ DEV void labels_body(const SceneK& S, const SceneD& D, int bi)
     }
 }
 
-// ------------------------------------------------------------------- slot tables
-// For every node: the distinct codes of the particles in its 8 incident cells, in
-// ascending order (compact slots, Sec. III-G).  Skipped (count copied) when the
-// labels did not change since the source table was built.
-DEV void slots_body(const SceneK& S, const SceneD& D, int bi, int dst, int src, int force)
-{
-    const long long id = (long long)bi * blockDim.x + threadIdx.x;
-    if (id >= S.NN) return;
-    long long nb = id >> 6;
-    int lid = (int)(id & 63);
-    int hx = (int)(nb % S.nbx), hy = (int)((nb / S.nbx) % S.nby), hz = (int)(nb / ((long long)S.nbx * S.nby));
-    bool rebuild = force != 0;
-    const int stamp = D.ctr[0];
-    if (!rebuild) {
-        // a node depends on the cells of bricks h - {0,1}^3
-        int any = 0;
-#pragma unroll
-        for (int d = 0; d < 8; d++) {
-            int bx = hx - (d & 1), by = hy - ((d >> 1) & 1), bz = hz - ((d >> 2) & 1);
-            if (bx < 0 || by < 0 || bz < 0 || bx >= S.cbx || by >= S.cby || bz >= S.cbz) continue;
-            any |= D.bdirty[((long long)bz * S.cby + by) * S.cbx + bx] == stamp;
-        }
-        rebuild = any != 0;
-    }
-    if (!rebuild) {
-        if (dst != src) {
-            int c = D.cnt[src][id];
-            D.cnt[dst][id] = (uint8_t)c;
-            for (int s = 0; s < c; s++) D.scode[dst][s * S.NN + id] = D.scode[src][s * S.NN + id];
-        }
-        return;
-    }
-    int gx = hx * 4 + (lid & 3), gy = hy * 4 + ((lid >> 2) & 3), gz = hz * 4 + (lid >> 4);
-    uint32_t codes[TL_SCAP_MAX];
-    int c = 0;
-    bool over = false;
-    auto insert = [&](uint32_t k) {
-        int pos = 0;
-        while (pos < c && codes[pos] < k) pos++;
-        if (pos < c && codes[pos] == k) return;
-        if (c == S.scap) {
-            over = true;
-            return;
-        }
-        for (int q = c; q > pos; q--) codes[q] = codes[q - 1];
-        codes[pos] = k;
-        c++;
-    };
-    if (gx <= S.cx && gy <= S.cy && gz <= S.cz) {
-        // the 8 incident cells: their one-key summaries, all loaded before use
-        long long cell[8];
-        uint32_t cc[8];
-#pragma unroll
-        for (int d = 0; d < 8; d++) {
-            int x = gx - (d & 1), y = gy - ((d >> 1) & 1), z = gz - ((d >> 2) & 1);
-            cell[d] = -1;
-            cc[d] = TL_CC_EMPTY;
-            if (x < 0 || y < 0 || z < 0 || x >= S.cx || y >= S.cy || z >= S.cz) continue;
-            long long brick = ((long long)(z >> 2) * S.cby + (y >> 2)) * S.cbx + (x >> 2);
-            int lx = x & 3, ly = y & 3, lz = z & 3;
-            int w = (lx & 1) | ((ly & 1) << 1) | ((lz & 1) << 2);
-            int i = (lx >> 1) | ((ly >> 1) << 1) | ((lz >> 1) << 2);
-            cell[d] = brick * TL_CELLS + w * 8 + i;
-            cc[d] = D.ccode[cell[d]];
-        }
-        for (int d = 0; d < 8; d++) {
-            if (cc[d] == TL_CC_EMPTY) continue;
-            if (cc[d] < TL_CC_FEW) {
-                insert(cc[d]);
-            } else if (cc[d] != TL_CC_MIXED) {
-                const int n = (int)(cc[d] & 7u);
-                uint32_t kk[TL_CKEYS];
-#pragma unroll
-                for (int k = 0; k < TL_CKEYS; k++) kk[k] = k < n ? D.ckeys[cell[d] * TL_CKEYS + k] : 0u;
-#pragma unroll
-                for (int k = 0; k < TL_CKEYS; k++)
-                    if (k < n) insert(kk[k]);
-            } else {
-                for (int p = D.cell_start[cell[d]]; p < D.cell_start[cell[d] + 1]; p++) insert(slot_key(S, D.code[p]));
-            }
-        }
-    }
-    if (over) atomicOr(D.status, TL_ST_SLOT);
-    D.cnt[dst][id] = (uint8_t)c;
-    for (int s = 0; s < c; s++) D.scode[dst][s * S.NN + id] = codes[s];
-}
-
 // --------------------------------------------------------------- small kernels
 // D := 0 for a new cut (Sec. III-A), over particle block bi
 DEV void resetD_body(const SceneK& S, const SceneD& D, int bi)
@@ -1581,6 +1494,28 @@ TL_WRAP(aabb, 256, , )
 TL_WRAP(wrench, 256, , )
 TL_WRAP(resetD, 256, , )
 TL_WRAP(call_start, 64, , )
+
+// The label pass and rigid contact in one launch: blocks below nl take the label
+// pass of a brick, the others its rigid contact.  Rigid contact reads only the last
+// substep's motion, the tools and the cutting progress, none of which the label pass
+// writes, and the label pass reads nothing rigid contact writes.
+__global__ __launch_bounds__(256) void k_labels_rigid(SceneK S, SceneD D, int nl)
+{
+    if ((int)blockIdx.x < nl)
+        labels_body(S, D, blockIdx.x);
+    else
+        rigid_body(S, D, blockIdx.x - nl);
+}
+__global__ __launch_bounds__(256) void k_labels_rigid_b(const SceneK* __restrict__ Ks, const SceneD* __restrict__ Ds,
+                                                        const int2* __restrict__ it, int nl)
+{
+    const bool lb = (int)blockIdx.x < nl;
+    const int2 t = it[lb ? blockIdx.x : blockIdx.x - nl];
+    if (lb)
+        labels_body(Ks[t.x], Ds[t.x], t.y);
+    else
+        rigid_body(Ks[t.x], Ds[t.x], t.y);
+}
 
 // at most 80 VGPRs: three 512-thread workgroups per CU
 // Neo-Hookean: at most 80 VGPRs (three workgroups per CU); the general path (polar
@@ -1736,6 +1671,17 @@ hipError_t tl_launch_g2p(const TlLaunch* L, int cur)
 hipError_t tl_launch_labels(const TlLaunch* L)
 {
     return tl_run(*L, IT_BRICK, plain_bricks(*L), 256, k_labels, k_labels_b);
+}
+
+hipError_t tl_launch_labels_rigid(const TlLaunch* L)
+{
+    const int n = L->S ? plain_bricks(*L) : L->n_items[IT_BRICK];
+    if (n <= 0) return hipSuccess;
+    if (L->S)
+        hipLaunchKernelGGL(k_labels_rigid, dim3(2 * n), dim3(256), 0, L->st, *L->S, *L->D, n);
+    else
+        hipLaunchKernelGGL(k_labels_rigid_b, dim3(2 * n), dim3(256), 0, L->st, L->Ks, L->Ds, L->items[IT_BRICK], n);
+    return hipGetLastError();
 }
 
 hipError_t tl_launch_slots(const TlLaunch* L, int dst, int src, int force)
