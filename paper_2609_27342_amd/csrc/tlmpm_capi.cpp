@@ -32,7 +32,7 @@ hipError_t tl_launch_cellmask(const TlLaunch*, int with_static, int force);
 hipError_t tl_launch_cand(const TlLaunch*, int force);
 hipError_t tl_launch_contact(const TlLaunch*);
 hipError_t tl_launch_labels_rigid(const TlLaunch*);
-hipError_t tl_launch_contact_slots(const TlLaunch*, int dst, int src);
+hipError_t tl_launch_cand_contact_slots(const TlLaunch*, int dst, int src);
 hipError_t tl_launch_fill_f32(float*, long long, float, hipStream_t);
 hipError_t tl_launch_fill_i32(int*, long long, int, hipStream_t);
 hipError_t tl_launch_quad(const TlLaunch*, int par, int stage);
@@ -920,7 +920,8 @@ static tlmpm_status one_substep_quad(Exec& X, const CallFlags& f, bool first)
 // A substep of one scene with a label pass, untimed: one stream, with the label pass
 // and rigid contact in one launch and the slot tables in the launch of the pair
 // search (each pair touches disjoint arrays), instead of the second stream, whose
-// fork and join events cost more than the launches they overlap.  Only scenes of at
+// fork and join events cost more than the launches they overlap; the binning blocks
+// sum the candidate offsets themselves (no scan launch).  Only scenes of at
 // most TL_FUSE_BRICKS active bricks: there the two launches of a pair fit the chip
 // side by side; a large scene (27k bricks) measured slower fused (labels and rigid
 // contact 0.22 ms against 0.06 ms with rigid contact beside it), and batches keep the
@@ -933,8 +934,7 @@ static tlmpm_status fused_label_substep(Exec& X, const CallFlags& f)
     // a pending F update still needs the tables of its re-scatter
     const int dst = (X.pending && X.cur == X.rsb) ? 1 - X.cur : X.cur;
     if (X.L.any_material) {
-        HIPCHK(tl_launch_cand(&X.L, 0));
-        HIPCHK(tl_launch_contact_slots(&X.L, dst, X.cur));
+        HIPCHK(tl_launch_cand_contact_slots(&X.L, dst, X.cur));
     } else {
         HIPCHK(tl_launch_slots(&X.L, dst, X.cur, 0));
     }

@@ -249,19 +249,39 @@ DEV void make_rec(const SceneK& S, const SceneD& D, int p, const float x[3], flo
 // are kept in arrival order, later candidates go to a lock-free overflow list
 // (generation-stamped heads, never cleared).  The pair pass sorts a bucket's
 // numbers before use, so its result does not depend on the arrival order.
-DEV void bin_insert_body(const SceneK& S, const SceneD& D, int bi)
+// self_scan: the block sums the candidate counts of the bricks before it itself (no
+// scan launch; each block reads up to n_active counts, so only for scenes of few
+// bricks), and the last brick's block writes the total for the pair pass.
+DEV void bin_insert_body(const SceneK& S, const SceneD& D, int bi, int self_scan = 0)
 {
     if (!S.material_contact) return;
     const unsigned gen = (unsigned)D.ctr[0];
     const int brick = D.active[bi];
     const int nc = D.bcand[bi];
-    if (!nc && bi != 0) return;
+    const bool last = self_scan && bi == D.n_active - 1;
+    if (!nc && bi != 0 && !last) return;
     const float hb = bin_edge(S, D);
     if (bi == 0 && threadIdx.x == 0) D.hbin[0] = hb; // for the pair pass
+    int g0;
+    if (self_scan) {
+        __shared__ int s_sum[4];
+        int a = 0;
+        for (int i = threadIdx.x; i < bi; i += blockDim.x) a += D.bcand[i];
+        for (int o = 32; o >= 1; o >>= 1) a += __shfl_xor(a, o, 64);
+        if ((threadIdx.x & 63) == 0) s_sum[threadIdx.x >> 6] = a;
+        __syncthreads();
+        g0 = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); w++) g0 += s_sum[w];
+        if (threadIdx.x == 0) {
+            D.coff[bi] = g0;
+            if (last) D.coff[bi + 1] = g0 + nc;
+        }
+    } else {
+        g0 = D.coff[bi];
+    }
     if (!nc) return;
     const float inv_h = 1.0f / hb;
     const int beg = D.cell_start[(long long)brick * TL_CELLS];
-    const int g0 = D.coff[bi];
     int* bcount = D.bcount + (gen & 1u) * ((long long)D.hmask + 1); // this substep's counts
     for (int c = threadIdx.x; c < nc; c += blockDim.x) {
         const int p = D.cand_idx[beg + c];
@@ -679,6 +699,7 @@ DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
 TL_WRAP(cellmask, TL_COMMA int with_static TL_COMMA int force, TL_COMMA with_static TL_COMMA force)
 TL_WRAP(cand, TL_COMMA int force, TL_COMMA force)
 TL_WRAP(bin_insert, , )
+__global__ __launch_bounds__(256) void k_bin_insert_scan(SceneK S, SceneD D) { bin_insert_body(S, D, blockIdx.x, 1); }
 // at most 128 VGPRs: four waves per SIMD
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_pairs(SceneK S, SceneD D)
 {
@@ -703,17 +724,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         slots_body(S, D, blockIdx.x, dst, src, 0);
     else
         pairs_body(S, D, blockIdx.x - nn);
-}
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_pairs_slots_b(
-    const SceneK* __restrict__ Ks, const SceneD* __restrict__ Ds, const int2* __restrict__ itn,
-    const int2* __restrict__ itp, int nn, int dst, int src)
-{
-    const bool sl = (int)blockIdx.x < nn;
-    const int2 t = sl ? itn[blockIdx.x] : itp[blockIdx.x - nn];
-    if (sl)
-        slots_body(Ks[t.x], Ds[t.x], t.y, dst, src, 0);
-    else
-        pairs_body(Ks[t.x], Ds[t.x], t.y);
 }
 __global__ __launch_bounds__(TL_SCAN_T) void k_cscan(SceneK S, SceneD D) { cscan_body(S, D, 0); }
 __global__ __launch_bounds__(TL_SCAN_T) void k_cscan_b(const SceneK* __restrict__ Ks, const SceneD* __restrict__ Ds,
@@ -771,27 +781,19 @@ hipError_t tl_launch_contact(const TlLaunch* L)
 
 hipError_t tl_launch_slots(const TlLaunch* L, int dst, int src, int force);
 
-// binning, then pairs together with the slot tables dst (built from src)
-hipError_t tl_launch_contact_slots(const TlLaunch* L, int dst, int src)
+// One scene of few bricks, substep with a label pass: candidates, binning with the
+// candidate offsets summed per block (no scan launch), then pairs together with the
+// slot tables dst (built from src).
+hipError_t tl_launch_cand_contact_slots(const TlLaunch* L, int dst, int src)
 {
-    int np, nn;
-    if (L->S) {
-        const int nbrick = L->D->n_active;
-        if (nbrick == 0) return tl_launch_slots(L, dst, src, 0);
-        np = L->S->pair_blocks;
-        nn = (int)((L->S->NN + 255) / 256);
-    } else {
-        np = L->n_items[IT_PAIR];
-        nn = L->n_items[IT_NODE];
-    }
-    hipError_t e = tl_run(*L, IT_BRICK, L->S ? L->D->n_active : 0, k_bin_insert, k_bin_insert_b);
-    if (e != hipSuccess) return e;
-    if (np + nn <= 0) return hipSuccess;
-    if (L->S)
-        hipLaunchKernelGGL(k_pairs_slots, dim3(nn + np), dim3(256), 0, L->st, *L->S, *L->D, nn, dst, src);
-    else
-        hipLaunchKernelGGL(k_pairs_slots_b, dim3(nn + np), dim3(256), 0, L->st, L->Ks, L->Ds, L->items[IT_NODE],
-                           L->items[IT_PAIR], nn, dst, src);
+    if (!L->S) return hipErrorInvalidValue;
+    const int nbrick = L->D->n_active;
+    if (nbrick == 0) return tl_launch_slots(L, dst, src, 0);
+    const int np = L->S->pair_blocks;
+    const int nn = (int)((L->S->NN + 255) / 256);
+    hipLaunchKernelGGL(k_cand, dim3(nbrick), dim3(256), 0, L->st, *L->S, *L->D, 0);
+    hipLaunchKernelGGL(k_bin_insert_scan, dim3(nbrick), dim3(256), 0, L->st, *L->S, *L->D);
+    hipLaunchKernelGGL(k_pairs_slots, dim3(nn + np), dim3(256), 0, L->st, *L->S, *L->D, nn, dst, src);
     return hipGetLastError();
 }
 }
