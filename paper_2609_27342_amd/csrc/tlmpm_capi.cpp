@@ -878,21 +878,35 @@ struct CallFlags {
 // one substep with the quadratic stencil: labels and contact as in the trilinear
 // path, then the transfers of tlmpm_quad.hip with the node tables of parity X.cur
 // (flipped every substep); the F update completes inside the substep.
+// Scenes of at most this many active bricks run a substep with a label pass on one
+// stream (see fused_label_substep).
+static const int TL_FUSE_BRICKS = 2048;
+
+static bool one_stream(const Exec& X, const CallFlags& f)
+{
+    return f.any_labels && X.L.S && X.L.D->n_active <= TL_FUSE_BRICKS && !(X.prof && X.prof->on);
+}
+
 static tlmpm_status one_substep_quad(Exec& X, const CallFlags& f, bool first)
 {
+    const bool fused = one_stream(X, f); // label pass and rigid contact in one launch
     Side side(X);
-    side.par = side.par && X.L.any_material;
+    side.par = side.par && X.L.any_material && !fused;
     if (f.any_labels && f.any_new && first) {
         ProfScope ps(X.prof, 5);
         HIPCHK(tl_launch_resetD(&X.L));
     }
-    if (f.any_rigid && side.par) {
-        HIPCHK(side.after_main(0));
-        HIPCHK(tl_launch_rigid(&side.La));
-    }
-    if (f.any_labels) {
-        ProfScope ps(X.prof, 2);
-        HIPCHK(tl_launch_labels(&X.L));
+    if (fused) {
+        HIPCHK(f.any_rigid ? tl_launch_labels_rigid(&X.L) : tl_launch_labels(&X.L));
+    } else {
+        if (f.any_rigid && side.par) {
+            HIPCHK(side.after_main(0));
+            HIPCHK(tl_launch_rigid(&side.La));
+        }
+        if (f.any_labels) {
+            ProfScope ps(X.prof, 2);
+            HIPCHK(tl_launch_labels(&X.L));
+        }
     }
     {
         ProfScope ps(X.prof, 3);
@@ -903,7 +917,7 @@ static tlmpm_status one_substep_quad(Exec& X, const CallFlags& f, bool first)
         if (f.any_labels) HIPCHK(tl_launch_cand(&X.L, 0));
         HIPCHK(tl_launch_contact(&X.L));
     }
-    if (f.any_rigid && !side.par) {
+    if (f.any_rigid && !side.par && !fused) {
         ProfScope ps(X.prof, 5);
         HIPCHK(tl_launch_rigid(&X.L));
     }
@@ -926,8 +940,6 @@ static tlmpm_status one_substep_quad(Exec& X, const CallFlags& f, bool first)
 // side by side; a large scene (27k bricks) measured slower fused (labels and rigid
 // contact 0.22 ms against 0.06 ms with rigid contact beside it), and batches keep the
 // second stream as well.
-static const int TL_FUSE_BRICKS = 2048;
-
 static tlmpm_status fused_label_substep(Exec& X, const CallFlags& f)
 {
     HIPCHK(f.any_rigid ? tl_launch_labels_rigid(&X.L) : tl_launch_labels(&X.L));
@@ -945,8 +957,7 @@ static tlmpm_status fused_label_substep(Exec& X, const CallFlags& f)
 static tlmpm_status one_substep(Exec& X, const CallFlags& f, bool first)
 {
     if (X.L.S && X.L.S->stencil == 1) return one_substep_quad(X, f, first);
-    const bool fused =
-        f.any_labels && X.L.S && X.L.D->n_active <= TL_FUSE_BRICKS && !(X.prof && X.prof->on);
+    const bool fused = one_stream(X, f);
     Side side(X);
     side.par = side.par && X.L.any_material && !fused;
     const bool reset_D = f.any_labels && f.any_new && first;
