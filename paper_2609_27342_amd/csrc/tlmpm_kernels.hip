@@ -1214,26 +1214,40 @@ DEV void cell_summaries(const SceneK& S, const SceneD& D, int bi, int brick)
         const long long cs = (long long)brick * TL_CELLS + c;
         const int b0 = D.cell_start[cs], b1 = D.cell_start[cs + 1];
         int* meta = D.gmeta + ((long long)bi * TL_CELLS + c) * TL_GMAX;
-        int ng = 0, pos = 0;
+        const int n = b1 - b0;
+        // the keys of the cell's first TL_KC particles, loaded once (registers: every
+        // index below is a compile-time constant); the rest are read when needed
+        constexpr int TL_KC = 8;
+        uint32_t kc[TL_KC];
+#pragma unroll
+        for (int q = 0; q < TL_KC; q++) kc[q] = q < n ? slot_key(S, D.code[b0 + q]) : 0u;
+        int ng = 0, pos = 0, gstart = 0;
         uint32_t last = 0;
         bool first = true;
-        while (pos < b1 - b0) {
+        auto place = [&](int p) {
+            D.gperm[b0 + pos] = p;
+            pos++;
+            if (pos - gstart == 8) {
+                if (ng < TL_GMAX) meta[ng] = (gstart << 4) | 8;
+                ng++;
+                gstart = pos;
+            }
+        };
+        while (pos < n) {
             uint32_t kmin = 0xFFFFFFFFu; // smallest key above the last one
-            for (int p = b0; p < b1; p++) {
-                const uint32_t k = slot_key(S, D.code[p]);
+#pragma unroll
+            for (int q = 0; q < TL_KC; q++)
+                if (q < n && (first || kc[q] > last) && kc[q] < kmin) kmin = kc[q];
+            for (int q = TL_KC; q < n; q++) {
+                const uint32_t k = slot_key(S, D.code[b0 + q]);
                 if ((first || k > last) && k < kmin) kmin = k;
             }
-            int gstart = pos;
-            for (int p = b0; p < b1; p++) {
-                if (slot_key(S, D.code[p]) != kmin) continue;
-                D.gperm[b0 + pos] = p;
-                pos++;
-                if (pos - gstart == 8) {
-                    if (ng < TL_GMAX) meta[ng] = (gstart << 4) | 8;
-                    ng++;
-                    gstart = pos;
-                }
-            }
+            gstart = pos;
+#pragma unroll
+            for (int q = 0; q < TL_KC; q++)
+                if (q < n && kc[q] == kmin) place(b0 + q);
+            for (int q = TL_KC; q < n; q++)
+                if (slot_key(S, D.code[b0 + q]) == kmin) place(b0 + q);
             if (pos > gstart) {
                 if (ng < TL_GMAX) meta[ng] = (gstart << 4) | (pos - gstart);
                 ng++;
