@@ -23,7 +23,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes per particle and launch (FP32 state; see the design notes):
+# algorithmic bytes per particle and launch (FP32 state, each field counted once):
 #   P2G kernel: read X 12, code 4, v 12, F 36; write F 36            -> 100 B
 #   G2P kernel: read X 12, code 4, u 12, v 12; write u 12, v 12       ->  64 B
 #   whole substep (each persistent field read/written once)           -> 136 B
@@ -348,8 +348,8 @@ def main():
         print(json.dumps({"copy_calibration_bytes": nb}))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
-                                   "described in the design notes, not built)"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1 (sharding across GPUs "
+                                   "is not implemented)"}))
         sys.exit(2)
 
     import torch

@@ -10,8 +10,7 @@
  * It is written for obviousness, not speed: array-of-structs state in FP64, a
  * scatter P2G into per-node linked lists of (code, state) accumulators, a brute
  * per-digit conflict test, linear scans.  Every function cites the passage of the
- * paper it follows.  Where the paper is silent the reading used is stated inline
- * (the same readings are listed in the design notes of the repository).
+ * paper it follows.  Where the paper is silent the reading used is stated inline.
  *
  * Step order within one substep (Sec. III-B, III-D, III-E, App.):
  *   contact impulses on x^n, v^n, c^n -> label-masked P2G (Eq. 2) with gravity and
