@@ -13,7 +13,7 @@
  *     deformation-gradient update (Sec. III-B, App. Eq. 17).
  * Per scene: Neo-Hookean or fixed-corotated elasticity with Newtonian viscosity and
  * von Mises plasticity (Sec. III-B), trilinear or quadratic B-spline interpolation
- * (Eq. 1), prescribed or free (two-way coupled) tools (Sec. III-A, III-F).
+ * (Eq. 1), prescribed or free (two-way coupled) tools (Sec. III-A, III-E, III-G).
  *
  * Conventions
  *   - Every call returns a tlmpm_status; nothing throws across the ABI.  The text of
@@ -115,7 +115,7 @@ typedef struct {
 /* A rigid tool: the zero-thickness rectangle of its blade record, |l| <= half_len
  * along e and -b_back <= f <= 0 along d, in the plane s = 0, moving with the twist
  * (v_B, omega_B) about x_B.  Its inverse effective mass at a contact point x_c
- * along the contact normal n (Sec. III-F, rigid contact) is
+ * along the contact normal n (Sec. III-E, Eq. 15) is
  *   w = w_B + inv_mass + (r x n) . inv_inertia (r x n),  r = x_c - x_B,
  * so a kinematically prescribed tool has all three zero, and a free rigid body
  * has x_B at its centre of mass, inv_mass = 1/M and inv_inertia = I^-1 in world
@@ -143,7 +143,7 @@ tlmpm_status tlmpm_create_scene(const tlmpm_scene_desc* desc, void* dev_workspac
 
 tlmpm_status tlmpm_destroy_scene(tlmpm_scene* scene);
 
-/* ---- Two-way tool coupling (Sec. III-A, III-F, III-G).  The paper leaves the
+/* ---- Two-way tool coupling (Sec. III-A, III-E, III-G).  The paper leaves the
  * tool's rigid-body dynamics to an external solver that receives the interval-
  * averaged wrench of tlmpm_step and returns the next pose and twist; these two
  * host-only calls are such a solver for a free rigid tool (a knife released under

@@ -7,15 +7,23 @@ SRC = os.path.join(HERE, "tlmpm_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
 
+def compile_source(src, out, openmp=False):
+    """gcc the oracle source file `src` into the shared library `out`."""
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
+           "-Wall", "-Wno-unused-function"]
+    if openmp:
+        cmd.append("-fopenmp")
+    cmd += ["-o", out + ".tmp", src, "-lm"]
+    subprocess.check_call(cmd)
+    os.replace(out + ".tmp", out)
+    return out
+
+
 def build(force=True):
     """Build liboracle.so; with force=False only when missing or stale."""
     if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
         return LIB
-    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
-           "-Wall", "-Wno-unused-function", "-o", LIB + ".tmp", SRC, "-lm"]
-    subprocess.check_call(cmd)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    return compile_source(SRC, LIB)
 
 
 if __name__ == "__main__":

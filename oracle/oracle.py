@@ -11,7 +11,7 @@ import numpy as np
 
 from .build import LIB, build
 
-__all__ = ["Params", "Blade", "Tool", "OracleScene", "lib", "shape", "neo_hookean_P",
+__all__ = ["Params", "Blade", "Tool", "OracleScene", "lib", "load", "shape", "neo_hookean_P",
            "neo_hookean_psi", "fcr_P", "fcr_psi", "polar", "visc_P", "vm_project", "conflict", "encode", "digit", "couple", "label_digit",
            "labels_on"]
 
@@ -52,59 +52,71 @@ class Tool(C.Structure):
 _lib = None
 
 
+def load(path):
+    """Load a compiled oracle library from `path` and declare its entry points.
+    lib() loads the one built from oracle/tlmpm_oracle.c; the pins also load
+    variants built from edited copies of the source to show that each pin fails
+    under the mistake it targets."""
+    L = C.CDLL(path)
+    _declare(L)
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         build(force=False)
-        L = C.CDLL(LIB)
-        dp = C.POINTER(C.c_double)
-        u8p = C.POINTER(C.c_uint8)
-        L.orc_create.restype = C.c_void_p
-        L.orc_create.argtypes = [C.POINTER(Params), C.c_long, dp, dp, dp, dp, dp]
-        L.orc_destroy.argtypes = [C.c_void_p]
-        L.orc_assign_labels.restype = C.c_long
-        L.orc_assign_labels.argtypes = [C.c_void_p, C.POINTER(Blade), C.c_int]
-        L.orc_step.restype = C.c_int
-        L.orc_step.argtypes = [C.c_void_p, C.POINTER(Tool), C.c_int, dp, C.c_int]
-        L.orc_get.argtypes = [C.c_void_p, dp, dp, dp, u8p, dp]
-        L.orc_set.argtypes = [C.c_void_p, dp, dp, dp, u8p, dp]
-        L.orc_shape.restype = C.c_int
-        L.orc_shape.argtypes = [C.POINTER(Params), dp, C.POINTER(C.c_long), dp, dp]
-        L.orc_neo_hookean_P.restype = C.c_int
-        L.orc_neo_hookean_P.argtypes = [C.c_double, C.c_double, dp, dp]
-        L.orc_neo_hookean_psi.restype = C.c_double
-        L.orc_neo_hookean_psi.argtypes = [C.c_double, C.c_double, dp]
-        L.orc_fcr_P.restype = C.c_int
-        L.orc_fcr_P.argtypes = [C.c_double, C.c_double, dp, dp]
-        L.orc_fcr_psi.restype = C.c_double
-        L.orc_fcr_psi.argtypes = [C.c_double, C.c_double, dp]
-        L.orc_polar.restype = C.c_int
-        L.orc_polar.argtypes = [dp, dp, dp]
-        L.orc_vm_project.restype = C.c_int
-        L.orc_vm_project.argtypes = [C.c_double, C.c_double, C.c_double, dp, dp]
-        L.orc_visc_P.restype = C.c_int
-        L.orc_visc_P.argtypes = [C.c_double, dp, dp, dp]
-        L.orc_conflict.restype = C.c_int
-        L.orc_conflict.argtypes = [C.c_uint64, C.c_uint64, C.c_int]
-        L.orc_encode.restype = C.c_uint64
-        L.orc_encode.argtypes = [u8p, C.c_int]
-        L.orc_digit.restype = C.c_int
-        L.orc_digit.argtypes = [C.c_uint64, C.c_int]
-        L.orc_couple.argtypes = [C.c_int, dp, C.POINTER(C.c_uint64), C.c_int, dp, dp]
-        L.orc_label_digit.restype = C.c_int
-        L.orc_label_digit.argtypes = [dp, dp, C.POINTER(Blade), C.c_double, C.c_int]
-        L.orc_candidates.argtypes = [C.c_void_p, u8p]
-        L.orc_label_pass.restype = C.c_long
-        L.orc_label_pass.argtypes = [C.c_long, dp, dp, u8p, C.c_int, C.POINTER(Blade), C.c_int, C.c_double]
-        L.orc_last_pairs.restype = C.c_long
-        L.orc_last_pairs.argtypes = [C.c_void_p]
-        L.orc_last_candidates.restype = C.c_long
-        L.orc_last_candidates.argtypes = [C.c_void_p]
-        L.orc_grid_dump.restype = C.c_long
-        L.orc_grid_dump.argtypes = [C.c_void_p, C.c_long, C.POINTER(C.c_int64), C.POINTER(C.c_uint64),
-                                    dp, dp, dp, dp]
-        _lib = L
+        _lib = load(LIB)
     return _lib
+
+
+def _declare(L):
+    dp = C.POINTER(C.c_double)
+    u8p = C.POINTER(C.c_uint8)
+    L.orc_create.restype = C.c_void_p
+    L.orc_create.argtypes = [C.POINTER(Params), C.c_long, dp, dp, dp, dp, dp]
+    L.orc_destroy.argtypes = [C.c_void_p]
+    L.orc_assign_labels.restype = C.c_long
+    L.orc_assign_labels.argtypes = [C.c_void_p, C.POINTER(Blade), C.c_int]
+    L.orc_step.restype = C.c_int
+    L.orc_step.argtypes = [C.c_void_p, C.POINTER(Tool), C.c_int, dp, C.c_int]
+    L.orc_get.argtypes = [C.c_void_p, dp, dp, dp, u8p, dp]
+    L.orc_set.argtypes = [C.c_void_p, dp, dp, dp, u8p, dp]
+    L.orc_shape.restype = C.c_int
+    L.orc_shape.argtypes = [C.POINTER(Params), dp, C.POINTER(C.c_long), dp, dp]
+    L.orc_neo_hookean_P.restype = C.c_int
+    L.orc_neo_hookean_P.argtypes = [C.c_double, C.c_double, dp, dp]
+    L.orc_neo_hookean_psi.restype = C.c_double
+    L.orc_neo_hookean_psi.argtypes = [C.c_double, C.c_double, dp]
+    L.orc_fcr_P.restype = C.c_int
+    L.orc_fcr_P.argtypes = [C.c_double, C.c_double, dp, dp]
+    L.orc_fcr_psi.restype = C.c_double
+    L.orc_fcr_psi.argtypes = [C.c_double, C.c_double, dp]
+    L.orc_polar.restype = C.c_int
+    L.orc_polar.argtypes = [dp, dp, dp]
+    L.orc_vm_project.restype = C.c_int
+    L.orc_vm_project.argtypes = [C.c_double, C.c_double, C.c_double, dp, dp]
+    L.orc_visc_P.restype = C.c_int
+    L.orc_visc_P.argtypes = [C.c_double, dp, dp, dp]
+    L.orc_conflict.restype = C.c_int
+    L.orc_conflict.argtypes = [C.c_uint64, C.c_uint64, C.c_int]
+    L.orc_encode.restype = C.c_uint64
+    L.orc_encode.argtypes = [u8p, C.c_int]
+    L.orc_digit.restype = C.c_int
+    L.orc_digit.argtypes = [C.c_uint64, C.c_int]
+    L.orc_couple.argtypes = [C.c_int, dp, C.POINTER(C.c_uint64), C.c_int, dp, dp]
+    L.orc_label_digit.restype = C.c_int
+    L.orc_label_digit.argtypes = [dp, dp, C.POINTER(Blade), C.c_double, C.c_int]
+    L.orc_candidates.argtypes = [C.c_void_p, u8p]
+    L.orc_label_pass.restype = C.c_long
+    L.orc_label_pass.argtypes = [C.c_long, dp, dp, u8p, C.c_int, C.POINTER(Blade), C.c_int, C.c_double]
+    L.orc_last_pairs.restype = C.c_long
+    L.orc_last_pairs.argtypes = [C.c_void_p]
+    L.orc_last_candidates.restype = C.c_long
+    L.orc_last_candidates.argtypes = [C.c_void_p]
+    L.orc_grid_dump.restype = C.c_long
+    L.orc_grid_dump.argtypes = [C.c_void_p, C.c_long, C.POINTER(C.c_int64), C.POINTER(C.c_uint64),
+                                dp, dp, dp, dp]
 
 
 def _dp(a):
@@ -179,8 +191,9 @@ class OracleScene:
     """One FP64 scene.  ``scene`` is a dict as produced by the workload generators:
     params (dict) plus arrays X [n,3], v0 [n,3] or None, vol0 [n], mass [n], E [n]."""
 
-    def __init__(self, scene):
-        L = lib()
+    def __init__(self, scene, L=None):
+        L = L or lib()
+        self.L = L
         self.P = make_params(scene["params"])
         X = _f64(scene["X"], (-1, 3))
         self.n = X.shape[0]
@@ -198,12 +211,12 @@ class OracleScene:
 
     def __del__(self):
         if getattr(self, "h", None):
-            lib().orc_destroy(self.h)
+            self.L.orc_destroy(self.h)
             self.h = None
 
     def assign_labels(self, blades):
         arr = (Blade * max(1, len(blades)))(*[make_blade(b) for b in blades])
-        r = lib().orc_assign_labels(self.h, arr, len(blades))
+        r = self.L.orc_assign_labels(self.h, arr, len(blades))
         if r < 0:
             raise ValueError("bad cut index")
         return r
@@ -213,7 +226,7 @@ class OracleScene:
         nt = len(tools)
         arr = (Tool * max(1, nt))(*[make_tool(t) for t in tools])
         w = np.zeros((max(1, nt), 6))
-        st = lib().orc_step(self.h, arr, nt, _dp(w), int(bool(brute_pairs)))
+        st = self.L.orc_step(self.h, arr, nt, _dp(w), int(bool(brute_pairs)))
         return st, w[:nt]
 
     def get(self):
@@ -223,7 +236,7 @@ class OracleScene:
         F = np.empty((n, 3, 3))
         dig = np.zeros((n, max(1, K)), np.uint8)
         D = np.empty(n)
-        lib().orc_get(self.h, _dp(x), _dp(v), _dp(F), dig.ctypes.data_as(C.POINTER(C.c_uint8)), _dp(D))
+        self.L.orc_get(self.h, _dp(x), _dp(v), _dp(F), dig.ctypes.data_as(C.POINTER(C.c_uint8)), _dp(D))
         return {"x": x, "v": v, "F": F, "digits": dig[:, :K], "D": D}
 
     def set(self, x=None, v=None, F=None, digits=None, D=None):
@@ -242,7 +255,7 @@ class OracleScene:
             d = np.ascontiguousarray(np.asarray(digits, np.uint8).reshape(n, K))
             keep.append(d)
             dg = d.ctypes.data_as(C.POINTER(C.c_uint8))
-        lib().orc_set(self.h, conv(x, (n, 3)), conv(v, (n, 3)), conv(F, (n, 9)), dg, conv(D, (n,)))
+        self.L.orc_set(self.h, conv(x, (n, 3)), conv(v, (n, 3)), conv(F, (n, 9)), dg, conv(D, (n,)))
 
     def codes(self):
         """Ternary codes c_p = sum_k d_k 3^k (Eq. 7) as uint64."""
@@ -252,11 +265,11 @@ class OracleScene:
 
     def candidates(self):
         c = np.zeros(self.n, np.uint8)
-        lib().orc_candidates(self.h, c.ctypes.data_as(C.POINTER(C.c_uint8)))
+        self.L.orc_candidates(self.h, c.ctypes.data_as(C.POINTER(C.c_uint8)))
         return c.astype(bool)
 
     def last_pairs(self):
-        return lib().orc_last_pairs(self.h)
+        return self.L.orc_last_pairs(self.h)
 
     def grid_dump(self):
         cap = 27 * self.n + 8
@@ -266,7 +279,7 @@ class OracleScene:
         vn = np.empty((cap, 3))
         vn1 = np.empty((cap, 3))
         vt = np.empty((cap, 3))
-        k = lib().orc_grid_dump(self.h, cap, node.ctypes.data_as(C.POINTER(C.c_int64)),
+        k = self.L.orc_grid_dump(self.h, cap, node.ctypes.data_as(C.POINTER(C.c_int64)),
                                 code.ctypes.data_as(C.POINTER(C.c_uint64)), _dp(m), _dp(vn), _dp(vn1), _dp(vt))
         return {"node": node[:k], "code": code[:k], "m": m[:k], "vn": vn[:k], "vn1": vn1[:k], "vt": vt[:k]}
 

@@ -3,7 +3,7 @@
 Test infrastructure only.  The paper couples the TLMPM solver to an external
 rigid-body system (Sec. III-A) that takes the interval-averaged wrench (Sec. III-G)
 and returns the tool's next pose and twist; the tool's inverse effective mass at
-a contact (Sec. III-F) comes from the same body.  The integrator is semi-implicit
+a contact (Sec. III-E, Eq. 15) comes from the same body.  The integrator is semi-implicit
 (symplectic) Euler of the Newton-Euler equations (reading R30):
 
     v      <- v + h (F / M + g)

@@ -836,7 +836,7 @@ static void rigid_contact(orc_scene* s, int body, const orc_tool* T, double* wre
         /* relative velocity at the contact point and predicted gap (Eq. 14) */
         double arm[3] = {xc[0] - xB[0], xc[1] - xB[1], xc[2] - xB[2]}, wxr[3];
         if (body > 0) {
-            /* inverse effective mass of the tool at x_c along n_B (Sec. III-F):
+            /* inverse effective mass of the tool at x_c along n_B (Sec. III-E, Eq. 15):
              * the normal velocity change of the contact point per unit normal
              * impulse, 1/M + (r x n) . I^-1 (r x n), plus a given constant part */
             double rn[3], Irn[3];

@@ -1,4 +1,4 @@
-"""Two-way coupling of free rigid knives and the TLMPM scene (Sec. III-A, III-F,
+"""Two-way coupling of free rigid knives and the TLMPM scene (Sec. III-A, III-E,
 III-G): every interval, each knife's tool record (pose and twist, mass properties)
 is held over `interval` substeps of tlmpm_step, whose interval-averaged wrench per
 tool then advances each knife (tlmpm_rigid_step).  The first interval starts the

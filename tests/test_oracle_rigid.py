@@ -3,7 +3,7 @@ host-side rigid step against it.
 
 The oracle's integrator is checked against closed forms of its own scheme and
 against invariants of rigid-body motion; its impulse response against the C
-oracle's per-contact inverse effective mass (Sec. III-F); the product's
+oracle's per-contact inverse effective mass (Sec. III-E, Eq. 15); the product's
 tlmpm_rigid_step / tlmpm_rigid_tool (host code, no GPU) against the oracle.
 """
 import math
@@ -122,7 +122,7 @@ def test_impulse_response_equals_inverse_effective_mass():
 
 
 def test_oracle_contact_uses_tool_inverse_effective_mass():
-    """Sec. III-F: a particle pressed against a free tool receives
+    """Sec. III-E, Eq. 15: a particle pressed against a free tool receives
     J_n = s_n m_eff / dt max(-phi_hat, 0) with m_eff = (1/m + w)^-1 and w the tool's
     inverse effective mass at the contact point along the normal."""
     p = W.base_params(0.01, (-0.05, -0.05, -0.05), (10, 10, 10), 1e-4, 0.3, floor_on=0, gravity=[0.0, 0.0, 0.0])
