@@ -197,13 +197,16 @@ tlmpm_status tlmpm_step(tlmpm_scene* scene, const tlmpm_tool* tools, int32_t n_t
 #define TLMPM_FIELD_CODE 16u  /* uint64 [n] ternary code sum_k d_k 3^k (Eq. 7) */
 #define TLMPM_FIELD_D 32u     /* float [n] cutting progress */
 #define TLMPM_FIELD_DIGITS 64u /* uint8 [n][max_cuts] ternary digits */
+#define TLMPM_FIELD_H 128u     /* float [n][9] H = F - I, row major: the stored form of F, which
+                                  keeps small strains to FP32 relative precision (F in FP32
+                                  rounds them to multiples of 2^-24) */
 
 /* Copy fields to host buffers in the caller's original particle order.  host_out
  * has one pointer per bit of field_mask, in increasing bit order.  Synchronises. */
 tlmpm_status tlmpm_read_state(tlmpm_scene* scene, uint32_t field_mask, void* const* host_out);
 
 /* Overwrite fields from host buffers (original order; same layout as read_state;
- * TLMPM_FIELD_X and TLMPM_FIELD_CODE are not writable).  For restarts and
+ * TLMPM_FIELD_X and TLMPM_FIELD_CODE are not writable; F and H not both in one call).  For restarts and
  * shared-input comparisons.  Synchronises. */
 tlmpm_status tlmpm_write_state(tlmpm_scene* scene, uint32_t field_mask, const void* const* host_in);
 
@@ -259,6 +262,12 @@ typedef struct tlmpm_batch tlmpm_batch; /* opaque */
 /* Device bytes of a batch over these scenes (n_scenes >= 1, no repeats, none in a
  * live batch). */
 tlmpm_status tlmpm_batch_footprint(tlmpm_scene* const* scenes, int32_t n_scenes, size_t* device_bytes);
+
+/* Upper bound on the device bytes one scene of this description adds to a batch
+ * workspace: for any set of such scenes, tlmpm_batch_footprint() is at most the sum
+ * of their bounds.  For admission by device memory before the scene exists (a
+ * server reserves tlmpm_scene_footprint() plus this for every running rollout). */
+tlmpm_status tlmpm_batch_scene_bytes(const tlmpm_scene_desc* desc, size_t* device_bytes);
 
 /* Build a batch.  Scenes whose pending deformation-gradient update was left in a
  * different slot-table state than the others first complete it alone. */

@@ -172,6 +172,14 @@ struct Layout {
     }
 };
 
+// blocks of the grid-stride pair search of a scene of N particles
+int pair_blocks_of(long long N) { return (int)std::min<long long>(4096, std::max<long long>(1, N / 128)); }
+
+// workgroups for the later same-code rounds of mixed bricks: scenes of 512 to 4096
+// active bricks only (smaller scenes have few long workgroups to hide, larger ones
+// many rounds of workgroups)
+int xcap_of(long long n_active) { return (n_active >= 512 && n_active <= 4096) ? (int)std::min<long long>(256, n_active / 4) : 0; }
+
 struct Dims {
     long long N;
     int cx, cy, cz, cbx, cby, cbz, nbx, nby, nbz;
@@ -542,7 +550,7 @@ extern "C" tlmpm_status tlmpm_create_scene(const tlmpm_scene_desc* d, void* ws, 
     K.material = d->material;
     K.visc = d->viscosity;
     K.ystress = d->yield_stress;
-    K.pair_blocks = (int)std::min<long long>(4096, std::max<long long>(1, N / 128));
+    K.pair_blocks = pair_blocks_of(N);
     K.stencil = d->stencil;
     // workgroups for the later rounds of bricks with a mixed cell: a quarter of the
     // bricks, at most 256 (with more mixed bricks no brick is split).  Only scenes of
@@ -551,7 +559,7 @@ extern "C" tlmpm_status tlmpm_create_scene(const tlmpm_scene_desc* d, void* ws, 
     // smaller scenes (the many-scene batches) and larger ones measured slower with the
     // extra launch slots than the rounds cost.
     const size_t na = active.size();
-    K.xcap = (na >= 512 && na <= 4096) ? (int)std::min<size_t>(256, na / 4) : 0;
+    K.xcap = xcap_of((long long)na);
     float vmax0 = d->vol0_uniform;
     if (d->vol0)
         for (long long p = 0; p < N; p++) vmax0 = std::max(vmax0, d->vol0[p]);
@@ -1252,18 +1260,18 @@ extern "C" tlmpm_status tlmpm_read_state(tlmpm_scene* sc, uint32_t mask, void* c
     std::vector<uint32_t> cb;
     HIPCHK(hipStreamSynchronize(sc->st));
     int slot = 0;
-    for (uint32_t bit = 1; bit <= TLMPM_FIELD_DIGITS; bit <<= 1) {
+    for (uint32_t bit = 1; bit <= TLMPM_FIELD_H; bit <<= 1) {
         if (!(mask & bit)) continue;
         void* dst = out[slot++];
         if (!dst) return fail(TLMPM_E_INVALID, "null output buffer");
         if (bit == TLMPM_FIELD_X || bit == TLMPM_FIELD_U || bit == TLMPM_FIELD_V || bit == TLMPM_FIELD_F ||
-            bit == TLMPM_FIELD_D) {
-            int comps = bit == TLMPM_FIELD_F ? 9 : (bit == TLMPM_FIELD_D ? 1 : 3);
+            bit == TLMPM_FIELD_D || bit == TLMPM_FIELD_H) {
+            int comps = (bit == TLMPM_FIELD_F || bit == TLMPM_FIELD_H) ? 9 : (bit == TLMPM_FIELD_D ? 1 : 3);
             const float* src = bit == TLMPM_FIELD_X ? D.X
                                : bit == TLMPM_FIELD_U ? D.u
                                : bit == TLMPM_FIELD_V ? D.v
-                               : bit == TLMPM_FIELD_F ? D.H
-                                                      : D.D;
+                               : (bit == TLMPM_FIELD_F || bit == TLMPM_FIELD_H) ? D.H
+                                                                                : D.D;
             buf.resize((size_t)comps * N);
             if (N) HIPCHK(hipMemcpyAsync(buf.data(), src, (size_t)comps * N * 4, hipMemcpyDeviceToHost, sc->st));
             HIPCHK(hipStreamSynchronize(sc->st));
@@ -1298,6 +1306,7 @@ extern "C" tlmpm_status tlmpm_write_state(tlmpm_scene* sc, uint32_t mask, const 
     if (tlmpm_status r = refuse_batched(sc)) return r;
     if (mask && !in) return fail(TLMPM_E_INVALID, "bad arguments");
     if (mask & (TLMPM_FIELD_X | TLMPM_FIELD_CODE)) return fail(TLMPM_E_INVALID, "X and CODE are not writable");
+    if ((mask & TLMPM_FIELD_F) && (mask & TLMPM_FIELD_H)) return fail(TLMPM_E_INVALID, "write F or H, not both");
     tlmpm_status s = flush_F(sc);
     if (s) return s;
     const long long N = sc->K.N;
@@ -1308,7 +1317,7 @@ extern "C" tlmpm_status tlmpm_write_state(tlmpm_scene* sc, uint32_t mask, const 
     std::vector<float> buf;
     int slot = 0;
     bool codes_changed = false;
-    for (uint32_t bit = 1; bit <= TLMPM_FIELD_DIGITS; bit <<= 1) {
+    for (uint32_t bit = 1; bit <= TLMPM_FIELD_H; bit <<= 1) {
         if (!(mask & bit)) continue;
         const void* src = in[slot++];
         if (!src) return fail(TLMPM_E_INVALID, "null input buffer");
@@ -1330,8 +1339,11 @@ extern "C" tlmpm_status tlmpm_write_state(tlmpm_scene* sc, uint32_t mask, const 
             codes_changed = true;
             continue;
         }
-        int comps = bit == TLMPM_FIELD_F ? 9 : (bit == TLMPM_FIELD_D ? 1 : 3);
-        float* dstp = bit == TLMPM_FIELD_U ? D.u : bit == TLMPM_FIELD_V ? D.v : bit == TLMPM_FIELD_F ? D.H : D.D;
+        int comps = (bit == TLMPM_FIELD_F || bit == TLMPM_FIELD_H) ? 9 : (bit == TLMPM_FIELD_D ? 1 : 3);
+        float* dstp = bit == TLMPM_FIELD_U   ? D.u
+                      : bit == TLMPM_FIELD_V ? D.v
+                      : (bit == TLMPM_FIELD_F || bit == TLMPM_FIELD_H) ? D.H
+                                                                       : D.D;
         buf.resize((size_t)comps * N);
         const float* f = (const float*)src;
         for (long long q = 0; q < N; q++)
@@ -1555,20 +1567,26 @@ struct BatchPlan {
 
 int ceil_div(long long a, int b) { return (int)((a + b - 1) / b); }
 
-// work items of each kind for one scene
+// work items of each kind for one scene of n_active bricks
+void items_of(long long n_active, long long n_bricks, long long NN, long long N, int material_contact,
+              int pair_blocks, int xcap, int n[TL_ITEM_KINDS])
+{
+    n[IT_BRICK] = (int)n_active;
+    n[IT_NODE] = ceil_div(NN, 256);
+    n[IT_CELL] = material_contact ? ceil_div(n_bricks * TL_CELLS, 256) : 0;
+    n[IT_WRENCH] = TL_MAX_TOOLS * 6;
+    n[IT_SCENE] = 1;
+    n[IT_PART] = ceil_div(N, 256);
+    n[IT_BFLAG] = ceil_div(n_bricks, 256);
+    n[IT_PAIR] = material_contact ? pair_blocks : 0;
+    n[IT_XBRICK] = n_active > 0 ? xcap : 0;
+}
+
 void scene_items(const tlmpm_scene* sc, int n[TL_ITEM_KINDS])
 {
     const SceneK& K = sc->K;
-    const long long n_bricks = (long long)K.cbx * K.cby * K.cbz;
-    n[IT_BRICK] = sc->D.n_active;
-    n[IT_NODE] = ceil_div(K.NN, 256);
-    n[IT_CELL] = K.material_contact ? ceil_div(n_bricks * TL_CELLS, 256) : 0;
-    n[IT_WRENCH] = TL_MAX_TOOLS * 6;
-    n[IT_SCENE] = 1;
-    n[IT_PART] = ceil_div(K.N, 256);
-    n[IT_BFLAG] = ceil_div(n_bricks, 256);
-    n[IT_PAIR] = K.material_contact ? K.pair_blocks : 0;
-    n[IT_XBRICK] = sc->D.n_active > 0 ? K.xcap : 0;
+    items_of(sc->D.n_active, (long long)K.cbx * K.cby * K.cbz, K.NN, K.N, K.material_contact, K.pair_blocks, K.xcap,
+             n);
 }
 
 tlmpm_status batch_plan(tlmpm_scene* const* scenes, int n, BatchPlan& P)
@@ -1637,6 +1655,23 @@ extern "C" tlmpm_status tlmpm_batch_footprint(tlmpm_scene* const* scenes, int32_
     BatchPlan P;
     if (tlmpm_status r = batch_plan(scenes, n_scenes, P)) return r;
     *device_bytes = P.total;
+    return TLMPM_OK;
+}
+
+extern "C" tlmpm_status tlmpm_batch_scene_bytes(const tlmpm_scene_desc* desc, size_t* device_bytes)
+{
+    tlmpm_status s = validate(desc);
+    if (s) return s;
+    if (!device_bytes) return fail(TLMPM_E_INVALID, "null output");
+    const Dims g = dims_of(desc);
+    const long long na = count_active(desc);
+    int c[TL_ITEM_KINDS];
+    items_of(na, g.n_bricks, g.NN, g.N, desc->material_contact != 0, pair_blocks_of(g.N), xcap_of(na), c);
+    size_t b = sizeof(SceneK) + sizeof(SceneD) + sizeof(BatchTools) + TL_MAX_TOOLS * 6 * sizeof(double);
+    for (int k = 0; k < TL_ITEM_KINDS; k++) b += (size_t)c[k] * sizeof(int2);
+    // the alignment of the batch layout's 4 + TL_ITEM_KINDS arrays and its tail
+    b += (4 + TL_ITEM_KINDS) * 255 + 256;
+    *device_bytes = b;
     return TLMPM_OK;
 }
 

@@ -24,6 +24,7 @@
 #include <stdint.h>
 
 #include "tlmpm_common.h"
+#include "tlmpm_band.h"
 #include "tlmpm_device.h"
 
 
@@ -428,44 +429,43 @@ DEV void friction(const SceneK& S, const float vrel[3], const float n[3], float 
 
 // One rigid body against one particle (Eqs. 14-16, 5).  body 0 = floor, else tool.
 // Returns the impulse on the particle in J (added), updates D and the wrench sums.
-DEV void rigid_one(const SceneK& S, const SceneD& D, const DevTool* T, int slot, long long p, const float x[3],
+// The contact geometry (closest point, gap, normal, front-band coordinates) is
+// formed in FP64 from the exact current position x = X + u: the normal impulse is
+// s_n m / dt times the gap, and for a particle close to the zero-thickness blade
+// the normal is (x - x_c) / |x - x_c| of a short vector, so FP32 rounding of the
+// positions (1e-8 m at 0.2 m) would shift the gap and turn the normal by far more
+// than the FP32 state error.
+DEV void rigid_one(const SceneK& S, const SceneD& D, const DevTool* T, int slot, long long p, const double x[3],
                    const float v[3], float m, float V0, float R, int stamp, double jdt, float J[3], float& Dp,
                    float Dstart, float* wr)
 {
     const float dt = S.dt;
     double adv = (T && (T->flags & TL_TOOL_ADVANCE)) ? jdt : 0.0;
-    float xc[3], nB[3], phi, vB[3] = {0.0f, 0.0f, 0.0f}, arm[3] = {0.0f, 0.0f, 0.0f};
+    float nB[3], phi, vB[3] = {0.0f, 0.0f, 0.0f}, arm[3] = {0.0f, 0.0f, 0.0f};
     float invm = 0.0f;
+    double r[3] = {0.0, 0.0, 0.0}; // x - x_e of a tool
     if (!T) {
-        xc[0] = x[0];
-        xc[1] = x[1];
-        xc[2] = S.floor_z;
         nB[0] = 0.0f;
         nB[1] = 0.0f;
         nB[2] = 1.0f;
-        phi = (x[2] - S.floor_z) - R;
+        phi = (float)((x[2] - (double)S.floor_z) - (double)R);
     } else {
         const DevBlade& B = T->b;
-        float xe[3] = {(float)(B.xe[0] + adv * B.ve[0]), (float)(B.xe[1] + adv * B.ve[1]), (float)(B.xe[2] + adv * B.ve[2])};
-        float r[3] = {x[0] - xe[0], x[1] - xe[1], x[2] - xe[2]};
-        float e[3] = {(float)B.e[0], (float)B.e[1], (float)B.e[2]};
-        float d[3] = {(float)B.d[0], (float)B.d[1], (float)B.d[2]};
-        float al = r[0] * e[0] + r[1] * e[1] + r[2] * e[2];
-        float be = -(r[0] * d[0] + r[1] * d[1] + r[2] * d[2]);
-        al = fminf(fmaxf(al, -(float)B.half_len), (float)B.half_len);
-        be = fminf(fmaxf(be, 0.0f), (float)B.b_back);
-        float df[3];
-        for (int a = 0; a < 3; a++) {
-            xc[a] = xe[a] + al * e[a] - be * d[a];
-            df[a] = x[a] - xc[a];
-        }
-        float dist = sqrtf(df[0] * df[0] + df[1] * df[1] + df[2] * df[2]);
-        if (dist > 0.0f)
-            for (int a = 0; a < 3; a++) nB[a] = df[a] / dist;
+        for (int a = 0; a < 3; a++) r[a] = x[a] - (B.xe[a] + adv * B.ve[a]);
+        double al = r[0] * B.e[0] + r[1] * B.e[1] + r[2] * B.e[2];
+        double be = -(r[0] * B.d[0] + r[1] * B.d[1] + r[2] * B.d[2]);
+        al = fmin(fmax(al, -B.half_len), B.half_len);
+        be = fmin(fmax(be, 0.0), B.b_back);
+        double df[3];
+        for (int a = 0; a < 3; a++) df[a] = r[a] - al * B.e[a] + be * B.d[a]; // x - x_c
+        const double dist = sqrt(df[0] * df[0] + df[1] * df[1] + df[2] * df[2]);
+        if (dist > 0.0)
+            for (int a = 0; a < 3; a++) nB[a] = (float)(df[a] / dist);
         else
             for (int a = 0; a < 3; a++) nB[a] = (float)B.n[a];
-        phi = dist - R;
-        for (int a = 0; a < 3; a++) arm[a] = xc[a] - (float)(T->xB[a] + adv * T->vB[a]);
+        phi = (float)(dist - (double)R);
+        for (int a = 0; a < 3; a++)
+            arm[a] = (float)((x[a] - df[a]) - (T->xB[a] + adv * T->vB[a])); // x_c - x_B
         float wxr[3] = {T->wB[1] * arm[2] - T->wB[2] * arm[1], T->wB[2] * arm[0] - T->wB[0] * arm[2],
                         T->wB[0] * arm[1] - T->wB[1] * arm[0]};
         for (int a = 0; a < 3; a++) vB[a] = (float)T->vB[a] + wxr[a];
@@ -499,15 +499,12 @@ DEV void rigid_one(const SceneK& S, const SceneD& D, const DevTool* T, int slot,
     float JpB[3] = {Jn * nB[0] + ft[0] * dt, Jn * nB[1] + ft[1] * dt, Jn * nB[2] + ft[2] * dt};
     if (T && (T->flags & TL_TOOL_CUTTING)) {
         const DevBlade& B = T->b;
-        float r[3] = {x[0] - (float)(B.xe[0] + adv * B.ve[0]), x[1] - (float)(B.xe[1] + adv * B.ve[1]),
-                      x[2] - (float)(B.xe[2] + adv * B.ve[2])};
-        float sv = r[0] * (float)B.n[0] + r[1] * (float)B.n[1] + r[2] * (float)B.n[2];
-        float lv = r[0] * (float)B.e[0] + r[1] * (float)B.e[1] + r[2] * (float)B.e[2];
-        float fv = r[0] * (float)B.d[0] + r[1] * (float)B.d[1] + r[2] * (float)B.d[2];
+        const double sv = r[0] * B.n[0] + r[1] * B.n[1] + r[2] * B.n[2];
+        const double lv = r[0] * B.e[0] + r[1] * B.e[1] + r[2] * B.e[2];
+        const double fv = r[0] * B.d[0] + r[1] * B.d[1] + r[2] * B.d[2];
         float uc = ((float)B.ve[0] - v[0]) * (float)B.d[0] + ((float)B.ve[1] - v[1]) * (float)B.d[1] +
                    ((float)B.ve[2] - v[2]) * (float)B.d[2];
-        if (fabsf(sv) <= (float)B.half_width && fabsf(lv) <= (float)B.half_len && fv >= 0.0f &&
-            fv <= (float)B.b_lead && uc > S.u_min) {
+        if (fabs(sv) <= B.half_width && fabs(lv) <= B.half_len && fv >= 0.0 && fv <= B.b_lead && uc > S.u_min) {
             float dd[3] = {(float)B.d[0], (float)B.d[1], (float)B.d[2]};
             float Jc = fmaxf(JpB[0] * dd[0] + JpB[1] * dd[1] + JpB[2] * dd[2], 0.0f);
             if (Dstart < 1.0f) {
@@ -634,11 +631,12 @@ DEV void rigid_body(const SceneK& S, const SceneD& D, int bi)
         for (int p0 = beg; p0 < end; p0 += blockDim.x) {
             const int p = p0 + tid;
             const bool valid = p < end;
-            float x[3] = {0.0f, 0.0f, 0.0f}, v[3] = {0.0f, 0.0f, 0.0f}, m = 0.0f, V0 = 0.0f, R = 0.0f, Dp = 0.0f;
+            double x[3] = {0.0, 0.0, 0.0};
+            float v[3] = {0.0f, 0.0f, 0.0f}, m = 0.0f, V0 = 0.0f, R = 0.0f, Dp = 0.0f;
             float Jc[3] = {0.0f, 0.0f, 0.0f};
             if (valid) {
                 for (int a = 0; a < 3; a++) {
-                    x[a] = D.X[a * N + p] + D.u[a * N + p];
+                    x[a] = (double)D.X[a * N + p] + (double)D.u[a * N + p];
                     v[a] = D.v[a * N + p];
                 }
                 m = S.m_uniform ? S.m0 : D.m[p];
@@ -1271,46 +1269,10 @@ DEV void mixed_body(const SceneK& S, const SceneD& D, int bi, int force)
 }
 
 // ------------------------------------------------------------------------ labels
-// Side-label pass (Eqs. 3, 4, 6).  FP64 predicates with a fixed evaluation order
-// and no contraction (the same order as the CPU reference), on x = X + u and v.
-// One brick per workgroup; a brick whose AABB cannot meet any band exits at once.
-DEV bool brick_near_band(const SceneK& S, const float* bb, const DevBlade& B)
-{
-    // band extents in (s, l, f); the rear bound grows by max(u_c dt, 0)
-    double ucmax = sqrt(B.ve[0] * B.ve[0] + B.ve[1] * B.ve[1] + B.ve[2] * B.ve[2]) + (double)bb[6];
-    double flo = -B.b_back - ucmax * S.dt_d - 1e-9, fhi = B.b_lead + 1e-9;
-    double smin = 1e300, smax = -1e300, lmin = 1e300, lmax = -1e300, fmn = 1e300, fmx = -1e300;
-    for (int c = 0; c < 8; c++) {
-        double pt[3] = {(double)bb[(c & 1) ? 3 : 0], (double)bb[(c & 2) ? 4 : 1], (double)bb[(c & 4) ? 5 : 2]};
-        double r[3] = {pt[0] - B.xe[0], pt[1] - B.xe[1], pt[2] - B.xe[2]};
-        double s = r[0] * B.n[0] + r[1] * B.n[1] + r[2] * B.n[2];
-        double l = r[0] * B.e[0] + r[1] * B.e[1] + r[2] * B.e[2];
-        double f = r[0] * B.d[0] + r[1] * B.d[1] + r[2] * B.d[2];
-        smin = fmin(smin, s);
-        smax = fmax(smax, s);
-        lmin = fmin(lmin, l);
-        lmax = fmax(lmax, l);
-        fmn = fmin(fmn, f);
-        fmx = fmax(fmx, f);
-    }
-    double h = B.half_width + 1e-9, L = B.half_len + 1e-9;
-    return !(smin > h || smax < -h || lmin > L || lmax < -L || fmn > fhi || fmx < flo);
-}
-
-DEV int label_digit(const double x[3], const double v[3], const DevBlade& B, double dt)
-{
-#pragma clang fp contract(off)
-    double r0 = x[0] - B.xe[0], r1 = x[1] - B.xe[1], r2 = x[2] - B.xe[2];
-    double s = (r0 * B.n[0] + r1 * B.n[1]) + r2 * B.n[2];
-    double l = (r0 * B.e[0] + r1 * B.e[1]) + r2 * B.e[2];
-    double f = (r0 * B.d[0] + r1 * B.d[1]) + r2 * B.d[2];
-    double uc = ((B.ve[0] - v[0]) * B.d[0] + (B.ve[1] - v[1]) * B.d[1]) + (B.ve[2] - v[2]) * B.d[2];
-    double lo = -B.b_back - fmax(uc * dt, 0.0);
-    bool in_band = fabs(s) <= B.half_width && fabs(l) <= B.half_len && lo <= f && f <= B.b_lead;
-    if (!in_band || !(f <= 0.0)) return 0;
-    return (s < 0.0) ? 1 : 2;
-}
-
+// Side-label pass (Eqs. 3, 4, 6) with the predicates of tlmpm_band.h (FP64, a
+// fixed evaluation order, no contraction: the order of the CPU reference), on
+// x = X + u and v.  One brick per workgroup; a brick whose box cannot meet any band
+// exits at once.
 // Blade of tool b at this substep (TL_TOOL_ADVANCE translates the edge).
 DEV DevBlade blade_at(const DevTool& T, double jdt)
 {
@@ -1336,7 +1298,7 @@ DEV void labels_body(const SceneK& S, const SceneD& D, int bi)
         for (int b = 0; b < n_tools; b++) {
             if (!(D.tools[b].flags & TL_TOOL_LABELS)) continue;
             DevBlade B = blade_at(D.tools[b], jdt);
-            if (brick_near_band(S, bb, B)) {
+            if (brick_near_band(bb, B, S.dt_d)) {
                 s_bl[nb++] = B;
                 go = 1;
             }

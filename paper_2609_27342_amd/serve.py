@@ -1,11 +1,16 @@
 """Continuous batching of cutting rollouts on one GPU.
 
 Requests (a scene and its tool schedule over a horizon of substeps) arrive over
-time.  A request is admitted when its device footprint (tlmpm_scene_footprint)
-fits the HBM budget; every admitted request advances by one tick of substeps per
-iteration through one batched step (tlmpm_batch_step), so each kernel launch
-covers all running rollouts.  The batch is rebuilt whenever a rollout finishes or
-starts.  New scenes are built on a second stream while the current tick runs.
+time.  A request is admitted (first in, first out) when its device bytes fit the
+HBM budget beside those of the running rollouts: its scene workspace
+(tlmpm_scene_footprint) plus a bound on its share of the batch workspace
+(tlmpm_batch_scene_bytes), so the scene workspaces and the batch workspace together
+never exceed the budget.  A request that alone exceeds the budget is refused
+(status TLMPM_E_NOMEM) instead of admitted.  Every admitted request advances by one
+tick of substeps per iteration through one batched step (tlmpm_batch_step), so
+each kernel launch covers all running rollouts.  The batch is rebuilt whenever a
+rollout finishes or starts.  New scenes are built on a second stream while the
+current tick runs.
 
 The tool schedule of a request is constant over each tick: its tools at the
 first substep of the tick, moved by TLMPM_TOOL_ADVANCE within the tick.
@@ -17,9 +22,40 @@ import numpy as np
 from . import tlmpm
 
 
+class Admission:
+    """Device-byte accounting of the running rollouts against a budget."""
+
+    def __init__(self, budget_bytes):
+        self.budget = int(budget_bytes)
+        self.used = 0
+
+    def refuses(self, nbytes):
+        """A request of nbytes can never run (more than the whole budget)."""
+        return nbytes > self.budget
+
+    def fits(self, nbytes):
+        return self.used + nbytes <= self.budget
+
+    def take(self, nbytes):
+        if not self.fits(nbytes):
+            raise ValueError("admission beyond the device budget")
+        self.used += nbytes
+
+    def release(self, nbytes):
+        self.used -= nbytes
+        assert self.used >= 0
+
+
+def request_bytes(scene_dict):
+    """Device bytes a request holds while it runs: its scene workspace plus its
+    bound on the batch workspace."""
+    return tlmpm.footprint(scene_dict) + tlmpm.batch_scene_bytes(scene_dict)
+
+
 class Rollout:
-    def __init__(self, req, scene_dict, scene, arrival, admitted):
+    def __init__(self, req, scene_dict, scene, arrival, admitted, nbytes):
         self.req = req
+        self.nbytes = nbytes
         self.sd = scene_dict
         self.scene = scene
         self.arrival = arrival
@@ -48,24 +84,32 @@ class Server:
         self.create_stream = torch.cuda.Stream()
         self.results = {}
 
-    def _admit(self, queue, active, used, now_fn):
-        """Builds scenes for queued requests (FIFO) while they fit."""
+    def _admit(self, queue, active, adm, now_fn):
+        """Builds scenes for queued requests (FIFO) while they fit; refuses those
+        that exceed the whole budget."""
         admitted = []
         while queue and len(active) + len(admitted) < self.max_batch:
             req, sd, nbytes = queue[0]
             if sd is None:
                 sd = self.build(req)
-                nbytes = tlmpm.footprint(sd)
+                nbytes = request_bytes(sd)
                 queue[0] = (req, sd, nbytes)
-            if used + nbytes > self.budget and (active or admitted):
+            if adm.refuses(nbytes):
+                queue.pop(0)
+                t = now_fn()
+                self.results[req["index"]] = dict(fields=None, status=tlmpm.E_NOMEM, n=int(sd["X"].shape[0]),
+                                                  steps=int(sd["steps"]), arrival=req["_arrival_wall"], admitted=None,
+                                                  done=t, bytes=nbytes)
+                continue
+            if not adm.fits(nbytes):
                 break
             queue.pop(0)
+            adm.take(nbytes)
             with self.torch.cuda.stream(self.create_stream):
-                ws = self.torch.empty(nbytes, dtype=self.torch.uint8, device="cuda")
+                ws = self.torch.empty(tlmpm.footprint(sd), dtype=self.torch.uint8, device="cuda")
                 g = tlmpm.Scene(sd, stream=self.create_stream, workspace=ws)
-            admitted.append(Rollout(req, sd, g, req["_arrival_wall"], now_fn()))
-            used += nbytes
-        return admitted, used
+            admitted.append(Rollout(req, sd, g, req["_arrival_wall"], now_fn(), nbytes))
+        return admitted
 
     def run(self, requests, realtime=True, log=None):
         """Serves `requests` (dicts with 'arrival' seconds and whatever build()
@@ -77,7 +121,8 @@ class Server:
         pending = sorted(requests, key=lambda r: r["arrival"])
         queue = []  # (req, scene dict or None, bytes)
         active = []
-        used = 0
+        adm = Admission(self.budget)
+        self.peak_bytes = 0
         batch = None
         lat = {}
         work = 0
@@ -97,7 +142,8 @@ class Server:
                 tools = [ro.tools(self.tick) for ro in active]
                 batch.step(tools, self.tick)
             # build newly admissible scenes while the tick runs
-            new, used = self._admit(queue, active, used, now)
+            new = self._admit(queue, active, adm, now)
+            self.peak_bytes = max(self.peak_bytes, adm.used)
             if active:
                 batch.sync()
                 iters += 1
@@ -114,7 +160,7 @@ class Server:
                     out = ro.scene.read(self.read_fields)
                     st = ro.scene.status()
                     ro.scene.close()
-                    used -= ro.scene.bytes
+                    adm.release(ro.nbytes)
                     done = now()
                     lat[ro.req["index"]] = done - ro.arrival
                     self.results[ro.req["index"]] = dict(fields=out, status=st, n=ro.n, steps=ro.horizon,
@@ -126,9 +172,12 @@ class Server:
                 if active:
                     self.create_stream.synchronize()
                     batch = tlmpm.Batch([ro.scene for ro in active], stream=self.stream)
+                    # the batch workspace is within the bytes reserved at admission
+                    assert adm.used >= sum(ro.scene.bytes for ro in active) + batch.bytes
         wall = now()
         L = np.array([lat[k] for k in sorted(lat)])
-        return dict(requests=len(L), wall_s=wall, particle_steps=work, throughput=work / wall if wall > 0 else 0.0,
+        refused = sum(1 for r in self.results.values() if r["status"] == tlmpm.E_NOMEM)
+        return dict(requests=len(L), refused=refused, peak_bytes=self.peak_bytes, wall_s=wall, particle_steps=work, throughput=work / wall if wall > 0 else 0.0,
                     p50_s=float(np.percentile(L, 50)) if len(L) else None,
                     p99_s=float(np.percentile(L, 99)) if len(L) else None,
                     mean_batch=float(np.mean(sizes)) if sizes else 0.0, iterations=iters)

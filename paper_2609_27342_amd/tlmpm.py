@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libtlmpm.so")
 
 OK, E_INVALID, E_NOMEM, E_DEVICE, E_SLOT_OVERFLOW, E_NONFINITE = range(6)
 TOOL_LABELS, TOOL_CONTACT, TOOL_CUTTING, TOOL_ADVANCE = 1, 2, 4, 8
-FIELD_X, FIELD_U, FIELD_V, FIELD_F, FIELD_CODE, FIELD_D, FIELD_DIGITS = 1, 2, 4, 8, 16, 32, 64
+FIELD_X, FIELD_U, FIELD_V, FIELD_F, FIELD_CODE, FIELD_D, FIELD_DIGITS, FIELD_H = 1, 2, 4, 8, 16, 32, 64, 128
 MAX_TOOLS = 4
 
 
@@ -87,6 +87,7 @@ def lib():
         L.tlmpm_profile_enable.argtypes = [vp, C.c_int32]
         L.tlmpm_profile_read.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.tlmpm_batch_footprint.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(C.c_size_t)]
+        L.tlmpm_batch_scene_bytes.argtypes = [C.POINTER(SceneDesc), C.POINTER(C.c_size_t)]
         L.tlmpm_batch_create.argtypes = [C.POINTER(vp), C.c_int32, vp, C.c_size_t, vp, C.POINTER(vp)]
         L.tlmpm_batch_destroy.argtypes = [vp]
         L.tlmpm_batch_step.argtypes = [vp, C.POINTER(Tool), C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_double)]
@@ -98,7 +99,8 @@ def lib():
         L.tlmpm_last_error.restype = C.c_char_p
         for f in ("tlmpm_scene_footprint", "tlmpm_create_scene", "tlmpm_destroy_scene", "tlmpm_assign_labels",
                   "tlmpm_step", "tlmpm_read_state", "tlmpm_write_state", "tlmpm_get_status", "tlmpm_slot_stats", "tlmpm_contact_stats", "tlmpm_rigid_step", "tlmpm_rigid_tool",
-                  "tlmpm_profile_enable", "tlmpm_profile_read", "tlmpm_batch_footprint", "tlmpm_batch_create",
+                  "tlmpm_profile_enable", "tlmpm_profile_read", "tlmpm_batch_footprint", "tlmpm_batch_scene_bytes",
+                  "tlmpm_batch_create",
                   "tlmpm_batch_destroy", "tlmpm_batch_step", "tlmpm_batch_sync", "tlmpm_batch_profile_enable",
                   "tlmpm_batch_profile_read", "tlmpm_set_graphs", "tlmpm_batch_set_graphs"):
             getattr(L, f).restype = C.c_int
@@ -258,6 +260,15 @@ def footprint(scene):
     return nb.value
 
 
+def batch_scene_bytes(scene):
+    """Bound on the bytes the scene adds to a batch workspace (tlmpm_batch_scene_bytes)."""
+    keep = []
+    d = make_desc(scene, keep)
+    nb = C.c_size_t()
+    _check(lib().tlmpm_batch_scene_bytes(C.byref(d), C.byref(nb)))
+    return nb.value
+
+
 class Scene:
     """A scene resident on the current torch device.  `stream` is a torch stream
     (default: the current one)."""
@@ -310,7 +321,7 @@ class Scene:
         spec = {"X": (FIELD_X, (n, 3), np.float32), "u": (FIELD_U, (n, 3), np.float32),
                 "v": (FIELD_V, (n, 3), np.float32), "F": (FIELD_F, (n, 3, 3), np.float32),
                 "code": (FIELD_CODE, (n,), np.uint64), "D": (FIELD_D, (n,), np.float32),
-                "digits": (FIELD_DIGITS, (n, K), np.uint8)}
+                "digits": (FIELD_DIGITS, (n, K), np.uint8), "H": (FIELD_H, (n, 3, 3), np.float32)}
         order = sorted(fields, key=lambda f: spec[f][0])
         mask = 0
         outs = {}
@@ -324,7 +335,7 @@ class Scene:
 
     def write(self, **fields):
         spec = {"u": (FIELD_U, np.float32), "v": (FIELD_V, np.float32), "F": (FIELD_F, np.float32),
-                "D": (FIELD_D, np.float32), "digits": (FIELD_DIGITS, np.uint8)}
+                "D": (FIELD_D, np.float32), "digits": (FIELD_DIGITS, np.uint8), "H": (FIELD_H, np.float32)}
         order = sorted(fields, key=lambda f: spec[f][0])
         mask = 0
         keep = []

@@ -11,7 +11,9 @@ Tolerances (FP32 state against FP64, the two knives moved by their own wrenches)
 knife position and velocity within 1e-3 of their change over the run, angular
 velocity within 2 % of its largest component plus 1e-3 rad/s, particle positions
 within 1e-3 relative to the largest displacement, side digits equal for at least
-99.5 % of the particles.
+99.5 % of the particles (the two knives move apart by their own rounding).  Label
+parity proper (reading R25b) is checked with both sides driven by the same knife:
+the oracle's tool records, interval by interval, stepped one substep at a time.
 """
 import numpy as np
 import pytest
@@ -20,7 +22,7 @@ import oracle
 from oracle.rigid import Body
 from paper_2609_27342_amd import workloads as W
 
-from harness import disp_err, gpu_x, oracle_substep
+from harness import LabelWatch, disp_err, gpu_x, oracle_substep
 
 pytestmark = pytest.mark.gpu
 
@@ -155,3 +157,47 @@ def test_thrown_knives_parity(tl):
     print(f"[thrown] disp {e:.2e} digits {agree:.5f}", flush=True)
     assert e < 1e-3
     assert agree >= 0.995
+
+
+@pytest.mark.parametrize("which", ["knife", "thrown"])
+def test_knife_labels_with_shared_tool_records(tl, which):
+    """Reading R25b on the free-knife scenes: the GPU scene and the oracle are both
+    driven by the oracle's knives (their tool records, held over each interval and
+    advanced by the oracle's interval-averaged wrench), one substep at a time in
+    lockstep; every label that differs must belong to a particle within the
+    FP32-vs-FP64 state difference of a band face."""
+    sc = _scene() if which == "knife" else W.thrown_knives(dx=0.004, interval=5, drop=0.0005)
+    ks = [sc["knife"]] if which == "knife" else sc["knives"]["bodies"]
+    n = sc["knife"]["interval"] if which == "knife" else sc["knives"]["interval"]
+    X = sc["X"].astype(np.float64)
+    dt = sc["params"]["dt"]
+    grav = np.asarray(sc["params"]["gravity"], np.float64)
+    print(f"[case] knife labels {which} n={X.shape[0]}", flush=True)
+    g = tl.Scene(sc)
+    o = oracle.OracleScene(sc)
+    bodies = [Body(k["body"]["x"], k["body"]["q"], k["body"]["v"], k["body"]["omega"], k["body"]["mass"],
+                   k["body"]["inertia"]) for k in ks]
+    watch = LabelWatch(X, dt)
+    for it in range(N_INTERVALS):
+        tools = [b.tool(dict(k["blade"], new_cut=int(it == 0))) for b, k in zip(bodies, ks)]
+        ws = np.zeros((len(tools), 6))
+        for sub in range(n):
+            tk = tools if sub == 0 else [dict(t, blade=dict(t["blade"], new_cut=0)) for t in tools]
+            watch.before(g, o, tk)
+            g.step(tk, 1)
+            st, w = oracle_substep(o, tk)
+            assert st == 0
+            watch.after(g, o)
+            ws += np.asarray(w)
+        ws /= n
+        for b, w in zip(bodies, ws):
+            b.step(w, grav, n * dt)
+    assert g.status() == 0
+    b = o.get()
+    a = g.read(("u", "digits"))
+    e = disp_err(gpu_x(a, X), b["x"], X)
+    print(f"[knife labels {which}] disp {e:.2e} labelled {(b['digits'] != 0).sum()} mismatches {watch.mismatched()} "
+          f"checked {watch.checked}", flush=True)
+    assert (b["digits"] != 0).sum() > 10
+    assert not watch.bad, watch.bad[:5]
+    assert e < 1e-3

@@ -1,8 +1,11 @@
 """GPU path (through the C ABI) against the FP64 oracle on the same seeded inputs.
 
-Tolerances: labels bit-exact; after one substep the FP32 state is within 1e-5 of
-the oracle relative to the field's largest value; after 100 substeps positions are
-within 1e-3 relative to the largest displacement.
+Tolerances: labels bit-exact in shared-input mode, and in independent rollouts any
+label that differs must come from a particle within the FP32-vs-FP64 state
+difference of a band face (reading R25b); after one substep the displacement
+u = x - X, the velocity and H = F - I are within 1e-5 of the oracle's, each
+relative to its own largest value; after 100 substeps positions are within 1e-3
+relative to the largest displacement.
 """
 import numpy as np
 import pytest
@@ -10,7 +13,7 @@ import pytest
 import oracle
 from paper_2609_27342_amd import workloads as W
 
-from harness import disp_err, field_err, gpu_x, oracle_substep
+from harness import LabelWatch, disp_err, field_err, gpu_x, oracle_substep, state_errs
 
 pytestmark = pytest.mark.gpu
 
@@ -38,12 +41,12 @@ def test_one_substep_parity(tl, deep):
     tools = s["tools_at"](0)
     g.step(tools)
     oracle_substep(o, tools)
-    a = g.read(("u", "v", "F", "digits"))
+    a = g.read(("u", "v", "F", "H", "digits"))
     b = o.get()
     assert np.array_equal(a["digits"], b["digits"])
-    assert field_err(gpu_x(a, s["X"]), b["x"]) < 1e-5
-    assert field_err(a["v"], b["v"]) < 1e-5
-    assert field_err(a["F"], b["F"]) < 1e-5
+    eu, ev, eH = state_errs(a, b, s["X"], s["params"])
+    print(f"[one_substep] {s['name']} u {eu:.2e} v {ev:.2e} H {eH:.2e}", flush=True)
+    assert eu < 1e-5 and ev < 1e-5 and eH < 1e-5, (eu, ev, eH)
     assert g.status() == 0
     if deep:
         tot, mx = g.slot_stats()
@@ -73,15 +76,19 @@ def test_hundred_substeps_positions(tl):
     _print_case("hundred", scene=s["name"])
     g = tl.Scene(s)
     o = oracle.OracleScene(s)
+    watch = LabelWatch(s["X"], s["params"]["dt"])
     for j in range(100):
         tools = s["tools_at"](j)
+        watch.before(g, o, tools)
         g.step(tools)
         oracle_substep(o, tools)
+        watch.after(g, o)
     a = g.read(("u", "v", "digits"))
     b = o.get()
-    mism = (a["digits"] != b["digits"]).sum()
-    assert mism <= 0.001 * a["digits"].size
-    assert disp_err(gpu_x(a, s["X"]), b["x"], s["X"]) < 1e-3
+    e = disp_err(gpu_x(a, s["X"]), b["x"], s["X"])
+    print(f"[hundred] disp {e:.2e} label mismatches {watch.mismatched()} checked {watch.checked}", flush=True)
+    assert not watch.bad, watch.bad[:5]
+    assert e < 1e-3
     assert g.status() == 0
 
 
@@ -92,7 +99,7 @@ def test_determinism_bitwise(tl):
         g = tl.Scene(s)
         for j in range(5):
             g.step(s["tools_at"](j))
-        outs.append(g.read(("u", "v", "F")))
+        outs.append(g.read(("u", "v", "F", "H")))
     for k in outs[0]:
         assert np.array_equal(outs[0][k], outs[1][k]), k
 
@@ -128,13 +135,13 @@ def test_momentum_conservation_gpu(tl, beta, cuts):
         g.step([])
         o.step([])
     assert g.status() == 0
-    a = g.read(("u", "v", "F"))
+    a = g.read(("u", "v", "F", "H"))
     P1 = (m[:, None] * a["v"]).sum(axis=0)
     assert np.abs(P1 - P0).max() < 1e-5 * scale
     b = o.get()
-    assert field_err(a["v"], b["v"]) < 1e-5
-    assert field_err(a["F"], b["F"]) < 1e-5
-    assert field_err(gpu_x(a, s["X"]), b["x"]) < 1e-5
+    eu, ev, eH = state_errs(a, b, s["X"], s["params"])
+    print(f"[momentum] beta={beta} cuts={cuts} u {eu:.2e} v {ev:.2e} H {eH:.2e}", flush=True)
+    assert eu < 1e-5 and ev < 1e-5 and eH < 1e-5, (eu, ev, eH)
 
 
 def test_zero_exchange_gpu(tl):
@@ -165,7 +172,7 @@ def test_uniform_translation_gpu(tl):
     g = tl.Scene(s)
     dt = s["params"]["dt"]
     g.step([], n_substeps=4)
-    a = g.read(("u", "v", "F"))
+    a = g.read(("u", "v", "F", "H"))
     vv = np.array(v0, np.float32).astype(np.float64)
     assert np.abs(a["v"] - vv).max() < 1e-6
     assert np.abs(a["F"] - np.eye(3)).max() < 1e-6
@@ -203,17 +210,26 @@ def test_split_bricks_parity_and_determinism(tl):
         for j in range(20):
             g.step(tools_at(j))
         assert g.status() == 0
-        runs.append(g.read(("u", "v", "F", "digits")))
+        runs.append(g.read(("u", "v", "F", "H", "digits")))
     for f in ("u", "v", "F", "digits"):
         assert np.array_equal(runs[0][f], runs[1][f]), f
     o = oracle.OracleScene(s)
+    g = tl.Scene(s)
+    watch = LabelWatch(s["X"], dt)
     for j in range(20):
+        watch.before(g, o, tools_at(j))
+        g.step(tools_at(j))
         oracle_substep(o, tools_at(j))
+        watch.after(g, o)
     b = o.get()
-    a = runs[0]
+    a = g.read(("u", "v", "F", "H", "digits"))
+    for f in ("u", "v", "F", "digits"):
+        assert np.array_equal(a[f], runs[0][f]), f
     assert (b["digits"] > 0).sum() > 1000  # the cut went through many cells
-    assert np.mean(np.all(a["digits"] == b["digits"], axis=1)) >= 0.999
-    assert disp_err(gpu_x(a, s["X"]), b["x"], s["X"]) < 1e-3
+    e = disp_err(gpu_x(a, s["X"]), b["x"], s["X"])
+    print(f"[split] disp {e:.2e} label mismatches {watch.mismatched()} checked {watch.checked}", flush=True)
+    assert not watch.bad, watch.bad[:5]
+    assert e < 1e-3
 
 
 def test_one_stream_launches_equal_two_stream_launches(tl):
@@ -231,7 +247,7 @@ def test_one_stream_launches_equal_two_stream_launches(tl):
         for j in range(30):
             g.step(s["tools_at"](j))
         assert g.status() == 0
-        outs.append(g.read(("u", "v", "F", "digits")))
+        outs.append(g.read(("u", "v", "F", "H", "digits")))
     assert outs[0]["digits"].any()
     for k in outs[0]:
         assert np.array_equal(outs[0][k], outs[1][k]), k

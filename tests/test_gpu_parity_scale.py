@@ -1,0 +1,161 @@
+"""GPU path against the FP64 oracle on the scene families of the many-scene,
+served and large workloads, through the C ABI.
+
+- Three scenes of the many-scene workload (random box or cylinder, two or three
+  simultaneous blades each with its own cut, slot capacity 16, floor and material
+  contact) over 20 substeps, each run alone in lockstep with the oracle; the same
+  scenes stepped as one batch end bitwise equal to the runs alone.
+- One request of the served workload (one to four sequential cuts) served by the
+  continuous-batching loop, against the oracle fed the same tool poses.
+- The large box at dx = 2.5 mm (3.07M particles, about 6,600 active bricks: more
+  than 4096, so unsplit bricks in several rounds of workgroups, the second stream,
+  separate label / rigid / pair launches and large hash tables) over 5 substeps
+  with three blades cutting.
+
+Tolerances: one substep within 1e-5 (u, v, H each relative to its own largest
+value or one substep's increment scale, tests/harness.py), positions after the rollout within 1e-3 of the largest displacement, and
+every label that differs explained by the FP32-vs-FP64 state difference at a band
+face (reading R25b).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2609_27342_amd import workloads as W
+
+from harness import LabelWatch, disp_err, gpu_x, oracle_substep, state_errs
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("u", "v", "F", "H", "code", "D", "digits")
+
+
+@pytest.fixture(scope="module")
+def tl():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2609_27342_amd import tlmpm
+    tlmpm.lib()
+    return tlmpm
+
+
+def _print_case(name, **kw):
+    print(f"[case] {name} {kw}", flush=True)
+
+
+def _lockstep(tl, s, calls, one_step_check=True):
+    """Runs the GPU scene and the oracle through calls [(tools, count)], one substep
+    at a time with the tools of each substep (poses moved by dt * velocity inside a
+    call exactly as TLMPM_TOOL_ADVANCE does on the device).  Returns (GPU state,
+    oracle state, LabelWatch, GPU scene)."""
+    X = s["X"].astype(np.float64)
+    dt = s["params"]["dt"]
+    g = tl.Scene(s)
+    o = oracle.OracleScene(s)
+    watch = LabelWatch(X, dt)
+    first = True
+    for tools, cnt in calls:
+        for k in range(cnt):
+            tk = [_advanced(t, k, dt) for t in tools]
+            watch.before(g, o, tk)
+            g.step([dict(t, advance=False) for t in tk], 1)
+            st, _ = oracle_substep(o, tk)
+            assert st == 0
+            watch.after(g, o)
+            if first and one_step_check:
+                a, b = g.read(("u", "v", "F", "H")), o.get()
+                eu, ev, eH = state_errs(a, b, X, s["params"])
+                print(f"[lockstep] {s.get('name')} one substep u {eu:.2e} v {ev:.2e} H {eH:.2e}", flush=True)
+                assert eu < 1e-5 and ev < 1e-5 and eH < 1e-5, (eu, ev, eH)
+            first = False
+    return g.read(FIELDS), o.get(), watch, g
+
+
+def _advanced(t, k, dt):
+    """Tool t after k substeps of TLMPM_TOOL_ADVANCE: pose + (k dt) * velocity, the
+    expression the kernels evaluate in FP64."""
+    if k == 0 or not t.get("advance"):
+        return dict(t)
+    jdt = float(k) * dt
+    bl = dict(t["blade"], x_e=np.asarray(t["blade"]["x_e"]) + jdt * np.asarray(t["blade"]["v_e"]), new_cut=0)
+    return dict(t, blade=bl, x_B=np.asarray(t["x_B"]) + jdt * np.asarray(t["v_B"]))
+
+
+def _report(tag, s, a, b, watch):
+    X = s["X"].astype(np.float64)
+    e = disp_err(gpu_x(a, X), b["x"], X)
+    eu, ev, eH = state_errs(a, b, X, s["params"])
+    print(f"[{tag}] n={X.shape[0]} disp {e:.2e} u {eu:.2e} v {ev:.2e} H {eH:.2e} label mismatches "
+          f"{watch.mismatched()} checked {watch.checked} labelled {(b['digits'] != 0).sum()}", flush=True)
+    return e
+
+
+def test_batch_scenes_match_oracle(tl):
+    scenes = [W.batch_scene(21, i, 30000, steps=40) for i in (6, 9, 1)]
+    K = 20
+    assert [len(s["tools_at"](0)) for s in scenes] == [3, 3, 2]
+    assert all(s["params"]["slot_capacity"] == 16 for s in scenes)
+    _print_case("batch scenes vs oracle", n=[s["X"].shape[0] for s in scenes], steps=K)
+    alone = []
+    for s in scenes:
+        calls = [(s["tools_at"](j), 1) for j in range(K)]
+        a, b, watch, g = _lockstep(tl, s, calls)
+        assert g.status() == 0
+        e = _report("batch scene", s, a, b, watch)
+        assert (b["digits"] != 0).sum() > 100
+        assert not watch.bad, watch.bad[:5]
+        assert e < 1e-3
+        alone.append(a)
+        g.close()
+    gs = [tl.Scene(s) for s in scenes]
+    with tl.Batch(gs) as bt:
+        for j in range(K):
+            bt.step([s["tools_at"](j) for s in scenes], 1)
+    for i, g in enumerate(gs):
+        assert g.status() == 0
+        got = g.read(FIELDS)
+        for f in FIELDS:
+            assert np.array_equal(got[f], alone[i][f]), (i, f)
+
+
+def test_served_request_matches_oracle(tl):
+    from paper_2609_27342_amd import serve
+    tick, horizon = 20, 80
+    req = dict(index=3, arrival=0.0, n_target=20000, horizon=horizon, seed=17, tick=tick)
+    build = lambda r: W.served_request(r["seed"], r["index"], r["n_target"], r["horizon"], r["tick"])
+    sd = build(req)
+    cuts = {t["blade"]["cut_index"] for j in range(0, horizon, tick) for t in sd["tools_at"](j)}
+    assert len(cuts) >= 2, cuts
+    _print_case("served request vs oracle", n=sd["X"].shape[0], cuts=len(cuts))
+    srv = serve.Server(build, 1 << 40, tick=tick, read_fields=FIELDS)
+    srv.run([req], realtime=False)
+    got = srv.results[req["index"]]
+    assert got["status"] == 0
+    calls = [([dict(t, advance=True) for t in sd["tools_at"](j)], tick) for j in range(0, horizon, tick)]
+    a, b, watch, g = _lockstep(tl, sd, calls)
+    e = _report("served request", sd, a, b, watch)
+    assert not watch.bad, watch.bad[:5]
+    assert e < 1e-3
+    # the served rollout (TLMPM_TOOL_ADVANCE within each tick, poses formed on the
+    # device) and the lockstep run (poses formed on the host) are the same rollout
+    # up to the rounding of those poses
+    X = sd["X"].astype(np.float64)
+    assert disp_err(gpu_x(got["fields"], X), gpu_x(a, X), X) < 1e-4
+
+
+@pytest.mark.timeout(900)
+def test_large_scene_over_4096_bricks_matches_oracle(tl):
+    s = W.large(dx=0.0025)
+    n = s["X"].shape[0]
+    _print_case("large dx=2.5mm vs oracle", n=n)
+    K = 5
+    calls = [(s["tools_at"](j), 1) for j in range(K)]
+    a, b, watch, g = _lockstep(tl, s, calls)
+    assert g.status() == 0
+    tot, mx = g.slot_stats()
+    assert mx >= 3  # nodes where crossing cuts meet
+    e = _report("large", s, a, b, watch)
+    assert (b["digits"] != 0).sum() > 10000
+    assert not watch.bad, watch.bad[:5]
+    assert e < 1e-3

@@ -46,3 +46,30 @@ def test_served_rollouts_equal_alone(tl):
         for f in ref:
             assert np.array_equal(got["fields"][f], ref[f]), (r["index"], f)
         g.close()
+
+
+def test_admission_budget_and_refusal(tl):
+    """Admission holds the running rollouts' scene workspaces plus their bounds on
+    the batch workspace within the budget (the batch the loop builds fits what was
+    reserved, checked inside the loop); a request larger than the whole budget is
+    refused with TLMPM_E_NOMEM, and the others are served."""
+    from paper_2609_27342_amd import serve
+    reqs = W.served(seed=8, n_requests=5, n_range=(2500, 6000), horizon_s=(0.01, 0.02), tick=TICK)
+    big = W.served(seed=9, n_requests=1, n_range=(60000, 60000), horizon_s=(0.01, 0.01), tick=TICK)[0]
+    big = dict(big, index=99, arrival=reqs[1]["arrival"])
+    sds = {r["index"]: _build(r) for r in reqs + [big]}
+    need = {i: serve.request_bytes(sd) for i, sd in sds.items()}
+    budget = sum(sorted(need[r["index"]] for r in reqs)[-2:]) + 1  # two small rollouts at a time
+    assert need[99] > budget
+    print(f"[case] admission budget={budget} bytes={need}", flush=True)
+    srv = serve.Server(lambda r: sds[r["index"]], budget, tick=TICK)
+    stats = srv.run(reqs + [big], realtime=False)
+    assert stats["refused"] == 1 and srv.results[99]["status"] == tl.E_NOMEM
+    assert srv.results[99]["fields"] is None
+    assert stats["requests"] == len(reqs)
+    assert all(srv.results[r["index"]]["status"] == 0 for r in reqs)
+    assert 0 < stats["peak_bytes"] <= budget
+    # the per-scene bounds cover the batch workspace of any set of these scenes
+    gs = [tl.Scene(sds[r["index"]]) for r in reqs]
+    with tl.Batch(gs) as b:
+        assert b.bytes <= sum(tl.batch_scene_bytes(sds[r["index"]]) for r in reqs)
