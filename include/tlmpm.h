@@ -274,6 +274,25 @@ tlmpm_status tlmpm_batch_scene_bytes(const tlmpm_scene_desc* desc, size_t* devic
 tlmpm_status tlmpm_batch_create(tlmpm_scene* const* scenes, int32_t n_scenes, void* dev_workspace, size_t bytes,
                                 void* hip_stream, tlmpm_batch** out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): tlmpm_batch_create
+ * without a workspace argument.  The batch workspace is a fixed array of
+ * TL_STATIC_SCRATCH_BYTES = 16 MiB in the library's device image, one per GPU
+ * (the calling thread's current device, 0..7), held until the process ends; its
+ * per-call tool staging is a static host array (pageable, so each tlmpm_batch_step
+ * first waits for the batch's stream).  This call allocates no device or pinned
+ * memory (no hipMalloc, hipHostMalloc, hipFree or torch allocator); the handle's
+ * host bookkeeping is on the C++ heap.  A device's array serves one batch at a
+ * time: while a batch built here is alive, another call on the same device fails
+ * with TLMPM_E_INVALID (two batches on one array would race).  Nothing in the
+ * array needs to start at zero: creation uploads the tables and every step
+ * uploads its tools and clears its wrench sums.  TLMPM_E_NOMEM if the batch needs
+ * more than 16 MiB (tlmpm_batch_footprint) or more than 1024 scenes; 256 scenes of
+ * 13.3M particles need 3.2 MiB.  Otherwise as tlmpm_batch_create; destroy with
+ * tlmpm_batch_destroy, which releases the array. */
+tlmpm_status tlmpm_batch_create_static(tlmpm_scene* const* scenes, int32_t n_scenes, void* hip_stream,
+                                       tlmpm_batch** out);
+
 tlmpm_status tlmpm_batch_destroy(tlmpm_batch* batch);
 
 /* n_substeps substeps of every member scene (as tlmpm_step).  tools: array of

@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -36,6 +37,7 @@ hipError_t tl_launch_cand_contact_slots(const TlLaunch*, int dst, int src);
 hipError_t tl_launch_fill_f32(float*, long long, float, hipStream_t);
 hipError_t tl_launch_fill_i32(int*, long long, int, hipStream_t);
 hipError_t tl_launch_quad(const TlLaunch*, int par, int stage);
+hipError_t tl_static_scratch(int dev, void** ptr);
 }
 
 static thread_local std::string g_err;
@@ -1626,8 +1628,21 @@ tlmpm_status check_members(tlmpm_scene* const* scenes, int n)
 }
 } // namespace
 
+// Host staging of the batches built on a device's static scratch: static arrays,
+// so that such a batch allocates no pinned memory; one batch per device at a time.
+namespace {
+struct StaticStaging {
+    BatchTools tools[TL_STATIC_MAX_SCENES];
+    double wacc[TL_STATIC_MAX_SCENES * TL_MAX_TOOLS * 6];
+};
+StaticStaging g_static_staging[TL_STATIC_DEVICES];
+bool g_static_held[TL_STATIC_DEVICES];
+std::mutex g_static_mutex;
+} // namespace
+
 struct tlmpm_batch {
     std::vector<tlmpm_scene*> sc;
+    int static_dev = -1; // device whose static scratch and staging this batch holds, else -1
     hipStream_t st;
     TlLaunch L;
     BatchTools* d_tools;
@@ -1640,6 +1655,11 @@ struct tlmpm_batch {
     Fork fork;
     ~tlmpm_batch()
     {
+        if (static_dev >= 0) {
+            std::lock_guard<std::mutex> lk(g_static_mutex);
+            g_static_held[static_dev] = false;
+            return;
+        }
         if (h_tools) (void)hipHostFree(h_tools);
         if (h_wacc) (void)hipHostFree(h_wacc);
         if (up_done) (void)hipEventDestroy(up_done);
@@ -1675,15 +1695,27 @@ extern "C" tlmpm_status tlmpm_batch_scene_bytes(const tlmpm_scene_desc* desc, si
     return TLMPM_OK;
 }
 
-extern "C" tlmpm_status tlmpm_batch_create(tlmpm_scene* const* scenes, int32_t n_scenes, void* ws, size_t bytes,
-                                           void* hip_stream, tlmpm_batch** out)
+// static_dev >= 0: ws is that device's static scratch, already held for this batch
+// (released by the batch, or here on failure), staging from the static arrays.
+static tlmpm_status batch_create(tlmpm_scene* const* scenes, int32_t n_scenes, void* ws, size_t bytes,
+                                 void* hip_stream, tlmpm_batch** out, int static_dev)
 {
-    if (tlmpm_status r = check_members(scenes, n_scenes)) return r;
-    if (!out) return fail(TLMPM_E_INVALID, "null output");
+    auto release = [&]() {
+        if (static_dev < 0) return;
+        std::lock_guard<std::mutex> lk(g_static_mutex);
+        g_static_held[static_dev] = false;
+    };
+    if (tlmpm_status r = check_members(scenes, n_scenes)) return release(), r;
+    if (!out) return release(), fail(TLMPM_E_INVALID, "null output");
     *out = nullptr;
     BatchPlan P;
-    if (tlmpm_status r = batch_plan(scenes, n_scenes, P)) return r;
-    if (!ws || bytes < P.total) return fail(TLMPM_E_NOMEM, "workspace smaller than tlmpm_batch_footprint()");
+    if (tlmpm_status r = batch_plan(scenes, n_scenes, P)) return release(), r;
+    if (static_dev >= 0 && (P.total > TL_STATIC_SCRATCH_BYTES || n_scenes > TL_STATIC_MAX_SCENES))
+        return release(), fail(TLMPM_E_NOMEM, "batch needs " + std::to_string(P.total) + " bytes over " +
+                                                  std::to_string(n_scenes) + " scenes; the static scratch holds " +
+                                                  std::to_string((size_t)TL_STATIC_SCRATCH_BYTES) + " bytes and " +
+                                                  std::to_string(TL_STATIC_MAX_SCENES) + " scenes");
+    if (!ws || bytes < P.total) return release(), fail(TLMPM_E_NOMEM, "workspace smaller than tlmpm_batch_footprint()");
 
     // common slot-table state: that of the scenes with a pending F update (the
     // first one's); scenes in another state apply their F update alone, and scenes
@@ -1700,17 +1732,22 @@ extern "C" tlmpm_status tlmpm_batch_create(tlmpm_scene* const* scenes, int32_t n
     for (int s = 0; s < n_scenes; s++) {
         tlmpm_scene* sc = scenes[s];
         if (sc->f_pending && (sc->cur != cur || sc->rsb != rsb))
-            if (tlmpm_status r = flush_F(sc)) return r;
+            if (tlmpm_status r = flush_F(sc)) return release(), r;
         if (!sc->f_pending && sc->cur != cur) {
             const TlLaunch L1 = single_launch(sc);
-            HIPCHK(tl_launch_slots(&L1, cur, sc->cur, 0));
+            hipError_t e = tl_launch_slots(&L1, cur, sc->cur, 0);
+            if (e != hipSuccess) return release(), fail(TLMPM_E_DEVICE, std::string("slot tables: ") + hipGetErrorString(e));
             sc->cur = cur;
         }
         if (!sc->f_pending) sc->rsb = rsb;
     }
-    for (int s = 0; s < n_scenes; s++) HIPCHK(hipStreamSynchronize(scenes[s]->st));
+    for (int s = 0; s < n_scenes; s++) {
+        hipError_t e = hipStreamSynchronize(scenes[s]->st);
+        if (e != hipSuccess) return release(), fail(TLMPM_E_DEVICE, std::string("scene stream: ") + hipGetErrorString(e));
+    }
 
     tlmpm_batch* b = new tlmpm_batch();
+    b->static_dev = static_dev; // from here the batch releases the hold
     b->sc.assign(scenes, scenes + n_scenes);
     b->st = (hipStream_t)hip_stream;
     b->prof.st = b->st;
@@ -1761,17 +1798,50 @@ extern "C" tlmpm_status tlmpm_batch_create(tlmpm_scene* const* scenes, int32_t n
                                 hipMemcpyHostToDevice, b->st)) != hipSuccess)
             return bail(e, "upload work items");
     }
-    if ((e = hipHostMalloc((void**)&b->h_tools, n_scenes * sizeof(BatchTools), hipHostMallocDefault)) != hipSuccess)
-        return bail(e, "pinned staging");
-    if ((e = hipHostMalloc((void**)&b->h_wacc, n_scenes * TL_MAX_TOOLS * 6 * sizeof(double), hipHostMallocDefault)) !=
-        hipSuccess)
-        return bail(e, "pinned staging");
-    if ((e = hipEventCreateWithFlags(&b->up_done, hipEventDisableTiming)) != hipSuccess) return bail(e, "event");
+    if (static_dev >= 0) {
+        // pageable staging: batch_step waits for the batch's stream before reusing it
+        b->h_tools = g_static_staging[static_dev].tools;
+        b->h_wacc = g_static_staging[static_dev].wacc;
+    } else {
+        if ((e = hipHostMalloc((void**)&b->h_tools, n_scenes * sizeof(BatchTools), hipHostMallocDefault)) !=
+            hipSuccess)
+            return bail(e, "pinned staging");
+        if ((e = hipHostMalloc((void**)&b->h_wacc, n_scenes * TL_MAX_TOOLS * 6 * sizeof(double),
+                               hipHostMallocDefault)) != hipSuccess)
+            return bail(e, "pinned staging");
+        if ((e = hipEventCreateWithFlags(&b->up_done, hipEventDisableTiming)) != hipSuccess) return bail(e, "event");
+    }
 
     if ((e = hipStreamSynchronize(b->st)) != hipSuccess) return bail(e, "create batch");
     for (tlmpm_scene* sc : b->sc) sc->in_batch = 1;
     *out = b;
     return TLMPM_OK;
+}
+
+extern "C" tlmpm_status tlmpm_batch_create(tlmpm_scene* const* scenes, int32_t n_scenes, void* ws, size_t bytes,
+                                           void* hip_stream, tlmpm_batch** out)
+{
+    return batch_create(scenes, n_scenes, ws, bytes, hip_stream, out, -1);
+}
+
+extern "C" tlmpm_status tlmpm_batch_create_static(tlmpm_scene* const* scenes, int32_t n_scenes, void* hip_stream,
+                                                  tlmpm_batch** out)
+{
+    if (out) *out = nullptr;
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= TL_STATIC_DEVICES)
+        return fail(TLMPM_E_INVALID, "static scratch exists for devices 0.." + std::to_string(TL_STATIC_DEVICES - 1));
+    void* ptr = nullptr;
+    HIPCHK(tl_static_scratch(dev, &ptr)); // first call on this device: hipGetSymbolAddress
+    {
+        std::lock_guard<std::mutex> lk(g_static_mutex);
+        if (g_static_held[dev])
+            return fail(TLMPM_E_INVALID, "the static scratch of device " + std::to_string(dev) +
+                                             " is held by a live batch (destroy it first)");
+        g_static_held[dev] = true;
+    }
+    return batch_create(scenes, n_scenes, ptr, TL_STATIC_SCRATCH_BYTES, hip_stream, out, dev);
 }
 
 extern "C" tlmpm_status tlmpm_batch_destroy(tlmpm_batch* b)
@@ -1792,7 +1862,12 @@ extern "C" tlmpm_status tlmpm_batch_step(tlmpm_batch* b, const tlmpm_tool* tools
     for (int s = 0; s < n; s++)
         if (n_tools[s] < 0 || n_tools[s] > TL_MAX_TOOLS || (n_tools[s] > 0 && !tools))
             return fail(TLMPM_E_INVALID, "bad tool count (at most 4 tools per scene)");
-    HIPCHK(hipEventSynchronize(b->up_done)); // staging free again
+    // staging free again: the last upload from it finished (pageable staging of a
+    // batch on static scratch: the whole stream)
+    if (b->up_done)
+        HIPCHK(hipEventSynchronize(b->up_done));
+    else
+        HIPCHK(hipStreamSynchronize(b->st));
     CallFlags f;
     for (int s = 0; s < n; s++) {
         tlmpm_status r = convert_tools(b->sc[s], n_tools[s] ? tools + (size_t)s * TL_MAX_TOOLS : nullptr, n_tools[s],
@@ -1800,7 +1875,7 @@ extern "C" tlmpm_status tlmpm_batch_step(tlmpm_batch* b, const tlmpm_tool* tools
         if (r) return fail(r, "scene " + std::to_string(s) + ": " + g_err);
     }
     HIPCHK(hipMemcpyAsync(b->d_tools, b->h_tools, n * sizeof(BatchTools), hipMemcpyHostToDevice, b->st));
-    HIPCHK(hipEventRecord(b->up_done, b->st));
+    if (b->up_done) HIPCHK(hipEventRecord(b->up_done, b->st));
     HIPCHK(b->fork.init());
     Exec X;
     X.L = b->L;

@@ -20,6 +20,9 @@
 #define TL_BOX_SLOTS 640       // slots of one brick box held in LDS
 #define TL_MAX_TOOLS 4          // tools per scene (rigid-history slots 1..4; slot 0 = floor)
 #define TL_WG 512              // threads per brick workgroup: 8 waves = 8 parity classes
+#define TL_STATIC_SCRATCH_BYTES (16u << 20) // workspace of a batch that allocates nothing (16 MiB)
+#define TL_STATIC_DEVICES 8    // GPUs of one process that can hold such a batch
+#define TL_STATIC_MAX_SCENES 1024 // scenes of such a batch (its host staging is static)
 
 #define TL_CODE_MASK 0x3FFFFFFFu
 #define TL_PREV_BIT 0x40000000u

@@ -23,6 +23,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "tlmpm_common.h"
 #include "tlmpm_band.h"
 #include "tlmpm_device.h"
@@ -1359,6 +1361,11 @@ DEV void call_start_body(const SceneK& S, const SceneD& D, int bi)
     if (D.tinfo[1] && threadIdx.x < TL_MAX_TOOLS * 6) D.wacc[threadIdx.x] = 0.0;
 }
 
+// Workspace of the batches that allocate no device memory (tlmpm_batch_create_static):
+// one array per GPU, held by at most one such batch at a time, for the life of the
+// process.  Its size bounds their footprint (TL_STATIC_SCRATCH_BYTES).
+static __device__ __align__(256) unsigned char scratch[TL_STATIC_SCRATCH_BYTES];
+
 __global__ void k_fill_f32(float* p, long long n, float v)
 {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1702,5 +1709,30 @@ hipError_t tl_launch_fill_i32(int* p, long long n, int v, hipStream_t st)
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
     return hipGetLastError();
+}
+
+// Device address of this GPU's copy of `scratch` (the batch workspace of
+// tlmpm_batch_create_static), looked up once per device with that device current
+// and kept: in host code the array's name is only a stand-in, never a device
+// address.
+hipError_t tl_static_scratch(int dev, void** ptr)
+{
+    static std::mutex m;
+    static void* addr[TL_STATIC_DEVICES] = {};
+    if (dev < 0 || dev >= TL_STATIC_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(m);
+    if (!addr[dev]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != dev) return hipErrorInvalidDevice;
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
 }
 }

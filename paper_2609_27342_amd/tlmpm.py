@@ -89,6 +89,7 @@ def lib():
         L.tlmpm_batch_footprint.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(C.c_size_t)]
         L.tlmpm_batch_scene_bytes.argtypes = [C.POINTER(SceneDesc), C.POINTER(C.c_size_t)]
         L.tlmpm_batch_create.argtypes = [C.POINTER(vp), C.c_int32, vp, C.c_size_t, vp, C.POINTER(vp)]
+        L.tlmpm_batch_create_static.argtypes = [C.POINTER(vp), C.c_int32, vp, C.POINTER(vp)]
         L.tlmpm_batch_destroy.argtypes = [vp]
         L.tlmpm_batch_step.argtypes = [vp, C.POINTER(Tool), C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_double)]
         L.tlmpm_batch_sync.argtypes = [vp]
@@ -100,7 +101,7 @@ def lib():
         for f in ("tlmpm_scene_footprint", "tlmpm_create_scene", "tlmpm_destroy_scene", "tlmpm_assign_labels",
                   "tlmpm_step", "tlmpm_read_state", "tlmpm_write_state", "tlmpm_get_status", "tlmpm_slot_stats", "tlmpm_contact_stats", "tlmpm_rigid_step", "tlmpm_rigid_tool",
                   "tlmpm_profile_enable", "tlmpm_profile_read", "tlmpm_batch_footprint", "tlmpm_batch_scene_bytes",
-                  "tlmpm_batch_create",
+                  "tlmpm_batch_create", "tlmpm_batch_create_static",
                   "tlmpm_batch_destroy", "tlmpm_batch_step", "tlmpm_batch_sync", "tlmpm_batch_profile_enable",
                   "tlmpm_batch_profile_read", "tlmpm_set_graphs", "tlmpm_batch_set_graphs"):
             getattr(L, f).restype = C.c_int
@@ -387,7 +388,9 @@ class Batch:
     """Scenes advanced together by shared kernel launches.  While the batch is
     open its scenes refuse single-scene calls; close() releases them."""
 
-    def __init__(self, scenes, stream=None, workspace=None):
+    def __init__(self, scenes, stream=None, workspace=None, static=False):
+        """static=True: the workspace is the library's per-device static array
+        (tlmpm_batch_create_static), nothing is allocated."""
         import torch
         L = lib()
         self.scenes = list(scenes)
@@ -396,14 +399,19 @@ class Batch:
         nb = C.c_size_t()
         _check(L.tlmpm_batch_footprint(self._hs, n, C.byref(nb)))
         self.bytes = nb.value
-        if workspace is None:
-            workspace = torch.empty(self.bytes, dtype=torch.uint8, device="cuda")
-        assert workspace.numel() >= self.bytes and workspace.is_cuda
-        self.ws = workspace
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = C.c_void_p()
-        _check(L.tlmpm_batch_create(self._hs, n, C.c_void_p(workspace.data_ptr()), self.bytes,
-                                    C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        if static:
+            assert workspace is None
+            self.ws = None
+            _check(L.tlmpm_batch_create_static(self._hs, n, C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        else:
+            if workspace is None:
+                workspace = torch.empty(self.bytes, dtype=torch.uint8, device="cuda")
+            assert workspace.numel() >= self.bytes and workspace.is_cuda
+            self.ws = workspace
+            _check(L.tlmpm_batch_create(self._hs, n, C.c_void_p(workspace.data_ptr()), self.bytes,
+                                        C.c_void_p(self.stream.cuda_stream), C.byref(h)))
         self.h = h
         self._tools = (Tool * (MAX_TOOLS * max(1, n)))()
         self._counts = (C.c_int32 * max(1, n))()
