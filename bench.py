@@ -7,9 +7,14 @@ and grid update, G2P, MUSL re-scatter and the deformation-gradient update.  The
 workload is a seeded synthetic scene (paper_2609_27342_amd.workloads) resident in
 HBM before timing; tool schedules run as constant-velocity segments.
 
-Prints ONE JSON line (rank 0) with particle-steps/s, the roofline of the dominant
-kernel (algorithmic bytes over its event-timed duration) and the FP64 CPU oracle
-timed on a bounded sample of the same workload.
+Default workload: the large box (14.2M particles, three blades cutting from the
+first substep), the HBM-bound configuration; the many-scene workload (plain one
+scene per call against one batch) is reported beside it in config.batched.
+
+Prints ONE JSON line with particle-steps/s, the roofline of the dominant kernel
+(P2G: algorithmic bytes over its duration, timed by HIP events on the scene's
+stream around its launches inside the timed region) and the FP64 CPU oracle timed
+on a bounded sample of the same workload, on one thread and on all threads.
 """
 import argparse
 import json
@@ -30,9 +35,11 @@ HBM_PEAK_GBS = 8000.0
 ALG_BYTES = {"p2g": 100, "g2p": 64}
 # quadratic stencil: P2G reads X, code, v and F (64 B); the F update is a kernel of its own
 ALG_BYTES_QUAD = {"p2g": 64, "g2p": 64}
-ALG_STEP_BYTES = 136
-DEFAULTS = {"small": (100, 10), "small-deep": (100, 10), "medium": (3000, 300), "large": (200, 10),
+ALG_STEP_BYTES = 136  # + 4 with per-particle E
+DEFAULTS = {"small": (100, 10), "small-deep": (100, 10), "medium": (3000, 300), "large": (100, 10),
             "batched": (100, 10), "knife": (600, 50), "thrown-knives": (300, 20)}
+# the part of the large box the CPU baseline runs on: where cuts 0 and 2 cross
+LARGE_SAMPLE = ((0.07, 0.13), (0.07, 0.13))
 
 
 def step_calls(scene, j0, j1):
@@ -52,14 +59,40 @@ def run_steps(g, scene, j0, j1):
     run_calls(g, step_calls(scene, j0, j1))
 
 
-def cpu_baseline(scene, budget_s=12.0, max_steps=400):
-    """The FP64 oracle as it stands, single-threaded, on the first substeps of the
-    same workload until about budget_s seconds of CPU time have been spent."""
+def cpu_info():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model
+
+
+def crop(scene, xr, yr):
+    """The particles of `scene` with x in xr and y in yr, as a scene of their own
+    (same grid, parameters and tools)."""
+    X = scene["X"]
+    keep = (X[:, 0] >= xr[0]) & (X[:, 0] <= xr[1]) & (X[:, 1] >= yr[0]) & (X[:, 1] <= yr[1])
+    out = dict(scene, X=np.ascontiguousarray(X[keep]), vol0=scene["vol0"][keep], mass=scene["mass"][keep],
+               E=scene["E"][keep], name=scene["name"] + "-sample")
+    if scene.get("v0") is not None:
+        out["v0"] = scene["v0"][keep]
+    return out
+
+
+def oracle_rate(scene, threads, budget_s, max_steps=400):
+    """(particle-steps/s, substeps) of the FP64 oracle from the first substep of
+    `scene`, until about budget_s seconds have been spent."""
     import oracle
+    oracle.set_threads(threads)
     o = oracle.OracleScene(scene)
     t0 = time.perf_counter()
     steps = 0
-    while steps < max_steps and time.perf_counter() - t0 < budget_s:
+    while steps < max_steps and (steps == 0 or time.perf_counter() - t0 < budget_s):
         tools = scene["tools_at"](steps)
         blades = [t["blade"] for t in tools if t["labels"]]
         if blades:
@@ -67,9 +100,26 @@ def cpu_baseline(scene, budget_s=12.0, max_steps=400):
         o.step([dict(t, contact=int(t["contact"]), cutting=int(t["cutting"])) for t in tools])
         steps += 1
     dt = time.perf_counter() - t0
-    n = scene["X"].shape[0]
-    return {"value": n * steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {steps} substeps of {scene['name']} ({n} particles), FP64 C oracle, 1 thread"}
+    return scene["X"].shape[0] * steps / dt, steps
+
+
+def cpu_baseline(scene, budget_s=10.0, sample=None):
+    """The FP64 oracle as it stands on a bounded sample of the same workload (the
+    whole scene, or the particles of `sample` = (x range, y range)), from its first
+    substep: one thread, then all threads (OpenMP over the loops with independent
+    iterations; the results do not depend on the thread count)."""
+    sc = crop(scene, *sample) if sample else scene
+    n = sc["X"].shape[0]
+    threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+    v1, s1 = oracle_rate(sc, 1, budget_s)
+    va, sa = oracle_rate(sc, threads, budget_s)
+    where = (f"particles of {scene['name']} with x in {list(sample[0])} m and y in {list(sample[1])} m "
+             f"({n} of {scene['X'].shape[0]}; the same grid, parameters and blades)") if sample else \
+        f"{scene['name']} ({n} particles)"
+    return {"value": va, "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {sa} substeps of {where}, FP64 C oracle, {threads} OpenMP threads",
+            "single_thread": {"value": v1, "cores": 1, "substeps": s1},
+            "nproc": os.cpu_count(), "cpu_model": cpu_info()}
 
 
 def kernel_source_hash():
@@ -77,7 +127,8 @@ def kernel_source_hash():
     measured hardware traffic is stored in profiles/traffic.json)."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("tlmpm_common.h", "tlmpm_device.h", "tlmpm_kernels.hip", "tlmpm_contact.hip", "tlmpm_quad.hip"):
+    for f in ("tlmpm_common.h", "tlmpm_device.h", "tlmpm_band.h", "tlmpm_kernels.hip", "tlmpm_contact.hip",
+              "tlmpm_quad.hip"):
         with open(os.path.join(ROOT, "paper_2609_27342_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -97,18 +148,25 @@ def measured_traffic(workload, cls):
     return rec["bytes"] if rec else None
 
 
-def roofline_of(prof, value, n, per_particle_extra=0, workload=None, alg=None):
-    """Roofline of the dominant kernel class from event timings {class: (ms, launches)}."""
-    alg = alg or ALG_BYTES
+def roofline_of(prof, value, n, step_bytes, own=None, workload=None):
+    """Roofline of the dominant kernel (P2G or G2P by summed duration) from event
+    timings {class: (ms, launches)}: achieved = step_bytes (the substep's
+    algorithmic bytes per particle, each persistent field read or written once)
+    times the N particles one launch covers, over the kernel's average launch
+    duration.  `own`: the kernel's own algorithmic bytes per particle, reported
+    beside it."""
+    own = own or ALG_BYTES
     kern = {k: {"ms_avg": (v[0] / v[1]) if v[1] else None, "launches": v[1]} for k, v in prof.items()}
     dom = max(("p2g", "g2p"), key=lambda k: prof[k][0])
     avg_s = prof[dom][0] / prof[dom][1] * 1e-3
-    per_particle = alg[dom] + (per_particle_extra if dom == "p2g" else 0)
-    achieved = per_particle * n / avg_s / 1e9
-    return {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+    achieved = step_bytes * n / avg_s / 1e9
+    own_gbs = {k: own[k] * n / (prof[k][0] / prof[k][1] * 1e-3) / 1e9 for k in ("p2g", "g2p") if prof[k][1]}
+    return {"bound": "hbm", "kernel": "k_" + dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(workload, dom) if workload else None,
-            "alg_bytes_per_launch": per_particle * n,
-            "step_alg_frac": value * ALG_STEP_BYTES / (HBM_PEAK_GBS * 1e9), "kernels": kern}
+            "alg_bytes_per_launch": step_bytes * n, "alg_bytes_per_particle": step_bytes,
+            "own_bytes_per_particle": {k: own[k] for k in own},
+            "own_frac": {k: v / HBM_PEAK_GBS for k, v in own_gbs.items()},
+            "step_alg_frac": value * step_bytes / (HBM_PEAK_GBS * 1e9), "kernels": kern}
 
 
 def batch_calls(scene, j0, j1):
@@ -120,7 +178,7 @@ def batch_calls(scene, j0, j1):
     return [(adv, j1 - j0)] if j1 > j0 else []
 
 
-def bench_batched(args, K, Wm):
+def bench_batched(args, K, Wm, cpu=True):
     """The many-scene workload stepped (a) one scene at a time, each scene's K
     substeps in one call, and (b) as one batch, every launch covering all scenes."""
     import torch
@@ -167,14 +225,12 @@ def bench_batched(args, K, Wm):
 
     run(plan_of(0, Wm))
     per = plan_of(Wm, Wm + K)
+    bt.profile("transfers")  # events around the P2G and G2P launches of the timed region
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     run(per)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
-    P = min(args.profile_steps, K)
-    bt.profile(True)
-    run(plan_of(Wm + K, Wm + K + P))
     prof = bt.profile_read()
     bt.profile(False)
     bt.close()
@@ -182,10 +238,12 @@ def bench_batched(args, K, Wm):
     value = n * K / t_batch
     plain_value = n * K / t_plain
     print(f"[bench] batched: {t_batch * 1e3 / K:.4f} ms/step, status={status}", file=sys.stderr, flush=True)
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(scenes[0])
-        cpu["sample"] = "scene 0 of the batch: " + cpu["sample"]
+    cpu_b = None
+    if cpu and not args.no_cpu_baseline:
+        cpu_b = cpu_baseline(scenes[0])
+        cpu_b["sample"] = "scene 0 of the batch: " + cpu_b["sample"]
+    for g in gs:
+        g.close()
     return {
         "metric": "particle-steps/s per GPU",
         "value": value,
@@ -204,8 +262,8 @@ def bench_batched(args, K, Wm):
                    "plain": {"value": plain_value, "ms_per_step": t_plain * 1e3 / K, "status": status_plain},
                    "batched_over_plain": value / plain_value},
         "status": status,
-        "roofline": roofline_of(prof, value, n, 0, "batched"),
-        "cpu_baseline": cpu,
+        "roofline": roofline_of(prof, value, n, ALG_STEP_BYTES, None, "batched"),
+        "cpu_baseline": cpu_b,
     }
 
 
@@ -260,7 +318,8 @@ def bench_knife(args, K, Wm):
                    "knife_end": [{"x": st["x"].tolist(), "v": st["v"].tolist(), "omega": st["omega"].tolist()}
                                  for st in ends]},
         "status": status,
-        "roofline": roofline_of(prof, value, n, material_extra_bytes(sc["params"]), None),
+        "roofline": roofline_of(prof, value, n, ALG_STEP_BYTES + material_extra_bytes(sc["params"]),
+                                dict(ALG_BYTES, p2g=ALG_BYTES["p2g"] + material_extra_bytes(sc["params"]))),
         "cpu_baseline": None,
     }
 
@@ -323,7 +382,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", default=os.environ.get("TLMPM_BENCH_WORKLOAD", "medium"))
+    ap.add_argument("--workload", default=os.environ.get("TLMPM_BENCH_WORKLOAD", "large"))
+    ap.add_argument("--no-batched", action="store_true", help="large: skip the many-scene run beside it")
+    ap.add_argument("--batched-steps", type=int, default=20, help="large: timed substeps of the many-scene run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=200)
     ap.add_argument("--requests", type=int, default=100, help="served: number of requests")
@@ -376,29 +437,49 @@ def main():
           flush=True)
     run_steps(g, scene, 0, Wm)
     calls = step_calls(scene, Wm, Wm + K)
+    labelled_steps = sum(cnt for tools, cnt in calls if any(t["labels"] for t in tools))
+    # HIP events on the scene's stream around the P2G and G2P launches of the timed
+    # region (the launch arrangement is unchanged)
+    g.profile("transfers")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     run_calls(g, calls)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    prof = g.profile_read()
+    g.profile(False)
     ms_per_step = (t1 - t0) * 1e3 / K
     value = n * K / (t1 - t0)
     status = g.status()
+    tot_slots, max_slots = g.slot_stats()
+    g.close()
     print(f"[bench] timed {K} steps: {ms_per_step:.4f} ms/step, status={status}", file=sys.stderr, flush=True)
-
-    # per-kernel durations from HIP events on the scene's stream, over a following
-    # stretch of the same schedule
-    P = min(args.profile_steps, K)
-    g.profile(True)
-    run_steps(g, scene, Wm + K, Wm + K + P)
-    prof = g.profile_read()
-    g.profile(False)
     quad = scene["params"].get("stencil", 0) == 1
-    roofline = roofline_of(prof, value, n, 4 if scene["E"].min() != scene["E"].max() else 0, args.workload,
-                           ALG_BYTES_QUAD if quad else None)
+    per_E = scene["E"].min() != scene["E"].max()
+    step_bytes = ALG_STEP_BYTES + (4 if per_E else 0)
+    own = dict(ALG_BYTES_QUAD if quad else ALG_BYTES)
+    own["p2g"] += 4 if per_E else 0
+    roofline = roofline_of(prof, value, n, step_bytes, own, args.workload)
+    extra = None
+    if args.workload == "large" and not args.no_batched:
+        # the many-scene workload beside the headline: plain one scene per call
+        # against one batch, the same substeps
+        bk = bench_batched(args, args.batched_steps, 5, cpu=False)
+        extra = {"value": bk["value"], "ms_per_step": bk["ms_per_step"], "steps": bk["steps"],
+                 "warmup": bk["warmup"], "scenes": bk["config"]["scenes"], "particles": bk["config"]["particles"],
+                 "plain": bk["config"]["plain"], "batched_over_plain": bk["config"]["batched_over_plain"],
+                 "status": bk["status"], "roofline": {k: bk["roofline"][k] for k in
+                                                      ("kernel", "achieved", "frac", "step_alg_frac", "kernels")}}
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(scene)
+        cpu = cpu_baseline(scene, sample=LARGE_SAMPLE if args.workload == "large" else None)
+    cfg = {"workload": args.workload, "particles": n, "dt": scene["params"]["dt"],
+           "material_contact": bool(scene["params"]["material_contact"]),
+           "stencil": "quadratic" if quad else "trilinear", "path": "graph" if args.graphs else "plain",
+           "timed_substeps": [Wm, Wm + K], "substeps_with_label_pass": labelled_steps,
+           "slots": {"total": tot_slots, "max_per_node": max_slots}}
+    if extra is not None:
+        cfg["batched"] = extra
     out = {
         "metric": "particle-steps/s per GPU",
         "value": value,
@@ -412,10 +493,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": args.workload, "particles": n, "dt": scene["params"]["dt"],
-                   "material_contact": bool(scene["params"]["material_contact"]),
-                   "stencil": "quadratic" if quad else "trilinear",
-                   "path": "graph" if args.graphs else "plain"},
+        "config": cfg,
         "status": status,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -233,11 +233,14 @@ tlmpm_status tlmpm_contact_stats(tlmpm_scene* scene, double out[6]);
  * is on.  Default: off. */
 tlmpm_status tlmpm_set_graphs(tlmpm_scene* scene, int32_t enable);
 
-/* Kernel timing (diagnostics).  While enabled, every kernel the scene launches is
- * bracketed by HIP events on the scene's stream.  tlmpm_profile_read synchronises
- * and returns, per kernel class (0 P2G, 1 grid update + G2P, 2 labels, 3 slot
- * tables, 4 material contact, 5 other), the summed duration in ms and the launch
- * count, then clears the record.  n_classes: length of both output arrays (<= 6). */
+/* Kernel timing (diagnostics).  enable = 1: every kernel the scene launches is
+ * bracketed by HIP events on the scene's stream (each kernel then has a launch of
+ * its own, on one stream).  enable = 2: only the P2G and G2P launches are
+ * bracketed, the launch arrangement is unchanged (for timing those two inside a
+ * measured run).  0: off.  tlmpm_profile_read synchronises and returns, per kernel
+ * class (0 P2G, 1 grid update + G2P, 2 labels, 3 slot tables, 4 material contact,
+ * 5 other), the summed duration in ms and the launch count, then clears the
+ * record.  n_classes: length of both output arrays (<= 6). */
 tlmpm_status tlmpm_profile_enable(tlmpm_scene* scene, int32_t enable);
 tlmpm_status tlmpm_profile_read(tlmpm_scene* scene, int32_t n_classes, double* ms, int64_t* launches);
 

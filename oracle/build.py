@@ -7,13 +7,11 @@ SRC = os.path.join(HERE, "tlmpm_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
 
-def compile_source(src, out, openmp=False):
-    """gcc the oracle source file `src` into the shared library `out`."""
-    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
-           "-Wall", "-Wno-unused-function"]
-    if openmp:
-        cmd.append("-fopenmp")
-    cmd += ["-o", out + ".tmp", src, "-lm"]
+def compile_source(src, out):
+    """gcc the oracle source file `src` into the shared library `out` (OpenMP on the
+    loops with independent iterations; orc_set_threads picks the thread count)."""
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+           "-Wall", "-Wno-unused-function", "-o", out + ".tmp", src, "-lm"]
     subprocess.check_call(cmd)
     os.replace(out + ".tmp", out)
     return out

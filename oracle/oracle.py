@@ -13,7 +13,7 @@ from .build import LIB, build
 
 __all__ = ["Params", "Blade", "Tool", "OracleScene", "lib", "load", "shape", "neo_hookean_P",
            "neo_hookean_psi", "fcr_P", "fcr_psi", "polar", "visc_P", "vm_project", "conflict", "encode", "digit", "couple", "label_digit",
-           "labels_on"]
+           "labels_on", "set_threads", "get_threads"]
 
 
 class Params(C.Structure):
@@ -114,6 +114,8 @@ def _declare(L):
     L.orc_last_pairs.argtypes = [C.c_void_p]
     L.orc_last_candidates.restype = C.c_long
     L.orc_last_candidates.argtypes = [C.c_void_p]
+    L.orc_set_threads.argtypes = [C.c_int]
+    L.orc_get_threads.restype = C.c_int
     L.orc_grid_dump.restype = C.c_long
     L.orc_grid_dump.argtypes = [C.c_void_p, C.c_long, C.POINTER(C.c_int64), C.POINTER(C.c_uint64),
                                 dp, dp, dp, dp]
@@ -282,6 +284,16 @@ class OracleScene:
         k = self.L.orc_grid_dump(self.h, cap, node.ctypes.data_as(C.POINTER(C.c_int64)),
                                 code.ctypes.data_as(C.POINTER(C.c_uint64)), _dp(m), _dp(vn), _dp(vn1), _dp(vt))
         return {"node": node[:k], "code": code[:k], "m": m[:k], "vn": vn[:k], "vn1": vn1[:k], "vt": vt[:k]}
+
+
+def set_threads(n):
+    """Threads of the oracle's loops with independent iterations (results do not
+    depend on it)."""
+    lib().orc_set_threads(int(n))
+
+
+def get_threads():
+    return lib().orc_get_threads()
 
 
 # --- primitives, for the pins -------------------------------------------------

@@ -20,8 +20,14 @@
  *
  * Parity status of each part is recorded next to its function ("pinned by ..." or
  * "parity unpinned").
+ *
+ * Threads: loops whose iterations are independent (per particle or per node, each
+ * writing only its own entries) may run under OpenMP; every sum over particles
+ * (the scatter into node accumulators, the wrench) stays serial in particle order,
+ * so the result does not depend on the thread count.  orc_set_threads selects it.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -601,6 +607,10 @@ int orc_label_digit(const double* x, const double* v, const orc_blade* B, double
     return (s < 0.0) ? 1 : 2;
 }
 
+/* Threads of the loops with independent iterations (see the file header). */
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int orc_get_threads(void) { return omp_get_max_threads(); }
+
 /* ------------------------------------------------------------------------- */
 /* Scene lifetime.                                                            */
 /* ------------------------------------------------------------------------- */
@@ -721,6 +731,7 @@ long orc_label_pass(long n, const double* x, const double* v, uint8_t* dig, int 
     for (int b = 0; b < nb; b++) {
         const orc_blade* B = &blades[b];
         if (B->cut_index < 0 || B->cut_index >= K) return -1;
+#pragma omp parallel for reduction(+ : changed)
         for (long p = 0; p < n; p++) {
             uint8_t* dg = &dig[(size_t)p * K + B->cut_index];
             int nd = orc_label_digit(&x[3 * p], &v[3 * p], B, dt, *dg);
@@ -795,6 +806,10 @@ static void rigid_contact(orc_scene* s, int body, const orc_tool* T, double* wre
 {
     const orc_params* P = &s->P;
     double dt = P->dt;
+    /* per-particle reactions, summed in particle order after the loop */
+    double* wb = wrench ? (double*)malloc(sizeof(double) * 6 * (s->n + 1)) : NULL;
+    uint8_t* wf = wrench ? (uint8_t*)calloc(s->n + 1, 1) : NULL;
+#pragma omp parallel for
     for (long p = 0; p < s->n; p++) {
         const double* x = &s->x[3 * p];
         const double* v = &s->v[3 * p];
@@ -889,10 +904,18 @@ static void rigid_contact(orc_scene* s, int body, const orc_tool* T, double* wre
             double Fb[3] = {-JpB[0] / dt, -JpB[1] / dt, -JpB[2] / dt}, tq[3];
             cross3(arm, Fb, tq);
             for (int j = 0; j < 3; j++) {
-                wrench[j] += Fb[j];
-                wrench[3 + j] += tq[j];
+                wb[6 * p + j] = Fb[j];
+                wb[6 * p + 3 + j] = tq[j];
             }
+            wf[p] = 1;
         }
+    }
+    if (wrench) {
+        for (long p = 0; p < s->n; p++)
+            if (wf[p])
+                for (int j = 0; j < 6; j++) wrench[j] += wb[6 * p + j];
+        free(wb);
+        free(wf);
     }
 }
 
@@ -942,6 +965,7 @@ void orc_candidates(const orc_scene* s, uint8_t* cand)
     long* fill = (long*)malloc(sizeof(long) * (nc + 1));
     memcpy(fill, start, sizeof(long) * (nc + 1));
     for (long p = 0; p < s->n; p++) list[fill[s->cell_of[p]]++] = p;
+#pragma omp parallel for
     for (long p = 0; p < s->n; p++) {
         int ijk[3];
         cell_ijk(s, s->cell_of[p], ijk);
@@ -1246,8 +1270,12 @@ int orc_step(orc_scene* s, const orc_tool* tools, int nt, double* wrench, int br
     s->n_pool = 0;
     long node[27];
     double w[27], g[81];
+    /* first Piola-Kirchhoff stress of every particle at F^n (independent per particle) */
+    double* Pall = (double*)malloc(sizeof(double) * 9 * (n + 1));
+    int bad_any = 0;
+#pragma omp parallel for reduction(| : bad_any)
     for (long p = 0; p < n; p++) {
-        double Pk[9];
+        double* Pk = &Pall[9 * p];
         int bad;
         if (P->material == 1 && P->yield_stress > 0.0) {
             /* P = P_fcr(F_e) F_p^{-T}, F_e = F F_p^{-1} (reading R32) */
@@ -1264,12 +1292,17 @@ int orc_step(orc_scene* s, const orc_tool* tools, int nt, double* wrench, int br
             bad = P->material == 1 ? orc_fcr_P(s->E[p], P->nu, &s->F[9 * p], Pk)
                                    : orc_neo_hookean_P(s->E[p], P->nu, &s->F[9 * p], Pk);
         }
-        if (bad) s->status = ORC_E_NONFINITE;
+        if (bad) bad_any = 1;
         if (P->viscosity > 0.0) {
             double Pv[9];
-            if (orc_visc_P(P->viscosity, &s->F[9 * p], &s->Fdot[9 * p], Pv)) s->status = ORC_E_NONFINITE;
+            if (orc_visc_P(P->viscosity, &s->F[9 * p], &s->Fdot[9 * p], Pv)) bad_any = 1;
             for (int i = 0; i < 9; i++) Pk[i] += Pv[i];
         }
+    }
+    if (bad_any) s->status = ORC_E_NONFINITE;
+    /* scatter into the node accumulators, serially in particle order */
+    for (long p = 0; p < n; p++) {
+        const double* Pk = &Pall[9 * p];
         orc_shape(P, &s->X[3 * p], node, w, g);
         uint64_t c = code_of(s, p);
         double mp = s->mass[p], V0 = s->vol0[p];
@@ -1287,12 +1320,18 @@ int orc_step(orc_scene* s, const orc_tool* tools, int nt, double* wrench, int br
         }
     }
 
+    free(Pall);
+
     /* 3. compatibility coupling (Eq. 8) */
+#pragma omp parallel for schedule(dynamic, 4096)
     for (long i = 0; i < nn; i++) couple_node(s, i, 0);
 
     /* 4-5. grid update (Eq. 9) and PIC/FLIP G2P (Eq. 17); x moves with v^{n+1} (reading R4) */
     double* vnew = (double*)malloc(sizeof(double) * 3 * (n + 1));
+#pragma omp parallel for
     for (long p = 0; p < n; p++) {
+        long node[27];
+        double w[27], g[81];
         orc_shape(P, &s->X[3 * p], node, w, g);
         uint64_t c = code_of(s, p);
         double acc_v[3] = {0, 0, 0}, acc_x[3] = {0, 0, 0};
@@ -1325,14 +1364,20 @@ int orc_step(orc_scene* s, const orc_tool* tools, int nt, double* wrench, int br
             for (int j = 0; j < 3; j++) e->pt[j] += w[k] * s->mass[p] * s->v[3 * p + j];
         }
     }
+#pragma omp parallel for schedule(dynamic, 4096)
     for (long i = 0; i < nn; i++) couple_node(s, i, 1);
+#pragma omp parallel for
     for (long k = 0; k < s->n_pool; k++) {
         node_entry* e = &s->pool[k];
         for (int j = 0; j < 3; j++) e->vt[j] = e->ptbar[j] / e->m;
     }
 
     /* 7. deformation gradient from the remapped velocities (reading R5) */
+    int bad_F = 0;
+#pragma omp parallel for reduction(| : bad_F)
     for (long p = 0; p < n; p++) {
+        long node[27];
+        double w[27], g[81];
         orc_shape(P, &s->X[3 * p], node, w, g);
         uint64_t c = code_of(s, p);
         double L[9] = {0};
@@ -1355,8 +1400,9 @@ int orc_step(orc_scene* s, const orc_tool* tools, int nt, double* wrench, int br
         double J = det3(F);
         int finite = 1;
         for (int i = 0; i < 9; i++) finite &= isfinite(F[i]);
-        if (!(J > 0.0) || !finite) s->status = ORC_E_NONFINITE;
+        if (!(J > 0.0) || !finite) bad_F = 1;
     }
+    if (bad_F) s->status = ORC_E_NONFINITE;
     (void)K;
     return s->status;
 }

@@ -69,9 +69,12 @@ struct GraphCache {
     }
 };
 
-// Kernel timing (diagnostics): pairs of events around launches, per class.
+// Kernel timing (diagnostics): pairs of events around launches, per class.  on:
+// every launch, each kernel in a launch of its own on the main stream; xfer: only
+// the P2G and G2P launches, the launch arrangement left as it is.
 struct Timing {
     bool on = false;
+    bool xfer = false;
     hipStream_t st = nullptr;
     std::vector<hipEvent_t> pool;
     std::vector<std::pair<int, int>> used; // (class, first event index)
@@ -126,7 +129,7 @@ struct ProfScope {
     int idx = -1;
     ProfScope(Timing* t, int c) : tm(t), cls(c)
     {
-        if (!tm || !tm->on) return;
+        if (!tm || !(tm->on || (tm->xfer && (c == 0 || c == 1)))) return;
         while (tm->pool.size() < tm->next + 2) {
             hipEvent_t e;
             if (hipEventCreate(&e) != hipSuccess) return;
@@ -784,7 +787,8 @@ extern "C" tlmpm_status tlmpm_set_graphs(tlmpm_scene* sc, int32_t enable)
 extern "C" tlmpm_status tlmpm_profile_enable(tlmpm_scene* sc, int32_t enable)
 {
     if (!sc) return fail(TLMPM_E_INVALID, "null scene");
-    sc->prof.on = enable != 0;
+    sc->prof.on = enable == 1;
+    sc->prof.xfer = enable == 2;
     return TLMPM_OK;
 }
 
@@ -1919,7 +1923,8 @@ extern "C" tlmpm_status tlmpm_batch_sync(tlmpm_batch* b)
 extern "C" tlmpm_status tlmpm_batch_profile_enable(tlmpm_batch* b, int32_t enable)
 {
     if (!b) return fail(TLMPM_E_INVALID, "null batch");
-    b->prof.on = enable != 0;
+    b->prof.on = enable == 1;
+    b->prof.xfer = enable == 2;
     return TLMPM_OK;
 }
 

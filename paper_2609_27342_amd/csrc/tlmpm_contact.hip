@@ -86,36 +86,60 @@ DEV void cellmask_body(const SceneK& S, const SceneD& D, int bi, int with_static
 // order, stored over the brick's particle range).  Without `force`, only bricks
 // next to a brick whose codes changed are recomputed.
 // First global candidate index of every active brick (exclusive scan of the
-// candidate counts in active-brick order) by one block; each thread scans a
-// contiguous run of bricks.
+// candidate counts in active-brick order) by one block of TL_SCAN_T threads, in
+// chunks of TL_SCAN_T * TL_SCAN_PER counts: each chunk is loaded coalesced into LDS,
+// every thread scans TL_SCAN_PER consecutive counts there, the thread totals are
+// scanned across the block, and the offsets are stored coalesced.
+#define TL_SCAN_T 1024
+#define TL_SCAN_PER 8
 DEV void scan_offsets(const SceneD& D)
 {
-    __shared__ int s_w[16];
+    constexpr int T = TL_SCAN_T, CH = T * TL_SCAN_PER;
+    __shared__ int s_c[CH];
+    __shared__ int s_w[T / 64];
     const int n = D.n_active;
-    const int T = blockDim.x;
-    const int per = (n + T - 1) / T;
-    const int i0 = threadIdx.x * per, i1 = min(n, i0 + per);
-    int loc = 0;
-#pragma unroll 8
-    for (int i = i0; i < i1; i++) loc += D.bcand[i];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    int incl = loc;
-    for (int o = 1; o < 64; o <<= 1) {
-        int t = __shfl_up(incl, o, 64);
-        if (lane >= o) incl += t;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    int carry = 0;
+    for (int base = 0; base < n; base += CH) {
+#pragma unroll
+        for (int k = 0; k < TL_SCAN_PER; k++) {
+            const int i = base + k * T + t;
+            s_c[k * T + t] = i < n ? D.bcand[i] : 0;
+        }
+        __syncthreads();
+        int loc = 0;
+#pragma unroll
+        for (int k = 0; k < TL_SCAN_PER; k++) loc += s_c[t * TL_SCAN_PER + k];
+        int incl = loc;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int v = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += v;
+        }
+        if (lane == 63) s_w[wv] = incl;
+        __syncthreads();
+        int before = 0, total = 0;
+#pragma unroll
+        for (int w = 0; w < T / 64; w++) {
+            before += w < wv ? s_w[w] : 0;
+            total += s_w[w];
+        }
+        int run = carry + before + incl - loc;
+#pragma unroll
+        for (int k = 0; k < TL_SCAN_PER; k++) {
+            const int c = s_c[t * TL_SCAN_PER + k];
+            s_c[t * TL_SCAN_PER + k] = run;
+            run += c;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < TL_SCAN_PER; k++) {
+            const int i = base + k * T + t;
+            if (i < n) D.coff[i] = s_c[k * T + t];
+        }
+        carry += total;
+        __syncthreads();
     }
-    if (lane == 63) s_w[wv] = incl;
-    __syncthreads();
-    int before = 0;
-    for (int w = 0; w < wv; w++) before += s_w[w];
-    int run = before + incl - loc;
-#pragma unroll 8
-    for (int i = i0; i < i1; i++) {
-        const int c = D.bcand[i];
-        D.coff[i] = run;
-        run += c;
-    }
-    if (threadIdx.x == T - 1) D.coff[n] = run;
+    if (t == 0) D.coff[n] = carry;
 }
 
 // candidate bits and the ordered candidate list of one brick
@@ -191,7 +215,6 @@ DEV void cand_body(const SceneK& S, const SceneD& D, int bi, int force)
 }
 
 // one block of TL_SCAN_T threads per scene
-#define TL_SCAN_T 1024
 DEV void cscan_body(const SceneK& S, const SceneD& D, int bi)
 {
     if (S.material_contact) scan_offsets(D);

@@ -359,7 +359,10 @@ class Scene:
         _check(lib().tlmpm_set_graphs(self.h, int(bool(enable))))
 
     def profile(self, enable=True):
-        _check(lib().tlmpm_profile_enable(self.h, int(bool(enable))))
+        """enable: True / 1 every launch timed (each kernel alone, one stream);
+        "transfers" / 2 only P2G and G2P, the launch arrangement unchanged; False off."""
+        mode = 2 if enable == "transfers" else int(enable)
+        _check(lib().tlmpm_profile_enable(self.h, mode))
 
     def profile_read(self):
         """{class: (total ms, launches)} since the last read (synchronises)."""
@@ -455,7 +458,9 @@ class Batch:
         _check(lib().tlmpm_batch_set_graphs(self.h, int(bool(enable))))
 
     def profile(self, enable=True):
-        _check(lib().tlmpm_batch_profile_enable(self.h, int(bool(enable))))
+        """As Scene.profile."""
+        mode = 2 if enable == "transfers" else int(enable)
+        _check(lib().tlmpm_batch_profile_enable(self.h, mode))
 
     def profile_read(self):
         """{class: (total ms, launches)} since the last read (synchronises)."""

@@ -573,3 +573,30 @@ def test_cutting_work_release_step_count_and_wrench():
             assert np.abs(dv).max() < 1e-12 and np.abs(w).max() < 1e-12
     assert pushed == expect_steps
     assert o.get()["D"][0] == 1.0
+
+
+def test_thread_count_does_not_change_results():
+    """The oracle's loops with independent iterations run under OpenMP; sums over
+    particles stay in particle order, so 1 and 4 threads give bitwise the same
+    state and wrench on a scene with labels, blade, floor and material contact."""
+    s = W.small(deep=True)
+    s["params"] = dict(s["params"], material_contact=1)
+    runs = []
+    for nt in (1, 4):
+        oracle.set_threads(nt)
+        o = oracle.OracleScene(s)
+        ws = []
+        for j in range(4):
+            tools = [dict(t, contact=1, cutting=1) for t in s["tools_at"](j)]
+            o.assign_labels([t["blade"] for t in tools])
+            st, w = o.step(tools)
+            assert st == 0
+            ws.append(w)
+        g = o.get()
+        runs.append((g, np.array(ws), o.last_pairs()))
+    oracle.set_threads(1)
+    (a, wa, pa), (b, wb, pb) = runs
+    for k in ("x", "v", "F", "digits", "D"):
+        assert np.array_equal(a[k], b[k]), k
+    assert np.array_equal(wa, wb) and pa == pb and pa > 0
+    assert np.abs(wa).max() > 0
