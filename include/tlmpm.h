@@ -244,6 +244,43 @@ tlmpm_status tlmpm_set_graphs(tlmpm_scene* scene, int32_t enable);
 tlmpm_status tlmpm_profile_enable(tlmpm_scene* scene, int32_t enable);
 tlmpm_status tlmpm_profile_read(tlmpm_scene* scene, int32_t n_classes, double* ms, int64_t* launches);
 
+/* ---- Surface reconstruction for visualisation (Sec. III-F), outside the substep.
+ * The surface of the scene's current side codes on the 2x2x2 sub-cell lattice of
+ * the reference grid (site spacing dx / 2, site floor((X - origin) / (dx / 2)) per
+ * axis; a site is material when a particle lies in it, the one of smallest index if
+ * several do):
+ *   - a link between face-adjacent material sites is intact unless their side codes
+ *     conflict (the blade sweep cut it); a directed link from a material site to an
+ *     empty site or across a cut is a transition, with Hermite data (link midpoint,
+ *     link direction outward);
+ *   - each cube of 8 sites splits its material corners into local material regions
+ *     (connected components of its intact edges); a region with a transition edge
+ *     has one vertex, placed per axis at the mean coordinate of its transition
+ *     midpoints along that axis (along all of them if none): local dual contouring;
+ *   - one quad per directed transition through the vertices of its site's regions
+ *     in the four cubes around the link, counter-clockwise seen from outside; a cut
+ *     link gives one quad on each side (the two coincident faces of the cut);
+ *   - vertex motion (one-way): fixed trilinear weights over its region's particles.
+ * Vertices are ordered by cube (x fastest) and region (lowest corner); quads by site
+ * (x fastest), axis x, y, z and outward +, -.
+ * Device memory: a caller workspace.  tlmpm_surface_footprint gives the bytes of the
+ * lattice tables (they depend on the grid only); tlmpm_surface_build counts the
+ * vertices and quads in them, returns counts[2] = {vertices, quads} and the bytes
+ * the whole surface needs in *needed, and fills the surface if the workspace holds
+ * that many bytes (else TLMPM_E_NOMEM, counts and *needed still set: call again
+ * with a workspace that large).  Both synchronise. */
+tlmpm_status tlmpm_surface_footprint(tlmpm_scene* scene, size_t* bytes);
+tlmpm_status tlmpm_surface_build(tlmpm_scene* scene, void* workspace, size_t bytes, int64_t counts[2],
+                                 size_t* needed);
+
+/* The built surface in workspace (the last tlmpm_surface_build of this scene):
+ * x [nv][3] current vertex positions (the embedding in the current displacements),
+ * X [nv][3] reference positions, code [nv] ternary side code of the vertex's region
+ * (the union of its particles' digits), quads [nq][4] vertex indices, cut [nq] 1
+ * for a quad on a cut face.  Any output may be NULL.  Synchronises. */
+tlmpm_status tlmpm_surface_read(tlmpm_scene* scene, const void* workspace, size_t bytes, float* x, float* X,
+                                uint64_t* code, int32_t* quads, uint8_t* cut);
+
 /* ---- Batches: many independent scenes advanced by shared launches.
  * The substep is exactly that of tlmpm_step (Sec. III); a batch only groups the
  * kernel launches of its member scenes, so each kernel launch covers the work items

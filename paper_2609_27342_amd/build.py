@@ -6,7 +6,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtlmpm.so")
 SOURCES = [os.path.join(CSRC, "tlmpm_kernels.hip"), os.path.join(CSRC, "tlmpm_contact.hip"),
-           os.path.join(CSRC, "tlmpm_quad.hip"), os.path.join(CSRC, "tlmpm_capi.cpp")]
+           os.path.join(CSRC, "tlmpm_quad.hip"), os.path.join(CSRC, "tlmpm_surface.hip"),
+           os.path.join(CSRC, "tlmpm_capi.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",

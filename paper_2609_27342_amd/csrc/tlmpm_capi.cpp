@@ -38,6 +38,9 @@ hipError_t tl_launch_fill_f32(float*, long long, float, hipStream_t);
 hipError_t tl_launch_fill_i32(int*, long long, int, hipStream_t);
 hipError_t tl_launch_quad(const TlLaunch*, int par, int stage);
 hipError_t tl_static_scratch(int dev, void** ptr);
+hipError_t tl_surface_count(const SceneK*, const SceneD*, const SurfGrid*, const SurfMem*, hipStream_t);
+hipError_t tl_surface_fill(const SceneK*, const SceneD*, const SurfGrid*, const SurfMem*, hipStream_t);
+hipError_t tl_surface_embed(const SceneK*, const SceneD*, const SurfMem*, int nv, hipStream_t);
 }
 
 static thread_local std::string g_err;
@@ -1938,5 +1941,154 @@ extern "C" tlmpm_status tlmpm_batch_set_graphs(tlmpm_batch* b, int32_t enable)
 {
     if (!b) return fail(TLMPM_E_INVALID, "null batch");
     b->graphs.on = enable != 0;
+    return TLMPM_OK;
+}
+
+// ------------------------------------------------------------ surface (Sec. III-F)
+namespace {
+SurfGrid surf_grid(const tlmpm_scene* sc)
+{
+    SurfGrid G;
+    G.sx = 2 * sc->K.cx;
+    G.sy = 2 * sc->K.cy;
+    G.sz = 2 * sc->K.cz;
+    G.S = (long long)G.sx * G.sy * G.sz;
+    G.C = (long long)(G.sx + 1) * (G.sy + 1) * (G.sz + 1);
+    G.ox = sc->K.ox;
+    G.oy = sc->K.oy;
+    G.oz = sc->K.oz;
+    G.h = 0.5 * sc->K.dx;
+    return G;
+}
+
+struct SurfLayout {
+    size_t head, smap, creg, voff, qoff, bsum, vX, vp, vw, vcode, vx, quads, qcut, total;
+};
+
+// the tables of the lattice first (their size depends on the grid only), then the
+// vertex and quad arrays
+SurfLayout surf_layout(const SurfGrid& G, long long nv, long long nq)
+{
+    Layout L;
+    SurfLayout o;
+    o.head = L.take(2 * sizeof(long long));
+    o.smap = L.take((size_t)G.S * 8);
+    o.creg = L.take((size_t)G.C * 4);
+    o.voff = L.take((size_t)(G.C + 1) * 4);
+    o.qoff = L.take((size_t)(G.S + 1) * 4);
+    const long long nb = (std::max(G.C, G.S) + 1023) / 1024;
+    o.bsum = L.take((size_t)(nb + 1) * 4);
+    o.vX = L.take((size_t)nv * 16);
+    o.vp = L.take((size_t)nv * 32);
+    o.vw = L.take((size_t)nv * 32);
+    o.vcode = L.take((size_t)nv * 4);
+    o.vx = L.take((size_t)nv * 16);
+    o.quads = L.take((size_t)nq * 16);
+    o.qcut = L.take((size_t)nq);
+    o.total = L.take(0) + 256;
+    return o;
+}
+
+SurfMem surf_mem(void* ws, const SurfLayout& o)
+{
+    char* b = (char*)ws;
+    SurfMem M;
+    M.smap = (unsigned long long*)(b + o.smap);
+    M.creg = (uint32_t*)(b + o.creg);
+    M.voff = (int*)(b + o.voff);
+    M.qoff = (int*)(b + o.qoff);
+    M.bsum = (int*)(b + o.bsum);
+    M.vX = (float4*)(b + o.vX);
+    M.vp = (int*)(b + o.vp);
+    M.vw = (float*)(b + o.vw);
+    M.vcode = (uint32_t*)(b + o.vcode);
+    M.vx = (float4*)(b + o.vx);
+    M.quads = (int4*)(b + o.quads);
+    M.qcut = (uint8_t*)(b + o.qcut);
+    return M;
+}
+} // namespace
+
+extern "C" tlmpm_status tlmpm_surface_footprint(tlmpm_scene* sc, size_t* bytes)
+{
+    if (!sc || !bytes) return fail(TLMPM_E_INVALID, "bad arguments");
+    *bytes = surf_layout(surf_grid(sc), 0, 0).total;
+    return TLMPM_OK;
+}
+
+extern "C" tlmpm_status tlmpm_surface_build(tlmpm_scene* sc, void* ws, size_t bytes, int64_t counts[2],
+                                            size_t* needed)
+{
+    if (!sc || !counts || !needed) return fail(TLMPM_E_INVALID, "bad arguments");
+    if (tlmpm_status r = refuse_batched(sc)) return r;
+    const SurfGrid G = surf_grid(sc);
+    const SurfLayout base = surf_layout(G, 0, 0);
+    if (G.S >= (1LL << 31) || G.C >= (1LL << 31)) return fail(TLMPM_E_INVALID, "site lattice too large");
+    if (!ws || bytes < base.total) return fail(TLMPM_E_NOMEM, "workspace smaller than tlmpm_surface_footprint()");
+    const SurfMem M0 = surf_mem(ws, base);
+    HIPCHK(tl_surface_count(&sc->K, &sc->D, &G, &M0, sc->st));
+    int nvq[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(&nvq[0], M0.voff + G.C, 4, hipMemcpyDeviceToHost, sc->st));
+    HIPCHK(hipMemcpyAsync(&nvq[1], M0.qoff + G.S, 4, hipMemcpyDeviceToHost, sc->st));
+    HIPCHK(hipStreamSynchronize(sc->st));
+    counts[0] = nvq[0];
+    counts[1] = nvq[1];
+    const SurfLayout full = surf_layout(G, nvq[0], nvq[1]);
+    *needed = full.total;
+    if (bytes < full.total)
+        return fail(TLMPM_E_NOMEM, "the surface needs " + std::to_string(full.total) + " bytes of workspace");
+    const SurfMem M = surf_mem(ws, full);
+    HIPCHK(tl_surface_fill(&sc->K, &sc->D, &G, &M, sc->st));
+    const long long head[2] = {nvq[0], nvq[1]};
+    HIPCHK(hipMemcpyAsync((char*)ws + full.head, head, sizeof(head), hipMemcpyHostToDevice, sc->st));
+    HIPCHK(hipStreamSynchronize(sc->st));
+    return TLMPM_OK;
+}
+
+extern "C" tlmpm_status tlmpm_surface_read(tlmpm_scene* sc, const void* ws, size_t bytes, float* x, float* X,
+                                           uint64_t* code, int32_t* quads, uint8_t* cut)
+{
+    if (!sc || !ws) return fail(TLMPM_E_INVALID, "bad arguments");
+    if (tlmpm_status r = refuse_batched(sc)) return r;
+    const SurfGrid G = surf_grid(sc);
+    long long head[2] = {0, 0};
+    if (bytes < surf_layout(G, 0, 0).total) return fail(TLMPM_E_NOMEM, "workspace smaller than the surface's");
+    HIPCHK(hipMemcpyAsync(head, ws, sizeof(head), hipMemcpyDeviceToHost, sc->st));
+    HIPCHK(hipStreamSynchronize(sc->st));
+    const long long nv = head[0], nq = head[1];
+    const SurfLayout o = surf_layout(G, nv, nq);
+    if (nv < 0 || nq < 0 || bytes < o.total) return fail(TLMPM_E_INVALID, "workspace does not hold a built surface");
+    const SurfMem M = surf_mem(const_cast<void*>(ws), o);
+    if (x) HIPCHK(tl_surface_embed(&sc->K, &sc->D, &M, (int)nv, sc->st));
+    std::vector<float4> f4;
+    if (x || X) f4.resize((size_t)nv);
+    auto copy4 = [&](const float4* src, float* dst) -> tlmpm_status {
+        if (nv) HIPCHK(hipMemcpyAsync(f4.data(), src, (size_t)nv * 16, hipMemcpyDeviceToHost, sc->st));
+        HIPCHK(hipStreamSynchronize(sc->st));
+        for (long long i = 0; i < nv; i++) {
+            dst[3 * i] = f4[i].x;
+            dst[3 * i + 1] = f4[i].y;
+            dst[3 * i + 2] = f4[i].z;
+        }
+        return TLMPM_OK;
+    };
+    if (x)
+        if (tlmpm_status r = copy4(M.vx, x)) return r;
+    if (X)
+        if (tlmpm_status r = copy4(M.vX, X)) return r;
+    if (code) {
+        std::vector<uint32_t> c((size_t)nv);
+        if (nv) HIPCHK(hipMemcpyAsync(c.data(), M.vcode, (size_t)nv * 4, hipMemcpyDeviceToHost, sc->st));
+        HIPCHK(hipStreamSynchronize(sc->st));
+        for (long long i = 0; i < nv; i++) code[i] = code_to_ternary(c[i], sc->max_cuts);
+    }
+    if (quads) {
+        if (nq) HIPCHK(hipMemcpyAsync(quads, M.quads, (size_t)nq * 16, hipMemcpyDeviceToHost, sc->st));
+        HIPCHK(hipStreamSynchronize(sc->st));
+    }
+    if (cut) {
+        if (nq) HIPCHK(hipMemcpyAsync(cut, M.qcut, (size_t)nq, hipMemcpyDeviceToHost, sc->st));
+        HIPCHK(hipStreamSynchronize(sc->st));
+    }
     return TLMPM_OK;
 }

@@ -184,6 +184,30 @@ struct SceneD {
     int* qmap;          // [rounds][512] particle of thread h * 64 + l: cell slot l, half pattern h (-1: none)
 };
 
+// Surface reconstruction (tlmpm_surface.hip): the site lattice of one scene and
+// the arrays of a surface workspace
+struct SurfGrid {
+    int sx, sy, sz;       // sites per axis (2 x cells)
+    long long S, C;       // sites, cubes ((sx + 1)(sy + 1)(sz + 1), min corner -1 .. s - 1)
+    double ox, oy, oz, h; // origin, site spacing
+};
+
+struct SurfMem {
+    unsigned long long* smap;
+    uint32_t* creg;
+    int* voff; // [C + 1]: counts, then exclusive offsets
+    int* qoff; // [S + 1]
+    int* bsum; // scan block sums
+    float4* vX;
+    int* vp;     // [nv][8]
+    float* vw;   // [nv][8]
+    uint32_t* vcode;
+    float4* vx;
+    int4* quads;
+    uint8_t* qcut;
+};
+
+
 // Workgroups are dealt to the 8 XCDs (each with its own L2) round-robin by
 // dispatch index.  xcd_order(b, G) maps dispatch index b of G to a work index such
 // that the workgroups of one XCD take one contiguous range of work items, so

@@ -88,6 +88,9 @@ def lib():
         L.tlmpm_profile_read.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.tlmpm_batch_footprint.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(C.c_size_t)]
         L.tlmpm_batch_scene_bytes.argtypes = [C.POINTER(SceneDesc), C.POINTER(C.c_size_t)]
+        L.tlmpm_surface_footprint.argtypes = [vp, C.POINTER(C.c_size_t)]
+        L.tlmpm_surface_build.argtypes = [vp, vp, C.c_size_t, C.POINTER(C.c_int64), C.POINTER(C.c_size_t)]
+        L.tlmpm_surface_read.argtypes = [vp, vp, C.c_size_t, vp, vp, vp, vp, vp]
         L.tlmpm_batch_create.argtypes = [C.POINTER(vp), C.c_int32, vp, C.c_size_t, vp, C.POINTER(vp)]
         L.tlmpm_batch_create_static.argtypes = [C.POINTER(vp), C.c_int32, vp, C.POINTER(vp)]
         L.tlmpm_batch_destroy.argtypes = [vp]
@@ -101,6 +104,7 @@ def lib():
         for f in ("tlmpm_scene_footprint", "tlmpm_create_scene", "tlmpm_destroy_scene", "tlmpm_assign_labels",
                   "tlmpm_step", "tlmpm_read_state", "tlmpm_write_state", "tlmpm_get_status", "tlmpm_slot_stats", "tlmpm_contact_stats", "tlmpm_rigid_step", "tlmpm_rigid_tool",
                   "tlmpm_profile_enable", "tlmpm_profile_read", "tlmpm_batch_footprint", "tlmpm_batch_scene_bytes",
+                  "tlmpm_surface_footprint", "tlmpm_surface_build", "tlmpm_surface_read",
                   "tlmpm_batch_create", "tlmpm_batch_create_static",
                   "tlmpm_batch_destroy", "tlmpm_batch_step", "tlmpm_batch_sync", "tlmpm_batch_profile_enable",
                   "tlmpm_batch_profile_read", "tlmpm_set_graphs", "tlmpm_batch_set_graphs"):
@@ -370,6 +374,31 @@ class Scene:
         cnt = (C.c_int64 * 6)()
         _check(lib().tlmpm_profile_read(self.h, 6, ms, cnt))
         return {k: (ms[i], cnt[i]) for i, k in enumerate(self.KERNEL_CLASSES)}
+
+    def surface(self):
+        """The surface of the current side codes (tlmpm_surface_*): dict of x [nv,3]
+        current and X [nv,3] reference vertex positions, code [nv], quads [nq,4] and
+        cut [nq] (bool)."""
+        import torch
+        L = lib()
+        nb = C.c_size_t()
+        _check(L.tlmpm_surface_footprint(self.h, C.byref(nb)))
+        ws = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+        counts = (C.c_int64 * 2)()
+        need = C.c_size_t()
+        r = L.tlmpm_surface_build(self.h, C.c_void_p(ws.data_ptr()), nb.value, counts, C.byref(need))
+        if r == E_NOMEM and need.value > nb.value:
+            ws = torch.empty(need.value, dtype=torch.uint8, device="cuda")
+            r = L.tlmpm_surface_build(self.h, C.c_void_p(ws.data_ptr()), need.value, counts, C.byref(need))
+        _check(r)
+        nv, nq = counts[0], counts[1]
+        out = {"x": np.zeros((nv, 3), np.float32), "X": np.zeros((nv, 3), np.float32),
+               "code": np.zeros(nv, np.uint64), "quads": np.zeros((nq, 4), np.int32), "cut": np.zeros(nq, np.uint8)}
+        _check(L.tlmpm_surface_read(self.h, C.c_void_p(ws.data_ptr()), ws.numel(), out["x"].ctypes.data,
+                                    out["X"].ctypes.data, out["code"].ctypes.data, out["quads"].ctypes.data,
+                                    out["cut"].ctypes.data))
+        out["cut"] = out["cut"].astype(bool)
+        return out
 
     def slot_stats(self):
         tot = C.c_int64()
