@@ -336,23 +336,101 @@ def material_extra_bytes(params):
     return extra
 
 
-def bench_served(args):
-    """Continuous batching of arriving rollouts (Poisson arrivals, HBM-budget
-    admission); latency from arrival to result."""
+def served_roofline(kernel_time, value):
+    """Roofline of the served loop's dominant kernel over every batch it ran:
+    achieved = substep algorithmic bytes x (particles x launches) summed over the
+    batches, over the summed launch durations (HIP events, mode 2)."""
+    if not kernel_time:
+        return None
+    dom = max(("p2g", "g2p"), key=lambda k: kernel_time.get(k, [0.0])[0])
+    ms, launches, pl = kernel_time[dom]
+    achieved = ALG_STEP_BYTES * pl / (ms * 1e-3) / 1e9
+    own = {k: ALG_BYTES[k] * kernel_time[k][2] / (kernel_time[k][0] * 1e-3) / 1e9 / HBM_PEAK_GBS
+           for k in ("p2g", "g2p") if k in kernel_time and kernel_time[k][0] > 0}
+    return {"bound": "hbm", "kernel": "k_" + dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "alg_bytes_per_launch": ALG_STEP_BYTES * pl / max(1, launches), "alg_bytes_per_particle": ALG_STEP_BYTES,
+            "own_frac": own, "step_alg_frac": value * ALG_STEP_BYTES / (HBM_PEAK_GBS * 1e9),
+            "kernels": {k: {"ms_avg": v[0] / v[1] if v[1] else None, "launches": v[1]} for k, v in kernel_time.items()}}
+
+
+def served_run(args, reqs, log=None, realtime=True):
+    """One served run of `reqs` (warm kernels and allocator first); returns
+    (server, stats) with P2G/G2P launch timings collected."""
     import torch
     from paper_2609_27342_amd import serve, workloads as W
-    torch.cuda.set_device(0)
-    reqs = W.served(seed=5, n_requests=args.requests, rate=args.rate, tick=args.tick)
     build = lambda r: W.served_request(r["seed"], r["index"], r["n_target"], r["horizon"], r["tick"])
-    # warm the kernels and the allocator on one small request
     warm = W.served(seed=6, n_requests=1, n_range=(20000, 20000), horizon_s=(0.02, 0.02), tick=args.tick)
     serve.Server(build, args.budget_gb * 1e9, tick=args.tick).run(warm, realtime=False)
     torch.cuda.synchronize()
-    log = lambda m: print(m, file=sys.stderr, flush=True)
-    srv = serve.Server(build, args.budget_gb * 1e9, tick=args.tick)
-    st = srv.run(reqs, realtime=True, log=log if args.verbose else None)
-    status = max(r["status"] for r in srv.results.values())
-    mean_work = np.mean([r["n"] * r["steps"] for r in srv.results.values()])
+    srv = serve.Server(build, args.budget_gb * 1e9, tick=args.tick, profile=True)
+    st = srv.run(reqs, realtime=realtime, log=log)
+    return srv, st
+
+
+def served_summary(srv, st, reqs, rate):
+    """The served figures of one run: latency from arrival to result (p50, p99),
+    queueing before admission, throughput, batch sizes, admission."""
+    from paper_2609_27342_amd import tlmpm
+    res = [srv.results[r["index"]] for r in reqs]
+    done = [r for r in res if r["status"] != tlmpm.E_NOMEM]
+    wait = np.array([r["admitted"] - r["arrival"] for r in done]) if done else np.zeros(0)
+    lat = np.array([r["done"] - r["arrival"] for r in done]) if done else np.zeros(0)
+    work = np.array([r["n"] * r["steps"] for r in res], np.float64)
+    return {"requests": len(reqs), "completed": st["requests"], "refused": st["refused"],
+            "rate_per_s": rate, "arrival_span_s": reqs[-1]["arrival"] if reqs else 0.0,
+            "latency_s": {"p50": st["p50_s"], "p99": st["p99_s"], "mean": float(lat.mean()) if len(lat) else None,
+                          "max": float(lat.max()) if len(lat) else None},
+            "queue_wait_s": {"p50": float(np.percentile(wait, 50)) if len(wait) else None,
+                             "p99": float(np.percentile(wait, 99)) if len(wait) else None},
+            "throughput": st["throughput"], "wall_s": st["wall_s"], "iterations": st["iterations"],
+            "mean_batch": st["mean_batch"], "peak_bytes": int(st["peak_bytes"]),
+            "particles": {"mean": float(np.mean([r["n"] for r in res])), "max": int(max(r["n"] for r in res))},
+            "horizon_substeps": {"mean": float(np.mean([r["steps"] for r in res])),
+                                 "min": int(min(r["steps"] for r in res)), "max": int(max(r["steps"] for r in res))},
+            "capacity_requests_per_s": st["throughput"] / float(work.mean()),
+            "status": max((r["status"] for r in done), default=0)}
+
+
+def bench_served(args):
+    """Continuous batching of arriving rollouts (Poisson arrivals, log-uniform
+    particle counts, horizons U[0.5, 2] s, HBM-budget admission); latency from
+    arrival to result.  --capacity-frac F first measures the capacity (requests/s)
+    with the first --capacity-requests requests all queued at once, then serves
+    --requests arrivals at F times that rate."""
+    import torch
+    from paper_2609_27342_amd import workloads as W
+    torch.cuda.set_device(0)
+    log = (lambda m: print(m, file=sys.stderr, flush=True)) if args.verbose else None
+    rate = args.rate
+    capacity = None
+    if args.capacity_frac:
+        probe = W.served(seed=args.served_seed, n_requests=args.capacity_requests, rate=args.rate, tick=args.tick)
+        srv, st = served_run(args, probe, log, realtime=False)
+        capacity = served_summary(srv, st, probe, None)
+        rate = args.capacity_frac * capacity["capacity_requests_per_s"]
+        print(f"[bench] capacity {capacity['capacity_requests_per_s']:.3f} requests/s from {len(probe)} queued "
+              f"requests; serving at {rate:.3f}/s", file=sys.stderr, flush=True)
+    reqs = W.served(seed=args.served_seed + (1 if args.capacity_frac else 0), n_requests=args.requests, rate=rate,
+                    tick=args.tick)
+    print(f"[bench] served: {len(reqs)} requests at {rate:.3f}/s, tick {args.tick}", file=sys.stderr, flush=True)
+    srv, st = served_run(args, reqs, log)
+    sm = served_summary(srv, st, reqs, rate)
+    print(f"[bench] served: p50 {sm['latency_s']['p50']:.2f} s p99 {sm['latency_s']['p99']:.2f} s "
+          f"throughput {sm['throughput']:.3e} wall {sm['wall_s']:.1f} s", file=sys.stderr, flush=True)
+    cpu = None
+    if not args.no_cpu_baseline:
+        r0 = reqs[0]
+        sd = W.served_request(r0["seed"], r0["index"], r0["n_target"], r0["horizon"], r0["tick"])
+        cpu = cpu_baseline(sd)
+        cpu["sample"] = "request 0 of the stream: " + cpu["sample"]
+    cfg = {"workload": "served", "tick": args.tick, "budget_gb": args.budget_gb, "path": "served",
+           "horizon_s": [0.5, 2.0], "n_range": [10000, 1000000]}
+    cfg.update(sm)
+    if capacity is not None:
+        cfg["capacity_probe"] = {k: capacity[k] for k in ("requests", "throughput", "wall_s", "mean_batch",
+                                                           "capacity_requests_per_s")}
+        cfg["capacity_frac"] = args.capacity_frac
     return {
         "metric": "particle-steps/s per GPU",
         "value": st["throughput"],
@@ -366,15 +444,59 @@ def bench_served(args):
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "served", "requests": st["requests"], "rate_per_s": args.rate, "tick": args.tick,
-                   "budget_gb": args.budget_gb, "path": "served",
-                   "latency_s": {"p50": st["p50_s"], "p99": st["p99_s"]},
-                   "mean_batch": st["mean_batch"], "wall_s": st["wall_s"],
-                   "capacity_requests_per_s": st["throughput"] / mean_work},
-        "status": status,
-        "roofline": None,
-        "cpu_baseline": None,
+        "config": cfg,
+        "status": sm["status"],
+        "roofline": served_roofline(srv.kernel_time, st["throughput"]),
+        "cpu_baseline": cpu,
     }
+
+
+def bench_scene(args, name, scene, K, Wm):
+    """One scene stepped K substeps after Wm untimed ones; returns (figures,
+    event timings of the P2G and G2P launches in the timed region)."""
+    import torch
+    from paper_2609_27342_amd import tlmpm
+    n = scene["X"].shape[0]
+    g = tlmpm.Scene(scene)
+    g.graphs(args.graphs)
+    print(f"[bench] workload={name} n={n} warmup={Wm} steps={K} graphs={args.graphs}", file=sys.stderr, flush=True)
+    run_steps(g, scene, 0, Wm)
+    calls = step_calls(scene, Wm, Wm + K)
+    labelled_steps = sum(cnt for tools, cnt in calls if any(t["labels"] for t in tools))
+    # HIP events on the scene's stream around the P2G and G2P launches of the timed
+    # region (the launch arrangement is unchanged)
+    g.profile("transfers")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run_calls(g, calls)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = g.profile_read()
+    g.profile(False)
+    status = g.status()
+    tot_slots, max_slots = g.slot_stats()
+    g.close()
+    print(f"[bench] {name}: {(t1 - t0) * 1e3 / K:.4f} ms/step, status={status}", file=sys.stderr, flush=True)
+    quad = scene["params"].get("stencil", 0) == 1
+    per_E = scene["E"].min() != scene["E"].max()
+    step_bytes = ALG_STEP_BYTES + (4 if per_E else 0)
+    own = dict(ALG_BYTES_QUAD if quad else ALG_BYTES)
+    own["p2g"] += 4 if per_E else 0
+    value = n * K / (t1 - t0)
+    fig = {"value": value, "ms_per_step": (t1 - t0) * 1e3 / K, "status": status, "particles": n,
+           "timed_substeps": [Wm, Wm + K], "substeps_with_label_pass": labelled_steps,
+           "slots": {"total": tot_slots, "max_per_node": max_slots},
+           "stencil": "quadratic" if quad else "trilinear",
+           "roofline": roofline_of(prof, value, n, step_bytes, own, name)}
+    return fig
+
+
+def bench_scenes(args, W):
+    """The scene for --workload: medium starts with the first blade inside the tube
+    (z = 0.034 m), so every timed substep cuts."""
+    if args.workload == "medium":
+        return W.medium(z_start=0.034)
+    return W.CONFIGS[args.workload]()
 
 
 def main():
@@ -387,7 +509,15 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=20, help="large: timed substeps of the many-scene run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=200)
-    ap.add_argument("--requests", type=int, default=100, help="served: number of requests")
+    ap.add_argument("--requests", type=int, default=500, help="served: number of requests")
+    ap.add_argument("--served-seed", type=int, default=5, help="served: seed of the arrival stream")
+    ap.add_argument("--capacity-frac", type=float, default=0.0,
+                    help="served: serve at this fraction of the capacity measured first (0: at --rate)")
+    ap.add_argument("--capacity-requests", type=int, default=24, help="served: requests of the capacity probe")
+    ap.add_argument("--served-requests", type=int, default=40,
+                    help="large: requests of the served stream run beside the headline (0: none)")
+    ap.add_argument("--no-others", dest="others", action="store_false",
+                    help="large: skip the small and medium scenes beside the headline")
     ap.add_argument("--rate", type=float, default=40.0, help="served: Poisson arrival rate per second")
     ap.add_argument("--tick", type=int, default=100, help="served: substeps per batched iteration")
     ap.add_argument("--budget-gb", type=float, default=200.0, help="served: device bytes for running rollouts")
@@ -428,74 +558,62 @@ def main():
     if args.workload in ("knife", "thrown-knives"):
         print(json.dumps(bench_knife(args, K, Wm)))
         return
-    scene = W.CONFIGS[args.workload]()
+    scene = bench_scenes(args, W)
     n = scene["X"].shape[0]
     torch.cuda.set_device(0)
-    g = tlmpm.Scene(scene)
-    g.graphs(args.graphs)
-    print(f"[bench] workload={args.workload} n={n} warmup={Wm} steps={K} graphs={args.graphs}", file=sys.stderr,
-          flush=True)
-    run_steps(g, scene, 0, Wm)
-    calls = step_calls(scene, Wm, Wm + K)
-    labelled_steps = sum(cnt for tools, cnt in calls if any(t["labels"] for t in tools))
-    # HIP events on the scene's stream around the P2G and G2P launches of the timed
-    # region (the launch arrangement is unchanged)
-    g.profile("transfers")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    run_calls(g, calls)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = g.profile_read()
-    g.profile(False)
-    ms_per_step = (t1 - t0) * 1e3 / K
-    value = n * K / (t1 - t0)
-    status = g.status()
-    tot_slots, max_slots = g.slot_stats()
-    g.close()
-    print(f"[bench] timed {K} steps: {ms_per_step:.4f} ms/step, status={status}", file=sys.stderr, flush=True)
-    quad = scene["params"].get("stencil", 0) == 1
-    per_E = scene["E"].min() != scene["E"].max()
-    step_bytes = ALG_STEP_BYTES + (4 if per_E else 0)
-    own = dict(ALG_BYTES_QUAD if quad else ALG_BYTES)
-    own["p2g"] += 4 if per_E else 0
-    roofline = roofline_of(prof, value, n, step_bytes, own, args.workload)
-    extra = None
+    fig = bench_scene(args, args.workload, scene, K, Wm)
+    extra = {}
     if args.workload == "large" and not args.no_batched:
         # the many-scene workload beside the headline: plain one scene per call
         # against one batch, the same substeps
         bk = bench_batched(args, args.batched_steps, 5, cpu=False)
-        extra = {"value": bk["value"], "ms_per_step": bk["ms_per_step"], "steps": bk["steps"],
-                 "warmup": bk["warmup"], "scenes": bk["config"]["scenes"], "particles": bk["config"]["particles"],
-                 "plain": bk["config"]["plain"], "batched_over_plain": bk["config"]["batched_over_plain"],
-                 "status": bk["status"], "roofline": {k: bk["roofline"][k] for k in
-                                                      ("kernel", "achieved", "frac", "step_alg_frac", "kernels")}}
+        extra["batched"] = {
+            "value": bk["value"], "ms_per_step": bk["ms_per_step"], "steps": bk["steps"], "warmup": bk["warmup"],
+            "scenes": bk["config"]["scenes"], "particles": bk["config"]["particles"], "plain": bk["config"]["plain"],
+            "batched_over_plain": bk["config"]["batched_over_plain"], "status": bk["status"],
+            "roofline": {k: bk["roofline"][k] for k in ("kernel", "achieved", "frac", "step_alg_frac", "kernels")}}
+    if args.workload == "large" and args.served_requests:
+        # the first requests of the served stream (40/s, horizons U[0.5, 2] s)
+        reqs = W.served(seed=args.served_seed, n_requests=args.served_requests, rate=args.rate, tick=args.tick)
+        srv, st = served_run(args, reqs)
+        sm = served_summary(srv, st, reqs, args.rate)
+        sm["roofline"] = served_roofline(srv.kernel_time, st["throughput"])
+        print(f"[bench] served sample: p50 {sm['latency_s']['p50']:.2f} s p99 {sm['latency_s']['p99']:.2f} s "
+              f"throughput {sm['throughput']:.3e}", file=sys.stderr, flush=True)
+        extra["served"] = sm
+    if args.workload == "large" and args.others:
+        # the smaller scene families of the same path, each timed inside its cut
+        extra["others"] = {}
+        for nm, sc, k, w in (("small", W.small(), 100, 10), ("medium", W.medium(z_start=0.034), 1000, 100)):
+            f = bench_scene(args, nm, sc, k, w)
+            f["roofline"] = {kk: f["roofline"][kk] for kk in ("kernel", "achieved", "frac", "step_alg_frac",
+                                                                "kernels")}
+            extra["others"][nm] = f
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(scene, sample=LARGE_SAMPLE if args.workload == "large" else None)
     cfg = {"workload": args.workload, "particles": n, "dt": scene["params"]["dt"],
            "material_contact": bool(scene["params"]["material_contact"]),
-           "stencil": "quadratic" if quad else "trilinear", "path": "graph" if args.graphs else "plain",
-           "timed_substeps": [Wm, Wm + K], "substeps_with_label_pass": labelled_steps,
-           "slots": {"total": tot_slots, "max_per_node": max_slots}}
-    if extra is not None:
-        cfg["batched"] = extra
+           "stencil": fig["stencil"], "path": "graph" if args.graphs else "plain",
+           "timed_substeps": fig["timed_substeps"], "substeps_with_label_pass": fig["substeps_with_label_pass"],
+           "slots": fig["slots"]}
+    cfg.update(extra)
     out = {
         "metric": "particle-steps/s per GPU",
-        "value": value,
+        "value": fig["value"],
         "unit": "particle-steps/s",
         "n_gpus": 1,
         "steps": K,
         "warmup": Wm,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": fig["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
         "config": cfg,
-        "status": status,
-        "roofline": roofline,
+        "status": fig["status"],
+        "roofline": fig["roofline"],
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -72,7 +72,11 @@ class Server:
     """budget_bytes: device bytes that running rollouts may hold; tick: substeps
     per iteration; build(req) -> scene dict of a request."""
 
-    def __init__(self, build, budget_bytes, tick=100, max_batch=256, read_fields=("u", "D", "digits")):
+    def __init__(self, build, budget_bytes, tick=100, max_batch=256, read_fields=("u", "D", "digits"),
+                 profile=False):
+        """profile: time the P2G and G2P launches of every batch with HIP events
+        (tlmpm_profile_enable mode 2, the launch arrangement unchanged); the sums are
+        in self.kernel_time {class: [ms, launches, particles x launches]}."""
         import torch
         self.torch = torch
         self.build = build
@@ -83,6 +87,17 @@ class Server:
         self.stream = torch.cuda.current_stream()
         self.create_stream = torch.cuda.Stream()
         self.results = {}
+        self.profile = bool(profile)
+        self.kernel_time = {}
+
+    def _close_batch(self, batch, n_particles):
+        if self.profile:
+            for k, (ms, cnt) in batch.profile_read().items():
+                acc = self.kernel_time.setdefault(k, [0.0, 0, 0])
+                acc[0] += ms
+                acc[1] += cnt
+                acc[2] += cnt * n_particles
+        batch.close()
 
     def _admit(self, queue, active, adm, now_fn):
         """Builds scenes for queued requests (FIFO) while they fit; refuses those
@@ -124,10 +139,12 @@ class Server:
         adm = Admission(self.budget)
         self.peak_bytes = 0
         batch = None
+        batch_n = 0
         lat = {}
         work = 0
         iters = 0
         sizes = []
+        last_log = 0.0
         while pending or queue or active:
             tnow = now()
             while pending and (not realtime or pending[0]["arrival"] <= tnow):
@@ -151,10 +168,15 @@ class Server:
                 for ro in active:
                     ro.done_steps += self.tick
                     work += ro.n * self.tick
+                if log and now() - last_log > 15.0:
+                    last_log = now()
+                    log(f"[serve] t={last_log:.1f}s iteration {iters} running={len(active)} "
+                        f"particles={sum(ro.n for ro in active)} queued={len(queue)} done={len(lat)} "
+                        f"bytes={adm.used}")
             finished = [ro for ro in active if ro.done_steps >= ro.horizon]
             if finished or new:
                 if batch is not None:
-                    batch.close()
+                    self._close_batch(batch, batch_n)
                     batch = None
                 for ro in finished:
                     out = ro.scene.read(self.read_fields)
@@ -172,6 +194,9 @@ class Server:
                 if active:
                     self.create_stream.synchronize()
                     batch = tlmpm.Batch([ro.scene for ro in active], stream=self.stream)
+                    batch_n = sum(ro.n for ro in active)
+                    if self.profile:
+                        batch.profile("transfers")
                     # the batch workspace is within the bytes reserved at admission
                     assert adm.used >= sum(ro.scene.bytes for ro in active) + batch.bytes
         wall = now()

@@ -352,7 +352,7 @@ def served_request(seed, index, n_target, horizon_steps, tick, dx=0.0025, dt=1e-
     return sc
 
 
-def served(seed=5, n_requests=200, rate=40.0, n_range=(10000, 1000000), horizon_s=(0.05, 0.2), tick=100,
+def served(seed=5, n_requests=500, rate=40.0, n_range=(10000, 1000000), horizon_s=(0.5, 2.0), tick=100,
            dt=1e-4):
     """Arrivals of the served workload: Poisson at `rate` per second; per request a
     log-uniform particle count in n_range and a horizon U[horizon_s] seconds
