@@ -187,6 +187,7 @@ def bench_batched(args, K, Wm, cpu=True):
     scenes = B["scenes"]
     n = sum(s["X"].shape[0] for s in scenes)
     torch.cuda.set_device(0)
+    tuning = tuned(args, "batched", scenes, True) if args.tune else None
     print(f"[bench] workload=batched scenes={len(scenes)} n={n} warmup={Wm} steps={K}", file=sys.stderr, flush=True)
 
     def fresh():
@@ -235,6 +236,9 @@ def bench_batched(args, K, Wm, cpu=True):
     bt.profile(False)
     bt.close()
     status = max(g.status() for g in gs)
+    contact = contact_of(gs)
+    if tuning is not None:
+        tlmpm.set_tuning(None)
     value = n * K / t_batch
     plain_value = n * K / t_plain
     print(f"[bench] batched: {t_batch * 1e3 / K:.4f} ms/step, status={status}", file=sys.stderr, flush=True)
@@ -260,7 +264,7 @@ def bench_batched(args, K, Wm, cpu=True):
         "config": {"workload": "batched", "scenes": len(scenes), "particles": n, "dt": scenes[0]["params"]["dt"],
                    "material_contact": True, "path": "batched+graph" if args.graphs else "batched",
                    "plain": {"value": plain_value, "ms_per_step": t_plain * 1e3 / K, "status": status_plain},
-                   "batched_over_plain": value / plain_value},
+                   "batched_over_plain": value / plain_value, "tuning": tuning, "contact": contact},
         "status": status,
         "roofline": roofline_of(prof, value, n, ALG_STEP_BYTES, None, "batched"),
         "cpu_baseline": cpu_b,
@@ -389,7 +393,10 @@ def served_summary(srv, st, reqs, rate):
             "horizon_substeps": {"mean": float(np.mean([r["steps"] for r in res])),
                                  "min": int(min(r["steps"] for r in res)), "max": int(max(r["steps"] for r in res))},
             "capacity_requests_per_s": st["throughput"] / float(work.mean()),
-            "status": max((r["status"] for r in done), default=0)}
+            "status": max((r["status"] for r in done), default=0),
+            "failed": [{"index": q["index"], "status": r["status"], "detail": r.get("detail", ""), "n": r["n"],
+                        "steps": r["steps"]} for q, r in zip(reqs, res)
+                       if r["status"] not in (0, tlmpm.E_NOMEM)]}
 
 
 def bench_served(args):
@@ -451,6 +458,16 @@ def bench_served(args):
     }
 
 
+def contact_of(gs):
+    """Material-contact search of the last substep summed over scenes: candidates,
+    pairs in contact and the pair search's algorithmic bytes (40 B per candidate:
+    its record and bucket reads; 24 B per pair: the partner's state)."""
+    c = [g.contact_stats() for g in gs]
+    cand = sum(x["candidates"] for x in c)
+    pairs = sum(x["pairs"] for x in c)
+    return {"candidates": cand, "pairs": pairs, "pair_search_alg_bytes": 40 * cand + 24 * pairs}
+
+
 def bench_scene(args, name, scene, K, Wm):
     """One scene stepped K substeps after Wm untimed ones; returns (figures,
     event timings of the P2G and G2P launches in the timed region)."""
@@ -475,6 +492,7 @@ def bench_scene(args, name, scene, K, Wm):
     g.profile(False)
     status = g.status()
     tot_slots, max_slots = g.slot_stats()
+    contact = contact_of([g])
     g.close()
     print(f"[bench] {name}: {(t1 - t0) * 1e3 / K:.4f} ms/step, status={status}", file=sys.stderr, flush=True)
     quad = scene["params"].get("stencil", 0) == 1
@@ -485,10 +503,69 @@ def bench_scene(args, name, scene, K, Wm):
     value = n * K / (t1 - t0)
     fig = {"value": value, "ms_per_step": (t1 - t0) * 1e3 / K, "status": status, "particles": n,
            "timed_substeps": [Wm, Wm + K], "substeps_with_label_pass": labelled_steps,
-           "slots": {"total": tot_slots, "max_per_node": max_slots},
+           "slots": {"total": tot_slots, "max_per_node": max_slots}, "contact": contact,
            "stencil": "quadratic" if quad else "trilinear",
            "roofline": roofline_of(prof, value, n, step_bytes, own, name)}
     return fig
+
+
+class _BatchRun:
+    """A batch of scenes as one object with the status()/close() of a scene (for the
+    autotuner's trials)."""
+
+    def __init__(self, scene_dicts):
+        from paper_2609_27342_amd import tlmpm
+        self.dicts = scene_dicts
+        self.gs = [tlmpm.Scene(s) for s in scene_dicts]
+        self.bt = tlmpm.Batch(self.gs)
+
+    def status(self):
+        # member scenes answer once their batch is gone
+        if self.bt is not None:
+            self.bt.close()
+            self.bt = None
+        return max(g.status() for g in self.gs)
+
+    def close(self):
+        if self.bt is not None:
+            self.bt.close()
+            self.bt = None
+        for g in self.gs:
+            g.close()
+
+
+def tuned(args, name, scene_dicts, batch):
+    """Applies the autotuned launch shape of this workload (cached per signature in
+    paper_2609_27342_amd/tuning_cache.json; timed now when absent or with
+    --retune).  Returns the record reported in config.tuning."""
+    from paper_2609_27342_amd import autotune, tlmpm
+    key = f"{name}:" + autotune.signature(scene_dicts)
+    if batch:
+        def make():
+            return [_BatchRun(scene_dicts)]
+
+        def step(objs, j0, j1):
+            br = objs[0]
+            per = [batch_calls(s, j0, j1) for s in br.dicts]
+            for c in range(len(per[0])):
+                br.bt.step([p[c][0] for p in per], per[0][c][1])
+    else:
+        sc = scene_dicts[0]
+
+        def make():
+            return [tlmpm.Scene(sc)]
+
+        def step(objs, j0, j1):
+            run_steps(objs[0], sc, j0, j1)
+    log = lambda m: print(m, file=sys.stderr, flush=True)
+    choice, trials, source = autotune.tune(key, make, step, steps=args.tune_steps, warmup=5, force=args.retune,
+                                           log=log)
+    autotune.apply(choice)
+    default = {k: v[0] for k, v in autotune.KNOBS.items()}
+    ms = {json.dumps(c, sort_keys=True): m for c, m in trials}
+    return {"key": key, "choice": choice, "source": source, "setting": tlmpm.get_tuning(),
+            "best_ms_per_substep": ms.get(json.dumps(choice, sort_keys=True)),
+            "default_ms_per_substep": ms.get(json.dumps(default, sort_keys=True)), "trials": len(trials)}
 
 
 def bench_scenes(args, W):
@@ -522,6 +599,10 @@ def main():
     ap.add_argument("--tick", type=int, default=100, help="served: substeps per batched iteration")
     ap.add_argument("--budget-gb", type=float, default=200.0, help="served: device bytes for running rollouts")
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--tune", action="store_true",
+                    help="run the timed scenes under the autotuned launch shape (cached per workload)")
+    ap.add_argument("--retune", action="store_true", help="with --tune: time the candidates again")
+    ap.add_argument("--tune-steps", type=int, default=20, help="timed substeps per autotuner trial")
     ap.add_argument("--graphs", action="store_true",
                     help="replay pairs of substeps as captured HIP graphs (tlmpm_set_graphs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -561,7 +642,10 @@ def main():
     scene = bench_scenes(args, W)
     n = scene["X"].shape[0]
     torch.cuda.set_device(0)
+    tuning = tuned(args, args.workload, [scene], False) if args.tune else None
     fig = bench_scene(args, args.workload, scene, K, Wm)
+    if args.tune:
+        tlmpm.set_tuning(None)
     extra = {}
     if args.workload == "large" and not args.no_batched:
         # the many-scene workload beside the headline: plain one scene per call
@@ -571,6 +655,7 @@ def main():
             "value": bk["value"], "ms_per_step": bk["ms_per_step"], "steps": bk["steps"], "warmup": bk["warmup"],
             "scenes": bk["config"]["scenes"], "particles": bk["config"]["particles"], "plain": bk["config"]["plain"],
             "batched_over_plain": bk["config"]["batched_over_plain"], "status": bk["status"],
+            "contact": bk["config"]["contact"], "tuning": bk["config"]["tuning"],
             "roofline": {k: bk["roofline"][k] for k in ("kernel", "achieved", "frac", "step_alg_frac", "kernels")}}
     if args.workload == "large" and args.served_requests:
         # the first requests of the served stream (40/s, horizons U[0.5, 2] s)
@@ -584,7 +669,8 @@ def main():
     if args.workload == "large" and args.others:
         # the smaller scene families of the same path, each timed inside its cut
         extra["others"] = {}
-        for nm, sc, k, w in (("small", W.small(), 100, 10), ("medium", W.medium(z_start=0.034), 1000, 100)):
+        for nm, sc, k, w in (("small", W.small(), 100, 10), ("medium", W.medium(z_start=0.034), 1000, 100),
+                             ("large-4.7m", W.CONFIGS["large-4.7m"](), 100, 10)):
             f = bench_scene(args, nm, sc, k, w)
             f["roofline"] = {kk: f["roofline"][kk] for kk in ("kernel", "achieved", "frac", "step_alg_frac",
                                                                 "kernels")}
@@ -596,8 +682,10 @@ def main():
            "material_contact": bool(scene["params"]["material_contact"]),
            "stencil": fig["stencil"], "path": "graph" if args.graphs else "plain",
            "timed_substeps": fig["timed_substeps"], "substeps_with_label_pass": fig["substeps_with_label_pass"],
-           "slots": fig["slots"]}
+           "slots": fig["slots"], "contact": fig["contact"]}
     cfg.update(extra)
+    if tuning is not None:
+        cfg["tuning"] = tuning
     out = {
         "metric": "particle-steps/s per GPU",
         "value": fig["value"],

@@ -220,9 +220,38 @@ tlmpm_status tlmpm_slot_stats(tlmpm_scene* scene, int64_t* total_slots, int32_t*
 /* Diagnostics of the material-contact search of the last substep (Sec. III-E):
  * out[0] contact candidates, out[1] hash buckets, out[2] occupied buckets,
  * out[3] buckets holding more candidates than their inline records, out[4] the
- * largest bucket count, out[5] the bin edge in metres.  All zero without material
- * contact.  Synchronises. */
-tlmpm_status tlmpm_contact_stats(tlmpm_scene* scene, double out[6]);
+ * largest bucket count, out[5] the bin edge in metres, out[6] the pairs in contact
+ * (each contact is kept by both partners, at most 16 per particle; half the sum of
+ * the particles' counts).  All zero without material contact.  Synchronises. */
+tlmpm_status tlmpm_contact_stats(tlmpm_scene* scene, double out[7]);
+
+/* Launch-shape settings, process-wide.  A scene takes them when it is created
+ * (and tlmpm_batch_scene_bytes reads them), so set them before creating the scenes
+ * they are meant for; scenes created earlier keep theirs.  They change how work is
+ * divided among workgroups, not what is computed: the pair search and the stream
+ * arrangement give bitwise the same results for any setting; splitting mixed bricks
+ * adds a brick's later same-code rounds as a second partial, which changes the
+ * rounding of those sums (a batch equals its scenes run alone when all were
+ * created with the same settings).
+ *   pair_div, pair_cap: pair-search workgroups of a scene = min(pair_cap,
+ *       max(1, N / pair_div)) (defaults 128, 4096);
+ *   split_lo, split_hi, split_div, split_cap: scenes of split_lo..split_hi active
+ *       bricks run the later rounds of bricks with a mixed cell in min(split_cap,
+ *       active / split_div) extra workgroups of P2G and G2P (512, 4096, 4, 256;
+ *       split_cap 0 turns the split off);
+ *   one_stream_bricks: a single scene of at most this many active bricks runs a
+ *       substep with a label pass on one stream (label pass and rigid contact in
+ *       one launch, slot tables and pair search in one launch), larger ones put
+ *       rigid contact and the slot tables on a second stream (2048).
+ * tlmpm_set_tuning(NULL) restores the defaults; TLMPM_E_INVALID for values out of
+ * range (a divisor or cap below 1, split_hi < split_lo, a negative value). */
+typedef struct {
+    int32_t pair_div, pair_cap;
+    int32_t split_lo, split_hi, split_div, split_cap;
+    int32_t one_stream_bricks;
+} tlmpm_tuning;
+tlmpm_status tlmpm_set_tuning(const tlmpm_tuning* tuning);
+tlmpm_status tlmpm_get_tuning(tlmpm_tuning* tuning);
 
 /* HIP graph replay of substeps.  While enabled, a tlmpm_step of n >= 3 substeps
  * runs its first substep as plain launches and the following pairs of substeps as

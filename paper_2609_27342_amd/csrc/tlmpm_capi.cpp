@@ -119,6 +119,7 @@ struct tlmpm_scene {
     int rsb;       // slot table of the pending re-scatter
     bool f_pending; // host copy of the device flag D.ctr[1]
     int in_batch = 0; // member of a live batch: single-scene calls are refused
+    int fuse_bricks = 0; // one-stream substeps up to this many active bricks (tuning at creation)
     std::vector<int> active_host;
     Timing prof;
     GraphCache graphs;
@@ -180,13 +181,34 @@ struct Layout {
     }
 };
 
-// blocks of the grid-stride pair search of a scene of N particles
-int pair_blocks_of(long long N) { return (int)std::min<long long>(4096, std::max<long long>(1, N / 128)); }
+// Launch-shape settings (tlmpm_set_tuning), read when a scene is created or its
+// batch footprint is asked for.  Defaults: the measured best on the workloads of
+// the benchmark.
+static const tlmpm_tuning k_tuning_default = {128, 4096, 512, 4096, 4, 256, 2048};
+static tlmpm_tuning g_tuning = k_tuning_default;
+static std::mutex g_tuning_mutex;
 
-// workgroups for the later same-code rounds of mixed bricks: scenes of 512 to 4096
-// active bricks only (smaller scenes have few long workgroups to hide, larger ones
-// many rounds of workgroups)
-int xcap_of(long long n_active) { return (n_active >= 512 && n_active <= 4096) ? (int)std::min<long long>(256, n_active / 4) : 0; }
+static tlmpm_tuning tuning_now()
+{
+    std::lock_guard<std::mutex> lk(g_tuning_mutex);
+    return g_tuning;
+}
+
+// blocks of the grid-stride pair search of a scene of N particles
+int pair_blocks_of(long long N, const tlmpm_tuning& t)
+{
+    return (int)std::min<long long>(t.pair_cap, std::max<long long>(1, N / t.pair_div));
+}
+
+// workgroups for the later same-code rounds of mixed bricks: scenes of split_lo to
+// split_hi active bricks only (smaller scenes have few long workgroups to hide,
+// larger ones many rounds of workgroups)
+int xcap_of(long long n_active, const tlmpm_tuning& t)
+{
+    return (n_active >= t.split_lo && n_active <= t.split_hi)
+               ? (int)std::min<long long>(t.split_cap, n_active / t.split_div)
+               : 0;
+}
 
 struct Dims {
     long long N;
@@ -504,6 +526,7 @@ extern "C" tlmpm_status tlmpm_create_scene(const tlmpm_scene_desc* d, void* ws, 
     sc->prof.st = sc->st;
 
     sc->max_cuts = d->max_cuts;
+    sc->fuse_bricks = tuning_now().one_stream_bricks;
     sc->n_bricks = (int)g.n_bricks;
     sc->cur = 0;
     sc->rsb = 0;
@@ -558,7 +581,8 @@ extern "C" tlmpm_status tlmpm_create_scene(const tlmpm_scene_desc* d, void* ws, 
     K.material = d->material;
     K.visc = d->viscosity;
     K.ystress = d->yield_stress;
-    K.pair_blocks = pair_blocks_of(N);
+    const tlmpm_tuning tun = tuning_now();
+    K.pair_blocks = pair_blocks_of(N, tun);
     K.stencil = d->stencil;
     // workgroups for the later rounds of bricks with a mixed cell: a quarter of the
     // bricks, at most 256 (with more mixed bricks no brick is split).  Only scenes of
@@ -567,7 +591,7 @@ extern "C" tlmpm_status tlmpm_create_scene(const tlmpm_scene_desc* d, void* ws, 
     // smaller scenes (the many-scene batches) and larger ones measured slower with the
     // extra launch slots than the rounds cost.
     const size_t na = active.size();
-    K.xcap = xcap_of((long long)na);
+    K.xcap = xcap_of((long long)na, tun);
     float vmax0 = d->vol0_uniform;
     if (d->vol0)
         for (long long p = 0; p < N; p++) vmax0 = std::max(vmax0, d->vol0[p]);
@@ -780,6 +804,24 @@ static tlmpm_status timing_read(Timing& tm, int n_classes, double* ms, int64_t* 
     return TLMPM_OK;
 }
 
+extern "C" tlmpm_status tlmpm_set_tuning(const tlmpm_tuning* t)
+{
+    tlmpm_tuning v = t ? *t : k_tuning_default;
+    if (v.pair_div < 1 || v.pair_cap < 1 || v.split_lo < 0 || v.split_hi < v.split_lo || v.split_div < 1 ||
+        v.split_cap < 0 || v.one_stream_bricks < 0)
+        return fail(TLMPM_E_INVALID, "tuning out of range");
+    std::lock_guard<std::mutex> lk(g_tuning_mutex);
+    g_tuning = v;
+    return TLMPM_OK;
+}
+
+extern "C" tlmpm_status tlmpm_get_tuning(tlmpm_tuning* t)
+{
+    if (!t) return fail(TLMPM_E_INVALID, "null output");
+    *t = tuning_now();
+    return TLMPM_OK;
+}
+
 extern "C" tlmpm_status tlmpm_set_graphs(tlmpm_scene* sc, int32_t enable)
 {
     if (!sc) return fail(TLMPM_E_INVALID, "null scene");
@@ -820,6 +862,7 @@ struct Exec {
     int cur, rsb;      // slot table in use / of the pending re-scatter
     bool pending;      // some scene has a pending F update
     Fork* fork = nullptr; // second stream, or null (everything on L.st)
+    int fuse_bricks = 0;  // single scene: one-stream substeps up to this many active bricks
 };
 
 // launches on the second stream (after the main stream's work so far) when there
@@ -895,13 +938,12 @@ struct CallFlags {
 // one substep with the quadratic stencil: labels and contact as in the trilinear
 // path, then the transfers of tlmpm_quad.hip with the node tables of parity X.cur
 // (flipped every substep); the F update completes inside the substep.
-// Scenes of at most this many active bricks run a substep with a label pass on one
-// stream (see fused_label_substep).
-static const int TL_FUSE_BRICKS = 2048;
-
+// Single scenes of at most X.fuse_bricks active bricks (tlmpm_tuning.one_stream_bricks
+// when the scene was created) run a substep with a label pass on one stream (see
+// fused_label_substep).
 static bool one_stream(const Exec& X, const CallFlags& f)
 {
-    return f.any_labels && X.L.S && X.L.D->n_active <= TL_FUSE_BRICKS && !(X.prof && X.prof->on);
+    return f.any_labels && X.L.S && X.L.D->n_active <= X.fuse_bricks && !(X.prof && X.prof->on);
 }
 
 static tlmpm_status one_substep_quad(Exec& X, const CallFlags& f, bool first)
@@ -953,7 +995,7 @@ static tlmpm_status one_substep_quad(Exec& X, const CallFlags& f, bool first)
 // search (each pair touches disjoint arrays), instead of the second stream, whose
 // fork and join events cost more than the launches they overlap; the binning blocks
 // sum the candidate offsets themselves (no scan launch).  Only scenes of at
-// most TL_FUSE_BRICKS active bricks: there the two launches of a pair fit the chip
+// most one_stream_bricks active bricks: there the two launches of a pair fit the chip
 // side by side; a large scene (27k bricks) measured slower fused (labels and rigid
 // contact 0.22 ms against 0.06 ms with rigid contact beside it), and batches keep the
 // second stream as well.
@@ -1093,6 +1135,7 @@ static Exec single_exec(tlmpm_scene* sc)
     X.cur = sc->cur;
     X.rsb = sc->rsb;
     X.pending = sc->f_pending;
+    X.fuse_bricks = sc->fuse_bricks;
     return X;
 }
 
@@ -1398,11 +1441,11 @@ extern "C" tlmpm_status tlmpm_slot_stats(tlmpm_scene* sc, int64_t* total_slots, 
     return TLMPM_OK;
 }
 
-extern "C" tlmpm_status tlmpm_contact_stats(tlmpm_scene* sc, double out[6])
+extern "C" tlmpm_status tlmpm_contact_stats(tlmpm_scene* sc, double out[7])
 {
     if (!out) return fail(TLMPM_E_INVALID, "null output");
     if (tlmpm_status r = refuse_batched(sc)) return r;
-    for (int i = 0; i < 6; i++) out[i] = 0.0;
+    for (int i = 0; i < 7; i++) out[i] = 0.0;
     if (!sc->K.material_contact) return TLMPM_OK;
     const size_t nb = (size_t)sc->D.hmask + 1;
     std::vector<int> cnt(nb);
@@ -1429,6 +1472,17 @@ extern "C" tlmpm_status tlmpm_contact_stats(tlmpm_scene* sc, double out[6])
     out[3] = (double)over;
     out[4] = mx;
     out[5] = hb;
+    // pairs in contact: every contact is kept in both partners' spring lists of
+    // the substep's stamp (at most TL_PCAP per particle)
+    const long long N = sc->K.N;
+    std::vector<int> hdr((size_t)N);
+    HIPCHK(hipMemcpyAsync(hdr.data(), sc->D.ph_n + (size_t)((stamp - 1) & 1) * N, (size_t)N * 4,
+                          hipMemcpyDeviceToHost, sc->st));
+    HIPCHK(hipStreamSynchronize(sc->st));
+    long long ends = 0;
+    for (int h : hdr)
+        if ((h >> 8) == stamp - 1) ends += h & 0xFF;
+    out[6] = 0.5 * (double)ends;
     return TLMPM_OK;
 }
 
@@ -1693,7 +1747,8 @@ extern "C" tlmpm_status tlmpm_batch_scene_bytes(const tlmpm_scene_desc* desc, si
     const Dims g = dims_of(desc);
     const long long na = count_active(desc);
     int c[TL_ITEM_KINDS];
-    items_of(na, g.n_bricks, g.NN, g.N, desc->material_contact != 0, pair_blocks_of(g.N), xcap_of(na), c);
+    const tlmpm_tuning tun = tuning_now();
+    items_of(na, g.n_bricks, g.NN, g.N, desc->material_contact != 0, pair_blocks_of(g.N, tun), xcap_of(na, tun), c);
     size_t b = sizeof(SceneK) + sizeof(SceneD) + sizeof(BatchTools) + TL_MAX_TOOLS * 6 * sizeof(double);
     for (int k = 0; k < TL_ITEM_KINDS; k++) b += (size_t)c[k] * sizeof(int2);
     // the alignment of the batch layout's 4 + TL_ITEM_KINDS arrays and its tail

@@ -3,14 +3,17 @@
 // Work decomposition.  Particles are sorted into bricks of 4x4x4 reference cells;
 // inside a brick by cell parity class (8 classes of 8 cells that share no grid node)
 // and then by cell.  One 512-thread workgroup owns one brick: wave w holds parity
-// class w, lane (i, j) holds particle j of cell i of that class.  A brick touches
-// the 5x5x5 box of nodes around it.
+// class w, lane (i, j) holds particle j of cell i of that class, where the bits of
+// j sit at lane bits 0, 1 and 4 and those of i at lane bits 2, 3 and 5 (a cell's 8
+// lanes are two quads in rows 2q and 2q+1 of the wave).  A brick touches the 5x5x5
+// box of nodes around it.
 //
 // Particle-to-grid sums are gathers with a fixed order, without float atomics:
 //   1. every lane forms its particle's contribution to the 8 corner nodes of its
 //      cell;
 //   2. an 8-lane butterfly reduce-scatter leaves in lane (i, k) the sum of cell i's
-//      particles for corner k;
+//      particles for corner k (the j bit 2 stage swaps rows with
+//      v_permlane16_swap, the other two add across the quad with DPP);
 //   3. the 8 waves add their per-node sums into LDS one class after another;
 //   4. the box sums are written as this brick's partial; a node's total is the sum
 //      of the partials of the (up to 8) bricks around it, formed in fixed order by
@@ -249,8 +252,8 @@ DEV Lane lane_of(const SceneD& D, int brick)
     int tid = threadIdx.x;
     L.w = tid >> 6;
     L.lane = tid & 63;
-    L.i = L.lane >> 3;
-    L.j = L.lane & 7;
+    L.i = ((L.lane >> 2) & 3) | ((L.lane >> 3) & 4); // lane bits 2, 3, 5
+    L.j = (L.lane & 3) | ((L.lane >> 2) & 4);        // lane bits 0, 1, 4
     L.cxl = 2 * (L.i & 1) + (L.w & 1);
     L.cyl = 2 * ((L.i >> 1) & 1) + ((L.w >> 1) & 1);
     L.czl = 2 * ((L.i >> 2) & 1) + ((L.w >> 2) & 1);
@@ -298,42 +301,80 @@ DEV void corner_weights(const float t[3], int k, float& wx, float& wy, float& wz
 }
 
 // --------------------------------------------------------- butterfly reduce-scatter
-// gen(k, out) produces this lane's contribution to corner k of its cell.  Result:
-// res[Q] = sum over the 8 lanes of the cell group of their corner-(lane & 7)
-// values.  Corners are generated in pairs so at most 4 x Q partial sums are live.
-template <int Q, class Gen>
+// Weights of the 8 corners of a lane's cell in the order the relative butterfly
+// takes them: corner r has x bit (r & 1) and y bit (r >> 1 & 1) relative to the
+// lane's own corner j (clear: j's side, set: the other side) and z bit (r >> 2)
+// absolute, so its absolute index is r ^ (j & 3).  Each factor is the one
+// corner_weights gives for the absolute corner.
+struct CornerW {
+    float wx[2], wy[2], wz[2];
+};
+
+DEV CornerW corner_table(const float t[3], int j)
+{
+    CornerW c;
+    const bool bx = j & 1, by = (j >> 1) & 1;
+    const float ox = 1.0f - t[0], oy = 1.0f - t[1];
+    c.wx[0] = bx ? t[0] : ox;
+    c.wx[1] = bx ? ox : t[0];
+    c.wy[0] = by ? t[1] : oy;
+    c.wy[1] = by ? oy : t[1];
+    c.wz[0] = 1.0f - t[2];
+    c.wz[1] = t[2];
+    return c;
+}
+
+// gen(r, out) produces this lane's contribution to corner r of its cell.  Result:
+// res[Q] = sum over the 8 lanes of the cell group of their values for corner j (the
+// lane's own).  REL: corners in the order of CornerW (x and y bits relative to j);
+// else absolute corner indices.  Stage 1 pairs j with j ^ 4 (lane ^ 16):
+// v_permlane16_swap of (z = 0, z = 1) leaves in the even row (z bit of j clear) its
+// own and its partner's z = 0 values, in the odd row the z = 1 values; stages 2 and
+// 3 pair j ^ 2 and j ^ 1 within the quad, each lane sending the value of the
+// partner's side (REL: its other-side value, no select).  The sum tree is ((j,
+// j^4), (j^2, j^6)), ((j^1, j^5), (j^3, j^7)), own operand first, for every lane
+// order.  Corners are generated in (z = 0, z = 1) pairs, so at most 4 x Q partial
+// sums are live.
+template <int Q, bool REL, class Gen>
 DEV void reduce_scatter8(Gen&& gen, float (&res)[Q], int j)
 {
     float c1[4][Q];
-    const bool b2 = (j >> 2) & 1;
 #pragma unroll
-    for (int kk = 0; kk < 4; kk++) {
+    for (int rr = 0; rr < 4; rr++) {
         float lo[Q], hi[Q];
-        gen(kk, lo);
-        gen(kk | 4, hi);
+        gen(rr, lo);
+        gen(rr | 4, hi);
 #pragma unroll
         for (int q = 0; q < Q; q++) {
-            float send = b2 ? lo[q] : hi[q];
-            float keep = b2 ? hi[q] : lo[q];
-            c1[kk][q] = keep + lane_xor<4>(send);
+            const auto sw = __builtin_amdgcn_permlane16_swap(__float_as_uint(lo[q]), __float_as_uint(hi[q]), false,
+                                                             false);
+            c1[rr][q] = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
         }
     }
     float c2[2][Q];
     const bool b1 = (j >> 1) & 1;
 #pragma unroll
-    for (int kk = 0; kk < 2; kk++)
+    for (int rr = 0; rr < 2; rr++)
 #pragma unroll
         for (int q = 0; q < Q; q++) {
-            float send = b1 ? c1[kk][q] : c1[kk | 2][q];
-            float keep = b1 ? c1[kk | 2][q] : c1[kk][q];
-            c2[kk][q] = keep + lane_xor<2>(send);
+            if constexpr (REL) {
+                c2[rr][q] = c1[rr][q] + lane_xor<2>(c1[rr | 2][q]);
+            } else {
+                const float send = b1 ? c1[rr][q] : c1[rr | 2][q];
+                const float keep = b1 ? c1[rr | 2][q] : c1[rr][q];
+                c2[rr][q] = keep + lane_xor<2>(send);
+            }
         }
     const bool b0 = j & 1;
 #pragma unroll
     for (int q = 0; q < Q; q++) {
-        float send = b0 ? c2[0][q] : c2[1][q];
-        float keep = b0 ? c2[1][q] : c2[0][q];
-        res[q] = keep + lane_xor<1>(send);
+        if constexpr (REL) {
+            res[q] = c2[0][q] + lane_xor<1>(c2[1][q]);
+        } else {
+            const float send = b0 ? c2[0][q] : c2[1][q];
+            const float keep = b0 ? c2[1][q] : c2[0][q];
+            res[q] = keep + lane_xor<1>(send);
+        }
     }
 }
 
@@ -342,24 +383,24 @@ DEV void reduce_scatter8(Gen&& gen, float (&res)[Q], int j)
 // butterflies keep fewer partial sums live).  Every 8-lane group holds particles
 // of one code (bricks with a mixed cell are processed in same-code groups).
 // Component q of the generated values is stored at (q + ROT) mod Q of a slot.
-template <int QA, int QB, int ROT = 0, class GA, class GB>
+template <int QA, int QB, bool REL, int ROT = 0, class GA, class GB>
 DEV void accumulate_classes(const Lane& L, bool valid, uint32_t key, GA&& ga, GB&& gb, const BoxTab& T, float* acc,
                             int* status)
 {
     constexpr int Q = QA + QB;
-    const int leader = L.lane & ~7;
+    const int leader = L.lane & ~0x13; // j = 0 of the lane's cell
     const uint32_t lkey = __shfl(key, leader, 64);
     const bool gvalid = __shfl((int)valid, leader, 64) != 0;
     if (__any(valid && key != lkey) && L.lane == 0) atomicOr(status, TL_ST_LOOKUP);
     float res[Q];
     {
         float ra[QA];
-        reduce_scatter8<QA>(ga, ra, L.j);
+        reduce_scatter8<QA, REL>(ga, ra, L.j);
 #pragma unroll
         for (int q = 0; q < QA; q++) res[q] = ra[q];
         if constexpr (QB > 0) {
             float rb[QB];
-            reduce_scatter8<QB>(gb, rb, L.j);
+            reduce_scatter8<QB, REL>(gb, rb, L.j);
 #pragma unroll
             for (int q = 0; q < QB; q++) res[QA + q] = rb[q];
         }
@@ -933,6 +974,8 @@ DEV void p2g_body(const SceneK& S, const SceneD& D, int bi, KA_Args A, int part)
 #pragma unroll
         for (int a = 0; a < 9; a++) Pk[a] *= sA;
         const float mm = valid ? m : 0.0f;
+        // absolute corners (the CornerW order needs more registers here than the
+        // selects it saves: the impulse generator also needs per-lane gradient signs)
         auto gen_mp = [&](int k, float* o) { // mass and momentum
             float wx, wy, wz;
             corner_weights(t, k, wx, wy, wz);
@@ -958,7 +1001,7 @@ DEV void p2g_body(const SceneK& S, const SceneD& D, int bi, KA_Args A, int part)
         };
         // impulses first: their butterfly then runs while fewer values are live;
         // stored as (m, m v, dp) like the other order
-        accumulate_classes<3, 4, 4>(L, valid, key, gen_dp, gen_mp, T, s_acc, D.status);
+        accumulate_classes<3, 4, false, 4>(L, valid, key, gen_dp, gen_mp, T, s_acc, D.status);
     }
     if (!A.do_p2g) return;
     if (SPLIT && part == 0 && tid == 0) D.xp2g[bi] = split ? 1 : 0;
@@ -1107,16 +1150,16 @@ DEV void g2p_body(const SceneK& S, const SceneD& D, int bi, int cur, int part)
             m = S.m_uniform ? S.m0 : D.m[p];
         }
         const float mm = valid ? m : 0.0f;
-        auto gen = [&](int k, float* o) {
-            float wx, wy, wz;
-            corner_weights(t, k, wx, wy, wz);
+        const CornerW cw = corner_table(t, L.j);
+        auto gen = [&](int r, float* o) {
+            const float wx = cw.wx[r & 1], wy = cw.wy[(r >> 1) & 1], wz = cw.wz[r >> 2];
             float w = wx * wy * wz * mm;
             o[0] = w;
             o[1] = w * vn1[0];
             o[2] = w * vn1[1];
             o[3] = w * vn1[2];
         };
-        accumulate_classes<4, 0>(L, valid, key, gen, gen, T, s_acc, D.status);
+        accumulate_classes<4, 0, true>(L, valid, key, gen, gen, T, s_acc, D.status);
     }
     if (SPLIT && part == 0 && tid == 0) D.xrs[bi] = split ? 1 : 0;
     write_partials<4>(S, part ? D.rs_x : D.rs, bi, T, total, s_acc);

@@ -180,13 +180,16 @@ class Server:
                     batch = None
                 for ro in finished:
                     out = ro.scene.read(self.read_fields)
-                    st = ro.scene.status()
+                    st, detail = ro.scene.status_detail()
+                    if st:
+                        detail += f"; largest slot count {ro.scene.slot_stats()[1]}"
                     ro.scene.close()
                     adm.release(ro.nbytes)
                     done = now()
                     lat[ro.req["index"]] = done - ro.arrival
-                    self.results[ro.req["index"]] = dict(fields=out, status=st, n=ro.n, steps=ro.horizon,
-                                                         arrival=ro.arrival, admitted=ro.admitted, done=done)
+                    self.results[ro.req["index"]] = dict(fields=out, status=st, detail=detail, n=ro.n,
+                                                         steps=ro.horizon, arrival=ro.arrival, admitted=ro.admitted,
+                                                         done=done)
                     if log:
                         log(f"[serve] t={done:.2f}s done request {ro.req['index']} n={ro.n} "
                             f"steps={ro.horizon} latency={done - ro.arrival:.2f}s running={len(active) - 1}")

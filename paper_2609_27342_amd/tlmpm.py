@@ -56,6 +56,14 @@ class Tool(C.Structure):
 _lib = None
 
 
+class Tuning(C.Structure):
+    _fields_ = [("pair_div", C.c_int32), ("pair_cap", C.c_int32), ("split_lo", C.c_int32), ("split_hi", C.c_int32),
+                ("split_div", C.c_int32), ("split_cap", C.c_int32), ("one_stream_bricks", C.c_int32)]
+
+
+TUNING_KEYS = tuple(k for k, _ in Tuning._fields_)
+
+
 class RigidBodyC(C.Structure):
     _fields_ = [
         ("x", C.c_double * 3), ("q", C.c_double * 4), ("v", C.c_double * 3), ("omega", C.c_double * 3),
@@ -100,6 +108,8 @@ def lib():
         L.tlmpm_set_graphs.argtypes = [vp, C.c_int32]
         L.tlmpm_batch_set_graphs.argtypes = [vp, C.c_int32]
         L.tlmpm_batch_profile_read.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        L.tlmpm_set_tuning.argtypes = [C.POINTER(Tuning)]
+        L.tlmpm_get_tuning.argtypes = [C.POINTER(Tuning)]
         L.tlmpm_last_error.restype = C.c_char_p
         for f in ("tlmpm_scene_footprint", "tlmpm_create_scene", "tlmpm_destroy_scene", "tlmpm_assign_labels",
                   "tlmpm_step", "tlmpm_read_state", "tlmpm_write_state", "tlmpm_get_status", "tlmpm_slot_stats", "tlmpm_contact_stats", "tlmpm_rigid_step", "tlmpm_rigid_tool",
@@ -107,10 +117,35 @@ def lib():
                   "tlmpm_surface_footprint", "tlmpm_surface_build", "tlmpm_surface_read",
                   "tlmpm_batch_create", "tlmpm_batch_create_static",
                   "tlmpm_batch_destroy", "tlmpm_batch_step", "tlmpm_batch_sync", "tlmpm_batch_profile_enable",
-                  "tlmpm_batch_profile_read", "tlmpm_set_graphs", "tlmpm_batch_set_graphs"):
+                  "tlmpm_batch_profile_read", "tlmpm_set_graphs", "tlmpm_batch_set_graphs", "tlmpm_set_tuning",
+                  "tlmpm_get_tuning"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
+
+
+def get_tuning():
+    """The launch-shape settings new scenes take (tlmpm_get_tuning), as a dict."""
+    t = Tuning()
+    _check(lib().tlmpm_get_tuning(C.byref(t)))
+    return {k: int(getattr(t, k)) for k in TUNING_KEYS}
+
+
+def set_tuning(tuning=None, **kw):
+    """Sets the launch-shape settings of scenes created from now on
+    (tlmpm_set_tuning): keys of TUNING_KEYS, unnamed ones unchanged; set_tuning(None)
+    with no keywords restores the defaults."""
+    if tuning is None and not kw:
+        _check(lib().tlmpm_set_tuning(None))
+        return
+    cur = get_tuning()
+    cur.update(tuning or {})
+    cur.update(kw)
+    unknown = set(cur) - set(TUNING_KEYS)
+    if unknown:
+        raise ValueError(f"unknown tuning keys {sorted(unknown)}")
+    t = Tuning(**{k: int(cur[k]) for k in TUNING_KEYS})
+    _check(lib().tlmpm_set_tuning(C.byref(t)))
 
 
 class TlmpmError(RuntimeError):
@@ -356,6 +391,11 @@ class Scene:
         _check(lib().tlmpm_get_status(self.h, C.byref(st)))
         return st.value
 
+    def status_detail(self):
+        """(status, the device status bits as text, empty when OK)."""
+        st = self.status()
+        return st, (lib().tlmpm_last_error().decode() if st else "")
+
     KERNEL_CLASSES = ("p2g", "g2p", "labels", "slots", "contact", "other")
 
     def graphs(self, enable=True):
@@ -409,10 +449,10 @@ class Scene:
     def contact_stats(self):
         """Material-contact search of the last substep: candidates, buckets,
         occupied buckets, buckets beyond their inline records, largest bucket
-        count, bin edge (m)."""
-        out = (C.c_double * 6)()
+        count, bin edge (m), pairs in contact."""
+        out = (C.c_double * 7)()
         _check(lib().tlmpm_contact_stats(self.h, out))
-        keys = ("candidates", "buckets", "occupied", "overflowing", "max_count", "bin_edge")
+        keys = ("candidates", "buckets", "occupied", "overflowing", "max_count", "bin_edge", "pairs")
         return {k: (out[i] if k == "bin_edge" else int(out[i])) for i, k in enumerate(keys)}
 
 

@@ -296,7 +296,8 @@ def _random_scene(rng, n_target, dx, dt):
     origin, cells = _grid(lo, ext, dx, pad=1)
     X = jittered_lattice(lo, ext, dx, origin, inside, rng)
     E = float(np.exp(rng.uniform(math.log(2e4), math.log(1e5))))
-    # up to four crossing cuts in a small body: room for 16 logical grids per node
+    # up to three crossing cuts (many-scene workload) or four slices in a small
+    # body: room for 16 logical grids per node
     params = base_params(dx, origin, cells, dt, 0.3, material_contact=1, floor_on=1, slot_capacity=16)
     return shape, ext, X, E, params
 
@@ -328,16 +329,41 @@ def batch_scene(seed, index, n_target, dx=0.0025, steps=1000, dt=1e-4):
     return sc
 
 
+def _slicing_blades(rng, ext, n_cuts):
+    """Sequential slicing (the paper's scenes with successive cuts): one knife
+    orientation per request (d and n drawn as in _random_blade), cut k in the plane
+    of normal n through the body's centre moved by o_k along n, o_k at the k-th of
+    n_cuts interior points dividing [-r, r] into equal parts (r = half the smallest
+    extent, so that the plane's point on the centre line lies in the body), each
+    jittered by up to +-20 % of a part; the cuts proceed from one side; each has its
+    own speed U[0.05, 0.3] m/s and starts where its line through that point along -d
+    leaves the bounding box.  Returns [(start, n, d, speed)] in cut order."""
+    d = _random_dir_down(rng)
+    a = rng.normal(size=3)
+    n = a - np.dot(a, d) * d
+    n /= np.linalg.norm(n)
+    r = 0.5 * float(np.min(ext))
+    part = 2.0 * r / (n_cuts + 1)
+    centre = 0.5 * np.asarray(ext, np.float64)
+    out = []
+    for k in range(n_cuts):
+        o = -r + (k + 1) * part + rng.uniform(-0.2, 0.2) * part
+        aim = centre + o * n
+        start = aim - d * _exit_distance(aim, -d, np.zeros(3), ext)
+        out.append((start, n.copy(), d.copy(), rng.uniform(0.05, 0.3)))
+    return out
+
+
 def served_request(seed, index, n_target, horizon_steps, tick, dx=0.0025, dt=1e-4):
-    """One request of the served workload: body, material and blades as
-    batch_scene, with one to four cuts made one after another, each in its own
-    window of the horizon (windows are whole ticks; a blade is withdrawn when its
-    window ends)."""
+    """One request of the served workload: body and material as batch_scene, cut by
+    sequential slicing (_slicing_blades): one to four parallel cuts made one after
+    another, each in its own window of the horizon (windows are whole ticks; a
+    blade is withdrawn when its window ends)."""
     rng = np.random.default_rng([seed, index])
     shape, ext, X, E, params = _random_scene(rng, n_target, dx, dt)
     diag = float(np.linalg.norm(ext))
     n_cuts = int(rng.integers(1, 5))
-    specs = [_random_blade(rng, ext) for _ in range(n_cuts)]
+    specs = _slicing_blades(rng, ext, n_cuts)
     n_ticks = max(1, horizon_steps // tick)
     bounds = [tick * ((n_ticks * k) // n_cuts) for k in range(n_cuts + 1)]
 
@@ -527,4 +553,7 @@ def quadratic(scene):
 
 CONFIGS = {"small": small, "small-deep": lambda **k: small(deep=True, **k), "medium": medium,
            "medium-quad": lambda **k: quadratic(medium(**k)), "large-quad": lambda **k: quadratic(large(**k)),
-           "large": large}
+           "large": large,
+           # the large box at the particle count the scene description states (~4.7M);
+           # its literal dx = 1.5 mm gives 14.2M
+           "large-4.7m": lambda **k: large(dx=0.00217, **k)}

@@ -70,3 +70,23 @@ def test_batch_validation_without_gpu():
     out = ctypes.c_void_p()
     assert L.tlmpm_batch_create(None, 0, None, ctypes.c_size_t(0), None, ctypes.byref(out)) == 1
     assert L.tlmpm_batch_step(None, None, None, 1, None) == 1
+
+
+def test_tuning_round_trip_and_validation_without_gpu():
+    from paper_2609_27342_amd import tlmpm
+    d = tlmpm.get_tuning()
+    assert d == {"pair_div": 128, "pair_cap": 4096, "split_lo": 512, "split_hi": 4096, "split_div": 4,
+                 "split_cap": 256, "one_stream_bricks": 2048}
+    try:
+        tlmpm.set_tuning(pair_div=64, split_cap=0)
+        assert tlmpm.get_tuning() == dict(d, pair_div=64, split_cap=0)
+        for bad in (dict(pair_div=0), dict(pair_cap=0), dict(split_lo=5000), dict(split_div=0), dict(split_cap=-1),
+                    dict(one_stream_bricks=-1)):
+            with pytest.raises(tlmpm.TlmpmError):
+                tlmpm.set_tuning(**bad)
+        assert tlmpm.get_tuning() == dict(d, pair_div=64, split_cap=0)  # a refused setting changes nothing
+        with pytest.raises(ValueError):
+            tlmpm.set_tuning(lanes=4)
+    finally:
+        tlmpm.set_tuning(None)
+    assert tlmpm.get_tuning() == d
