@@ -128,7 +128,7 @@ def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
     for f in ("tlmpm_common.h", "tlmpm_device.h", "tlmpm_band.h", "tlmpm_kernels.hip", "tlmpm_contact.hip",
-              "tlmpm_quad.hip"):
+              "tlmpm_quad.hip", "tlmpm_surface.hip"):
         with open(os.path.join(ROOT, "paper_2609_27342_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -559,7 +559,7 @@ def tuned(args, name, scene_dicts, batch):
             run_steps(objs[0], sc, j0, j1)
     log = lambda m: print(m, file=sys.stderr, flush=True)
     choice, trials, source = autotune.tune(key, make, step, steps=args.tune_steps, warmup=5, force=args.retune,
-                                           log=log)
+                                           log=log, scene_dicts=scene_dicts, single=not batch)
     autotune.apply(choice)
     default = {k: v[0] for k, v in autotune.KNOBS.items()}
     ms = {json.dumps(c, sort_keys=True): m for c, m in trials}
