@@ -72,18 +72,6 @@ def cpu_info():
     return model
 
 
-def crop(scene, xr, yr):
-    """The particles of `scene` with x in xr and y in yr, as a scene of their own
-    (same grid, parameters and tools)."""
-    X = scene["X"]
-    keep = (X[:, 0] >= xr[0]) & (X[:, 0] <= xr[1]) & (X[:, 1] >= yr[0]) & (X[:, 1] <= yr[1])
-    out = dict(scene, X=np.ascontiguousarray(X[keep]), vol0=scene["vol0"][keep], mass=scene["mass"][keep],
-               E=scene["E"][keep], name=scene["name"] + "-sample")
-    if scene.get("v0") is not None:
-        out["v0"] = scene["v0"][keep]
-    return out
-
-
 def oracle_rate(scene, threads, budget_s, max_steps=400):
     """(particle-steps/s, substeps) of the FP64 oracle from the first substep of
     `scene`, until about budget_s seconds have been spent."""
@@ -108,7 +96,8 @@ def cpu_baseline(scene, budget_s=10.0, sample=None):
     whole scene, or the particles of `sample` = (x range, y range)), from its first
     substep: one thread, then all threads (OpenMP over the loops with independent
     iterations; the results do not depend on the thread count)."""
-    sc = crop(scene, *sample) if sample else scene
+    from paper_2609_27342_amd import workloads as W
+    sc = W.crop(scene, *sample) if sample else scene
     n = sc["X"].shape[0]
     threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
     v1, s1 = oracle_rate(sc, 1, budget_s)
@@ -492,6 +481,7 @@ def bench_scene(args, name, scene, K, Wm):
     g.profile(False)
     status = g.status()
     tot_slots, max_slots = g.slot_stats()
+    hist = g.slot_histogram()
     contact = contact_of([g])
     g.close()
     print(f"[bench] {name}: {(t1 - t0) * 1e3 / K:.4f} ms/step, status={status}", file=sys.stderr, flush=True)
@@ -503,7 +493,9 @@ def bench_scene(args, name, scene, K, Wm):
     value = n * K / (t1 - t0)
     fig = {"value": value, "ms_per_step": (t1 - t0) * 1e3 / K, "status": status, "particles": n,
            "timed_substeps": [Wm, Wm + K], "substeps_with_label_pass": labelled_steps,
-           "slots": {"total": tot_slots, "max_per_node": max_slots}, "contact": contact,
+           "slots": {"total": tot_slots, "max_per_node": max_slots,
+                     "nodes_by_slots": {str(c): h for c, h in enumerate(hist) if h and c}},
+           "contact": contact,
            "stencil": "quadratic" if quad else "trilinear",
            "roofline": roofline_of(prof, value, n, step_bytes, own, name)}
     return fig

@@ -217,6 +217,11 @@ tlmpm_status tlmpm_get_status(tlmpm_scene* scene, int32_t* status);
  * largest count at one node (Sec. III-G, compact slots).  Synchronises. */
 tlmpm_status tlmpm_slot_stats(tlmpm_scene* scene, int64_t* total_slots, int32_t* max_per_node);
 
+/* Diagnostics: hist[c] = number of grid nodes holding c logical-grid slots,
+ * c = 0..16 (Sec. III-G, compact slots; Fig. 10b counts the occupied slots).
+ * Synchronises. */
+tlmpm_status tlmpm_slot_histogram(tlmpm_scene* scene, int64_t hist[17]);
+
 /* Diagnostics of the material-contact search of the last substep (Sec. III-E):
  * out[0] contact candidates, out[1] hash buckets, out[2] occupied buckets,
  * out[3] buckets holding more candidates than their inline records, out[4] the

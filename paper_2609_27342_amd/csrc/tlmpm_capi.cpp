@@ -1441,6 +1441,18 @@ extern "C" tlmpm_status tlmpm_slot_stats(tlmpm_scene* sc, int64_t* total_slots, 
     return TLMPM_OK;
 }
 
+extern "C" tlmpm_status tlmpm_slot_histogram(tlmpm_scene* sc, int64_t hist[TL_SCAP_MAX + 1])
+{
+    if (!hist) return fail(TLMPM_E_INVALID, "null output");
+    if (tlmpm_status r = refuse_batched(sc)) return r;
+    std::vector<uint8_t> c(sc->K.NN);
+    HIPCHK(hipMemcpyAsync(c.data(), sc->D.cnt[sc->cur], sc->K.NN, hipMemcpyDeviceToHost, sc->st));
+    HIPCHK(hipStreamSynchronize(sc->st));
+    for (int i = 0; i <= TL_SCAP_MAX; i++) hist[i] = 0;
+    for (uint8_t v : c) hist[std::min<int>(v, TL_SCAP_MAX)]++;
+    return TLMPM_OK;
+}
+
 extern "C" tlmpm_status tlmpm_contact_stats(tlmpm_scene* sc, double out[7])
 {
     if (!out) return fail(TLMPM_E_INVALID, "null output");

@@ -44,7 +44,7 @@
 #define TL_HSLOTS 64  // slots of the speed-bound maximum (spreads the atomics)
 #define TL_HSTRIDE 1  // ints between slots (consecutive: cheap to read in every binning block)
 #ifndef TL_PLANES
-#define TL_PLANES 8            // lanes per candidate in the pair search (4 or 8)
+#define TL_PLANES 4            // lanes per candidate in the pair search (4 or 8)
 #endif
 #define TL_PCAND (256 / TL_PLANES) // candidates per pair-search block (256 threads)
 #define TL_BCAP 8              // candidate records stored inline per hash bucket

@@ -253,8 +253,10 @@ DEV void cur_pos(const SceneK& S, const SceneD& D, long long p, float x[3])
     x[2] = D.X[2 * S.N + p] + D.u[2 * S.N + p];
 }
 
-// Candidate record: {id, code, reference cell x | y << 16, R}, {x, m}, {v, cell z}
-// (three float4; cells per axis are below 2^16).
+// Candidate record: {id, code, reference cell x | y << 16, cell z}, {x, m}, {v, R}
+// (three float4; cells per axis are below 2^16).  The first two hold what the pair
+// search's filters read (reach, reference-neighbour exclusion, bin), so the third
+// is loaded only for the few entries that pass them.
 DEV void make_rec(const SceneK& S, const SceneD& D, int p, const float x[3], float4 r[3])
 {
     float m = S.m_uniform ? S.m0 : D.m[p];
@@ -262,9 +264,9 @@ DEV void make_rec(const SceneK& S, const SceneD& D, int p, const float x[3], flo
     int c[3];
     slot_cell(S, D.pcell[p], c[0], c[1], c[2]); // reference cell, packed 16 + 16 bits and 16 bits
     r[0] = make_float4(__int_as_float(p), __uint_as_float(D.code[p]), __int_as_float(c[0] | (c[1] << 16)),
-                       0.5f * S.s_R * cbrtf(V0));
+                       __int_as_float(c[2]));
     r[1] = make_float4(x[0], x[1], x[2], m);
-    r[2] = make_float4(D.v[p], D.v[S.N + p], D.v[2 * S.N + p], __int_as_float(c[2]));
+    r[2] = make_float4(D.v[p], D.v[S.N + p], D.v[2 * S.N + p], 0.5f * S.s_R * cbrtf(V0));
 }
 
 // Bins the candidates of every brick: each candidate writes its record at its
@@ -382,17 +384,17 @@ DEV PState pstate_of(const float4 r[3])
     s.v[0] = r[2].x;
     s.v[1] = r[2].y;
     s.v[2] = r[2].z;
-    s.R = r[0].w;
+    s.R = r[2].w;
     return s;
 }
 
-// reference cell of a record (x | y << 16 in the first vector, z in the third)
-DEV void rec_cell(const float4 r[3], int c[3])
+// reference cell of a record (x | y << 16 and z in its first vector)
+DEV void rec_cell(const float4& r0, int c[3])
 {
-    const int xy = __float_as_int(r[0].z);
+    const int xy = __float_as_int(r0.z);
     c[0] = xy & 0xFFFF;
     c[1] = (xy >> 16) & 0xFFFF;
-    c[2] = __float_as_int(r[2].w);
+    c[2] = __float_as_int(r0.w);
 }
 
 // Pair impulse on the owner o (lower index) from r, Eqs. 10-12; u is the owner's
@@ -591,27 +593,32 @@ DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
             const uint32_t kp = ckey(S, __float_as_uint(rp[0].y));
             const PState sp = pstate_of(rp);
             int cp[3];
-            rec_cell(rp, cp);
+            rec_cell(rp[0], cp);
             int* ql_new = D.ph_q + ((long long)hnew * N + p) * TL_PCAP;
             float* ul_new = D.ph_u + ((long long)hnew * N + p) * TL_PCAP * 3;
-            auto visit = [&](const float4 rec[3], int d) {
-                const int q = __float_as_int(rec[0].x);
+            // entry src of bin d, its first two vectors r0, r1 already loaded
+            auto visit = [&](const float4* src, const float4& r0, const float4& r1, int d) {
+                const int q = __float_as_int(r0.x);
                 if (q == p) return;
                 {
-                    const float ex = sp.x[0] - rec[1].x, ey = sp.x[1] - rec[1].y, ez = sp.x[2] - rec[1].z;
+                    const float ex = sp.x[0] - r1.x, ey = sp.x[1] - r1.y, ez = sp.x[2] - r1.z;
                     if (ex * ex + ey * ey + ez * ez >= reach2) return;
                 }
-                uint32_t kq = ckey(S, __float_as_uint(rec[0].y));
+                uint32_t kq = ckey(S, __float_as_uint(r0.y));
                 int cq[3];
-                rec_cell(rec, cq);
+                rec_cell(r0, cq);
                 bool near = abs(cp[0] - cq[0]) <= 1 && abs(cp[1] - cq[1]) <= 1 && abs(cp[2] - cq[2]) <= 1;
                 if (near && !cconflict(kp, kq)) return; // reading R17 exclusion
+                {
+                    const float xq[3] = {r1.x, r1.y, r1.z};
+                    int bz[3];
+                    bin_of(xq, inv_h, bz);
+                    // hash collision: the entry's own bin is not the probed one
+                    if (bz[0] != bq[0] + d % 3 - 1 || bz[1] != bq[1] + (d / 3) % 3 - 1 || bz[2] != bq[2] + d / 9 - 1)
+                        return;
+                }
+                const float4 rec[3] = {r0, r1, src[2]};
                 PState sq = pstate_of(rec);
-                int bz[3];
-                bin_of(sq.x, inv_h, bz);
-                // hash collision: the entry's own bin is not the probed one
-                if (bz[0] != bq[0] + d % 3 - 1 || bz[1] != bq[1] + (d / 3) % 3 - 1 || bz[2] != bq[2] + d / 9 - 1)
-                    return;
                 const bool own = p < q;
                 // the pair's spring of the last substep
                 float u[3] = {0.0f, 0.0f, 0.0f};
@@ -646,10 +653,9 @@ DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
                 const bool two = i2 < nl;
                 const float4* s1 = D.crec + (long long)s_ids[sub][i] * 3;
                 const float4* s2 = D.crec + (long long)s_ids[sub][two ? i2 : i] * 3;
-                float4 r1[3] = {s1[0], s1[1], s1[2]};
-                float4 r2[3] = {s2[0], s2[1], s2[2]};
-                visit(r1, s_bin[sub][i]);
-                if (two) visit(r2, s_bin[sub][i2]);
+                const float4 a0 = s1[0], a1 = s1[1], b0 = s2[0], b1 = s2[1];
+                visit(s1, a0, a1, s_bin[sub][i]);
+                if (two) visit(s2, b0, b1, s_bin[sub][i2]);
             }
             // entries beyond the list, then overflow lists (rare), by the bin's lane
 #pragma unroll
@@ -664,8 +670,7 @@ DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
                     for (int k = 0; k < TL_BCAP; k++) {
                         if (k >= c || pos[j] + k < TL_PLIST) continue;
                         const float4* src = D.crec + (long long)e[k] * 3;
-                        float4 rec[3] = {src[0], src[1], src[2]};
-                        visit(rec, d);
+                        visit(src, src[0], src[1], d);
                     }
                 }
                 if (cntq[j] > TL_BCAP) {
@@ -680,8 +685,7 @@ DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
                                 if (q > last && q < best) best = q;
                             if (best == INT_MAX) break;
                             const float4* src = D.crec + (long long)best * 3;
-                            float4 rec[3] = {src[0], src[1], src[2]};
-                            visit(rec, d);
+                            visit(src, src[0], src[1], d);
                             last = best;
                         }
                     }

@@ -89,6 +89,7 @@ def lib():
         L.tlmpm_get_status.argtypes = [vp, C.POINTER(C.c_int32)]
         L.tlmpm_slot_stats.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
         L.tlmpm_contact_stats.argtypes = [vp, C.POINTER(C.c_double)]
+        L.tlmpm_slot_histogram.argtypes = [vp, C.POINTER(C.c_int64)]
         dp = C.POINTER(C.c_double)
         L.tlmpm_rigid_step.argtypes = [C.POINTER(RigidBodyC), dp, dp, C.c_double]
         L.tlmpm_rigid_tool.argtypes = [C.POINTER(RigidBodyC), C.POINTER(Blade), C.c_uint32, C.POINTER(Tool)]
@@ -112,7 +113,7 @@ def lib():
         L.tlmpm_get_tuning.argtypes = [C.POINTER(Tuning)]
         L.tlmpm_last_error.restype = C.c_char_p
         for f in ("tlmpm_scene_footprint", "tlmpm_create_scene", "tlmpm_destroy_scene", "tlmpm_assign_labels",
-                  "tlmpm_step", "tlmpm_read_state", "tlmpm_write_state", "tlmpm_get_status", "tlmpm_slot_stats", "tlmpm_contact_stats", "tlmpm_rigid_step", "tlmpm_rigid_tool",
+                  "tlmpm_step", "tlmpm_read_state", "tlmpm_write_state", "tlmpm_get_status", "tlmpm_slot_stats", "tlmpm_slot_histogram", "tlmpm_contact_stats", "tlmpm_rigid_step", "tlmpm_rigid_tool",
                   "tlmpm_profile_enable", "tlmpm_profile_read", "tlmpm_batch_footprint", "tlmpm_batch_scene_bytes",
                   "tlmpm_surface_footprint", "tlmpm_surface_build", "tlmpm_surface_read",
                   "tlmpm_batch_create", "tlmpm_batch_create_static",
@@ -445,6 +446,12 @@ class Scene:
         mx = C.c_int32()
         _check(lib().tlmpm_slot_stats(self.h, C.byref(tot), C.byref(mx)))
         return tot.value, mx.value
+
+    def slot_histogram(self):
+        """Nodes by number of logical-grid slots: list h, h[c] nodes with c slots."""
+        h = (C.c_int64 * 17)()
+        _check(lib().tlmpm_slot_histogram(self.h, h))
+        return [int(x) for x in h]
 
     def contact_stats(self):
         """Material-contact search of the last substep: candidates, buckets,

@@ -329,7 +329,7 @@ def batch_scene(seed, index, n_target, dx=0.0025, steps=1000, dt=1e-4):
     return sc
 
 
-def _slicing_blades(rng, ext, n_cuts):
+def _slicing_blades(rng, ext, n_cuts, dx):
     """Sequential slicing (the paper's scenes with successive cuts): one knife
     orientation per request (d and n drawn as in _random_blade), cut k in the plane
     of normal n through the body's centre moved by o_k along n, o_k at the k-th of
@@ -337,12 +337,16 @@ def _slicing_blades(rng, ext, n_cuts):
     extent, so that the plane's point on the centre line lies in the body), each
     jittered by up to +-20 % of a part; the cuts proceed from one side; each has its
     own speed U[0.05, 0.3] m/s and starts where its line through that point along -d
-    leaves the bounding box.  Returns [(start, n, d, speed)] in cut order."""
+    leaves the bounding box.  Slices are at least 4 dx thick before the jitter: a
+    body too small for n_cuts such slices gets fewer cuts (at least one), since
+    thinner slices put every particle in the label bands of several cuts at once.  Returns [(start, n, d, speed)] in
+    cut order."""
     d = _random_dir_down(rng)
     a = rng.normal(size=3)
     n = a - np.dot(a, d) * d
     n /= np.linalg.norm(n)
     r = 0.5 * float(np.min(ext))
+    n_cuts = max(1, min(n_cuts, int(2.0 * r / (4.0 * dx)) - 1))
     part = 2.0 * r / (n_cuts + 1)
     centre = 0.5 * np.asarray(ext, np.float64)
     out = []
@@ -362,8 +366,8 @@ def served_request(seed, index, n_target, horizon_steps, tick, dx=0.0025, dt=1e-
     rng = np.random.default_rng([seed, index])
     shape, ext, X, E, params = _random_scene(rng, n_target, dx, dt)
     diag = float(np.linalg.norm(ext))
-    n_cuts = int(rng.integers(1, 5))
-    specs = _slicing_blades(rng, ext, n_cuts)
+    specs = _slicing_blades(rng, ext, int(rng.integers(1, 5)), dx)
+    n_cuts = len(specs)
     n_ticks = max(1, horizon_steps // tick)
     bounds = [tick * ((n_ticks * k) // n_cuts) for k in range(n_cuts + 1)]
 
@@ -376,6 +380,18 @@ def served_request(seed, index, n_target, horizon_steps, tick, dx=0.0025, dt=1e-
     sc = _finish(f"request-{index}-{shape}", params, X, 1000.0, E, rng, tick * n_ticks, tools_at)
     sc["shape"] = shape
     return sc
+
+
+def crop(scene, xr, yr):
+    """The particles of `scene` with x in xr and y in yr, as a scene of their own
+    (same grid, parameters and tools)."""
+    X = scene["X"]
+    keep = (X[:, 0] >= xr[0]) & (X[:, 0] <= xr[1]) & (X[:, 1] >= yr[0]) & (X[:, 1] <= yr[1])
+    out = dict(scene, X=np.ascontiguousarray(X[keep]), vol0=scene["vol0"][keep], mass=scene["mass"][keep],
+               E=scene["E"][keep], name=scene["name"] + "-sample")
+    if scene.get("v0") is not None:
+        out["v0"] = scene["v0"][keep]
+    return out
 
 
 def served(seed=5, n_requests=500, rate=40.0, n_range=(10000, 1000000), horizon_s=(0.5, 2.0), tick=100,

@@ -5,12 +5,15 @@ served and large workloads, through the C ABI.
   simultaneous blades each with its own cut, slot capacity 16, floor and material
   contact) over 20 substeps, each run alone in lockstep with the oracle; the same
   scenes stepped as one batch end bitwise equal to the runs alone.
-- One request of the served workload (one to four sequential cuts) served by the
+- One request of the served workload (two sequential slices) served by the
   continuous-batching loop, against the oracle fed the same tool poses.
 - The large box at dx = 2.5 mm (3.07M particles, about 6,600 active bricks: more
   than 4096, so unsplit bricks in several rounds of workgroups, the second stream,
   separate label / rigid / pair launches and large hash tables) over 5 substeps
   with three blades cutting.
+- The large box at its own resolution (dx = 1.5 mm, dt = 3e-5, per-particle E) on
+  the region x, y in [0.07, 0.13] m where cuts 0 and 2 cross (851,231 particles,
+  the sample the CPU baseline times) over its first 20 substeps.
 
 Tolerances: one substep within 1e-5 (u, v, H each relative to its own largest
 value or one substep's increment scale, tests/harness.py), positions after the rollout within 1e-3 of the largest displacement, and
@@ -122,7 +125,7 @@ def test_batch_scenes_match_oracle(tl):
 def test_served_request_matches_oracle(tl):
     from paper_2609_27342_amd import serve
     tick, horizon = 20, 80
-    req = dict(index=3, arrival=0.0, n_target=20000, horizon=horizon, seed=17, tick=tick)
+    req = dict(index=0, arrival=0.0, n_target=20000, horizon=horizon, seed=17, tick=tick)
     build = lambda r: W.served_request(r["seed"], r["index"], r["n_target"], r["horizon"], r["tick"])
     sd = build(req)
     cuts = {t["blade"]["cut_index"] for j in range(0, horizon, tick) for t in sd["tools_at"](j)}
@@ -157,5 +160,36 @@ def test_large_scene_over_4096_bricks_matches_oracle(tl):
     assert mx >= 3  # nodes where crossing cuts meet
     e = _report("large", s, a, b, watch)
     assert (b["digits"] != 0).sum() > 10000
+    assert not watch.bad, watch.bad[:5]
+    assert e < 1e-3
+
+
+@pytest.mark.timeout(900)
+def test_large_resolution_region_20_substeps_matches_oracle(tl):
+    s = W.crop(W.large(), (0.07, 0.13), (0.07, 0.13))
+    n = s["X"].shape[0]
+    _print_case("large region dx=1.5mm vs oracle", n=n, steps=20)
+    calls = [(s["tools_at"](j), 1) for j in range(20)]
+    a, b, watch, g = _lockstep(tl, s, calls)
+    assert g.status() == 0
+    e = _report("large region", s, a, b, watch)
+    assert (b["digits"] != 0).sum() > 10000
+    assert not watch.bad, watch.bad[:5]
+    assert e < 1e-3
+
+
+@pytest.mark.timeout(900)
+def test_medium_200_substeps_matches_oracle(tl):
+    """The medium tube over 200 substeps with the first blade inside the tube from
+    the first substep (z = 0.034 m: labels, blade contact and material contact in
+    every substep), independent rollouts in lockstep."""
+    s = W.medium(z_start=0.034, steps=200)
+    n = s["X"].shape[0]
+    _print_case("medium 200 substeps vs oracle", n=n)
+    calls = [(s["tools_at"](j), 1) for j in range(200)]
+    a, b, watch, g = _lockstep(tl, s, calls)
+    assert g.status() == 0
+    e = _report("medium 200", s, a, b, watch)
+    assert (b["digits"] != 0).sum() > 500
     assert not watch.bad, watch.bad[:5]
     assert e < 1e-3
