@@ -116,8 +116,8 @@ def kernel_source_hash():
     measured hardware traffic is stored in profiles/traffic.json)."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("tlmpm_common.h", "tlmpm_device.h", "tlmpm_band.h", "tlmpm_kernels.hip", "tlmpm_contact.hip",
-              "tlmpm_quad.hip", "tlmpm_surface.hip"):
+    for f in ("tlmpm_common.h", "tlmpm_device.h", "tlmpm_band.h", "tlmpm_reach.h", "tlmpm_kernels.hip",
+              "tlmpm_contact.hip", "tlmpm_quad.hip", "tlmpm_surface.hip"):
         with open(os.path.join(ROOT, "paper_2609_27342_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

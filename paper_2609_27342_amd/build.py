@@ -24,6 +24,7 @@ def build(force=True, verbose=False):
     newest = max(os.path.getmtime(p) for p in SOURCES + [os.path.join(CSRC, "tlmpm_common.h"),
                                                           os.path.join(CSRC, "tlmpm_device.h"),
                                                           os.path.join(CSRC, "tlmpm_band.h"),
+                                                          os.path.join(CSRC, "tlmpm_reach.h"),
                                                           os.path.join(HERE, "..", "include", "tlmpm.h")])
     if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= newest:
         return LIB

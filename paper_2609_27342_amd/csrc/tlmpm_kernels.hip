@@ -30,6 +30,7 @@
 
 #include "tlmpm_common.h"
 #include "tlmpm_band.h"
+#include "tlmpm_reach.h"
 #include "tlmpm_device.h"
 
 
@@ -570,8 +571,6 @@ DEV void rigid_one(const SceneK& S, const SceneD& D, const DevTool* T, int slot,
     }
 }
 
-// Conservative test: can a particle of a brick with AABB [lo, hi] and speed bound
-// vmax touch the rectangle of tool T (or the floor) during this substep?
 // Current AABB and speed bound of an active brick: the box written by its G2P, joined
 // with that of its second workgroup when the brick was split
 DEV void brick_aabb(const SceneK& S, const SceneD& D, int bi, int brick, float bb[7])
@@ -593,29 +592,6 @@ DEV void brick_aabb(const SceneK& S, const SceneD& D, int bi, int brick, float b
     const bool join = D.xg[0] != 0 && D.xrs[bi] != 0;
 #pragma unroll
     for (int q = 0; q < 7; q++) bb[q] = !join ? ra[q] : (q < 3 ? fminf(ra[q], rx[q]) : fmaxf(ra[q], rx[q]));
-}
-
-DEV bool brick_near_tool(const SceneK& S, const float* bb, const DevTool* T, float Rmax, double jdt)
-{
-    float vmax = bb[6];
-    if (!T) return bb[2] - Rmax - S.dt * vmax - 1e-6f <= S.floor_z;
-    const DevBlade& B = T->b;
-    double adv = (T->flags & TL_TOOL_ADVANCE) ? jdt : 0.0;
-    float margin = Rmax + S.dt * (vmax + fabsf((float)T->vB[0]) + fabsf((float)T->vB[1]) + fabsf((float)T->vB[2])) +
-                   1e-5f;
-    float lo[3] = {1e30f, 1e30f, 1e30f}, hi[3] = {-1e30f, -1e30f, -1e30f};
-    for (int c = 0; c < 4; c++) {
-        float al = (c & 1) ? (float)B.half_len : -(float)B.half_len;
-        float be = (c & 2) ? (float)B.b_back : 0.0f;
-        for (int a = 0; a < 3; a++) {
-            float pt = (float)(B.xe[a] + adv * B.ve[a]) + al * (float)B.e[a] - be * (float)B.d[a];
-            lo[a] = fminf(lo[a], pt);
-            hi[a] = fmaxf(hi[a], pt);
-        }
-    }
-    for (int a = 0; a < 3; a++)
-        if (bb[a] > hi[a] + margin || bb[3 + a] < lo[a] - margin) return false;
-    return true;
 }
 
 // --------------------------------------------------------------------------- K_A
@@ -653,9 +629,9 @@ DEV void rigid_body(const SceneK& S, const SceneD& D, int bi)
         brick_aabb(S, D, bi, brick, bb);
         int nr = 0;
         if (tid == 0)
-            nr = S.floor_on ? brick_near_tool(S, bb, nullptr, S.Rmax, jdt) : 0;
+            nr = S.floor_on ? brick_near_floor(bb, S.floor_z, S.Rmax, S.dt) : 0;
         else if (tid - 1 < n_tools)
-            nr = (D.tools[tid - 1].flags & TL_TOOL_CONTACT) ? brick_near_tool(S, bb, &D.tools[tid - 1], S.Rmax, jdt)
+            nr = (D.tools[tid - 1].flags & TL_TOOL_CONTACT) ? brick_near_tool(bb, D.tools[tid - 1], S.Rmax, S.dt, jdt)
                                                              : 0;
         s_near[tid] = nr;
     }
