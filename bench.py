@@ -454,7 +454,9 @@ def contact_of(gs):
     c = [g.contact_stats() for g in gs]
     cand = sum(x["candidates"] for x in c)
     pairs = sum(x["pairs"] for x in c)
-    return {"candidates": cand, "pairs": pairs, "pair_search_alg_bytes": 40 * cand + 24 * pairs}
+    skipped = sum(x["skipped"] for x in c)
+    return {"candidates": cand, "pairs": pairs, "searches_skipped": skipped,
+            "pair_search_alg_bytes": 40 * cand + 24 * pairs}
 
 
 def bench_scene(args, name, scene, K, Wm):

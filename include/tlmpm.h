@@ -227,8 +227,10 @@ tlmpm_status tlmpm_slot_histogram(tlmpm_scene* scene, int64_t hist[17]);
  * out[3] buckets holding more candidates than their inline records, out[4] the
  * largest bucket count, out[5] the bin edge in metres, out[6] the pairs in contact
  * (each contact is kept by both partners, at most 16 per particle; half the sum of
- * the particles' counts).  All zero without material contact.  Synchronises. */
-tlmpm_status tlmpm_contact_stats(tlmpm_scene* scene, double out[7]);
+ * the particles' counts), out[7] the candidates whose search the binning skipped
+ * (no partner possible: every particle within the bin edge is a reference neighbour
+ * with a compatible code).  All zero without material contact.  Synchronises. */
+tlmpm_status tlmpm_contact_stats(tlmpm_scene* scene, double out[8]);
 
 /* Launch-shape settings, process-wide.  A scene takes them when it is created
  * (and tlmpm_batch_scene_bytes reads them), so set them before creating the scenes

@@ -237,7 +237,8 @@ Dims dims_of(const tlmpm_scene_desc* d)
 struct Offsets {
     size_t X, u, v, H, code, code_prev, D, perm, E, m, V0, cell_start, active, cnt0, cnt1, sc0, sc1, p2g, rs, p2g_x,
         rs_x, xp2g, xrs, aabb_x, xlist, xin, xg, hist,
-        aabb, wpart, Fdot, Gp, wacc, Jmat, Jrig, brig, bmixed, ccode, ckeys, gmeta, gperm, bround, tools, tinfo, ctr, bact, status, dirty, bdirty, pcell, cand_idx, coff, cmask, cstatic, bcand, hbin, hmax, bcount, bids, crec, htab, hnext, ph_n, ph_q, ph_u,
+        aabb, wpart, Fdot, Gp, wacc, Jmat, Jrig, brig, bmixed, ccode, ckeys, gmeta, gperm, bround, tools, tinfo, ctr, bact, status, dirty, bdirty, pcell, cand_idx, coff, cmask, cstatic, bcand, hbin, hmax, uanc, uanc_x, uref, bor, umm,
+        bcount, bids, crec, htab, hnext, ph_n, ph_q, ph_u,
         qcode, qacc, qrs, qnodes, qround, qmap, total;
     uint32_t hmask;
 };
@@ -372,6 +373,11 @@ Offsets plan(const tlmpm_scene_desc* d, long long n_active)
         o.coff = L.take(((size_t)n_active + 1) * 4);
         o.hbin = L.take(4);
         o.hmax = L.take(TL_HSLOTS * TL_HSTRIDE * 4);
+        o.uanc = L.take((size_t)g.n_bricks * 4 * f);
+        o.uanc_x = L.take((size_t)g.n_bricks * 4 * f);
+        o.uref = L.take((size_t)g.n_bricks * 4 * f);
+        o.bor = L.take((size_t)g.n_bricks * 4);
+        o.umm = L.take((6 * TL_USLOTS + 1) * 4);
         size_t buckets = 4096;
         while (buckets < N / 2) buckets <<= 1;
         o.hmask = (uint32_t)(buckets - 1);
@@ -584,6 +590,7 @@ extern "C" tlmpm_status tlmpm_create_scene(const tlmpm_scene_desc* d, void* ws, 
     const tlmpm_tuning tun = tuning_now();
     K.pair_blocks = pair_blocks_of(N, tun);
     K.stencil = d->stencil;
+    K.pair_skip = (d->material_contact && d->stencil == 0) ? 1 : 0;
     // workgroups for the later rounds of bricks with a mixed cell: a quarter of the
     // bricks, at most 256 (with more mixed bricks no brick is split).  Only scenes of
     // 512 to 4096 active bricks split: their launches are about one round of
@@ -655,6 +662,11 @@ extern "C" tlmpm_status tlmpm_create_scene(const tlmpm_scene_desc* d, void* ws, 
         D.coff = (int*)(base + o.coff);
         D.hbin = (float*)(base + o.hbin);
         D.hmax = (int*)(base + o.hmax);
+        D.uanc = (float*)(base + o.uanc);
+        D.uanc_x = (float*)(base + o.uanc_x);
+        D.uref = (float*)(base + o.uref);
+        D.bor = (uint32_t*)(base + o.bor);
+        D.umm = (uint32_t*)(base + o.umm);
         D.hmask = o.hmask;
         D.bcount = (int*)(base + o.bcount);
         D.bids = (int*)(base + o.bids);
@@ -1419,6 +1431,7 @@ extern "C" tlmpm_status tlmpm_write_state(tlmpm_scene* sc, uint32_t mask, const 
     }
     // speed bounds of the new velocities replace those gathered by the last G2P
     if (sc->K.material_contact) HIPCHK(tl_launch_fill_i32(sc->D.hmax, TL_HSLOTS * TL_HSTRIDE, 0, sc->st));
+    if (sc->K.pair_skip) HIPCHK(tl_launch_fill_i32((int*)sc->D.umm, 6 * TL_USLOTS + 1, 0, sc->st));
     HIPCHK(tl_launch_aabb(&L));
     HIPCHK(hipStreamSynchronize(sc->st));
     return TLMPM_OK;
@@ -1453,11 +1466,11 @@ extern "C" tlmpm_status tlmpm_slot_histogram(tlmpm_scene* sc, int64_t hist[TL_SC
     return TLMPM_OK;
 }
 
-extern "C" tlmpm_status tlmpm_contact_stats(tlmpm_scene* sc, double out[7])
+extern "C" tlmpm_status tlmpm_contact_stats(tlmpm_scene* sc, double out[8])
 {
     if (!out) return fail(TLMPM_E_INVALID, "null output");
     if (tlmpm_status r = refuse_batched(sc)) return r;
-    for (int i = 0; i < 7; i++) out[i] = 0.0;
+    for (int i = 0; i < 8; i++) out[i] = 0.0;
     if (!sc->K.material_contact) return TLMPM_OK;
     const size_t nb = (size_t)sc->D.hmask + 1;
     std::vector<int> cnt(nb);
@@ -1495,6 +1508,21 @@ extern "C" tlmpm_status tlmpm_contact_stats(tlmpm_scene* sc, double out[7])
     for (int h : hdr)
         if ((h >> 8) == stamp - 1) ends += h & 0xFF;
     out[6] = 0.5 * (double)ends;
+    // candidates the binning marked as without a possible partner (first vector of
+    // each record: the flag beside the cell's z)
+    if (total > 0) {
+        std::vector<float4> r0((size_t)total);
+        HIPCHK(hipMemcpy2DAsync(r0.data(), sizeof(float4), sc->D.crec, 3 * sizeof(float4), sizeof(float4),
+                                (size_t)total, hipMemcpyDeviceToHost, sc->st));
+        HIPCHK(hipStreamSynchronize(sc->st));
+        long long skipped = 0;
+        for (const float4& r : r0) {
+            int w;
+            std::memcpy(&w, &r.w, 4);
+            skipped += (w >> 30) & 1;
+        }
+        out[7] = (double)skipped;
+    }
     return TLMPM_OK;
 }
 

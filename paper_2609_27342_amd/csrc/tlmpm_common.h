@@ -43,6 +43,7 @@
 #define TL_PCAP 16             // persistent pair springs kept per particle (all its partners)
 #define TL_HSLOTS 64  // slots of the speed-bound maximum (spreads the atomics)
 #define TL_HSTRIDE 1  // ints between slots (consecutive: cheap to read in every binning block)
+#define TL_USLOTS 64  // slots of each displacement bound
 #ifndef TL_PLANES
 #define TL_PLANES 4            // lanes per candidate in the pair search (4 or 8)
 #endif
@@ -101,6 +102,8 @@ struct SceneK {
     int pair_blocks;  // blocks of the pair search (grid-stride over the candidates)
     int stencil;      // 0 trilinear (8 nodes), 1 quadratic B-spline (27 nodes)
     int xcap;         // workgroups for the later rounds of mixed bricks (used while xlist fits)
+    int pair_skip;    // the binning may mark candidates that provably have no contact partner
+                      // (material contact, trilinear stencil: its G2P keeps the displacement anchors)
     double dt_d;
 };
 
@@ -164,6 +167,15 @@ struct SceneD {
     int* coff;          // [active bricks + 1] first global candidate index of each active brick
     float* hbin;        // bin edge (device scalar)
     int* hmax;          // [TL_HSLOTS] largest brick speed bounds for the next binning (float bits)
+    float* uanc;        // [bricks][4] displacement anchor a (3) and spread s of the brick's particles,
+                        // |u_p - a|_inf <= s after the last G2P (pair-search skip)
+    float* uanc_x;      // [bricks][4] the same for the later rounds of a split brick
+    float* uref;        // [bricks][4] centre of the box of the brick's reference positions (static)
+    uint32_t* bor;      // [bricks] OR of the side keys of the brick's particles
+    uint32_t* umm;      // [6][TL_USLOTS] scene bounds of the anchors of the bricks with candidates:
+                        // a + s per axis, then s - a (ordered float keys, maximum over the slots),
+                        // then [1] set when a brick gained its first candidates after its anchor
+                        // was taken (no skipping in that substep); cleared by the pair pass
     uint32_t hmask;     // buckets - 1 (power of two)
     int* bcount;        // [2][buckets] entries of each bucket (buffer = stamp parity; the
                         // pair pass clears the other buffer for the next substep)

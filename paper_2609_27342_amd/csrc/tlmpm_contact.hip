@@ -24,6 +24,7 @@
 
 #include "tlmpm_common.h"
 #include "tlmpm_device.h"
+#include "tlmpm_reach.h"
 
 DEV uint32_t ckey(const SceneK& S, uint32_t code) { return S.single_field ? 0u : (code & TL_CODE_MASK); }
 
@@ -190,7 +191,11 @@ DEV void cand_brick(const SceneK& S, const SceneD& D, int bi, int brick, int bx,
         base += tot;
         __syncthreads();
     }
-    if (threadIdx.x == 0) D.bcand[bi] = base;
+    if (threadIdx.x == 0) {
+        // a brick with its first candidates has no displacement anchor from the last G2P
+        if (S.pair_skip && base > 0 && D.bcand[bi] == 0) atomicOr(D.umm + 6 * TL_USLOTS, 1u);
+        D.bcand[bi] = base;
+    }
 }
 
 DEV void cand_body(const SceneK& S, const SceneD& D, int bi, int force)
@@ -269,6 +274,77 @@ DEV void make_rec(const SceneK& S, const SceneD& D, int p, const float x[3], flo
     r[2] = make_float4(D.v[p], D.v[S.N + p], D.v[2 * S.N + p], 0.5f * S.s_R * cbrtf(V0));
 }
 
+// Flag in the fourth word of a candidate record (beside the cell's z, 16 bits): the
+// binning found that the candidate has no contact partner this substep, and the pair
+// pass writes its zero impulse without searching.
+#define TL_REC_SKIP (1 << 30)
+
+// Can a candidate of brick `brick` (active index bi) have a contact partner this
+// substep?  Run by the 64 lanes of the first wave; *skip = 1 when no candidate of the
+// brick can have one except through a side-key conflict with *orn, the OR of the keys
+// of the bricks with candidates among the 27 around it (this one included).  Only
+// candidates are partners, so only bricks with candidates enter the bounds; their
+// anchors were taken by the last G2P unless a brick gained its first candidates
+// since (then nothing is skipped in this substep).  The bounds (pair_skip_bounds_ok):
+// the scene's displacement range per axis from the anchors' slot maxima (u in
+// [min (a - s), max (a + s)]), and for the 27 bricks |u_p - u_q| <= |a_b - a_b'| +
+// s_b + s_b' (|u - a| <= s within a brick).
+DEV void pair_skip_test(const SceneK& S, const SceneD& D, int bi, int brick, float hb, int* skip, uint32_t* orn)
+{
+    const int l = threadIdx.x;
+    float um[6];
+    for (int f = 0; f < 6; f++) {
+        uint32_t k = 0u;
+        for (int q = l; q < TL_USLOTS; q += 64) {
+            const uint32_t t = D.umm[f * TL_USLOTS + q];
+            k = t > k ? t : k;
+        }
+        for (int o = 32; o >= 1; o >>= 1) {
+            const uint32_t t = (uint32_t)__shfl_xor((int)k, o, 64);
+            k = t > k ? t : k;
+        }
+        um[f] = fkey_value(k);
+    }
+    const int bx = brick % S.cbx, by = (brick / S.cbx) % S.cby, bz = brick / (S.cbx * S.cby);
+    float a[3] = {0.0f, 0.0f, 0.0f}, sp = -1.0f;
+    uint32_t orr = 0u;
+    if (l < 27) {
+        const int x = bx + l % 3 - 1, y = by + (l / 3) % 3 - 1, z = bz + l / 9 - 1;
+        if (x >= 0 && y >= 0 && z >= 0 && x < S.cbx && y < S.cby && z < S.cbz) {
+            const long long nb = ((long long)z * S.cby + y) * S.cbx + x;
+            const int nbi = D.bact[nb];
+            // only bricks with candidates hold partners (and keep anchors)
+            if (nbi >= 0 && D.bcand[nbi] > 0) {
+                brick_anchor(S, D, nbi, (int)nb, a, sp);
+                orr = D.bor[nb];
+            }
+        }
+    }
+    float a0[3];
+    for (int k = 0; k < 3; k++) a0[k] = __shfl(a[k], 13, 64);
+    const float s0 = __shfl(sp, 13, 64);
+    float dk[3];
+    for (int k = 0; k < 3; k++) dk[k] = sp >= 0.0f ? fabsf(a[k] - a0[k]) + sp : 0.0f;
+    for (int o = 32; o >= 1; o >>= 1) {
+        for (int k = 0; k < 3; k++) dk[k] = fmaxf(dk[k], __shfl_xor(dk[k], o, 64));
+        orr |= (uint32_t)__shfl_xor((int)orr, o, 64);
+    }
+    if (l == 0) {
+        float bb[7];
+        brick_aabb(S, D, bi, brick, bb);
+        float M = 0.0f;
+        for (int k = 0; k < 6; k++) M = fmaxf(M, fabsf(bb[k]));
+        float U[3], Dk[3];
+        for (int k = 0; k < 3; k++) {
+            U[k] = um[k] + um[3 + k];
+            Dk[k] = dk[k] + s0;
+        }
+        const bool fresh = D.umm[6 * TL_USLOTS] == 0u;
+        *skip = (fresh && s0 >= 0.0f && pair_skip_bounds_ok(U, Dk, hb, (float)S.dx, M)) ? 1 : 0;
+        *orn = orr;
+    }
+}
+
 // Bins the candidates of every brick: each candidate writes its record at its
 // global number g; slot = atomicAdd on the bucket count; the first TL_BCAP numbers
 // are kept in arrival order, later candidates go to a lock-free overflow list
@@ -305,6 +381,14 @@ DEV void bin_insert_body(const SceneK& S, const SceneD& D, int bi, int self_scan
         g0 = D.coff[bi];
     }
     if (!nc) return;
+    __shared__ int s_skip;
+    __shared__ uint32_t s_orn;
+    if (S.pair_skip) {
+        if (threadIdx.x < 64) pair_skip_test(S, D, bi, brick, hb, &s_skip, &s_orn);
+        __syncthreads();
+    }
+    const bool may_skip = S.pair_skip && s_skip;
+    const uint32_t orn = S.pair_skip ? s_orn : 0u;
     const float inv_h = 1.0f / hb;
     const int beg = D.cell_start[(long long)brick * TL_CELLS];
     int* bcount = D.bcount + (gen & 1u) * ((long long)D.hmask + 1); // this substep's counts
@@ -315,6 +399,8 @@ DEV void bin_insert_body(const SceneK& S, const SceneD& D, int bi, int self_scan
         cur_pos(S, D, p, x);
         float4 r[3];
         make_rec(S, D, p, x, r);
+        if (may_skip && !cconflict(ckey(S, __float_as_uint(r[0].y)), orn))
+            r[0].w = __int_as_float(__float_as_int(r[0].w) | TL_REC_SKIP);
         float4* dst = D.crec + (long long)g * 3;
         dst[0] = r[0];
         dst[1] = r[1];
@@ -394,7 +480,7 @@ DEV void rec_cell(const float4& r0, int c[3])
     const int xy = __float_as_int(r0.z);
     c[0] = xy & 0xFFFF;
     c[1] = (xy >> 16) & 0xFFFF;
-    c[2] = __float_as_int(r0.w);
+    c[2] = __float_as_int(r0.w) & 0xFFFF;
 }
 
 // Pair impulse on the owner o (lower index) from r, Eqs. 10-12; u is the owner's
@@ -467,9 +553,13 @@ DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
     const int stamp = D.ctr[0];
     const unsigned gen = (unsigned)stamp;
     const int hnew = stamp & 1, hold = hnew ^ 1;
-    // the binning has read the speed bounds: G2P gathers them anew for the next
-    // substep
-    if (bi == 0 && threadIdx.x < TL_HSLOTS) D.hmax[threadIdx.x * TL_HSTRIDE] = 0;
+    // the binning has read the speed bounds and the displacement bounds: G2P gathers
+    // them anew for the next substep
+    if (bi == 0) {
+        if (threadIdx.x < TL_HSLOTS) D.hmax[threadIdx.x * TL_HSTRIDE] = 0;
+        if (S.pair_skip)
+            for (int q = threadIdx.x; q <= 6 * TL_USLOTS; q += blockDim.x) D.umm[q] = 0u;
+    }
     // bucket counts: this substep's buffer, and the other one cleared for the next
     const long long nbk = (long long)D.hmask + 1;
     const int* bcount = D.bcount + (stamp & 1) * nbk;
@@ -505,6 +595,8 @@ DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
             rp[2] = src[2];
         }
         const int p = has ? __float_as_int(rp[0].x) : -1;
+        // a candidate the binning found without a possible partner: zero impulse, no springs
+        const bool look = has && !(__float_as_int(rp[0].w) & TL_REC_SKIP);
         // this lane's bins: l, l + TL_PLANES, ... of the 27 around the candidate
         int bq[3] = {0, 0, 0};
         if (has) {
@@ -534,11 +626,11 @@ DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
                 e2 += e * e;
             }
             hq[j] = bin_hash(bq[0] + o[0], bq[1] + o[1], bq[2] + o[2], D.hmask);
-            cntq[j] = (has && d < 27 && e2 < 0.999f * reach2) ? bcount[hq[j]] : 0;
+            cntq[j] = (look && d < 27 && e2 < 0.999f * reach2) ? bcount[hq[j]] : 0;
         }
         // the candidate's springs of the last substep, staged in LDS
         int nold = 0;
-        if (has) {
+        if (look) {
             const int hdr = D.ph_n[(long long)hold * N + p];
             if ((hdr >> 8) == stamp - 1) nold = min(hdr & 0xFF, TL_PCAP);
         }
@@ -589,7 +681,7 @@ DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
         }
         __syncthreads();
         float Jt[3] = {0.0f, 0.0f, 0.0f};
-        if (has) {
+        if (look) {
             const uint32_t kp = ckey(S, __float_as_uint(rp[0].y));
             const PState sp = pstate_of(rp);
             int cp[3];

@@ -24,6 +24,85 @@ DEV bool codes_conflict(uint32_t a, uint32_t b)
 
 DEV uint32_t slot_key(const SceneK& S, uint32_t code) { return S.single_field ? 0u : (code & TL_CODE_MASK); }
 
+// ------------------------------------------------------------ displacement anchors
+// Order-preserving map of a float to an unsigned key (larger float, larger key), so
+// that a maximum over floats of either sign is an integer atomicMax; key 0 lies below
+// the key of every float (the slots start at 0).
+DEV uint32_t fkey(float f)
+{
+    const uint32_t b = __float_as_uint(f);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+DEV float fkey_value(uint32_t k) { return __uint_as_float((k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k); }
+
+// Records the displacement anchor a and spread s of a brick (part 0) or of a split
+// brick's later rounds (part 1): |u_p - a|_inf <= s for all its particles.  The
+// scene bounds of a + s and s - a per axis go to the slot maxima of umm.
+DEV void put_anchor(const SceneD& D, int bi, int brick, int part, const float a[3], float s)
+{
+    float* o = (part ? D.uanc_x : D.uanc) + (long long)brick * 4;
+    o[0] = a[0];
+    o[1] = a[1];
+    o[2] = a[2];
+    o[3] = s;
+    uint32_t* mm = D.umm + (bi & (TL_USLOTS - 1));
+    for (int k = 0; k < 3; k++) {
+        atomicMax(mm + k * TL_USLOTS, fkey(a[k] + s));
+        atomicMax(mm + (3 + k) * TL_USLOTS, fkey(s - a[k]));
+    }
+}
+
+// Anchor of a G2P workgroup: the centre of a box record of the brick's particles
+// after the last G2P (box) minus the centre of the box of their reference positions,
+// the displacement of a rigid translation.  Any value serves (the spread is measured
+// against it); this one follows the motion.
+DEV void g2p_anchor(const SceneD& D, const float* box, int brick, float a[3])
+{
+    const float* rc = D.uref + (long long)brick * 4;
+    for (int k = 0; k < 3; k++) a[k] = 0.5f * (box[k] + box[3 + k]) - rc[k];
+}
+
+// Current AABB and speed bound of an active brick: the box written by its G2P, joined
+// with that of its second workgroup when the brick was split
+DEV void brick_aabb(const SceneK& S, const SceneD& D, int bi, int brick, float bb[7])
+{
+    const float* a = D.aabb + (long long)brick * 8;
+    if (S.xcap == 0) { // the scene never splits
+#pragma unroll
+        for (int q = 0; q < 7; q++) bb[q] = a[q];
+        return;
+    }
+    // all loads issued together, then the join
+    const float* x = D.aabb_x + (long long)brick * 8;
+    float ra[7], rx[7];
+#pragma unroll
+    for (int q = 0; q < 7; q++) {
+        ra[q] = a[q];
+        rx[q] = x[q];
+    }
+    const bool join = D.xg[0] != 0 && D.xrs[bi] != 0;
+#pragma unroll
+    for (int q = 0; q < 7; q++) bb[q] = !join ? ra[q] : (q < 3 ? fminf(ra[q], rx[q]) : fmaxf(ra[q], rx[q]));
+}
+
+// Anchor a and spread s of all particles of active brick bi (= brick): the record of
+// its last G2P, joined with that of the later rounds when that G2P split it.
+DEV void brick_anchor(const SceneK& S, const SceneD& D, int bi, int brick, float a[3], float& s)
+{
+    const float* r = D.uanc + (long long)brick * 4;
+    a[0] = r[0];
+    a[1] = r[1];
+    a[2] = r[2];
+    s = r[3];
+    if (S.xcap > 0 && D.xg[0] != 0 && D.xrs[bi] != 0) {
+        const float* x = D.uanc_x + (long long)brick * 4;
+        float t = 0.0f;
+        for (int k = 0; k < 3; k++) t = fmaxf(t, fabsf(x[k] - a[k]));
+        s = fmaxf(s, x[3] + t);
+    }
+}
+
 // Workgroup barrier that orders LDS only: global loads issued before it stay in
 // flight (a full __syncthreads() would also wait for them).
 DEV void lds_barrier()

@@ -571,29 +571,6 @@ DEV void rigid_one(const SceneK& S, const SceneD& D, const DevTool* T, int slot,
     }
 }
 
-// Current AABB and speed bound of an active brick: the box written by its G2P, joined
-// with that of its second workgroup when the brick was split
-DEV void brick_aabb(const SceneK& S, const SceneD& D, int bi, int brick, float bb[7])
-{
-    const float* a = D.aabb + (long long)brick * 8;
-    if (S.xcap == 0) { // the scene never splits
-#pragma unroll
-        for (int q = 0; q < 7; q++) bb[q] = a[q];
-        return;
-    }
-    // all loads issued together, then the join
-    const float* x = D.aabb_x + (long long)brick * 8;
-    float ra[7], rx[7];
-#pragma unroll
-    for (int q = 0; q < 7; q++) {
-        ra[q] = a[q];
-        rx[q] = x[q];
-    }
-    const bool join = D.xg[0] != 0 && D.xrs[bi] != 0;
-#pragma unroll
-    for (int q = 0; q < 7; q++) bb[q] = !join ? ra[q] : (q < 3 ? fminf(ra[q], rx[q]) : fmaxf(ra[q], rx[q]));
-}
-
 // --------------------------------------------------------------------------- K_A
 // P2G kernel (one brick per workgroup).  If f_pending: finalize the remapped
 // velocities of the previous substep's MUSL re-scatter on the box (tables rs),
@@ -999,7 +976,7 @@ DEV void g2p_body(const SceneK& S, const SceneD& D, int bi, int cur, int part)
     __shared__ int s_total;
     __shared__ int s_nb[27];
     __shared__ int s_rounds;
-    __shared__ float s_bb[8][7];
+    __shared__ float s_bb[8][8];
 
     const int nround = SPLIT ? D.bround[bi] : 0; // rounds of a brick with a mixed cell, else 0
     if (SPLIT && part == 1 && nround <= 1) return; // (split bricks as in the P2G)
@@ -1022,6 +999,15 @@ DEV void g2p_body(const SceneK& S, const SceneD& D, int bi, int cur, int part)
     const int tid = threadIdx.x;
     const long long N = S.N;
     const float dt = S.dt, beta = S.beta;
+    // displacement anchor of this workgroup's particles (pair-search skip), kept for
+    // bricks with contact candidates (only candidates can be partners): the centre of
+    // the brick's box after the last G2P minus the centre of its particles' reference
+    // box.  A split brick's second workgroup reads the first one's record, which that
+    // one may rewrite in this launch; either value is a valid anchor, since the spread
+    // is measured against the anchor taken.
+    const bool track = S.pair_skip && D.bcand[bi] > 0;
+    float ap[3] = {0.0f, 0.0f, 0.0f};
+    if (track) g2p_anchor(D, D.aabb + (long long)brick * 8, brick, ap);
 
     // ---- phase 1: cell index, box counts, round-0 particle loads
     Lane L = lane_of(D, brick);
@@ -1081,7 +1067,9 @@ DEV void g2p_body(const SceneK& S, const SceneD& D, int bi, int cur, int part)
     for (int q = tid; q < total * 4; q += TL_WG) s_acc[q] = 0.0f;
     lds_barrier();
     const int rounds = (split && part == 0) ? 1 : s_rounds;
-    float bb[7] = {1e30f, 1e30f, 1e30f, -1e30f, -1e30f, -1e30f, 0.0f};
+    // box of x^{n+1}, speed bound, and the largest |u^{n+1} - a| about the anchor a
+    // (for the pair-search skip)
+    float bb[8] = {1e30f, 1e30f, 1e30f, -1e30f, -1e30f, -1e30f, 0.0f, 0.0f};
     const float* gv = s_grid;
     const float* gdv = s_grid + TL_BOX_SLOTS * 3;
     for (int r = r0; r < rounds; r++) {
@@ -1121,6 +1109,7 @@ DEV void g2p_body(const SceneK& S, const SceneD& D, int bi, int cur, int part)
                 float xa = Xp[a] + un;
                 bb[a] = fminf(bb[a], xa);
                 bb[3 + a] = fmaxf(bb[3 + a], xa);
+                bb[7] = fmaxf(bb[7], fabsf(un - ap[a]));
             }
             bb[6] = fmaxf(bb[6], sqrtf(vn1[0] * vn1[0] + vn1[1] * vn1[1] + vn1[2] * vn1[2]));
             m = S.m_uniform ? S.m0 : D.m[p];
@@ -1142,7 +1131,9 @@ DEV void g2p_body(const SceneK& S, const SceneD& D, int bi, int cur, int part)
     // brick AABB of x^{n+1} and speed bound (used to skip distant contact work); a
     // split brick's second workgroup keeps the box of its particles apart
     // (brick_aabb joins the two)
-    for (int q = 0; q < 7; q++) {
+#pragma unroll
+    for (int q = 0; q < 8; q++) {
+        if (q == 7 && !track) break;
         float val = bb[q];
         auto mm = [&](float other) { val = (q < 3) ? fminf(val, other) : fmaxf(val, other); };
         mm(lane_xor<1>(val));
@@ -1160,6 +1151,10 @@ DEV void g2p_body(const SceneK& S, const SceneD& D, int bi, int cur, int part)
         // of non-negative floats is taken on their bit patterns (order-independent)
         if (tid == 6 && S.material_contact && val > 0.0f)
             atomicMax(D.hmax + (bi & (TL_HSLOTS - 1)) * TL_HSTRIDE, __float_as_int(val));
+    } else if (tid == 7 && track) {
+        float dv = s_bb[0][7];
+        for (int wv = 1; wv < 8; wv++) dv = fmaxf(dv, s_bb[wv][7]);
+        put_anchor(D, bi, brick, part, ap, dv);
     }
 }
 
@@ -1172,7 +1167,12 @@ DEV void g2p_body(const SceneK& S, const SceneD& D, int bi, int cur, int part)
 DEV void cell_summaries(const SceneK& S, const SceneD& D, int bi, int brick)
 {
     __shared__ int s_rounds;
-    if (threadIdx.x == 0) s_rounds = 1;
+    __shared__ uint32_t s_bor;
+    if (threadIdx.x == 0) {
+        s_rounds = 1;
+        s_bor = 0u;
+    }
+    __syncthreads();
     bool mixed = false;
     for (int c = threadIdx.x; c < TL_CELLS; c += blockDim.x) {
         const long long cs = (long long)brick * TL_CELLS + c;
@@ -1215,10 +1215,12 @@ DEV void cell_summaries(const SceneK& S, const SceneD& D, int bi, int brick)
         if (cm && !many)
             for (int q = 0; q < nk; q++) D.ckeys[cs * TL_CKEYS + q] = ks[q];
         if (S.material_contact) D.cmask[cs] = orm;
+        if (S.pair_skip && orm) atomicOr(&s_bor, orm);
         mixed |= cm;
     }
     const int m = __syncthreads_or(mixed);
     if (threadIdx.x == 0) {
+        if (S.pair_skip) D.bor[brick] = s_bor; // (the barrier above ordered the LDS ORs)
         D.bmixed[brick] = m;
         if (!m) {
             D.bround[bi] = 0; // no split workgroup for this brick
@@ -1397,41 +1399,72 @@ __global__ void k_fill_i32(int* p, long long n, int v)
     if (i < n) p[i] = v;
 }
 
-// brick AABB from the current state (scene creation, after a state write)
+// brick AABB from the current state (scene creation, after a state write); with the
+// pair-search skip also the centre of the box of the reference positions and the
+// displacement anchor (exact spread: a second pass over the particles)
 DEV void aabb_body(const SceneK& S, const SceneD& D, int bi)
 {
-    __shared__ float s_bb[4][7];
+    __shared__ float s_bb[4][13];
+    __shared__ float s_a[3];
     const int brick = D.active[bi];
     const long long N = S.N;
     const int beg = D.cell_start[(long long)brick * TL_CELLS], end = D.cell_start[(long long)(brick + 1) * TL_CELLS];
-    float bb[7] = {1e30f, 1e30f, 1e30f, -1e30f, -1e30f, -1e30f, 0.0f};
+    // current box (0-5), speed (6), reference box (7-12)
+    float bb[13] = {1e30f, 1e30f, 1e30f, -1e30f, -1e30f, -1e30f, 0.0f, 1e30f, 1e30f, 1e30f, -1e30f, -1e30f, -1e30f};
     for (int p = beg + threadIdx.x; p < end; p += blockDim.x) {
         float sp = 0.0f;
         for (int a = 0; a < 3; a++) {
-            float xa = D.X[a * N + p] + D.u[a * N + p];
+            const float X = D.X[a * N + p];
+            float xa = X + D.u[a * N + p];
             bb[a] = fminf(bb[a], xa);
             bb[3 + a] = fmaxf(bb[3 + a], xa);
+            bb[7 + a] = fminf(bb[7 + a], X);
+            bb[10 + a] = fmaxf(bb[10 + a], X);
             sp += D.v[a * N + p] * D.v[a * N + p];
         }
         bb[6] = fmaxf(bb[6], sqrtf(sp));
     }
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (int q = 0; q < 7; q++) {
+    auto is_min = [](int q) { return q < 3 || (q >= 7 && q < 10); };
+    for (int q = 0; q < 13; q++) {
         float val = bb[q];
         for (int o = 32; o >= 1; o >>= 1) {
             float other = __shfl_xor(val, o, 64);
-            val = (q < 3) ? fminf(val, other) : fmaxf(val, other);
+            val = is_min(q) ? fminf(val, other) : fmaxf(val, other);
         }
         if (lane == 0) s_bb[w][q] = val;
     }
     __syncthreads();
-    if (threadIdx.x < 7) {
+    if (threadIdx.x < 13) {
         int q = threadIdx.x;
         float val = s_bb[0][q];
-        for (int wv = 1; wv < 4; wv++) val = (q < 3) ? fminf(val, s_bb[wv][q]) : fmaxf(val, s_bb[wv][q]);
-        D.aabb[(long long)brick * 8 + q] = val;
+        for (int wv = 1; wv < 4; wv++) val = is_min(q) ? fminf(val, s_bb[wv][q]) : fmaxf(val, s_bb[wv][q]);
+        if (q < 7) D.aabb[(long long)brick * 8 + q] = val;
         if (q == 6 && S.material_contact && val > 0.0f)
             atomicMax(D.hmax + (bi & (TL_HSLOTS - 1)) * TL_HSTRIDE, __float_as_int(val));
+        s_bb[0][q] = val;
+    }
+    if (!S.pair_skip) return;
+    __syncthreads();
+    if (threadIdx.x < 3) { // (the anchor g2p_anchor would form from this box)
+        const int a = threadIdx.x;
+        const float rc = 0.5f * (s_bb[0][7 + a] + s_bb[0][10 + a]);
+        D.uref[(long long)brick * 4 + a] = rc;
+        s_a[a] = 0.5f * (s_bb[0][a] + s_bb[0][3 + a]) - rc;
+    }
+    __syncthreads();
+    // spread about the anchor: exact, from a second pass over the particles
+    float dv = 0.0f;
+    for (int p = beg + threadIdx.x; p < end; p += blockDim.x)
+        for (int a = 0; a < 3; a++) dv = fmaxf(dv, fabsf(D.u[a * N + p] - s_a[a]));
+    for (int o = 32; o >= 1; o >>= 1) dv = fmaxf(dv, __shfl_xor(dv, o, 64));
+    __syncthreads();
+    if (lane == 0) s_bb[w][7] = dv;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int wv = 1; wv < 4; wv++) dv = fmaxf(dv, s_bb[wv][7]);
+        const float a[3] = {s_a[0], s_a[1], s_a[2]};
+        put_anchor(D, bi, brick, 0, a, dv);
     }
 }
 

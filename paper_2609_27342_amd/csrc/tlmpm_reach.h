@@ -1,6 +1,8 @@
-// tlmpm_reach.h -- the test that lets rigid contact (Sec. III-E, Eqs. 14-16) skip a
-// whole brick: can a tool's blade rectangle touch any particle of the brick during
-// this substep?  Host and device code, so that it can be checked on the CPU.
+// tlmpm_reach.h -- reach tests that let contact work skip what cannot touch
+// (Sec. III-E): can a tool's blade rectangle touch any particle of a brick during
+// this substep (Eqs. 14-16), and can a material-contact candidate have a partner at
+// all (Eqs. 10-13 with the reference-neighbour exclusion)?  Host and device code, so
+// that both can be checked on the CPU.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -63,4 +65,30 @@ __host__ __device__ inline bool brick_near_tool(const float* bb, const DevTool& 
 __host__ __device__ inline bool brick_near_floor(const float* bb, float floor_z, float Rmax, float dt)
 {
     return bb[2] - Rmax - dt * bb[6] - 1e-6f <= floor_z;
+}
+
+// Material contact: a candidate p (reference brick b) is searched for partners q
+// within the bin edge hb in the current configuration, |x_p - x_q| < hb; a pair of
+// reference neighbours (reference cells at most one apart per axis) with compatible
+// side codes is excluded.  With x = X + u, per axis |X_p - X_q| <= |x_p - x_q| +
+// |u_p - u_q|.  U[k]: the range of the displacements of the whole scene along axis
+// k; Dk[k]: a bound on |u_p - u_q| along k for p in b and q in the 27 bricks around
+// it (b included).  True when
+//  - no particle of a brick outside the 27 can be within hb: such a brick's
+//    reference positions are more than 4 dx from p's along some axis, so it needs
+//    U[k] > 4 dx - hb along that axis;
+//  - every particle of the 27 bricks within hb is a reference neighbour of p:
+//    |X_p - X_q| < hb + Dk[k] <= dx along every axis.
+// Then p can only have a partner whose side code conflicts with its own.  M bounds
+// the magnitude of the coordinates: the slack covers the FP32 rounding of x =
+// fl(X + u) (half an ulp of each coordinate), of the reach test and of the bounds'
+// own arithmetic (a relative 1e-5 on U and Dk).
+__host__ __device__ inline bool pair_skip_bounds_ok(const float U[3], const float Dk[3], float hb, float dx, float M)
+{
+    const float slack = 4e-7f * (M + hb) + 1e-6f * dx;
+    for (int k = 0; k < 3; k++) {
+        if (!(U[k] * (1.0f + 1e-5f) + hb + slack <= 4.0f * dx)) return false;
+        if (!(Dk[k] * (1.0f + 1e-5f) + hb + slack <= dx)) return false;
+    }
+    return true;
 }

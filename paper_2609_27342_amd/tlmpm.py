@@ -456,10 +456,11 @@ class Scene:
     def contact_stats(self):
         """Material-contact search of the last substep: candidates, buckets,
         occupied buckets, buckets beyond their inline records, largest bucket
-        count, bin edge (m), pairs in contact."""
-        out = (C.c_double * 7)()
+        count, bin edge (m), pairs in contact, candidates whose search was skipped
+        (no partner possible)."""
+        out = (C.c_double * 8)()
         _check(lib().tlmpm_contact_stats(self.h, out))
-        keys = ("candidates", "buckets", "occupied", "overflowing", "max_count", "bin_edge", "pairs")
+        keys = ("candidates", "buckets", "occupied", "overflowing", "max_count", "bin_edge", "pairs", "skipped")
         return {k: (out[i] if k == "bin_edge" else int(out[i])) for i, k in enumerate(keys)}
 
 
