@@ -207,7 +207,9 @@ def large(seed=3, steps=2000, dx=0.0015, box=(0.3, 0.2, 0.1)):
 
     X = jittered_lattice((0, 0, 0), box, dx, origin, inside, rng)
     E = np.exp(rng.uniform(math.log(2e4), math.log(2e5), size=X.shape[0])).astype(np.float32)
-    params = base_params(dx, origin, cells, 3e-5, 0.3, material_contact=1, floor_on=1)
+    # three cuts cross along the line x = y = 0.10 from step 1000 on: nodes there hold
+    # up to 3 x 2 x 2 side codes (a digit 0, 1 or 2 of the newest cut), beyond 8 slots
+    params = base_params(dx, origin, cells, 3e-5, 0.3, material_contact=1, floor_on=1, slot_capacity=16)
     dt = params["dt"]
     s = bx / 0.3  # keep the blade layout proportional when the box is scaled
     c60 = (math.cos(math.radians(60)), math.sin(math.radians(60)), 0.0)
