@@ -377,7 +377,7 @@ Offsets plan(const tlmpm_scene_desc* d, long long n_active)
         o.uanc_x = L.take((size_t)g.n_bricks * 4 * f);
         o.uref = L.take((size_t)g.n_bricks * 4 * f);
         o.bor = L.take((size_t)g.n_bricks * 4);
-        o.umm = L.take((6 * TL_USLOTS + 1) * 4);
+        o.umm = L.take(6 * TL_USLOTS * 4);
         size_t buckets = 4096;
         while (buckets < N / 2) buckets <<= 1;
         o.hmask = (uint32_t)(buckets - 1);
@@ -1431,7 +1431,7 @@ extern "C" tlmpm_status tlmpm_write_state(tlmpm_scene* sc, uint32_t mask, const 
     }
     // speed bounds of the new velocities replace those gathered by the last G2P
     if (sc->K.material_contact) HIPCHK(tl_launch_fill_i32(sc->D.hmax, TL_HSLOTS * TL_HSTRIDE, 0, sc->st));
-    if (sc->K.pair_skip) HIPCHK(tl_launch_fill_i32((int*)sc->D.umm, 6 * TL_USLOTS + 1, 0, sc->st));
+    if (sc->K.pair_skip) HIPCHK(tl_launch_fill_i32((int*)sc->D.umm, 6 * TL_USLOTS, 0, sc->st));
     HIPCHK(tl_launch_aabb(&L));
     HIPCHK(hipStreamSynchronize(sc->st));
     return TLMPM_OK;

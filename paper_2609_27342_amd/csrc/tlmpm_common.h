@@ -173,9 +173,8 @@ struct SceneD {
     float* uref;        // [bricks][4] centre of the box of the brick's reference positions (static)
     uint32_t* bor;      // [bricks] OR of the side keys of the brick's particles
     uint32_t* umm;      // [6][TL_USLOTS] scene bounds of the anchors of the bricks with candidates:
-                        // a + s per axis, then s - a (ordered float keys, maximum over the slots),
-                        // then [1] set when a brick gained its first candidates after its anchor
-                        // was taken (no skipping in that substep); cleared by the pair pass
+                        // a + s per axis, then s - a (ordered float keys, maximum over the slots;
+                        // cleared by the pair pass)
     uint32_t hmask;     // buckets - 1 (power of two)
     int* bcount;        // [2][buckets] entries of each bucket (buffer = stamp parity; the
                         // pair pass clears the other buffer for the next substep)

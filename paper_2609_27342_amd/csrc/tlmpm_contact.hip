@@ -143,10 +143,46 @@ DEV void scan_offsets(const SceneD& D)
     if (t == 0) D.coff[n] = carry;
 }
 
+// Exact displacement anchor of a brick from its particles' current u (the midpoint
+// and half range of each axis): for a brick that gains its first candidates, which
+// the last G2P did not keep an anchor for.  Whole block.
+DEV void anchor_exact(const SceneK& S, const SceneD& D, int bi, int brick, int beg, int end)
+{
+    __shared__ float s_r[4][6];
+    const long long N = S.N;
+    float r[6] = {1e30f, 1e30f, 1e30f, -1e30f, -1e30f, -1e30f};
+    for (int p = beg + threadIdx.x; p < end; p += blockDim.x)
+        for (int a = 0; a < 3; a++) {
+            const float ua = D.u[a * N + p];
+            r[a] = fminf(r[a], ua);
+            r[3 + a] = fmaxf(r[3 + a], ua);
+        }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int q = 0; q < 6; q++) {
+        for (int o = 32; o >= 1; o >>= 1) {
+            const float t = __shfl_xor(r[q], o, 64);
+            r[q] = q < 3 ? fminf(r[q], t) : fmaxf(r[q], t);
+        }
+        if (lane == 0) s_r[wv][q] = r[q];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x >> 6); w++)
+            for (int q = 0; q < 6; q++) r[q] = q < 3 ? fminf(r[q], s_r[w][q]) : fmaxf(r[q], s_r[w][q]);
+        float a[3], sp = 0.0f;
+        for (int k = 0; k < 3; k++) {
+            a[k] = 0.5f * (r[k] + r[3 + k]);
+            sp = fmaxf(sp, fmaxf(r[3 + k] - a[k], a[k] - r[k]));
+        }
+        put_anchor(D, bi, brick, 0, a, sp * (1.0f + 1e-6f));
+    }
+}
+
 // candidate bits and the ordered candidate list of one brick
 DEV void cand_brick(const SceneK& S, const SceneD& D, int bi, int brick, int bx, int by, int bz, uint32_t* s_nm,
                     int* s_st, int* s_wave)
 {
+    const int had = D.bcand[bi]; // (read before thread 0 rewrites it below)
     if (threadIdx.x < TL_CELLS) {
         const int c = threadIdx.x;
         long long cs = (long long)brick * TL_CELLS + c;
@@ -191,11 +227,9 @@ DEV void cand_brick(const SceneK& S, const SceneD& D, int bi, int brick, int bx,
         base += tot;
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        // a brick with its first candidates has no displacement anchor from the last G2P
-        if (S.pair_skip && base > 0 && D.bcand[bi] == 0) atomicOr(D.umm + 6 * TL_USLOTS, 1u);
-        D.bcand[bi] = base;
-    }
+    // a brick with its first candidates has no displacement anchor from the last G2P
+    if (S.pair_skip && base > 0 && had == 0) anchor_exact(S, D, bi, brick, beg, end);
+    if (threadIdx.x == 0) D.bcand[bi] = base;
 }
 
 DEV void cand_body(const SceneK& S, const SceneD& D, int bi, int force)
@@ -284,8 +318,8 @@ DEV void make_rec(const SceneK& S, const SceneD& D, int p, const float x[3], flo
 // brick can have one except through a side-key conflict with *orn, the OR of the keys
 // of the bricks with candidates among the 27 around it (this one included).  Only
 // candidates are partners, so only bricks with candidates enter the bounds; their
-// anchors were taken by the last G2P unless a brick gained its first candidates
-// since (then nothing is skipped in this substep).  The bounds (pair_skip_bounds_ok):
+// anchors come from the last G2P, or, for a brick that gained its first candidates
+// in this substep's candidate pass, from that pass (anchor_exact).  The bounds (pair_skip_bounds_ok):
 // the scene's displacement range per axis from the anchors' slot maxima (u in
 // [min (a - s), max (a + s)]), and for the 27 bricks |u_p - u_q| <= |a_b - a_b'| +
 // s_b + s_b' (|u - a| <= s within a brick).
@@ -339,8 +373,7 @@ DEV void pair_skip_test(const SceneK& S, const SceneD& D, int bi, int brick, flo
             U[k] = um[k] + um[3 + k];
             Dk[k] = dk[k] + s0;
         }
-        const bool fresh = D.umm[6 * TL_USLOTS] == 0u;
-        *skip = (fresh && s0 >= 0.0f && pair_skip_bounds_ok(U, Dk, hb, (float)S.dx, M)) ? 1 : 0;
+        *skip = (s0 >= 0.0f && pair_skip_bounds_ok(U, Dk, hb, (float)S.dx, M)) ? 1 : 0;
         *orn = orr;
     }
 }
@@ -558,7 +591,7 @@ DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
     if (bi == 0) {
         if (threadIdx.x < TL_HSLOTS) D.hmax[threadIdx.x * TL_HSTRIDE] = 0;
         if (S.pair_skip)
-            for (int q = threadIdx.x; q <= 6 * TL_USLOTS; q += blockDim.x) D.umm[q] = 0u;
+            for (int q = threadIdx.x; q < 6 * TL_USLOTS; q += blockDim.x) D.umm[q] = 0u;
     }
     // bucket counts: this substep's buffer, and the other one cleared for the next
     const long long nbk = (long long)D.hmask + 1;
