@@ -1509,16 +1509,15 @@ extern "C" tlmpm_status tlmpm_contact_stats(tlmpm_scene* sc, double out[8])
         if ((h >> 8) == stamp - 1) ends += h & 0xFF;
     out[6] = 0.5 * (double)ends;
     // candidates the binning marked as without a possible partner (first vector of
-    // each record: the flag beside the cell's z)
+    // each record: the flag beside the cell's z); the whole records are copied
     if (total > 0) {
-        std::vector<float4> r0((size_t)total);
-        HIPCHK(hipMemcpy2DAsync(r0.data(), sizeof(float4), sc->D.crec, 3 * sizeof(float4), sizeof(float4),
-                                (size_t)total, hipMemcpyDeviceToHost, sc->st));
+        std::vector<float4> rec((size_t)total * 3);
+        HIPCHK(hipMemcpyAsync(rec.data(), sc->D.crec, rec.size() * sizeof(float4), hipMemcpyDeviceToHost, sc->st));
         HIPCHK(hipStreamSynchronize(sc->st));
         long long skipped = 0;
-        for (const float4& r : r0) {
+        for (size_t g = 0; g < (size_t)total; g++) {
             int w;
-            std::memcpy(&w, &r.w, 4);
+            std::memcpy(&w, &rec[3 * g].w, 4);
             skipped += (w >> 30) & 1;
         }
         out[7] = (double)skipped;
