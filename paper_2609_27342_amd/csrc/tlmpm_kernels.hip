@@ -1305,32 +1305,33 @@ DEV DevBlade blade_at(const DevTool& T, double jdt)
     return B;
 }
 
-DEV void labels_body(const SceneK& S, const SceneD& D, int bi)
+// Blades whose band can reach active brick bi (= brick) this substep: bit b for
+// tools[b] (label tools only; brick_near_band, conservative).
+DEV int label_mask(const SceneK& S, const SceneD& D, int bi, int brick, int n_tools, double jdt)
+{
+    float bb[7];
+    brick_aabb(S, D, bi, brick, bb);
+    int m = 0;
+    for (int b = 0; b < n_tools; b++) {
+        if (!(D.tools[b].flags & TL_TOOL_LABELS)) continue;
+        if (brick_near_band(bb, blade_at(D.tools[b], jdt), S.dt_d)) m |= 1 << b;
+    }
+    return m;
+}
+
+// Label pass of one brick within reach of the blades of mask m (whole block).
+DEV void labels_brick(const SceneK& S, const SceneD& D, int bi, int brick, int m, double jdt)
 {
     const bool mark_prev = D.ctr[1] != 0; // keep the codes the pending F update needs
-    const int n_tools = D.tinfo[0];
-    const double jdt = (double)D.ctr[2] * S.dt_d; // substep of the call (TL_TOOL_ADVANCE poses)
-    __shared__ int s_go;
     __shared__ DevBlade s_bl[TL_MAX_TOOLS];
     __shared__ int s_nb;
-    const int brick = D.active[bi];
     if (threadIdx.x == 0) {
-        float bb[7];
-        brick_aabb(S, D, bi, brick, bb);
-        int go = 0, nb = 0;
-        for (int b = 0; b < n_tools; b++) {
-            if (!(D.tools[b].flags & TL_TOOL_LABELS)) continue;
-            DevBlade B = blade_at(D.tools[b], jdt);
-            if (brick_near_band(bb, B, S.dt_d)) {
-                s_bl[nb++] = B;
-                go = 1;
-            }
-        }
+        int nb = 0;
+        for (int b = 0; b < TL_MAX_TOOLS; b++)
+            if ((m >> b) & 1) s_bl[nb++] = blade_at(D.tools[b], jdt);
         s_nb = nb;
-        s_go = go;
     }
     __syncthreads();
-    if (!s_go) return;
     const long long N = S.N;
     const int beg = D.cell_start[(long long)brick * TL_CELLS], end = D.cell_start[(long long)(brick + 1) * TL_CELLS];
     bool any = false;
@@ -1362,6 +1363,43 @@ DEV void labels_body(const SceneK& S, const SceneD& D, int bi)
         if (threadIdx.x == 0) D.bdirty[brick] = D.ctr[0];
         __syncthreads(); // the new codes of the brick, visible to the whole block
         cell_summaries(S, D, bi, brick);
+    }
+}
+
+DEV void labels_body(const SceneK& S, const SceneD& D, int bi)
+{
+    const double jdt = (double)D.ctr[2] * S.dt_d; // substep of the call (TL_TOOL_ADVANCE poses)
+    __shared__ int s_m;
+    const int brick = D.active[bi];
+    if (threadIdx.x == 0) s_m = label_mask(S, D, bi, brick, D.tinfo[0], jdt);
+    __syncthreads();
+    const int m = s_m;
+    if (!m) return;
+    labels_brick(S, D, bi, brick, m, jdt);
+}
+
+// Label pass of one scene with TL_LBRICKS bricks per workgroup: the first lanes test
+// the bands of bricks w, w + G, w + 2G, ... (G workgroups: the bricks of a blade's
+// band, neighbours in the active order, fall to different workgroups), then the
+// workgroup labels the bricks within reach one after another.  Far fewer workgroups
+// than bricks, most of which only test.
+#define TL_LBRICKS 16
+__global__ __launch_bounds__(256) void k_labels_multi(SceneK S, SceneD D)
+{
+    __shared__ int s_m[TL_LBRICKS];
+    const double jdt = (double)D.ctr[2] * S.dt_d;
+    const int G = gridDim.x;
+    if (threadIdx.x < TL_LBRICKS) {
+        const int bi = blockIdx.x + threadIdx.x * G;
+        s_m[threadIdx.x] = bi < D.n_active ? label_mask(S, D, bi, D.active[bi], D.tinfo[0], jdt) : 0;
+    }
+    __syncthreads();
+    for (int k = 0; k < TL_LBRICKS; k++) {
+        const int m = s_m[k];
+        if (!m) continue;
+        const int bi = blockIdx.x + k * G;
+        labels_brick(S, D, bi, D.active[bi], m, jdt);
+        __syncthreads(); // the brick's LDS words are reused by the next one
     }
 }
 
@@ -1705,6 +1743,13 @@ hipError_t tl_launch_g2p(const TlLaunch* L, int cur)
 
 hipError_t tl_launch_labels(const TlLaunch* L)
 {
+    if (L->S) { // one scene: TL_LBRICKS bricks per workgroup
+        const int n = plain_bricks(*L);
+        if (n <= 0) return hipSuccess;
+        hipLaunchKernelGGL(k_labels_multi, dim3((n + TL_LBRICKS - 1) / TL_LBRICKS), dim3(256), 0, L->st, *L->S,
+                           *L->D);
+        return hipGetLastError();
+    }
     return tl_run(*L, IT_BRICK, plain_bricks(*L), 256, k_labels, k_labels_b);
 }
 
