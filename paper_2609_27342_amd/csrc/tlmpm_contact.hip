@@ -253,6 +253,46 @@ DEV void cand_body(const SceneK& S, const SceneD& D, int bi, int force)
     if (go) cand_brick(S, D, bi, brick, bx, by, bz, s_nm, s_st, s_wave);
 }
 
+// Candidate pass of one scene with TL_CBRICKS bricks per workgroup (bricks w, w + G,
+// w + 2G, ... of G workgroups): 27 threads per brick look for a code change in its
+// 3x3x3 neighbourhood at once, then the workgroup recomputes the bricks that need it
+// one after another.  Far fewer workgroups than bricks, most of which only look.
+#define TL_CBRICKS 8
+__global__ __launch_bounds__(256) void k_cand_multi(SceneK S, SceneD D, int force)
+{
+    static_assert(27 * TL_CBRICKS <= 256, "27 threads per brick");
+    if (!S.material_contact) return;
+    __shared__ uint32_t s_nm[TL_CELLS];
+    __shared__ int s_st[TL_CELLS];
+    __shared__ int s_wave[4];
+    __shared__ int s_go[TL_CBRICKS];
+    const int stamp = D.ctr[0];
+    const int G = gridDim.x;
+    if (threadIdx.x < TL_CBRICKS) s_go[threadIdx.x] = force;
+    __syncthreads();
+    if (!force && threadIdx.x < 27 * TL_CBRICKS) {
+        const int k = threadIdx.x / 27, d = threadIdx.x % 27;
+        const int bi = blockIdx.x + k * G;
+        if (bi < D.n_active) {
+            const int brick = D.active[bi];
+            const int bx = brick % S.cbx, by = (brick / S.cbx) % S.cby, bz = brick / (S.cbx * S.cby);
+            const int x = bx + d % 3 - 1, y = by + (d / 3) % 3 - 1, z = bz + d / 9 - 1;
+            if (x >= 0 && y >= 0 && z >= 0 && x < S.cbx && y < S.cby && z < S.cbz &&
+                D.bdirty[((long long)z * S.cby + y) * S.cbx + x] == stamp)
+                s_go[k] = 1; // (every writer stores 1)
+        }
+    }
+    __syncthreads();
+    for (int k = 0; k < TL_CBRICKS; k++) {
+        const int bi = blockIdx.x + k * G;
+        if (!s_go[k] || bi >= D.n_active) continue;
+        const int brick = D.active[bi];
+        const int bx = brick % S.cbx, by = (brick / S.cbx) % S.cby, bz = brick / (S.cbx * S.cby);
+        cand_brick(S, D, bi, brick, bx, by, bz, s_nm, s_st, s_wave);
+        __syncthreads(); // the brick's LDS words are reused by the next one
+    }
+}
+
 // one block of TL_SCAN_T threads per scene
 DEV void cscan_body(const SceneK& S, const SceneD& D, int bi)
 {
@@ -916,7 +956,16 @@ hipError_t tl_launch_cellmask(const TlLaunch* L, int with_static, int force)
 // candidate bits and lists, then the global candidate offsets
 hipError_t tl_launch_cand(const TlLaunch* L, int force)
 {
-    hipError_t e = tl_run(*L, IT_BRICK, L->S ? L->D->n_active : 0, k_cand, k_cand_b, force);
+    hipError_t e;
+    if (L->S) { // one scene: TL_CBRICKS bricks per workgroup
+        const int n = L->D->n_active;
+        if (n > 0)
+            hipLaunchKernelGGL(k_cand_multi, dim3((n + TL_CBRICKS - 1) / TL_CBRICKS), dim3(256), 0, L->st, *L->S,
+                               *L->D, force);
+        e = hipGetLastError();
+    } else {
+        e = tl_run(*L, IT_BRICK, 0, k_cand, k_cand_b, force);
+    }
     if (e != hipSuccess) return e;
     return tl_run_t(*L, IT_SCENE, 1, TL_SCAN_T, k_cscan, k_cscan_b);
 }
