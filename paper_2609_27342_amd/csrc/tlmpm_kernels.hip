@@ -1403,6 +1403,35 @@ __global__ __launch_bounds__(256) void k_labels_multi(SceneK S, SceneD D)
     }
 }
 
+// The same over the n (scene, brick) work items of a batch.
+__global__ __launch_bounds__(256) void k_labels_multi_b(const SceneK* __restrict__ Ks, const SceneD* __restrict__ Ds,
+                                                        const int2* __restrict__ it, int n)
+{
+    __shared__ int s_m[TL_LBRICKS];
+    const int G = gridDim.x;
+    if (threadIdx.x < TL_LBRICKS) {
+        const int i = blockIdx.x + threadIdx.x * G;
+        int m = 0;
+        if (i < n) {
+            const int2 t = it[i];
+            const SceneK& S = Ks[t.x];
+            const SceneD& D = Ds[t.x];
+            m = label_mask(S, D, t.y, D.active[t.y], D.tinfo[0], (double)D.ctr[2] * S.dt_d);
+        }
+        s_m[threadIdx.x] = m;
+    }
+    __syncthreads();
+    for (int k = 0; k < TL_LBRICKS; k++) {
+        const int m = s_m[k];
+        if (!m) continue;
+        const int2 t = it[blockIdx.x + k * G];
+        const SceneK& S = Ks[t.x];
+        const SceneD& D = Ds[t.x];
+        labels_brick(S, D, t.y, D.active[t.y], m, (double)D.ctr[2] * S.dt_d);
+        __syncthreads();
+    }
+}
+
 // --------------------------------------------------------------- small kernels
 // D := 0 for a new cut (Sec. III-A), over particle block bi
 DEV void resetD_body(const SceneK& S, const SceneD& D, int bi)
@@ -1750,7 +1779,11 @@ hipError_t tl_launch_labels(const TlLaunch* L)
                            *L->D);
         return hipGetLastError();
     }
-    return tl_run(*L, IT_BRICK, plain_bricks(*L), 256, k_labels, k_labels_b);
+    const int n = L->n_items[IT_BRICK]; // a batch: TL_LBRICKS work items per workgroup
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_labels_multi_b, dim3((n + TL_LBRICKS - 1) / TL_LBRICKS), dim3(256), 0, L->st, L->Ks, L->Ds,
+                       L->items[IT_BRICK], n);
+    return hipGetLastError();
 }
 
 hipError_t tl_launch_labels_rigid(const TlLaunch* L)
