@@ -930,7 +930,8 @@ DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
     }
 #define TL_COMMA ,
 TL_WRAP(cellmask, TL_COMMA int with_static TL_COMMA int force, TL_COMMA with_static TL_COMMA force)
-TL_WRAP(cand, TL_COMMA int force, TL_COMMA force)
+// one workgroup per brick (the one-stream substeps of scenes of few bricks)
+__global__ __launch_bounds__(256) void k_cand(SceneK S, SceneD D, int force) { cand_body(S, D, blockIdx.x, force); }
 TL_WRAP(bin_insert, , )
 __global__ __launch_bounds__(256) void k_bin_insert_scan(SceneK S, SceneD D) { bin_insert_body(S, D, blockIdx.x, 1); }
 // at most 128 VGPRs: four waves per SIMD

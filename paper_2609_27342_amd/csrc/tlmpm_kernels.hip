@@ -1589,7 +1589,6 @@ DEV void wrench_body(const SceneK& S, const SceneD& D, int bi)
 
 #define TL_COMMA ,
 TL_WRAP(rigid, 256, , )
-TL_WRAP(labels, 256, , )
 TL_WRAP(slots, 256, TL_COMMA int dst TL_COMMA int src TL_COMMA int force, TL_COMMA dst TL_COMMA src TL_COMMA force)
 TL_WRAP(mixed, 256, TL_COMMA int force, TL_COMMA force)
 TL_WRAP(aabb, 256, , )
