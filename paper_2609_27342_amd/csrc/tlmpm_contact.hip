@@ -293,47 +293,6 @@ __global__ __launch_bounds__(256) void k_cand_multi(SceneK S, SceneD D, int forc
     }
 }
 
-// The same over the n (scene, brick) work items of a batch.
-__global__ __launch_bounds__(256) void k_cand_multi_b(const SceneK* __restrict__ Ks, const SceneD* __restrict__ Ds,
-                                                      const int2* __restrict__ it, int n, int force)
-{
-    __shared__ uint32_t s_nm[TL_CELLS];
-    __shared__ int s_st[TL_CELLS];
-    __shared__ int s_wave[4];
-    __shared__ int s_go[TL_CBRICKS];
-    const int G = gridDim.x;
-    if (threadIdx.x < TL_CBRICKS) s_go[threadIdx.x] = force;
-    __syncthreads();
-    if (!force && threadIdx.x < 27 * TL_CBRICKS) {
-        const int k = threadIdx.x / 27, d = threadIdx.x % 27;
-        const int i = blockIdx.x + k * G;
-        if (i < n) {
-            const int2 t = it[i];
-            const SceneK& S = Ks[t.x];
-            const SceneD& D = Ds[t.x];
-            const int brick = D.active[t.y];
-            const int bx = brick % S.cbx, by = (brick / S.cbx) % S.cby, bz = brick / (S.cbx * S.cby);
-            const int x = bx + d % 3 - 1, y = by + (d / 3) % 3 - 1, z = bz + d / 9 - 1;
-            if (S.material_contact && x >= 0 && y >= 0 && z >= 0 && x < S.cbx && y < S.cby && z < S.cbz &&
-                D.bdirty[((long long)z * S.cby + y) * S.cbx + x] == D.ctr[0])
-                s_go[k] = 1;
-        }
-    }
-    __syncthreads();
-    for (int k = 0; k < TL_CBRICKS; k++) {
-        const int i = blockIdx.x + k * G;
-        if (!s_go[k] || i >= n) continue;
-        const int2 t = it[i];
-        const SceneK& S = Ks[t.x];
-        const SceneD& D = Ds[t.x];
-        if (!S.material_contact) continue;
-        const int brick = D.active[t.y];
-        const int bx = brick % S.cbx, by = (brick / S.cbx) % S.cby, bz = brick / (S.cbx * S.cby);
-        cand_brick(S, D, t.y, brick, bx, by, bz, s_nm, s_st, s_wave);
-        __syncthreads();
-    }
-}
-
 // one block of TL_SCAN_T threads per scene
 DEV void cscan_body(const SceneK& S, const SceneD& D, int bi)
 {
@@ -930,8 +889,10 @@ DEV void pairs_body(const SceneK& S, const SceneD& D, int bi)
     }
 #define TL_COMMA ,
 TL_WRAP(cellmask, TL_COMMA int with_static TL_COMMA int force, TL_COMMA with_static TL_COMMA force)
-// one workgroup per brick (the one-stream substeps of scenes of few bricks)
-__global__ __launch_bounds__(256) void k_cand(SceneK S, SceneD D, int force) { cand_body(S, D, blockIdx.x, force); }
+// one workgroup per brick: the one-stream substeps of scenes of few bricks, and
+// batches (whose small scenes have many bricks next to a code change: there one
+// workgroup per work item measured faster than several)
+TL_WRAP(cand, TL_COMMA int force, TL_COMMA force)
 TL_WRAP(bin_insert, , )
 __global__ __launch_bounds__(256) void k_bin_insert_scan(SceneK S, SceneD D) { bin_insert_body(S, D, blockIdx.x, 1); }
 // at most 128 VGPRs: four waves per SIMD
@@ -1005,12 +966,8 @@ hipError_t tl_launch_cand(const TlLaunch* L, int force)
             hipLaunchKernelGGL(k_cand_multi, dim3((n + TL_CBRICKS - 1) / TL_CBRICKS), dim3(256), 0, L->st, *L->S,
                                *L->D, force);
         e = hipGetLastError();
-    } else { // a batch: TL_CBRICKS work items per workgroup
-        const int n = L->n_items[IT_BRICK];
-        if (n > 0)
-            hipLaunchKernelGGL(k_cand_multi_b, dim3((n + TL_CBRICKS - 1) / TL_CBRICKS), dim3(256), 0, L->st, L->Ks,
-                               L->Ds, L->items[IT_BRICK], n, force);
-        e = hipGetLastError();
+    } else {
+        e = tl_run(*L, IT_BRICK, 0, k_cand, k_cand_b, force);
     }
     if (e != hipSuccess) return e;
     return tl_run_t(*L, IT_SCENE, 1, TL_SCAN_T, k_cscan, k_cscan_b);
