@@ -249,13 +249,18 @@ tlmpm_status tlmpm_contact_stats(tlmpm_scene* scene, double out[8]);
  *   one_stream_bricks: a single scene of at most this many active bricks runs a
  *       substep with a label pass on one stream (label pass and rigid contact in
  *       one launch, slot tables and pair search in one launch), larger ones put
- *       rigid contact and the slot tables on a second stream (2048).
+ *       rigid contact and the slot tables on a second stream (2048);
+ *   pair_skip: 1 lets the binning mark the material-contact candidates that
+ *       provably have no partner, whose search the pair pass then skips (Sec.
+ *       III-E; bitwise the same results), 0 searches every candidate (1).
  * tlmpm_set_tuning(NULL) restores the defaults; TLMPM_E_INVALID for values out of
- * range (a divisor or cap below 1, split_hi < split_lo, a negative value). */
+ * range (a divisor or cap below 1, split_hi < split_lo, a negative value,
+ * pair_skip other than 0 or 1). */
 typedef struct {
     int32_t pair_div, pair_cap;
     int32_t split_lo, split_hi, split_div, split_cap;
     int32_t one_stream_bricks;
+    int32_t pair_skip;
 } tlmpm_tuning;
 tlmpm_status tlmpm_set_tuning(const tlmpm_tuning* tuning);
 tlmpm_status tlmpm_get_tuning(tlmpm_tuning* tuning);

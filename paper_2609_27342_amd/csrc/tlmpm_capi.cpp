@@ -184,7 +184,7 @@ struct Layout {
 // Launch-shape settings (tlmpm_set_tuning), read when a scene is created or its
 // batch footprint is asked for.  Defaults: the measured best on the workloads of
 // the benchmark.
-static const tlmpm_tuning k_tuning_default = {128, 4096, 512, 4096, 4, 256, 2048};
+static const tlmpm_tuning k_tuning_default = {128, 4096, 512, 4096, 4, 256, 2048, 1};
 static tlmpm_tuning g_tuning = k_tuning_default;
 static std::mutex g_tuning_mutex;
 
@@ -590,7 +590,7 @@ extern "C" tlmpm_status tlmpm_create_scene(const tlmpm_scene_desc* d, void* ws, 
     const tlmpm_tuning tun = tuning_now();
     K.pair_blocks = pair_blocks_of(N, tun);
     K.stencil = d->stencil;
-    K.pair_skip = (d->material_contact && d->stencil == 0) ? 1 : 0;
+    K.pair_skip = (d->material_contact && d->stencil == 0 && tun.pair_skip) ? 1 : 0;
     // workgroups for the later rounds of bricks with a mixed cell: a quarter of the
     // bricks, at most 256 (with more mixed bricks no brick is split).  Only scenes of
     // 512 to 4096 active bricks split: their launches are about one round of
@@ -820,7 +820,7 @@ extern "C" tlmpm_status tlmpm_set_tuning(const tlmpm_tuning* t)
 {
     tlmpm_tuning v = t ? *t : k_tuning_default;
     if (v.pair_div < 1 || v.pair_cap < 1 || v.split_lo < 0 || v.split_hi < v.split_lo || v.split_div < 1 ||
-        v.split_cap < 0 || v.one_stream_bricks < 0)
+        v.split_cap < 0 || v.one_stream_bricks < 0 || (v.pair_skip != 0 && v.pair_skip != 1))
         return fail(TLMPM_E_INVALID, "tuning out of range");
     std::lock_guard<std::mutex> lk(g_tuning_mutex);
     g_tuning = v;

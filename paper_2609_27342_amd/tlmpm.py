@@ -58,7 +58,8 @@ _lib = None
 
 class Tuning(C.Structure):
     _fields_ = [("pair_div", C.c_int32), ("pair_cap", C.c_int32), ("split_lo", C.c_int32), ("split_hi", C.c_int32),
-                ("split_div", C.c_int32), ("split_cap", C.c_int32), ("one_stream_bricks", C.c_int32)]
+                ("split_div", C.c_int32), ("split_cap", C.c_int32), ("one_stream_bricks", C.c_int32),
+                ("pair_skip", C.c_int32)]
 
 
 TUNING_KEYS = tuple(k for k, _ in Tuning._fields_)

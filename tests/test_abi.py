@@ -76,12 +76,12 @@ def test_tuning_round_trip_and_validation_without_gpu():
     from paper_2609_27342_amd import tlmpm
     d = tlmpm.get_tuning()
     assert d == {"pair_div": 128, "pair_cap": 4096, "split_lo": 512, "split_hi": 4096, "split_div": 4,
-                 "split_cap": 256, "one_stream_bricks": 2048}
+                 "split_cap": 256, "one_stream_bricks": 2048, "pair_skip": 1}
     try:
         tlmpm.set_tuning(pair_div=64, split_cap=0)
         assert tlmpm.get_tuning() == dict(d, pair_div=64, split_cap=0)
         for bad in (dict(pair_div=0), dict(pair_cap=0), dict(split_lo=5000), dict(split_div=0), dict(split_cap=-1),
-                    dict(one_stream_bricks=-1)):
+                    dict(one_stream_bricks=-1), dict(pair_skip=2)):
             with pytest.raises(tlmpm.TlmpmError):
                 tlmpm.set_tuning(**bad)
         assert tlmpm.get_tuning() == dict(d, pair_div=64, split_cap=0)  # a refused setting changes nothing
